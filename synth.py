@@ -1,0 +1,85 @@
+"""Seeded synthetic inputs and workload shapes shared by the tests, the smoke check and the benchmark.
+
+Holds no arithmetic of the method: only shapes, seeds and numpy random draws
+(complex-normal RBM parameters, +-1 spin configurations).  Both the oracle-side
+and GPU-side tests take their inputs from here.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass(frozen=True)
+class Workload:
+    name: str
+    kind: int            # 0 periodic chain, 1 periodic square lattice
+    Lx: int
+    Ly: int
+    M: int               # hidden units
+    chains: int
+    sweeps: int
+    proposal: int        # 0 single flip, 1 pair exchange at fixed total S^z
+    diag_shift: float
+    param_std: float = 0.01
+    param_seed: int = 1000
+    chain_seed: int = 2000
+
+    @property
+    def N(self):
+        return self.Lx * self.Ly
+
+    @property
+    def P(self):
+        return self.N + self.M + self.N * self.M
+
+    @property
+    def n_bonds(self):
+        return self.N if self.kind == 0 else 2 * self.N
+
+    @property
+    def n_samples(self):
+        return self.chains * self.sweeps
+
+
+# The five benchmark configurations (shapes only).
+CHAIN10_ENUM = Workload("chain10_alpha1_enum", 0, 10, 1, 10, 0, 0, 0, 1e-3, param_seed=1001, chain_seed=2001)
+CHAIN40 = Workload("chain40_alpha2", 0, 40, 1, 80, 1024, 256, 1, 1e-3, param_seed=1002, chain_seed=2002)
+SQUARE10 = Workload("square10x10_alpha4", 1, 10, 10, 400, 4096, 128, 1, 1e-4, param_seed=1003, chain_seed=2003)
+SQUARE8 = Workload("square8x8_alpha2_batched", 1, 8, 8, 128, 0, 16, 1, 1e-4, param_seed=1004, chain_seed=2004)
+SQUARE16 = Workload("square16x16_alpha2_grad", 1, 16, 16, 512, 8192, 64, 1, 0.0, param_seed=1005, chain_seed=2005)
+
+# Ground-state energy scales used only to fix the Chebyshev window when the
+# lattice is too large for exact diagonalisation: Hulthen's infinite-chain
+# value (1/4 - ln 2 per site) and the square-lattice value -0.6694 per site
+# (quantum Monte Carlo literature).  They are scale constants, not results.
+E0_PER_SITE_CHAIN = 0.25 - math.log(2.0)
+E0_PER_SITE_SQUARE = -0.6694
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+def complex_normal(r, shape, std):
+    return (r.normal(0.0, std, size=shape) + 1j * r.normal(0.0, std, size=shape)).astype(np.complex128)
+
+
+def random_rbm_arrays(seed, N, M, std=0.01, std_w=None):
+    """(a[N], b[M], W[N][M]) complex128 with Re, Im ~ N(0, std^2) (W: std_w if given)."""
+    r = rng(seed)
+    a = complex_normal(r, (N,), std)
+    b = complex_normal(r, (M,), std)
+    W = complex_normal(r, (N, M), std if std_w is None else std_w)
+    return a, b, W
+
+
+def random_spins(seed, n, N, zero_magnetisation=False):
+    """int8 [n][N] of +-1; with zero_magnetisation each row has N/2 up spins."""
+    r = rng(seed)
+    if not zero_magnetisation:
+        return (2 * r.integers(0, 2, size=(n, N)) - 1).astype(np.int8)
+    base = np.array([1] * (N // 2) + [-1] * (N - N // 2), dtype=np.int8)
+    return np.stack([r.permutation(base) for _ in range(n)]).astype(np.int8)
