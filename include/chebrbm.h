@@ -1,0 +1,201 @@
+/*
+ * chebrbm -- MI355X (gfx950) hot path of the Chebyshev-RBM spectral-function
+ * method (Hendry, Chen, Weinberg, Feiguin, arXiv:2103.08804).
+ *
+ * A small C ABI.  The calls follow the paper's statement of the problem:
+ *   crbm_init_rbm          RBM parameters of the form of Sec. I
+ *   crbm_init_chains       starting spin configurations of the Markov chains
+ *   crbm_sample            samples s ~ |psi_s|^2 / <psi|psi>              (Sec. III)
+ *   crbm_local_estimators  per-sample log psi, local energy (Sec. VI Hamiltonian),
+ *                          Chebyshev target ratio R = phi/psi (Sec. III
+ *                          recursion of targets), tanh(theta) and O_k     (Sec. III)
+ *   crbm_sr_step           natural-gradient step (S + eps I) dalpha = F   (Sec. III)
+ *   crbm_chebyshev_moment  mu_n = <t_0|t_n> by sampling psi_gs           (Sec. II, App. A)
+ *   crbm_fidelity_grad     gradient of the frozen-sample fidelity surrogate
+ *
+ * Conventions
+ *  - Spins are int8 +-1, row-major [rows][N].  Site r = x + Lx*y.
+ *  - Complex arrays named "complex64" are interleaved (re, im) float pairs
+ *    (torch.complex64 layout); "complex128" are interleaved double pairs.
+ *  - RBM parameters: a[N], b[M], W[N][M] complex64 (W row-major).  A packed
+ *    parameter vector is [a | b | W] of length P = N + M + N*M.
+ *  - Array arguments are DEVICE pointers owned by the caller unless a comment
+ *    says "host".  The library never frees or retains caller memory; it owns
+ *    only the workspace inside a plan.
+ *  - Every call is asynchronous on the given stream and never synchronises
+ *    the host.  Scalar results are written to device memory.
+ *  - Return value: CRBM_OK or a negative CRBM_E* code.  Argument errors are
+ *    detected on the host before anything is enqueued; crbm_last_error()
+ *    then returns a thread-local message.  Conditions found on the device
+ *    (non-finite values, CG not converged, failed Cholesky pivot) are reported
+ *    as bits in the caller's device stats buffer, not as return codes.
+ *  - A plan must not be used from two streams at the same time.
+ */
+#ifndef CHEBRBM_H
+#define CHEBRBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define CRBM_OK            0
+#define CRBM_EINVAL       -1   /* bad argument (null pointer, negative size, unknown enum) */
+#define CRBM_EUNSUPPORTED -2   /* valid but unsupported shape (e.g. N > 256, M > 512) */
+#define CRBM_EHIP         -3   /* a HIP runtime call failed */
+#define CRBM_ENOMEM       -4   /* workspace allocation failed / plan too small */
+
+/* device flag bits in stats_out[6] of crbm_sr_step */
+#define CRBM_FLAG_NOT_CONVERGED 1
+#define CRBM_FLAG_NONFINITE     2
+#define CRBM_FLAG_CHOLESKY_FAIL 4
+
+enum { CRBM_LATTICE_CHAIN = 0, CRBM_LATTICE_SQUARE = 1 };
+enum { CRBM_PROPOSAL_FLIP = 0, CRBM_PROPOSAL_EXCHANGE = 1 };
+enum { CRBM_SOLVER_CG_DENSE = 0, CRBM_SOLVER_CG_MATFREE = 1, CRBM_SOLVER_CHOLESKY = 2 };
+enum { CRBM_PREC_FP32 = 0, CRBM_PREC_BF16 = 1 };
+
+/* plan flags */
+#define CRBM_PLAN_DENSE_S 1    /* reserve the dense P x P complex64 matrix S (needed by CG_DENSE) */
+#define CRBM_PLAN_CHOLESKY 2   /* also reserve a P x P complex128 factor (CHOLESKY; needs P <= 4000) */
+
+/* workspace buffers readable through crbm_plan_buffer (device pointers) */
+enum {
+    CRBM_BUF_F = 0,        /* complex128 [P]   right-hand side F of the last sr_step */
+    CRBM_BUF_DALPHA = 1,   /* complex128 [P]   solution dalpha of the last sr_step */
+    CRBM_BUF_OMEAN = 2,    /* complex128 [P]   <O_k> of the last sr_step */
+    CRBM_BUF_S = 3         /* complex64 [P][P] S of the last dense sr_step (both triangles) */
+};
+
+typedef struct crbm_plan_s* crbm_plan;
+
+/* One RBM (Sec. I): psi(sigma) = exp(sum_i a_i sigma_i) prod_j 2 cosh(theta_j),
+ * theta_j = b_j + sum_i W_ij sigma_i.  All three arrays are complex64 device memory. */
+typedef struct {
+    int n_visible;   /* N */
+    int n_hidden;    /* M */
+    void* a;         /* complex64 [N] */
+    void* b;         /* complex64 [M] */
+    void* W;         /* complex64 [N][M] */
+} crbm_rbm;
+
+/* Periodic nearest-neighbour lattice of the Heisenberg model H = J sum_<ij> S_i.S_j (Sec. VI).
+ * CHAIN: N = Lx sites, bonds (i, i+1 mod N).  SQUARE: N = Lx*Ly, bonds (r, r+x) and (r, r+y)
+ * for every site r (coinciding bonds of a side of length 2 are kept twice). */
+typedef struct {
+    int kind;        /* CRBM_LATTICE_* */
+    int Lx, Ly;      /* Ly ignored for CHAIN */
+    double J;
+} crbm_lattice;
+
+/* Chebyshev stage (Sec. III recursion of targets, rescaled Hamiltonian of Sec. II):
+ * the state being fitted is t~_{n+1}; H~ = (H - E_c)/W_scale; the target is
+ *   order 0:   phi = beta_n H~ t_0,                   t_0 = f_q psi_gs
+ *   order >=1: phi = 2 beta_n H~ t~_n - beta_nm1 t~_{n-1},   t~_0 = t_0
+ * f_q(sigma) = N^{-1/2} sum_r exp(-i q.r) sigma_r / 2 (the S^z_q operator of App. B). */
+typedef struct {
+    int order;
+    double E_c, W_scale;
+    double beta_n[2];    /* complex (re, im) */
+    double beta_nm1[2];  /* complex (re, im) */
+    double q[2];         /* (q_x, q_y); q_y ignored on a chain */
+} crbm_cheb;
+
+/* Plan: lattice, hidden width and the largest sample count any later call on it will use.
+ * Allocates the device workspace (O(max_samples * (N + M)) plus O(P) vectors; plus
+ * 8*P*P bytes with CRBM_PLAN_DENSE_S).  Limits: N even or odd up to 256, M up to 512.
+ * Uses the current HIP device. */
+int crbm_plan_create(crbm_plan* plan, const crbm_lattice* lattice, int n_hidden, long max_samples, int flags);
+int crbm_plan_destroy(crbm_plan plan);
+/* Device pointer and size in bytes of a workspace buffer (CRBM_BUF_*), valid until destroy. */
+int crbm_plan_buffer(crbm_plan plan, int which, void** dev_ptr, size_t* bytes);
+/* Thread-local text of the last error returned on this thread. */
+const char* crbm_last_error(void);
+
+/* Fill a, b, W with complex numbers whose real and imaginary parts are independent
+ * N(0, stddev^2): parameter k of the packed vector takes Philox4x32-10 block
+ * (key = seed, counter = (k, 0, 0, 2)), u1 = ((x0 >> 8) + 1) 2^-24, u2 = (x1 >> 8) 2^-24,
+ * and Box-Muller stddev sqrt(-2 ln u1) (cos 2 pi u2, sin 2 pi u2). */
+int crbm_init_rbm(const crbm_rbm* rbm, uint64_t seed, float stddev, hipStream_t stream);
+
+/* Starting configurations spins[n_chains][N].  zero_magnetisation = 0: sigma_i = +1 iff bit 0
+ * of x0 of block (seed; chain, i, 0, 1).  zero_magnetisation = 1 (N even): N/2 up spins then
+ * N/2 down spins, Fisher-Yates shuffled: for k = N-1 .. 1 swap k with floor(x0 (k+1) / 2^32),
+ * x0 from block (seed; chain, k, 0, 1). */
+int crbm_init_chains(crbm_plan plan, int8_t* spins, int n_chains, uint64_t seed, int zero_magnetisation,
+                     hipStream_t stream);
+
+/* Metropolis sampling of P(s) = |psi_s|^2 / <psi|psi> (Sec. III), n_chains independent chains.
+ * Step t = step_offset + sweep*N + k (k = 0..N-1) of chain c draws Philox block
+ * (key = seed; counter = (c, t lo32, t hi32, 0)): i = floor(x0 N / 2^32), j = floor(x1 N / 2^32),
+ * u = (x2 >> 8) 2^-24.  FLIP flips site i; EXCHANGE swaps sites i and j if sigma_i != sigma_j,
+ * else the step is a null move.  Accept iff u < |psi(sigma')/psi(sigma)|^2.  One sample is the
+ * state after each sweep of N steps.
+ *   spins        int8 [n_chains][N]      in: start states, out: final states
+ *   theta_out    complex64 [n_chains][M] or NULL: theta of the final states
+ *   logpsi_out   complex64 [n_chains]    or NULL: log psi of the final states (Im mod 2 pi)
+ *   samples_out  int8 [n_sweeps][n_chains][N] or NULL
+ *   n_accept     uint32 [n_chains] or NULL: accepted steps in this call
+ *   accept_trace uint32 [n_chains][ceil(n_sweeps*N/32)] or NULL: bit (sweep*N+k) = accepted */
+int crbm_sample(crbm_plan plan, const crbm_rbm* psi, int8_t* spins, void* theta_out, void* logpsi_out,
+                int n_chains, int n_sweeps, int proposal, uint64_t seed, uint64_t step_offset,
+                int8_t* samples_out, uint32_t* n_accept, uint32_t* accept_trace, hipStream_t stream);
+
+/* Per-sample estimators on samples[n_samples][N] (Sec. III, Sec. VI).
+ * Energy mode (psi_n == NULL, cheb ignored): eloc_out = (H fit)(s)/fit(s).
+ * Chebyshev mode (psi_n != NULL): fit = t~_{n+1}; psi_n = t~_n (psi_gs at order 0);
+ *   psi_nm1 = t~_{n-1} (psi_gs at order 1, unused at order 0);
+ *   eloc_out = (H g)(s)/psi_n(s) with g = t_0 at order 0 and g = psi_n otherwise;
+ *   R_out = phi(s)/fit(s).
+ * Outputs (any may be NULL): logpsi_out complex64 [n] (log fit, Im mod 2 pi), eloc_out
+ * complex64 [n], R_out complex64 [n], tanh_out complex64 [n][M] (tanh theta of fit),
+ * O_out complex64 [n][P] (O_a = sigma, O_b = tanh theta, O_W = sigma_i tanh theta_j). */
+int crbm_local_estimators(crbm_plan plan, const crbm_rbm* fit, const crbm_rbm* psi_n, const crbm_rbm* psi_nm1,
+                          const crbm_cheb* cheb, const int8_t* samples, long n_samples,
+                          void* logpsi_out, void* eloc_out, void* R_out, void* tanh_out, void* O_out,
+                          hipStream_t stream);
+
+/* Natural-gradient step on fit (Sec. III), from the samples, their tanh(theta) (as written by
+ * crbm_local_estimators) and the target ratios R:
+ *   gamma = arccos sqrt(|<R>|^2/<|R|^2>), beta = <R>,
+ *   F_k = dgamma gamma cot(gamma) [<O_k^* R>/<R> - <O_k^*>]   (gamma cot gamma -> 1 - gamma^2/3 below 1e-4)
+ *   S_kk' = <O_k^* O_k'> - <O_k>^* <O_k'>,   (S + diag_shift I) dalpha = F,   alpha += dalpha.
+ * <f> = sum_s w_s f_s with w = weights (double [n]) or 1/n if weights == NULL.
+ * solver: CG_DENSE (S built densely by OO^H contraction in s_precision, CG with double vectors),
+ *         CG_MATFREE (S v = <O^*(O v)> - <O>^*(<O> v) from the factored O each iteration),
+ *         CHOLESKY (S built densely, factorised in double).
+ * s_precision: FP32 or BF16 operands for the dense S contraction (accumulation in FP32).
+ * cg_tol: relative residual |F - (S+eps)x| / |F|; cg_maxit: iteration cap.
+ * stats_out: device double [8] = {gamma, Re beta, Im beta, |F|_2, relative residual,
+ *            iterations, flags (CRBM_FLAG_*), |dalpha|_2}.
+ * The parameters of fit are updated in place (complex64). */
+int crbm_sr_step(crbm_plan plan, const crbm_rbm* fit, const int8_t* samples, const double* weights,
+                 const void* tanh_theta, const void* R, long n_samples, double dgamma, double diag_shift,
+                 int solver, int s_precision, double cg_tol, int cg_maxit, double* stats_out,
+                 hipStream_t stream);
+
+/* Chebyshev moments by sampling s ~ |psi_gs|^2 (Sec. II, App. A):
+ *   mu_0(q) = <|f_q|^2>,  mu_n(q) = < f_q(s)^* beta_n t~_n(s)/psi_gs(s) >  (n = 1..n_max)
+ * t_params: complex64 [n_max][P], packed [a|b|W] of t~_1 .. t~_{n_max}; betas: complex128 [n_max];
+ * q: HOST double [n_q][2]; weights as in crbm_sr_step; mu_out: complex128 [n_q][n_max+1],
+ * accumulated in double. */
+int crbm_chebyshev_moment(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_params, const double* betas,
+                          int n_max, const double* q, int n_q, const int8_t* samples, const double* weights,
+                          long n_samples, void* mu_out, hipStream_t stream);
+
+/* Gradient of the frozen-sample fidelity surrogate L = (1/n) sum_s |1 - R_s|^2 with respect to the
+ * parameters of fit (R = phi/fit, so dR/dalpha_k = -R O_k):
+ *   grad_k = 2 dL/d conj(alpha_k) = (2/n) sum_s (1 - R_s) conj(R_s) conj(O_k(s)),
+ * i.e. dL/dRe alpha_k + i dL/dIm alpha_k.  grad_out: complex128 [P]; loss_out: double [1] or NULL.
+ * tanh_theta and R as written by crbm_local_estimators for the same fit and samples. */
+int crbm_fidelity_grad(crbm_plan plan, const crbm_rbm* fit, const int8_t* samples, const void* tanh_theta,
+                       const void* R, long n_samples, void* grad_out, double* loss_out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHEBRBM_H */

@@ -1,0 +1,294 @@
+"""Python binding of libchebrbm (the gfx950 Chebyshev-RBM hot path).
+
+Argument marshalling only: every function checks dtype / device / shape of
+the torch tensors it is given, passes their device pointers and the current
+HIP stream to the C ABI declared in ``include/chebrbm.h``, and raises on a
+non-zero status.  All arithmetic runs in the HIP kernels of the library.
+Importing this module never falls back to anything else: if the library is
+missing, ``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchebrbm.so")
+
+CRBM_OK, CRBM_EINVAL, CRBM_EUNSUPPORTED, CRBM_EHIP, CRBM_ENOMEM = 0, -1, -2, -3, -4
+FLAG_NOT_CONVERGED, FLAG_NONFINITE, FLAG_CHOLESKY_FAIL = 1, 2, 4
+CHAIN, SQUARE = 0, 1
+FLIP, EXCHANGE = 0, 1
+CG_DENSE, CG_MATFREE, CHOLESKY = 0, 1, 2
+FP32, BF16 = 0, 1
+PLAN_DENSE_S, PLAN_CHOLESKY = 1, 2
+BUF_F, BUF_DALPHA, BUF_OMEAN, BUF_S = 0, 1, 2, 3
+
+# names declared in include/chebrbm.h
+EXPORTS = ("crbm_plan_create", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_last_error", "crbm_init_rbm",
+           "crbm_init_chains", "crbm_sample", "crbm_local_estimators", "crbm_sr_step", "crbm_chebyshev_moment",
+           "crbm_fidelity_grad")
+
+
+class CrbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"chebrbm error {code}: {msg}")
+        self.code = code
+
+
+class _Rbm(ctypes.Structure):
+    _fields_ = [("n_visible", ctypes.c_int), ("n_hidden", ctypes.c_int), ("a", ctypes.c_void_p),
+                ("b", ctypes.c_void_p), ("W", ctypes.c_void_p)]
+
+
+class _Lattice(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("Lx", ctypes.c_int), ("Ly", ctypes.c_int), ("J", ctypes.c_double)]
+
+
+class _Cheb(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int), ("E_c", ctypes.c_double), ("W_scale", ctypes.c_double),
+                ("beta_n", ctypes.c_double * 2), ("beta_nm1", ctypes.c_double * 2), ("q", ctypes.c_double * 2)]
+
+
+_lib = None
+_vp, _i, _l, _u64, _d, _f = ctypes.c_void_p, ctypes.c_int, ctypes.c_long, ctypes.c_uint64, ctypes.c_double, ctypes.c_float
+
+
+def lib():
+    """Load libchebrbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2103_08804_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.crbm_last_error.restype = ctypes.c_char_p
+        L.crbm_plan_create.argtypes = [P(_vp), P(_Lattice), _i, _l, _i]
+        L.crbm_plan_destroy.argtypes = [_vp]
+        L.crbm_plan_buffer.argtypes = [_vp, _i, P(_vp), P(ctypes.c_size_t)]
+        L.crbm_init_rbm.argtypes = [P(_Rbm), _u64, _f, _vp]
+        L.crbm_init_chains.argtypes = [_vp, _vp, _i, _u64, _i, _vp]
+        L.crbm_sample.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _i, _i, _i, _u64, _u64, _vp, _vp, _vp, _vp]
+        L.crbm_local_estimators.argtypes = [_vp, P(_Rbm), P(_Rbm), P(_Rbm), P(_Cheb), _vp, _l, _vp, _vp, _vp, _vp,
+                                            _vp, _vp]
+        L.crbm_sr_step.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _l, _d, _d, _i, _i, _d, _i, _vp, _vp]
+        L.crbm_chebyshev_moment.argtypes = [_vp, P(_Rbm), _vp, _vp, _i, P(_d), _i, _vp, _vp, _l, _vp, _vp]
+        L.crbm_fidelity_grad.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _l, _vp, _vp, _vp]
+        for name in EXPORTS:
+            if name != "crbm_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != CRBM_OK:
+        raise CrbmError(rc, lib().crbm_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t, dtype=None, shape=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@dataclasses.dataclass
+class RBM:
+    """Device parameters of one RBM: a[N], b[M], W[N][M] (torch.complex64, contiguous)."""
+    a: torch.Tensor
+    b: torch.Tensor
+    W: torch.Tensor
+
+    @property
+    def N(self):
+        return self.a.shape[0]
+
+    @property
+    def M(self):
+        return self.b.shape[0]
+
+    @classmethod
+    def empty(cls, N, M, device="cuda"):
+        z = lambda *s: torch.zeros(*s, dtype=torch.complex64, device=device)
+        return cls(z(N), z(M), z(N, M))
+
+    @classmethod
+    def from_packed(cls, v, N, M):
+        """Views into one packed [a | b | W] vector (complex64, length N + M + N*M)."""
+        return cls(v[:N], v[N:N + M], v[N + M:].view(N, M))
+
+    def struct(self):
+        N, M = self.N, self.M
+        return _Rbm(N, M, _ptr(self.a, torch.complex64, (N,), "a"), _ptr(self.b, torch.complex64, (M,), "b"),
+                    _ptr(self.W, torch.complex64, (N, M), "W"))
+
+
+class Plan:
+    """Lattice + hidden width + workspace (see crbm_plan_create)."""
+
+    def __init__(self, kind, Lx, Ly=1, M=1, max_samples=1, flags=0, J=1.0):
+        self.kind, self.Lx, self.Ly, self.M, self.J = kind, Lx, (Ly if kind == SQUARE else 1), M, J
+        self.N = self.Lx * self.Ly
+        self.P = self.N + M + self.N * M
+        self.max_samples = max_samples
+        self._h = ctypes.c_void_p()
+        lat = _Lattice(kind, Lx, Ly, J)
+        _check(lib().crbm_plan_create(ctypes.byref(self._h), ctypes.byref(lat), M, max_samples, flags))
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("plan is closed")
+        return self._h
+
+    def close(self):
+        if self._h:
+            _check(lib().crbm_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def buffer_ptr(self, which):
+        """(device pointer, bytes) of a workspace buffer (CRBM_BUF_*)."""
+        p, n = ctypes.c_void_p(), ctypes.c_size_t()
+        _check(lib().crbm_plan_buffer(self.handle, which, ctypes.byref(p), ctypes.byref(n)))
+        return p.value, n.value
+
+
+def copy_plan_buffer(plan, which, out):
+    """Copy a workspace buffer into the tensor ``out`` (same byte size) on the current stream."""
+    ptr, nbytes = plan.buffer_ptr(which)
+    if out.numel() * out.element_size() != nbytes:
+        raise ValueError(f"buffer has {nbytes} bytes, out has {out.numel() * out.element_size()}")
+    src = torch.cuda.current_stream()
+    hip = _hip_runtime()
+    rc = hip.hipMemcpyAsync(ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ptr), ctypes.c_size_t(nbytes),
+                            ctypes.c_int(3), ctypes.c_void_p(src.cuda_stream))
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpyAsync failed with {rc}")
+    return out
+
+
+_hip = None
+
+
+def _hip_runtime():
+    global _hip
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpyAsync.restype = ctypes.c_int
+    return _hip
+
+
+# --------------------------------------------------------------------------- entry points
+def init_rbm(rbm: RBM, seed: int, stddev: float, stream=None):
+    s = rbm.struct()
+    _check(lib().crbm_init_rbm(ctypes.byref(s), seed, stddev, _stream(stream)))
+
+
+def init_chains(plan: Plan, spins, seed: int, zero_magnetisation: bool, stream=None):
+    C = spins.shape[0]
+    p = _ptr(spins, torch.int8, (C, plan.N), "spins")
+    _check(lib().crbm_init_chains(plan.handle, p, C, seed, int(zero_magnetisation), _stream(stream)))
+
+
+def sample(plan: Plan, psi: RBM, spins, n_sweeps: int, proposal: int, seed: int, step_offset: int = 0,
+           theta_out=None, logpsi_out=None, samples_out=None, n_accept=None, trace=None, stream=None):
+    C = spins.shape[0]
+    N, M = plan.N, plan.M
+    words = (n_sweeps * N + 31) // 32
+    s = psi.struct()
+    _check(lib().crbm_sample(
+        plan.handle, ctypes.byref(s), _ptr(spins, torch.int8, (C, N), "spins"),
+        _ptr(theta_out, torch.complex64, (C, M), "theta_out"), _ptr(logpsi_out, torch.complex64, (C,), "logpsi_out"),
+        C, n_sweeps, proposal, seed, step_offset,
+        _ptr(samples_out, torch.int8, (n_sweeps, C, N), "samples_out"),
+        _ptr(n_accept, torch.int32, (C,), "n_accept"), _ptr(trace, torch.int32, (C, words), "trace"),
+        _stream(stream)))
+
+
+def make_cheb(order, E_c, W_scale, beta_n=1.0, beta_nm1=1.0, q=(0.0, 0.0)):
+    c = _Cheb()
+    c.order, c.E_c, c.W_scale = int(order), float(E_c), float(W_scale)
+    bn, bm = complex(beta_n), complex(beta_nm1)
+    c.beta_n[0], c.beta_n[1] = bn.real, bn.imag
+    c.beta_nm1[0], c.beta_nm1[1] = bm.real, bm.imag
+    c.q[0], c.q[1] = float(q[0]), float(q[1])
+    return c
+
+
+def local_estimators(plan: Plan, fit: RBM, samples, psi_n: RBM | None = None, psi_nm1: RBM | None = None,
+                     cheb=None, logpsi_out=None, eloc_out=None, R_out=None, tanh_out=None, O_out=None, stream=None):
+    n = samples.shape[0]
+    N, M, P = plan.N, plan.M, plan.P
+    f = fit.struct()
+    pn = psi_n.struct() if psi_n is not None else None
+    pm = psi_nm1.struct() if psi_nm1 is not None else None
+    _check(lib().crbm_local_estimators(
+        plan.handle, ctypes.byref(f), ctypes.byref(pn) if pn is not None else None,
+        ctypes.byref(pm) if pm is not None else None, ctypes.byref(cheb) if cheb is not None else None,
+        _ptr(samples, torch.int8, (n, N), "samples"), n,
+        _ptr(logpsi_out, torch.complex64, (n,), "logpsi_out"), _ptr(eloc_out, torch.complex64, (n,), "eloc_out"),
+        _ptr(R_out, torch.complex64, (n,), "R_out"), _ptr(tanh_out, torch.complex64, (n, M), "tanh_out"),
+        _ptr(O_out, torch.complex64, (n, P), "O_out"), _stream(stream)))
+
+
+def sr_step(plan: Plan, fit: RBM, samples, tanh_theta, R, dgamma: float, diag_shift: float, solver: int,
+            precision: int, cg_tol: float, cg_maxit: int, stats_out, weights=None, stream=None):
+    n = samples.shape[0]
+    N, M = plan.N, plan.M
+    f = fit.struct()
+    _check(lib().crbm_sr_step(
+        plan.handle, ctypes.byref(f), _ptr(samples, torch.int8, (n, N), "samples"),
+        _ptr(weights, torch.float64, (n,), "weights"), _ptr(tanh_theta, torch.complex64, (n, M), "tanh_theta"),
+        _ptr(R, torch.complex64, (n,), "R"), n, dgamma, diag_shift, solver, precision, cg_tol, cg_maxit,
+        _ptr(stats_out, torch.float64, (8,), "stats_out"), _stream(stream)))
+
+
+def chebyshev_moment(plan: Plan, psi_gs: RBM, t_params, betas, qs, samples, mu_out, weights=None, stream=None):
+    n = samples.shape[0]
+    N, P = plan.N, plan.P
+    n_max = 0 if t_params is None else t_params.shape[0]
+    qflat = [float(v) for q in qs for v in (q[0], q[1])]
+    n_q = len(qflat) // 2
+    qarr = (ctypes.c_double * len(qflat))(*qflat)
+    g = psi_gs.struct()
+    _check(lib().crbm_chebyshev_moment(
+        plan.handle, ctypes.byref(g),
+        _ptr(t_params, torch.complex64, (n_max, P), "t_params") if n_max else None,
+        _ptr(betas, torch.complex128, (n_max,), "betas") if n_max else None, n_max,
+        qarr, n_q, _ptr(samples, torch.int8, (n, N), "samples"), _ptr(weights, torch.float64, (n,), "weights"), n,
+        _ptr(mu_out, torch.complex128, (n_q, n_max + 1), "mu_out"), _stream(stream)))
+
+
+def fidelity_grad(plan: Plan, fit: RBM, samples, tanh_theta, R, grad_out, loss_out=None, stream=None):
+    n = samples.shape[0]
+    N, M, P = plan.N, plan.M, plan.P
+    f = fit.struct()
+    _check(lib().crbm_fidelity_grad(
+        plan.handle, ctypes.byref(f), _ptr(samples, torch.int8, (n, N), "samples"),
+        _ptr(tanh_theta, torch.complex64, (n, M), "tanh_theta"), _ptr(R, torch.complex64, (n,), "R"), n,
+        _ptr(grad_out, torch.complex128, (P,), "grad_out"), _ptr(loss_out, torch.float64, (1,), "loss_out"),
+        _stream(stream)))

@@ -1,0 +1,448 @@
+// C-ABI layer of the chebrbm library: argument validation, plan and
+// workspace management, and the launch sequence of every entry point.
+// Nothing here synchronises the host; every launch goes to the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/chebrbm.h"
+#include "internal.hpp"
+
+namespace crbm {
+hipError_t launch_theta(const int8_t* sig, long n, int N, int M, const float2* b, const float2* W, float2* theta,
+                        hipStream_t stream, const double* skip = nullptr);
+hipError_t launch_local_core(const LocalArgs& A, const float2* th1, const float2* thn, const float2* thm,
+                             hipStream_t stream);
+hipError_t launch_moment_ratio(int N, int M, const int8_t* sig, long n_s, const float2* a_t, const float2* a_g,
+                               const float2* th_t, const float2* th_g, const double2* beta, double2* B,
+                               hipStream_t stream);
+hipError_t launch_fq_chunk(const Geometry& g, const int8_t* sig, long n_s, const double* q_host, int n_q,
+                           double2* f, hipStream_t stream);
+hipError_t launch_moment_accum(const double2* f, const double2* B, int b_is_f, const double* w, long n_s, int n_q,
+                               int nn, int entry0, int total, double2* partial, int n_blocks, hipStream_t stream);
+hipError_t launch_moment_final(const double2* partial, int n_blocks, int total, double2* mu, hipStream_t stream);
+}  // namespace crbm
+
+using namespace crbm;
+
+namespace {
+constexpr int kMaxN = 256;
+constexpr int kMaxM = 512;
+constexpr long kCholMaxP = 4000;
+constexpr int kQChunk = 8;
+constexpr int kMomBlocks = 256;
+constexpr int kMaxMomentEntries = 4096;   // n_q * (n_max + 1)
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+int hip_fail(hipError_t e, const char* where) {
+    return fail(CRBM_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+}  // namespace
+
+struct crbm_plan_s {
+    int device = 0;
+    crbm_lattice lat{};
+    int N = 0, M = 0;
+    long P = 0;
+    int n_bonds = 0;
+    long max_samples = 0;
+    int flags = 0;
+    int2* bonds = nullptr;
+    SrWork w{};
+    float2* theta[3] = {nullptr, nullptr, nullptr};
+    double2* momB = nullptr;
+    double2* momF = nullptr;
+    double2* mom_partial = nullptr;
+    std::vector<void*> allocs;
+
+    Geometry geometry() const {
+        Geometry g;
+        g.N = N; g.M = M; g.P = (int)P; g.n_bonds = n_bonds; g.bonds = bonds;
+        g.kind = lat.kind; g.Lx = lat.Lx; g.J = lat.J;
+        return g;
+    }
+    template <class T>
+    int alloc(T** p, size_t count) {
+        void* q = nullptr;
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc(&q, count * sizeof(T));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CRBM_ENOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+        }
+        allocs.push_back(q);
+        *p = static_cast<T*>(q);
+        return CRBM_OK;
+    }
+    ~crbm_plan_s() {
+        for (void* p : allocs) (void)hipFree(p);
+    }
+};
+
+namespace {
+// Upper bound on the sample chunks of the O^H c contraction for any n <= max_samples:
+// chunks of at least 256 samples and at least n/256 samples, so at most min(ceil(n/256), 257).
+long ot_chunks_bound(long max_samples) {
+    const long c = (max_samples + 255) / 256;
+    return c < 257 ? c : 257;
+}
+
+int check_rbm(const crbm_plan_s* p, const crbm_rbm* r, const char* name) {
+    if (!r) return fail(CRBM_EINVAL, "%s is NULL", name);
+    if (!r->a || !r->b || !r->W) return fail(CRBM_EINVAL, "%s has a NULL parameter array", name);
+    if (r->n_visible != p->N || r->n_hidden != p->M)
+        return fail(CRBM_EINVAL, "%s has shape (N=%d, M=%d) but the plan has (N=%d, M=%d)", name, r->n_visible,
+                    r->n_hidden, p->N, p->M);
+    return CRBM_OK;
+}
+
+RbmView view(const crbm_rbm* r) {
+    RbmView v;
+    v.a = static_cast<const float2*>(r->a);
+    v.b = static_cast<const float2*>(r->b);
+    v.W = static_cast<const float2*>(r->W);
+    return v;
+}
+
+int check_plan(crbm_plan p) {
+    if (!p) return fail(CRBM_EINVAL, "plan is NULL");
+    return CRBM_OK;
+}
+
+int set_device(crbm_plan p) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (cur != p->device) return fail(CRBM_EINVAL, "plan was created on device %d but device %d is current",
+                                      p->device, cur);
+    return CRBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+const char* crbm_last_error(void) { return g_err; }
+
+int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long max_samples, int flags) {
+    if (!out) return fail(CRBM_EINVAL, "plan output pointer is NULL");
+    *out = nullptr;
+    if (!lat) return fail(CRBM_EINVAL, "lattice is NULL");
+    if (lat->kind != CRBM_LATTICE_CHAIN && lat->kind != CRBM_LATTICE_SQUARE)
+        return fail(CRBM_EINVAL, "unknown lattice kind %d", lat->kind);
+    const int Ly = lat->kind == CRBM_LATTICE_CHAIN ? 1 : lat->Ly;
+    if (lat->Lx < 2 || Ly < 1 || (lat->kind == CRBM_LATTICE_SQUARE && Ly < 2))
+        return fail(CRBM_EINVAL, "lattice sides must be >= 2 (got Lx=%d, Ly=%d)", lat->Lx, Ly);
+    const long N = (long)lat->Lx * Ly;
+    if (N > kMaxN) return fail(CRBM_EUNSUPPORTED, "N = %ld sites exceeds the limit of %d", N, kMaxN);
+    if (n_hidden < 1) return fail(CRBM_EINVAL, "n_hidden must be >= 1 (got %d)", n_hidden);
+    if (n_hidden > kMaxM) return fail(CRBM_EUNSUPPORTED, "M = %d hidden units exceeds the limit of %d", n_hidden, kMaxM);
+    if (max_samples < 1) return fail(CRBM_EINVAL, "max_samples must be >= 1 (got %ld)", max_samples);
+    if (flags & ~(CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY)) return fail(CRBM_EINVAL, "unknown plan flags 0x%x", flags);
+
+    crbm_plan_s* p = new (std::nothrow) crbm_plan_s();
+    if (!p) return fail(CRBM_ENOMEM, "host allocation of the plan failed");
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
+    p->lat = *lat;
+    p->lat.Ly = Ly;
+    p->N = (int)N;
+    p->M = n_hidden;
+    p->P = N + n_hidden + N * n_hidden;
+    p->max_samples = max_samples;
+    p->flags = flags;
+    if ((flags & CRBM_PLAN_CHOLESKY) && p->P > kCholMaxP) {
+        delete p;
+        return fail(CRBM_EUNSUPPORTED, "CRBM_PLAN_CHOLESKY needs P <= %ld (P = %ld)", kCholMaxP, N + n_hidden + N * n_hidden);
+    }
+
+    // bonds of the periodic lattice (Sec. VI)
+    std::vector<int2> bonds;
+    if (lat->kind == CRBM_LATTICE_CHAIN) {
+        for (int i = 0; i < lat->Lx; ++i) bonds.push_back(make_int2(i, (i + 1) % lat->Lx));
+    } else {
+        for (int y = 0; y < Ly; ++y)
+            for (int x = 0; x < lat->Lx; ++x) {
+                const int r = x + lat->Lx * y;
+                bonds.push_back(make_int2(r, (x + 1) % lat->Lx + lat->Lx * y));
+                bonds.push_back(make_int2(r, x + lat->Lx * ((y + 1) % Ly)));
+            }
+    }
+    p->n_bonds = (int)bonds.size();
+
+    const long P = p->P, M = n_hidden, S = max_samples;
+    const long plane = (N + 1) * (M + 1);
+    const long red_len = ot_chunks_bound(S) * 2 * plane + 2048;
+    int rc = CRBM_OK;
+    rc = rc ? rc : p->alloc(&p->bonds, bonds.size());
+    rc = rc ? rc : p->alloc(&p->w.scal, 32);
+    rc = rc ? rc : p->alloc(&p->w.Om, P);
+    rc = rc ? rc : p->alloc(&p->w.ORm, P);
+    rc = rc ? rc : p->alloc(&p->w.F, P);
+    rc = rc ? rc : p->alloc(&p->w.x, P);
+    rc = rc ? rc : p->alloc(&p->w.r, P);
+    rc = rc ? rc : p->alloc(&p->w.p, P);
+    rc = rc ? rc : p->alloc(&p->w.Ap, P);
+    rc = rc ? rc : p->alloc(&p->w.vstage, P);
+    rc = rc ? rc : p->alloc(&p->w.u, S);
+    rc = rc ? rc : p->alloc(&p->w.red, red_len);
+    rc = rc ? rc : p->alloc(&p->w.G, S * M);
+    for (int k = 0; k < 3 && !rc; ++k) rc = p->alloc(&p->theta[k], S * M);
+    rc = rc ? rc : p->alloc(&p->momB, S);
+    rc = rc ? rc : p->alloc(&p->momF, (long)kQChunk * S);
+    rc = rc ? rc : p->alloc(&p->mom_partial, (long)kMomBlocks * kMaxMomentEntries);
+    if (!rc && (flags & (CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY))) rc = p->alloc(&p->w.S, P * P);
+    if (!rc && (flags & CRBM_PLAN_CHOLESKY)) rc = p->alloc(&p->w.S64, P * P);
+    if (rc) { delete p; return rc; }
+    p->w.red_len = red_len;
+    e = hipMemcpy(p->bonds, bonds.data(), bonds.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(p->w.scal, 0, 32 * sizeof(double));
+    if (e != hipSuccess) { delete p; return hip_fail(e, "plan initialisation"); }
+    *out = p;
+    return CRBM_OK;
+}
+
+int crbm_plan_destroy(crbm_plan plan) {
+    if (!plan) return fail(CRBM_EINVAL, "plan is NULL");
+    delete plan;
+    return CRBM_OK;
+}
+
+int crbm_plan_buffer(crbm_plan p, int which, void** ptr, size_t* bytes) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (!ptr) return fail(CRBM_EINVAL, "dev_ptr is NULL");
+    size_t b = 0;
+    switch (which) {
+        case CRBM_BUF_F: *ptr = p->w.F; b = p->P * sizeof(double2); break;
+        case CRBM_BUF_DALPHA: *ptr = p->w.x; b = p->P * sizeof(double2); break;
+        case CRBM_BUF_OMEAN: *ptr = p->w.Om; b = p->P * sizeof(double2); break;
+        case CRBM_BUF_S:
+            if (!p->w.S) return fail(CRBM_EINVAL, "the plan holds no dense S (create it with CRBM_PLAN_DENSE_S)");
+            *ptr = p->w.S; b = p->P * p->P * sizeof(float2); break;
+        default: return fail(CRBM_EINVAL, "unknown buffer id %d", which);
+    }
+    if (bytes) *bytes = b;
+    return CRBM_OK;
+}
+
+int crbm_init_rbm(const crbm_rbm* r, uint64_t seed, float stddev, hipStream_t stream) {
+    if (!r || !r->a || !r->b || !r->W) return fail(CRBM_EINVAL, "rbm or one of its arrays is NULL");
+    if (r->n_visible < 1 || r->n_hidden < 1) return fail(CRBM_EINVAL, "rbm sizes must be >= 1");
+    if (!(stddev >= 0.f)) return fail(CRBM_EINVAL, "stddev must be >= 0");
+    hipError_t e = launch_init_rbm((float2*)r->a, (float2*)r->b, (float2*)r->W, r->n_visible, r->n_hidden, seed,
+                                   stddev, stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "init_rbm launch");
+}
+
+int crbm_init_chains(crbm_plan p, int8_t* spins, int n_chains, uint64_t seed, int zero_mag, hipStream_t stream) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (!spins) return fail(CRBM_EINVAL, "spins is NULL");
+    if (n_chains < 1) return fail(CRBM_EINVAL, "n_chains must be >= 1");
+    if (zero_mag != 0 && zero_mag != 1) return fail(CRBM_EINVAL, "zero_magnetisation must be 0 or 1");
+    if (zero_mag && (p->N % 2)) return fail(CRBM_EINVAL, "zero magnetisation needs an even number of sites");
+    if (int rc = set_device(p)) return rc;
+    hipError_t e = launch_init_chains(spins, p->N, n_chains, seed, zero_mag, stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "init_chains launch");
+}
+
+int crbm_sample(crbm_plan p, const crbm_rbm* psi, int8_t* spins, void* theta_out, void* logpsi_out, int n_chains,
+                int n_sweeps, int proposal, uint64_t seed, uint64_t step_offset, int8_t* samples_out,
+                uint32_t* n_accept, uint32_t* accept_trace, hipStream_t stream) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (int rc = check_rbm(p, psi, "psi")) return rc;
+    if (!spins) return fail(CRBM_EINVAL, "spins is NULL");
+    if (n_chains < 1) return fail(CRBM_EINVAL, "n_chains must be >= 1");
+    if (n_sweeps < 0) return fail(CRBM_EINVAL, "n_sweeps must be >= 0");
+    if (proposal != CRBM_PROPOSAL_FLIP && proposal != CRBM_PROPOSAL_EXCHANGE)
+        return fail(CRBM_EINVAL, "unknown proposal %d", proposal);
+    if (int rc = set_device(p)) return rc;
+    SampleArgs A;
+    A.psi = view(psi);
+    A.N = p->N;
+    A.M = p->M;
+    A.spins = spins;
+    A.theta_out = static_cast<float2*>(theta_out);
+    A.logpsi_out = static_cast<float2*>(logpsi_out);
+    A.n_chains = n_chains;
+    A.n_sweeps = n_sweeps;
+    A.proposal = proposal;
+    A.seed = seed;
+    A.step_offset = step_offset;
+    A.samples_out = samples_out;
+    A.n_accept = n_accept;
+    A.trace = accept_trace;
+    A.trace_words = (int)(((long)n_sweeps * p->N + 31) / 32);
+    hipError_t e = launch_sample(A, stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "sample launch");
+}
+
+int crbm_local_estimators(crbm_plan p, const crbm_rbm* fit, const crbm_rbm* psi_n, const crbm_rbm* psi_nm1,
+                          const crbm_cheb* cheb, const int8_t* samples, long n, void* logpsi_out, void* eloc_out,
+                          void* R_out, void* tanh_out, void* O_out, hipStream_t stream) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (int rc = check_rbm(p, fit, "fit")) return rc;
+    if (!samples) return fail(CRBM_EINVAL, "samples is NULL");
+    if (n < 0) return fail(CRBM_EINVAL, "n_samples must be >= 0");
+    if (n > p->max_samples) return fail(CRBM_ENOMEM, "n_samples = %ld exceeds the plan's max_samples = %ld", n,
+                                        p->max_samples);
+    const bool cheb_mode = psi_n != nullptr;
+    if (cheb_mode) {
+        if (!cheb) return fail(CRBM_EINVAL, "cheb is NULL in Chebyshev mode");
+        if (int rc = check_rbm(p, psi_n, "psi_n")) return rc;
+        if (cheb->order < 0) return fail(CRBM_EINVAL, "order must be >= 0");
+        if (cheb->order >= 1)
+            if (int rc = check_rbm(p, psi_nm1, "psi_nm1")) return rc;
+        if (!(cheb->W_scale != 0.0)) return fail(CRBM_EINVAL, "W_scale must be non-zero");
+    } else if (R_out) {
+        return fail(CRBM_EINVAL, "R_out needs Chebyshev mode (psi_n != NULL)");
+    }
+    if (int rc = set_device(p)) return rc;
+    if (n == 0) return CRBM_OK;
+
+    LocalArgs A{};
+    A.g = p->geometry();
+    A.fit = view(fit);
+    A.cheb_mode = cheb_mode;
+    if (cheb_mode) {
+        A.psn = view(psi_n);
+        if (cheb->order >= 1) A.psm = view(psi_nm1);
+        A.order = cheb->order;
+        A.E_c = cheb->E_c;
+        A.W_scale = cheb->W_scale;
+        A.beta_n = make_double2(cheb->beta_n[0], cheb->beta_n[1]);
+        A.beta_nm1 = make_double2(cheb->beta_nm1[0], cheb->beta_nm1[1]);
+        A.q0 = cheb->q[0];
+        A.q1 = p->lat.kind == CRBM_LATTICE_CHAIN ? 0.0 : cheb->q[1];
+    }
+    A.samples = samples;
+    A.n_samples = n;
+    A.logpsi_out = static_cast<float2*>(logpsi_out);
+    A.eloc_out = static_cast<float2*>(eloc_out);
+    A.R_out = static_cast<float2*>(R_out);
+    A.tanh_out = static_cast<float2*>(tanh_out);
+    A.O_out = static_cast<float2*>(O_out);
+    hipError_t e = launch_theta(samples, n, p->N, p->M, A.fit.b, A.fit.W, p->theta[0], stream);
+    if (e == hipSuccess && cheb_mode) e = launch_theta(samples, n, p->N, p->M, A.psn.b, A.psn.W, p->theta[1], stream);
+    if (e == hipSuccess && cheb_mode && cheb->order >= 1)
+        e = launch_theta(samples, n, p->N, p->M, A.psm.b, A.psm.W, p->theta[2], stream);
+    if (e == hipSuccess) e = launch_local_core(A, p->theta[0], p->theta[1], p->theta[2], stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "local_estimators launch");
+}
+
+int crbm_sr_step(crbm_plan p, const crbm_rbm* fit, const int8_t* samples, const double* weights, const void* T,
+                 const void* R, long n, double dgamma, double eps, int solver, int prec, double cg_tol, int cg_maxit,
+                 double* stats_out, hipStream_t stream) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (int rc = check_rbm(p, fit, "fit")) return rc;
+    if (!samples || !T || !R) return fail(CRBM_EINVAL, "samples, tanh_theta and R must be non-NULL");
+    if (n < 1) return fail(CRBM_EINVAL, "n_samples must be >= 1");
+    if (n > p->max_samples) return fail(CRBM_ENOMEM, "n_samples = %ld exceeds the plan's max_samples = %ld", n,
+                                        p->max_samples);
+    if (solver != CRBM_SOLVER_CG_DENSE && solver != CRBM_SOLVER_CG_MATFREE && solver != CRBM_SOLVER_CHOLESKY)
+        return fail(CRBM_EINVAL, "unknown solver %d", solver);
+    if (prec != CRBM_PREC_FP32 && prec != CRBM_PREC_BF16) return fail(CRBM_EINVAL, "unknown precision %d", prec);
+    if (prec == CRBM_PREC_BF16) return fail(CRBM_EUNSUPPORTED, "BF16 S contraction is not available in this build");
+    if (!(eps >= 0.0)) return fail(CRBM_EINVAL, "diag_shift must be >= 0");
+    if (solver != CRBM_SOLVER_CHOLESKY && (cg_maxit < 1 || !(cg_tol > 0.0)))
+        return fail(CRBM_EINVAL, "cg_maxit must be >= 1 and cg_tol > 0");
+    if (solver == CRBM_SOLVER_CG_DENSE && !p->w.S)
+        return fail(CRBM_EINVAL, "CG_DENSE needs a plan created with CRBM_PLAN_DENSE_S");
+    if (solver == CRBM_SOLVER_CHOLESKY && !p->w.S64)
+        return fail(CRBM_EINVAL, "CHOLESKY needs a plan created with CRBM_PLAN_CHOLESKY");
+    if (int rc = set_device(p)) return rc;
+    SrArgs A{};
+    A.N = p->N; A.M = p->M; A.P = (int)p->P;
+    A.a = (float2*)fit->a; A.b = (float2*)fit->b; A.W = (float2*)fit->W;
+    A.samples = samples;
+    A.weights = weights;
+    A.T = static_cast<const float2*>(T);
+    A.R = static_cast<const float2*>(R);
+    A.n = n;
+    A.dgamma = dgamma;
+    A.eps = eps;
+    A.solver = solver;
+    A.prec = prec;
+    A.cg_tol = cg_tol;
+    A.cg_maxit = solver == CRBM_SOLVER_CHOLESKY ? 0 : cg_maxit;
+    A.stats = stats_out;
+    hipError_t e = launch_sr_step(A, p->w, stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "sr_step launch");
+}
+
+int crbm_chebyshev_moment(crbm_plan p, const crbm_rbm* gs, const void* t_params, const double* betas, int n_max,
+                          const double* q, int n_q, const int8_t* samples, const double* weights, long n,
+                          void* mu_out, hipStream_t stream) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (int rc = check_rbm(p, gs, "psi_gs")) return rc;
+    if (n_max < 0) return fail(CRBM_EINVAL, "n_max must be >= 0");
+    if (n_max > 0 && (!t_params || !betas)) return fail(CRBM_EINVAL, "t_params and betas must be non-NULL");
+    if (n_q < 1 || !q) return fail(CRBM_EINVAL, "need n_q >= 1 momenta");
+    if ((long)n_q * (n_max + 1) > kMaxMomentEntries)
+        return fail(CRBM_EUNSUPPORTED, "n_q * (n_max + 1) = %ld exceeds %d", (long)n_q * (n_max + 1),
+                    kMaxMomentEntries);
+    if (!samples || !mu_out) return fail(CRBM_EINVAL, "samples and mu_out must be non-NULL");
+    if (n < 1) return fail(CRBM_EINVAL, "n_samples must be >= 1");
+    if (n > p->max_samples) return fail(CRBM_ENOMEM, "n_samples = %ld exceeds the plan's max_samples = %ld", n,
+                                        p->max_samples);
+    if (int rc = set_device(p)) return rc;
+    const Geometry g = p->geometry();
+    const RbmView vg = view(gs);
+    const int nn = n_max + 1;
+    const long P = p->P;
+    const float2* tp = static_cast<const float2*>(t_params);
+    hipError_t e = launch_theta(samples, n, p->N, p->M, vg.b, vg.W, p->theta[0], stream);
+    for (int q0 = 0; q0 < n_q && e == hipSuccess; q0 += kQChunk) {
+        const int nq = (n_q - q0) < kQChunk ? (n_q - q0) : kQChunk;
+        e = launch_fq_chunk(g, samples, n, q + 2 * q0, nq, p->momF, stream);
+        if (e == hipSuccess)
+            e = launch_moment_accum(p->momF, nullptr, 1, weights, n, nq, nn, q0 * nn, nn * n_q, p->mom_partial,
+                                    kMomBlocks, stream);
+        for (int t = 1; t <= n_max && e == hipSuccess; ++t) {
+            const float2* at = tp + (long)(t - 1) * P;
+            e = launch_theta(samples, n, p->N, p->M, at + p->N, at + p->N + p->M, p->theta[1], stream);
+            if (e == hipSuccess)
+                e = launch_moment_ratio(p->N, p->M, samples, n, at, vg.a, p->theta[1], p->theta[0],
+                                        reinterpret_cast<const double2*>(betas) + (t - 1), p->momB, stream);
+            if (e == hipSuccess)
+                e = launch_moment_accum(p->momF, p->momB, 0, weights, n, nq, nn, q0 * nn + t, nn * n_q,
+                                        p->mom_partial, kMomBlocks, stream);
+        }
+    }
+    if (e == hipSuccess)
+        e = launch_moment_final(p->mom_partial, kMomBlocks, nn * n_q, static_cast<double2*>(mu_out), stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "chebyshev_moment launch");
+}
+
+int crbm_fidelity_grad(crbm_plan p, const crbm_rbm* fit, const int8_t* samples, const void* T, const void* R, long n,
+                       void* grad_out, double* loss_out, hipStream_t stream) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (int rc = check_rbm(p, fit, "fit")) return rc;
+    if (!samples || !T || !R || !grad_out) return fail(CRBM_EINVAL, "samples, tanh_theta, R and grad_out must be non-NULL");
+    if (n < 1) return fail(CRBM_EINVAL, "n_samples must be >= 1");
+    if (n > p->max_samples) return fail(CRBM_ENOMEM, "n_samples = %ld exceeds the plan's max_samples = %ld", n,
+                                        p->max_samples);
+    if (int rc = set_device(p)) return rc;
+    GradArgs A{};
+    A.N = p->N; A.M = p->M; A.P = (int)p->P;
+    A.samples = samples;
+    A.T = static_cast<const float2*>(T);
+    A.R = static_cast<const float2*>(R);
+    A.n = n;
+    A.grad = static_cast<double2*>(grad_out);
+    A.loss = loss_out;
+    hipError_t e = launch_fidelity_grad(A, p->w, stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "fidelity_grad launch");
+}
+
+}  // extern "C"

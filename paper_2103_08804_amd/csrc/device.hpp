@@ -1,0 +1,161 @@
+// Device-side building blocks shared by the gfx950 kernels: complex float
+// arithmetic, the Philox4x32-10 counter-based generator, log(2 cosh z) and
+// tanh z for complex z, and wave64 reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace crbm {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------- complex float
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cdiv(float2 a, float2 b) {
+    // Smith's algorithm keeps the intermediate magnitudes bounded
+    if (fabsf(b.x) >= fabsf(b.y)) {
+        float r = b.y / b.x, d = b.x + b.y * r;
+        return make_float2((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+    }
+    float r = b.x / b.y, d = b.x * r + b.y;
+    return make_float2((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+}
+__device__ __forceinline__ float2 cexpf(float2 z) {
+    float e = expf(z.x), s, c;
+    sincosf(z.y, &s, &c);
+    return make_float2(e * c, e * s);
+}
+
+// double complex
+__device__ __forceinline__ double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zconjmul(double2 a, double2 b) {  // conj(a) * b
+    return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ double2 zdiv(double2 a, double2 b) {
+    double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// ---------------------------------------------------------------- Philox4x32-10
+// Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3"
+// (SC'11): ten rounds of the 4x32 bijection, round keys advanced by the Weyl
+// increments.  Counter (c0, c1, c2, c3), key (k0, k1).
+struct u32x4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1) {
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hiA = __umulhi(kMulA, c0), loA = kMulA * c0;
+        const uint32_t hiB = __umulhi(kMulB, c2), loB = kMulB * c2;
+        const uint32_t n0 = hiB ^ c1 ^ k0, n2 = hiA ^ c3 ^ k1;
+        c0 = n0; c1 = loB; c2 = n2; c3 = loA;
+        k0 += kWeylA; k1 += kWeylB;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// Stream layout used throughout: key = (seed lo, seed hi), counter = (a, b lo, b hi, tag).
+__device__ __forceinline__ u32x4 draw(uint64_t seed, uint32_t a, uint64_t b, uint32_t tag) {
+    return philox4x32_10(a, (uint32_t)b, (uint32_t)(b >> 32), tag, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+__device__ __forceinline__ int draw_index(uint32_t x, int n) { return (int)__umulhi(x, (uint32_t)n); }
+__device__ __forceinline__ float draw_unit(uint32_t x) { return (float)(x >> 8) * (1.0f / 16777216.0f); }
+
+// ---------------------------------------------------------------- log(2 cosh z), tanh z
+// log(2 cosh z) = s z + log(1 + w), w = exp(-2 s z), s = sign(Re z), |w| <= 1.
+__device__ __forceinline__ float2 log2cosh(float2 z) {
+    const float s = z.x >= 0.f ? 1.f : -1.f;
+    const float ax = fabsf(z.x), sy = s * z.y;
+    const float e = expf(-2.f * ax);
+    float sn, cs;
+    sincosf(2.f * sy, &sn, &cs);
+    const float wr = e * cs, wi = -e * sn;
+    return make_float2(ax + 0.5f * log1pf(2.f * wr + e * e), sy + atan2f(wi, 1.f + wr));
+}
+// Re log(2 cosh z) = |x| + log(1 + 2 e cos 2y + e^2)/2, e = exp(-2|x|)  (hardware transcendentals)
+__device__ __forceinline__ float re_log2cosh_fast(float2 z) {
+    const float ax = fabsf(z.x);
+    const float e = __expf(-2.f * ax);
+    const float c = __cosf(2.f * z.y);
+    return ax + 0.5f * __logf(fmaf(e, e, fmaf(2.f * e, c, 1.f)));
+}
+// tanh z = s (1 - w) / (1 + w), w = exp(-2 s z)
+__device__ __forceinline__ float2 ctanhf(float2 z) {
+    const float s = z.x >= 0.f ? 1.f : -1.f;
+    const float e = expf(-2.f * fabsf(z.x));
+    float sn, cs;
+    sincosf(2.f * s * z.y, &sn, &cs);
+    const float wr = e * cs, wi = -e * sn;
+    float2 q = cdiv(make_float2(1.f - wr, -wi), make_float2(1.f + wr, wi));
+    return make_float2(s * q.x, s * q.y);
+}
+
+// ---------------------------------------------------------------- wave64 reductions
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ float2 wave_sum(float2 v) { return make_float2(wave_sum(v.x), wave_sum(v.y)); }
+__device__ __forceinline__ double2 wave_sum(double2 v) { return make_double2(wave_sum(v.x), wave_sum(v.y)); }
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Spin configuration spread over a wave: slot q of lane l holds site 64 q + l.
+struct WaveSpins {
+    int s[4];
+    __device__ __forceinline__ void load(const int8_t* row, int N, int lane) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int site = q * kWave + lane;
+            s[q] = site < N ? (int)row[site] : 0;
+        }
+    }
+    __device__ __forceinline__ void store(int8_t* row, int N, int lane) const {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int site = q * kWave + lane;
+            if (site < N) row[site] = (int8_t)s[q];
+        }
+    }
+    // value of site i (i wave-uniform), broadcast to every lane
+    __device__ __forceinline__ int get(int i) const {
+        const int q = i >> 6;
+        int v = s[0];
+        v = (q == 1) ? s[1] : v;
+        v = (q == 2) ? s[2] : v;
+        v = (q == 3) ? s[3] : v;
+        return __builtin_amdgcn_readlane(v, i & 63);
+    }
+    __device__ __forceinline__ void set(int i, int value, int lane) {
+        if ((i & 63) == lane) {
+            const int q = i >> 6;
+            s[0] = (q == 0) ? value : s[0];
+            s[1] = (q == 1) ? value : s[1];
+            s[2] = (q == 2) ? value : s[2];
+            s[3] = (q == 3) ? value : s[3];
+        }
+    }
+};
+
+}  // namespace crbm

@@ -1,0 +1,128 @@
+// Internal launch interface between the C-ABI layer and the kernel
+// translation units.  Every launcher enqueues on `stream` and returns the
+// hipError_t of the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace crbm {
+
+struct RbmView {            // device pointers, complex64 interleaved
+    const float2* a;
+    const float2* b;
+    const float2* W;
+};
+
+struct Geometry {
+    int N, M, P;
+    int n_bonds;
+    const int2* bonds;      // device [n_bonds]
+    int kind, Lx;           // for site positions (f_q phases)
+    double J;
+};
+
+// ---------------------------------------------------------------- init
+hipError_t launch_init_rbm(float2* a, float2* b, float2* W, int N, int M, uint64_t seed, float stddev,
+                           hipStream_t stream);
+hipError_t launch_init_chains(int8_t* spins, int N, int n_chains, uint64_t seed, int zero_mag, hipStream_t stream);
+
+// ---------------------------------------------------------------- sampling
+struct SampleArgs {
+    RbmView psi;
+    int N, M;
+    int8_t* spins;
+    float2* theta_out;
+    float2* logpsi_out;
+    int n_chains, n_sweeps, proposal;
+    uint64_t seed, step_offset;
+    int8_t* samples_out;
+    uint32_t* n_accept;
+    uint32_t* trace;
+    int trace_words;
+};
+hipError_t launch_sample(const SampleArgs& args, hipStream_t stream);
+
+// ---------------------------------------------------------------- local estimators
+struct LocalArgs {
+    Geometry g;
+    RbmView fit, psn, psm;  // psn.a == nullptr -> energy mode; psm unused at order 0
+    int cheb_mode;
+    int order;
+    double E_c, W_scale;
+    double2 beta_n, beta_nm1;
+    double q0, q1;
+    const int8_t* samples;
+    long n_samples;
+    float2* logpsi_out;
+    float2* eloc_out;
+    float2* R_out;
+    float2* tanh_out;
+    float2* O_out;
+};
+hipError_t launch_local(const LocalArgs& args, hipStream_t stream);
+
+// ---------------------------------------------------------------- moments
+struct MomentArgs {
+    Geometry g;
+    RbmView gs;
+    const float2* t_params;   // [n_max][P]
+    const double2* betas;     // [n_max]
+    int n_max;
+    const double* q;          // device [n_q][2]
+    int n_q;
+    const int8_t* samples;
+    const double* weights;
+    long n_samples;
+    double2* partial;         // workspace [n_blocks][n_q][n_max + 1]
+    int n_blocks;
+    double2* mu_out;          // [n_q][n_max + 1]
+};
+hipError_t launch_moments(const MomentArgs& args, hipStream_t stream);
+
+// ---------------------------------------------------------------- natural-gradient step
+struct SrWork {
+    double* scal;             // [32] device scalars (see kernels_sr.hip)
+    double2* Om;              // [P]  <O>
+    double2* ORm;             // [P]  <O^* R>
+    double2* F;               // [P]
+    double2* x;               // [P]  solution
+    double2* r;               // [P]
+    double2* p;               // [P]
+    double2* Ap;              // [P]
+    double2* u;               // [n]  per-sample scratch for the matrix-free product
+    double2* red;             // reduction scratch [red_len]
+    long red_len;
+    float2* S;                // [P][P] dense (may be null)
+    double2* S64;             // [P][P] dense double (Cholesky, may be null)
+    float2* G;                // [n][M] scratch of the matrix-free product
+    float2* vstage;           // [P] float copy of a CG direction
+};
+
+struct SrArgs {
+    int N, M, P;
+    float2* a; float2* b; float2* W;   // fit parameters (updated in place)
+    const int8_t* samples;
+    const double* weights;             // may be null
+    const float2* T;                   // tanh theta [n][M]
+    const float2* R;                   // [n]
+    long n;
+    double dgamma, eps;
+    int solver, prec;
+    double cg_tol;
+    int cg_maxit;
+    double* stats;                     // device [8]
+};
+hipError_t launch_sr_step(const SrArgs& args, const SrWork& w, hipStream_t stream);
+
+struct GradArgs {
+    int N, M, P;
+    const int8_t* samples;
+    const float2* T;
+    const float2* R;
+    long n;
+    double2* grad;                     // [P]
+    double* loss;                      // [1] or null
+};
+hipError_t launch_fidelity_grad(const GradArgs& args, const SrWork& w, hipStream_t stream);
+
+}  // namespace crbm

@@ -1,0 +1,416 @@
+// theta GEMM, per-sample local estimators and Chebyshev moments.
+//
+//   theta = sigma W + 1 b^T          (RBM of Sec. I), a [n x N] x [N x M] product
+//   E_loc(s) = sum_bonds [J/4 s_i s_j + [s_i != s_j] J/2 psi(s^{ij})/psi(s)]   (Sec. VI)
+//   R(s)     = phi(s)/psi_{n+1}(s)  for the Chebyshev targets of Sec. III
+//   mu_n(q)  = < f_q^* beta_n t~_n / psi_gs >                    (Sec. II, App. A)
+//
+// A pair swap changes theta by Delta_k = -2 s_i (W_ik - W_jk), and
+//   cosh(theta_k + Delta_k)/cosh(theta_k) = cosh(Delta_k) + tanh(theta_k) sinh(Delta_k),
+// so the amplitude ratio of a bond is a product of M complex factors; each
+// lane multiplies its own factors and the wave adds their logarithms.
+// Log-amplitude differences between RBMs are summed element by element so
+// that the M log 2 constants cancel before any rounding of the total.
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace crbm {
+
+// ------------------------------------------------------------------ theta GEMM
+// Block: 256 threads -> 64 samples x 64 hidden units.  Thread (ty, tx) owns
+// samples 4 ty .. 4 ty + 3 and hidden units tx + 16 c (c < 4).
+constexpr int TG_S = 64, TG_K = 64, TG_I = 32;
+
+__global__ __launch_bounds__(256) void k_theta(const int8_t* __restrict__ sig, long n, int N, int M,
+                                                const float2* __restrict__ b, const float2* __restrict__ W,
+                                                float2* __restrict__ theta, const double* __restrict__ skip) {
+    if (skip && *skip != 0.0) return;     // a converged iterative solve skips the product
+    __shared__ float s_sig[TG_I][TG_S + 1];
+    __shared__ float2 s_w[TG_I][TG_K];
+    const int tid = threadIdx.x;
+    const int ty = tid >> 4, tx = tid & 15;
+    const long s0 = (long)blockIdx.x * TG_S;
+    const int k0 = blockIdx.y * TG_K;
+    float2 acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = make_float2(0.f, 0.f);
+
+    for (int i0 = 0; i0 < N; i0 += TG_I) {
+        // stage spins [TG_S samples][TG_I sites] transposed, and W rows
+        for (int e = tid; e < TG_S * TG_I; e += 256) {
+            const int ss = e / TG_I, ii = e % TG_I;
+            const long s = s0 + ss;
+            const int i = i0 + ii;
+            s_sig[ii][ss] = (s < n && i < N) ? (float)sig[s * N + i] : 0.f;
+        }
+        for (int e = tid; e < TG_I * TG_K; e += 256) {
+            const int ii = e / TG_K, kk = e % TG_K;
+            const int i = i0 + ii, k = k0 + kk;
+            s_w[ii][kk] = (i < N && k < M) ? W[(long)i * M + k] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int ii = 0; ii < TG_I; ++ii) {
+            float sv[4];
+            float2 wv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sv[r] = s_sig[ii][ty * 4 + r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) wv[c] = s_w[ii][tx + 16 * c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    acc[r][c].x = fmaf(sv[r], wv[c].x, acc[r][c].x);
+                    acc[r][c].y = fmaf(sv[r], wv[c].y, acc[r][c].y);
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const long s = s0 + ty * 4 + r;
+        if (s >= n) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int k = k0 + tx + 16 * c;
+            if (k < M) theta[s * M + k] = cadd(acc[r][c], b[k]);
+        }
+    }
+}
+
+hipError_t launch_theta(const int8_t* sig, long n, int N, int M, const float2* b, const float2* W, float2* theta,
+                        hipStream_t stream, const double* skip) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid((unsigned)((n + TG_S - 1) / TG_S), (unsigned)((M + TG_K - 1) / TG_K));
+    hipLaunchKernelGGL(k_theta, grid, dim3(256), 0, stream, sig, n, N, M, b, W, theta, skip);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ helpers
+// f_q(sigma) = N^{-1/2} sum_r exp(-i q.r) sigma_r / 2 over the wave's spins
+__device__ __forceinline__ float2 site_phase(int r, int kind, int Lx, double q0, double q1) {
+    const int x = kind == 0 ? r : r % Lx;
+    const int y = kind == 0 ? 0 : r / Lx;
+    const double ph = q0 * x + q1 * y;
+    double s, c;
+    sincos(ph, &s, &c);
+    return make_float2((float)c, (float)-s);
+}
+
+__device__ __forceinline__ float2 fq_wave(const WaveSpins& sp, int lane, const Geometry& g, double q0, double q1) {
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int site = q * kWave + lane;
+        if (site < g.N) acc = cadd(acc, cscale(site_phase(site, g.kind, g.Lx, q0, q1), 0.5f * (float)sp.s[q]));
+    }
+    acc = wave_sum(acc);
+    return cscale(acc, rsqrtf((float)g.N));
+}
+
+// sum_i a_i sigma_i over the wave
+__device__ __forceinline__ float2 a_dot_sigma(const float2* a, const WaveSpins& sp, int lane, int N) {
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int site = q * kWave + lane;
+        if (site < N) acc = cadd(acc, cscale(a[site], (float)sp.s[q]));
+    }
+    return acc;
+}
+
+// ------------------------------------------------------------------ local estimators
+// One wave per sample.  th1/thn/thm: theta of fit / psi_n / psi_{n-1} (precomputed).
+template <int E>
+__global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __restrict__ th1g,
+                                               const float2* __restrict__ thng, const float2* __restrict__ thmg) {
+    const int lane = threadIdx.x & 63;
+    const long s = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (s >= A.n_samples) return;
+    const Geometry& g = A.g;
+    const int N = g.N, M = g.M;
+    WaveSpins sp;
+    sp.load(A.samples + s * N, N, lane);
+
+    float2 t1[E], tE[E], TE[E];
+    float2 lc1 = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = e * kWave + lane;
+        t1[e] = (k < M) ? th1g[s * M + k] : make_float2(0.f, 0.f);
+    }
+    // log psi of fit and tanh theta of fit
+    float2 T1[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = e * kWave + lane;
+        if (k < M) {
+            lc1 = cadd(lc1, log2cosh(t1[e]));
+            T1[e] = ctanhf(t1[e]);
+        } else {
+            T1[e] = make_float2(0.f, 0.f);
+        }
+    }
+    const float2 asig1 = a_dot_sigma(A.fit.a, sp, lane, N);
+    if (A.logpsi_out) {
+        const float2 lp = wave_sum(cadd(lc1, asig1));
+        if (lane == 0) A.logpsi_out[s] = lp;
+    }
+    if (A.tanh_out) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = e * kWave + lane;
+            if (k < M) A.tanh_out[s * M + k] = T1[e];
+        }
+    }
+    if (A.O_out) {
+        float2* row = A.O_out + s * (long)g.P;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int site = q * kWave + lane;
+            if (site < N) row[site] = make_float2((float)sp.s[q], 0.f);
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = e * kWave + lane;
+            if (k < M) row[N + k] = T1[e];
+        }
+        for (int i = 0; i < N; ++i) {
+            const float si = (float)sp.get(i);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = e * kWave + lane;
+                if (k < M) row[N + M + (long)i * M + k] = cscale(T1[e], si);
+            }
+        }
+    }
+    if (!A.eloc_out && !A.R_out) return;
+
+    // the RBM whose Hamiltonian action is needed
+    const RbmView& pe = A.cheb_mode ? A.psn : A.fit;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = e * kWave + lane;
+        if (A.cheb_mode) {
+            tE[e] = (k < M) ? thng[s * M + k] : make_float2(0.f, 0.f);
+            TE[e] = (k < M) ? ctanhf(tE[e]) : make_float2(0.f, 0.f);
+        } else {
+            tE[e] = t1[e];
+            TE[e] = T1[e];
+        }
+    }
+    const bool with_fq = A.cheb_mode && A.order == 0;
+    const float2 d0 = with_fq ? fq_wave(sp, lane, g, A.q0, A.q1) : make_float2(1.f, 0.f);
+    const float inv_sqrt_n = rsqrtf((float)N);
+
+    float2 acc = make_float2(0.f, 0.f);
+    const float J = (float)g.J;
+    for (int bnd = 0; bnd < g.n_bonds; ++bnd) {
+        const int2 ij = g.bonds[bnd];
+        const int i = uniform(ij.x), j = uniform(ij.y);
+        const int si = sp.get(i), sj = sp.get(j);
+        acc = cadd(acc, cscale(d0, 0.25f * J * (float)(si * sj)));
+        if (si == sj) continue;
+        const float m2si = -2.f * (float)si;
+        const float2* Wi = pe.W + (long)i * M;
+        const float2* Wj = pe.W + (long)j * M;
+        float2 prod = make_float2(1.f, 0.f);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = e * kWave + lane;
+            if (k < M) {
+                const float2 d = cscale(csub(Wi[k], Wj[k]), m2si);     // Delta_k
+                const float ex = expf(d.x), emx = 1.f / ex;
+                float sn, cs;
+                sincosf(d.y, &sn, &cs);
+                const float chx = 0.5f * (ex + emx), shx = 0.5f * (ex - emx);
+                const float2 chd = make_float2(chx * cs, shx * sn);
+                const float2 shd = make_float2(shx * cs, chx * sn);
+                prod = cmul(prod, cadd(chd, cmul(TE[e], shd)));
+            }
+        }
+        float2 lg = make_float2(0.5f * logf(prod.x * prod.x + prod.y * prod.y), atan2f(prod.y, prod.x));
+        lg = wave_sum(lg);
+        const float2 da = cscale(csub(pe.a[i], pe.a[j]), m2si);
+        const float2 rho = cexpf(cadd(lg, da));
+        float2 d1 = make_float2(1.f, 0.f);
+        if (with_fq) {
+            // f_q(s^{ij}) = f_q(s) - N^{-1/2} s_i (e^{-iq.r_i} - e^{-iq.r_j})
+            const float2 pd = csub(site_phase(i, g.kind, g.Lx, A.q0, A.q1), site_phase(j, g.kind, g.Lx, A.q0, A.q1));
+            d1 = csub(d0, cscale(pd, inv_sqrt_n * (float)si));
+        }
+        acc = cadd(acc, cscale(cmul(d1, rho), 0.5f * J));
+    }
+    if (A.eloc_out && lane == 0) A.eloc_out[s] = acc;
+    if (!A.cheb_mode || !A.R_out) return;
+
+    // R = phi / psi_{n+1}
+    const float2 ht = cscale(csub(acc, cmul(make_float2((float)A.E_c, 0.f), d0)), (float)(1.0 / A.W_scale));
+    float2 dn = csub(a_dot_sigma(A.psn.a, sp, lane, N), asig1);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        if (e * kWave + lane < M) dn = cadd(dn, csub(log2cosh(tE[e]), log2cosh(t1[e])));
+    dn = wave_sum(dn);
+    const float2 bn = make_float2((float)A.beta_n.x, (float)A.beta_n.y);
+    float2 R;
+    if (A.order == 0) {
+        R = cmul(cmul(bn, ht), cexpf(dn));
+    } else {
+        float2 dm = csub(a_dot_sigma(A.psm.a, sp, lane, N), asig1);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = e * kWave + lane;
+            if (k < M) dm = cadd(dm, csub(log2cosh(thmg[s * M + k]), log2cosh(t1[e])));
+        }
+        dm = wave_sum(dm);
+        const float2 fm = (A.order == 1) ? fq_wave(sp, lane, g, A.q0, A.q1) : make_float2(1.f, 0.f);
+        const float2 bm = make_float2((float)A.beta_nm1.x, (float)A.beta_nm1.y);
+        R = csub(cscale(cmul(cmul(bn, ht), cexpf(dn)), 2.f), cmul(cmul(bm, fm), cexpf(dm)));
+    }
+    if (lane == 0) A.R_out[s] = R;
+}
+
+hipError_t launch_local_core(const LocalArgs& A, const float2* th1, const float2* thn, const float2* thm,
+                             hipStream_t stream) {
+    const int E = (A.g.M + kWave - 1) / kWave;
+    const dim3 grid((unsigned)((A.n_samples + 3) / 4)), block(256);
+    switch (E) {
+#define CRBM_CASE(e) case e: hipLaunchKernelGGL(k_local<e>, grid, block, 0, stream, A, th1, thn, thm); break;
+        CRBM_CASE(1) CRBM_CASE(2) CRBM_CASE(3) CRBM_CASE(4) CRBM_CASE(5) CRBM_CASE(6) CRBM_CASE(7) CRBM_CASE(8)
+#undef CRBM_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ moments
+// B[n][s] = beta_n exp(log t~_n(s) - log psi_gs(s)) for one order n (one wave per sample).
+template <int E>
+__global__ __launch_bounds__(256) void k_moment_ratio(int N, int M, const int8_t* __restrict__ sig, long n_s,
+                                                      const float2* __restrict__ a_t, const float2* __restrict__ a_g,
+                                                      const float2* __restrict__ th_t, const float2* __restrict__ th_g,
+                                                      const double2* __restrict__ beta, double2* __restrict__ B) {
+    const int lane = threadIdx.x & 63;
+    const long s = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (s >= n_s) return;
+    WaveSpins sp;
+    sp.load(sig + s * N, N, lane);
+    float2 d = csub(a_dot_sigma(a_t, sp, lane, N), a_dot_sigma(a_g, sp, lane, N));
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = e * kWave + lane;
+        if (k < M) d = cadd(d, csub(log2cosh(th_t[s * M + k]), log2cosh(th_g[s * M + k])));
+    }
+    d = wave_sum(d);
+    if (lane == 0) {
+        const float2 r = cexpf(d);
+        B[s] = zmul(*beta, make_double2((double)r.x, (double)r.y));
+    }
+}
+
+// f[q][s] = f_q(s) (double) for a chunk of up to 8 momenta, one wave per sample
+struct QChunk { double q[8][2]; };
+
+__global__ __launch_bounds__(256) void k_fq(Geometry g, const int8_t* __restrict__ sig, long n_s, QChunk qc, int n_q,
+                                            double2* __restrict__ f) {
+    const int lane = threadIdx.x & 63;
+    const long s = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (s >= n_s) return;
+    WaveSpins sp;
+    sp.load(sig + s * g.N, g.N, lane);
+    const double inv = 1.0 / sqrt((double)g.N);
+    for (int iq = 0; iq < n_q; ++iq) {
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int site = q * kWave + lane;
+            if (site < g.N) {
+                const int x = g.kind == 0 ? site : site % g.Lx;
+                const int y = g.kind == 0 ? 0 : site / g.Lx;
+                double sn, cs;
+                sincos(qc.q[iq][0] * x + qc.q[iq][1] * y, &sn, &cs);
+                acc.x += 0.5 * sp.s[q] * cs;
+                acc.y -= 0.5 * sp.s[q] * sn;
+            }
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) f[(long)iq * n_s + s] = make_double2(acc.x * inv, acc.y * inv);
+    }
+}
+
+// partial[blk][entry0 + iq*nn] = sum over the block's samples of w conj(f_q) B  (B = f_q when b_is_f)
+__global__ __launch_bounds__(256) void k_moment_accum(const double2* __restrict__ f, const double2* __restrict__ B,
+                                                      int b_is_f, const double* __restrict__ w, long n_s, int n_q,
+                                                      int nn, int entry0, int total, long chunk,
+                                                      double2* __restrict__ partial) {
+    __shared__ double shx[4], shy[4];
+    const long s_begin = (long)blockIdx.x * chunk;
+    const long s_end = min(n_s, s_begin + chunk);
+    const double wdef = 1.0 / (double)n_s;
+    for (int iq = 0; iq < n_q; ++iq) {
+        double ax = 0.0, ay = 0.0;
+        for (long s = s_begin + threadIdx.x; s < s_end; s += blockDim.x) {
+            const double ws = w ? w[s] : wdef;
+            const double2 fs = f[(long)iq * n_s + s];
+            const double2 t = zconjmul(fs, b_is_f ? fs : B[s]);
+            ax += ws * t.x;
+            ay += ws * t.y;
+        }
+        ax = wave_sum(ax);
+        ay = wave_sum(ay);
+        if ((threadIdx.x & 63) == 0) { shx[threadIdx.x >> 6] = ax; shy[threadIdx.x >> 6] = ay; }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            partial[(long)blockIdx.x * total + entry0 + iq * nn] =
+                make_double2(shx[0] + shx[1] + shx[2] + shx[3], shy[0] + shy[1] + shy[2] + shy[3]);
+        __syncthreads();
+    }
+}
+
+__global__ void k_moment_final(const double2* __restrict__ partial, int n_blocks, int total, double2* __restrict__ mu) {
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int b = 0; b < n_blocks; ++b) acc = zadd(acc, partial[(long)b * total + idx]);
+    mu[idx] = acc;
+}
+
+hipError_t launch_moment_ratio(int N, int M, const int8_t* sig, long n_s, const float2* a_t, const float2* a_g,
+                               const float2* th_t, const float2* th_g, const double2* beta, double2* B,
+                               hipStream_t stream) {
+    const int E = (M + kWave - 1) / kWave;
+    const dim3 grid((unsigned)((n_s + 3) / 4)), block(256);
+    switch (E) {
+#define CRBM_CASE(e) case e: hipLaunchKernelGGL(k_moment_ratio<e>, grid, block, 0, stream, N, M, sig, n_s, a_t, a_g, th_t, th_g, beta, B); break;
+        CRBM_CASE(1) CRBM_CASE(2) CRBM_CASE(3) CRBM_CASE(4) CRBM_CASE(5) CRBM_CASE(6) CRBM_CASE(7) CRBM_CASE(8)
+#undef CRBM_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fq_chunk(const Geometry& g, const int8_t* sig, long n_s, const double* q_host, int n_q,
+                           double2* f, hipStream_t stream) {
+    QChunk qc{};
+    for (int k = 0; k < n_q && k < 8; ++k) { qc.q[k][0] = q_host[2 * k]; qc.q[k][1] = g.kind == 0 ? 0.0 : q_host[2 * k + 1]; }
+    hipLaunchKernelGGL(k_fq, dim3((unsigned)((n_s + 3) / 4)), dim3(256), 0, stream, g, sig, n_s, qc, n_q, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_moment_accum(const double2* f, const double2* B, int b_is_f, const double* w, long n_s, int n_q,
+                               int nn, int entry0, int total, double2* partial, int n_blocks, hipStream_t stream) {
+    const long chunk = (n_s + n_blocks - 1) / n_blocks;
+    hipLaunchKernelGGL(k_moment_accum, dim3(n_blocks), dim3(256), 0, stream, f, B, b_is_f, w, n_s, n_q, nn, entry0,
+                       total, chunk, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_moment_final(const double2* partial, int n_blocks, int total, double2* mu, hipStream_t stream) {
+    hipLaunchKernelGGL(k_moment_final, dim3((total + 255) / 256), dim3(256), 0, stream, partial, n_blocks, total, mu);
+    return hipGetLastError();
+}
+
+}  // namespace crbm

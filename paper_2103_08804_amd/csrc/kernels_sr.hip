@@ -1,0 +1,644 @@
+// Natural-gradient (stochastic reconfiguration) step of Sec. III on the GPU.
+//
+// With the extended index sets i in [0, N] and j in [0, M], where sigma~_N = 1
+// and T~_M = 1, every log-derivative is a product O_(i,j)(s) = sigma~_si T~_sj:
+// (i < N, j = M) is O_{a_i} = sigma_i, (i = N, j < M) is O_{b_j} = tanh theta_j
+// and (i < N, j < M) is O_{W_ij}.  Every P-vector contraction over samples,
+//   out_(i,j) = sum_s sigma~_si conj(T~_sj) c_s,
+// is then one [(N+1) x n] x [n x (M+1)] product with a per-sample complex
+// coefficient c_s:  <O>^* (c = w), <O^* R> (c = w R), the matrix-free
+// S v (c = w u, u = O v) and the fidelity gradient (c = 2(1-R) conj(R)/n).
+// Partial sums run in FP32 over a chunk of samples and in FP64 across chunks.
+#include <float.h>
+
+#include "../../include/chebrbm.h"
+#include "device.hpp"
+#include "internal.hpp"
+
+namespace crbm {
+
+hipError_t launch_theta(const int8_t* sig, long n, int N, int M, const float2* b, const float2* W, float2* theta,
+                        hipStream_t stream, const double* skip = nullptr);
+
+// device scalar slots
+enum {
+    SC_RM_RE = 0, SC_RM_IM, SC_R2, SC_GAMMA, SC_GCOT, SC_COEF,
+    SC_RR = 8, SC_PAP, SC_ALPHA, SC_RRNEW, SC_FF, SC_DONE, SC_ITERS, SC_FLAGS, SC_RESID, SC_XX,
+    SC_COUNT = 32
+};
+
+// ------------------------------------------------------------------ P-index <-> (i, j)
+__device__ __forceinline__ void p_to_ij(long k, int N, int M, int& i, int& j) {
+    if (k < N) { i = (int)k; j = M; }
+    else if (k < N + M) { i = N; j = (int)(k - N); }
+    else { const long r = k - N - M; i = (int)(r / M); j = (int)(r % M); }
+}
+__device__ __forceinline__ long ij_to_p(int i, int j, int N, int M) {
+    if (j == M) return i;                 // i < N
+    if (i == N) return (long)N + j;
+    return (long)N + M + (long)i * M + j;
+}
+
+// ------------------------------------------------------------------ scalar reductions
+// red[blk] = (sum w R, sum w |R|^2)
+__global__ __launch_bounds__(256) void k_r_moments(const float2* __restrict__ R, const double* __restrict__ w, long n,
+                                                   double2* __restrict__ red) {
+    __shared__ double sh[3][4];
+    double rx = 0, ry = 0, r2 = 0;
+    const double wdef = 1.0 / (double)n;
+    for (long s = (long)blockIdx.x * 256 + threadIdx.x; s < n; s += (long)gridDim.x * 256) {
+        const double ws = w ? w[s] : wdef;
+        const double x = R[s].x, y = R[s].y;
+        rx += ws * x; ry += ws * y; r2 += ws * (x * x + y * y);
+    }
+    rx = wave_sum(rx); ry = wave_sum(ry); r2 = wave_sum(r2);
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { sh[0][wv] = rx; sh[1][wv] = ry; sh[2][wv] = r2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0, b = 0, c = 0;
+        for (int k = 0; k < 4; ++k) { a += sh[0][k]; b += sh[1][k]; c += sh[2][k]; }
+        red[2 * blockIdx.x] = make_double2(a, b);
+        red[2 * blockIdx.x + 1] = make_double2(c, 0.0);
+    }
+}
+
+__global__ void k_r_final(const double2* __restrict__ red, int n_blocks, double dgamma, double* __restrict__ sc) {
+    if (threadIdx.x != 0) return;
+    double a = 0, b = 0, c = 0;
+    for (int k = 0; k < n_blocks; ++k) { a += red[2 * k].x; b += red[2 * k].y; c += red[2 * k + 1].x; }
+    const double ratio = (a * a + b * b) / c;
+    const double gamma = acos(fmin(1.0, sqrt(ratio)));
+    const double gcot = (gamma < 1e-4) ? 1.0 - gamma * gamma / 3.0 : gamma / tan(gamma);
+    sc[SC_RM_RE] = a; sc[SC_RM_IM] = b; sc[SC_R2] = c;
+    sc[SC_GAMMA] = gamma; sc[SC_GCOT] = gcot; sc[SC_COEF] = dgamma * gcot;
+    for (int k = SC_RR; k < SC_COUNT; ++k) sc[k] = 0.0;
+    if (!(c > 0.0) || !isfinite(a) || !isfinite(b) || !isfinite(c)) sc[SC_FLAGS] = CRBM_FLAG_NONFINITE;
+}
+
+// ------------------------------------------------------------------ O^H c contraction
+// Tile: 32 extended sites x 64 extended hidden units per block; blockIdx.z = sample chunk.
+// coef kinds: 0 -> c = w; 1 -> c = w R; 2 -> c = w u (u double2 [n]);
+//             3 -> c = 2 (1 - R) conj(R) / n
+constexpr int OT_I = 32, OT_J = 64, OT_S = 32;
+
+__device__ __forceinline__ float2 coef_of(int kind, long s, const double* w, double wdef, const float2* R,
+                                          const double2* u, double two_over_n) {
+    const float ws = w ? (float)w[s] : (float)wdef;
+    switch (kind) {
+        case 0: return make_float2(ws, 0.f);
+        case 1: return cscale(R[s], ws);
+        case 2: return make_float2((float)(u[s].x) * ws, (float)(u[s].y) * ws);
+        default: {
+            const float2 r = R[s];
+            const float2 d = cmul(make_float2(1.f - r.x, -r.y), cconj(r));
+            return cscale(d, (float)two_over_n);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ot(int N, int M, const int8_t* __restrict__ sig, const float2* __restrict__ T,
+                                            long n, long chunk, int kind0, int kind1, int nk,
+                                            const double* __restrict__ w, const float2* __restrict__ R,
+                                            const double2* __restrict__ u, double2* __restrict__ partial,
+                                            const double* __restrict__ skip) {
+    if (skip && *skip != 0.0) return;
+    __shared__ float s_sig[OT_S][OT_I + 1];
+    __shared__ float2 s_t[OT_S][OT_J];
+    __shared__ float2 s_c[2][OT_S];
+    const int tid = threadIdx.x;
+    const int i0 = blockIdx.x * OT_I, j0 = blockIdx.y * OT_J;
+    const long s_begin = (long)blockIdx.z * chunk;
+    const long s_end = min(n, s_begin + chunk);
+    const int jl = tid & 63, ib = (tid >> 6) * 8;
+    const double wdef = 1.0 / (double)n;
+    const double two_over_n = 2.0 / (double)n;
+    float2 acc[2][8];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) acc[c][r] = make_float2(0.f, 0.f);
+
+    for (long sb = s_begin; sb < s_end; sb += OT_S) {
+        for (int e = tid; e < OT_S * OT_I; e += 256) {
+            const int ss = e / OT_I, ii = e % OT_I;
+            const long s = sb + ss;
+            const int i = i0 + ii;
+            float v = 0.f;
+            if (s < s_end && i <= N) v = (i == N) ? 1.f : (float)sig[s * N + i];
+            s_sig[ss][ii] = v;
+        }
+        for (int e = tid; e < OT_S * OT_J; e += 256) {
+            const int ss = e / OT_J, jj = e % OT_J;
+            const long s = sb + ss;
+            const int j = j0 + jj;
+            float2 v = make_float2(0.f, 0.f);
+            if (s < s_end && j <= M) v = (j == M) ? make_float2(1.f, 0.f) : cconj(T[s * M + j]);
+            s_t[ss][jj] = v;
+        }
+        if (tid < OT_S * 2) {
+            const int c = tid / OT_S, ss = tid % OT_S;
+            const long s = sb + ss;
+            float2 v = make_float2(0.f, 0.f);
+            if (s < s_end && c < nk) v = coef_of(c == 0 ? kind0 : kind1, s, w, wdef, R, u, two_over_n);
+            s_c[c][ss] = v;
+        }
+        __syncthreads();
+        for (int ss = 0; ss < OT_S; ++ss) {
+            const float2 t = s_t[ss][jl];
+            const float2 y0 = cmul(t, s_c[0][ss]);
+            const float2 y1 = cmul(t, s_c[1][ss]);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const float sv = s_sig[ss][ib + r];
+                acc[0][r].x = fmaf(sv, y0.x, acc[0][r].x);
+                acc[0][r].y = fmaf(sv, y0.y, acc[0][r].y);
+                acc[1][r].x = fmaf(sv, y1.x, acc[1][r].x);
+                acc[1][r].y = fmaf(sv, y1.y, acc[1][r].y);
+            }
+        }
+        __syncthreads();
+    }
+    const int j = j0 + jl;
+    if (j > M) return;
+    const long plane = (long)(N + 1) * (M + 1);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int i = i0 + ib + r;
+        if (i > N) continue;
+        const long o = (long)i * (M + 1) + j;
+        for (int c = 0; c < nk; ++c)
+            partial[((long)blockIdx.z * nk + c) * plane + o] =
+                make_double2((double)acc[c][r].x, (double)acc[c][r].y);
+    }
+}
+
+// out[c][P-index] = sum over chunks (FP64), with optional conjugation.
+__global__ void k_ot_reduce(int N, int M, const double2* __restrict__ partial, int n_chunks, int nk, int conj0,
+                            double2* __restrict__ out0, double2* __restrict__ out1, const double* __restrict__ skip) {
+    if (skip && *skip != 0.0) return;
+    const long plane = (long)(N + 1) * (M + 1);
+    const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= plane) return;
+    const int i = (int)(o / (M + 1)), j = (int)(o % (M + 1));
+    if (i == N && j == M) return;
+    const long k = ij_to_p(i, j, N, M);
+    for (int c = 0; c < nk; ++c) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int b = 0; b < n_chunks; ++b) acc = zadd(acc, partial[((long)b * nk + c) * plane + o]);
+        if (c == 0 && conj0) acc.y = -acc.y;
+        (c == 0 ? out0 : out1)[k] = acc;
+    }
+}
+
+struct OtPlan { long chunk; int n_chunks; };
+static OtPlan ot_plan(long n) {
+    long chunk = (n + 255) / 256;
+    chunk = ((chunk + OT_S - 1) / OT_S) * OT_S;
+    if (chunk < 256) chunk = 256;
+    return {chunk, (int)((n + chunk - 1) / chunk)};
+}
+
+static hipError_t run_ot(int N, int M, const int8_t* sig, const float2* T, long n, int kind0, int kind1, int nk,
+                         const double* w, const float2* R, const double2* u, double2* partial, int conj0,
+                         double2* out0, double2* out1, hipStream_t stream, const double* skip = nullptr) {
+    const OtPlan op = ot_plan(n);
+    dim3 grid((N + 1 + OT_I - 1) / OT_I, (M + 1 + OT_J - 1) / OT_J, op.n_chunks);
+    hipLaunchKernelGGL(k_ot, grid, dim3(256), 0, stream, N, M, sig, T, n, op.chunk, kind0, kind1, nk, w, R, u, partial,
+                       skip);
+    const long plane = (long)(N + 1) * (M + 1);
+    hipLaunchKernelGGL(k_ot_reduce, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, stream, N, M, partial,
+                       op.n_chunks, nk, conj0, out0, out1, skip);
+    return hipGetLastError();
+}
+
+// F_k = coef [ORm_k / <R> - conj(Om_k)];  Om holds conj(<O>) on entry and <O> on exit.
+__global__ void k_make_f(long P, double2* __restrict__ Om, const double2* __restrict__ ORm, const double* __restrict__ sc,
+                         double2* __restrict__ F) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P) return;
+    const double2 rm = make_double2(sc[SC_RM_RE], sc[SC_RM_IM]);
+    const double coef = sc[SC_COEF];
+    const double2 omc = Om[k];
+    const double2 q = zdiv(ORm[k], rm);
+    F[k] = make_double2(coef * (q.x - omc.x), coef * (q.y - omc.y));
+    Om[k] = make_double2(omc.x, -omc.y);
+}
+
+// ------------------------------------------------------------------ dense S (FP32, VALU)
+// Upper-triangle tiles (I <= J) of 64 x 64; S[k][k'] = sum_s w conj(O_sk) O_sk' - conj(Om_k) Om_k',
+// mirrored into the lower triangle so that S is stored in full.
+constexpr int SB_T = 64, SB_K = 16;
+
+__global__ __launch_bounds__(256) void k_sbuild(int N, int M, long P, const int8_t* __restrict__ sig,
+                                                const float2* __restrict__ T, const double* __restrict__ w, long n,
+                                                const double2* __restrict__ Om, float2* __restrict__ S, int ntile) {
+    __shared__ float2 sa[SB_K][SB_T];
+    __shared__ float2 sb[SB_K][SB_T];
+    // map blockIdx.x -> (I, J), I <= J
+    long rem = blockIdx.x;
+    int I = 0;
+    while (rem >= ntile - I) { rem -= ntile - I; ++I; }
+    const int J = I + (int)rem;
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    const long kA0 = (long)I * SB_T, kB0 = (long)J * SB_T;
+    // columns loaded by this thread: column c = tid & 63, rows ss = tid >> 6 (+4 steps)
+    const int lc = tid & 63;
+    int ia, ja, ib, jb;
+    const bool va = kA0 + lc < P, vb = kB0 + lc < P;
+    p_to_ij(va ? kA0 + lc : 0, N, M, ia, ja);
+    p_to_ij(vb ? kB0 + lc : 0, N, M, ib, jb);
+    const double wdef = 1.0 / (double)n;
+    float2 acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = make_float2(0.f, 0.f);
+
+    for (long s0 = 0; s0 < n; s0 += SB_K) {
+#pragma unroll
+        for (int st = 0; st < SB_K / 4; ++st) {
+            const int ss = (tid >> 6) + 4 * st;
+            const long s = s0 + ss;
+            float2 oa = make_float2(0.f, 0.f), ob = make_float2(0.f, 0.f);
+            if (s < n) {
+                const float ws = w ? (float)w[s] : (float)wdef;
+                if (va) {
+                    const float sv = (ia == N) ? 1.f : (float)sig[s * N + ia];
+                    const float2 tv = (ja == M) ? make_float2(1.f, 0.f) : T[s * M + ja];
+                    oa = cscale(cconj(tv), sv * ws);
+                }
+                if (vb) {
+                    const float sv = (ib == N) ? 1.f : (float)sig[s * N + ib];
+                    const float2 tv = (jb == M) ? make_float2(1.f, 0.f) : T[s * M + jb];
+                    ob = cscale(tv, sv);
+                }
+            }
+            sa[ss][lc] = oa;
+            sb[ss][lc] = ob;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < SB_K; ++kk) {
+            float2 av[4], bv[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) av[r] = sa[kk][ty + 16 * r];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) bv[c] = sb[kk][tx + 16 * c];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    acc[r][c].x = fmaf(av[r].x, bv[c].x, fmaf(-av[r].y, bv[c].y, acc[r][c].x));
+                    acc[r][c].y = fmaf(av[r].x, bv[c].y, fmaf(av[r].y, bv[c].x, acc[r][c].y));
+                }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const long k = kA0 + ty + 16 * r;
+        if (k >= P) continue;
+        const double2 omk = Om[k];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const long kp = kB0 + tx + 16 * c;
+            if (kp >= P) continue;
+            const double2 omkp = Om[kp];
+            const double2 mm = zconjmul(omk, omkp);
+            const float2 v = make_float2((float)((double)acc[r][c].x - mm.x), (float)((double)acc[r][c].y - mm.y));
+            S[k * P + kp] = v;
+            if (I != J) S[kp * P + k] = cconj(v);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ dense complex matvec
+// y = (S + eps I) x, one wave per row, double accumulation
+__global__ __launch_bounds__(256) void k_symv(long P, const float2* __restrict__ S, const double2* __restrict__ x,
+                                              double eps, double2* __restrict__ y, const double* __restrict__ sc) {
+    if (sc[SC_DONE] != 0.0) return;
+    const int lane = threadIdx.x & 63;
+    const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= P) return;
+    const float2* Sr = S + row * P;
+    double ax = 0, ay = 0;
+    for (long k = lane; k < P; k += 64) {
+        const float2 a = Sr[k];
+        const double2 b = x[k];
+        ax += (double)a.x * b.x - (double)a.y * b.y;
+        ay += (double)a.x * b.y + (double)a.y * b.x;
+    }
+    ax = wave_sum(ax);
+    ay = wave_sum(ay);
+    if (lane == 0) y[row] = make_double2(ax + eps * x[row].x, ay + eps * x[row].y);
+}
+
+// ------------------------------------------------------------------ matrix-free S v
+// u_s = sum_j T~_sj G_sj + sum_i sigma_si v_a_i with G = theta-GEMM(b = v_b, W = v_W)
+__global__ __launch_bounds__(256) void k_pack_v(int N, int M, const double2* __restrict__ v, float2* __restrict__ vb,
+                                                float2* __restrict__ vW, const double* __restrict__ sc) {
+    if (sc[SC_DONE] != 0.0) return;
+    const long P = (long)N + M + (long)N * M;
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < N || k >= P) return;
+    const float2 f = make_float2((float)v[k].x, (float)v[k].y);
+    if (k < N + M) vb[k - N] = f; else vW[k - N - M] = f;
+}
+
+template <int E>
+__global__ __launch_bounds__(256) void k_ov(int N, int M, const int8_t* __restrict__ sig, const float2* __restrict__ T,
+                                            const float2* __restrict__ G, const double2* __restrict__ v, long n,
+                                            double2* __restrict__ u, const double* __restrict__ sc) {
+    if (sc[SC_DONE] != 0.0) return;
+    const int lane = threadIdx.x & 63;
+    const long s = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (s >= n) return;
+    double ax = 0, ay = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = e * kWave + lane;
+        if (k < M) {
+            const float2 t = T[s * M + k], g = G[s * M + k];
+            ax += (double)t.x * g.x - (double)t.y * g.y;
+            ay += (double)t.x * g.y + (double)t.y * g.x;
+        }
+    }
+    for (int i = lane; i < N; i += 64) {
+        const double sv = (double)sig[s * N + i];
+        ax += sv * v[i].x;
+        ay += sv * v[i].y;
+    }
+    ax = wave_sum(ax);
+    ay = wave_sum(ay);
+    if (lane == 0) u[s] = make_double2(ax, ay);
+}
+
+// u <- u - <O>.v (scalar), so that the contraction gives <O^*(O v)> - <O>^* <O>.v with <O^*> folded.
+__global__ __launch_bounds__(256) void k_dot_ov(long P, const double2* __restrict__ Om, const double2* __restrict__ v,
+                                                double2* __restrict__ red, const double* __restrict__ sc) {
+    if (sc[SC_DONE] != 0.0) return;
+    __shared__ double sh[2][4];
+    double ax = 0, ay = 0;
+    for (long k = (long)blockIdx.x * 256 + threadIdx.x; k < P; k += (long)gridDim.x * 256) {
+        const double2 t = zmul(Om[k], v[k]);
+        ax += t.x; ay += t.y;
+    }
+    ax = wave_sum(ax); ay = wave_sum(ay);
+    if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = ax; sh[1][threadIdx.x >> 6] = ay; }
+    __syncthreads();
+    if (threadIdx.x == 0) red[blockIdx.x] = make_double2(sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3],
+                                                         sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3]);
+}
+
+__global__ __launch_bounds__(256) void k_sub_mean(long n, double2* __restrict__ u, const double2* __restrict__ red,
+                                                  int n_red, const double* __restrict__ sc) {
+    if (sc[SC_DONE] != 0.0) return;
+    double2 m = make_double2(0.0, 0.0);
+    for (int b = 0; b < n_red; ++b) m = zadd(m, red[b]);
+    const long s = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < n) u[s] = make_double2(u[s].x - m.x, u[s].y - m.y);
+}
+
+__global__ void k_add_shift(long P, const double2* __restrict__ x, double eps, double2* __restrict__ y,
+                            const double* __restrict__ sc) {
+    if (sc[SC_DONE] != 0.0) return;
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < P) y[k] = make_double2(y[k].x + eps * x[k].x, y[k].y + eps * x[k].y);
+}
+
+// ------------------------------------------------------------------ CG helpers (double)
+// red[blk] = sum conj(a) b over the block's range
+__global__ __launch_bounds__(256) void k_zdot(long P, const double2* __restrict__ a, const double2* __restrict__ b,
+                                              double2* __restrict__ red, const double* __restrict__ sc, int check) {
+    if (check && sc[SC_DONE] != 0.0) return;
+    __shared__ double sh[2][4];
+    double ax = 0, ay = 0;
+    for (long k = (long)blockIdx.x * 256 + threadIdx.x; k < P; k += (long)gridDim.x * 256) {
+        const double2 t = zconjmul(a[k], b[k]);
+        ax += t.x; ay += t.y;
+    }
+    ax = wave_sum(ax); ay = wave_sum(ay);
+    if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = ax; sh[1][threadIdx.x >> 6] = ay; }
+    __syncthreads();
+    if (threadIdx.x == 0) red[blockIdx.x] = make_double2(sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3],
+                                                         sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3]);
+}
+
+// slot <- Re sum(red)
+__global__ void k_sum_to(const double2* __restrict__ red, int n_red, double* __restrict__ sc, int slot, int check) {
+    if (check && sc[SC_DONE] != 0.0) return;
+    if (threadIdx.x != 0) return;
+    double a = 0;
+    for (int b = 0; b < n_red; ++b) a += red[b].x;
+    sc[slot] = a;
+}
+
+// x += alpha p; r -= alpha Ap  with alpha = rr / pAp
+__global__ __launch_bounds__(256) void k_cg_xr(long P, double2* __restrict__ x, double2* __restrict__ r,
+                                               const double2* __restrict__ p, const double2* __restrict__ Ap,
+                                               const double* __restrict__ sc) {
+    if (sc[SC_DONE] != 0.0) return;
+    const double alpha = sc[SC_RR] / sc[SC_PAP];
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P) return;
+    x[k] = make_double2(x[k].x + alpha * p[k].x, x[k].y + alpha * p[k].y);
+    r[k] = make_double2(r[k].x - alpha * Ap[k].x, r[k].y - alpha * Ap[k].y);
+}
+
+// convergence test and beta; runs after SC_RRNEW is set
+__global__ void k_cg_check(double* __restrict__ sc, double tol, int maxit) {
+    if (threadIdx.x != 0 || sc[SC_DONE] != 0.0) return;
+    sc[SC_ITERS] += 1.0;
+    const double rn = sc[SC_RRNEW];
+    const bool bad = !isfinite(rn) || !(sc[SC_PAP] > 0.0);
+    if (bad) { sc[SC_FLAGS] = (double)((int)sc[SC_FLAGS] | CRBM_FLAG_NONFINITE); sc[SC_DONE] = 1.0; return; }
+    if (sqrt(rn) <= tol * sqrt(sc[SC_FF])) { sc[SC_DONE] = 1.0; sc[SC_RR] = rn; return; }
+    if (sc[SC_ITERS] >= (double)maxit) {
+        sc[SC_FLAGS] = (double)((int)sc[SC_FLAGS] | CRBM_FLAG_NOT_CONVERGED);
+        sc[SC_DONE] = 1.0;
+        sc[SC_RR] = rn;
+        return;
+    }
+    sc[SC_ALPHA] = rn / sc[SC_RR];   // beta of the direction update
+    sc[SC_RR] = rn;
+}
+
+__global__ __launch_bounds__(256) void k_cg_p(long P, double2* __restrict__ p, const double2* __restrict__ r,
+                                              const double* __restrict__ sc) {
+    if (sc[SC_DONE] != 0.0) return;
+    const double beta = sc[SC_ALPHA];
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P) return;
+    p[k] = make_double2(r[k].x + beta * p[k].x, r[k].y + beta * p[k].y);
+}
+
+__global__ __launch_bounds__(256) void k_cg_init(long P, const double2* __restrict__ F, double2* __restrict__ x,
+                                                 double2* __restrict__ r, double2* __restrict__ p) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P) return;
+    x[k] = make_double2(0.0, 0.0);
+    r[k] = F[k];
+    p[k] = F[k];
+}
+
+__global__ void k_cg_start(double* __restrict__ sc) {
+    if (threadIdx.x != 0) return;
+    sc[SC_RR] = sc[SC_FF];
+    sc[SC_DONE] = (sc[SC_FF] == 0.0 || (int)sc[SC_FLAGS] != 0) ? 1.0 : 0.0;
+    sc[SC_ITERS] = 0.0;
+}
+
+// r = F - Ap (true residual), used once after the iterations
+__global__ __launch_bounds__(256) void k_resid(long P, const double2* __restrict__ F, const double2* __restrict__ Ax,
+                                               double2* __restrict__ r) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < P) r[k] = make_double2(F[k].x - Ax[k].x, F[k].y - Ax[k].y);
+}
+
+__global__ void k_undone(double* __restrict__ sc) { if (threadIdx.x == 0) sc[SC_DONE] = 0.0; }
+
+// a, b, W += dalpha  (skipped when the step was flagged non-finite)
+__global__ __launch_bounds__(256) void k_update(int N, int M, float2* __restrict__ a, float2* __restrict__ b,
+                                                float2* __restrict__ W, const double2* __restrict__ x,
+                                                const double* __restrict__ sc) {
+    if (((int)sc[SC_FLAGS] & (CRBM_FLAG_NONFINITE | CRBM_FLAG_CHOLESKY_FAIL)) != 0) return;
+    const long P = (long)N + M + (long)N * M;
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P) return;
+    float2* dst = (k < N) ? &a[k] : (k < N + M) ? &b[k - N] : &W[k - N - M];
+    *dst = make_float2(dst->x + (float)x[k].x, dst->y + (float)x[k].y);
+}
+
+__global__ void k_stats(const double* __restrict__ sc, double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    out[0] = sc[SC_GAMMA];
+    out[1] = sc[SC_RM_RE];
+    out[2] = sc[SC_RM_IM];
+    out[3] = sqrt(sc[SC_FF]);
+    out[4] = sc[SC_FF] > 0.0 ? sqrt(sc[SC_RESID] / sc[SC_FF]) : 0.0;
+    out[5] = sc[SC_ITERS];
+    out[6] = sc[SC_FLAGS];
+    out[7] = sqrt(sc[SC_XX]);
+}
+
+// ------------------------------------------------------------------ driver
+static inline unsigned nblk(long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_cholesky_solve(long P, const float2* S, double eps, const double2* F, double2* A64, double2* x,
+                                 double* sc, hipStream_t stream);
+
+static hipError_t apply_op(const SrArgs& A, const SrWork& W, const double2* v, double2* y, hipStream_t stream) {
+    const long P = A.P;
+    if (A.solver == CRBM_SOLVER_CG_MATFREE) {
+        // G = sigma V_W + V_b  (theta GEMM with b = v_b, W = v_W), into the T-sized scratch
+        float2* vb = W.vstage;
+        float2* vW = vb + A.M;
+        hipLaunchKernelGGL(k_pack_v, dim3(nblk(P)), dim3(256), 0, stream, A.N, A.M, v, vb, vW, W.scal);
+        float2* G = W.G;                                          // [n][M] scratch
+        hipError_t e = launch_theta(A.samples, A.n, A.N, A.M, vb, vW, G, stream, W.scal + SC_DONE);
+        if (e != hipSuccess) return e;
+        const int E = (A.M + 63) / 64;
+        const dim3 g4(nblk(A.n, 4)), b256(256);
+        switch (E) {
+#define CRBM_CASE(e) case e: hipLaunchKernelGGL(k_ov<e>, g4, b256, 0, stream, A.N, A.M, A.samples, A.T, G, v, A.n, W.u, W.scal); break;
+            CRBM_CASE(1) CRBM_CASE(2) CRBM_CASE(3) CRBM_CASE(4) CRBM_CASE(5) CRBM_CASE(6) CRBM_CASE(7) CRBM_CASE(8)
+#undef CRBM_CASE
+            default: return hipErrorInvalidValue;
+        }
+        hipLaunchKernelGGL(k_dot_ov, dim3(64), dim3(256), 0, stream, P, W.Om, v, W.red, W.scal);
+        hipLaunchKernelGGL(k_sub_mean, dim3(nblk(A.n)), dim3(256), 0, stream, A.n, W.u, W.red, 64, W.scal);
+        e = run_ot(A.N, A.M, A.samples, A.T, A.n, 2, 0, 1, A.weights, A.R, W.u, W.red + 64, 0, y, nullptr, stream,
+                   W.scal + SC_DONE);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_add_shift, dim3(nblk(P)), dim3(256), 0, stream, P, v, A.eps, y, W.scal);
+    } else {
+        hipLaunchKernelGGL(k_symv, dim3(nblk(P, 4)), dim3(256), 0, stream, P, W.S, v, A.eps, y, W.scal);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) {
+    const long P = A.P;
+    hipError_t e;
+    // scalars gamma, beta, gamma cot gamma
+    const int nb_r = 256;
+    hipLaunchKernelGGL(k_r_moments, dim3(nb_r), dim3(256), 0, stream, A.R, A.weights, A.n, W.red);
+    hipLaunchKernelGGL(k_r_final, dim3(1), dim3(64), 0, stream, W.red, nb_r, A.dgamma, W.scal);
+    // conj(<O>) and <O^* R>
+    e = run_ot(A.N, A.M, A.samples, A.T, A.n, 0, 1, 2, A.weights, A.R, nullptr, W.red, 0, W.Om, W.ORm, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_make_f, dim3(nblk(P)), dim3(256), 0, stream, P, W.Om, W.ORm, W.scal, W.F);
+    hipLaunchKernelGGL(k_zdot, dim3(64), dim3(256), 0, stream, P, W.F, W.F, W.red, W.scal, 0);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(64), 0, stream, W.red, 64, W.scal, (int)SC_FF, 0);
+
+    if (A.solver != CRBM_SOLVER_CG_MATFREE) {
+        if (A.prec == CRBM_PREC_BF16) {
+            return hipErrorNotSupported;
+        } else {
+            const int nt = (int)((P + SB_T - 1) / SB_T);
+            const long ntri = (long)nt * (nt + 1) / 2;
+            hipLaunchKernelGGL(k_sbuild, dim3((unsigned)ntri), dim3(256), 0, stream, A.N, A.M, P, A.samples, A.T,
+                               A.weights, A.n, W.Om, W.S, nt);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) return e;
+    }
+
+    if (A.solver == CRBM_SOLVER_CHOLESKY) {
+        e = launch_cholesky_solve(P, W.S, A.eps, W.F, W.S64, W.x, W.scal, stream);
+        if (e != hipSuccess) return e;
+        // residual of the double solve against the FP32-stored S
+        hipLaunchKernelGGL(k_undone, dim3(1), dim3(64), 0, stream, W.scal);
+    } else {
+        hipLaunchKernelGGL(k_cg_init, dim3(nblk(P)), dim3(256), 0, stream, P, W.F, W.x, W.r, W.p);
+        hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(64), 0, stream, W.scal);
+        for (int it = 0; it < A.cg_maxit; ++it) {
+            e = apply_op(A, W, W.p, W.Ap, stream);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_zdot, dim3(64), dim3(256), 0, stream, P, W.p, W.Ap, W.red, W.scal, 1);
+            hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(64), 0, stream, W.red, 64, W.scal, (int)SC_PAP, 1);
+            hipLaunchKernelGGL(k_cg_xr, dim3(nblk(P)), dim3(256), 0, stream, P, W.x, W.r, W.p, W.Ap, W.scal);
+            hipLaunchKernelGGL(k_zdot, dim3(64), dim3(256), 0, stream, P, W.r, W.r, W.red, W.scal, 1);
+            hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(64), 0, stream, W.red, 64, W.scal, (int)SC_RRNEW, 1);
+            hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64), 0, stream, W.scal, A.cg_tol, A.cg_maxit);
+            hipLaunchKernelGGL(k_cg_p, dim3(nblk(P)), dim3(256), 0, stream, P, W.p, W.r, W.scal);
+        }
+        hipLaunchKernelGGL(k_undone, dim3(1), dim3(64), 0, stream, W.scal);
+    }
+    // true residual |F - (S + eps) x|^2 in double
+    e = apply_op(A, W, W.x, W.Ap, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_resid, dim3(nblk(P)), dim3(256), 0, stream, P, W.F, W.Ap, W.r);
+    hipLaunchKernelGGL(k_zdot, dim3(64), dim3(256), 0, stream, P, W.r, W.r, W.red, W.scal, 0);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(64), 0, stream, W.red, 64, W.scal, (int)SC_RESID, 0);
+    hipLaunchKernelGGL(k_zdot, dim3(64), dim3(256), 0, stream, P, W.x, W.x, W.red, W.scal, 0);
+    hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(64), 0, stream, W.red, 64, W.scal, (int)SC_XX, 0);
+    hipLaunchKernelGGL(k_update, dim3(nblk(P)), dim3(256), 0, stream, A.N, A.M, A.a, A.b, A.W, W.x, W.scal);
+    if (A.stats) hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, stream, W.scal, A.stats);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ fidelity gradient
+__global__ void k_loss(const float2* __restrict__ R, long n, double* __restrict__ loss) {
+    __shared__ double sh[4];
+    double acc = 0;
+    for (long s = threadIdx.x; s < n; s += blockDim.x) {
+        const double x = 1.0 - (double)R[s].x, y = -(double)R[s].y;
+        acc += x * x + y * y;
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) *loss = (sh[0] + sh[1] + sh[2] + sh[3]) / (double)n;
+}
+
+hipError_t launch_fidelity_grad(const GradArgs& A, const SrWork& W, hipStream_t stream) {
+    hipError_t e = run_ot(A.N, A.M, A.samples, A.T, A.n, 3, 0, 1, nullptr, A.R, nullptr, W.red, 0, A.grad, nullptr,
+                          stream);
+    if (e != hipSuccess) return e;
+    if (A.loss) hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, stream, A.R, A.n, A.loss);
+    return hipGetLastError();
+}
+
+}  // namespace crbm

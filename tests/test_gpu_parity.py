@@ -1,0 +1,321 @@
+"""GPU parity: every entry point of the HIP library against the FP64 oracle.
+
+Tolerances (FP32 kernels vs FP64 definitions): log psi (Re, relative to its
+magnitude), local energies, R, tanh theta and O within 1e-5 relative; Im log psi
+by the wrapped difference; Philox streams, chain starts, proposals and
+Metropolis trajectories bit-exact (decisions replayed with a 1e-4 margin).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2103_08804_amd as crbm
+import synth
+from gpu_util import np_of, rel_err, to_device_rbm, to_oracle_rbm, wrapped
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    crbm.lib()
+
+
+def _plan(kind, Lx, Ly, M, n, flags=0):
+    return crbm.Plan(kind, Lx, Ly, M, n, flags)
+
+
+# ------------------------------------------------------------------ init
+@pytest.mark.parametrize("N,M,seed,std", [(10, 10, 1001, 0.01), (100, 400, 1003, 0.01), (7, 3, 5, 0.7)])
+def test_init_rbm(orc, N, M, seed, std):
+    dev = crbm.RBM.empty(N, M)
+    crbm.init_rbm(dev, seed, std)
+    torch.cuda.synchronize()
+    ref = orc.init_rbm(N, M, seed, std)
+    got = to_oracle_rbm(orc, dev)
+    for g, r in ((got.a, ref.a), (got.b, ref.b), (got.W, ref.W)):
+        assert np.max(np.abs(g - r)) <= 2e-6 * std * 8, np.max(np.abs(g - r))
+
+
+@pytest.mark.parametrize("N,C,zero", [(10, 33, 1), (40, 1024, 1), (100, 70, 1), (256, 5, 1), (13, 65, 0)])
+def test_init_chains_bit_exact(orc, N, C, zero):
+    kind, Lx, Ly = (0, N, 1)
+    plan = _plan(kind, Lx, Ly, 4, 1)
+    s = torch.zeros(C, N, dtype=torch.int8, device="cuda")
+    crbm.init_chains(plan, s, 2002, bool(zero))
+    torch.cuda.synchronize()
+    assert np.array_equal(np_of(s), orc.init_chains(N, C, 2002, zero))
+
+
+# ------------------------------------------------------------------ local estimators
+CASES = [
+    # kind, Lx, Ly, M, n_samples (None = full enumeration), param std
+    (0, 10, 1, 10, None, 0.01),
+    (0, 10, 1, 10, None, 0.3),
+    (0, 40, 1, 80, 97, 0.05),
+    (1, 4, 4, 24, 333, 0.2),
+    (1, 10, 10, 400, 45, 0.01),
+    (1, 10, 10, 400, 19, 0.05),
+    (1, 16, 16, 512, 9, 0.02),
+]
+
+
+def _samples(orc, N, n, seed):
+    if n is None:
+        return orc.enumerate_configs(N)
+    return synth.random_spins(seed, n, N, zero_magnetisation=(N % 2 == 0))
+
+
+@pytest.mark.parametrize("kind,Lx,Ly,M,n,std", CASES)
+def test_local_energy_logpsi_tanh_O(orc, kind, Lx, Ly, M, n, std):
+    N = Lx * Ly
+    lat = orc.Lattice(kind, Lx, Ly)
+    fit_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(7 + N, N, M, std)))
+    fit = to_oracle_rbm(orc, fit_d)
+    sig = _samples(orc, N, n, 11 + N)
+    ns = sig.shape[0]
+    plan = _plan(kind, Lx, Ly, M, ns)
+    sig_d = torch.from_numpy(sig).cuda()
+    lp = torch.zeros(ns, dtype=torch.complex64, device="cuda")
+    el = torch.zeros_like(lp)
+    T = torch.zeros(ns, M, dtype=torch.complex64, device="cuda")
+    want_O = plan.P * ns <= 4_000_000
+    O = torch.zeros(ns, plan.P, dtype=torch.complex64, device="cuda") if want_O else None
+    crbm.local_estimators(plan, fit_d, sig_d, logpsi_out=lp, eloc_out=el, tanh_out=T, O_out=O)
+    torch.cuda.synchronize()
+    lp_ref = orc.logpsi(fit, sig)
+    el_ref = orc.local_energy(fit, lat, sig)
+    O_ref = orc.logderiv(fit, sig)
+    got_lp = np_of(lp).astype(np.complex128)
+    assert np.max(np.abs(got_lp.real - lp_ref.real) / np.maximum(np.abs(lp_ref.real), 1.0)) < TOL
+    assert np.max(np.abs(wrapped(got_lp.imag - lp_ref.imag))) < TOL * max(1.0, np.abs(lp_ref).max())
+    assert rel_err(np_of(el), el_ref) < TOL
+    assert rel_err(np_of(T), O_ref[:, N:N + M]) < TOL
+    if want_O:
+        assert rel_err(np_of(O), O_ref) < TOL
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 6])
+@pytest.mark.parametrize("kind,Lx,Ly,M,n,std", [CASES[1], CASES[3], CASES[5]])
+def test_target_ratio(orc, order, kind, Lx, Ly, M, n, std):
+    N = Lx * Ly
+    lat = orc.Lattice(kind, Lx, Ly)
+    rb = lambda s: to_device_rbm(orc.RBM(*synth.random_rbm_arrays(s, N, M, std)))
+    fit_d, psn_d, psm_d = rb(100 + order), rb(200 + order), rb(300 + order)
+    fit, psn, psm = (to_oracle_rbm(orc, r) for r in (fit_d, psn_d, psm_d))
+    sig = _samples(orc, N, n, 5 + order)
+    ns = sig.shape[0]
+    E_c, W_scale = -0.6 * N * 0.9875 + 0.1, 1.5 * 0.45 * N
+    bn, bm = 0.8 - 0.3j, 1.2 + 0.1j
+    q = (np.pi, 0.0) if kind == 0 else (np.pi / 2, np.pi)
+    plan = _plan(kind, Lx, Ly, M, ns)
+    cheb = crbm.make_cheb(order, E_c, W_scale, bn, bm, q)
+    R = torch.zeros(ns, dtype=torch.complex64, device="cuda")
+    hp = torch.zeros_like(R)
+    crbm.local_estimators(plan, fit_d, torch.from_numpy(sig).cuda(), psi_n=psn_d,
+                          psi_nm1=psm_d if order >= 1 else None, cheb=cheb, R_out=R, eloc_out=hp)
+    torch.cuda.synchronize()
+    R_ref, hp_ref = orc.target_ratio(fit, psn, psm if order >= 1 else None, lat, sig, order, E_c, W_scale, bn, bm,
+                                     q, return_hpsi=True)
+    assert rel_err(np_of(R), R_ref) < TOL
+    assert rel_err(np_of(hp), hp_ref) < TOL
+
+
+# ------------------------------------------------------------------ Metropolis sampling
+@pytest.mark.parametrize("kind,Lx,Ly,M,C,sweeps,proposal,std", [
+    (0, 10, 1, 10, 37, 20, 0, 0.3),
+    (0, 10, 1, 10, 37, 20, 1, 0.3),
+    (0, 40, 1, 80, 64, 8, 1, 0.05),
+    (1, 10, 10, 400, 8, 3, 1, 0.02),
+    (1, 16, 16, 512, 3, 1, 1, 0.02),
+    (1, 4, 4, 24, 129, 10, 0, 0.4),
+])
+def test_sample_replay(orc, kind, Lx, Ly, M, C, sweeps, proposal, std):
+    N = Lx * Ly
+    psi_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(31 + N, N, M, std)))
+    psi = to_oracle_rbm(orc, psi_d)
+    plan = _plan(kind, Lx, Ly, M, 1)
+    spins = torch.zeros(C, N, dtype=torch.int8, device="cuda")
+    crbm.init_chains(plan, spins, 2000 + N, proposal == 1)
+    s0 = np_of(spins).copy()
+    words = (sweeps * N + 31) // 32
+    samples = torch.zeros(sweeps, C, N, dtype=torch.int8, device="cuda")
+    nacc = torch.zeros(C, dtype=torch.int32, device="cuda")
+    trace = torch.zeros(C, words, dtype=torch.int32, device="cuda")
+    theta = torch.zeros(C, M, dtype=torch.complex64, device="cuda")
+    lp = torch.zeros(C, dtype=torch.complex64, device="cuda")
+    seed, off = 77 + N, 1234
+    crbm.sample(plan, psi_d, spins, sweeps, proposal, seed, off, theta_out=theta, logpsi_out=lp,
+                samples_out=samples, n_accept=nacc, trace=trace)
+    torch.cuda.synchronize()
+    s_ref = s0.copy()
+    tr = np_of(trace).view(np.uint32)
+    smp_ref, nacc_ref, amb, mis = orc.metropolis(psi, s_ref, sweeps, proposal, seed, off, trace=tr)
+    assert mis == 0
+    assert np.array_equal(np_of(samples), smp_ref)
+    assert np.array_equal(np_of(spins), s_ref)
+    assert np.array_equal(np_of(nacc).view(np.uint32), nacc_ref)
+    total_moves = sweeps * N * C
+    assert amb <= max(3, 1e-3 * total_moves)
+    # state of the chains at the end
+    lp_ref = orc.logpsi(psi, s_ref)
+    got = np_of(lp).astype(np.complex128)
+    assert np.max(np.abs(got.real - lp_ref.real) / np.maximum(np.abs(lp_ref.real), 1.0)) < TOL
+    th_ref = orc.RBM(psi.a, psi.b, psi.W)
+    theta_ref = psi.b[None, :] + s_ref.astype(np.float64) @ psi.W
+    assert rel_err(np_of(theta), theta_ref) < 1e-5
+
+
+def test_sample_continuation_matches_single_call(orc):
+    """Two calls with step_offset continue the same Philox streams as one longer call."""
+    N, M, C = 12, 6, 20
+    psi_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(3, N, M, 0.3)))
+    plan = _plan(0, N, 1, M, 1)
+    a = torch.zeros(C, N, dtype=torch.int8, device="cuda")
+    crbm.init_chains(plan, a, 9, True)
+    b = a.clone()
+    sa = torch.zeros(6, C, N, dtype=torch.int8, device="cuda")
+    crbm.sample(plan, psi_d, a, 6, 1, 5, 0, samples_out=sa)
+    s1 = torch.zeros(2, C, N, dtype=torch.int8, device="cuda")
+    s2 = torch.zeros(4, C, N, dtype=torch.int8, device="cuda")
+    crbm.sample(plan, psi_d, b, 2, 1, 5, 0, samples_out=s1)
+    crbm.sample(plan, psi_d, b, 4, 1, 5, 2 * N, samples_out=s2)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.cat([s1, s2]), sa)
+    assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------------ natural-gradient step
+def _sr_inputs(orc, N, M, std, seed):
+    fit_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(seed, N, M, std)))
+    fit = to_oracle_rbm(orc, fit_d)
+    sig = orc.enumerate_configs(N)
+    p = orc.enum_weights(orc.logpsi(fit, sig))
+    r = np.random.default_rng(seed)
+    R = (1.0 + 0.4 * r.normal(size=sig.shape[0]) + 0.3j * r.normal(size=sig.shape[0])).astype(np.complex64)
+    return fit_d, fit, sig, p, R
+
+
+@pytest.mark.parametrize("solver,flags", [(crbm.CG_DENSE, crbm.PLAN_DENSE_S), (crbm.CG_MATFREE, 0),
+                                          (crbm.CHOLESKY, crbm.PLAN_CHOLESKY)])
+def test_sr_step_enumeration(orc, solver, flags):
+    N, M = 10, 10
+    fit_d, fit, sig, p, R = _sr_inputs(orc, N, M, 0.3, 4)
+    ns = sig.shape[0]
+    plan = _plan(0, N, 1, M, ns, flags)
+    sig_d = torch.from_numpy(sig).cuda()
+    T = torch.zeros(ns, M, dtype=torch.complex64, device="cuda")
+    crbm.local_estimators(plan, fit_d, sig_d, tanh_out=T)
+    R_d = torch.from_numpy(R).cuda()
+    w_d = torch.from_numpy(p).cuda()
+    stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+    eps, dg = 1e-3, 0.1
+    crbm.sr_step(plan, fit_d, sig_d, T, R_d, dg, eps, solver, crbm.FP32, 1e-10, 2000, stats, weights=w_d)
+    F = torch.zeros(plan.P, dtype=torch.complex128, device="cuda")
+    dx = torch.zeros_like(F)
+    Om = torch.zeros_like(F)
+    crbm.copy_plan_buffer(plan, crbm.BUF_F, F)
+    crbm.copy_plan_buffer(plan, crbm.BUF_DALPHA, dx)
+    crbm.copy_plan_buffer(plan, crbm.BUF_OMEAN, Om)
+    torch.cuda.synchronize()
+    new_ref, info = orc.sr_step(fit, sig, R.astype(np.complex128), dg, eps, weights=p, want_S=True)
+    st = np_of(stats)
+    assert abs(st[0] - info["gamma"]) < 1e-6
+    assert abs(complex(st[1], st[2]) - info["beta"]) < 1e-6 * abs(info["beta"])
+    assert int(st[6]) == 0, st
+    O = orc.logderiv(fit, sig)
+    assert rel_err(np_of(Om), p @ O) < TOL
+    assert rel_err(np_of(F), info["F"]) < 1e-5
+    # S is stored in FP32: the solution carries its rounding times the condition number
+    assert rel_err(np_of(dx), info["dalpha"]) < 2e-3
+    got_new = to_oracle_rbm(orc, fit_d).vector()
+    assert rel_err(got_new - fit.vector(), info["dalpha"]) < 2e-3
+    if solver == crbm.CG_DENSE:
+        S = torch.zeros(plan.P, plan.P, dtype=torch.complex64, device="cuda")
+        crbm.copy_plan_buffer(plan, crbm.BUF_S, S)
+        torch.cuda.synchronize()
+        assert rel_err(np_of(S), info["S"]) < 1e-5
+
+
+def test_sr_step_mc_weights_dense_vs_matfree(orc):
+    """Uniform MC weights, square lattice: dense and matrix-free CG agree and match the oracle's F."""
+    kind, Lx, Ly, M = 1, 4, 4, 8
+    N = 16
+    fit_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(8, N, M, 0.2)))
+    fit = to_oracle_rbm(orc, fit_d)
+    sig = synth.random_spins(9, 777, N, True)
+    r = np.random.default_rng(1)
+    R = (1 + 0.3 * r.normal(size=777) + 0.2j * r.normal(size=777)).astype(np.complex64)
+    res = []
+    for solver, flags in ((crbm.CG_DENSE, crbm.PLAN_DENSE_S), (crbm.CG_MATFREE, 0)):
+        fd = crbm.RBM(fit_d.a.clone(), fit_d.b.clone(), fit_d.W.clone())
+        plan = _plan(kind, Lx, Ly, M, 777, flags)
+        sd = torch.from_numpy(sig).cuda()
+        T = torch.zeros(777, M, dtype=torch.complex64, device="cuda")
+        crbm.local_estimators(plan, fd, sd, tanh_out=T)
+        stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+        crbm.sr_step(plan, fd, sd, T, torch.from_numpy(R).cuda(), 0.2, 1e-2, solver, crbm.FP32, 1e-10, 1000, stats)
+        dx = torch.zeros(plan.P, dtype=torch.complex128, device="cuda")
+        crbm.copy_plan_buffer(plan, crbm.BUF_DALPHA, dx)
+        torch.cuda.synchronize()
+        assert int(np_of(stats)[6]) == 0
+        res.append(np_of(dx))
+    _, info = orc.sr_step(fit, sig, R.astype(np.complex128), 0.2, 1e-2)
+    assert rel_err(res[0], info["dalpha"]) < 1e-3
+    assert rel_err(res[1], info["dalpha"]) < 1e-3
+
+
+# ------------------------------------------------------------------ moments and gradient
+@pytest.mark.parametrize("kind,Lx,Ly,M,n,std", [CASES[1], CASES[3]])
+def test_chebyshev_moments(orc, kind, Lx, Ly, M, n, std):
+    N = Lx * Ly
+    lat = orc.Lattice(kind, Lx, Ly)
+    gs_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(50, N, M, std)))
+    gs = to_oracle_rbm(orc, gs_d)
+    n_max = 5
+    P = N + M + N * M
+    tvec = []
+    for t in range(n_max):
+        tvec.append(orc.RBM(*synth.random_rbm_arrays(51 + t, N, M, std)).vector())
+    tp = torch.from_numpy(np.stack(tvec).astype(np.complex64)).cuda()
+    ts = [orc.RBM.from_vector(np_of(tp[t]).astype(np.complex128), N, M) for t in range(n_max)]
+    betas = np.array([1.0, 0.9 - 0.2j, -0.5 + 0.1j, 0.3j, 2.0])
+    sig = _samples(orc, N, n, 3)
+    ns = sig.shape[0]
+    w = orc.enum_weights(orc.logpsi(gs, sig)) if n is None else None
+    qs = [(np.pi, 0.0), (2 * np.pi / Lx, 0.0)] if kind == 0 else [(np.pi, np.pi), (np.pi / 2, 0.0), (0.0, np.pi)]
+    plan = _plan(kind, Lx, Ly, M, ns)
+    mu = torch.zeros(len(qs), n_max + 1, dtype=torch.complex128, device="cuda")
+    crbm.chebyshev_moment(plan, gs_d, tp, torch.from_numpy(betas).cuda(), qs, torch.from_numpy(sig).cuda(), mu,
+                          weights=None if w is None else torch.from_numpy(w).cuda())
+    torch.cuda.synchronize()
+    ref = orc.moments(gs, ts, betas, qs, lat, sig, weights=w)
+    assert rel_err(np_of(mu), ref) < TOL
+
+
+def test_fidelity_grad(orc):
+    kind, Lx, Ly, M = 1, 4, 4, 8
+    N = 16
+    lat = orc.Lattice(kind, Lx, Ly)
+    rb = lambda s: to_device_rbm(orc.RBM(*synth.random_rbm_arrays(s, N, M, 0.2)))
+    fit_d, psn_d, psm_d = rb(1), rb(2), rb(3)
+    fit, psn, psm = (to_oracle_rbm(orc, r) for r in (fit_d, psn_d, psm_d))
+    sig = synth.random_spins(4, 300, N, True)
+    plan = _plan(kind, Lx, Ly, M, 300)
+    cheb = crbm.make_cheb(3, -10.0, 16.0, 0.9, 1.1)
+    sd = torch.from_numpy(sig).cuda()
+    R = torch.zeros(300, dtype=torch.complex64, device="cuda")
+    T = torch.zeros(300, M, dtype=torch.complex64, device="cuda")
+    crbm.local_estimators(plan, fit_d, sd, psi_n=psn_d, psi_nm1=psm_d, cheb=cheb, R_out=R, tanh_out=T)
+    g = torch.zeros(plan.P, dtype=torch.complex128, device="cuda")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    crbm.fidelity_grad(plan, fit_d, sd, T, R, g, loss)
+    torch.cuda.synchronize()
+    R_ref = orc.target_ratio(fit, psn, psm, lat, sig, 3, -10.0, 16.0, 0.9, 1.1)
+    L_ref, g_ref = orc.fidelity_grad(fit, sig, R_ref)
+    assert abs(np_of(loss)[0] - L_ref) < 1e-5 * max(1.0, L_ref)
+    assert rel_err(np_of(g), g_ref) < 1e-5
