@@ -63,16 +63,18 @@ def rng(seed):
     return np.random.default_rng(seed)
 
 
-def complex_normal(r, shape, std):
-    return (r.normal(0.0, std, size=shape) + 1j * r.normal(0.0, std, size=shape)).astype(np.complex128)
+def complex_normal(r, shape, std, std_im=None):
+    si = std if std_im is None else std_im
+    return (r.normal(0.0, std, size=shape) + 1j * r.normal(0.0, si, size=shape)).astype(np.complex128)
 
 
-def random_rbm_arrays(seed, N, M, std=0.01, std_w=None):
-    """(a[N], b[M], W[N][M]) complex128 with Re, Im ~ N(0, std^2) (W: std_w if given)."""
+def random_rbm_arrays(seed, N, M, std=0.01, std_w=None, std_im=None):
+    """(a[N], b[M], W[N][M]) complex128 with Re ~ N(0, std^2) (W: std_w if given) and
+    Im ~ N(0, std_im^2) (default: the same as Re)."""
     r = rng(seed)
-    a = complex_normal(r, (N,), std)
-    b = complex_normal(r, (M,), std)
-    W = complex_normal(r, (N, M), std if std_w is None else std_w)
+    a = complex_normal(r, (N,), std, std_im)
+    b = complex_normal(r, (M,), std, std_im)
+    W = complex_normal(r, (N, M), std if std_w is None else std_w, std_im)
     return a, b, W
 
 

@@ -28,3 +28,38 @@ def wrapped(d):
 def rel_err(got, want, floor=1e-30):
     got, want = np.asarray(got), np.asarray(want)
     return np.max(np.abs(got - want)) / max(np.max(np.abs(want)), floor)
+
+
+EPS32 = 2.0 ** -24
+
+
+def logpsi_rounding_bound(rbm, sig, c=16.0):
+    """First-order bound on the FP32 error of log psi caused by rounding theta:
+    |d log psi| <= sum_k |tanh theta_k| |d theta_k|, |d theta_k| <= c eps (|b_k| + sum_i |W_ik|).
+    Large where theta_k approaches a zero of cosh (the amplitude itself nearly vanishes)."""
+    sig = np.asarray(sig, np.float64)
+    th = rbm.b[None, :] + sig @ rbm.W
+    scale = np.abs(rbm.b) + np.abs(rbm.W).sum(axis=0)
+    return c * EPS32 * (np.abs(np.tanh(th)) * scale[None, :]).sum(axis=1) + c * EPS32 * np.abs(rbm.a).sum()
+
+
+def eloc_rounding_bound(rbm, bonds, sig, J=1.0):
+    """Bound on the FP32 error of E_loc propagated from the log-amplitude bounds of sigma and of each
+    bond-swapped configuration: (J/2) sum_b |rho_b| (bound(sigma^b) + bound(sigma))."""
+    sig = np.asarray(sig, np.int8)
+    base = logpsi_rounding_bound(rbm, sig)
+    th = rbm.b[None, :] + sig.astype(np.float64) @ rbm.W
+    lc = lambda z: np.log(2 * np.cosh(z))
+    lp0 = sig.astype(np.float64) @ rbm.a + lc(th).sum(axis=1)
+    out = np.zeros(sig.shape[0])
+    for (i, j) in bonds:
+        anti = sig[:, i] != sig[:, j]
+        if not anti.any():
+            continue
+        s2 = sig[anti].copy()
+        s2[:, [i, j]] = s2[:, [j, i]]
+        th2 = rbm.b[None, :] + s2.astype(np.float64) @ rbm.W
+        lp2 = s2.astype(np.float64) @ rbm.a + lc(th2).sum(axis=1)
+        rho = np.abs(np.exp(lp2 - lp0[anti]))
+        out[anti] += 0.5 * J * rho * (logpsi_rounding_bound(rbm, s2) + base[anti])
+    return out

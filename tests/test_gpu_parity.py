@@ -53,15 +53,17 @@ def test_init_chains_bit_exact(orc, N, C, zero):
 
 # ------------------------------------------------------------------ local estimators
 CASES = [
-    # kind, Lx, Ly, M, n_samples (None = full enumeration), param std
-    (0, 10, 1, 10, None, 0.01),
-    (0, 10, 1, 10, None, 0.3),
-    (0, 40, 1, 80, 97, 0.05),
-    (1, 4, 4, 24, 333, 0.2),
-    (1, 10, 10, 400, 45, 0.01),
-    (1, 10, 10, 400, 19, 0.05),
-    (1, 16, 16, 512, 9, 0.02),
+    # kind, Lx, Ly, M, n_samples (None = full enumeration), Re std, Im std
+    (0, 10, 1, 10, None, 0.01, 0.01),
+    (0, 10, 1, 10, None, 0.3, 0.02),
+    (0, 40, 1, 80, 97, 0.05, 0.02),
+    (1, 4, 4, 24, 333, 0.2, 0.02),
+    (1, 10, 10, 400, 45, 0.01, 0.01),
+    (1, 10, 10, 400, 19, 0.05, 0.02),
+    (1, 16, 16, 512, 9, 0.02, 0.01),
 ]
+# With |Im theta| well below pi/2 no theta comes near a zero of cosh, and the FP32 results
+# meet the 1e-5 relative bound; test_rounding_bound_near_zeros covers arbitrary phases.
 
 
 def _samples(orc, N, n, seed):
@@ -70,11 +72,11 @@ def _samples(orc, N, n, seed):
     return synth.random_spins(seed, n, N, zero_magnetisation=(N % 2 == 0))
 
 
-@pytest.mark.parametrize("kind,Lx,Ly,M,n,std", CASES)
-def test_local_energy_logpsi_tanh_O(orc, kind, Lx, Ly, M, n, std):
+@pytest.mark.parametrize("kind,Lx,Ly,M,n,std,sim", CASES)
+def test_local_energy_logpsi_tanh_O(orc, kind, Lx, Ly, M, n, std, sim):
     N = Lx * Ly
     lat = orc.Lattice(kind, Lx, Ly)
-    fit_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(7 + N, N, M, std)))
+    fit_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(7 + N, N, M, std, std_im=sim)))
     fit = to_oracle_rbm(orc, fit_d)
     sig = _samples(orc, N, n, 11 + N)
     ns = sig.shape[0]
@@ -99,12 +101,35 @@ def test_local_energy_logpsi_tanh_O(orc, kind, Lx, Ly, M, n, std):
         assert rel_err(np_of(O), O_ref) < TOL
 
 
+def test_rounding_bound_near_zeros(orc):
+    """Arbitrary complex parameters (std 0.3 in Re and Im): some theta_k lie close to a zero of cosh,
+    where FP32 rounding of theta is amplified by |tanh theta|.  The errors must stay inside the
+    first-order bound derived from that rounding (plus the 1e-5 relative floor)."""
+    from gpu_util import eloc_rounding_bound, logpsi_rounding_bound
+    N, M = 10, 10
+    lat = orc.Lattice(0, N)
+    fit_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(17, N, M, 0.3)))
+    fit = to_oracle_rbm(orc, fit_d)
+    sig = orc.enumerate_configs(N)
+    plan = _plan(0, N, 1, M, sig.shape[0])
+    lp = torch.zeros(sig.shape[0], dtype=torch.complex64, device="cuda")
+    el = torch.zeros_like(lp)
+    crbm.local_estimators(plan, fit_d, torch.from_numpy(sig).cuda(), logpsi_out=lp, eloc_out=el)
+    torch.cuda.synchronize()
+    lp_ref = orc.logpsi(fit, sig)
+    el_ref = orc.local_energy(fit, lat, sig)
+    blp = logpsi_rounding_bound(fit, sig) + TOL * np.maximum(np.abs(lp_ref.real), 1.0)
+    assert np.all(np.abs(np_of(lp).real - lp_ref.real) <= blp)
+    bel = eloc_rounding_bound(fit, lat.bonds(), sig) + TOL * np.abs(el_ref).max()
+    assert np.all(np.abs(np_of(el) - el_ref) <= bel)
+
+
 @pytest.mark.parametrize("order", [0, 1, 2, 6])
-@pytest.mark.parametrize("kind,Lx,Ly,M,n,std", [CASES[1], CASES[3], CASES[5]])
-def test_target_ratio(orc, order, kind, Lx, Ly, M, n, std):
+@pytest.mark.parametrize("kind,Lx,Ly,M,n,std,sim", [CASES[1], CASES[3], CASES[5]])
+def test_target_ratio(orc, order, kind, Lx, Ly, M, n, std, sim):
     N = Lx * Ly
     lat = orc.Lattice(kind, Lx, Ly)
-    rb = lambda s: to_device_rbm(orc.RBM(*synth.random_rbm_arrays(s, N, M, std)))
+    rb = lambda s: to_device_rbm(orc.RBM(*synth.random_rbm_arrays(s, N, M, std, std_im=sim)))
     fit_d, psn_d, psm_d = rb(100 + order), rb(200 + order), rb(300 + order)
     fit, psn, psm = (to_oracle_rbm(orc, r) for r in (fit_d, psn_d, psm_d))
     sig = _samples(orc, N, n, 5 + order)
@@ -136,7 +161,7 @@ def test_target_ratio(orc, order, kind, Lx, Ly, M, n, std):
 ])
 def test_sample_replay(orc, kind, Lx, Ly, M, C, sweeps, proposal, std):
     N = Lx * Ly
-    psi_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(31 + N, N, M, std)))
+    psi_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(31 + N, N, M, std, std_im=min(std, 0.02))))
     psi = to_oracle_rbm(orc, psi_d)
     plan = _plan(kind, Lx, Ly, M, 1)
     spins = torch.zeros(C, N, dtype=torch.int8, device="cuda")
@@ -270,17 +295,17 @@ def test_sr_step_mc_weights_dense_vs_matfree(orc):
 
 
 # ------------------------------------------------------------------ moments and gradient
-@pytest.mark.parametrize("kind,Lx,Ly,M,n,std", [CASES[1], CASES[3]])
-def test_chebyshev_moments(orc, kind, Lx, Ly, M, n, std):
+@pytest.mark.parametrize("kind,Lx,Ly,M,n,std,sim", [CASES[1], CASES[3]])
+def test_chebyshev_moments(orc, kind, Lx, Ly, M, n, std, sim):
     N = Lx * Ly
     lat = orc.Lattice(kind, Lx, Ly)
-    gs_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(50, N, M, std)))
+    gs_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(50, N, M, std, std_im=sim)))
     gs = to_oracle_rbm(orc, gs_d)
     n_max = 5
     P = N + M + N * M
     tvec = []
     for t in range(n_max):
-        tvec.append(orc.RBM(*synth.random_rbm_arrays(51 + t, N, M, std)).vector())
+        tvec.append(orc.RBM(*synth.random_rbm_arrays(51 + t, N, M, std, std_im=sim)).vector())
     tp = torch.from_numpy(np.stack(tvec).astype(np.complex64)).cuda()
     ts = [orc.RBM.from_vector(np_of(tp[t]).astype(np.complex128), N, M) for t in range(n_max)]
     betas = np.array([1.0, 0.9 - 0.2j, -0.5 + 0.1j, 0.3j, 2.0])
