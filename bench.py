@@ -1,0 +1,230 @@
+"""Benchmark of the Chebyshev-RBM hot path on one MI355X.
+
+Workload: 2D Heisenberg model on a periodic 10 x 10 square lattice (N = 100),
+complex RBMs with alpha = 4 (M = 400, P = 40,500 parameters), 4096 Markov
+chains x 128 sweeps of N pair-exchange proposals at total S^z = 0.
+
+One step = one pass over every stage of the hot path on one batch:
+  1. sample the fitted state t~_{n+1}: 4096 chains x 128 sweeps -> 524,288 samples
+  2. local estimators: theta, tanh(theta), local energy of t~_n and the
+     Chebyshev target ratio R = (2 beta_n H~ t~_n - beta_{n-1} t~_{n-1}) / t~_{n+1}
+  3. natural-gradient step: <R>, gamma, F, dense S = <O^* O> - <O>^*<O> on the
+     matrix cores (BF16 operands, FP32 accumulation), CG with double vectors
+     (diagonal shift 1e-4, tol 1e-6, at most 500 iterations), parameter update
+  4. sample psi_gs: 4096 chains x 128 sweeps
+  5. Chebyshev moments mu_n(q), n <= 20, q = (pi, pi), double accumulation
+Inputs are synthetic (seeded complex-normal parameters, Fisher-Yates starts).
+
+Prints one JSON line.  value = fitted samples per second of the whole step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+import synth  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+FP32_MATRIX_PEAK_TFLOPS = 157.3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", choices=["bf16", "fp32"], default="bf16")
+    ap.add_argument("--solver", choices=["dense", "matfree"], default="dense")
+    ap.add_argument("--chains", type=int, default=synth.SQUARE10.chains)
+    ap.add_argument("--sweeps", type=int, default=synth.SQUARE10.sweeps)
+    ap.add_argument("--cg-maxit", type=int, default=500)
+    ap.add_argument("--n-moments", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import paper_2103_08804_amd as crbm
+
+    torch.cuda.set_device(0)
+    wl = synth.SQUARE10
+    N, M, P = wl.N, wl.M, wl.P
+    C, sweeps = args.chains, args.sweeps
+    ns = C * sweeps
+    prec = crbm.BF16 if args.precision == "bf16" else crbm.FP32
+    solver = crbm.CG_DENSE if args.solver == "dense" else crbm.CG_MATFREE
+    flags = crbm.PLAN_DENSE_S if solver == crbm.CG_DENSE else 0
+    plan = crbm.Plan(crbm.SQUARE, wl.Lx, wl.Ly, M, ns, flags)
+
+    # synthetic RBMs: psi_gs, t~_{n-1}, t~_n and the fitted t~_{n+1}; n_moments stored RBMs for mu_n
+    def new_rbm(seed):
+        r = crbm.RBM.empty(N, M)
+        crbm.init_rbm(r, seed, wl.param_std)
+        return r
+
+    gs, psm, psn, fit = new_rbm(wl.param_seed), new_rbm(wl.param_seed + 1), new_rbm(wl.param_seed + 2), \
+        new_rbm(wl.param_seed + 3)
+    n_max = args.n_moments
+    tp = torch.zeros(n_max, P, dtype=torch.complex64, device="cuda")
+    for t in range(n_max):
+        crbm.init_rbm(crbm.RBM.from_packed(tp[t], N, M), wl.param_seed + 10 + t, wl.param_std)
+    betas = torch.ones(n_max, dtype=torch.complex128, device="cuda")
+    E0 = synth.E0_PER_SITE_SQUARE * N
+    W_scale = 1.5 * abs(E0)
+    E_c = E0 + (1.0 - 0.0125) * W_scale
+    cheb = crbm.make_cheb(2, E_c, W_scale, 1.0, 1.0, (math.pi, math.pi))
+
+    chains_fit = torch.zeros(C, N, dtype=torch.int8, device="cuda")
+    chains_gs = torch.zeros(C, N, dtype=torch.int8, device="cuda")
+    crbm.init_chains(plan, chains_fit, wl.chain_seed, True)
+    crbm.init_chains(plan, chains_gs, wl.chain_seed + 1, True)
+    samples = torch.zeros(sweeps, C, N, dtype=torch.int8, device="cuda")
+    samples_gs = torch.zeros(sweeps, C, N, dtype=torch.int8, device="cuda")
+    flat, flat_gs = samples.view(ns, N), samples_gs.view(ns, N)
+    T = torch.zeros(ns, M, dtype=torch.complex64, device="cuda")
+    R = torch.zeros(ns, dtype=torch.complex64, device="cuda")
+    El = torch.zeros(ns, dtype=torch.complex64, device="cuda")
+    stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+    mu = torch.zeros(1, n_max + 1, dtype=torch.complex128, device="cuda")
+    # burn-in (untimed)
+    crbm.sample(plan, fit, chains_fit, 16, crbm.EXCHANGE, 11, 0)
+    crbm.sample(plan, gs, chains_gs, 16, crbm.EXCHANGE, 12, 0)
+    offset = [16 * N]
+
+    def step():
+        crbm.sample(plan, fit, chains_fit, sweeps, crbm.EXCHANGE, 11, offset[0], samples_out=samples)
+        crbm.local_estimators(plan, fit, flat, psi_n=psn, psi_nm1=psm, cheb=cheb, eloc_out=El, R_out=R, tanh_out=T)
+        crbm.sr_step(plan, fit, flat, T, R, 0.1, wl.diag_shift, solver, prec, 1e-6, args.cg_maxit, stats)
+        crbm.sample(plan, gs, chains_gs, sweeps, crbm.EXCHANGE, 12, offset[0], samples_out=samples_gs)
+        crbm.chebyshev_moment(plan, gs, tp, betas, [(math.pi, math.pi)], flat_gs, mu)
+        offset[0] += sweeps * N
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = plan.profile_read()
+    plan.profile(False)
+    st = stats.cpu().numpy()
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = ns / (elapsed / args.steps)
+
+    phases = {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof.items()}
+    # dominant kernel: the dense S contraction (matrix cores) when it runs, else the O^H c contraction
+    if "sbuild" in prof and solver == crbm.CG_DENSE:
+        c, t = prof["sbuild"]
+        avg_s = t / c / 1e3
+        flops = 4.0 * P * (P + 1) * ns          # 8 real flops per complex MAC, P(P+1)/2 entries
+        peak = BF16_PEAK_TFLOPS if prec == crbm.BF16 else FP32_MATRIX_PEAK_TFLOPS
+        achieved = flops / avg_s / 1e12
+        roof = {"kernel": "k_sbuild_mfma", "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None, "algorithmic_flops": flops}
+    else:
+        c, t = prof["ot"]
+        avg_s = t / c / 1e3
+        byts = ns * (M * 8 + N + 16)
+        achieved = byts / avg_s / 1e9
+        roof = {"kernel": "k_ot", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": byts}
+
+    line = {
+        "metric": "MC samples/s + SR steps/s, 10x10 RBM alpha=4, BF16/batched vs plain FP32 at equal mu_n error",
+        "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16" if prec == crbm.BF16 else "f32", "data": "synthetic",
+        "config": {"workload": "heisenberg_square10x10_rbm_alpha4", "lattice": "10x10 periodic", "N": N, "M": M,
+                   "P": P, "chains": C, "sweeps": sweeps, "samples_per_step": ns, "proposal": "pair_exchange",
+                   "solver": args.solver, "s_precision": args.precision, "diag_shift": wl.diag_shift,
+                   "cg_tol": 1e-6, "cg_maxit": args.cg_maxit, "n_moments": n_max, "parallelism": "single_gpu"},
+        "sr_steps_per_s": 1e3 / ms_per_step,
+        "sampler_samples_per_s": (C * sweeps) / (prof["sample"][1] / prof["sample"][0] / 1e3) if "sample" in prof else None,
+        "cg_iterations": float(st[5]), "cg_rel_residual": float(st[4]), "sr_flags": int(st[6]),
+        "gamma": float(st[0]),
+        "phases": phases,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_budget_s, ns, sweeps, C)
+    print(json.dumps(line))
+    plan.close()
+
+
+def cpu_baseline(budget_s, ns, sweeps, C):
+    """The FP64 oracle on the host cores, on a bounded sample of the same workload.
+
+    Per-sample stages are timed on a few hundred samples and scaled to the step's
+    sample count; the natural-gradient step is left out because the oracle's
+    dense S for P = 40,500 (26 GB in double) and its O(P^2 n + P^3) cost do not fit
+    a bounded run."""
+    import oracle as orc
+
+    wl = synth.SQUARE10
+    N, M = wl.N, wl.M
+    lat = orc.Lattice(1, wl.Lx, wl.Ly)
+    mk = lambda s: orc.init_rbm(N, M, s, wl.param_std)
+    fit, psn, psm, gs = mk(wl.param_seed + 3), mk(wl.param_seed + 2), mk(wl.param_seed + 1), mk(wl.param_seed)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # calibrate: sampler on a few chains x 1 sweep
+    n_ch = 32
+    spins = orc.init_chains(N, n_ch, wl.chain_seed, 1)
+    t0 = time.perf_counter()
+    smp, _, _, _ = orc.metropolis(fit, spins, 1, 1, 11, 0)
+    t_sweep = (time.perf_counter() - t0) / n_ch           # seconds per chain-sweep
+    sig = smp.reshape(-1, N)
+    n_loc = 32
+    E0 = synth.E0_PER_SITE_SQUARE * N
+    W_scale = 1.5 * abs(E0)
+    E_c = E0 + (1.0 - 0.0125) * W_scale
+    t0 = time.perf_counter()
+    orc.target_ratio(fit, psn, psm, lat, sig[:n_loc], 2, E_c, W_scale, q=(math.pi, math.pi))
+    t_loc = (time.perf_counter() - t0) / n_loc
+    ts = [mk(wl.param_seed + 10 + t) for t in range(20)]
+    t0 = time.perf_counter()
+    orc.moments(gs, ts, np.ones(20), [(math.pi, math.pi)], lat, sig[:n_loc])
+    t_mom = (time.perf_counter() - t0) / n_loc
+    # scale the bounded sample up to the budget
+    per_sample = 2 * t_sweep + t_loc + t_mom
+    n_big = max(n_loc, int(budget_s / max(per_sample, 1e-9)) // 2)
+    n_big = min(n_big, 4096)
+    spins = orc.init_chains(N, n_big, wl.chain_seed, 1)
+    t0 = time.perf_counter()
+    smp, _, _, _ = orc.metropolis(fit, spins, 1, 1, 11, 0)
+    t1 = time.perf_counter()
+    sig = smp.reshape(-1, N)
+    orc.target_ratio(fit, psn, psm, lat, sig, 2, E_c, W_scale, q=(math.pi, math.pi))
+    t2 = time.perf_counter()
+    orc.moments(gs, ts, np.ones(20), [(math.pi, math.pi)], lat, sig)
+    t3 = time.perf_counter()
+    per_sample = 2 * (t1 - t0) / n_big + (t2 - t1) / n_big + (t3 - t2) / n_big
+    return {"value": 1.0 / per_sample, "unit": "samples/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{n_big} chains x 1 sweep (x2 for the psi_gs chains), local estimators and 20 moments on "
+                       f"{n_big} samples of the 10x10 alpha=4 workload, {t3 - t0:.1f} s of CPU time; "
+                       "natural-gradient step excluded (oracle dense S of 26 GB)"),
+            "seconds": t3 - t0}
+
+
+if __name__ == "__main__":
+    main()

@@ -60,7 +60,8 @@ enum { CRBM_SOLVER_CG_DENSE = 0, CRBM_SOLVER_CG_MATFREE = 1, CRBM_SOLVER_CHOLESK
 enum { CRBM_PREC_FP32 = 0, CRBM_PREC_BF16 = 1 };
 
 /* plan flags */
-#define CRBM_PLAN_DENSE_S 1    /* reserve the dense P x P complex64 matrix S (needed by CG_DENSE) */
+#define CRBM_PLAN_DENSE_S 1    /* reserve the dense P x P complex64 matrix S and the packed operands of
+                                  its matrix-core contraction (needed by CG_DENSE) */
 #define CRBM_PLAN_CHOLESKY 2   /* also reserve a P x P complex128 factor (CHOLESKY; needs P <= 4000) */
 
 /* workspace buffers readable through crbm_plan_buffer (device pointers) */
@@ -116,6 +117,26 @@ int crbm_plan_buffer(crbm_plan plan, int which, void** dev_ptr, size_t* bytes);
 /* Thread-local text of the last error returned on this thread. */
 const char* crbm_last_error(void);
 
+/* Instrumentation.  While enabled, the library records HIP events on the call's stream around
+ * each kernel group below (one kernel launch per record unless noted).  crbm_plan_profile
+ * enables (1) or disables (0) recording and discards earlier records; crbm_plan_profile_read
+ * waits for the recorded events of one group and returns the number of records and their total
+ * duration in milliseconds. */
+enum {
+    CRBM_PROF_SAMPLE = 0,   /* Metropolis sweep kernel */
+    CRBM_PROF_THETA,        /* theta = sigma W + b product */
+    CRBM_PROF_LOCAL,        /* local-estimator kernel */
+    CRBM_PROF_OT,           /* O^H c contraction kernel */
+    CRBM_PROF_SBUILD,       /* dense S contraction kernel (matrix cores) */
+    CRBM_PROF_CG,           /* whole conjugate-gradient loop (many kernels) */
+    CRBM_PROF_MOMENT,       /* per-order moment ratio kernel */
+    CRBM_PROF_PACK,         /* operand packing for the S contraction (two kernels) */
+    CRBM_PROF_CHOLESKY,     /* whole Cholesky factorisation and solve (many kernels) */
+    CRBM_PROF_COUNT
+};
+int crbm_plan_profile(crbm_plan plan, int enable);
+int crbm_plan_profile_read(crbm_plan plan, int group, int* count, double* total_ms);
+
 /* Fill a, b, W with complex numbers whose real and imaginary parts are independent
  * N(0, stddev^2): parameter k of the packed vector takes Philox4x32-10 block
  * (key = seed, counter = (k, 0, 0, 2)), u1 = ((x0 >> 8) + 1) 2^-24, u2 = (x1 >> 8) 2^-24,
@@ -165,10 +186,11 @@ int crbm_local_estimators(crbm_plan plan, const crbm_rbm* fit, const crbm_rbm* p
  *   F_k = dgamma gamma cot(gamma) [<O_k^* R>/<R> - <O_k^*>]   (gamma cot gamma -> 1 - gamma^2/3 below 1e-4)
  *   S_kk' = <O_k^* O_k'> - <O_k>^* <O_k'>,   (S + diag_shift I) dalpha = F,   alpha += dalpha.
  * <f> = sum_s w_s f_s with w = weights (double [n]) or 1/n if weights == NULL.
- * solver: CG_DENSE (S built densely by OO^H contraction in s_precision, CG with double vectors),
+ * solver: CG_DENSE (S built densely by the O^H O contraction, CG with double vectors),
  *         CG_MATFREE (S v = <O^*(O v)> - <O>^*(<O> v) from the factored O each iteration),
  *         CHOLESKY (S built densely, factorised in double).
- * s_precision: FP32 or BF16 operands for the dense S contraction (accumulation in FP32).
+ * s_precision: FP32 or BF16 operands of the dense S contraction on the matrix cores, FP32 accumulation
+ *         (BF16 needs weights == NULL; with weights the FP32 contraction runs on the vector units).
  * cg_tol: relative residual |F - (S+eps)x| / |F|; cg_maxit: iteration cap.
  * stats_out: device double [8] = {gamma, Re beta, Im beta, |F|_2, relative residual,
  *            iterations, flags (CRBM_FLAG_*), |dalpha|_2}.

@@ -28,9 +28,11 @@ PLAN_DENSE_S, PLAN_CHOLESKY = 1, 2
 BUF_F, BUF_DALPHA, BUF_OMEAN, BUF_S = 0, 1, 2, 3
 
 # names declared in include/chebrbm.h
-EXPORTS = ("crbm_plan_create", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_last_error", "crbm_init_rbm",
-           "crbm_init_chains", "crbm_sample", "crbm_local_estimators", "crbm_sr_step", "crbm_chebyshev_moment",
-           "crbm_fidelity_grad")
+EXPORTS = ("crbm_plan_create", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_last_error", "crbm_plan_profile",
+           "crbm_plan_profile_read", "crbm_init_rbm", "crbm_init_chains", "crbm_sample", "crbm_local_estimators",
+           "crbm_sr_step", "crbm_chebyshev_moment", "crbm_fidelity_grad")
+PROF_SAMPLE, PROF_THETA, PROF_LOCAL, PROF_OT, PROF_SBUILD, PROF_CG, PROF_MOMENT, PROF_PACK, PROF_CHOLESKY = range(9)
+PROF_NAMES = ("sample", "theta", "local", "ot", "sbuild", "cg", "moment", "pack", "cholesky")
 
 
 class CrbmError(RuntimeError):
@@ -69,6 +71,8 @@ def lib():
         L.crbm_plan_create.argtypes = [P(_vp), P(_Lattice), _i, _l, _i]
         L.crbm_plan_destroy.argtypes = [_vp]
         L.crbm_plan_buffer.argtypes = [_vp, _i, P(_vp), P(ctypes.c_size_t)]
+        L.crbm_plan_profile.argtypes = [_vp, _i]
+        L.crbm_plan_profile_read.argtypes = [_vp, _i, P(_i), P(_d)]
         L.crbm_init_rbm.argtypes = [P(_Rbm), _u64, _f, _vp]
         L.crbm_init_chains.argtypes = [_vp, _vp, _i, _u64, _i, _vp]
         L.crbm_sample.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _i, _i, _i, _u64, _u64, _vp, _vp, _vp, _vp]
@@ -169,6 +173,20 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def profile(self, enable: bool):
+        """Start (True) or stop (False) recording kernel-group timings; discards earlier records."""
+        _check(lib().crbm_plan_profile(self.handle, int(enable)))
+
+    def profile_read(self):
+        """{group name: (count, total_ms)} of the recorded kernel groups (waits for their events)."""
+        out = {}
+        for gid, name in enumerate(PROF_NAMES):
+            c, t = ctypes.c_int(), ctypes.c_double()
+            _check(lib().crbm_plan_profile_read(self.handle, gid, ctypes.byref(c), ctypes.byref(t)))
+            if c.value:
+                out[name] = (c.value, t.value)
+        return out
 
     def buffer_ptr(self, which):
         """(device pointer, bytes) of a workspace buffer (CRBM_BUF_*)."""

@@ -25,6 +25,7 @@ hipError_t launch_fq_chunk(const Geometry& g, const int8_t* sig, long n_s, const
 hipError_t launch_moment_accum(const double2* f, const double2* B, int b_is_f, const double* w, long n_s, int n_q,
                                int nn, int entry0, int total, double2* partial, int n_blocks, hipStream_t stream);
 hipError_t launch_moment_final(const double2* partial, int n_blocks, int total, double2* mu, hipStream_t stream);
+size_t sbuild_pack_bytes(int N, int M, long max_samples);
 }  // namespace crbm
 
 using namespace crbm;
@@ -65,6 +66,7 @@ struct crbm_plan_s {
     double2* momB = nullptr;
     double2* momF = nullptr;
     double2* mom_partial = nullptr;
+    Profiler prof;
     std::vector<void*> allocs;
 
     Geometry geometry() const {
@@ -188,6 +190,7 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
     rc = rc ? rc : p->alloc(&p->bonds, bonds.size());
     rc = rc ? rc : p->alloc(&p->w.scal, 32);
     rc = rc ? rc : p->alloc(&p->w.Om, P);
+    rc = rc ? rc : p->alloc(&p->w.Om16, P);
     rc = rc ? rc : p->alloc(&p->w.ORm, P);
     rc = rc ? rc : p->alloc(&p->w.F, P);
     rc = rc ? rc : p->alloc(&p->w.x, P);
@@ -204,6 +207,11 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
     rc = rc ? rc : p->alloc(&p->mom_partial, (long)kMomBlocks * kMaxMomentEntries);
     if (!rc && (flags & (CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY))) rc = p->alloc(&p->w.S, P * P);
     if (!rc && (flags & CRBM_PLAN_CHOLESKY)) rc = p->alloc(&p->w.S64, P * P);
+    if (!rc && (flags & (CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY))) {
+        p->w.pack_bytes = sbuild_pack_bytes((int)N, (int)M, S);
+        rc = p->alloc(reinterpret_cast<unsigned char**>(&p->w.pack), p->w.pack_bytes);
+    }
+    p->w.prof = &p->prof;
     if (rc) { delete p; return rc; }
     p->w.red_len = red_len;
     e = hipMemcpy(p->bonds, bonds.data(), bonds.size() * sizeof(int2), hipMemcpyHostToDevice);
@@ -233,6 +241,34 @@ int crbm_plan_buffer(crbm_plan p, int which, void** ptr, size_t* bytes) {
         default: return fail(CRBM_EINVAL, "unknown buffer id %d", which);
     }
     if (bytes) *bytes = b;
+    return CRBM_OK;
+}
+
+int crbm_plan_profile(crbm_plan p, int enable) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (enable != 0 && enable != 1) return fail(CRBM_EINVAL, "enable must be 0 or 1");
+    p->prof.reset();
+    p->prof.on = enable != 0;
+    return CRBM_OK;
+}
+
+int crbm_plan_profile_read(crbm_plan p, int group, int* count, double* total_ms) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (group < 0 || group >= PROF_COUNT) return fail(CRBM_EINVAL, "unknown profile group %d", group);
+    int c = 0;
+    double t = 0.0;
+    for (const auto& r : p->prof.recs) {
+        if (r.id != group) continue;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        ++c;
+        t += ms;
+    }
+    if (count) *count = c;
+    if (total_ms) *total_ms = t;
     return CRBM_OK;
 }
 
@@ -283,7 +319,9 @@ int crbm_sample(crbm_plan p, const crbm_rbm* psi, int8_t* spins, void* theta_out
     A.n_accept = n_accept;
     A.trace = accept_trace;
     A.trace_words = (int)(((long)n_sweeps * p->N + 31) / 32);
+    p->prof.begin(PROF_SAMPLE, stream);
     hipError_t e = launch_sample(A, stream);
+    p->prof.end(stream);
     return e == hipSuccess ? CRBM_OK : hip_fail(e, "sample launch");
 }
 
@@ -332,11 +370,20 @@ int crbm_local_estimators(crbm_plan p, const crbm_rbm* fit, const crbm_rbm* psi_
     A.R_out = static_cast<float2*>(R_out);
     A.tanh_out = static_cast<float2*>(tanh_out);
     A.O_out = static_cast<float2*>(O_out);
-    hipError_t e = launch_theta(samples, n, p->N, p->M, A.fit.b, A.fit.W, p->theta[0], stream);
-    if (e == hipSuccess && cheb_mode) e = launch_theta(samples, n, p->N, p->M, A.psn.b, A.psn.W, p->theta[1], stream);
-    if (e == hipSuccess && cheb_mode && cheb->order >= 1)
-        e = launch_theta(samples, n, p->N, p->M, A.psm.b, A.psm.W, p->theta[2], stream);
-    if (e == hipSuccess) e = launch_local_core(A, p->theta[0], p->theta[1], p->theta[2], stream);
+    auto theta = [&](const RbmView& v, float2* out) {
+        p->prof.begin(PROF_THETA, stream);
+        hipError_t r = launch_theta(samples, n, p->N, p->M, v.b, v.W, out, stream);
+        p->prof.end(stream);
+        return r;
+    };
+    hipError_t e = theta(A.fit, p->theta[0]);
+    if (e == hipSuccess && cheb_mode) e = theta(A.psn, p->theta[1]);
+    if (e == hipSuccess && cheb_mode && cheb->order >= 1) e = theta(A.psm, p->theta[2]);
+    if (e == hipSuccess) {
+        p->prof.begin(PROF_LOCAL, stream);
+        e = launch_local_core(A, p->theta[0], p->theta[1], p->theta[2], stream);
+        p->prof.end(stream);
+    }
     return e == hipSuccess ? CRBM_OK : hip_fail(e, "local_estimators launch");
 }
 
@@ -352,7 +399,8 @@ int crbm_sr_step(crbm_plan p, const crbm_rbm* fit, const int8_t* samples, const 
     if (solver != CRBM_SOLVER_CG_DENSE && solver != CRBM_SOLVER_CG_MATFREE && solver != CRBM_SOLVER_CHOLESKY)
         return fail(CRBM_EINVAL, "unknown solver %d", solver);
     if (prec != CRBM_PREC_FP32 && prec != CRBM_PREC_BF16) return fail(CRBM_EINVAL, "unknown precision %d", prec);
-    if (prec == CRBM_PREC_BF16) return fail(CRBM_EUNSUPPORTED, "BF16 S contraction is not available in this build");
+    if (prec == CRBM_PREC_BF16 && weights && solver != CRBM_SOLVER_CG_MATFREE)
+        return fail(CRBM_EUNSUPPORTED, "the BF16 S contraction needs uniform weights (weights == NULL)");
     if (!(eps >= 0.0)) return fail(CRBM_EINVAL, "diag_shift must be >= 0");
     if (solver != CRBM_SOLVER_CHOLESKY && (cg_maxit < 1 || !(cg_tol > 0.0)))
         return fail(CRBM_EINVAL, "cg_maxit must be >= 1 and cg_tol > 0");
@@ -410,10 +458,15 @@ int crbm_chebyshev_moment(crbm_plan p, const crbm_rbm* gs, const void* t_params,
                                     kMomBlocks, stream);
         for (int t = 1; t <= n_max && e == hipSuccess; ++t) {
             const float2* at = tp + (long)(t - 1) * P;
+            p->prof.begin(PROF_THETA, stream);
             e = launch_theta(samples, n, p->N, p->M, at + p->N, at + p->N + p->M, p->theta[1], stream);
-            if (e == hipSuccess)
+            p->prof.end(stream);
+            if (e == hipSuccess) {
+                p->prof.begin(PROF_MOMENT, stream);
                 e = launch_moment_ratio(p->N, p->M, samples, n, at, vg.a, p->theta[1], p->theta[0],
                                         reinterpret_cast<const double2*>(betas) + (t - 1), p->momB, stream);
+                p->prof.end(stream);
+            }
             if (e == hipSuccess)
                 e = launch_moment_accum(p->momF, p->momB, 0, weights, n, nq, nn, q0 * nn + t, nn * n_q,
                                         p->mom_partial, kMomBlocks, stream);

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "profile.hpp"
+
 namespace crbm {
 
 struct RbmView {            // device pointers, complex64 interleaved
@@ -83,6 +85,7 @@ hipError_t launch_moments(const MomentArgs& args, hipStream_t stream);
 struct SrWork {
     double* scal;             // [32] device scalars (see kernels_sr.hip)
     double2* Om;              // [P]  <O>
+    double2* Om16;            // [P]  <O> of the BF16-rounded operands
     double2* ORm;             // [P]  <O^* R>
     double2* F;               // [P]
     double2* x;               // [P]  solution
@@ -96,7 +99,14 @@ struct SrWork {
     double2* S64;             // [P][P] dense double (Cholesky, may be null)
     float2* G;                // [n][M] scratch of the matrix-free product
     float2* vstage;           // [P] float copy of a CG direction
+    void* pack;               // packed operand planes of the matrix-core S contraction
+    size_t pack_bytes;
+    Profiler* prof;
 };
+
+// instrumentation group ids (mirrors CRBM_PROF_* of the public header)
+enum { PROF_SAMPLE = 0, PROF_THETA, PROF_LOCAL, PROF_OT, PROF_SBUILD, PROF_CG, PROF_MOMENT, PROF_PACK, PROF_CHOLESKY,
+       PROF_COUNT };
 
 struct SrArgs {
     int N, M, P;

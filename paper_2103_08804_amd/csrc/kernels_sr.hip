@@ -82,6 +82,13 @@ __global__ void k_r_final(const double2* __restrict__ red, int n_blocks, double 
 //             3 -> c = 2 (1 - R) conj(R) / n
 constexpr int OT_I = 32, OT_J = 64, OT_S = 32;
 
+// the value a binary32 takes after rounding to bfloat16 (nearest, ties to even)
+__device__ __forceinline__ float round_to_bf16(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return __uint_as_float(u & 0xFFFF0000u);
+}
+
 __device__ __forceinline__ float2 coef_of(int kind, long s, const double* w, double wdef, const float2* R,
                                           const double2* u, double two_over_n) {
     const float ws = w ? (float)w[s] : (float)wdef;
@@ -101,7 +108,7 @@ __global__ __launch_bounds__(256) void k_ot(int N, int M, const int8_t* __restri
                                             long n, long chunk, int kind0, int kind1, int nk,
                                             const double* __restrict__ w, const float2* __restrict__ R,
                                             const double2* __restrict__ u, double2* __restrict__ partial,
-                                            const double* __restrict__ skip) {
+                                            const double* __restrict__ skip, int round_bf16) {
     if (skip && *skip != 0.0) return;
     __shared__ float s_sig[OT_S][OT_I + 1];
     __shared__ float2 s_t[OT_S][OT_J];
@@ -134,6 +141,7 @@ __global__ __launch_bounds__(256) void k_ot(int N, int M, const int8_t* __restri
             const int j = j0 + jj;
             float2 v = make_float2(0.f, 0.f);
             if (s < s_end && j <= M) v = (j == M) ? make_float2(1.f, 0.f) : cconj(T[s * M + j]);
+            if (round_bf16) v = make_float2(round_to_bf16(v.x), round_to_bf16(v.y));
             s_t[ss][jj] = v;
         }
         if (tid < OT_S * 2) {
@@ -201,11 +209,14 @@ static OtPlan ot_plan(long n) {
 
 static hipError_t run_ot(int N, int M, const int8_t* sig, const float2* T, long n, int kind0, int kind1, int nk,
                          const double* w, const float2* R, const double2* u, double2* partial, int conj0,
-                         double2* out0, double2* out1, hipStream_t stream, const double* skip = nullptr) {
+                         double2* out0, double2* out1, hipStream_t stream, const double* skip, Profiler* prof,
+                         int round_bf16 = 0) {
     const OtPlan op = ot_plan(n);
     dim3 grid((N + 1 + OT_I - 1) / OT_I, (M + 1 + OT_J - 1) / OT_J, op.n_chunks);
+    if (prof) prof->begin(PROF_OT, stream);
     hipLaunchKernelGGL(k_ot, grid, dim3(256), 0, stream, N, M, sig, T, n, op.chunk, kind0, kind1, nk, w, R, u, partial,
-                       skip);
+                       skip, round_bf16);
+    if (prof) prof->end(stream);
     const long plane = (long)(N + 1) * (M + 1);
     hipLaunchKernelGGL(k_ot_reduce, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, stream, N, M, partial,
                        op.n_chunks, nk, conj0, out0, out1, skip);
@@ -527,6 +538,8 @@ static inline unsigned nblk(long n, int t = 256) { return (unsigned)((n + t - 1)
 
 hipError_t launch_cholesky_solve(long P, const float2* S, double eps, const double2* F, double2* A64, double2* x,
                                  double* sc, hipStream_t stream);
+hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n, const double2* Om,
+                              float2* S, int prec, void* pack, size_t pack_bytes, Profiler* prof, hipStream_t stream);
 
 static hipError_t apply_op(const SrArgs& A, const SrWork& W, const double2* v, double2* y, hipStream_t stream) {
     const long P = A.P;
@@ -549,7 +562,7 @@ static hipError_t apply_op(const SrArgs& A, const SrWork& W, const double2* v, d
         hipLaunchKernelGGL(k_dot_ov, dim3(64), dim3(256), 0, stream, P, W.Om, v, W.red, W.scal);
         hipLaunchKernelGGL(k_sub_mean, dim3(nblk(A.n)), dim3(256), 0, stream, A.n, W.u, W.red, 64, W.scal);
         e = run_ot(A.N, A.M, A.samples, A.T, A.n, 2, 0, 1, A.weights, A.R, W.u, W.red + 64, 0, y, nullptr, stream,
-                   W.scal + SC_DONE);
+                   W.scal + SC_DONE, nullptr);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_add_shift, dim3(nblk(P)), dim3(256), 0, stream, P, v, A.eps, y, W.scal);
     } else {
@@ -566,33 +579,50 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
     hipLaunchKernelGGL(k_r_moments, dim3(nb_r), dim3(256), 0, stream, A.R, A.weights, A.n, W.red);
     hipLaunchKernelGGL(k_r_final, dim3(1), dim3(64), 0, stream, W.red, nb_r, A.dgamma, W.scal);
     // conj(<O>) and <O^* R>
-    e = run_ot(A.N, A.M, A.samples, A.T, A.n, 0, 1, 2, A.weights, A.R, nullptr, W.red, 0, W.Om, W.ORm, stream);
+    e = run_ot(A.N, A.M, A.samples, A.T, A.n, 0, 1, 2, A.weights, A.R, nullptr, W.red, 0, W.Om, W.ORm, stream, nullptr,
+               W.prof);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_make_f, dim3(nblk(P)), dim3(256), 0, stream, P, W.Om, W.ORm, W.scal, W.F);
     hipLaunchKernelGGL(k_zdot, dim3(64), dim3(256), 0, stream, P, W.F, W.F, W.red, W.scal, 0);
     hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(64), 0, stream, W.red, 64, W.scal, (int)SC_FF, 0);
 
     if (A.solver != CRBM_SOLVER_CG_MATFREE) {
-        if (A.prec == CRBM_PREC_BF16) {
-            return hipErrorNotSupported;
+        if (A.weights == nullptr) {
+            // With BF16 operands the subtracted mean comes from the same rounded operands, so that
+            // S stays the centred Gram matrix of one set of vectors (positive semi-definite).
+            const double2* om_s = W.Om;
+            if (A.prec == CRBM_PREC_BF16) {
+                e = run_ot(A.N, A.M, A.samples, A.T, A.n, 0, 0, 1, nullptr, A.R, nullptr, W.red, 1, W.Om16, nullptr,
+                           stream, nullptr, nullptr, 1);
+                if (e != hipSuccess) return e;
+                om_s = W.Om16;
+            }
+            e = launch_sbuild_mfma(A.N, A.M, P, A.samples, A.T, A.n, om_s, W.S, A.prec, W.pack, W.pack_bytes, W.prof,
+                                   stream);
         } else {
+            // weighted (enumeration) sums: FP32 contraction on the vector units
             const int nt = (int)((P + SB_T - 1) / SB_T);
             const long ntri = (long)nt * (nt + 1) / 2;
+            W.prof->begin(PROF_SBUILD, stream);
             hipLaunchKernelGGL(k_sbuild, dim3((unsigned)ntri), dim3(256), 0, stream, A.N, A.M, P, A.samples, A.T,
                                A.weights, A.n, W.Om, W.S, nt);
+            W.prof->end(stream);
             e = hipGetLastError();
         }
         if (e != hipSuccess) return e;
     }
 
     if (A.solver == CRBM_SOLVER_CHOLESKY) {
+        W.prof->begin(PROF_CHOLESKY, stream);
         e = launch_cholesky_solve(P, W.S, A.eps, W.F, W.S64, W.x, W.scal, stream);
+        W.prof->end(stream);
         if (e != hipSuccess) return e;
         // residual of the double solve against the FP32-stored S
         hipLaunchKernelGGL(k_undone, dim3(1), dim3(64), 0, stream, W.scal);
     } else {
         hipLaunchKernelGGL(k_cg_init, dim3(nblk(P)), dim3(256), 0, stream, P, W.F, W.x, W.r, W.p);
         hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(64), 0, stream, W.scal);
+        W.prof->begin(PROF_CG, stream);
         for (int it = 0; it < A.cg_maxit; ++it) {
             e = apply_op(A, W, W.p, W.Ap, stream);
             if (e != hipSuccess) return e;
@@ -604,6 +634,7 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
             hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64), 0, stream, W.scal, A.cg_tol, A.cg_maxit);
             hipLaunchKernelGGL(k_cg_p, dim3(nblk(P)), dim3(256), 0, stream, P, W.p, W.r, W.scal);
         }
+        W.prof->end(stream);
         hipLaunchKernelGGL(k_undone, dim3(1), dim3(64), 0, stream, W.scal);
     }
     // true residual |F - (S + eps) x|^2 in double
@@ -635,7 +666,7 @@ __global__ void k_loss(const float2* __restrict__ R, long n, double* __restrict_
 
 hipError_t launch_fidelity_grad(const GradArgs& A, const SrWork& W, hipStream_t stream) {
     hipError_t e = run_ot(A.N, A.M, A.samples, A.T, A.n, 3, 0, 1, nullptr, A.R, nullptr, W.red, 0, A.grad, nullptr,
-                          stream);
+                          stream, nullptr, W.prof);
     if (e != hipSuccess) return e;
     if (A.loss) hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, stream, A.R, A.n, A.loss);
     return hipGetLastError();

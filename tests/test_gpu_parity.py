@@ -344,3 +344,44 @@ def test_fidelity_grad(orc):
     L_ref, g_ref = orc.fidelity_grad(fit, sig, R_ref)
     assert abs(np_of(loss)[0] - L_ref) < 1e-5 * max(1.0, L_ref)
     assert rel_err(np_of(g), g_ref) < 1e-5
+
+
+# ------------------------------------------------------------------ matrix-core S contraction
+@pytest.mark.parametrize("kind,Lx,Ly,M,n", [(0, 10, 1, 10, 1000), (1, 4, 4, 40, 777), (0, 40, 1, 80, 130)])
+def test_dense_s_matrix_cores(orc, kind, Lx, Ly, M, n):
+    """S from the FP32 and BF16 matrix-core contractions (uniform weights) against the oracle's S.
+    FP32 operands: 1e-5 relative.  BF16 operands (8-bit significands) are reported and bounded
+    by 2^-7 relative to max|S| (both operands rounded once: 2 * 2^-9 per product)."""
+    N = Lx * Ly
+    fit_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(70 + N, N, M, 0.2, std_im=0.05)))
+    fit = to_oracle_rbm(orc, fit_d)
+    sig = synth.random_spins(71, n, N, True)
+    r = np.random.default_rng(2)
+    R = (1 + 0.3 * r.normal(size=n) + 0.2j * r.normal(size=n)).astype(np.complex64)
+    _, info = orc.sr_step(fit, sig, R.astype(np.complex128), 0.1, 1e-2, want_S=True)
+    errs = {}
+    for prec in (crbm.FP32, crbm.BF16):
+        fd = crbm.RBM(fit_d.a.clone(), fit_d.b.clone(), fit_d.W.clone())
+        plan = _plan(kind, Lx, Ly, M, n, crbm.PLAN_DENSE_S)
+        sd = torch.from_numpy(sig).cuda()
+        T = torch.zeros(n, M, dtype=torch.complex64, device="cuda")
+        crbm.local_estimators(plan, fd, sd, tanh_out=T)
+        stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+        crbm.sr_step(plan, fd, sd, T, torch.from_numpy(R).cuda(), 0.1, 1e-2, crbm.CG_DENSE, prec, 1e-10, 3000, stats)
+        S = torch.zeros(plan.P, plan.P, dtype=torch.complex64, device="cuda")
+        crbm.copy_plan_buffer(plan, crbm.BUF_S, S)
+        dx = torch.zeros(plan.P, dtype=torch.complex128, device="cuda")
+        crbm.copy_plan_buffer(plan, crbm.BUF_DALPHA, dx)
+        torch.cuda.synchronize()
+        assert int(np_of(stats)[6]) == 0, np_of(stats)
+        Sg = np_of(S)
+        assert np.max(np.abs(Sg - Sg.conj().T)) <= 1e-6 * np.abs(Sg).max()
+        assert np.all(np.diag(Sg).imag == 0)
+        errs[prec] = (rel_err(Sg, info["S"]), rel_err(np_of(dx), info["dalpha"]))
+    # first-order perturbation bound of the solve: |d x|/|x| <= kappa |d S|/|S + eps|
+    ev = np.linalg.eigvalsh(info["S"] + 1e-2 * np.eye(info["S"].shape[0]))
+    kappa = ev.max() / ev.min()
+    print("kappa", kappa, "S / dalpha relative errors FP32:", errs[crbm.FP32], "BF16:", errs[crbm.BF16])
+    assert errs[crbm.FP32][0] < 1e-5
+    assert errs[crbm.FP32][1] < max(1e-4, 4 * kappa * errs[crbm.FP32][0])
+    assert errs[crbm.BF16][0] < 2 ** -7
