@@ -207,8 +207,8 @@ def cpu_baseline(budget_s, ns, sweeps, C):
     t_mom = (time.perf_counter() - t0) / n_loc
     # scale the bounded sample up to the budget
     per_sample = 2 * t_sweep + t_loc + t_mom
-    n_big = max(n_loc, int(budget_s / max(per_sample, 1e-9)) // 2)
-    n_big = min(n_big, 4096)
+    n_big = max(n_loc, int(budget_s / max(per_sample, 1e-9)))
+    n_big = min(n_big, 1 << 17)
     spins = orc.init_chains(N, n_big, wl.chain_seed, 1)
     t0 = time.perf_counter()
     smp, _, _, _ = orc.metropolis(fit, spins, 1, 1, 11, 0)
