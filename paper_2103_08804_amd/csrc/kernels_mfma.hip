@@ -31,7 +31,10 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
 
 constexpr int MK_TI = 4;        // extended sites per row tile
 constexpr int MK_TJ = 32;       // extended hidden units per row tile
-constexpr int MK_KT = 64;       // samples per LDS K tile
+#ifndef CRBM_MK_KT
+#define CRBM_MK_KT 128
+#endif
+constexpr int MK_KT = CRBM_MK_KT;   // samples per LDS K tile
 
 // ------------------------------------------------------------------ packing
 // planes: Tr[jj][s], Ti[jj][s] for jj < Mp (jj == M -> 1 + 0i, jj > M -> 0), s < ns_pad (s >= n -> 0)
@@ -114,8 +117,9 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, in
                                                         const double2* __restrict__ Om, float inv_n,
                                                         float2* __restrict__ S) {
     using E = typename Pol<BF16>::E;
+    constexpr int KT = BF16 ? MK_KT : 64;          // samples per LDS K tile of this precision
     // bytes per LDS row, padded so that the 32 rows of a fragment read fall in distinct banks
-    constexpr int ROWB = MK_KT * (int)sizeof(E) + (BF16 ? 16 : 4);
+    constexpr int ROWB = KT * (int)sizeof(E) + (BF16 ? 16 : 4);
     constexpr int PLANE = MK_TJ * ROWB;                    // one [32][64] plane
     constexpr int MASKS = 2 * MK_TI * ROWB;                // 8 mask rows
     constexpr int STAGE = 4 * PLANE + MASKS;
@@ -134,7 +138,7 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, in
 
     // global -> LDS assignment: 4 planes of 32 rows x (64 samples) + 8 mask rows
     constexpr int CHUNK = 16;                               // bytes per load
-    constexpr int CH_PER_ROW = MK_KT * (int)sizeof(E) / CHUNK;
+    constexpr int CH_PER_ROW = KT * (int)sizeof(E) / CHUNK;
     const E* plane_src[4] = {Tr + (long)(J * MK_TJ) * ns_pad, Ti + (long)(J * MK_TJ) * ns_pad,
                              Tr + (long)(Jp * MK_TJ) * ns_pad, Ti + (long)(Jp * MK_TJ) * ns_pad};
 
@@ -146,7 +150,7 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, in
 #pragma unroll
             for (int v = 0; v < 16; ++v) { acc_re[a][b][v] = 0.f; acc_im[a][b][v] = 0.f; }
 
-    const long n_kt = ns_pad / MK_KT;
+    const long n_kt = ns_pad / KT;
     constexpr int PLANE_CHUNKS = MK_TJ * CH_PER_ROW;        // chunks per plane
     constexpr int TOTAL_CHUNKS = 4 * PLANE_CHUNKS + 2 * MK_TI * CH_PER_ROW;
     constexpr int PER_THREAD = (TOTAL_CHUNKS + 255) / 256;
@@ -158,7 +162,7 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, in
             const int c = tid + q * 256;
             i32x4 v = {0, 0, 0, 0};
             if (c < TOTAL_CHUNKS) {
-                const long s_off = kt * MK_KT;
+                const long s_off = kt * KT;
                 if (c < 4 * PLANE_CHUNKS) {
                     const int pl = c / PLANE_CHUNKS, rc = c % PLANE_CHUNKS;
                     const int row = rc / CH_PER_ROW, ch = rc % CH_PER_ROW;
@@ -210,7 +214,7 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, in
         if (kt + 1 < n_kt) gload(kt + 1);
         const unsigned char* base = lds + buf * STAGE;
 #pragma unroll
-        for (int ks = 0; ks < MK_KT; ks += Pol<BF16>::kStep) {
+        for (int ks = 0; ks < KT; ks += Pol<BF16>::kStep) {
             const int koff = (ks + Pol<BF16>::kPerLane * lhalf) * (int)sizeof(E);
             if constexpr (BF16) {
                 const i32x4 trA = *reinterpret_cast<const i32x4*>(base + 0 * PLANE + lrow * ROWB + koff);
@@ -224,22 +228,35 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, in
                     mB[a] = *reinterpret_cast<const i32x4*>(base + 4 * PLANE + (MK_TI + 2 * wj + a) * ROWB + koff);
                 }
                 const i32x4 neg = {(int)0x80008000, (int)0x80008000, (int)0x80008000, (int)0x80008000};
+                i32x4 ar[2], ai[2], br[2], bi[2], nbr[2];
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
-                    const i32x4 ar = trA ^ mA[a], ai = tiA ^ mA[a];
+                    ar[a] = trA ^ mA[a];
+                    ai[a] = tiA ^ mA[a];
+                    br[a] = trB ^ mB[a];
+                    bi[a] = tiB ^ mB[a];
+                    nbr[a] = br[a] ^ neg;
+                }
+                // first product of every accumulator, then the second: eight independent
+                // matrix-core operations separate the two updates of one accumulator
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
 #pragma unroll
                     for (int b = 0; b < 2; ++b) {
-                        const i32x4 br = trB ^ mB[b], bi = tiB ^ mB[b], nbr = br ^ neg;
                         acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            (bf16x8)ar, (bf16x8)br, acc_re[a][b], 0, 0, 0);
-                        acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            (bf16x8)ai, (bf16x8)bi, acc_re[a][b], 0, 0, 0);
+                            (bf16x8)ar[a], (bf16x8)br[b], acc_re[a][b], 0, 0, 0);
                         acc_im[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            (bf16x8)ar, (bf16x8)bi, acc_im[a][b], 0, 0, 0);
-                        acc_im[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                            (bf16x8)ai, (bf16x8)nbr, acc_im[a][b], 0, 0, 0);
+                            (bf16x8)ar[a], (bf16x8)bi[b], acc_im[a][b], 0, 0, 0);
                     }
-                }
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            (bf16x8)ai[a], (bf16x8)bi[b], acc_re[a][b], 0, 0, 0);
+                        acc_im[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                            (bf16x8)ai[a], (bf16x8)nbr[b], acc_im[a][b], 0, 0, 0);
+                    }
             } else {
                 const uint32_t trA = *reinterpret_cast<const uint32_t*>(base + 0 * PLANE + lrow * ROWB + koff);
                 const uint32_t tiA = *reinterpret_cast<const uint32_t*>(base + 1 * PLANE + lrow * ROWB + koff);
@@ -305,6 +322,7 @@ hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const flo
     const int Np = ((N + 1 + MK_TI - 1) / MK_TI) * MK_TI;
     const long ns_pad = ((n + MK_KT - 1) / MK_KT) * MK_KT;
     const int nJ = Mp / MK_TJ, nI = Np / MK_TI;
+    static_assert(MK_KT % 64 == 0, "the packing grid assumes 64-sample blocks");
     const long n_tiles = (long)nI * nJ;
     const long pairs = n_tiles * (n_tiles + 1) / 2;
     const bool bf16 = (prec == CRBM_PREC_BF16);
