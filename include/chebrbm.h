@@ -212,7 +212,8 @@ int crbm_chebyshev_moment(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_
 /* Gradient of the frozen-sample fidelity surrogate L = (1/n) sum_s |1 - R_s|^2 with respect to the
  * parameters of fit (R = phi/fit, so dR/dalpha_k = -R O_k):
  *   grad_k = 2 dL/d conj(alpha_k) = (2/n) sum_s (1 - R_s) conj(R_s) conj(O_k(s)),
- * i.e. dL/dRe alpha_k + i dL/dIm alpha_k.  grad_out: complex128 [P]; loss_out: double [1] or NULL.
+ * i.e. dL/dRe alpha_k + i dL/dIm alpha_k.  grad_out: complex128 [P] or NULL; loss_out: double [1] or NULL
+ * (at least one of the two).
  * tanh_theta and R as written by crbm_local_estimators for the same fit and samples. */
 int crbm_fidelity_grad(crbm_plan plan, const crbm_rbm* fit, const int8_t* samples, const void* tanh_theta,
                        const void* R, long n_samples, void* grad_out, double* loss_out, hipStream_t stream);

@@ -308,5 +308,6 @@ def fidelity_grad(plan: Plan, fit: RBM, samples, tanh_theta, R, grad_out, loss_o
     _check(lib().crbm_fidelity_grad(
         plan.handle, ctypes.byref(f), _ptr(samples, torch.int8, (n, N), "samples"),
         _ptr(tanh_theta, torch.complex64, (n, M), "tanh_theta"), _ptr(R, torch.complex64, (n,), "R"), n,
-        _ptr(grad_out, torch.complex128, (P,), "grad_out"), _ptr(loss_out, torch.float64, (1,), "loss_out"),
+        _ptr(grad_out, torch.complex128, (P,), "grad_out") if grad_out is not None else None,
+        _ptr(loss_out, torch.float64, (1,), "loss_out"),
         _stream(stream)))

@@ -481,7 +481,8 @@ int crbm_fidelity_grad(crbm_plan p, const crbm_rbm* fit, const int8_t* samples, 
                        void* grad_out, double* loss_out, hipStream_t stream) {
     if (check_plan(p)) return CRBM_EINVAL;
     if (int rc = check_rbm(p, fit, "fit")) return rc;
-    if (!samples || !T || !R || !grad_out) return fail(CRBM_EINVAL, "samples, tanh_theta, R and grad_out must be non-NULL");
+    if (!samples || !T || !R) return fail(CRBM_EINVAL, "samples, tanh_theta and R must be non-NULL");
+    if (!grad_out && !loss_out) return fail(CRBM_EINVAL, "at least one of grad_out and loss_out must be non-NULL");
     if (n < 1) return fail(CRBM_EINVAL, "n_samples must be >= 1");
     if (n > p->max_samples) return fail(CRBM_ENOMEM, "n_samples = %ld exceeds the plan's max_samples = %ld", n,
                                         p->max_samples);

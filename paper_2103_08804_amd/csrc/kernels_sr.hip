@@ -665,9 +665,11 @@ __global__ void k_loss(const float2* __restrict__ R, long n, double* __restrict_
 }
 
 hipError_t launch_fidelity_grad(const GradArgs& A, const SrWork& W, hipStream_t stream) {
-    hipError_t e = run_ot(A.N, A.M, A.samples, A.T, A.n, 3, 0, 1, nullptr, A.R, nullptr, W.red, 0, A.grad, nullptr,
-                          stream, nullptr, W.prof);
-    if (e != hipSuccess) return e;
+    if (A.grad) {
+        hipError_t e = run_ot(A.N, A.M, A.samples, A.T, A.n, 3, 0, 1, nullptr, A.R, nullptr, W.red, 0, A.grad, nullptr,
+                              stream, nullptr, W.prof);
+        if (e != hipSuccess) return e;
+    }
     if (A.loss) hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, stream, A.R, A.n, A.loss);
     return hipGetLastError();
 }
