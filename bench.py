@@ -51,7 +51,13 @@ def parse():
     ap.add_argument("--cg-maxit", type=int, default=500)
     ap.add_argument("--n-moments", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32-compare", action="store_true")
+    ap.add_argument("--fp32-fraction", type=int, default=16,
+                    help="the plain-FP32 S contraction is timed on N_s / this many samples and scaled")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
+    ap.add_argument("--workload", choices=["square10", "batched8x8"], default="square10",
+                    help="square10: the metric's 10x10 alpha=4 step (default); batched8x8: 2048 (q, n) moment "
+                         "instances of the 8x8 alpha=2 lattice in one persistent launch")
     return ap.parse_args()
 
 
@@ -64,6 +70,8 @@ def main():
     import paper_2103_08804_amd as crbm
 
     torch.cuda.set_device(0)
+    if args.workload == "batched8x8":
+        return bench_batched(crbm, args)
     wl = synth.SQUARE10
     N, M, P = wl.N, wl.M, wl.P
     C, sweeps = args.chains, args.sweeps
@@ -166,10 +174,108 @@ def main():
         "phases": phases,
         "roofline": roof,
     }
+    if not args.no_fp32_compare and solver == crbm.CG_DENSE and prec == crbm.BF16:
+        line["fp32_compare"] = fp32_compare(crbm, plan, fit, flat, T, R, wl, args, ms_per_step, prof)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_budget_s, ns, sweeps, C)
     print(json.dumps(line))
     plan.close()
+
+
+def bz_path(L, n_points):
+    """n_points momenta equally spaced in arc length along Gamma(0,0) -> X(pi,0) -> M(pi,pi) -> Gamma."""
+    corners = np.array([[0.0, 0.0], [math.pi, 0.0], [math.pi, math.pi], [0.0, 0.0]])
+    seg = np.linalg.norm(np.diff(corners, axis=0), axis=1)
+    cum = np.concatenate([[0.0], np.cumsum(seg)])
+    out = []
+    for t in np.linspace(0.0, cum[-1], n_points, endpoint=False):
+        k = min(int(np.searchsorted(cum, t, side="right")) - 1, len(seg) - 1)
+        out.append(corners[k] + (t - cum[k]) / seg[k] * (corners[k + 1] - corners[k]))
+    return np.array(out)
+
+
+def bench_batched(crbm, args):
+    """Moments of 32 momenta x 64 Chebyshev orders (2048 instances) of the 8x8, alpha = 2 lattice,
+    256..2048 chains per instance, 4 burn-in + 16 recorded sweeps, one persistent launch."""
+    wl = synth.SQUARE8
+    N, M, P = wl.N, wl.M, wl.P
+    n_q, n_ord = 32, 64
+    n_inst = n_q * n_ord
+    counts = np.random.default_rng(4).integers(256, 2049, n_inst)
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    total = int(offsets[-1])
+    plan = crbm.Plan(crbm.SQUARE, wl.Lx, wl.Ly, M, total)
+    gs = crbm.RBM.empty(N, M)
+    crbm.init_rbm(gs, wl.param_seed, wl.param_std)
+    tp = torch.zeros(n_inst, P, dtype=torch.complex64, device="cuda")
+    for i in range(n_inst):
+        crbm.init_rbm(crbm.RBM.from_packed(tp[i], N, M), wl.param_seed + 1 + i, wl.param_std)
+    betas = torch.ones(n_inst, dtype=torch.complex128, device="cuda")
+    qs = np.repeat(bz_path(wl.Lx, n_q), n_ord, axis=0)
+    qd = torch.from_numpy(np.ascontiguousarray(qs)).cuda()
+    od = torch.from_numpy(offsets).cuda()
+    mu = torch.zeros(n_inst, 2, dtype=torch.complex128, device="cuda")
+    n_burn, n_sweeps = 4, wl.sweeps
+    w, b, tune_ms = crbm.batched_autotune(plan, gs, tp, betas, qd, od, 1, crbm.EXCHANGE, wl.chain_seed)
+    for _ in range(args.warmup):
+        crbm.batched_moments(plan, gs, tp, betas, qd, od, n_burn, n_sweeps, crbm.EXCHANGE, wl.chain_seed, mu)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        crbm.batched_moments(plan, gs, tp, betas, qd, od, n_burn, n_sweeps, crbm.EXCHANGE, wl.chain_seed, mu)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / args.steps
+    prof = plan.profile_read()
+    plan.profile(False)
+    samples = total * n_sweeps
+    line = {"metric": "batched moment samples/s (instance-weighted)", "value": samples / el, "unit": "samples/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "heisenberg_square8x8_rbm_alpha2_batched_moments", "instances": n_inst,
+                       "momenta": n_q, "orders": n_ord, "total_chains": total, "burn_in_sweeps": n_burn,
+                       "recorded_sweeps": n_sweeps, "chains_per_instance": [int(counts.min()), int(counts.max())]},
+            "autotuned": {"waves_per_block": w, "blocks": b, "probe_ms": tune_ms},
+            "kernel_ms": prof["batched"][1] / prof["batched"][0],
+            "chain_steps_per_s": total * (n_burn + n_sweeps) * N / el}
+    print(json.dumps(line))
+    plan.close()
+
+
+def fp32_compare(crbm, plan, fit, flat, T, R, wl, args, ms_per_step, prof):
+    """The plain FP32 path: the same step with FP32 operands in the S contraction.
+
+    The FP32 contraction is timed on the first N_s/k samples (its cost is linear in
+    the sample count) and scaled by k; the other stages are shared with the BF16 step.
+    The BF16 and FP32 steps' dalpha are compared on that sub-sample."""
+    k = args.fp32_fraction
+    ns = flat.shape[0]
+    nk = ns // k
+    sub_s, sub_T, sub_R = flat[:nk], T[:nk], R[:nk]
+    stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+    out = {}
+    P = wl.P
+    dal = {}
+    for name, pr in (("fp32", crbm.FP32), ("bf16", crbm.BF16)):
+        f = crbm.RBM(fit.a.clone(), fit.b.clone(), fit.W.clone())
+        plan.profile(True)
+        crbm.sr_step(plan, f, sub_s, sub_T, sub_R, 0.1, wl.diag_shift, crbm.CG_DENSE, pr, 1e-6, args.cg_maxit, stats)
+        pr_ = plan.profile_read()
+        plan.profile(False)
+        dx = torch.zeros(P, dtype=torch.complex128, device="cuda")
+        crbm.copy_plan_buffer(plan, crbm.BUF_DALPHA, dx)
+        torch.cuda.synchronize()
+        dal[name] = dx
+        out[name + "_sbuild_ms_sub"] = pr_["sbuild"][1] / pr_["sbuild"][0]
+    fp32_build_full = out["fp32_sbuild_ms_sub"] * k
+    bf16_build = prof["sbuild"][1] / prof["sbuild"][0]
+    fp32_step = ms_per_step - bf16_build + fp32_build_full
+    rel = float((dal["bf16"] - dal["fp32"]).abs().max() / dal["fp32"].abs().max())
+    return {"sub_samples": nk, "fp32_sbuild_ms_scaled": fp32_build_full, "fp32_ms_per_step": fp32_step,
+            "fp32_samples_per_s": ns / (fp32_step / 1e3), "bf16_speedup_vs_fp32": fp32_step / ms_per_step,
+            "fp32_sbuild_tflops": 4.0 * P * (P + 1) * nk / (out["fp32_sbuild_ms_sub"] / 1e3) / 1e12,
+            "dalpha_bf16_vs_fp32_rel_diff": rel,
+            "mu_n": "identical in both paths (moments do not use S)"}
 
 
 def cpu_baseline(budget_s, ns, sweeps, C):

@@ -132,6 +132,7 @@ enum {
     CRBM_PROF_MOMENT,       /* per-order moment ratio kernel */
     CRBM_PROF_PACK,         /* operand packing for the S contraction (two kernels) */
     CRBM_PROF_CHOLESKY,     /* whole Cholesky factorisation and solve (many kernels) */
+    CRBM_PROF_BATCHED,      /* batched moments: counter reset, persistent kernel, per-instance reduction */
     CRBM_PROF_COUNT
 };
 int crbm_plan_profile(crbm_plan plan, int enable);
@@ -217,6 +218,33 @@ int crbm_chebyshev_moment(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_
  * tanh_theta and R as written by crbm_local_estimators for the same fit and samples. */
 int crbm_fidelity_grad(crbm_plan plan, const crbm_rbm* fit, const int8_t* samples, const void* tanh_theta,
                        const void* R, long n_samples, void* grad_out, double* loss_out, hipStream_t stream);
+
+/* Batched Chebyshev moments of many (q, n) instances in one persistent launch (Sec. II moments,
+ * App. A momentum form).  Instance i has a momentum q_i, a stored state t~_i and beta_i, and owns
+ * c_i = chain_offsets[i+1] - chain_offsets[i] Markov chains on psi_gs.  Chain g (global index) starts
+ * from a Fisher-Yates S^z = 0 configuration (Philox tag 1, counter a = g, as crbm_init_chains), runs
+ * n_burn unrecorded and n_sweeps recorded sweeps with the proposals of crbm_sample (counter a = g,
+ * step = sweep*N + k), and after each recorded sweep adds |f_q(s)|^2 and f_q(s)^* beta_i t~_i(s)/psi_gs(s).
+ *   t_params      complex64 [n_inst][P], packed [a|b|W] of each t~_i
+ *   betas         complex128 [n_inst]
+ *   q             device double [n_inst][2]
+ *   chain_offsets device int64 [n_inst + 1], non-decreasing, chain_offsets[0] = 0,
+ *                 chain_offsets[n_inst] = total_chains <= the plan's max_samples
+ *   mu_out        complex128 [n_inst][2] = (<|f_q|^2>, <f_q^* beta t~/psi_gs>) per instance
+ * Waves of a persistent grid take chains from an atomic counter; partial sums are reduced per
+ * instance in chain order, so the result does not depend on the schedule.  The launch shape is the
+ * plan's default or the one chosen by crbm_batched_autotune.  Safe to capture in a graph. */
+int crbm_batched_moments(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_params, const double* betas,
+                         const double* q, const int64_t* chain_offsets, int n_inst, int64_t total_chains, int n_burn,
+                         int n_sweeps, int proposal, uint64_t seed, void* mu_out, hipStream_t stream);
+/* Times the persistent kernel of crbm_batched_moments for several launch shapes (waves per block 1..8,
+ * blocks per compute unit 1..8) on the given instances with n_sweeps_probe sweeps, stores the fastest
+ * in the plan and returns it (any output may be NULL).  Synchronises the host: call it outside graph
+ * capture. */
+int crbm_batched_autotune(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_params, const double* betas,
+                          const double* q, const int64_t* chain_offsets, int n_inst, int64_t total_chains,
+                          int n_sweeps_probe, int proposal, uint64_t seed, void* mu_scratch,
+                          int* waves_per_block, int* blocks, double* best_ms, hipStream_t stream);
 
 #ifdef __cplusplus
 }

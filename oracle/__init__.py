@@ -82,6 +82,10 @@ def lib():
         L.orc_fidelity_grad.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _i8p, _c128p, _c.c_long,
                                         _c.c_void_p]
         L.orc_fidelity_grad.restype = _c.c_double
+        _i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+        L.orc_batched_moments.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _c128p, _c128p, _c128p, _f64p, _i64p,
+                                          _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_uint64, _c.c_int, _c.c_int,
+                                          _c.c_double, _c128p, _c.POINTER(_c.c_long)]
         _lib = L
     return _lib
 
@@ -289,3 +293,15 @@ def fidelity_grad(rbm, sig, R):
     g = np.zeros(rbm.P, np.complex128)
     L = lib().orc_fidelity_grad(rbm.N, rbm.M, rbm.b, rbm.W, sig, R, sig.shape[0], _ptr(g))
     return L, g
+
+
+def batched_moments(psi_gs, t_params, betas, qs, offsets, lat, n_burn, n_sweeps, proposal, seed, margin=1e-4):
+    """Per-instance (<|f_q|^2>, <conj(f_q) beta t~/psi_gs>) and the count of near-threshold steps."""
+    t_params = _c128(np.asarray(t_params).reshape(len(betas), -1))
+    out = np.zeros((len(betas), 2), np.complex128)
+    amb = ctypes.c_long(0)
+    lib().orc_batched_moments(psi_gs.N, psi_gs.M, psi_gs.a, psi_gs.b, psi_gs.W, t_params, _c128(betas),
+                              np.ascontiguousarray(np.asarray(qs, np.float64).reshape(-1, 2)),
+                              np.ascontiguousarray(offsets, np.int64), len(betas), n_burn, n_sweeps, proposal, seed,
+                              lat.kind, lat.Lx, margin, out, ctypes.byref(amb))
+    return out, amb.value

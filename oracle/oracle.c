@@ -604,3 +604,71 @@ double orc_fidelity_grad(int N, int M, const cplx* b, const cplx* W, const int8_
     free(O);
     return L;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Batched moments over (q, n) instances (Sec. II moments, App. A momentum     */
+/* form).  Instance i owns chains g in [offsets[i], offsets[i+1]) on psi_gs.  */
+/* Chain g starts from the Fisher-Yates S^z = 0 configuration of              */
+/* orc_init_chains (chain index g), runs n_burn + n_sweeps sweeps of the      */
+/* orc_metropolis proposals (counter (g, t, tag 0), t = sweep*N + k), and     */
+/* after each of the last n_sweeps sweeps adds |f_q(s)|^2 and                 */
+/* conj(f_q(s)) beta_i t~_i(s)/psi_gs(s), every amplitude from scratch.       */
+/* mu_out[i] = (<|f_q|^2>, <conj(f_q) beta t~/psi_gs>).  n_ambiguous counts   */
+/* steps with |u - r| <= margin * max(r, 1e-30) (where a lower-precision      */
+/* implementation could take the other branch).                               */
+/* ------------------------------------------------------------------------- */
+void orc_batched_moments(int N, int M, const cplx* ag, const cplx* bg, const cplx* Wg,
+                         const cplx* t_params, const cplx* betas, const double* qs,
+                         const int64_t* offsets, int n_inst, int n_burn, int n_sweeps, int proposal,
+                         uint64_t seed, int kind, int Lx, double margin, cplx* mu_out, long* n_ambiguous) {
+    long P = (long)N + M + (long)N * M;
+    long amb = 0;
+    for (int inst = 0; inst < n_inst; ++inst) {
+        const cplx* tp = t_params + (long)inst * P;
+        const double* q = qs + 2 * inst;
+        ksum s0 = {0, 0}, s1 = {0, 0};
+        long cnt = 0;
+        for (int64_t g = offsets[inst]; g < offsets[inst + 1]; ++g) {
+            int8_t* s = (int8_t*)malloc((size_t)N);
+            int8_t* prop = (int8_t*)malloc((size_t)N);
+            cplx* th = (cplx*)malloc(sizeof(cplx) * (size_t)M);
+            for (int i = 0; i < N; ++i) s[i] = (i < N / 2) ? 1 : -1;
+            for (int k = N - 1; k >= 1; --k) {
+                uint32_t r[4];
+                philox_draw(seed, (uint32_t)g, (uint64_t)k, 1u, r);
+                int m = draw_index(r[0], k + 1);
+                int8_t t = s[k]; s[k] = s[m]; s[m] = t;
+            }
+            for (int sw = 0; sw < n_burn + n_sweeps; ++sw) {
+                for (int k = 0; k < N; ++k) {
+                    uint32_t r4[4];
+                    philox_draw(seed, (uint32_t)g, (uint64_t)sw * N + k, 0u, r4);
+                    int i = draw_index(r4[0], N), j = draw_index(r4[1], N);
+                    double u = draw_unit(r4[2]);
+                    memcpy(prop, s, (size_t)N);
+                    if (proposal == 0) prop[i] = (int8_t)(-s[i]);
+                    else {
+                        if (s[i] == s[j]) continue;
+                        prop[i] = s[j]; prop[j] = s[i];
+                    }
+                    cplx l0 = logpsi_one(N, M, ag, bg, Wg, s, th);
+                    cplx l1 = logpsi_one(N, M, ag, bg, Wg, prop, th);
+                    double rr = exp(2.0 * creal(l1 - l0));
+                    if (fabs(u - rr) <= margin * fmax(rr, 1e-30)) ++amb;
+                    if (u < rr) memcpy(s, prop, (size_t)N);
+                }
+                if (sw < n_burn) continue;
+                cplx f = fq_of(kind, Lx, N, q, s);
+                cplx lg = logpsi_one(N, M, ag, bg, Wg, s, th);
+                cplx lt = logpsi_one(N, M, tp, tp + N, tp + N + M, s, th);
+                kadd(&s0, conj(f) * f);
+                kadd(&s1, conj(f) * betas[inst] * cexp(lt - lg));
+                ++cnt;
+            }
+            free(s); free(prop); free(th);
+        }
+        mu_out[2 * inst] = cnt ? s0.s / (double)cnt : 0.0;
+        mu_out[2 * inst + 1] = cnt ? s1.s / (double)cnt : 0.0;
+    }
+    if (n_ambiguous) *n_ambiguous = amb;
+}

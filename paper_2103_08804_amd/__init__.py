@@ -30,9 +30,9 @@ BUF_F, BUF_DALPHA, BUF_OMEAN, BUF_S = 0, 1, 2, 3
 # names declared in include/chebrbm.h
 EXPORTS = ("crbm_plan_create", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_last_error", "crbm_plan_profile",
            "crbm_plan_profile_read", "crbm_init_rbm", "crbm_init_chains", "crbm_sample", "crbm_local_estimators",
-           "crbm_sr_step", "crbm_chebyshev_moment", "crbm_fidelity_grad")
-PROF_SAMPLE, PROF_THETA, PROF_LOCAL, PROF_OT, PROF_SBUILD, PROF_CG, PROF_MOMENT, PROF_PACK, PROF_CHOLESKY = range(9)
-PROF_NAMES = ("sample", "theta", "local", "ot", "sbuild", "cg", "moment", "pack", "cholesky")
+           "crbm_sr_step", "crbm_chebyshev_moment", "crbm_fidelity_grad", "crbm_batched_moments",
+           "crbm_batched_autotune")
+PROF_NAMES = ("sample", "theta", "local", "ot", "sbuild", "cg", "moment", "pack", "cholesky", "batched")
 
 
 class CrbmError(RuntimeError):
@@ -81,6 +81,10 @@ def lib():
         L.crbm_sr_step.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _l, _d, _d, _i, _i, _d, _i, _vp, _vp]
         L.crbm_chebyshev_moment.argtypes = [_vp, P(_Rbm), _vp, _vp, _i, P(_d), _i, _vp, _vp, _l, _vp, _vp]
         L.crbm_fidelity_grad.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _l, _vp, _vp, _vp]
+        L.crbm_batched_moments.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _i, ctypes.c_int64, _i, _i, _i, _u64,
+                                           _vp, _vp]
+        L.crbm_batched_autotune.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _i, ctypes.c_int64, _i, _i, _u64, _vp,
+                                            P(_i), P(_i), P(_d), _vp]
         for name in EXPORTS:
             if name != "crbm_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -311,3 +315,32 @@ def fidelity_grad(plan: Plan, fit: RBM, samples, tanh_theta, R, grad_out, loss_o
         _ptr(grad_out, torch.complex128, (P,), "grad_out") if grad_out is not None else None,
         _ptr(loss_out, torch.float64, (1,), "loss_out"),
         _stream(stream)))
+
+
+def batched_moments(plan: Plan, psi_gs: RBM, t_params, betas, q, chain_offsets, n_burn: int, n_sweeps: int,
+                    proposal: int, seed: int, mu_out, stream=None):
+    """Per-instance (<|f_q|^2>, <f_q^* beta t~/psi_gs>) for all instances in one persistent launch."""
+    n_inst, P = t_params.shape
+    total = int(chain_offsets[-1].item()) if chain_offsets.numel() else 0
+    g = psi_gs.struct()
+    _check(lib().crbm_batched_moments(
+        plan.handle, ctypes.byref(g), _ptr(t_params, torch.complex64, (n_inst, plan.P), "t_params"),
+        _ptr(betas, torch.complex128, (n_inst,), "betas"), _ptr(q, torch.float64, (n_inst, 2), "q"),
+        _ptr(chain_offsets, torch.int64, (n_inst + 1,), "chain_offsets"), n_inst, total, n_burn, n_sweeps, proposal,
+        seed, _ptr(mu_out, torch.complex128, (n_inst, 2), "mu_out"), _stream(stream)))
+
+
+def batched_autotune(plan: Plan, psi_gs: RBM, t_params, betas, q, chain_offsets, n_sweeps_probe: int,
+                     proposal: int, seed: int, stream=None):
+    """Pick the launch shape of the batched kernel (host-synchronising). Returns (waves_per_block, blocks, ms)."""
+    n_inst = t_params.shape[0]
+    total = int(chain_offsets[-1].item())
+    scratch = torch.empty(n_inst, 2, dtype=torch.complex128, device=t_params.device)
+    g = psi_gs.struct()
+    w, b, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(lib().crbm_batched_autotune(
+        plan.handle, ctypes.byref(g), _ptr(t_params, torch.complex64, (n_inst, plan.P), "t_params"),
+        _ptr(betas, torch.complex128, (n_inst,), "betas"), _ptr(q, torch.float64, (n_inst, 2), "q"),
+        _ptr(chain_offsets, torch.int64, (n_inst + 1,), "chain_offsets"), n_inst, total, n_sweeps_probe, proposal,
+        seed, _ptr(scratch), ctypes.byref(w), ctypes.byref(b), ctypes.byref(ms), _stream(stream)))
+    return w.value, b.value, ms.value

@@ -26,6 +26,7 @@ hipError_t launch_moment_accum(const double2* f, const double2* B, int b_is_f, c
                                int nn, int entry0, int total, double2* partial, int n_blocks, hipStream_t stream);
 hipError_t launch_moment_final(const double2* partial, int n_blocks, int total, double2* mu, hipStream_t stream);
 size_t sbuild_pack_bytes(int N, int M, long max_samples);
+
 }  // namespace crbm
 
 using namespace crbm;
@@ -66,6 +67,10 @@ struct crbm_plan_s {
     double2* momB = nullptr;
     double2* momF = nullptr;
     double2* mom_partial = nullptr;
+    unsigned long long* bcounter = nullptr;
+    double2* bpartial = nullptr;
+    int n_cu = 256;
+    int b_waves = 4, b_blocks = 1024;
     Profiler prof;
     std::vector<void*> allocs;
 
@@ -205,6 +210,8 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
     rc = rc ? rc : p->alloc(&p->momB, S);
     rc = rc ? rc : p->alloc(&p->momF, (long)kQChunk * S);
     rc = rc ? rc : p->alloc(&p->mom_partial, (long)kMomBlocks * kMaxMomentEntries);
+    rc = rc ? rc : p->alloc(&p->bcounter, 1);
+    rc = rc ? rc : p->alloc(&p->bpartial, 2 * S);
     if (!rc && (flags & (CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY))) rc = p->alloc(&p->w.S, P * P);
     if (!rc && (flags & CRBM_PLAN_CHOLESKY)) rc = p->alloc(&p->w.S64, P * P);
     if (!rc && (flags & (CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY))) {
@@ -214,6 +221,10 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
     p->w.prof = &p->prof;
     if (rc) { delete p; return rc; }
     p->w.red_len = red_len;
+    if (hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || p->n_cu < 1)
+        p->n_cu = 256;
+    p->b_waves = 4;
+    p->b_blocks = 4 * p->n_cu;
     e = hipMemcpy(p->bonds, bonds.data(), bonds.size() * sizeof(int2), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->w.scal, 0, 32 * sizeof(double));
     if (e != hipSuccess) { delete p; return hip_fail(e, "plan initialisation"); }
@@ -497,6 +508,88 @@ int crbm_fidelity_grad(crbm_plan p, const crbm_rbm* fit, const int8_t* samples, 
     A.loss = loss_out;
     hipError_t e = launch_fidelity_grad(A, p->w, stream);
     return e == hipSuccess ? CRBM_OK : hip_fail(e, "fidelity_grad launch");
+}
+
+static int batched_args(crbm_plan p, const crbm_rbm* gs, const void* t_params, const double* betas, const double* q,
+                        const int64_t* offsets, int n_inst, int64_t total, int n_burn, int n_sweeps, int proposal,
+                        uint64_t seed, BatchedArgs& A) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (int rc = check_rbm(p, gs, "psi_gs")) return rc;
+    if (!t_params || !betas || !q || !offsets) return fail(CRBM_EINVAL, "t_params, betas, q and chain_offsets must be non-NULL");
+    if (n_inst < 1) return fail(CRBM_EINVAL, "n_inst must be >= 1");
+    if (total < 0 || total > p->max_samples)
+        return fail(CRBM_ENOMEM, "total_chains = %lld must be in [0, max_samples = %ld]", (long long)total, p->max_samples);
+    if (n_burn < 0 || n_sweeps < 1) return fail(CRBM_EINVAL, "need n_burn >= 0 and n_sweeps >= 1");
+    if (proposal != CRBM_PROPOSAL_FLIP && proposal != CRBM_PROPOSAL_EXCHANGE)
+        return fail(CRBM_EINVAL, "unknown proposal %d", proposal);
+    if (p->N % 2) return fail(CRBM_EINVAL, "the S^z = 0 chain starts need an even number of sites");
+    if (int rc = set_device(p)) return rc;
+    A.N = p->N; A.M = p->M; A.P = (int)p->P; A.kind = p->lat.kind; A.Lx = p->lat.Lx;
+    A.gs = view(gs);
+    A.t_params = static_cast<const float2*>(t_params);
+    A.betas = reinterpret_cast<const double2*>(betas);
+    A.q = q;
+    A.offsets = offsets;
+    A.n_inst = n_inst;
+    A.total = total;
+    A.n_burn = n_burn;
+    A.n_sweeps = n_sweeps;
+    A.proposal = proposal;
+    A.seed = seed;
+    A.counter = p->bcounter;
+    A.partial = p->bpartial;
+    return CRBM_OK;
+}
+
+int crbm_batched_moments(crbm_plan p, const crbm_rbm* gs, const void* t_params, const double* betas, const double* q,
+                         const int64_t* offsets, int n_inst, int64_t total, int n_burn, int n_sweeps, int proposal,
+                         uint64_t seed, void* mu_out, hipStream_t stream) {
+    BatchedArgs A{};
+    if (int rc = batched_args(p, gs, t_params, betas, q, offsets, n_inst, total, n_burn, n_sweeps, proposal, seed, A))
+        return rc;
+    if (!mu_out) return fail(CRBM_EINVAL, "mu_out is NULL");
+    p->prof.begin(PROF_BATCHED, stream);
+    hipError_t e = launch_batched(A, p->b_blocks, p->b_waves, static_cast<double2*>(mu_out), stream);
+    p->prof.end(stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "batched_moments launch");
+}
+
+int crbm_batched_autotune(crbm_plan p, const crbm_rbm* gs, const void* t_params, const double* betas, const double* q,
+                          const int64_t* offsets, int n_inst, int64_t total, int n_probe, int proposal, uint64_t seed,
+                          void* mu_scratch, int* waves_out, int* blocks_out, double* ms_out, hipStream_t stream) {
+    BatchedArgs A{};
+    if (int rc = batched_args(p, gs, t_params, betas, q, offsets, n_inst, total, 0, n_probe, proposal, seed, A))
+        return rc;
+    if (!mu_scratch) return fail(CRBM_EINVAL, "mu_scratch is NULL");
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(CRBM_EHIP, "hipEventCreate");
+    double best = 1e300;
+    int bw = p->b_waves, bb = p->b_blocks;
+    const int waves[4] = {1, 2, 4, 8}, per_cu[4] = {1, 2, 4, 8};
+    for (int wi = 0; wi < 4; ++wi)
+        for (int ci = 0; ci < 4; ++ci) {
+            const int blocks = per_cu[ci] * p->n_cu;
+            hipError_t r = hipEventRecord(e0, stream);
+            if (r == hipSuccess) r = launch_batched(A, blocks, waves[wi], static_cast<double2*>(mu_scratch), stream);
+            if (r == hipSuccess) r = hipEventRecord(e1, stream);
+            if (r == hipSuccess) r = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+            if (r != hipSuccess) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return hip_fail(r, "batched autotune");
+            }
+            if (ms < best) { best = ms; bw = waves[wi]; bb = blocks; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->b_waves = bw;
+    p->b_blocks = bb;
+    if (waves_out) *waves_out = bw;
+    if (blocks_out) *blocks_out = bb;
+    if (ms_out) *ms_out = best;
+    return CRBM_OK;
 }
 
 }  // extern "C"

@@ -106,7 +106,7 @@ struct SrWork {
 
 // instrumentation group ids (mirrors CRBM_PROF_* of the public header)
 enum { PROF_SAMPLE = 0, PROF_THETA, PROF_LOCAL, PROF_OT, PROF_SBUILD, PROF_CG, PROF_MOMENT, PROF_PACK, PROF_CHOLESKY,
-       PROF_COUNT };
+       PROF_BATCHED, PROF_COUNT };
 
 struct SrArgs {
     int N, M, P;
@@ -123,6 +123,23 @@ struct SrArgs {
     double* stats;                     // device [8]
 };
 hipError_t launch_sr_step(const SrArgs& args, const SrWork& w, hipStream_t stream);
+
+// ---------------------------------------------------------------- batched moments
+struct BatchedArgs {
+    int N, M, P, kind, Lx;
+    RbmView gs;
+    const float2* t_params;      // [n_inst][P]
+    const double2* betas;        // [n_inst]
+    const double* q;             // [n_inst][2]
+    const int64_t* offsets;      // [n_inst + 1]
+    int n_inst;
+    int64_t total;
+    int n_burn, n_sweeps, proposal;
+    uint64_t seed;
+    unsigned long long* counter;
+    double2* partial;            // [total][2]
+};
+hipError_t launch_batched(const BatchedArgs& A, int blocks, int waves_per_block, double2* mu, hipStream_t stream);
 
 struct GradArgs {
     int N, M, P;

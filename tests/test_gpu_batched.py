@@ -1,0 +1,87 @@
+"""Batched moments over (q, n) instances: parity with the oracle, graph capture and replay,
+and independence of the result from the launch shape chosen by the autotuner."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2103_08804_amd as crbm
+import synth
+from gpu_util import np_of, rel_err, to_device_rbm, to_oracle_rbm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    crbm.lib()
+
+
+def _instances(orc, kind, Lx, Ly, M, counts, seed=5):
+    N = Lx * Ly
+    gs_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(seed, N, M, 0.1, std_im=0.02)))
+    n_inst = len(counts)
+    tv = np.stack([orc.RBM(*synth.random_rbm_arrays(seed + 1 + i, N, M, 0.1, std_im=0.02)).vector()
+                   for i in range(n_inst)]).astype(np.complex64)
+    r = np.random.default_rng(seed)
+    betas = r.normal(size=n_inst) + 1j * r.normal(size=n_inst)
+    qs = np.stack([r.uniform(0, 2 * np.pi, n_inst), r.uniform(0, 2 * np.pi, n_inst) if kind == 1 else
+                   np.zeros(n_inst)], axis=1)
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    dev = dict(t=torch.from_numpy(tv).cuda(), b=torch.from_numpy(betas).cuda(), q=torch.from_numpy(qs).cuda(),
+               o=torch.from_numpy(offsets).cuda())
+    return gs_d, tv, betas, qs, offsets, dev
+
+
+@pytest.mark.parametrize("kind,Lx,Ly,M,counts,proposal", [
+    (1, 4, 4, 16, [3, 0, 5, 1, 7, 2], 1),
+    (0, 12, 1, 24, [2, 4, 1], 0),
+])
+def test_batched_vs_oracle(orc, kind, Lx, Ly, M, counts, proposal):
+    N = Lx * Ly
+    gs_d, tv, betas, qs, offsets, dev = _instances(orc, kind, Lx, Ly, M, counts)
+    plan = crbm.Plan(kind, Lx, Ly, M, int(offsets[-1]) + 1)
+    mu = torch.zeros(len(counts), 2, dtype=torch.complex128, device="cuda")
+    crbm.batched_moments(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 2, 5, proposal, 99, mu)
+    torch.cuda.synchronize()
+    gs = to_oracle_rbm(orc, gs_d)
+    lat = orc.Lattice(kind, Lx, Ly)
+    ref, amb = orc.batched_moments(gs, tv.astype(np.complex128), betas, qs, offsets, lat, 2, 5, proposal, 99)
+    assert amb == 0          # no step close enough to the threshold for FP32 to take the other branch
+    assert rel_err(np_of(mu), ref) < 1e-5
+
+
+def test_batched_graph_replay_and_autotune(orc):
+    kind, Lx, Ly, M = 1, 8, 8, 128
+    r = np.random.default_rng(4)
+    counts = r.integers(4, 33, 48)
+    gs_d, tv, betas, qs, offsets, dev = _instances(orc, kind, Lx, Ly, M, counts, seed=8)
+    plan = crbm.Plan(kind, Lx, Ly, M, int(offsets[-1]))
+    eager = torch.zeros(len(counts), 2, dtype=torch.complex128, device="cuda")
+    crbm.batched_moments(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 1, 3, 1, 7, eager)
+    torch.cuda.synchronize()
+    ref = eager.clone()
+    # graph capture of the whole launch sequence, several replays with eager work in between
+    out = torch.zeros_like(eager)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            crbm.batched_moments(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 1, 3, 1, 7, out)
+    torch.cuda.current_stream().wait_stream(s)
+    for k in range(3):
+        out.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), k
+        crbm.batched_moments(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 1, 3, 1, 7, eager)
+        torch.cuda.synchronize()
+        assert torch.equal(eager, ref)
+    # a different launch shape gives the same bits
+    w, b, ms = crbm.batched_autotune(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 1, 1, 7)
+    assert w in (1, 2, 4, 8) and b >= 1 and ms > 0
+    crbm.batched_moments(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 1, 3, 1, 7, eager)
+    torch.cuda.synchronize()
+    assert torch.equal(eager, ref)
