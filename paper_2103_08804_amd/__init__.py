@@ -318,10 +318,13 @@ def fidelity_grad(plan: Plan, fit: RBM, samples, tanh_theta, R, grad_out, loss_o
 
 
 def batched_moments(plan: Plan, psi_gs: RBM, t_params, betas, q, chain_offsets, n_burn: int, n_sweeps: int,
-                    proposal: int, seed: int, mu_out, stream=None):
-    """Per-instance (<|f_q|^2>, <f_q^* beta t~/psi_gs>) for all instances in one persistent launch."""
+                    proposal: int, seed: int, mu_out, total_chains: int | None = None, stream=None):
+    """Per-instance (<|f_q|^2>, <f_q^* beta t~/psi_gs>) for all instances in one persistent launch.
+
+    total_chains (= chain_offsets[-1]) must be given under graph capture, where reading it back from
+    the device is not allowed."""
     n_inst, P = t_params.shape
-    total = int(chain_offsets[-1].item()) if chain_offsets.numel() else 0
+    total = int(chain_offsets[-1].item()) if total_chains is None else int(total_chains)
     g = psi_gs.struct()
     _check(lib().crbm_batched_moments(
         plan.handle, ctypes.byref(g), _ptr(t_params, torch.complex64, (n_inst, plan.P), "t_params"),

@@ -69,7 +69,8 @@ def test_batched_graph_replay_and_autotune(orc):
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.stream(s):
         with torch.cuda.graph(graph, stream=s):
-            crbm.batched_moments(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 1, 3, 1, 7, out)
+            crbm.batched_moments(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 1, 3, 1, 7, out,
+                                 total_chains=int(offsets[-1]))
     torch.cuda.current_stream().wait_stream(s)
     for k in range(3):
         out.zero_()
