@@ -26,6 +26,7 @@ hipError_t launch_moment_accum(const double2* f, const double2* B, int b_is_f, c
                                int nn, int entry0, int total, double2* partial, int n_blocks, hipStream_t stream);
 hipError_t launch_moment_final(const double2* partial, int n_blocks, int total, double2* mu, hipStream_t stream);
 size_t sbuild_pack_bytes(int N, int M, long max_samples);
+std::vector<int2> sbuild_order(int N, int M, int n_xcd, int g);
 
 }  // namespace crbm
 
@@ -38,6 +39,11 @@ constexpr long kCholMaxP = 4000;
 constexpr int kQChunk = 8;
 constexpr int kMomBlocks = 256;
 constexpr int kMaxMomentEntries = 4096;   // n_q * (n_max + 1)
+constexpr int kXcds = 8;                   // accelerator complex dies of the MI355X (round-robin dispatch)
+#ifndef CRBM_SUPERTILE
+#define CRBM_SUPERTILE 8
+#endif
+constexpr int kSuperTile = CRBM_SUPERTILE; // tile pairs per super-tile side in the S contraction order
 
 thread_local char g_err[512] = "";
 
@@ -214,9 +220,15 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
     rc = rc ? rc : p->alloc(&p->bpartial, 2 * S);
     if (!rc && (flags & (CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY))) rc = p->alloc(&p->w.S, P * P);
     if (!rc && (flags & CRBM_PLAN_CHOLESKY)) rc = p->alloc(&p->w.S64, P * P);
+    std::vector<int2> order;
     if (!rc && (flags & (CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY))) {
         p->w.pack_bytes = sbuild_pack_bytes((int)N, (int)M, S);
         rc = p->alloc(reinterpret_cast<unsigned char**>(&p->w.pack), p->w.pack_bytes);
+        order = sbuild_order((int)N, (int)M, kXcds, kSuperTile);
+        int2* d_order = nullptr;
+        rc = rc ? rc : p->alloc(&d_order, order.size());
+        p->w.sb_order = d_order;
+        p->w.sb_order_len = (long)order.size();
     }
     p->w.prof = &p->prof;
     if (rc) { delete p; return rc; }
@@ -227,6 +239,9 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
     p->b_blocks = 4 * p->n_cu;
     e = hipMemcpy(p->bonds, bonds.data(), bonds.size() * sizeof(int2), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->w.scal, 0, 32 * sizeof(double));
+    if (e == hipSuccess && !order.empty())
+        e = hipMemcpy(const_cast<int2*>(p->w.sb_order), order.data(), order.size() * sizeof(int2),
+                      hipMemcpyHostToDevice);
     if (e != hipSuccess) { delete p; return hip_fail(e, "plan initialisation"); }
     *out = p;
     return CRBM_OK;

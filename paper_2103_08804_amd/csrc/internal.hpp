@@ -101,6 +101,8 @@ struct SrWork {
     float2* vstage;           // [P] float copy of a CG direction
     void* pack;               // packed operand planes of the matrix-core S contraction
     size_t pack_bytes;
+    const int2* sb_order;     // dispatch order of its tile pairs
+    long sb_order_len;
     Profiler* prof;
 };
 

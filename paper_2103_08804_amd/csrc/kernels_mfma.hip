@@ -19,6 +19,8 @@
 // index and writes the tile and its conjugate transpose.
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "../../include/chebrbm.h"
 #include "device.hpp"
 #include "internal.hpp"
@@ -110,7 +112,8 @@ struct Pol<false> {
 };
 
 template <bool BF16>
-__global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, int nJ, long n_tiles, long ns_pad,
+__global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, int nJ, const int2* __restrict__ order,
+                                                        long ns_pad,
                                                         const typename Pol<BF16>::E* __restrict__ Tr,
                                                         const typename Pol<BF16>::E* __restrict__ Ti,
                                                         const typename Pol<BF16>::E* __restrict__ Sm,
@@ -125,11 +128,10 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, in
     constexpr int STAGE = 4 * PLANE + MASKS;
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
 
-    // tile pair (u, u'), u <= u'
-    long rem = blockIdx.x;
-    long u = 0;
-    while (rem >= n_tiles - u) { rem -= n_tiles - u; ++u; }
-    const long up = u + rem;
+    // tile pair (u, u'), u <= u', from the dispatch-order table (entries < 0 are padding)
+    const int2 pr = order[blockIdx.x];
+    if (pr.x < 0) return;
+    const long u = pr.x, up = pr.y;
     const int I = (int)(u / nJ), J = (int)(u % nJ);
     const int Ip = (int)(up / nJ), Jp = (int)(up % nJ);
 
@@ -317,14 +319,15 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, in
 
 // ------------------------------------------------------------------ launcher
 hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n, const double2* Om,
-                              float2* S, int prec, void* pack, size_t pack_bytes, Profiler* prof, hipStream_t stream) {
+                              float2* S, int prec, void* pack, size_t pack_bytes, const int2* order, long n_order,
+                              Profiler* prof, hipStream_t stream) {
     const int Mp = ((M + 1 + MK_TJ - 1) / MK_TJ) * MK_TJ;
     const int Np = ((N + 1 + MK_TI - 1) / MK_TI) * MK_TI;
     const long ns_pad = ((n + MK_KT - 1) / MK_KT) * MK_KT;
     const int nJ = Mp / MK_TJ, nI = Np / MK_TI;
     static_assert(MK_KT % 64 == 0, "the packing grid assumes 64-sample blocks");
-    const long n_tiles = (long)nI * nJ;
-    const long pairs = n_tiles * (n_tiles + 1) / 2;
+    (void)nI;
+    const long pairs = n_order;
     const bool bf16 = (prec == CRBM_PREC_BF16);
     const size_t esz = bf16 ? 2 : 4;
     const size_t need = esz * ((size_t)2 * Mp * ns_pad + (size_t)Np * ns_pad);
@@ -342,7 +345,7 @@ hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const flo
                            Np, ns_pad, Sm);
         prof->end(stream);
         prof->begin(PROF_SBUILD, stream);
-        hipLaunchKernelGGL(k_sbuild_mfma<true>, dim3((unsigned)pairs), dim3(256), 0, stream, N, M, P, nJ, n_tiles,
+        hipLaunchKernelGGL(k_sbuild_mfma<true>, dim3((unsigned)pairs), dim3(256), 0, stream, N, M, P, nJ, order,
                            ns_pad, Tr, Ti, Sm, Om, inv_n, S);
         prof->end(stream);
     } else {
@@ -355,11 +358,39 @@ hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const flo
                            Np, ns_pad, Sm);
         prof->end(stream);
         prof->begin(PROF_SBUILD, stream);
-        hipLaunchKernelGGL(k_sbuild_mfma<false>, dim3((unsigned)pairs), dim3(256), 0, stream, N, M, P, nJ, n_tiles,
+        hipLaunchKernelGGL(k_sbuild_mfma<false>, dim3((unsigned)pairs), dim3(256), 0, stream, N, M, P, nJ, order,
                            ns_pad, Tr, Ti, Sm, Om, inv_n, S);
         prof->end(stream);
     }
     return hipGetLastError();
+}
+
+// Dispatch order of the tile pairs (u <= u').  Workgroup b runs on XCD b % n_xcd (round-robin
+// dispatch), so the pairs are grouped into g x g super-tiles, super-tiles are dealt to the XCDs in
+// turn, and each XCD's list is interleaved into the grid: the workgroups one XCD runs together
+// then share few operand slabs, which stay in that XCD's L2.  Padding entries are (-1, -1).
+std::vector<int2> sbuild_order(int N, int M, int n_xcd, int g) {
+    const int Mp = ((M + 1 + MK_TJ - 1) / MK_TJ) * MK_TJ;
+    const int Np = ((N + 1 + MK_TI - 1) / MK_TI) * MK_TI;
+    const int nt = (Np / MK_TI) * (Mp / MK_TJ);
+    const int ns = (nt + g - 1) / g;
+    std::vector<std::vector<int2>> per(n_xcd);
+    int st = 0;
+    for (int U = 0; U < ns; ++U)
+        for (int V = U; V < ns; ++V, ++st) {
+            std::vector<int2>& L = per[st % n_xcd];
+            for (int a = 0; a < g; ++a)
+                for (int b = 0; b < g; ++b) {
+                    const int u = U * g + a, v = V * g + b;
+                    if (u < nt && v < nt && u <= v) L.push_back(make_int2(u, v));
+                }
+        }
+    size_t longest = 0;
+    for (auto& L : per) longest = L.size() > longest ? L.size() : longest;
+    std::vector<int2> out(longest * n_xcd, make_int2(-1, -1));
+    for (int x = 0; x < n_xcd; ++x)
+        for (size_t k = 0; k < per[x].size(); ++k) out[k * n_xcd + x] = per[x][k];
+    return out;
 }
 
 size_t sbuild_pack_bytes(int N, int M, long max_samples) {

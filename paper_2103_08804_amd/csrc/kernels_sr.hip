@@ -539,7 +539,8 @@ static inline unsigned nblk(long n, int t = 256) { return (unsigned)((n + t - 1)
 hipError_t launch_cholesky_solve(long P, const float2* S, double eps, const double2* F, double2* A64, double2* x,
                                  double* sc, hipStream_t stream);
 hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n, const double2* Om,
-                              float2* S, int prec, void* pack, size_t pack_bytes, Profiler* prof, hipStream_t stream);
+                              float2* S, int prec, void* pack, size_t pack_bytes, const int2* order, long n_order,
+                              Profiler* prof, hipStream_t stream);
 
 static hipError_t apply_op(const SrArgs& A, const SrWork& W, const double2* v, double2* y, hipStream_t stream) {
     const long P = A.P;
@@ -597,8 +598,8 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
                 if (e != hipSuccess) return e;
                 om_s = W.Om16;
             }
-            e = launch_sbuild_mfma(A.N, A.M, P, A.samples, A.T, A.n, om_s, W.S, A.prec, W.pack, W.pack_bytes, W.prof,
-                                   stream);
+            e = launch_sbuild_mfma(A.N, A.M, P, A.samples, A.T, A.n, om_s, W.S, A.prec, W.pack, W.pack_bytes,
+                                   W.sb_order, W.sb_order_len, W.prof, stream);
         } else {
             // weighted (enumeration) sums: FP32 contraction on the vector units
             const int nt = (int)((P + SB_T - 1) / SB_T);
