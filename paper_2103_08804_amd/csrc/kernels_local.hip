@@ -1,6 +1,6 @@
 // theta GEMM, per-sample local estimators and Chebyshev moments.
 //
-//   theta = sigma W + 1 b^T          (RBM of Sec. I), a [n x N] x [N x M] product
+//   theta = sigma W + 1 b^T          (RBM of Sec. I), a [n x N] x [N x M] product on the matrix cores
 //   E_loc(s) = sum_bonds [J/4 s_i s_j + [s_i != s_j] J/2 psi(s^{ij})/psi(s)]   (Sec. VI)
 //   R(s)     = phi(s)/psi_{n+1}(s)  for the Chebyshev targets of Sec. III
 //   mu_n(q)  = < f_q^* beta_n t~_n / psi_gs >                    (Sec. II, App. A)
@@ -17,66 +17,88 @@
 namespace crbm {
 
 // ------------------------------------------------------------------ theta GEMM
-// Block: 256 threads -> 64 samples x 64 hidden units.  Thread (ty, tx) owns
-// samples 4 ty .. 4 ty + 3 and hidden units tx + 16 c (c < 4).
-constexpr int TG_S = 64, TG_K = 64, TG_I = 32;
+// theta = sigma W + b on the matrix cores.  sigma = +-1 is exact in BF16, and each
+// binary32 W entry is split exactly into three BF16 parts by truncation,
+//   W = hi + mid + lo   (8 + 8 + 8 significand bits),
+// so three v_mfma_f32_32x32x16_bf16 products give sigma W with exact products and
+// FP32 accumulation.  The complex W is a real [N][2M] matrix (re, im interleaved), so the
+// output rows are the complex64 theta rows.  Tile: 128 samples x 128 real columns per
+// workgroup (4 waves x 32 samples x 4 column blocks), K chunks of 32 sites through LDS.
+typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8_t;
+typedef __attribute__((__vector_size__(4 * sizeof(int)))) int i32x4_t;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16_t;
+
+constexpr int TH_S = 128, TH_C = 128, TH_K = 32;
+constexpr int TH_ROW = TH_K * 2 + 16;          // bytes per LDS row (32 bf16 + padding)
 
 __global__ __launch_bounds__(256) void k_theta(const int8_t* __restrict__ sig, long n, int N, int M,
                                                 const float2* __restrict__ b, const float2* __restrict__ W,
                                                 float2* __restrict__ theta, const double* __restrict__ skip) {
     if (skip && *skip != 0.0) return;     // a converged iterative solve skips the product
-    __shared__ float s_sig[TG_I][TG_S + 1];
-    __shared__ float2 s_w[TG_I][TG_K];
-    const int tid = threadIdx.x;
-    const int ty = tid >> 4, tx = tid & 15;
-    const long s0 = (long)blockIdx.x * TG_S;
-    const int k0 = blockIdx.y * TG_K;
-    float2 acc[4][4];
+    __shared__ __attribute__((aligned(16))) unsigned char s_sig[TH_S * TH_ROW];
+    __shared__ __attribute__((aligned(16))) unsigned char s_w[3][TH_C * TH_ROW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long s0 = (long)blockIdx.x * TH_S;
+    const int c0 = blockIdx.y * TH_C;                 // first real column
+    const int C = 2 * M;                              // real columns
+    const float* Wf = reinterpret_cast<const float*>(W);
+    floatx16_t acc[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
+    for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = make_float2(0.f, 0.f);
+        for (int v = 0; v < 16; ++v) acc[cb][v] = 0.f;
 
-    for (int i0 = 0; i0 < N; i0 += TG_I) {
-        // stage spins [TG_S samples][TG_I sites] transposed, and W rows
-        for (int e = tid; e < TG_S * TG_I; e += 256) {
-            const int ss = e / TG_I, ii = e % TG_I;
+    for (int k0 = 0; k0 < N; k0 += TH_K) {
+        // sigma tile [128 samples][32 sites] as BF16 (+1 = 0x3F80, -1 = 0xBF80, outside = 0)
+        for (int e = tid; e < TH_S * TH_K; e += 256) {
+            const int ss = e / TH_K, kk = e % TH_K;
             const long s = s0 + ss;
-            const int i = i0 + ii;
-            s_sig[ii][ss] = (s < n && i < N) ? (float)sig[s * N + i] : 0.f;
+            const int i = k0 + kk;
+            uint16_t v = 0;
+            if (s < n && i < N) v = sig[s * N + i] > 0 ? 0x3F80 : 0xBF80;
+            *reinterpret_cast<uint16_t*>(s_sig + ss * TH_ROW + kk * 2) = v;
         }
-        for (int e = tid; e < TG_I * TG_K; e += 256) {
-            const int ii = e / TG_K, kk = e % TG_K;
-            const int i = i0 + ii, k = k0 + kk;
-            s_w[ii][kk] = (i < N && k < M) ? W[(long)i * M + k] : make_float2(0.f, 0.f);
+        // W^T tile [128 columns][32 sites], three exact BF16 parts
+        for (int e = tid; e < TH_C * TH_K; e += 256) {
+            const int kk = e / TH_C, cc = e % TH_C;
+            const int i = k0 + kk, c = c0 + cc;
+            const float w = (i < N && c < C) ? Wf[(long)i * C + c] : 0.f;
+            const uint32_t u = __float_as_uint(w);
+            const uint32_t hi = u & 0xFFFF0000u;
+            const float r1 = w - __uint_as_float(hi);
+            const uint32_t mid = __float_as_uint(r1) & 0xFFFF0000u;
+            const float r2 = r1 - __uint_as_float(mid);
+            *reinterpret_cast<uint16_t*>(s_w[0] + cc * TH_ROW + kk * 2) = (uint16_t)(hi >> 16);
+            *reinterpret_cast<uint16_t*>(s_w[1] + cc * TH_ROW + kk * 2) = (uint16_t)(mid >> 16);
+            *reinterpret_cast<uint16_t*>(s_w[2] + cc * TH_ROW + kk * 2) = (uint16_t)(__float_as_uint(r2) >> 16);
         }
         __syncthreads();
-#pragma unroll 8
-        for (int ii = 0; ii < TG_I; ++ii) {
-            float sv[4];
-            float2 wv[4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) sv[r] = s_sig[ii][ty * 4 + r];
+        for (int kq = 0; kq < TH_K; kq += 16) {
+            const int koff = (kq + 8 * (lane >> 5)) * 2;
+            const i32x4_t a = *reinterpret_cast<const i32x4_t*>(s_sig + (wave * 32 + (lane & 31)) * TH_ROW + koff);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) wv[c] = s_w[ii][tx + 16 * c];
+            for (int part = 0; part < 3; ++part)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    acc[r][c].x = fmaf(sv[r], wv[c].x, acc[r][c].x);
-                    acc[r][c].y = fmaf(sv[r], wv[c].y, acc[r][c].y);
+                for (int cb = 0; cb < 4; ++cb) {
+                    const i32x4_t bw =
+                        *reinterpret_cast<const i32x4_t*>(s_w[part] + (cb * 32 + (lane & 31)) * TH_ROW + koff);
+                    acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16((bf16x8_t)a, (bf16x8_t)bw, acc[cb], 0, 0, 0);
                 }
         }
         __syncthreads();
     }
+    const float* bf = reinterpret_cast<const float*>(b);
+    float* out = reinterpret_cast<float*>(theta);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const long s = s0 + ty * 4 + r;
-        if (s >= n) continue;
+    for (int cb = 0; cb < 4; ++cb) {
+        const int c = c0 + cb * 32 + (lane & 31);
+        if (c >= C) continue;
+        const float bc = bf[c];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int k = k0 + tx + 16 * c;
-            if (k < M) theta[s * M + k] = cadd(acc[r][c], b[k]);
+        for (int v = 0; v < 16; ++v) {
+            const long s = s0 + wave * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            if (s < n) out[s * C + c] = acc[cb][v] + bc;
         }
     }
 }
@@ -84,7 +106,7 @@ __global__ __launch_bounds__(256) void k_theta(const int8_t* __restrict__ sig, l
 hipError_t launch_theta(const int8_t* sig, long n, int N, int M, const float2* b, const float2* W, float2* theta,
                         hipStream_t stream, const double* skip) {
     if (n <= 0) return hipSuccess;
-    dim3 grid((unsigned)((n + TG_S - 1) / TG_S), (unsigned)((M + TG_K - 1) / TG_K));
+    dim3 grid((unsigned)((n + TH_S - 1) / TH_S), (unsigned)((2 * M + TH_C - 1) / TH_C));
     hipLaunchKernelGGL(k_theta, grid, dim3(256), 0, stream, sig, n, N, M, b, W, theta, skip);
     return hipGetLastError();
 }
