@@ -325,24 +325,59 @@ __global__ __launch_bounds__(256) void k_sbuild(int N, int M, long P, const int8
 }
 
 // ------------------------------------------------------------------ dense complex matvec
-// y = (S + eps I) x, one wave per row, double accumulation
+// y = (S + eps I) x with S complex64 [P][P] (full storage), x and y complex128.
+// One wave owns SV_ROWS consecutive rows, so each x entry it loads serves SV_ROWS rows;
+// lanes read two complex S entries (16 bytes) per row and step; FP64 accumulation.
+constexpr int SV_ROWS = 8;
+
 __global__ __launch_bounds__(256) void k_symv(long P, const float2* __restrict__ S, const double2* __restrict__ x,
                                               double eps, double2* __restrict__ y, const double* __restrict__ sc) {
     if (sc[SC_DONE] != 0.0) return;
     const int lane = threadIdx.x & 63;
-    const long row = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= P) return;
-    const float2* Sr = S + row * P;
-    double ax = 0, ay = 0;
-    for (long k = lane; k < P; k += 64) {
-        const float2 a = Sr[k];
-        const double2 b = x[k];
-        ax += (double)a.x * b.x - (double)a.y * b.y;
-        ay += (double)a.x * b.y + (double)a.y * b.x;
+    const long row0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * SV_ROWS;
+    if (row0 >= P) return;
+    double ax[SV_ROWS], ay[SV_ROWS];
+#pragma unroll
+    for (int r = 0; r < SV_ROWS; ++r) { ax[r] = 0.0; ay[r] = 0.0; }
+    const long P2 = P & ~1L;                        // columns handled in pairs
+    for (long k = 2 * lane; k < P2; k += 128) {
+        const double2 x0 = x[k], x1 = x[k + 1];
+#pragma unroll
+        for (int r = 0; r < SV_ROWS; ++r) {
+            const long row = row0 + r;
+            if (row >= P) break;
+            const float2* Sr = S + row * P + k;
+            float2 a0, a1;
+            if (((row * P) & 1) == 0) {             // 16-byte aligned pair
+                const float4 v = *reinterpret_cast<const float4*>(Sr);
+                a0 = make_float2(v.x, v.y);
+                a1 = make_float2(v.z, v.w);
+            } else {
+                a0 = Sr[0];
+                a1 = Sr[1];
+            }
+            ax[r] += (double)a0.x * x0.x - (double)a0.y * x0.y + (double)a1.x * x1.x - (double)a1.y * x1.y;
+            ay[r] += (double)a0.x * x0.y + (double)a0.y * x0.x + (double)a1.x * x1.y + (double)a1.y * x1.x;
+        }
     }
-    ax = wave_sum(ax);
-    ay = wave_sum(ay);
-    if (lane == 0) y[row] = make_double2(ax + eps * x[row].x, ay + eps * x[row].y);
+    if ((P & 1) && lane == 0) {                     // last column of an odd P
+        const long k = P - 1;
+        const double2 xk = x[k];
+#pragma unroll
+        for (int r = 0; r < SV_ROWS; ++r) {
+            const long row = row0 + r;
+            if (row >= P) break;
+            const float2 a = S[row * P + k];
+            ax[r] += (double)a.x * xk.x - (double)a.y * xk.y;
+            ay[r] += (double)a.x * xk.y + (double)a.y * xk.x;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < SV_ROWS; ++r) {
+        const double sx = wave_sum(ax[r]), sy = wave_sum(ay[r]);
+        const long row = row0 + r;
+        if (lane == 0 && row < P) y[row] = make_double2(sx + eps * x[row].x, sy + eps * x[row].y);
+    }
 }
 
 // ------------------------------------------------------------------ matrix-free S v
@@ -567,7 +602,7 @@ static hipError_t apply_op(const SrArgs& A, const SrWork& W, const double2* v, d
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_add_shift, dim3(nblk(P)), dim3(256), 0, stream, P, v, A.eps, y, W.scal);
     } else {
-        hipLaunchKernelGGL(k_symv, dim3(nblk(P, 4)), dim3(256), 0, stream, P, W.S, v, A.eps, y, W.scal);
+        hipLaunchKernelGGL(k_symv, dim3(nblk(P, 4 * SV_ROWS)), dim3(256), 0, stream, P, W.S, v, A.eps, y, W.scal);
     }
     return hipGetLastError();
 }

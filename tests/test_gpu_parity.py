@@ -347,7 +347,8 @@ def test_fidelity_grad(orc):
 
 
 # ------------------------------------------------------------------ matrix-core S contraction
-@pytest.mark.parametrize("kind,Lx,Ly,M,n", [(0, 10, 1, 10, 1000), (1, 4, 4, 40, 777), (0, 40, 1, 80, 130)])
+@pytest.mark.parametrize("kind,Lx,Ly,M,n", [(0, 10, 1, 10, 1000), (1, 4, 4, 40, 777), (0, 40, 1, 80, 130),
+                                             (0, 7, 1, 3, 200)])
 def test_dense_s_matrix_cores(orc, kind, Lx, Ly, M, n):
     """S from the FP32 and BF16 matrix-core contractions (uniform weights) against the oracle's S.
     FP32 operands: 1e-5 relative.  BF16 operands (8-bit significands) are reported and bounded
