@@ -35,6 +35,21 @@ import torch  # noqa: E402
 import synth  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sbuild_mfma_bf16_square10x10_alpha4_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the S contraction from the committed counter runs, or None when the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+        src = open(os.path.join(ROOT, "paper_2103_08804_amd", "csrc", "kernels_mfma.hip"), "rb").read()
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest() != d["kernels_mfma_hip_sha256"]:
+        return None
+    return d["traffic_bytes_per_launch"]
 BF16_PEAK_TFLOPS = 2500.0
 FP32_MATRIX_PEAK_TFLOPS = 157.3
 
@@ -148,8 +163,11 @@ def main():
         flops = 4.0 * P * (P + 1) * ns          # 8 real flops per complex MAC, P(P+1)/2 entries
         peak = BF16_PEAK_TFLOPS if prec == crbm.BF16 else FP32_MATRIX_PEAK_TFLOPS
         achieved = flops / avg_s / 1e12
+        traffic = measured_traffic() if (prec == crbm.BF16 and C == wl.chains and sweeps == wl.sweeps) else None
         roof = {"kernel": "k_sbuild_mfma", "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None, "algorithmic_flops": flops}
+                "frac": achieved / peak, "traffic": traffic, "algorithmic_flops": flops,
+                "algorithmic_bytes": 2 * ((M + 1 + 31) // 32 * 32) * ns * 2 + ((N + 1 + 3) // 4 * 4) * ns * 2
+                + 8 * P * P}
     else:
         c, t = prof["ot"]
         avg_s = t / c / 1e3
