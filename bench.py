@@ -70,9 +70,11 @@ def parse():
     ap.add_argument("--fp32-fraction", type=int, default=16,
                     help="the plain-FP32 S contraction is timed on N_s / this many samples and scaled")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
-    ap.add_argument("--workload", choices=["square10", "batched8x8"], default="square10",
+    ap.add_argument("--workload", choices=["square10", "batched8x8", "chain40", "grad16x16"], default="square10",
                     help="square10: the metric's 10x10 alpha=4 step (default); batched8x8: 2048 (q, n) moment "
-                         "instances of the 8x8 alpha=2 lattice in one persistent launch")
+                         "instances of the 8x8 alpha=2 lattice in one persistent launch; chain40: the 40-site "
+                         "chain, alpha=2, FP32 dense SR with the FP64 Cholesky solve; grad16x16: forward and "
+                         "hand-written backward of the fidelity surrogate on the 16x16 alpha=2 lattice")
     return ap.parse_args()
 
 
@@ -87,6 +89,10 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batched8x8":
         return bench_batched(crbm, args)
+    if args.workload == "chain40":
+        return bench_chain40(crbm, args)
+    if args.workload == "grad16x16":
+        return bench_grad16(crbm, args)
     wl = synth.SQUARE10
     N, M, P = wl.N, wl.M, wl.P
     C, sweeps = args.chains, args.sweeps
@@ -257,6 +263,98 @@ def bench_batched(crbm, args):
             "kernel_ms": prof["batched"][1] / prof["batched"][0],
             "chain_steps_per_s": total * (n_burn + n_sweeps) * N / el}
     print(json.dumps(line))
+    plan.close()
+
+
+def _timed(plan, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    prof = plan.profile_read()
+    plan.profile(False)
+    return el, {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof.items()}
+
+
+def bench_chain40(crbm, args):
+    """40-site chain, alpha = 2 (P = 3320): 1024 chains x 256 sweeps, local estimators, FP32 dense S on the
+    matrix cores and the FP64 Cholesky solve with diagonal shift 1e-3."""
+    wl = synth.CHAIN40
+    N, M, P = wl.N, wl.M, wl.P
+    C, sweeps = wl.chains, wl.sweeps
+    ns = C * sweeps
+    plan = crbm.Plan(crbm.CHAIN, N, 1, M, ns, crbm.PLAN_CHOLESKY)
+    mk = lambda sd: (lambda r: (crbm.init_rbm(r, sd, wl.param_std), r)[1])(crbm.RBM.empty(N, M))
+    gs, psm, psn, fit = mk(wl.param_seed), mk(wl.param_seed + 1), mk(wl.param_seed + 2), mk(wl.param_seed + 3)
+    E0 = synth.E0_PER_SITE_CHAIN * N
+    W_scale = 1.5 * abs(E0)
+    cheb = crbm.make_cheb(2, E0 + 0.9875 * W_scale, W_scale, 1.0, 1.0, (math.pi, 0.0))
+    chains = torch.zeros(C, N, dtype=torch.int8, device="cuda")
+    crbm.init_chains(plan, chains, wl.chain_seed, True)
+    samples = torch.zeros(sweeps, C, N, dtype=torch.int8, device="cuda")
+    flat = samples.view(ns, N)
+    T = torch.zeros(ns, M, dtype=torch.complex64, device="cuda")
+    R = torch.zeros(ns, dtype=torch.complex64, device="cuda")
+    stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+    crbm.sample(plan, fit, chains, 16, crbm.EXCHANGE, 21, 0)
+    off = [16 * N]
+
+    def step():
+        crbm.sample(plan, fit, chains, sweeps, crbm.EXCHANGE, 21, off[0], samples_out=samples)
+        crbm.local_estimators(plan, fit, flat, psi_n=psn, psi_nm1=psm, cheb=cheb, R_out=R, tanh_out=T)
+        crbm.sr_step(plan, fit, flat, T, R, 0.1, wl.diag_shift, crbm.CHOLESKY, crbm.FP32, 1e-6, 1, stats)
+        off[0] += sweeps * N
+
+    el, phases = _timed(plan, step, args.steps, args.warmup)
+    st = stats.cpu().numpy()
+    print(json.dumps({"metric": "MC samples/s + SR steps/s", "value": ns / el, "unit": "samples/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3, "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "heisenberg_chain40_rbm_alpha2", "N": N, "M": M, "P": P, "chains": C,
+                                 "sweeps": sweeps, "samples_per_step": ns, "solver": "cholesky_fp64",
+                                 "s_precision": "fp32", "diag_shift": wl.diag_shift},
+                      "sr_steps_per_s": 1.0 / el, "sr_flags": int(st[6]), "rel_residual": float(st[4]),
+                      "phases": phases}))
+    plan.close()
+
+
+def bench_grad16(crbm, args):
+    """16x16 lattice, alpha = 2 (P = 131,840): 8192 frozen samples (64 burn-in sweeps, one recorded),
+    forward (R and tanh theta) and the hand-written backward of the fidelity surrogate."""
+    from paper_2103_08804_amd.autograd import fidelity_loss
+    wl = synth.SQUARE16
+    N, M, P = wl.N, wl.M, wl.P
+    C = wl.chains
+    plan = crbm.Plan(crbm.SQUARE, wl.Lx, wl.Ly, M, C)
+    mk = lambda sd: (lambda r: (crbm.init_rbm(r, sd, wl.param_std), r)[1])(crbm.RBM.empty(N, M))
+    psm, psn, fit = mk(wl.param_seed + 1), mk(wl.param_seed + 2), mk(wl.param_seed + 3)
+    E0 = synth.E0_PER_SITE_SQUARE * N
+    W_scale = 1.5 * abs(E0)
+    cheb = crbm.make_cheb(2, E0 + 0.9875 * W_scale, W_scale, 1.0, 1.0, (math.pi, math.pi))
+    chains = torch.zeros(C, N, dtype=torch.int8, device="cuda")
+    crbm.init_chains(plan, chains, wl.chain_seed, True)
+    crbm.sample(plan, fit, chains, 64, crbm.EXCHANGE, 31, 0)
+    samples = chains.clone()
+    a, b, W = (t.clone().requires_grad_(True) for t in (fit.a, fit.b, fit.W))
+
+    def step():
+        a.grad = b.grad = W.grad = None
+        L = fidelity_loss(crbm.RBM(a, b, W), plan, samples, psn, psm, cheb)
+        L.backward()
+
+    el, phases = _timed(plan, step, args.steps, args.warmup)
+    print(json.dumps({"metric": "fidelity-surrogate gradients/s", "value": 1.0 / el, "unit": "gradients/s",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3,
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                      "data": "synthetic",
+                      "config": {"workload": "heisenberg_square16x16_rbm_alpha2_gradient", "N": N, "M": M, "P": P,
+                                 "samples": C, "burn_in_sweeps": 64},
+                      "samples_per_s": C / el, "phases": phases}))
     plan.close()
 
 
