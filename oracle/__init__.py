@@ -82,6 +82,8 @@ def lib():
         L.orc_fidelity_grad.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _i8p, _c128p, _c.c_long,
                                         _c.c_void_p]
         L.orc_fidelity_grad.restype = _c.c_double
+        L.orc_sr_energy_step.argtypes = L.orc_sr_step.argtypes
+        L.orc_sr_energy_step.restype = _c.c_int
         _i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
         L.orc_batched_moments.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _c128p, _c128p, _c128p, _f64p, _i64p,
                                           _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_uint64, _c.c_int, _c.c_int,
@@ -269,6 +271,23 @@ def sr_step(rbm, sig, R, dgamma, eps, weights=None, want_S=False):
     rc = lib().orc_sr_step(rbm.N, rbm.M, new.a, new.b, new.W, sig, _ptr(w), R, n, dgamma, eps, stats,
                            _ptr(S), _ptr(F), _ptr(dx))
     info = dict(rc=rc, gamma=stats[0], beta=complex(stats[1], stats[2]), Fnorm=stats[3], F=F, dalpha=dx, S=S)
+    return new, info
+
+
+def sr_energy_step(rbm, sig, eloc, lr, eps, weights=None, want_S=False):
+    """One ground-state natural-gradient step; returns (new_rbm, info) with info['E'], info['var']."""
+    sig = _i8(sig)
+    E = _c128(eloc)
+    n = sig.shape[0]
+    new = rbm.copy()
+    stats = np.zeros(4, np.float64)
+    S = np.zeros((rbm.P, rbm.P), np.complex128) if want_S else None
+    F = np.zeros(rbm.P, np.complex128)
+    dx = np.zeros(rbm.P, np.complex128)
+    w = None if weights is None else np.ascontiguousarray(weights, np.float64)
+    rc = lib().orc_sr_energy_step(rbm.N, rbm.M, new.a, new.b, new.W, sig, _ptr(w), E, n, lr, eps, stats,
+                                  _ptr(S), _ptr(F), _ptr(dx))
+    info = dict(rc=rc, E=complex(stats[0], stats[1]), var=stats[2], Fnorm=stats[3], F=F, dalpha=dx, S=S)
     return new, info
 
 

@@ -672,3 +672,75 @@ void orc_batched_moments(int N, int M, const cplx* ag, const cplx* bg, const cpl
     }
     if (n_ambiguous) *n_ambiguous = amb;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Ground-state natural-gradient step (the paper obtains psi_gs by           */
+/* minimising E = <psi|H psi>/<psi|psi> with Monte Carlo, Sec. I; the step   */
+/* uses the same metric S as Sec. III):                                      */
+/*   E = <E_loc>,  F_k = -lr [ <O_k^* E_loc> - <O_k>^* <E_loc> ]             */
+/*     (the bracket is dE/d conj(alpha_k) for a holomorphic psi),            */
+/*   (S + eps I) dalpha = F,  alpha <- alpha + dalpha.                        */
+/* stats: [Re E, Im E, <|E_loc|^2> - |E|^2, |F|_2].  Returns 0 or -1.        */
+/* ------------------------------------------------------------------------- */
+int orc_sr_energy_step(int N, int M, cplx* a, cplx* b, cplx* W, const int8_t* sig,
+                       const double* weights, const cplx* E, long n, double lr, double eps,
+                       double* stats, cplx* S_out, cplx* F_out, cplx* dalpha_out) {
+    long P = (long)N + M + (long)N * M;
+    cplx* O = (cplx*)malloc(sizeof(cplx) * (size_t)(n * P));
+    orc_logderiv(N, M, b, W, sig, n, O);
+    ksum kE = {0, 0};
+    double e2 = 0.0;
+    for (long s = 0; s < n; ++s) {
+        double w = weights ? weights[s] : 1.0 / (double)n;
+        kadd(&kE, w * E[s]);
+        e2 += w * creal(E[s] * conj(E[s]));
+    }
+    cplx Em = kE.s;
+    cplx* Om = (cplx*)calloc((size_t)P, sizeof(cplx));
+    cplx* F = (cplx*)calloc((size_t)P, sizeof(cplx));
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < P; ++k) {
+        ksum s1 = {0, 0}, s2 = {0, 0};
+        for (long s = 0; s < n; ++s) {
+            double w = weights ? weights[s] : 1.0 / (double)n;
+            cplx o = O[s * P + k];
+            kadd(&s1, w * o);
+            kadd(&s2, w * conj(o) * E[s]);
+        }
+        Om[k] = s1.s;
+        F[k] = -lr * (s2.s - conj(s1.s) * Em);
+    }
+    cplx* S = (cplx*)malloc(sizeof(cplx) * (size_t)(P * P));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long k = 0; k < P; ++k)
+        for (long kp = 0; kp < P; ++kp) {
+            ksum acc = {0, 0};
+            for (long s = 0; s < n; ++s) {
+                double w = weights ? weights[s] : 1.0 / (double)n;
+                kadd(&acc, w * conj(O[s * P + k]) * O[s * P + kp]);
+            }
+            S[k * P + kp] = acc.s - conj(Om[k]) * Om[kp];
+        }
+    if (S_out) memcpy(S_out, S, sizeof(cplx) * (size_t)(P * P));
+    if (F_out) memcpy(F_out, F, sizeof(cplx) * (size_t)P);
+    for (long k = 0; k < P; ++k) S[k * P + k] += eps;
+    cplx* x = (cplx*)malloc(sizeof(cplx) * (size_t)P);
+    memcpy(x, F, sizeof(cplx) * (size_t)P);
+    int rc = chol_solve(P, S, x);
+    if (rc == 0) {
+        for (long k = 0; k < P; ++k) {
+            if (k < N) a[k] += x[k];
+            else if (k < N + M) b[k - N] += x[k];
+            else W[k - N - M] += x[k];
+        }
+        if (dalpha_out) memcpy(dalpha_out, x, sizeof(cplx) * (size_t)P);
+    }
+    double fn = 0.0;
+    for (long k = 0; k < P; ++k) fn += creal(F[k] * conj(F[k]));
+    if (stats) {
+        stats[0] = creal(Em); stats[1] = cimag(Em);
+        stats[2] = e2 - creal(Em * conj(Em)); stats[3] = sqrt(fn);
+    }
+    free(O); free(Om); free(F); free(S); free(x);
+    return rc;
+}
