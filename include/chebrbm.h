@@ -10,6 +10,7 @@
  *                          Chebyshev target ratio R = phi/psi (Sec. III
  *                          recursion of targets), tanh(theta) and O_k     (Sec. III)
  *   crbm_sr_step           natural-gradient step (S + eps I) dalpha = F   (Sec. III)
+ *   crbm_sr_energy_step    the same step on the energy gradient (ground state, Sec. I)
  *   crbm_chebyshev_moment  mu_n = <t_0|t_n> by sampling psi_gs           (Sec. II, App. A)
  *   crbm_fidelity_grad     gradient of the frozen-sample fidelity surrogate
  *
@@ -200,6 +201,21 @@ int crbm_sr_step(crbm_plan plan, const crbm_rbm* fit, const int8_t* samples, con
                  const void* tanh_theta, const void* R, long n_samples, double dgamma, double diag_shift,
                  int solver, int s_precision, double cg_tol, int cg_maxit, double* stats_out,
                  hipStream_t stream);
+
+/* Natural-gradient energy minimisation of psi, by which the ground state psi_gs that seeds the
+ * expansion is obtained (Sec. I, with the metric S of Sec. III):
+ *   E = <E_loc>,  F_k = -lr [<O_k^* E_loc> - <O_k>^* <E_loc>]   (the bracket is dE/d conj(alpha_k)),
+ *   (S + diag_shift I) dalpha = F,   alpha += dalpha.
+ * eloc: complex64 [n_samples], (H psi)(s)/psi(s) as written by crbm_local_estimators in energy mode
+ * for the same psi and samples; tanh_theta likewise.  Samples, weights, solver, s_precision, cg_tol
+ * and cg_maxit as in crbm_sr_step; lr must be finite.
+ * stats_out: device double [8] = {<|E_loc|^2> - |E|^2, Re E, Im E, |F|_2, relative residual,
+ *            iterations, flags (CRBM_FLAG_*), |dalpha|_2}.
+ * The parameters of psi are updated in place (complex64). */
+int crbm_sr_energy_step(crbm_plan plan, const crbm_rbm* psi, const int8_t* samples, const double* weights,
+                        const void* tanh_theta, const void* eloc, long n_samples, double lr, double diag_shift,
+                        int solver, int s_precision, double cg_tol, int cg_maxit, double* stats_out,
+                        hipStream_t stream);
 
 /* Chebyshev moments by sampling s ~ |psi_gs|^2 (Sec. II, App. A):
  *   mu_0(q) = <|f_q|^2>,  mu_n(q) = < f_q(s)^* beta_n t~_n(s)/psi_gs(s) >  (n = 1..n_max)

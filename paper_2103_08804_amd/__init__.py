@@ -30,7 +30,7 @@ BUF_F, BUF_DALPHA, BUF_OMEAN, BUF_S = 0, 1, 2, 3
 # names declared in include/chebrbm.h
 EXPORTS = ("crbm_plan_create", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_last_error", "crbm_plan_profile",
            "crbm_plan_profile_read", "crbm_init_rbm", "crbm_init_chains", "crbm_sample", "crbm_local_estimators",
-           "crbm_sr_step", "crbm_chebyshev_moment", "crbm_fidelity_grad", "crbm_batched_moments",
+           "crbm_sr_step", "crbm_sr_energy_step", "crbm_chebyshev_moment", "crbm_fidelity_grad", "crbm_batched_moments",
            "crbm_batched_autotune")
 PROF_NAMES = ("sample", "theta", "local", "ot", "sbuild", "cg", "moment", "pack", "cholesky", "batched")
 
@@ -79,6 +79,7 @@ def lib():
         L.crbm_local_estimators.argtypes = [_vp, P(_Rbm), P(_Rbm), P(_Rbm), P(_Cheb), _vp, _l, _vp, _vp, _vp, _vp,
                                             _vp, _vp]
         L.crbm_sr_step.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _l, _d, _d, _i, _i, _d, _i, _vp, _vp]
+        L.crbm_sr_energy_step.argtypes = L.crbm_sr_step.argtypes
         L.crbm_chebyshev_moment.argtypes = [_vp, P(_Rbm), _vp, _vp, _i, P(_d), _i, _vp, _vp, _l, _vp, _vp]
         L.crbm_fidelity_grad.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _l, _vp, _vp, _vp]
         L.crbm_batched_moments.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _i, ctypes.c_int64, _i, _i, _i, _u64,
@@ -286,6 +287,18 @@ def sr_step(plan: Plan, fit: RBM, samples, tanh_theta, R, dgamma: float, diag_sh
         plan.handle, ctypes.byref(f), _ptr(samples, torch.int8, (n, N), "samples"),
         _ptr(weights, torch.float64, (n,), "weights"), _ptr(tanh_theta, torch.complex64, (n, M), "tanh_theta"),
         _ptr(R, torch.complex64, (n,), "R"), n, dgamma, diag_shift, solver, precision, cg_tol, cg_maxit,
+        _ptr(stats_out, torch.float64, (8,), "stats_out"), _stream(stream)))
+
+
+def sr_energy_step(plan: Plan, psi: RBM, samples, tanh_theta, eloc, lr: float, diag_shift: float, solver: int,
+                   precision: int, cg_tol: float, cg_maxit: int, stats_out, weights=None, stream=None):
+    n = samples.shape[0]
+    N, M = plan.N, plan.M
+    f = psi.struct()
+    _check(lib().crbm_sr_energy_step(
+        plan.handle, ctypes.byref(f), _ptr(samples, torch.int8, (n, N), "samples"),
+        _ptr(weights, torch.float64, (n,), "weights"), _ptr(tanh_theta, torch.complex64, (n, M), "tanh_theta"),
+        _ptr(eloc, torch.complex64, (n,), "eloc"), n, lr, diag_shift, solver, precision, cg_tol, cg_maxit,
         _ptr(stats_out, torch.float64, (8,), "stats_out"), _stream(stream)))
 
 

@@ -413,12 +413,15 @@ int crbm_local_estimators(crbm_plan p, const crbm_rbm* fit, const crbm_rbm* psi_
     return e == hipSuccess ? CRBM_OK : hip_fail(e, "local_estimators launch");
 }
 
-int crbm_sr_step(crbm_plan p, const crbm_rbm* fit, const int8_t* samples, const double* weights, const void* T,
-                 const void* R, long n, double dgamma, double eps, int solver, int prec, double cg_tol, int cg_maxit,
-                 double* stats_out, hipStream_t stream) {
+static int sr_step_common(crbm_plan p, const crbm_rbm* fit, const int8_t* samples, const double* weights,
+                          const void* T, const void* R, long n, double dgamma, double eps, int solver, int prec,
+                          double cg_tol, int cg_maxit, double* stats_out, int mode, hipStream_t stream) {
     if (check_plan(p)) return CRBM_EINVAL;
     if (int rc = check_rbm(p, fit, "fit")) return rc;
-    if (!samples || !T || !R) return fail(CRBM_EINVAL, "samples, tanh_theta and R must be non-NULL");
+    if (!samples || !T || !R)
+        return fail(CRBM_EINVAL, mode == 1 ? "samples, tanh_theta and eloc must be non-NULL"
+                                           : "samples, tanh_theta and R must be non-NULL");
+    if (mode == 1 && !(dgamma - dgamma == 0.0)) return fail(CRBM_EINVAL, "lr must be finite");
     if (n < 1) return fail(CRBM_EINVAL, "n_samples must be >= 1");
     if (n > p->max_samples) return fail(CRBM_ENOMEM, "n_samples = %ld exceeds the plan's max_samples = %ld", n,
                                         p->max_samples);
@@ -450,8 +453,23 @@ int crbm_sr_step(crbm_plan p, const crbm_rbm* fit, const int8_t* samples, const 
     A.cg_tol = cg_tol;
     A.cg_maxit = solver == CRBM_SOLVER_CHOLESKY ? 0 : cg_maxit;
     A.stats = stats_out;
+    A.mode = mode;
     hipError_t e = launch_sr_step(A, p->w, stream);
     return e == hipSuccess ? CRBM_OK : hip_fail(e, "sr_step launch");
+}
+
+int crbm_sr_step(crbm_plan p, const crbm_rbm* fit, const int8_t* samples, const double* weights, const void* T,
+                 const void* R, long n, double dgamma, double eps, int solver, int prec, double cg_tol, int cg_maxit,
+                 double* stats_out, hipStream_t stream) {
+    return sr_step_common(p, fit, samples, weights, T, R, n, dgamma, eps, solver, prec, cg_tol, cg_maxit, stats_out,
+                          0, stream);
+}
+
+int crbm_sr_energy_step(crbm_plan p, const crbm_rbm* psi, const int8_t* samples, const double* weights, const void* T,
+                        const void* eloc, long n, double lr, double eps, int solver, int prec, double cg_tol,
+                        int cg_maxit, double* stats_out, hipStream_t stream) {
+    return sr_step_common(p, psi, samples, weights, T, eloc, n, -lr, eps, solver, prec, cg_tol, cg_maxit, stats_out,
+                          1, stream);
 }
 
 int crbm_chebyshev_moment(crbm_plan p, const crbm_rbm* gs, const void* t_params, const double* betas, int n_max,

@@ -123,6 +123,7 @@ struct SrArgs {
     double cg_tol;
     int cg_maxit;
     double* stats;                     // device [8]
+    int mode;                          // 0: Chebyshev fit (R = target ratio); 1: energy (R = E_loc, dgamma = -lr)
 };
 hipError_t launch_sr_step(const SrArgs& args, const SrWork& w, hipStream_t stream);
 

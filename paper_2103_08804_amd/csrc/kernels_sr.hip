@@ -63,16 +63,27 @@ __global__ __launch_bounds__(256) void k_r_moments(const float2* __restrict__ R,
     }
 }
 
-__global__ void k_r_final(const double2* __restrict__ red, int n_blocks, double dgamma, double* __restrict__ sc) {
+// Fit mode (0): gamma = arccos sqrt(|<R>|^2/<|R|^2>) and the force scale dgamma gamma cot gamma.
+// Energy mode (1): R holds E_loc; the SC_GAMMA slot takes the variance <|E|^2> - |<E>|^2 and the
+// force scale is -lr (passed as dgamma).
+__global__ void k_r_final(const double2* __restrict__ red, int n_blocks, double dgamma, int mode,
+                          double* __restrict__ sc) {
     if (threadIdx.x != 0) return;
     double a = 0, b = 0, c = 0;
     for (int k = 0; k < n_blocks; ++k) { a += red[2 * k].x; b += red[2 * k].y; c += red[2 * k + 1].x; }
+    sc[SC_RM_RE] = a; sc[SC_RM_IM] = b; sc[SC_R2] = c;
+    for (int k = SC_RR; k < SC_COUNT; ++k) sc[k] = 0.0;
+    if (mode == 1) {
+        sc[SC_GAMMA] = c - (a * a + b * b);
+        sc[SC_GCOT] = 1.0;
+        sc[SC_COEF] = dgamma;
+        if (!isfinite(a) || !isfinite(b) || !isfinite(c)) sc[SC_FLAGS] = CRBM_FLAG_NONFINITE;
+        return;
+    }
     const double ratio = (a * a + b * b) / c;
     const double gamma = acos(fmin(1.0, sqrt(ratio)));
     const double gcot = (gamma < 1e-4) ? 1.0 - gamma * gamma / 3.0 : gamma / tan(gamma);
-    sc[SC_RM_RE] = a; sc[SC_RM_IM] = b; sc[SC_R2] = c;
     sc[SC_GAMMA] = gamma; sc[SC_GCOT] = gcot; sc[SC_COEF] = dgamma * gcot;
-    for (int k = SC_RR; k < SC_COUNT; ++k) sc[k] = 0.0;
     if (!(c > 0.0) || !isfinite(a) || !isfinite(b) || !isfinite(c)) sc[SC_FLAGS] = CRBM_FLAG_NONFINITE;
 }
 
@@ -223,16 +234,23 @@ static hipError_t run_ot(int N, int M, const int8_t* sig, const float2* T, long 
     return hipGetLastError();
 }
 
-// F_k = coef [ORm_k / <R> - conj(Om_k)];  Om holds conj(<O>) on entry and <O> on exit.
-__global__ void k_make_f(long P, double2* __restrict__ Om, const double2* __restrict__ ORm, const double* __restrict__ sc,
-                         double2* __restrict__ F) {
+// Fit mode (0):    F_k = coef [ORm_k / <R> - conj(Om_k)];
+// energy mode (1): F_k = coef [ORm_k - conj(Om_k) <E>]   (ORm = <O^* E_loc>, coef = -lr).
+// Om holds conj(<O>) on entry and <O> on exit.
+__global__ void k_make_f(long P, int mode, double2* __restrict__ Om, const double2* __restrict__ ORm,
+                         const double* __restrict__ sc, double2* __restrict__ F) {
     const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= P) return;
     const double2 rm = make_double2(sc[SC_RM_RE], sc[SC_RM_IM]);
     const double coef = sc[SC_COEF];
     const double2 omc = Om[k];
-    const double2 q = zdiv(ORm[k], rm);
-    F[k] = make_double2(coef * (q.x - omc.x), coef * (q.y - omc.y));
+    if (mode == 1) {
+        const double2 d = zsub(ORm[k], zmul(omc, rm));
+        F[k] = make_double2(coef * d.x, coef * d.y);
+    } else {
+        const double2 q = zdiv(ORm[k], rm);
+        F[k] = make_double2(coef * (q.x - omc.x), coef * (q.y - omc.y));
+    }
     Om[k] = make_double2(omc.x, -omc.y);
 }
 
@@ -613,12 +631,12 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
     // scalars gamma, beta, gamma cot gamma
     const int nb_r = 256;
     hipLaunchKernelGGL(k_r_moments, dim3(nb_r), dim3(256), 0, stream, A.R, A.weights, A.n, W.red);
-    hipLaunchKernelGGL(k_r_final, dim3(1), dim3(64), 0, stream, W.red, nb_r, A.dgamma, W.scal);
+    hipLaunchKernelGGL(k_r_final, dim3(1), dim3(64), 0, stream, W.red, nb_r, A.dgamma, A.mode, W.scal);
     // conj(<O>) and <O^* R>
     e = run_ot(A.N, A.M, A.samples, A.T, A.n, 0, 1, 2, A.weights, A.R, nullptr, W.red, 0, W.Om, W.ORm, stream, nullptr,
                W.prof);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_make_f, dim3(nblk(P)), dim3(256), 0, stream, P, W.Om, W.ORm, W.scal, W.F);
+    hipLaunchKernelGGL(k_make_f, dim3(nblk(P)), dim3(256), 0, stream, P, A.mode, W.Om, W.ORm, W.scal, W.F);
     hipLaunchKernelGGL(k_zdot, dim3(64), dim3(256), 0, stream, P, W.F, W.F, W.red, W.scal, 0);
     hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(64), 0, stream, W.red, 64, W.scal, (int)SC_FF, 0);
 
