@@ -7,7 +7,8 @@ Python binding.  It shares no code with the HIP path.
 The numerics live in ``oracle.c`` (plain C, double precision, every quantity
 from its definition).  This module only marshals numpy arrays into it.
 ``exact`` holds the exact-vector references (Heisenberg matrix over all 2^N
-configurations, exact Chebyshev recursion).
+configurations, exact Chebyshev recursion); ``spectral`` the FP64 post-processing
+of moments (Jackson reconstruction, moment correction, continued-fraction spectrum).
 """
 from __future__ import annotations
 
@@ -79,6 +80,10 @@ def lib():
         L.orc_moments.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _c128p, _c128p, _c128p, _c.c_int,
                                   _f64p, _c.c_int, _c.c_int, _c.c_int, _i8p, _c.c_void_p, _c.c_long,
                                   _c128p]
+        L.orc_moment_matrices.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _c128p, _c128p, _c128p, _c.c_int,
+                                          _f64p, _c.c_int, _c.c_int, _c.c_int, _c.c_double, _i8p, _c.c_void_p,
+                                          _c.c_long, _c128p, _c128p]
+        L.orc_moment_matrices.restype = None
         L.orc_fidelity_grad.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _i8p, _c128p, _c.c_long,
                                         _c.c_void_p]
         L.orc_fidelity_grad.restype = _c.c_double
@@ -303,6 +308,22 @@ def moments(psi_gs, ts, betas, qs, lat, sig, weights=None):
                       _c128(np.asarray(betas, np.complex128).reshape(-1) if n_max else np.zeros(1)),
                       n_max, qs, qs.shape[0], lat.kind, lat.Lx, sig, _ptr(w), sig.shape[0], mu)
     return mu
+
+
+def moment_matrices(psi_gs, ts, betas, q, lat, sig, weights=None):
+    """(G, H), K x K with K = len(ts) + 1: G_nm = <conj(B_n) B_m>, H_nm = <conj(B_n) (H t_m)/psi_gs>."""
+    sig = _i8(sig)
+    n_max = len(ts)
+    K = n_max + 1
+    tp = np.concatenate([t.vector() for t in ts]) if n_max else np.zeros(1, np.complex128)
+    G = np.zeros((K, K), np.complex128)
+    H = np.zeros((K, K), np.complex128)
+    w = None if weights is None else np.ascontiguousarray(weights, np.float64)
+    lib().orc_moment_matrices(psi_gs.N, psi_gs.M, psi_gs.a, psi_gs.b, psi_gs.W, _c128(tp),
+                              _c128(np.asarray(betas, np.complex128).reshape(-1) if n_max else np.zeros(1)),
+                              n_max, np.ascontiguousarray(np.asarray(q, np.float64).reshape(2)), lat.kind, lat.Lx,
+                              lat.Ly, lat.J, sig, _ptr(w), sig.shape[0], G, H)
+    return G, H
 
 
 def fidelity_grad(rbm, sig, R):

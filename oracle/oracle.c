@@ -744,3 +744,58 @@ int orc_sr_energy_step(int N, int M, cplx* a, cplx* b, cplx* W, const int8_t* si
     free(O); free(Om); free(F); free(S); free(x);
     return rc;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Moment-correction matrices (Sec. IV; App. A, G and H) by sampling          */
+/* s ~ |psi_gs|^2.  Basis vectors t_0 = S^z_q psi_gs and t_n = beta_n t~_n;   */
+/* per sample B_n(s) = t_n(s)/psi_gs(s) and HB_n(s) = (H t_n)(s)/psi_gs(s):   */
+/*   B_0 = f_q(s),  HB_0 from the Heisenberg action on f_q psi_gs;            */
+/*   B_n = beta_n t~_n(s)/psi_gs(s),  HB_n = B_n (H t~_n)(s)/t~_n(s).         */
+/*   G_nm = <conj(B_n) B_m>,  H_nm = <conj(B_n) HB_m>   (K = n_max + 1).      */
+/* H is the physical Hamiltonian (units of J), not the rescaled one.          */
+/* ------------------------------------------------------------------------- */
+void orc_moment_matrices(int N, int M, const cplx* ag, const cplx* bg, const cplx* Wg,
+                         const cplx* t_params, const cplx* betas, int n_max, const double* q,
+                         int kind, int Lx, int Ly, double J, const int8_t* sig, const double* weights,
+                         long n, cplx* G_out, cplx* H_out) {
+    const long P = (long)N + M + (long)N * M;
+    const int K = n_max + 1;
+    int* bonds = (int*)malloc(sizeof(int) * 4 * (size_t)N);
+    int nb = orc_lattice_bonds(kind, Lx, Ly, bonds);
+    cplx* B = (cplx*)malloc(sizeof(cplx) * (size_t)(n * K));
+    cplx* HB = (cplx*)malloc(sizeof(cplx) * (size_t)(n * K));
+#pragma omp parallel
+    {
+        int8_t* tmp = (int8_t*)malloc((size_t)N);
+        cplx* th = (cplx*)malloc(sizeof(cplx) * (size_t)M);
+#pragma omp for schedule(static)
+        for (long s = 0; s < n; ++s) {
+            const int8_t* x = sig + s * N;
+            const cplx lg = logpsi_one(N, M, ag, bg, Wg, x, th);
+            B[s * K] = fq_of(kind, Lx, N, q, x);
+            HB[s * K] = hg_over_psi(N, M, ag, bg, Wg, nb, bonds, J, x, 1, kind, Lx, q, tmp, th);
+            for (int t = 1; t <= n_max; ++t) {
+                const cplx* tp = t_params + (long)(t - 1) * P;
+                const cplx lt = logpsi_one(N, M, tp, tp + N, tp + N + M, x, th);
+                const cplx r = betas[t - 1] * cexp(lt - lg);
+                const cplx el = hg_over_psi(N, M, tp, tp + N, tp + N + M, nb, bonds, J, x, 0, kind, Lx, q, tmp, th);
+                B[s * K + t] = r;
+                HB[s * K + t] = r * el;
+            }
+        }
+        free(tmp); free(th);
+    }
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < K * K; ++e) {
+        const int k = e / K, l = e % K;
+        ksum g = {0, 0}, h = {0, 0};
+        for (long s = 0; s < n; ++s) {
+            const double w = weights ? weights[s] : 1.0 / (double)n;
+            kadd(&g, w * conj(B[s * K + k]) * B[s * K + l]);
+            kadd(&h, w * conj(B[s * K + k]) * HB[s * K + l]);
+        }
+        G_out[e] = g.s;
+        H_out[e] = h.s;
+    }
+    free(bonds); free(B); free(HB);
+}
