@@ -13,6 +13,11 @@
  *   crbm_sr_energy_step    the same step on the energy gradient (ground state, Sec. I)
  *   crbm_chebyshev_moment  mu_n = <t_0|t_n> by sampling psi_gs           (Sec. II, App. A)
  *   crbm_fidelity_grad     gradient of the frozen-sample fidelity surrogate
+ *   crbm_moment_matrices   overlap and Hamiltonian matrices of the Chebyshev basis (Sec. IV, App. A)
+ *   crbm_corrected_moments moments of the recursion repeated inside that basis   (Sec. IV)
+ *   crbm_lanczos           tridiagonal form of the projected Hamiltonian        (Sec. V)
+ *   crbm_spectrum_kpm      Jackson-damped Chebyshev reconstruction A(omega)      (Sec. II, Eq. Aw)
+ *   crbm_spectrum_cf       continued-fraction spectrum from the tridiagonal form (Sec. V)
  *
  * Conventions
  *  - Spins are int8 +-1, row-major [rows][N].  Site r = x + Lx*y.
@@ -134,6 +139,7 @@ enum {
     CRBM_PROF_PACK,         /* operand packing for the S contraction (two kernels) */
     CRBM_PROF_CHOLESKY,     /* whole Cholesky factorisation and solve (many kernels) */
     CRBM_PROF_BATCHED,      /* batched moments: counter reset, persistent kernel, per-instance reduction */
+    CRBM_PROF_GRAM,         /* moment-correction matrices: G and H products and their reduction (two kernels) */
     CRBM_PROF_COUNT
 };
 int crbm_plan_profile(crbm_plan plan, int enable);
@@ -234,6 +240,52 @@ int crbm_chebyshev_moment(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_
  * tanh_theta and R as written by crbm_local_estimators for the same fit and samples. */
 int crbm_fidelity_grad(crbm_plan plan, const crbm_rbm* fit, const int8_t* samples, const void* tanh_theta,
                        const void* R, long n_samples, void* grad_out, double* loss_out, hipStream_t stream);
+
+/* Moment-correction matrices of the basis t_0 = S^z_q psi_gs, t_n = beta_n t~_n (n = 1..n_max), by
+ * sampling s ~ |psi_gs|^2 (Sec. IV; App. A, G and H):
+ *   B_0(s) = f_q(s),  B_n(s) = beta_n t~_n(s)/psi_gs(s),  HB_n(s) = (H t_n)(s)/psi_gs(s),
+ *   G_nm = <conj(B_n) B_m> = <t_n|t_m>/<psi_gs|psi_gs>,  H_nm = <conj(B_n) HB_m> = <t_n|H|t_m>/<psi_gs|psi_gs>.
+ * H is the lattice Hamiltonian of the plan (units of J, not rescaled).  K = n_max + 1 <= 256.
+ * t_params, betas, weights, samples as in crbm_chebyshev_moment; q: HOST double [2];
+ * G_out, H_out: complex128 [K][K] (row n, column m).  Row 0 of G is the moment estimate mu_m of
+ * crbm_chebyshev_moment on the same samples.  The first call with a given K * max_samples allocates
+ * 16 K max_samples bytes of plan workspace (kept until the plan is destroyed); later calls do not. */
+int crbm_moment_matrices(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_params, const double* betas,
+                         int n_max, const double* q, const int8_t* samples, const double* weights, long n_samples,
+                         void* G_out, void* H_out, hipStream_t stream);
+
+/* Corrected Chebyshev moments (Sec. IV): the recursion repeated for the Hamiltonian projected onto the
+ * span of the basis,  H' = (H - E_c G)/W_scale  (the rescaled Hamiltonian of Sec. II in the basis),
+ *   c_0 = e_0,  G c_1 = H' c_0,  G c_{n+1} = 2 H' c_n - G c_{n-1},  mu_n = Re sum_l G_0l c_ln,
+ * for n = 0 .. n_out-1 (n_out may exceed K).  G and H (complex128 [K][K], device) are replaced by their
+ * Hermitian parts; G is factorised by Cholesky in double.  mu_out: double [n_out] (device).
+ * info_out: double [3] (device) = {flags (CRBM_FLAG_CHOLESKY_FAIL if G is not positive definite; then
+ * mu_out is zero), max_n |mu_n|/mu_0 (exceeds 1 when the estimated matrices are inconsistent),
+ * smallest/largest Cholesky pivot}. */
+int crbm_corrected_moments(crbm_plan plan, const void* G, const void* H, int K, double E_c, double W_scale,
+                           int n_out, double* mu_out, double* info_out, hipStream_t stream);
+
+/* Lanczos tridiagonalisation of the Hamiltonian projected onto the basis (Sec. V), started from t_0,
+ * with full re-orthogonalisation, in double.  Hermitian parts of G and H are used.  Runs
+ * min(n_steps, K) steps or stops at an invariant subspace.
+ * a_out: double [n_steps] diagonal; b2_out: double [n_steps], b2_out[0] = G_00 = <t_0|t_0>/<psi_gs|psi_gs>
+ * and b2_out[j] = b_j^2 (j >= 1) the squared off-diagonal; info_out: double [2] = {flags, steps done m}.
+ * The Green's function of t_0 is b2_0 / (z - a_0 - b2_1 / (z - a_1 - ... b2_{m-1} / (z - a_{m-1}))). */
+int crbm_lanczos(crbm_plan plan, const void* G, const void* H, int K, int n_steps, double* a_out, double* b2_out,
+                 double* info_out, hipStream_t stream);
+
+/* Chebyshev reconstruction (Sec. II, Eq. Aw) on a frequency grid (all pointers device):
+ *   A(omega) = [g_0 mu_0 + 2 sum_{n=1}^{n_mom-1} g_n mu_n T_n(x)] / (pi W_scale sqrt(1 - x^2)),
+ *   x = (E0 + omega - E_c)/W_scale,  A = 0 for |x| >= 1,
+ * g_n the Jackson factors of Sec. VI for N = n_mom moments if jackson != 0, else 1.
+ * mu: double [n_mom] (real moments); omega: double [n_omega] excitation energies; A_out: double [n_omega]. */
+int crbm_spectrum_kpm(const double* mu, int n_mom, int jackson, double E0, double E_c, double W_scale,
+                      const double* omega, int n_omega, double* A_out, hipStream_t stream);
+
+/* Continued-fraction spectrum (Sec. V) from crbm_lanczos output with m levels (all pointers device):
+ *   A(omega) = -(1/pi) Im G(omega + E0 + i eta),  eta > 0 the broadening. */
+int crbm_spectrum_cf(const double* a, const double* b2, int m, double E0, double eta, const double* omega,
+                     int n_omega, double* A_out, hipStream_t stream);
 
 /* Batched Chebyshev moments of many (q, n) instances in one persistent launch (Sec. II moments,
  * App. A momentum form).  Instance i has a momentum q_i, a stored state t~_i and beta_i, and owns

@@ -31,8 +31,9 @@ BUF_F, BUF_DALPHA, BUF_OMEAN, BUF_S = 0, 1, 2, 3
 EXPORTS = ("crbm_plan_create", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_last_error", "crbm_plan_profile",
            "crbm_plan_profile_read", "crbm_init_rbm", "crbm_init_chains", "crbm_sample", "crbm_local_estimators",
            "crbm_sr_step", "crbm_sr_energy_step", "crbm_chebyshev_moment", "crbm_fidelity_grad", "crbm_batched_moments",
-           "crbm_batched_autotune")
-PROF_NAMES = ("sample", "theta", "local", "ot", "sbuild", "cg", "moment", "pack", "cholesky", "batched")
+           "crbm_batched_autotune", "crbm_moment_matrices", "crbm_corrected_moments", "crbm_lanczos",
+           "crbm_spectrum_kpm", "crbm_spectrum_cf")
+PROF_NAMES = ("sample", "theta", "local", "ot", "sbuild", "cg", "moment", "pack", "cholesky", "batched", "gram")
 
 
 class CrbmError(RuntimeError):
@@ -80,6 +81,11 @@ def lib():
                                             _vp, _vp]
         L.crbm_sr_step.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _l, _d, _d, _i, _i, _d, _i, _vp, _vp]
         L.crbm_sr_energy_step.argtypes = L.crbm_sr_step.argtypes
+        L.crbm_moment_matrices.argtypes = [_vp, P(_Rbm), _vp, _vp, _i, P(_d), _vp, _vp, _l, _vp, _vp, _vp]
+        L.crbm_corrected_moments.argtypes = [_vp, _vp, _vp, _i, _d, _d, _i, _vp, _vp, _vp]
+        L.crbm_lanczos.argtypes = [_vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp]
+        L.crbm_spectrum_kpm.argtypes = [_vp, _i, _i, _d, _d, _d, _vp, _i, _vp, _vp]
+        L.crbm_spectrum_cf.argtypes = [_vp, _vp, _i, _d, _d, _vp, _i, _vp, _vp]
         L.crbm_chebyshev_moment.argtypes = [_vp, P(_Rbm), _vp, _vp, _i, P(_d), _i, _vp, _vp, _l, _vp, _vp]
         L.crbm_fidelity_grad.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _l, _vp, _vp, _vp]
         L.crbm_batched_moments.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _i, ctypes.c_int64, _i, _i, _i, _u64,
@@ -327,6 +333,60 @@ def fidelity_grad(plan: Plan, fit: RBM, samples, tanh_theta, R, grad_out, loss_o
         _ptr(tanh_theta, torch.complex64, (n, M), "tanh_theta"), _ptr(R, torch.complex64, (n,), "R"), n,
         _ptr(grad_out, torch.complex128, (P,), "grad_out") if grad_out is not None else None,
         _ptr(loss_out, torch.float64, (1,), "loss_out"),
+        _stream(stream)))
+
+
+def moment_matrices(plan: Plan, psi_gs: RBM, t_params, betas, q, samples, G_out, H_out, weights=None, stream=None):
+    """G_nm = <conj(B_n) B_m>, H_nm = <conj(B_n) (H t_m)/psi_gs> over samples of |psi_gs|^2, K = n_max + 1."""
+    n = samples.shape[0]
+    N, P = plan.N, plan.P
+    n_max = 0 if t_params is None else t_params.shape[0]
+    K = n_max + 1
+    qarr = (ctypes.c_double * 2)(float(q[0]), float(q[1]))
+    g = psi_gs.struct()
+    _check(lib().crbm_moment_matrices(
+        plan.handle, ctypes.byref(g),
+        _ptr(t_params, torch.complex64, (n_max, P), "t_params") if n_max else None,
+        _ptr(betas, torch.complex128, (n_max,), "betas") if n_max else None, n_max, qarr,
+        _ptr(samples, torch.int8, (n, N), "samples"), _ptr(weights, torch.float64, (n,), "weights"), n,
+        _ptr(G_out, torch.complex128, (K, K), "G_out"), _ptr(H_out, torch.complex128, (K, K), "H_out"),
+        _stream(stream)))
+
+
+def corrected_moments(plan: Plan, G, H, E_c: float, W_scale: float, mu_out, info_out, stream=None):
+    K = G.shape[0]
+    n_out = mu_out.shape[0]
+    _check(lib().crbm_corrected_moments(
+        plan.handle, _ptr(G, torch.complex128, (K, K), "G"), _ptr(H, torch.complex128, (K, K), "H"), K, E_c, W_scale,
+        n_out, _ptr(mu_out, torch.float64, (n_out,), "mu_out"), _ptr(info_out, torch.float64, (3,), "info_out"),
+        _stream(stream)))
+
+
+def lanczos(plan: Plan, G, H, a_out, b2_out, info_out, stream=None):
+    K = G.shape[0]
+    m = a_out.shape[0]
+    _check(lib().crbm_lanczos(
+        plan.handle, _ptr(G, torch.complex128, (K, K), "G"), _ptr(H, torch.complex128, (K, K), "H"), K, m,
+        _ptr(a_out, torch.float64, (m,), "a_out"), _ptr(b2_out, torch.float64, (m,), "b2_out"),
+        _ptr(info_out, torch.float64, (2,), "info_out"), _stream(stream)))
+
+
+def spectrum_kpm(mu, E0: float, E_c: float, W_scale: float, omega, A_out, jackson: bool = True, stream=None):
+    n_mom = mu.shape[0]
+    n_w = omega.shape[0]
+    _check(lib().crbm_spectrum_kpm(
+        _ptr(mu, torch.float64, (n_mom,), "mu"), n_mom, int(bool(jackson)), E0, E_c, W_scale,
+        _ptr(omega, torch.float64, (n_w,), "omega"), n_w, _ptr(A_out, torch.float64, (n_w,), "A_out"),
+        _stream(stream)))
+
+
+def spectrum_cf(a, b2, m: int, E0: float, eta: float, omega, A_out, stream=None):
+    n_w = omega.shape[0]
+    if not 1 <= m <= min(a.shape[0], b2.shape[0]):
+        raise ValueError(f"m = {m} levels but a has {a.shape[0]} and b2 {b2.shape[0]} entries")
+    _check(lib().crbm_spectrum_cf(
+        _ptr(a, torch.float64, (a.shape[0],), "a"), _ptr(b2, torch.float64, (b2.shape[0],), "b2"), m, E0, eta,
+        _ptr(omega, torch.float64, (n_w,), "omega"), n_w, _ptr(A_out, torch.float64, (n_w,), "A_out"),
         _stream(stream)))
 
 

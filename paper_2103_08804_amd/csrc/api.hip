@@ -27,6 +27,19 @@ hipError_t launch_moment_accum(const double2* f, const double2* B, int b_is_f, c
 hipError_t launch_moment_final(const double2* partial, int n_blocks, int total, double2* mu, hipStream_t stream);
 size_t sbuild_pack_bytes(int N, int M, long max_samples);
 std::vector<int2> sbuild_order(int N, int M, int n_xcd, int g);
+hipError_t launch_basis_pack(long n, const double2* B, const float2* loc, int mul, float2* Bcol, float2* HBcol,
+                             hipStream_t stream);
+long gram_partial_len(int K);
+hipError_t launch_gram2(int K, long n, const float2* Bm, const float2* HBm, const double* w, double2* partial,
+                        double2* G, double2* H, hipStream_t stream);
+hipError_t launch_correct(int K, const double2* G, const double2* H, double E_c, double W_scale, int n_out,
+                          double2* work, double* mu, double* info, hipStream_t stream);
+hipError_t launch_lanczos(int K, const double2* G, const double2* H, int n_steps, double2* work, double* a, double* b2,
+                          double* info, hipStream_t stream);
+hipError_t launch_spec_kpm(const double* mu, int n_mom, int jackson, double E0, double E_c, double W_scale,
+                           const double* omega, int n_w, double* A, hipStream_t stream);
+hipError_t launch_spec_cf(const double* a, const double* b2, int m, double E0, double eta, const double* omega,
+                          int n_w, double* A, hipStream_t stream);
 
 }  // namespace crbm
 
@@ -39,6 +52,7 @@ constexpr long kCholMaxP = 4000;
 constexpr int kQChunk = 8;
 constexpr int kMomBlocks = 256;
 constexpr int kMaxMomentEntries = 4096;   // n_q * (n_max + 1)
+constexpr int kMaxBasis = 256;             // K = n_max + 1 of the moment-correction matrices
 constexpr int kXcds = 8;                   // accelerator complex dies of the MI355X (round-robin dispatch)
 #ifndef CRBM_SUPERTILE
 #define CRBM_SUPERTILE 8
@@ -79,6 +93,10 @@ struct crbm_plan_s {
     int b_waves = 4, b_blocks = 1024;
     Profiler prof;
     std::vector<void*> allocs;
+    // grow-only workspace of the moment-correction path (allocated on first use)
+    enum { GB_BASIS = 0, GB_HBASIS, GB_ELOC, GB_GRAM, GB_SMALL, GB_COUNT };
+    void* grow_ptr[GB_COUNT] = {};
+    size_t grow_cap[GB_COUNT] = {};
 
     Geometry geometry() const {
         Geometry g;
@@ -99,8 +117,25 @@ struct crbm_plan_s {
         *p = static_cast<T*>(q);
         return CRBM_OK;
     }
+    // make grow_ptr[id] hold at least `bytes`; an existing smaller buffer is released first
+    // (hipFree waits for the device, so no launch still reads it)
+    int grow(int id, size_t bytes) {
+        if (grow_cap[id] >= bytes) return CRBM_OK;
+        if (grow_ptr[id]) { (void)hipFree(grow_ptr[id]); grow_ptr[id] = nullptr; grow_cap[id] = 0; }
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CRBM_ENOMEM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+        }
+        grow_ptr[id] = q;
+        grow_cap[id] = bytes;
+        return CRBM_OK;
+    }
     ~crbm_plan_s() {
         for (void* p : allocs) (void)hipFree(p);
+        for (void* p : grow_ptr)
+            if (p) (void)hipFree(p);
     }
 };
 
@@ -541,6 +576,152 @@ int crbm_fidelity_grad(crbm_plan p, const crbm_rbm* fit, const int8_t* samples, 
     A.loss = loss_out;
     hipError_t e = launch_fidelity_grad(A, p->w, stream);
     return e == hipSuccess ? CRBM_OK : hip_fail(e, "fidelity_grad launch");
+}
+
+int crbm_moment_matrices(crbm_plan p, const crbm_rbm* gs, const void* t_params, const double* betas, int n_max,
+                         const double* q, const int8_t* samples, const double* weights, long n, void* G_out,
+                         void* H_out, hipStream_t stream) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (int rc = check_rbm(p, gs, "psi_gs")) return rc;
+    if (n_max < 0) return fail(CRBM_EINVAL, "n_max must be >= 0");
+    if (n_max + 1 > kMaxBasis) return fail(CRBM_EUNSUPPORTED, "K = n_max + 1 = %d exceeds %d", n_max + 1, kMaxBasis);
+    if (n_max > 0 && (!t_params || !betas)) return fail(CRBM_EINVAL, "t_params and betas must be non-NULL");
+    if (!q) return fail(CRBM_EINVAL, "q is NULL");
+    if (!samples || !G_out || !H_out) return fail(CRBM_EINVAL, "samples, G_out and H_out must be non-NULL");
+    if (n < 1) return fail(CRBM_EINVAL, "n_samples must be >= 1");
+    if (n > p->max_samples) return fail(CRBM_ENOMEM, "n_samples = %ld exceeds the plan's max_samples = %ld", n,
+                                        p->max_samples);
+    if (int rc = set_device(p)) return rc;
+    const int K = n_max + 1;
+    const size_t col_bytes = (size_t)K * (size_t)p->max_samples * sizeof(float2);
+    int rc = p->grow(crbm_plan_s::GB_BASIS, col_bytes);
+    rc = rc ? rc : p->grow(crbm_plan_s::GB_HBASIS, col_bytes);
+    rc = rc ? rc : p->grow(crbm_plan_s::GB_ELOC, (size_t)p->max_samples * sizeof(float2));
+    rc = rc ? rc : p->grow(crbm_plan_s::GB_GRAM, (size_t)gram_partial_len(kMaxBasis) * sizeof(double2));
+    if (rc) return rc;
+    float2* Bm = static_cast<float2*>(p->grow_ptr[crbm_plan_s::GB_BASIS]);
+    float2* HBm = static_cast<float2*>(p->grow_ptr[crbm_plan_s::GB_HBASIS]);
+    float2* loc = static_cast<float2*>(p->grow_ptr[crbm_plan_s::GB_ELOC]);
+    double2* part = static_cast<double2*>(p->grow_ptr[crbm_plan_s::GB_GRAM]);
+    const Geometry g = p->geometry();
+    const RbmView vg = view(gs);
+    const long P = p->P;
+    const float2* tp = static_cast<const float2*>(t_params);
+
+    // order 0: B_0 = f_q, HB_0 = (H S^z_q psi_gs)/psi_gs
+    p->prof.begin(PROF_THETA, stream);
+    hipError_t e = launch_theta(samples, n, p->N, p->M, vg.b, vg.W, p->theta[0], stream);
+    p->prof.end(stream);
+    if (e == hipSuccess) e = launch_fq_chunk(g, samples, n, q, 1, p->momF, stream);
+    LocalArgs A{};
+    A.g = g;
+    A.samples = samples;
+    A.n_samples = n;
+    A.eloc_out = loc;
+    A.fit = vg;
+    A.psn = vg;
+    A.cheb_mode = 1;
+    A.order = 0;
+    A.W_scale = 1.0;
+    A.q0 = q[0];
+    A.q1 = p->lat.kind == CRBM_LATTICE_CHAIN ? 0.0 : q[1];
+    if (e == hipSuccess) {
+        p->prof.begin(PROF_LOCAL, stream);
+        e = launch_local_core(A, p->theta[0], p->theta[0], nullptr, stream);
+        p->prof.end(stream);
+    }
+    if (e == hipSuccess) e = launch_basis_pack(n, p->momF, loc, 0, Bm, HBm, stream);
+    // orders 1..n_max: B_t = beta_t t~_t/psi_gs, HB_t = B_t E_loc[t~_t]
+    for (int t = 1; t <= n_max && e == hipSuccess; ++t) {
+        const float2* at = tp + (long)(t - 1) * P;
+        RbmView vt;
+        vt.a = at;
+        vt.b = at + p->N;
+        vt.W = at + p->N + p->M;
+        p->prof.begin(PROF_THETA, stream);
+        e = launch_theta(samples, n, p->N, p->M, vt.b, vt.W, p->theta[1], stream);
+        p->prof.end(stream);
+        LocalArgs At{};
+        At.g = g;
+        At.samples = samples;
+        At.n_samples = n;
+        At.eloc_out = loc;
+        At.fit = vt;
+        if (e == hipSuccess) {
+            p->prof.begin(PROF_LOCAL, stream);
+            e = launch_local_core(At, p->theta[1], nullptr, nullptr, stream);
+            p->prof.end(stream);
+        }
+        if (e == hipSuccess) {
+            p->prof.begin(PROF_MOMENT, stream);
+            e = launch_moment_ratio(p->N, p->M, samples, n, at, vg.a, p->theta[1], p->theta[0],
+                                    reinterpret_cast<const double2*>(betas) + (t - 1), p->momB, stream);
+            p->prof.end(stream);
+        }
+        if (e == hipSuccess) e = launch_basis_pack(n, p->momB, loc, 1, Bm + (long)t * n, HBm + (long)t * n, stream);
+    }
+    if (e == hipSuccess) {
+        p->prof.begin(PROF_GRAM, stream);
+        e = launch_gram2(K, n, Bm, HBm, weights, part, static_cast<double2*>(G_out), static_cast<double2*>(H_out),
+                         stream);
+        p->prof.end(stream);
+    }
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "moment_matrices launch");
+}
+
+int crbm_corrected_moments(crbm_plan p, const void* G, const void* H, int K, double E_c, double W_scale, int n_out,
+                           double* mu_out, double* info_out, hipStream_t stream) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (!G || !H || !mu_out || !info_out) return fail(CRBM_EINVAL, "G, H, mu_out and info_out must be non-NULL");
+    if (K < 1 || K > kMaxBasis) return fail(CRBM_EINVAL, "K must be in [1, %d] (got %d)", kMaxBasis, K);
+    if (n_out < 1) return fail(CRBM_EINVAL, "n_out must be >= 1");
+    if (!(W_scale != 0.0) || !(W_scale - W_scale == 0.0) || !(E_c - E_c == 0.0))
+        return fail(CRBM_EINVAL, "E_c must be finite and W_scale finite and non-zero");
+    if (int rc = set_device(p)) return rc;
+    if (int rc = p->grow(crbm_plan_s::GB_SMALL, (size_t)(4L * kMaxBasis * kMaxBasis + kMaxBasis) * sizeof(double2)))
+        return rc;
+    hipError_t e = launch_correct(K, static_cast<const double2*>(G), static_cast<const double2*>(H), E_c, W_scale,
+                                  n_out, static_cast<double2*>(p->grow_ptr[crbm_plan_s::GB_SMALL]), mu_out, info_out,
+                                  stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "corrected_moments launch");
+}
+
+int crbm_lanczos(crbm_plan p, const void* G, const void* H, int K, int n_steps, double* a_out, double* b2_out,
+                 double* info_out, hipStream_t stream) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (!G || !H || !a_out || !b2_out || !info_out)
+        return fail(CRBM_EINVAL, "G, H, a_out, b2_out and info_out must be non-NULL");
+    if (K < 1 || K > kMaxBasis) return fail(CRBM_EINVAL, "K must be in [1, %d] (got %d)", kMaxBasis, K);
+    if (n_steps < 1) return fail(CRBM_EINVAL, "n_steps must be >= 1");
+    if (int rc = set_device(p)) return rc;
+    if (int rc = p->grow(crbm_plan_s::GB_SMALL, (size_t)(4L * kMaxBasis * kMaxBasis + kMaxBasis) * sizeof(double2)))
+        return rc;
+    hipError_t e = launch_lanczos(K, static_cast<const double2*>(G), static_cast<const double2*>(H), n_steps,
+                                  static_cast<double2*>(p->grow_ptr[crbm_plan_s::GB_SMALL]), a_out, b2_out, info_out,
+                                  stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "lanczos launch");
+}
+
+int crbm_spectrum_kpm(const double* mu, int n_mom, int jackson, double E0, double E_c, double W_scale,
+                      const double* omega, int n_omega, double* A_out, hipStream_t stream) {
+    if (!mu || !omega || !A_out) return fail(CRBM_EINVAL, "mu, omega and A_out must be non-NULL");
+    if (n_mom < 1) return fail(CRBM_EINVAL, "n_mom must be >= 1");
+    if (n_omega < 0) return fail(CRBM_EINVAL, "n_omega must be >= 0");
+    if (!(W_scale != 0.0) || !(W_scale - W_scale == 0.0)) return fail(CRBM_EINVAL, "W_scale must be finite and non-zero");
+    if (n_omega == 0) return CRBM_OK;
+    hipError_t e = launch_spec_kpm(mu, n_mom, jackson != 0, E0, E_c, W_scale, omega, n_omega, A_out, stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "spectrum_kpm launch");
+}
+
+int crbm_spectrum_cf(const double* a, const double* b2, int m, double E0, double eta, const double* omega, int n_omega,
+                     double* A_out, hipStream_t stream) {
+    if (!a || !b2 || !omega || !A_out) return fail(CRBM_EINVAL, "a, b2, omega and A_out must be non-NULL");
+    if (m < 1) return fail(CRBM_EINVAL, "m must be >= 1");
+    if (n_omega < 0) return fail(CRBM_EINVAL, "n_omega must be >= 0");
+    if (!(eta > 0.0)) return fail(CRBM_EINVAL, "eta must be > 0");
+    if (n_omega == 0) return CRBM_OK;
+    hipError_t e = launch_spec_cf(a, b2, m, E0, eta, omega, n_omega, A_out, stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "spectrum_cf launch");
 }
 
 static int batched_args(crbm_plan p, const crbm_rbm* gs, const void* t_params, const double* betas, const double* q,

@@ -53,3 +53,22 @@ def test_binding_rejects_cpu_tensors():
                    torch.zeros(4, 3, dtype=torch.complex64))
     with pytest.raises(ValueError):
         rbm.struct()
+
+
+def test_host_side_errors_of_the_spectral_calls():
+    L = crbm.lib()
+    dummy = ctypes.c_void_p(256)      # never dereferenced: every case below fails validation first
+    assert L.crbm_spectrum_kpm(None, 4, 1, 0.0, 0.0, 1.0, dummy, 8, dummy, None) == crbm.CRBM_EINVAL
+    assert L.crbm_spectrum_kpm(dummy, 0, 1, 0.0, 0.0, 1.0, dummy, 8, dummy, None) == crbm.CRBM_EINVAL
+    assert L.crbm_spectrum_kpm(dummy, 4, 1, 0.0, 0.0, 0.0, dummy, 8, dummy, None) == crbm.CRBM_EINVAL
+    assert L.crbm_spectrum_kpm(dummy, 4, 1, 0.0, 0.0, float("inf"), dummy, 8, dummy, None) == crbm.CRBM_EINVAL
+    assert L.crbm_spectrum_kpm(dummy, 4, 1, 0.0, 0.0, 1.0, dummy, -1, dummy, None) == crbm.CRBM_EINVAL
+    assert L.crbm_spectrum_kpm(dummy, 4, 1, 0.0, 0.0, 1.0, dummy, 0, dummy, None) == crbm.CRBM_OK   # nothing to do
+    assert L.crbm_spectrum_cf(dummy, dummy, 3, 0.0, 0.0, dummy, 8, dummy, None) == crbm.CRBM_EINVAL
+    assert b"eta" in L.crbm_last_error()
+    assert L.crbm_spectrum_cf(dummy, dummy, 0, 0.0, 0.1, dummy, 8, dummy, None) == crbm.CRBM_EINVAL
+    assert L.crbm_corrected_moments(None, dummy, dummy, 4, 0.0, 1.0, 8, dummy, dummy, None) == crbm.CRBM_EINVAL
+    assert L.crbm_lanczos(None, dummy, dummy, 4, 4, dummy, dummy, dummy, None) == crbm.CRBM_EINVAL
+    assert L.crbm_moment_matrices(None, None, None, None, 0, None, None, None, 1, None, None, None) == crbm.CRBM_EINVAL
+    assert L.crbm_sr_energy_step(None, None, None, None, None, None, 1, 0.1, 0.0, 0, 0, 1e-6, 10, None,
+                                 None) == crbm.CRBM_EINVAL
