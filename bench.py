@@ -70,7 +70,8 @@ def parse():
     ap.add_argument("--fp32-fraction", type=int, default=16,
                     help="the plain-FP32 S contraction is timed on N_s / this many samples and scaled")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
-    ap.add_argument("--workload", choices=["square10", "batched8x8", "chain40", "grad16x16"], default="square10",
+    ap.add_argument("--workload", choices=["square10", "batched8x8", "chain40", "grad16x16", "spectral10x10",
+                                           "groundstate10x10"], default="square10",
                     help="square10: the metric's 10x10 alpha=4 step (default); batched8x8: 2048 (q, n) moment "
                          "instances of the 8x8 alpha=2 lattice in one persistent launch; chain40: the 40-site "
                          "chain, alpha=2, FP32 dense SR with the FP64 Cholesky solve; grad16x16: forward and "
@@ -93,6 +94,10 @@ def main():
         return bench_chain40(crbm, args)
     if args.workload == "grad16x16":
         return bench_grad16(crbm, args)
+    if args.workload == "spectral10x10":
+        return bench_spectral(crbm, args)
+    if args.workload == "groundstate10x10":
+        return bench_groundstate(crbm, args)
     wl = synth.SQUARE10
     N, M, P = wl.N, wl.M, wl.P
     C, sweeps = args.chains, args.sweeps
@@ -319,6 +324,109 @@ def bench_chain40(crbm, args):
                                  "sweeps": sweeps, "samples_per_step": ns, "solver": "cholesky_fp64",
                                  "s_precision": "fp32", "diag_shift": wl.diag_shift},
                       "sr_steps_per_s": 1.0 / el, "sr_flags": int(st[6]), "rel_residual": float(st[4]),
+                      "phases": phases}))
+    plan.close()
+
+
+def bench_spectral(crbm, args):
+    """Moment correction and both spectra on the 10x10 alpha = 4 lattice: 4096 chains x 128 sweeps of psi_gs,
+    G and H (K = n_moments + 1) over the 524,288 samples, corrected moments (10 K of them), Lanczos,
+    Jackson-damped and continued-fraction spectra on 1001 frequencies."""
+    wl = synth.SQUARE10
+    N, M, P = wl.N, wl.M, wl.P
+    C, sweeps = args.chains, args.sweeps
+    ns = C * sweeps
+    n_max = args.n_moments
+    K = n_max + 1
+    plan = crbm.Plan(crbm.SQUARE, wl.Lx, wl.Ly, M, ns)
+    gs = crbm.RBM.empty(N, M)
+    crbm.init_rbm(gs, wl.param_seed, wl.param_std)
+    tp = torch.zeros(n_max, P, dtype=torch.complex64, device="cuda")
+    for t in range(n_max):
+        crbm.init_rbm(crbm.RBM.from_packed(tp[t], N, M), wl.param_seed + 10 + t, wl.param_std)
+    betas = torch.ones(n_max, dtype=torch.complex128, device="cuda")
+    E0 = synth.E0_PER_SITE_SQUARE * N
+    W_scale = 1.5 * abs(E0)
+    E_c = E0 + (1.0 - 0.0125) * W_scale
+    q = (math.pi, math.pi)
+    chains = torch.zeros(C, N, dtype=torch.int8, device="cuda")
+    crbm.init_chains(plan, chains, wl.chain_seed + 1, True)
+    samples = torch.zeros(sweeps, C, N, dtype=torch.int8, device="cuda")
+    flat = samples.view(ns, N)
+    G = torch.zeros(K, K, dtype=torch.complex128, device="cuda")
+    H = torch.zeros_like(G)
+    n_out = 10 * K
+    mu = torch.zeros(n_out, dtype=torch.float64, device="cuda")
+    info = torch.zeros(3, dtype=torch.float64, device="cuda")
+    a = torch.zeros(K, dtype=torch.float64, device="cuda")
+    b2 = torch.zeros(K, dtype=torch.float64, device="cuda")
+    linfo = torch.zeros(2, dtype=torch.float64, device="cuda")
+    omega = torch.linspace(0.0, 2.0 * W_scale, 1001, dtype=torch.float64, device="cuda")
+    A_kpm = torch.zeros_like(omega)
+    A_cf = torch.zeros_like(omega)
+    crbm.sample(plan, gs, chains, 16, crbm.EXCHANGE, 12, 0)
+    off = [16 * N]
+
+    def step():
+        crbm.sample(plan, gs, chains, sweeps, crbm.EXCHANGE, 12, off[0], samples_out=samples)
+        crbm.moment_matrices(plan, gs, tp, betas, q, flat, G, H)
+        crbm.corrected_moments(plan, G, H, E_c, W_scale, mu, info)
+        crbm.lanczos(plan, G, H, a, b2, linfo)
+        crbm.spectrum_kpm(mu, E0, E_c, W_scale, omega, A_kpm)
+        crbm.spectrum_cf(a, b2, K, E0, 0.1, omega, A_cf)
+        off[0] += sweeps * N
+
+    el, phases = _timed(plan, step, args.steps, args.warmup)
+    inf, linf = info.cpu().numpy(), linfo.cpu().numpy()
+    print(json.dumps({"metric": "samples/s of the moment-correction pass (G and H over n_max RBMs) with both spectra",
+                      "value": ns / el, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": el * 1e3, "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "heisenberg_square10x10_rbm_alpha4_moment_correction", "N": N, "M": M,
+                                 "P": P, "chains": C, "sweeps": sweeps, "samples_per_step": ns, "K": K,
+                                 "corrected_moments": n_out, "omega_points": 1001},
+                      "correction_flags": int(inf[0]), "moment_growth": float(inf[1]),
+                      "lanczos_steps": int(linf[1]), "phases": phases}))
+    plan.close()
+
+
+def bench_groundstate(crbm, args):
+    """Ground-state natural-gradient step on the 10x10 alpha = 4 lattice: 4096 chains x 128 sweeps, local
+    energies, BF16 dense S on the matrix cores and CG (diagonal shift 1e-4, tol 1e-6)."""
+    wl = synth.SQUARE10
+    N, M, P = wl.N, wl.M, wl.P
+    C, sweeps = args.chains, args.sweeps
+    ns = C * sweeps
+    plan = crbm.Plan(crbm.SQUARE, wl.Lx, wl.Ly, M, ns, crbm.PLAN_DENSE_S)
+    psi = crbm.RBM.empty(N, M)
+    crbm.init_rbm(psi, wl.param_seed, wl.param_std)
+    chains = torch.zeros(C, N, dtype=torch.int8, device="cuda")
+    crbm.init_chains(plan, chains, wl.chain_seed, True)
+    samples = torch.zeros(sweeps, C, N, dtype=torch.int8, device="cuda")
+    flat = samples.view(ns, N)
+    T = torch.zeros(ns, M, dtype=torch.complex64, device="cuda")
+    El = torch.zeros(ns, dtype=torch.complex64, device="cuda")
+    stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+    crbm.sample(plan, psi, chains, 16, crbm.EXCHANGE, 41, 0)
+    off = [16 * N]
+
+    def step():
+        crbm.sample(plan, psi, chains, sweeps, crbm.EXCHANGE, 41, off[0], samples_out=samples)
+        crbm.local_estimators(plan, psi, flat, eloc_out=El, tanh_out=T)
+        crbm.sr_energy_step(plan, psi, flat, T, El, 0.05, wl.diag_shift, crbm.CG_DENSE, crbm.BF16, 1e-6,
+                            args.cg_maxit, stats)
+        off[0] += sweeps * N
+
+    el, phases = _timed(plan, step, args.steps, args.warmup)
+    st = stats.cpu().numpy()
+    print(json.dumps({"metric": "MC samples/s + SR steps/s of the ground-state search", "value": ns / el,
+                      "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": el * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "bf16", "data": "synthetic",
+                      "config": {"workload": "heisenberg_square10x10_rbm_alpha4_ground_state", "N": N, "M": M,
+                                 "P": P, "chains": C, "sweeps": sweeps, "samples_per_step": ns,
+                                 "diag_shift": wl.diag_shift, "lr": 0.05},
+                      "energy_per_site": float(st[1]) / N, "cg_iterations": float(st[5]), "sr_flags": int(st[6]),
                       "phases": phases}))
     plan.close()
 
