@@ -187,6 +187,17 @@ def main():
         roof = {"kernel": "k_ot", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes": byts}
 
+    # sustained ceilings of this device, measured after the timed region
+    if roof["bound"] == "mfma" and prec == crbm.BF16:
+        ceil = crbm.probe_mfma()
+        roof["measured_ceiling"] = {"value": ceil, "unit": "TFLOP/s",
+                                    "probe": "v_mfma_f32_32x32x16_bf16, 8 independent accumulators per wave, "
+                                             "2 workgroups x 4 waves per CU, no memory traffic"}
+        roof["frac_of_measured"] = roof["achieved"] / ceil
+    elif roof["bound"] == "hbm":
+        ceil = crbm.probe_hbm(1 << 30)
+        roof["measured_ceiling"] = {"value": ceil, "unit": "GB/s", "probe": "16-byte copy of 1 GiB, read + write"}
+        roof["frac_of_measured"] = roof["achieved"] / ceil
     line = {
         "metric": "MC samples/s + SR steps/s, 10x10 RBM alpha=4, BF16/batched vs plain FP32 at equal mu_n error",
         "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

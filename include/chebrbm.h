@@ -145,6 +145,16 @@ enum {
 int crbm_plan_profile(crbm_plan plan, int enable);
 int crbm_plan_profile_read(crbm_plan plan, int group, int* count, double* total_ms);
 
+/* Ceiling probes for rooflines (instrumentation; both synchronise the stream and allocate and free
+ * temporary device memory on the current device):
+ * crbm_probe_mfma: sustained TFLOP/s of the BF16 matrix cores (v_mfma_f32_32x32x16_bf16, eight
+ *   independent accumulators per wave, two workgroups of four waves per compute unit, no memory
+ *   traffic in the loop), written to host *tflops_out.
+ * crbm_probe_hbm: copy bandwidth in GB/s (bytes read + bytes written) of a 16-byte grid-stride copy
+ *   of `bytes` (>= 1 MiB) between two device buffers, written to host *gbs_out. */
+int crbm_probe_mfma(double* tflops_out, hipStream_t stream);
+int crbm_probe_hbm(size_t bytes, double* gbs_out, hipStream_t stream);
+
 /* Fill a, b, W with complex numbers whose real and imaginary parts are independent
  * N(0, stddev^2): parameter k of the packed vector takes Philox4x32-10 block
  * (key = seed, counter = (k, 0, 0, 2)), u1 = ((x0 >> 8) + 1) 2^-24, u2 = (x1 >> 8) 2^-24,

@@ -32,7 +32,7 @@ EXPORTS = ("crbm_plan_create", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_la
            "crbm_plan_profile_read", "crbm_init_rbm", "crbm_init_chains", "crbm_sample", "crbm_local_estimators",
            "crbm_sr_step", "crbm_sr_energy_step", "crbm_chebyshev_moment", "crbm_fidelity_grad", "crbm_batched_moments",
            "crbm_batched_autotune", "crbm_moment_matrices", "crbm_corrected_moments", "crbm_lanczos",
-           "crbm_spectrum_kpm", "crbm_spectrum_cf")
+           "crbm_spectrum_kpm", "crbm_spectrum_cf", "crbm_probe_mfma", "crbm_probe_hbm")
 PROF_NAMES = ("sample", "theta", "local", "ot", "sbuild", "cg", "moment", "pack", "cholesky", "batched", "gram")
 
 
@@ -86,6 +86,8 @@ def lib():
         L.crbm_lanczos.argtypes = [_vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp]
         L.crbm_spectrum_kpm.argtypes = [_vp, _i, _i, _d, _d, _d, _vp, _i, _vp, _vp]
         L.crbm_spectrum_cf.argtypes = [_vp, _vp, _i, _d, _d, _vp, _i, _vp, _vp]
+        L.crbm_probe_mfma.argtypes = [P(_d), _vp]
+        L.crbm_probe_hbm.argtypes = [ctypes.c_size_t, P(_d), _vp]
         L.crbm_chebyshev_moment.argtypes = [_vp, P(_Rbm), _vp, _vp, _i, P(_d), _i, _vp, _vp, _l, _vp, _vp]
         L.crbm_fidelity_grad.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _l, _vp, _vp, _vp]
         L.crbm_batched_moments.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _i, ctypes.c_int64, _i, _i, _i, _u64,
@@ -388,6 +390,20 @@ def spectrum_cf(a, b2, m: int, E0: float, eta: float, omega, A_out, stream=None)
         _ptr(a, torch.float64, (a.shape[0],), "a"), _ptr(b2, torch.float64, (b2.shape[0],), "b2"), m, E0, eta,
         _ptr(omega, torch.float64, (n_w,), "omega"), n_w, _ptr(A_out, torch.float64, (n_w,), "A_out"),
         _stream(stream)))
+
+
+def probe_mfma(stream=None) -> float:
+    """Sustained BF16 matrix-core TFLOP/s of the current device (synchronises)."""
+    v = ctypes.c_double()
+    _check(lib().crbm_probe_mfma(ctypes.byref(v), _stream(stream)))
+    return v.value
+
+
+def probe_hbm(nbytes: int = 1 << 30, stream=None) -> float:
+    """Copy bandwidth (read + write) in GB/s of the current device (synchronises)."""
+    v = ctypes.c_double()
+    _check(lib().crbm_probe_hbm(nbytes, ctypes.byref(v), _stream(stream)))
+    return v.value
 
 
 def batched_moments(plan: Plan, psi_gs: RBM, t_params, betas, q, chain_offsets, n_burn: int, n_sweeps: int,

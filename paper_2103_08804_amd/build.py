@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libchebrbm.so")
 SOURCES = ["api.hip", "kernels_sample.hip", "kernels_local.hip", "kernels_sr.hip", "kernels_chol.hip",
-           "kernels_mfma.hip", "kernels_batched.hip", "kernels_spectral.hip"]
+           "kernels_mfma.hip", "kernels_batched.hip", "kernels_spectral.hip", "kernels_probe.hip"]
 ARCH = "gfx950"
 # Packed-FP32 instructions are kept out of the generated code.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",

@@ -40,6 +40,8 @@ hipError_t launch_spec_kpm(const double* mu, int n_mom, int jackson, double E0, 
                            const double* omega, int n_w, double* A, hipStream_t stream);
 hipError_t launch_spec_cf(const double* a, const double* b2, int m, double E0, double eta, const double* omega,
                           int n_w, double* A, hipStream_t stream);
+hipError_t launch_probe_mfma(int blocks, int iters, float* out, hipStream_t stream);
+hipError_t launch_probe_copy(int blocks, const void* src, void* dst, long n16, hipStream_t stream);
 
 }  // namespace crbm
 
@@ -176,6 +178,31 @@ int set_device(crbm_plan p) {
     if (cur != p->device) return fail(CRBM_EINVAL, "plan was created on device %d but device %d is current",
                                       p->device, cur);
     return CRBM_OK;
+}
+}  // namespace
+
+namespace {
+// milliseconds of one launch sequence timed with events on `stream` (synchronises), or < 0 on error
+template <class F>
+double timed_ms(hipStream_t stream, F&& launch) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return -1.0; }
+    float ms = -1.f;
+    hipError_t r = hipEventRecord(e0, stream);
+    if (r == hipSuccess) r = launch();
+    if (r == hipSuccess) r = hipEventRecord(e1, stream);
+    if (r == hipSuccess) r = hipEventSynchronize(e1);
+    if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return r == hipSuccess ? (double)ms : -1.0;
+}
+int current_cus() {
+    int dev = 0, n_cu = 256;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1) n_cu = 256;
+    return n_cu;
 }
 }  // namespace
 
@@ -722,6 +749,45 @@ int crbm_spectrum_cf(const double* a, const double* b2, int m, double E0, double
     if (n_omega == 0) return CRBM_OK;
     hipError_t e = launch_spec_cf(a, b2, m, E0, eta, omega, n_omega, A_out, stream);
     return e == hipSuccess ? CRBM_OK : hip_fail(e, "spectrum_cf launch");
+}
+
+int crbm_probe_mfma(double* tflops_out, hipStream_t stream) {
+    if (!tflops_out) return fail(CRBM_EINVAL, "tflops_out is NULL");
+    const int blocks = 2 * current_cus(), iters = 20000;
+    float* out = nullptr;
+    hipError_t e = hipMalloc(&out, (size_t)blocks * 256 * sizeof(float));
+    if (e != hipSuccess) { (void)hipGetLastError(); return fail(CRBM_ENOMEM, "probe buffer: %s", hipGetErrorString(e)); }
+    auto launch = [&]() { return launch_probe_mfma(blocks, iters, out, stream); };
+    double ms = timed_ms(stream, launch);          // the first launch brings the clocks up
+    if (ms > 0) ms = timed_ms(stream, launch);
+    (void)hipFree(out);
+    if (!(ms > 0)) return fail(CRBM_EHIP, "matrix-core probe failed");
+    *tflops_out = (double)blocks * 4 * iters * 8 * 32768.0 / (ms * 1e-3) / 1e12;
+    return CRBM_OK;
+}
+
+int crbm_probe_hbm(size_t bytes, double* gbs_out, hipStream_t stream) {
+    if (!gbs_out) return fail(CRBM_EINVAL, "gbs_out is NULL");
+    if (bytes < (1u << 20)) return fail(CRBM_EINVAL, "bytes must be >= 1 MiB");
+    const long n16 = (long)(bytes / 16);
+    void *a = nullptr, *b = nullptr;
+    hipError_t e = hipMalloc(&a, (size_t)n16 * 16);
+    if (e == hipSuccess) e = hipMalloc(&b, (size_t)n16 * 16);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (a) (void)hipFree(a);
+        return fail(CRBM_ENOMEM, "probe buffers: %s", hipGetErrorString(e));
+    }
+    const int blocks = 8 * current_cus();
+    auto launch = [&]() { return launch_probe_copy(blocks, a, b, n16, stream); };
+    e = hipMemsetAsync(a, 1, (size_t)n16 * 16, stream);
+    double ms = e == hipSuccess ? timed_ms(stream, launch) : -1.0;
+    if (ms > 0) ms = timed_ms(stream, launch);
+    (void)hipFree(a);
+    (void)hipFree(b);
+    if (!(ms > 0)) return fail(CRBM_EHIP, "HBM probe failed");
+    *gbs_out = 2.0 * (double)n16 * 16 / (ms * 1e-3) / 1e9;
+    return CRBM_OK;
 }
 
 static int batched_args(crbm_plan p, const crbm_rbm* gs, const void* t_params, const double* betas, const double* q,
