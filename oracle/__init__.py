@@ -84,6 +84,10 @@ def lib():
                                           _f64p, _c.c_int, _c.c_int, _c.c_int, _c.c_double, _i8p, _c.c_void_p,
                                           _c.c_long, _c128p, _c128p]
         L.orc_moment_matrices.restype = None
+        L.orc_sym_matrices.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _c128p, _c128p, _c128p, _c.c_int,
+                                       _c.c_int, _c.c_int, _c.c_int, _c.c_double, _c.c_int, _i8p, _c.c_void_p,
+                                       _c.c_long, _c128p, _c128p]
+        L.orc_sym_matrices.restype = None
         L.orc_fidelity_grad.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _i8p, _c128p, _c.c_long,
                                         _c.c_void_p]
         L.orc_fidelity_grad.restype = _c.c_double
@@ -323,6 +327,24 @@ def moment_matrices(psi_gs, ts, betas, q, lat, sig, weights=None):
                               _c128(np.asarray(betas, np.complex128).reshape(-1) if n_max else np.zeros(1)),
                               n_max, np.ascontiguousarray(np.asarray(q, np.float64).reshape(2)), lat.kind, lat.Lx,
                               lat.Ly, lat.J, sig, _ptr(w), sig.shape[0], G, H)
+    return G, H
+
+
+def sym_matrices(psi_gs, ts, betas, lat, sig, rotations=True, weights=None):
+    """(G, H), each [N][K][K] over the N lattice momenta k = k1 + Lx k2, of the symmetry-projected
+    basis of App. A (t_000 = S^z_0 psi_gs, t_n00 = beta_n t~_n)."""
+    sig = _i8(sig)
+    n_max = len(ts)
+    K = n_max + 1
+    N = lat.N
+    tp = np.concatenate([t.vector() for t in ts]) if n_max else np.zeros(1, np.complex128)
+    G = np.zeros((N, K, K), np.complex128)
+    H = np.zeros((N, K, K), np.complex128)
+    w = None if weights is None else np.ascontiguousarray(weights, np.float64)
+    lib().orc_sym_matrices(psi_gs.N, psi_gs.M, psi_gs.a, psi_gs.b, psi_gs.W, _c128(tp),
+                           _c128(np.asarray(betas, np.complex128).reshape(-1) if n_max else np.zeros(1)),
+                           n_max, lat.kind, lat.Lx, lat.Ly, lat.J, int(bool(rotations)), sig, _ptr(w),
+                           sig.shape[0], G, H)
     return G, H
 
 

@@ -799,3 +799,138 @@ void orc_moment_matrices(int N, int M, const cplx* ag, const cplx* bg, const cpl
     }
     free(bonds); free(B); free(HB);
 }
+
+/* ------------------------------------------------------------------------- */
+/* Symmetry-projected moment-correction matrices (App. A).                    */
+/* The stored RBMs t_n00 approximate the Chebyshev vectors of the LOCAL       */
+/* operator: t_000 = S^z_0 psi_gs (site 0 = origin) and t_n00 = beta_n t~_n.  */
+/* A lattice symmetry g (a map of sites) acts on basis states so that         */
+/* <s|g|t> = t(s o g) with (s o g)_r = s_{g(r)}.  With translations T_m and   */
+/* the rotation R(x, y) = (L-1-y, x) of the L x L lattice,                     */
+/*   B_{n,m,rot}(s) = <s|T_m R^rot|t_n00> / psi_gs(s),                         */
+/* and the momentum-k projection of the rotation-averaged state is             */
+/*   Bt_{nk}(s) = N^{-1/2} sum_m e^{-i k.m} (1/4) [B_{n,m,0} + B_{n,m+(1,0),1} */
+/*                + B_{n,m+(1,1),2} + B_{n,m+(0,1),3}],   k.m = 2pi(k1 m1/Lx + k2 m2/Ly). */
+/* On a chain (or with use_rot = 0) only the rot = 0 term is kept, with       */
+/* weight 1.  HB uses (H t)(s o g) in place of t(s o g).  Then                */
+/*   G^(k)_nn' = <conj(Bt_nk) Bt_n'k>,  H^(k)_nn' = <conj(Bt_nk) HBt_n'k>,     */
+/* k = k1 + Lx k2 over all N momenta; G_out, H_out are [N][K][K].             */
+/* ------------------------------------------------------------------------- */
+static int sym_site(int kind, int Lx, int Ly, int m1, int m2, int rot, int r) {
+    int x = (kind == 0) ? r : r % Lx, y = (kind == 0) ? 0 : r / Lx;
+    for (int k = 0; k < rot; ++k) {         /* R(x, y) = (L-1-y, x), L = Lx = Ly */
+        int nx = Lx - 1 - y, ny = x;
+        x = nx; y = ny;
+    }
+    x = (x + m1) % Lx;
+    y = (kind == 0) ? 0 : (y + m2) % Ly;
+    return x + Lx * y;
+}
+
+/* sum over bonds of (H g)(y) / psi_ref with g(y) = f(y) exp(log t(y)), f = y_0/2 (local_f) or 1 */
+static cplx h_apply_over(int N, int M, const cplx* a, const cplx* b, const cplx* W, int nb, const int* bonds,
+                         double J, const int8_t* y, int local_f, cplx logref, int8_t* tmp, cplx* th) {
+    const cplx ly = logpsi_one(N, M, a, b, W, y, th);
+    const double fy = local_f ? 0.5 * (double)y[0] : 1.0;
+    cplx acc = 0.0;
+    memcpy(tmp, y, (size_t)N);
+    for (int e = 0; e < nb; ++e) {
+        const int i = bonds[2 * e], j = bonds[2 * e + 1];
+        acc += 0.25 * J * (double)(y[i] * y[j]) * fy * cexp(ly - logref);
+        if (y[i] != y[j]) {
+            tmp[i] = y[j]; tmp[j] = y[i];
+            const cplx l2 = logpsi_one(N, M, a, b, W, tmp, th);
+            const double f2 = local_f ? 0.5 * (double)tmp[0] : 1.0;
+            acc += 0.5 * J * f2 * cexp(l2 - logref);
+            tmp[i] = y[i]; tmp[j] = y[j];
+        }
+    }
+    return acc;
+}
+
+void orc_sym_matrices(int N, int M, const cplx* ag, const cplx* bg, const cplx* Wg,
+                      const cplx* t_params, const cplx* betas, int n_max,
+                      int kind, int Lx, int Ly, double J, int use_rot,
+                      const int8_t* sig, const double* weights, long n, cplx* G_out, cplx* H_out) {
+    const long P = (long)N + M + (long)N * M;
+    const int K = n_max + 1;
+    const int L2 = (kind == 0) ? 1 : Ly;
+    const int nrot = (use_rot && kind == 1) ? 4 : 1;
+    const int ng = N * nrot;                       /* group elements (m, rot) */
+    int* bonds = (int*)malloc(sizeof(int) * 4 * (size_t)N);
+    const int nb = orc_lattice_bonds(kind, Lx, Ly, bonds);
+    /* per sample: Bt[s][k][t], HBt[s][k][t] */
+    cplx* Bt = (cplx*)malloc(sizeof(cplx) * (size_t)n * N * K);
+    cplx* HBt = (cplx*)malloc(sizeof(cplx) * (size_t)n * N * K);
+#pragma omp parallel
+    {
+        int8_t* img = (int8_t*)malloc((size_t)N);
+        int8_t* tmp = (int8_t*)malloc((size_t)N);
+        cplx* th = (cplx*)malloc(sizeof(cplx) * (size_t)M);
+        cplx* B = (cplx*)malloc(sizeof(cplx) * (size_t)K * ng);
+        cplx* HB = (cplx*)malloc(sizeof(cplx) * (size_t)K * ng);
+#pragma omp for schedule(dynamic, 4)
+        for (long s = 0; s < n; ++s) {
+            const int8_t* x = sig + s * N;
+            const cplx lg = logpsi_one(N, M, ag, bg, Wg, x, th);
+            for (int m2 = 0; m2 < L2; ++m2)
+                for (int m1 = 0; m1 < Lx; ++m1)
+                    for (int rot = 0; rot < nrot; ++rot) {
+                        const int gi = ((m1 + Lx * m2) * nrot) + rot;
+                        for (int r = 0; r < N; ++r) img[r] = x[sym_site(kind, Lx, Ly, m1, m2, rot, r)];
+                        const cplx lgi = logpsi_one(N, M, ag, bg, Wg, img, th);
+                        B[gi] = 0.5 * (double)img[0] * cexp(lgi - lg);
+                        HB[gi] = h_apply_over(N, M, ag, bg, Wg, nb, bonds, J, img, 1, lg, tmp, th);
+                        for (int t = 1; t <= n_max; ++t) {
+                            const cplx* tp = t_params + (long)(t - 1) * P;
+                            const cplx lt = logpsi_one(N, M, tp, tp + N, tp + N + M, img, th);
+                            B[(long)t * ng + gi] = betas[t - 1] * cexp(lt - lg);
+                            HB[(long)t * ng + gi] = betas[t - 1] *
+                                h_apply_over(N, M, tp, tp + N, tp + N + M, nb, bonds, J, img, 0, lg, tmp, th);
+                        }
+                    }
+            /* the App. A combination for every momentum */
+            const int off[4][2] = {{0, 0}, {1, 0}, {1, 1}, {0, 1}};
+            for (int k2 = 0; k2 < L2; ++k2)
+                for (int k1 = 0; k1 < Lx; ++k1) {
+                    const int kk = k1 + Lx * k2;
+                    for (int t = 0; t < K; ++t) {
+                        cplx sb = 0.0, sh = 0.0;
+                        for (int m2 = 0; m2 < L2; ++m2)
+                            for (int m1 = 0; m1 < Lx; ++m1) {
+                                const double ph = 2.0 * M_PI * ((double)(k1 * m1) / Lx + (double)(k2 * m2) / Ly);
+                                const cplx e = cexp(-I * ph);
+                                cplx vb = 0.0, vh = 0.0;
+                                for (int rot = 0; rot < nrot; ++rot) {
+                                    const int a1 = (m1 + off[rot][0]) % Lx;
+                                    const int a2 = (kind == 0) ? 0 : (m2 + off[rot][1]) % Ly;
+                                    const int gi = ((a1 + Lx * a2) * nrot) + rot;
+                                    vb += B[(long)t * ng + gi];
+                                    vh += HB[(long)t * ng + gi];
+                                }
+                                sb += e * vb / (double)nrot;
+                                sh += e * vh / (double)nrot;
+                            }
+                        Bt[((long)s * N + kk) * K + t] = sb / sqrt((double)N);
+                        HBt[((long)s * N + kk) * K + t] = sh / sqrt((double)N);
+                    }
+                }
+        }
+        free(img); free(tmp); free(th); free(B); free(HB);
+    }
+    /* G^(k)_tu and H^(k)_tu summed in sample order */
+#pragma omp parallel for schedule(static)
+    for (long e = 0; e < (long)N * K * K; ++e) {
+        const int kk = (int)(e / ((long)K * K)), t = (int)((e / K) % K), u = (int)(e % K);
+        ksum g = {0, 0}, h = {0, 0};
+        for (long s = 0; s < n; ++s) {
+            const double w = weights ? weights[s] : 1.0 / (double)n;
+            const cplx bt = conj(Bt[((long)s * N + kk) * K + t]);
+            kadd(&g, w * bt * Bt[((long)s * N + kk) * K + u]);
+            kadd(&h, w * bt * HBt[((long)s * N + kk) * K + u]);
+        }
+        G_out[e] = g.s;
+        H_out[e] = h.s;
+    }
+    free(bonds); free(Bt); free(HBt);
+}
