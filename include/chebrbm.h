@@ -14,6 +14,7 @@
  *   crbm_chebyshev_moment  mu_n = <t_0|t_n> by sampling psi_gs           (Sec. II, App. A)
  *   crbm_fidelity_grad     gradient of the frozen-sample fidelity surrogate
  *   crbm_moment_matrices   overlap and Hamiltonian matrices of the Chebyshev basis (Sec. IV, App. A)
+ *   crbm_sym_matrices      the same matrices of symmetry-projected states, all momenta (App. A)
  *   crbm_corrected_moments moments of the recursion repeated inside that basis   (Sec. IV)
  *   crbm_lanczos           tridiagonal form of the projected Hamiltonian        (Sec. V)
  *   crbm_spectrum_kpm      Jackson-damped Chebyshev reconstruction A(omega)      (Sec. II, Eq. Aw)
@@ -263,6 +264,24 @@ int crbm_fidelity_grad(crbm_plan plan, const crbm_rbm* fit, const int8_t* sample
 int crbm_moment_matrices(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_params, const double* betas,
                          int n_max, const double* q, const int8_t* samples, const double* weights, long n_samples,
                          void* G_out, void* H_out, hipStream_t stream);
+
+/* Symmetry-projected moment-correction matrices (App. A) for all N lattice momenta at once.
+ * The stored RBMs approximate the Chebyshev vectors of the LOCAL operator at site 0:
+ * t_000 = S^z_0 psi_gs and t_n00 = beta_n t~_n (n = 1..n_max).  A symmetry g acts on configurations
+ * as (s o g)_r = s_{g(r)}; the group is the translations T_m and, if rotations = 1 (L x L lattice
+ * only), the rotation R(x, y) = (L-1-y, x).  Over samples s ~ |psi_gs|^2:
+ *   B_{n,m,rot}(s) = t_n00(s o T_m R^rot)/psi_gs(s)   (and HB with (H t_n00) in place of t_n00),
+ *   Bt_{nk}(s) = N^{-1/2} sum_m e^{-i k.m} (1/4) [B_{n,m,0} + B_{n,m+(1,0),1} + B_{n,m+(1,1),2}
+ *                + B_{n,m+(0,1),3}]   (only the first term, with weight 1, without rotations),
+ *   G^(k)_nn' = <conj(Bt_nk) Bt_n'k>,  H^(k)_nn' = <conj(Bt_nk) HBt_n'k>,
+ * k.m = 2 pi (k1 m1/Lx + k2 m2/Ly), k = k1 + Lx k2.  G_out, H_out: complex128 [N][K][K], K = n_max + 1.
+ * With a translation- and rotation-invariant psi_gs, row 0 of G^(k) holds the moments of S^z_k.
+ * The images of a sample are evaluated in chunks of max_samples / (N * (rotations ? 4 : 1)) samples
+ * (that quotient must be >= 1); the first call with a given chunk size allocates about
+ * 32 K max_samples + 9 max_samples bytes of plan workspace. */
+int crbm_sym_matrices(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_params, const double* betas,
+                      int n_max, int rotations, const int8_t* samples, const double* weights, long n_samples,
+                      void* G_out, void* H_out, hipStream_t stream);
 
 /* Corrected Chebyshev moments (Sec. IV): the recursion repeated for the Hamiltonian projected onto the
  * span of the basis,  H' = (H - E_c G)/W_scale  (the rescaled Hamiltonian of Sec. II in the basis),

@@ -32,7 +32,8 @@ EXPORTS = ("crbm_plan_create", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_la
            "crbm_plan_profile_read", "crbm_init_rbm", "crbm_init_chains", "crbm_sample", "crbm_local_estimators",
            "crbm_sr_step", "crbm_sr_energy_step", "crbm_chebyshev_moment", "crbm_fidelity_grad", "crbm_batched_moments",
            "crbm_batched_autotune", "crbm_moment_matrices", "crbm_corrected_moments", "crbm_lanczos",
-           "crbm_spectrum_kpm", "crbm_spectrum_cf", "crbm_probe_mfma", "crbm_probe_hbm")
+           "crbm_spectrum_kpm", "crbm_spectrum_cf", "crbm_probe_mfma", "crbm_probe_hbm",
+           "crbm_sym_matrices")
 PROF_NAMES = ("sample", "theta", "local", "ot", "sbuild", "cg", "moment", "pack", "cholesky", "batched", "gram")
 
 
@@ -82,6 +83,7 @@ def lib():
         L.crbm_sr_step.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _l, _d, _d, _i, _i, _d, _i, _vp, _vp]
         L.crbm_sr_energy_step.argtypes = L.crbm_sr_step.argtypes
         L.crbm_moment_matrices.argtypes = [_vp, P(_Rbm), _vp, _vp, _i, P(_d), _vp, _vp, _l, _vp, _vp, _vp]
+        L.crbm_sym_matrices.argtypes = [_vp, P(_Rbm), _vp, _vp, _i, _i, _vp, _vp, _l, _vp, _vp, _vp]
         L.crbm_corrected_moments.argtypes = [_vp, _vp, _vp, _i, _d, _d, _i, _vp, _vp, _vp]
         L.crbm_lanczos.argtypes = [_vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp]
         L.crbm_spectrum_kpm.argtypes = [_vp, _i, _i, _d, _d, _d, _vp, _i, _vp, _vp]
@@ -352,6 +354,23 @@ def moment_matrices(plan: Plan, psi_gs: RBM, t_params, betas, q, samples, G_out,
         _ptr(betas, torch.complex128, (n_max,), "betas") if n_max else None, n_max, qarr,
         _ptr(samples, torch.int8, (n, N), "samples"), _ptr(weights, torch.float64, (n,), "weights"), n,
         _ptr(G_out, torch.complex128, (K, K), "G_out"), _ptr(H_out, torch.complex128, (K, K), "H_out"),
+        _stream(stream)))
+
+
+def sym_matrices(plan: Plan, psi_gs: RBM, t_params, betas, samples, G_out, H_out, rotations: bool = True,
+                 weights=None, stream=None):
+    """G^(k), H^(k) [N][K][K] of the symmetry-projected basis (local S^z_0 RBMs) for all N momenta."""
+    n = samples.shape[0]
+    N, P = plan.N, plan.P
+    n_max = 0 if t_params is None else t_params.shape[0]
+    K = n_max + 1
+    g = psi_gs.struct()
+    _check(lib().crbm_sym_matrices(
+        plan.handle, ctypes.byref(g),
+        _ptr(t_params, torch.complex64, (n_max, P), "t_params") if n_max else None,
+        _ptr(betas, torch.complex128, (n_max,), "betas") if n_max else None, n_max, int(bool(rotations)),
+        _ptr(samples, torch.int8, (n, N), "samples"), _ptr(weights, torch.float64, (n,), "weights"), n,
+        _ptr(G_out, torch.complex128, (N, K, K), "G_out"), _ptr(H_out, torch.complex128, (N, K, K), "H_out"),
         _stream(stream)))
 
 

@@ -30,8 +30,15 @@ std::vector<int2> sbuild_order(int N, int M, int n_xcd, int g);
 hipError_t launch_basis_pack(long n, const double2* B, const float2* loc, int mul, float2* Bcol, float2* HBcol,
                              hipStream_t stream);
 long gram_partial_len(int K);
-hipError_t launch_gram2(int K, long n, const float2* Bm, const float2* HBm, const double* w, double2* partial,
-                        double2* G, double2* H, hipStream_t stream);
+hipError_t launch_gram2(int K, long n, const float2* Bm, const float2* HBm, const double* w, double wdef,
+                        double2* partial, double2* G, double2* H, int accumulate, hipStream_t stream);
+hipError_t launch_sym_images(const int8_t* sig, long c, int N, int kind, int Lx, int Ly, int nrot, int8_t* img,
+                             hipStream_t stream);
+hipError_t launch_sym_combine(long rows, int ng, int N, const int8_t* img, int order0, const float2* lt,
+                              const float2* el, const float2* lg, const double2* beta, float2* B, float2* HB,
+                              hipStream_t stream);
+hipError_t launch_sym_dft(long c, int K, int N, int kind, int Lx, int Ly, int nrot, const float2* B, const float2* HB,
+                          float2* Bt, float2* HBt, hipStream_t stream);
 hipError_t launch_correct(int K, const double2* G, const double2* H, double E_c, double W_scale, int n_out,
                           double2* work, double* mu, double* info, hipStream_t stream);
 hipError_t launch_lanczos(int K, const double2* G, const double2* H, int n_steps, double2* work, double* a, double* b2,
@@ -96,7 +103,8 @@ struct crbm_plan_s {
     Profiler prof;
     std::vector<void*> allocs;
     // grow-only workspace of the moment-correction path (allocated on first use)
-    enum { GB_BASIS = 0, GB_HBASIS, GB_ELOC, GB_GRAM, GB_SMALL, GB_COUNT };
+    enum { GB_BASIS = 0, GB_HBASIS, GB_ELOC, GB_GRAM, GB_SMALL, GB_SYMIMG, GB_SYMLT, GB_SYMLG, GB_SYMBT, GB_SYMHBT,
+           GB_COUNT };
     void* grow_ptr[GB_COUNT] = {};
     size_t grow_cap[GB_COUNT] = {};
 
@@ -689,11 +697,115 @@ int crbm_moment_matrices(crbm_plan p, const crbm_rbm* gs, const void* t_params, 
     }
     if (e == hipSuccess) {
         p->prof.begin(PROF_GRAM, stream);
-        e = launch_gram2(K, n, Bm, HBm, weights, part, static_cast<double2*>(G_out), static_cast<double2*>(H_out),
-                         stream);
+        e = launch_gram2(K, n, Bm, HBm, weights, 1.0 / (double)n, part, static_cast<double2*>(G_out),
+                         static_cast<double2*>(H_out), 0, stream);
         p->prof.end(stream);
     }
     return e == hipSuccess ? CRBM_OK : hip_fail(e, "moment_matrices launch");
+}
+
+int crbm_sym_matrices(crbm_plan p, const crbm_rbm* gs, const void* t_params, const double* betas, int n_max,
+                      int rotations, const int8_t* samples, const double* weights, long n, void* G_out, void* H_out,
+                      hipStream_t stream) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (int rc = check_rbm(p, gs, "psi_gs")) return rc;
+    if (n_max < 0) return fail(CRBM_EINVAL, "n_max must be >= 0");
+    if (n_max + 1 > kMaxBasis) return fail(CRBM_EUNSUPPORTED, "K = n_max + 1 = %d exceeds %d", n_max + 1, kMaxBasis);
+    if (n_max > 0 && (!t_params || !betas)) return fail(CRBM_EINVAL, "t_params and betas must be non-NULL");
+    if (!samples || !G_out || !H_out) return fail(CRBM_EINVAL, "samples, G_out and H_out must be non-NULL");
+    if (rotations != 0 && rotations != 1) return fail(CRBM_EINVAL, "rotations must be 0 or 1");
+    if (rotations && (p->lat.kind != CRBM_LATTICE_SQUARE || p->lat.Lx != p->lat.Ly))
+        return fail(CRBM_EINVAL, "rotations need a square L x L lattice");
+    if (n < 1) return fail(CRBM_EINVAL, "n_samples must be >= 1");
+    const int N = p->N, M = p->M, K = n_max + 1;
+    const int nrot = rotations ? 4 : 1;
+    const long ng = (long)N * nrot;
+    if (ng > p->max_samples)
+        return fail(CRBM_EUNSUPPORTED, "the plan's max_samples = %ld is below the %ld images of one sample",
+                    p->max_samples, ng);
+    if (int rc = set_device(p)) return rc;
+    const long cmax = p->max_samples / ng;                  // samples per chunk
+    const long rows_max = cmax * ng;
+    const size_t colb = (size_t)K * (size_t)rows_max * sizeof(float2);
+    int rc = p->grow(crbm_plan_s::GB_BASIS, colb);
+    rc = rc ? rc : p->grow(crbm_plan_s::GB_HBASIS, colb);
+    rc = rc ? rc : p->grow(crbm_plan_s::GB_SYMBT, colb);
+    rc = rc ? rc : p->grow(crbm_plan_s::GB_SYMHBT, colb);
+    rc = rc ? rc : p->grow(crbm_plan_s::GB_SYMIMG, (size_t)rows_max * N);
+    rc = rc ? rc : p->grow(crbm_plan_s::GB_SYMLT, (size_t)rows_max * sizeof(float2));
+    rc = rc ? rc : p->grow(crbm_plan_s::GB_ELOC, (size_t)rows_max * sizeof(float2));
+    rc = rc ? rc : p->grow(crbm_plan_s::GB_SYMLG, (size_t)cmax * sizeof(float2));
+    rc = rc ? rc : p->grow(crbm_plan_s::GB_GRAM, (size_t)gram_partial_len(kMaxBasis) * sizeof(double2));
+    if (rc) return rc;
+    float2* Bm = static_cast<float2*>(p->grow_ptr[crbm_plan_s::GB_BASIS]);
+    float2* HBm = static_cast<float2*>(p->grow_ptr[crbm_plan_s::GB_HBASIS]);
+    float2* Bt = static_cast<float2*>(p->grow_ptr[crbm_plan_s::GB_SYMBT]);
+    float2* HBt = static_cast<float2*>(p->grow_ptr[crbm_plan_s::GB_SYMHBT]);
+    int8_t* img = static_cast<int8_t*>(p->grow_ptr[crbm_plan_s::GB_SYMIMG]);
+    float2* lt = static_cast<float2*>(p->grow_ptr[crbm_plan_s::GB_SYMLT]);
+    float2* el = static_cast<float2*>(p->grow_ptr[crbm_plan_s::GB_ELOC]);
+    float2* lg = static_cast<float2*>(p->grow_ptr[crbm_plan_s::GB_SYMLG]);
+    double2* part = static_cast<double2*>(p->grow_ptr[crbm_plan_s::GB_GRAM]);
+    double2* G = static_cast<double2*>(G_out);
+    double2* H = static_cast<double2*>(H_out);
+    const Geometry geo = p->geometry();
+    const RbmView vg = view(gs);
+    const long P = p->P;
+    const float2* tp = static_cast<const float2*>(t_params);
+    const int Ly = p->lat.kind == CRBM_LATTICE_CHAIN ? 1 : p->lat.Ly;
+    hipError_t e = hipSuccess;
+    auto theta = [&](const int8_t* sig, long rows, const RbmView& v, float2* out) {
+        p->prof.begin(PROF_THETA, stream);
+        hipError_t r = launch_theta(sig, rows, N, M, v.b, v.W, out, stream);
+        p->prof.end(stream);
+        return r;
+    };
+    auto local = [&](const LocalArgs& A, const float2* th) {
+        p->prof.begin(PROF_LOCAL, stream);
+        hipError_t r = launch_local_core(A, th, th, nullptr, stream);
+        p->prof.end(stream);
+        return r;
+    };
+    for (long s0 = 0; s0 < n && e == hipSuccess; s0 += cmax) {
+        const long c = (n - s0) < cmax ? (n - s0) : cmax;
+        const long rows = c * ng;
+        const int8_t* sig = samples + s0 * N;
+        // log psi_gs of the chunk's samples
+        e = theta(sig, c, vg, p->theta[2]);
+        LocalArgs A0{};
+        A0.g = geo; A0.fit = vg; A0.samples = sig; A0.n_samples = c; A0.logpsi_out = lg;
+        if (e == hipSuccess) e = local(A0, p->theta[2]);
+        // the images of every sample under the group
+        if (e == hipSuccess) e = launch_sym_images(sig, c, N, p->lat.kind, p->lat.Lx, Ly, nrot, img, stream);
+        // order 0: t_000 = S^z_0 psi_gs on the images
+        if (e == hipSuccess) e = theta(img, rows, vg, p->theta[0]);
+        LocalArgs A1{};
+        A1.g = geo; A1.fit = vg; A1.psn = vg; A1.cheb_mode = 1; A1.local_op = 1; A1.order = 0; A1.W_scale = 1.0;
+        A1.samples = img; A1.n_samples = rows; A1.logpsi_out = lt; A1.eloc_out = el;
+        if (e == hipSuccess) e = local(A1, p->theta[0]);
+        if (e == hipSuccess) e = launch_sym_combine(rows, (int)ng, N, img, 1, lt, el, lg, nullptr, Bm, HBm, stream);
+        for (int t = 1; t <= n_max && e == hipSuccess; ++t) {
+            const float2* at = tp + (long)(t - 1) * P;
+            RbmView vt;
+            vt.a = at; vt.b = at + N; vt.W = at + N + M;
+            e = theta(img, rows, vt, p->theta[1]);
+            LocalArgs At{};
+            At.g = geo; At.fit = vt; At.samples = img; At.n_samples = rows; At.logpsi_out = lt; At.eloc_out = el;
+            if (e == hipSuccess) e = local(At, p->theta[1]);
+            if (e == hipSuccess)
+                e = launch_sym_combine(rows, (int)ng, N, img, 0, lt, el, lg,
+                                       reinterpret_cast<const double2*>(betas) + (t - 1), Bm + (long)t * rows,
+                                       HBm + (long)t * rows, stream);
+        }
+        // momentum projection for all N momenta, then G^(k), H^(k) accumulated over chunks
+        if (e == hipSuccess) e = launch_sym_dft(c, K, N, p->lat.kind, p->lat.Lx, Ly, nrot, Bm, HBm, Bt, HBt, stream);
+        p->prof.begin(PROF_GRAM, stream);
+        for (int kk = 0; kk < N && e == hipSuccess; ++kk)
+            e = launch_gram2(K, c, Bt + (long)kk * K * c, HBt + (long)kk * K * c, weights ? weights + s0 : nullptr,
+                             1.0 / (double)n, part, G + (long)kk * K * K, H + (long)kk * K * K, s0 > 0, stream);
+        p->prof.end(stream);
+    }
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "sym_matrices launch");
 }
 
 int crbm_corrected_moments(crbm_plan p, const void* G, const void* H, int K, double E_c, double W_scale, int n_out,

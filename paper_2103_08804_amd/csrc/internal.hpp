@@ -49,6 +49,7 @@ struct LocalArgs {
     Geometry g;
     RbmView fit, psn, psm;  // psn.a == nullptr -> energy mode; psm unused at order 0
     int cheb_mode;
+    int local_op;           // Chebyshev mode: t_0 = S^z_0 psi (local operator at site 0) instead of S^z_q psi
     int order;
     double E_c, W_scale;
     double2 beta_n, beta_nm1;

@@ -225,7 +225,9 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __rest
         }
     }
     const bool with_fq = A.cheb_mode && A.order == 0;
-    const float2 d0 = with_fq ? fq_wave(sp, lane, g, A.q0, A.q1) : make_float2(1.f, 0.f);
+    // diagonal factor of t_0: f_q (momentum q) or, with local_op, the local S^z_0 = s_0 / 2
+    const float2 d0 = !with_fq ? make_float2(1.f, 0.f)
+                    : A.local_op ? make_float2(0.5f * (float)sp.get(0), 0.f) : fq_wave(sp, lane, g, A.q0, A.q1);
     const float inv_sqrt_n = rsqrtf((float)N);
 
     float2 acc = make_float2(0.f, 0.f);
@@ -260,9 +262,14 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __rest
         const float2 rho = cexpf(cadd(lg, da));
         float2 d1 = make_float2(1.f, 0.f);
         if (with_fq) {
-            // f_q(s^{ij}) = f_q(s) - N^{-1/2} s_i (e^{-iq.r_i} - e^{-iq.r_j})
-            const float2 pd = csub(site_phase(i, g.kind, g.Lx, A.q0, A.q1), site_phase(j, g.kind, g.Lx, A.q0, A.q1));
-            d1 = csub(d0, cscale(pd, inv_sqrt_n * (float)si));
+            if (A.local_op) {
+                // s_0 / 2 after the swap of sites i and j (s_j = -s_i)
+                d1 = make_float2(i == 0 ? -0.5f * (float)si : (j == 0 ? 0.5f * (float)si : d0.x), 0.f);
+            } else {
+                // f_q(s^{ij}) = f_q(s) - N^{-1/2} s_i (e^{-iq.r_i} - e^{-iq.r_j})
+                const float2 pd = csub(site_phase(i, g.kind, g.Lx, A.q0, A.q1), site_phase(j, g.kind, g.Lx, A.q0, A.q1));
+                d1 = csub(d0, cscale(pd, inv_sqrt_n * (float)si));
+            }
         }
         acc = cadd(acc, cscale(cmul(d1, rho), 0.5f * J));
     }
@@ -288,7 +295,8 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __rest
             if (k < M) dm = cadd(dm, csub(log2cosh(thmg[s * M + k]), log2cosh(t1[e])));
         }
         dm = wave_sum(dm);
-        const float2 fm = (A.order == 1) ? fq_wave(sp, lane, g, A.q0, A.q1) : make_float2(1.f, 0.f);
+        const float2 fm = (A.order != 1) ? make_float2(1.f, 0.f)
+                        : A.local_op ? make_float2(0.5f * (float)sp.get(0), 0.f) : fq_wave(sp, lane, g, A.q0, A.q1);
         const float2 bm = make_float2((float)A.beta_nm1.x, (float)A.beta_nm1.y);
         R = csub(cscale(cmul(cmul(bn, ht), cexpf(dn)), 2.f), cmul(cmul(bm, fm), cexpf(dm)));
     }

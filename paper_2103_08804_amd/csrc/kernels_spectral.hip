@@ -50,7 +50,7 @@ constexpr int GR_T = 32, GR_S = 32;
 
 __global__ __launch_bounds__(256) void k_gram2(int K, long n, long chunk, const float2* __restrict__ Bm,
                                                const float2* __restrict__ HBm, const double* __restrict__ w,
-                                               double2* __restrict__ partial) {
+                                               double wdef, double2* __restrict__ partial) {
     __shared__ float2 sk[GR_S][GR_T + 1];
     __shared__ float2 sl[GR_S][GR_T + 1];
     __shared__ float2 sh[GR_S][GR_T + 1];
@@ -62,7 +62,6 @@ __global__ __launch_bounds__(256) void k_gram2(int K, long n, long chunk, const 
     const int kr = tid >> 3, lc = (tid & 7) * 4;
     const long s_begin = (long)blockIdx.x * chunk;
     const long s_end = min(n, s_begin + chunk);
-    const double wdef = 1.0 / (double)n;
     double2 g[4], h[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) { g[j] = make_double2(0.0, 0.0); h[j] = make_double2(0.0, 0.0); }
@@ -105,9 +104,10 @@ __global__ __launch_bounds__(256) void k_gram2(int K, long n, long chunk, const 
     }
 }
 
-// G[k][l], H[k][l] = sum over chunks (in chunk order) of the tile partials
+// G[k][l], H[k][l] = sum over chunks (in chunk order) of the tile partials (added to G, H if accumulate)
 __global__ __launch_bounds__(256) void k_gram_final(int K, int n_chunks, int tiles, const double2* __restrict__ partial,
-                                                    double2* __restrict__ G, double2* __restrict__ H) {
+                                                    int accumulate, double2* __restrict__ G,
+                                                    double2* __restrict__ H) {
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
     const long per = 2L * GR_T * GR_T;
     if (idx >= (long)tiles * per) return;
@@ -120,7 +120,8 @@ __global__ __launch_bounds__(256) void k_gram_final(int K, int n_chunks, int til
     if (k >= K || l >= K) return;
     double2 acc = make_double2(0.0, 0.0);
     for (int c = 0; c < n_chunks; ++c) acc = zadd(acc, partial[((long)c * tiles + tile) * per + r]);
-    (which ? H : G)[(long)k * K + l] = acc;
+    double2* dst = (which ? H : G) + (long)k * K + l;
+    *dst = accumulate ? zadd(*dst, acc) : acc;
 }
 
 long gram_partial_len(int K) {
@@ -130,18 +131,147 @@ long gram_partial_len(int K) {
     return (long)nbx * tiles * 2 * GR_T * GR_T;
 }
 
-hipError_t launch_gram2(int K, long n, const float2* Bm, const float2* HBm, const double* w, double2* partial,
-                        double2* G, double2* H, hipStream_t stream) {
+// columns Bm[k][n], HBm[k][n]; sample weights w[s] or wdef; G, H = (accumulate ? G, H + : ) the products
+hipError_t launch_gram2(int K, long n, const float2* Bm, const float2* HBm, const double* w, double wdef,
+                        double2* partial, double2* G, double2* H, int accumulate, hipStream_t stream) {
     const int nt = (K + GR_T - 1) / GR_T;
     const int tiles = nt * nt;
     int nbx = tiles >= 1024 ? 1 : 1024 / tiles;
     long chunk = (n + nbx - 1) / nbx;
     chunk = ((chunk + GR_S - 1) / GR_S) * GR_S;
     nbx = (int)((n + chunk - 1) / chunk);
-    hipLaunchKernelGGL(k_gram2, dim3(nbx, tiles), dim3(256), 0, stream, K, n, chunk, Bm, HBm, w, partial);
+    hipLaunchKernelGGL(k_gram2, dim3(nbx, tiles), dim3(256), 0, stream, K, n, chunk, Bm, HBm, w, wdef, partial);
     const long total = (long)tiles * 2 * GR_T * GR_T;
     hipLaunchKernelGGL(k_gram_final, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, K, nbx, tiles,
-                       partial, G, H);
+                       partial, accumulate, G, H);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ symmetry projection (App. A)
+// Group elements g = T_m R^rot, index gi = (m1 + Lx m2) nrot + rot, with R(x, y) = (L-1-y, x) on the
+// L x L lattice (nrot = 4) or translations only (nrot = 1).  An element acts on configurations as
+// (s o g)_r = s_{g(r)}, so that <s|g|t> = t(s o g).
+__device__ __forceinline__ int sym_map(int kind, int Lx, int Ly, int m1, int m2, int rot, int r) {
+    int x = kind == 0 ? r : r % Lx, y = kind == 0 ? 0 : r / Lx;
+    for (int q = 0; q < rot; ++q) {
+        const int nx = Lx - 1 - y;
+        y = x;
+        x = nx;
+    }
+    x += m1;
+    if (x >= Lx) x -= Lx;
+    if (kind == 0) return x;
+    y += m2;
+    if (y >= Ly) y -= Ly;
+    return x + Lx * y;
+}
+
+// img[(s ng + gi) N + r] = sig[s N + g(r)] for the c samples of a chunk
+__global__ __launch_bounds__(256) void k_sym_images(const int8_t* __restrict__ sig, long c, int N, int kind, int Lx,
+                                                    int Ly, int nrot, int8_t* __restrict__ img) {
+    const long ng = (long)N * nrot;
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= c * ng * N) return;
+    const int r = (int)(idx % N);
+    const long row = idx / N;
+    const int gi = (int)(row % ng);
+    const long s = row / ng;
+    const int rot = gi % nrot, m = gi / nrot;
+    const int m1 = m % Lx, m2 = m / Lx;
+    img[idx] = sig[s * N + sym_map(kind, Lx, Ly, m1, m2, rot, r)];
+}
+
+// Per image row (s, g):  order 0: B = (s o g)_0 / 2 psi_gs(s o g)/psi_gs(s), HB = ((H t_000)(s o g)/psi_gs(s o g))
+// psi_gs(s o g)/psi_gs(s);  order n: B = beta_n t_n(s o g)/psi_gs(s), HB = B E_loc[t_n](s o g).
+// lt: log amplitude of the order's RBM on the images; el: its local quantity there; lg: log psi_gs(s).
+__global__ __launch_bounds__(256) void k_sym_combine(long rows, int ng, int N, const int8_t* __restrict__ img,
+                                                     int order0, const float2* __restrict__ lt,
+                                                     const float2* __restrict__ el, const float2* __restrict__ lg,
+                                                     const double2* __restrict__ beta, float2* __restrict__ B,
+                                                     float2* __restrict__ HB) {
+    const long row = (long)blockIdx.x * 256 + threadIdx.x;
+    if (row >= rows) return;
+    const long s = row / ng;
+    const float2 r = cexpf(csub(lt[row], lg[s]));
+    if (order0) {
+        B[row] = cscale(r, 0.5f * (float)img[row * N]);
+        HB[row] = cmul(r, el[row]);
+    } else {
+        const float2 b = cmul(make_float2((float)beta->x, (float)beta->y), r);
+        B[row] = b;
+        HB[row] = cmul(b, el[row]);
+    }
+}
+
+// Bt[(k K + n) c + s] = N^{-1/2} (1/nrot) sum_m e^{-i k.m} sum_rot B[n][(s ng + g(m + d_rot, rot))],
+// d = (0,0), (1,0), (1,1), (0,1); likewise HBt.  One workgroup per (s, n); k = k1 + Lx k2 for all N momenta.
+__global__ __launch_bounds__(256) void k_sym_dft(long c, int K, int N, int kind, int Lx, int Ly, int nrot,
+                                                 const float2* __restrict__ B, const float2* __restrict__ HB,
+                                                 float2* __restrict__ Bt, float2* __restrict__ HBt) {
+    __shared__ float2 sb[1024], sh[1024];
+    __shared__ float2 twx[256], twy[256];
+    const long s = blockIdx.x;
+    const int n = blockIdx.y;
+    const int ng = N * nrot;
+    const int L2 = kind == 0 ? 1 : Ly;
+    const long base = (long)n * c * ng + s * ng;
+    for (int e = threadIdx.x; e < ng; e += 256) { sb[e] = B[base + e]; sh[e] = HB[base + e]; }
+    for (int e = threadIdx.x; e < Lx; e += 256) {
+        float sn, cs;
+        sincospif(-2.0f * (float)e / (float)Lx, &sn, &cs);
+        twx[e] = make_float2(cs, sn);
+    }
+    for (int e = threadIdx.x; e < L2; e += 256) {
+        float sn, cs;
+        sincospif(-2.0f * (float)e / (float)L2, &sn, &cs);
+        twy[e] = make_float2(cs, sn);
+    }
+    __syncthreads();
+    const int off1[4] = {0, 1, 1, 0}, off2[4] = {0, 0, 1, 1};
+    const float norm = rsqrtf((float)N) / (float)nrot;
+    for (int kk = threadIdx.x; kk < N; kk += 256) {
+        const int k1 = kk % Lx, k2 = kk / Lx;
+        float2 ab = make_float2(0.f, 0.f), ah = make_float2(0.f, 0.f);
+        for (int m2 = 0; m2 < L2; ++m2)
+            for (int m1 = 0; m1 < Lx; ++m1) {
+                const float2 tw = cmul(twx[(k1 * m1) % Lx], twy[(k2 * m2) % L2]);
+                float2 vb = make_float2(0.f, 0.f), vh = make_float2(0.f, 0.f);
+                for (int rot = 0; rot < nrot; ++rot) {
+                    int a1 = m1 + off1[rot], a2 = m2 + off2[rot];
+                    if (a1 >= Lx) a1 -= Lx;
+                    if (a2 >= L2) a2 -= L2;
+                    const int gi = (a1 + Lx * a2) * nrot + rot;
+                    vb = cadd(vb, sb[gi]);
+                    vh = cadd(vh, sh[gi]);
+                }
+                ab = cadd(ab, cmul(tw, vb));
+                ah = cadd(ah, cmul(tw, vh));
+            }
+        Bt[((long)kk * K + n) * c + s] = cscale(ab, norm);
+        HBt[((long)kk * K + n) * c + s] = cscale(ah, norm);
+    }
+}
+
+hipError_t launch_sym_images(const int8_t* sig, long c, int N, int kind, int Lx, int Ly, int nrot, int8_t* img,
+                             hipStream_t stream) {
+    const long total = c * (long)N * nrot * N;
+    hipLaunchKernelGGL(k_sym_images, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, sig, c, N, kind, Lx,
+                       Ly, nrot, img);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_combine(long rows, int ng, int N, const int8_t* img, int order0, const float2* lt,
+                              const float2* el, const float2* lg, const double2* beta, float2* B, float2* HB,
+                              hipStream_t stream) {
+    hipLaunchKernelGGL(k_sym_combine, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, stream, rows, ng, N, img,
+                       order0, lt, el, lg, beta, B, HB);
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_dft(long c, int K, int N, int kind, int Lx, int Ly, int nrot, const float2* B, const float2* HB,
+                          float2* Bt, float2* HBt, hipStream_t stream) {
+    hipLaunchKernelGGL(k_sym_dft, dim3((unsigned)c, (unsigned)K), dim3(256), 0, stream, c, K, N, kind, Lx, Ly, nrot,
+                       B, HB, Bt, HBt);
     return hipGetLastError();
 }
 
