@@ -71,7 +71,7 @@ def parse():
                     help="the plain-FP32 S contraction is timed on N_s / this many samples and scaled")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--workload", choices=["square10", "batched8x8", "chain40", "grad16x16", "spectral10x10",
-                                           "groundstate10x10"], default="square10",
+                                           "groundstate10x10", "symmetry6x6"], default="square10",
                     help="square10: the metric's 10x10 alpha=4 step (default); batched8x8: 2048 (q, n) moment "
                          "instances of the 8x8 alpha=2 lattice in one persistent launch; chain40: the 40-site "
                          "chain, alpha=2, FP32 dense SR with the FP64 Cholesky solve; grad16x16: forward and "
@@ -98,6 +98,8 @@ def main():
         return bench_spectral(crbm, args)
     if args.workload == "groundstate10x10":
         return bench_groundstate(crbm, args)
+    if args.workload == "symmetry6x6":
+        return bench_symmetry(crbm, args)
     wl = synth.SQUARE10
     N, M, P = wl.N, wl.M, wl.P
     C, sweeps = args.chains, args.sweeps
@@ -398,6 +400,72 @@ def bench_spectral(crbm, args):
                                  "corrected_moments": n_out, "omega_points": 1001},
                       "correction_flags": int(inf[0]), "moment_growth": float(inf[1]),
                       "lanczos_steps": int(linf[1]), "phases": phases}))
+    plan.close()
+
+
+def bench_symmetry(crbm, args):
+    """Symmetry-projected moment correction on the 6x6 lattice of the paper's 2D results (alpha = 2):
+    1024 chains x 64 sweeps of psi_gs, every sample evaluated on its 36 translations x 4 rotations for
+    psi_gs and the 20 stored local-operator RBMs, G^(k) and H^(k) for all 36 momenta, then per momentum
+    the corrected moments (10 K), Lanczos and both spectra on 1001 frequencies."""
+    wl = synth.SQUARE6
+    N, M, P = wl.N, wl.M, wl.P
+    C, sweeps = wl.chains, wl.sweeps
+    ns = C * sweeps
+    n_max = args.n_moments
+    K = n_max + 1
+    ng = 4 * N
+    plan = crbm.Plan(crbm.SQUARE, wl.Lx, wl.Ly, M, ns * ng)
+    gs = crbm.RBM.empty(N, M)
+    crbm.init_rbm(gs, wl.param_seed, wl.param_std)
+    tp = torch.zeros(n_max, P, dtype=torch.complex64, device="cuda")
+    for t in range(n_max):
+        crbm.init_rbm(crbm.RBM.from_packed(tp[t], N, M), wl.param_seed + 10 + t, wl.param_std)
+    betas = torch.ones(n_max, dtype=torch.complex128, device="cuda")
+    E0 = synth.E0_PER_SITE_SQUARE * N
+    W_scale = 1.5 * abs(E0)
+    E_c = E0 + (1.0 - 0.0125) * W_scale
+    chains = torch.zeros(C, N, dtype=torch.int8, device="cuda")
+    crbm.init_chains(plan, chains, wl.chain_seed, True)
+    samples = torch.zeros(sweeps, C, N, dtype=torch.int8, device="cuda")
+    flat = samples.view(ns, N)
+    G = torch.zeros(N, K, K, dtype=torch.complex128, device="cuda")
+    H = torch.zeros_like(G)
+    n_out = 10 * K
+    mu = torch.zeros(N, n_out, dtype=torch.float64, device="cuda")
+    info = torch.zeros(N, 3, dtype=torch.float64, device="cuda")
+    a = torch.zeros(N, K, dtype=torch.float64, device="cuda")
+    b2 = torch.zeros(N, K, dtype=torch.float64, device="cuda")
+    linfo = torch.zeros(N, 2, dtype=torch.float64, device="cuda")
+    omega = torch.linspace(0.0, 2.0 * W_scale, 1001, dtype=torch.float64, device="cuda")
+    A_kpm = torch.zeros(N, 1001, dtype=torch.float64, device="cuda")
+    A_cf = torch.zeros(N, 1001, dtype=torch.float64, device="cuda")
+    crbm.sample(plan, gs, chains, 16, crbm.EXCHANGE, 51, 0)
+    off = [16 * N]
+
+    def step():
+        crbm.sample(plan, gs, chains, sweeps, crbm.EXCHANGE, 51, off[0], samples_out=samples)
+        crbm.sym_matrices(plan, gs, tp, betas, flat, G, H, rotations=True)
+        for k in range(N):
+            crbm.corrected_moments(plan, G[k], H[k], E_c, W_scale, mu[k], info[k])
+            crbm.lanczos(plan, G[k], H[k], a[k], b2[k], linfo[k])
+            crbm.spectrum_kpm(mu[k], E0, E_c, W_scale, omega, A_kpm[k])
+            crbm.spectrum_cf(a[k], b2[k], K, E0, 0.1, omega, A_cf[k])
+        off[0] += sweeps * N
+
+    el, phases = _timed(plan, step, args.steps, args.warmup)
+    inf, linf = info.cpu().numpy(), linfo.cpu().numpy()
+    print(json.dumps({"metric": "samples/s of the symmetry-projected moment correction (all momenta) with both "
+                                "spectra", "value": ns / el, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": el * 1e3, "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "heisenberg_square6x6_rbm_alpha2_symmetry_projection", "N": N, "M": M,
+                                 "P": P, "chains": C, "sweeps": sweeps, "samples_per_step": ns, "K": K,
+                                 "group_elements": ng, "image_rows": ns * ng, "momenta": N,
+                                 "corrected_moments_per_momentum": n_out, "omega_points": 1001},
+                      "image_rows_per_s": ns * ng / el,
+                      "correction_flags": int(np.max(inf[:, 0])), "max_moment_growth": float(np.max(inf[:, 1])),
+                      "lanczos_steps": [int(v) for v in linf[:, 1][:4]], "phases": phases}))
     plan.close()
 
 

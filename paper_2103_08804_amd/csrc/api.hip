@@ -91,6 +91,7 @@ struct crbm_plan_s {
     long max_samples = 0;
     int flags = 0;
     int2* bonds = nullptr;
+    float4* bond_tab = nullptr;
     SrWork w{};
     float2* theta[3] = {nullptr, nullptr, nullptr};
     double2* momB = nullptr;
@@ -112,6 +113,7 @@ struct crbm_plan_s {
         Geometry g;
         g.N = N; g.M = M; g.P = (int)P; g.n_bonds = n_bonds; g.bonds = bonds;
         g.kind = lat.kind; g.Lx = lat.Lx; g.J = lat.J;
+        g.bond_tab = bond_tab;
         return g;
     }
     template <class T>
@@ -269,6 +271,7 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
     const long red_len = ot_chunks_bound(S) * 2 * plane + 2048;
     int rc = CRBM_OK;
     rc = rc ? rc : p->alloc(&p->bonds, bonds.size());
+    rc = rc ? rc : p->alloc(&p->bond_tab, bonds.size() * (size_t)n_hidden);
     rc = rc ? rc : p->alloc(&p->w.scal, 32);
     rc = rc ? rc : p->alloc(&p->w.Om, P);
     rc = rc ? rc : p->alloc(&p->w.Om16, P);

@@ -21,6 +21,7 @@ struct Geometry {
     const int2* bonds;      // device [n_bonds]
     int kind, Lx;           // for site positions (f_q phases)
     double J;
+    float4* bond_tab;       // device [n_bonds][M] workspace: (cosh 2D, sinh 2D), D = W_i - W_j of one RBM
 };
 
 // ---------------------------------------------------------------- init

@@ -239,21 +239,18 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __rest
         acc = cadd(acc, cscale(d0, 0.25f * J * (float)(si * sj)));
         if (si == sj) continue;
         const float m2si = -2.f * (float)si;
-        const float2* Wi = pe.W + (long)i * M;
-        const float2* Wj = pe.W + (long)j * M;
+        // Delta_k = -2 s_i D_k with D = W_i - W_j: cosh Delta = cosh 2D, sinh Delta = -s_i sinh 2D,
+        // both read from the bond's table
+        const float4* tab = g.bond_tab + (long)bnd * M;
+        const float nsi = -(float)si;
         float2 prod = make_float2(1.f, 0.f);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = e * kWave + lane;
             if (k < M) {
-                const float2 d = cscale(csub(Wi[k], Wj[k]), m2si);     // Delta_k
-                const float ex = expf(d.x), emx = 1.f / ex;
-                float sn, cs;
-                sincosf(d.y, &sn, &cs);
-                const float chx = 0.5f * (ex + emx), shx = 0.5f * (ex - emx);
-                const float2 chd = make_float2(chx * cs, shx * sn);
-                const float2 shd = make_float2(shx * cs, chx * sn);
-                prod = cmul(prod, cadd(chd, cmul(TE[e], shd)));
+                const float4 q = tab[k];
+                const float2 ts = cmul(TE[e], make_float2(q.z, q.w));
+                prod = cmul(prod, make_float2(fmaf(nsi, ts.x, q.x), fmaf(nsi, ts.y, q.y)));
             }
         }
         float2 lg = make_float2(0.5f * logf(prod.x * prod.x + prod.y * prod.y), atan2f(prod.y, prod.x));
@@ -303,8 +300,31 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __rest
     if (lane == 0) A.R_out[s] = R;
 }
 
+// tab[b][k] = (cosh 2D, sinh 2D) with D = W_ik - W_jk for bond b = (i, j); the difference of two
+// binary32 values is exact in binary64, and the functions are evaluated there before rounding
+__global__ __launch_bounds__(256) void k_bond_table(const int2* __restrict__ bonds, int nb, int M,
+                                                    const float2* __restrict__ W, float4* __restrict__ tab) {
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= (long)nb * M) return;
+    const int b = (int)(idx / M), k = (int)(idx % M);
+    const int2 ij = bonds[b];
+    const float2 wi = W[(long)ij.x * M + k], wj = W[(long)ij.y * M + k];
+    const double x = 2.0 * ((double)wi.x - (double)wj.x), y = 2.0 * ((double)wi.y - (double)wj.y);
+    const double ch = cosh(x), sh = sinh(x);
+    double sn, cs;
+    sincos(y, &sn, &cs);
+    tab[idx] = make_float4((float)(ch * cs), (float)(sh * sn), (float)(sh * cs), (float)(ch * sn));
+}
+
 hipError_t launch_local_core(const LocalArgs& A, const float2* th1, const float2* thn, const float2* thm,
                              hipStream_t stream) {
+    if (A.eloc_out || A.R_out) {
+        // the bond factors of the RBM whose Hamiltonian action is taken
+        const float2* W = A.cheb_mode ? A.psn.W : A.fit.W;
+        const long cnt = (long)A.g.n_bonds * A.g.M;
+        hipLaunchKernelGGL(k_bond_table, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, A.g.bonds,
+                           A.g.n_bonds, A.g.M, W, A.g.bond_tab);
+    }
     const int E = (A.g.M + kWave - 1) / kWave;
     const dim3 grid((unsigned)((A.n_samples + 3) / 4)), block(256);
     switch (E) {

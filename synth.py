@@ -50,6 +50,8 @@ CHAIN40 = Workload("chain40_alpha2", 0, 40, 1, 80, 1024, 256, 1, 1e-3, param_see
 SQUARE10 = Workload("square10x10_alpha4", 1, 10, 10, 400, 4096, 128, 1, 1e-4, param_seed=1003, chain_seed=2003)
 SQUARE8 = Workload("square8x8_alpha2_batched", 1, 8, 8, 128, 0, 16, 1, 1e-4, param_seed=1004, chain_seed=2004)
 SQUARE16 = Workload("square16x16_alpha2_grad", 1, 16, 16, 512, 8192, 64, 1, 0.0, param_seed=1005, chain_seed=2005)
+# The 6 x 6 lattice of the paper's two-dimensional results, for the symmetry-projected moment correction.
+SQUARE6 = Workload("square6x6_alpha2_symmetry", 1, 6, 6, 72, 1024, 64, 1, 1e-4, param_seed=1006, chain_seed=2006)
 
 # Ground-state energy scales used only to fix the Chebyshev window when the
 # lattice is too large for exact diagonalisation: Hulthen's infinite-chain
