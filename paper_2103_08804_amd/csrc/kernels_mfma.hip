@@ -1,22 +1,30 @@
 // Dense S = <O^* O> - <O>^* <O> (Sec. III) on the matrix cores.
 //
-// The log-derivatives are a Khatri-Rao product: over the extended index
-// (i, j), i in [0, N], j in [0, M] (sigma~_N = 1, T~_M = 1),
-// O_(i,j)(s) = sigma~_si T~_sj.  A row tile of the output is 4 extended sites
-// x 32 extended hidden units, so one workgroup streams only the T values of
-// 32 + 32 hidden units and the sign masks of 4 + 4 sites per sample and
-// synthesises the 128 + 128 operand rows by XOR-ing the sign into the
-// floating-point operands (sigma = +-1 is exact in any format).
+// The log-derivatives are a Khatri-Rao product: with sigma~_N = 1 and the
+// extended sites i in [0, N], the W and b parameters are the rows (i, j),
+// j in [0, M), with O_(i,j)(s) = sigma~_si T_sj (i = N gives O_b = T), and the
+// a parameters are the rows i < N with O_a = sigma_i.
 //
-// Operands are packed K-major (sample index fastest): Tr/Ti planes [Mp][ns]
-// and sign masks [Np][ns].  Each workgroup (4 waves) owns a 128 x 128
-// complex tile pair (u <= u') and accumulates, per wave, a 64 x 64 complex
-// block as 4 real products (RR + II -> Re, RI - IR -> Im) in FP32 with
+// Main kernel (W and b rows).  A row tile is 8 extended sites x 16 hidden
+// units = 128 rows, made of four 32-row matrix-core fragments of 2 sites x 16
+// hidden units each; N + 1 sites and M hidden units are padded only to
+// multiples of 8 and 16.  A workgroup streams, per sample, the T values of
+// 16 + 16 hidden units and the sign masks of 8 + 8 sites and synthesises the
+// 128 + 128 operand rows by XOR-ing the sign bit into the floating-point T
+// (sigma = +-1 is exact in any format).  Each workgroup (4 waves) owns a
+// 128 x 128 complex tile pair (u <= u') and accumulates, per wave, a 64 x 64
+// complex block as 4 real products (RR + II -> Re, RI - IR -> Im) in FP32 with
 //   v_mfma_f32_32x32x16_bf16   (BF16 operands), or
 //   v_mfma_f32_32x32x2f32      (FP32 operands).
-// K tiles of 64 samples are double-buffered through LDS.  The epilogue
-// scales by 1/n, subtracts <O_k>^* <O_k'>, maps (i, j) to the parameter
-// index and writes the tile and its conjugate transpose.
+// K tiles of samples are double-buffered through LDS.
+//
+// Border kernel (a rows).  The a rows are real (sigma_i), so a block of 128 of
+// them against a W/b tile needs 2 real products (sigma x sigma' T_re,
+// sigma x sigma' T_im), and against a block of a rows only one.  Their operand
+// is the sign XOR-ed into the sample-weight row (1, or 0 for padded samples).
+//
+// Both epilogues scale by 1/n, subtract <O_k>^* <O_k'>, map the row to the
+// parameter index and write the block and its conjugate transpose.
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -31,16 +39,34 @@ typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(int)))) int i32x4;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
 
-constexpr int MK_TI = 4;        // extended sites per row tile
-constexpr int MK_TJ = 32;       // extended hidden units per row tile
+constexpr int MK_TS = 8;        // extended sites per W/b row tile
+constexpr int MK_TH = 16;       // hidden units per W/b row tile
+constexpr int MK_AB = 128;      // a rows per border block
 #ifndef CRBM_MK_KT
 #define CRBM_MK_KT 128
 #endif
-constexpr int MK_KT = CRBM_MK_KT;   // samples per LDS K tile
+constexpr int MK_KT = CRBM_MK_KT;   // samples per LDS K tile (BF16 main kernel)
+
+struct SbGeom {
+    int N, M;
+    long P;
+    int nSB, nHB;       // site blocks of 8 (over N + 1 extended sites), hidden blocks of 16
+    int Np, Mp;         // padded plane heights: 8 nSB mask rows, 16 nHB T rows
+};
+static SbGeom sb_geom(int N, int M) {
+    SbGeom g;
+    g.N = N; g.M = M; g.P = (long)N + M + (long)N * M;
+    g.nSB = (N + 1 + MK_TS - 1) / MK_TS;
+    g.nHB = (M + MK_TH - 1) / MK_TH;
+    g.Np = g.nSB * MK_TS;
+    g.Mp = g.nHB * MK_TH;
+    return g;
+}
 
 // ------------------------------------------------------------------ packing
-// planes: Tr[jj][s], Ti[jj][s] for jj < Mp (jj == M -> 1 + 0i, jj > M -> 0), s < ns_pad (s >= n -> 0)
-// masks:  Sm[ii][s] = sign bit of sigma_si (ii < N), 0 for ii >= N
+// planes: Tr[j][s], Ti[j][s] for j < Mp (j >= M -> 0), s < ns_pad (s >= n -> 0)
+// masks:  Sm[i][s] = sign bit of sigma_si (i < N), 0 for i >= N (sigma~_N = 1 and padding);
+//         row Np holds the sample weights of the a rows: 1 for s < n, 0 for the padded samples
 template <typename E>
 __global__ __launch_bounds__(256) void k_pack_t(const float2* __restrict__ T, long n, int M, int Mp, long ns_pad,
                                                 E* __restrict__ Tr, E* __restrict__ Ti) {
@@ -51,9 +77,7 @@ __global__ __launch_bounds__(256) void k_pack_t(const float2* __restrict__ T, lo
     for (int r = ty; r < 64; r += 4) {
         const long s = s0 + r;
         const int j = j0 + tx;
-        float2 v = make_float2(0.f, 0.f);
-        if (s < n) v = (j < M) ? T[s * M + j] : (j == M ? make_float2(1.f, 0.f) : v);
-        tile[r][tx] = v;
+        tile[r][tx] = (s < n && j < M) ? T[s * M + j] : make_float2(0.f, 0.f);
     }
     __syncthreads();
     for (int r = ty; r < 64; r += 4) {
@@ -79,18 +103,19 @@ template <typename E>
 __global__ __launch_bounds__(256) void k_pack_sig(const int8_t* __restrict__ sig, long n, int N, int Np, long ns_pad,
                                                   E* __restrict__ Sm) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (long)Np * ns_pad) return;
+    if (idx >= (long)(Np + 1) * ns_pad) return;
     const int i = (int)(idx / ns_pad);
     const long s = idx % ns_pad;
     E m = 0;
-    if (i < N && s < n && sig[s * N + i] < 0) m = (E)(sizeof(E) == 2 ? 0x8000u : 0x80000000u);
+    if (i == Np) m = (s < n) ? (E)(sizeof(E) == 2 ? 0x3F80u : 0x3F800000u) : (E)0;
+    else if (i < N && s < n && sig[s * N + i] < 0) m = (E)(sizeof(E) == 2 ? 0x8000u : 0x80000000u);
     Sm[idx] = m;
 }
 
-// ------------------------------------------------------------------ S tiles
-__device__ __forceinline__ long ext_to_p(int i, int j, int N, int M) {
-    if (i > N || j > M || (i == N && j == M)) return -1;
-    if (j == M) return i;
+// ------------------------------------------------------------------ parameter index of a row
+// W/b row (extended site i, hidden j): W_ij for i < N, b_j for i = N; -1 for padding
+__device__ __forceinline__ long wb_to_p(int i, int j, int N, int M) {
+    if (i > N || j >= M) return -1;
     if (i == N) return (long)N + j;
     return (long)N + M + (long)i * M + j;
 }
@@ -103,17 +128,28 @@ struct Pol<true> {
     using E = uint16_t;
     static constexpr int kPerLane = 8;     // K values per lane per MFMA
     static constexpr int kStep = 16;       // samples per MFMA
+    static constexpr uint32_t kOne = 0x3F80u;
 };
 template <>
 struct Pol<false> {
     using E = uint32_t;
     static constexpr int kPerLane = 1;
     static constexpr int kStep = 2;
+    static constexpr uint32_t kOne = 0x3F800000u;
 };
 
+// 16-byte global -> LDS staging of a list of plane rows, through registers
+template <int ROWS, int KT, typename E>
+struct Stager {
+    static constexpr int CHUNK = 16;
+    static constexpr int CH_PER_ROW = KT * (int)sizeof(E) / CHUNK;
+    static constexpr int TOTAL = ROWS * CH_PER_ROW;
+    static constexpr int PER_THREAD = (TOTAL + 255) / 256;
+};
+
+// ------------------------------------------------------------------ main kernel: W/b tile pairs
 template <bool BF16>
-__global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, int nJ, const int2* __restrict__ order,
-                                                        long ns_pad,
+__global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* __restrict__ order, long ns_pad,
                                                         const typename Pol<BF16>::E* __restrict__ Tr,
                                                         const typename Pol<BF16>::E* __restrict__ Ti,
                                                         const typename Pol<BF16>::E* __restrict__ Sm,
@@ -121,28 +157,25 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, in
                                                         float2* __restrict__ S) {
     using E = typename Pol<BF16>::E;
     constexpr int KT = BF16 ? MK_KT : 64;          // samples per LDS K tile of this precision
-    // bytes per LDS row, padded so that the 32 rows of a fragment read fall in distinct banks
+    // bytes per LDS row, padded so that the 16 rows of a fragment read fall in distinct banks
     constexpr int ROWB = KT * (int)sizeof(E) + (BF16 ? 16 : 4);
-    constexpr int PLANE = MK_TJ * ROWB;                    // one [32][64] plane
-    constexpr int MASKS = 2 * MK_TI * ROWB;                // 8 mask rows
-    constexpr int STAGE = 4 * PLANE + MASKS;
+    // stage rows: [0,16) Tr(A) [16,32) Ti(A) [32,48) Tr(B) [48,64) Ti(B) [64,72) masks(A) [72,80) masks(B)
+    constexpr int ROWS = 80;
+    constexpr int STAGE = ROWS * ROWB;
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
+    using St = Stager<ROWS, KT, E>;
 
     // tile pair (u, u'), u <= u', from the dispatch-order table (entries < 0 are padding)
     const int2 pr = order[blockIdx.x];
     if (pr.x < 0) return;
-    const long u = pr.x, up = pr.y;
-    const int I = (int)(u / nJ), J = (int)(u % nJ);
-    const int Ip = (int)(up / nJ), Jp = (int)(up % nJ);
+    const int u = pr.x, up = pr.y;
+    const int sbA = u / gm.nHB, hbA = u % gm.nHB;
+    const int sbB = up / gm.nHB, hbB = up % gm.nHB;
+    const int N = gm.N, M = gm.M;
+    const long P = gm.P;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wi = wave >> 1, wj = wave & 1;
-
-    // global -> LDS assignment: 4 planes of 32 rows x (64 samples) + 8 mask rows
-    constexpr int CHUNK = 16;                               // bytes per load
-    constexpr int CH_PER_ROW = KT * (int)sizeof(E) / CHUNK;
-    const E* plane_src[4] = {Tr + (long)(J * MK_TJ) * ns_pad, Ti + (long)(J * MK_TJ) * ns_pad,
-                             Tr + (long)(Jp * MK_TJ) * ns_pad, Ti + (long)(Jp * MK_TJ) * ns_pad};
 
     floatx16 acc_re[2][2], acc_im[2][2];
 #pragma unroll
@@ -152,51 +185,38 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, in
 #pragma unroll
             for (int v = 0; v < 16; ++v) { acc_re[a][b][v] = 0.f; acc_im[a][b][v] = 0.f; }
 
-    const long n_kt = ns_pad / KT;
-    constexpr int PLANE_CHUNKS = MK_TJ * CH_PER_ROW;        // chunks per plane
-    constexpr int TOTAL_CHUNKS = 4 * PLANE_CHUNKS + 2 * MK_TI * CH_PER_ROW;
-    constexpr int PER_THREAD = (TOTAL_CHUNKS + 255) / 256;
-    i32x4 stage_regs[PER_THREAD];
-
+    i32x4 stage_regs[St::PER_THREAD];
+    auto src_row = [&](int row) -> const E* {
+        if (row < 64) {
+            const int pl = row >> 4, r = row & 15;
+            const E* plane = (pl & 1) ? Ti : Tr;
+            const int hb = (pl < 2) ? hbA : hbB;
+            return plane + (long)(hb * MK_TH + r) * ns_pad;
+        }
+        const int m = row - 64;                      // mask row 0..15
+        const int site = (m < MK_TS) ? sbA * MK_TS + m : sbB * MK_TS + (m - MK_TS);
+        return Sm + (long)site * ns_pad;
+    };
     auto gload = [&](long kt) {
 #pragma unroll
-        for (int q = 0; q < PER_THREAD; ++q) {
+        for (int q = 0; q < St::PER_THREAD; ++q) {
             const int c = tid + q * 256;
             i32x4 v = {0, 0, 0, 0};
-            if (c < TOTAL_CHUNKS) {
-                const long s_off = kt * KT;
-                if (c < 4 * PLANE_CHUNKS) {
-                    const int pl = c / PLANE_CHUNKS, rc = c % PLANE_CHUNKS;
-                    const int row = rc / CH_PER_ROW, ch = rc % CH_PER_ROW;
-                    const E* src = plane_src[pl] + (long)row * ns_pad + s_off + ch * (CHUNK / (int)sizeof(E));
-                    v = *reinterpret_cast<const i32x4*>(src);
-                } else {
-                    const int mc = c - 4 * PLANE_CHUNKS;
-                    const int row = mc / CH_PER_ROW, ch = mc % CH_PER_ROW;    // row 0..7
-                    const int site = (row < MK_TI) ? I * MK_TI + row : Ip * MK_TI + (row - MK_TI);
-                    const E* src = Sm + (long)site * ns_pad + s_off + ch * (CHUNK / (int)sizeof(E));
-                    v = *reinterpret_cast<const i32x4*>(src);
-                }
+            if (c < St::TOTAL) {
+                const int row = c / St::CH_PER_ROW, ch = c % St::CH_PER_ROW;
+                const E* src = src_row(row) + kt * KT + ch * (St::CHUNK / (int)sizeof(E));
+                v = *reinterpret_cast<const i32x4*>(src);
             }
             stage_regs[q] = v;
         }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-        for (int q = 0; q < PER_THREAD; ++q) {
+        for (int q = 0; q < St::PER_THREAD; ++q) {
             const int c = tid + q * 256;
-            if (c >= TOTAL_CHUNKS) continue;
-            unsigned char* base = lds + buf * STAGE;
-            unsigned char* dst;
-            if (c < 4 * PLANE_CHUNKS) {
-                const int pl = c / PLANE_CHUNKS, rc = c % PLANE_CHUNKS;
-                const int row = rc / CH_PER_ROW, ch = rc % CH_PER_ROW;
-                dst = base + pl * PLANE + row * ROWB + ch * CHUNK;
-            } else {
-                const int mc = c - 4 * PLANE_CHUNKS;
-                const int row = mc / CH_PER_ROW, ch = mc % CH_PER_ROW;
-                dst = base + 4 * PLANE + row * ROWB + ch * CHUNK;
-            }
+            if (c >= St::TOTAL) continue;
+            const int row = c / St::CH_PER_ROW, ch = c % St::CH_PER_ROW;
+            unsigned char* dst = lds + buf * STAGE + row * ROWB + ch * St::CHUNK;
             if constexpr (BF16) {
                 *reinterpret_cast<i32x4*>(dst) = stage_regs[q];
             } else {
@@ -210,7 +230,10 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, in
     lstore(0);
     __syncthreads();
 
-    const int lrow = lane & 31, lhalf = lane >> 5;
+    // fragment rows: lane row q = lane % 32 is (site 2f + q / 16, hidden q % 16) of fragment f
+    const int q = lane & 31, lhalf = lane >> 5;
+    const int trow = q & 15, qs = q >> 4;
+    const long n_kt = ns_pad / KT;
     for (long kt = 0; kt < n_kt; ++kt) {
         const int buf = (int)(kt & 1);
         if (kt + 1 < n_kt) gload(kt + 1);
@@ -219,15 +242,15 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, in
         for (int ks = 0; ks < KT; ks += Pol<BF16>::kStep) {
             const int koff = (ks + Pol<BF16>::kPerLane * lhalf) * (int)sizeof(E);
             if constexpr (BF16) {
-                const i32x4 trA = *reinterpret_cast<const i32x4*>(base + 0 * PLANE + lrow * ROWB + koff);
-                const i32x4 tiA = *reinterpret_cast<const i32x4*>(base + 1 * PLANE + lrow * ROWB + koff);
-                const i32x4 trB = *reinterpret_cast<const i32x4*>(base + 2 * PLANE + lrow * ROWB + koff);
-                const i32x4 tiB = *reinterpret_cast<const i32x4*>(base + 3 * PLANE + lrow * ROWB + koff);
+                const i32x4 trA = *reinterpret_cast<const i32x4*>(base + (0 + trow) * ROWB + koff);
+                const i32x4 tiA = *reinterpret_cast<const i32x4*>(base + (16 + trow) * ROWB + koff);
+                const i32x4 trB = *reinterpret_cast<const i32x4*>(base + (32 + trow) * ROWB + koff);
+                const i32x4 tiB = *reinterpret_cast<const i32x4*>(base + (48 + trow) * ROWB + koff);
                 i32x4 mA[2], mB[2];
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
-                    mA[a] = *reinterpret_cast<const i32x4*>(base + 4 * PLANE + (2 * wi + a) * ROWB + koff);
-                    mB[a] = *reinterpret_cast<const i32x4*>(base + 4 * PLANE + (MK_TI + 2 * wj + a) * ROWB + koff);
+                    mA[a] = *reinterpret_cast<const i32x4*>(base + (64 + 2 * (2 * wi + a) + qs) * ROWB + koff);
+                    mB[a] = *reinterpret_cast<const i32x4*>(base + (72 + 2 * (2 * wj + a) + qs) * ROWB + koff);
                 }
                 const i32x4 neg = {(int)0x80008000, (int)0x80008000, (int)0x80008000, (int)0x80008000};
                 i32x4 ar[2], ai[2], br[2], bi[2], nbr[2];
@@ -260,15 +283,15 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, in
                             (bf16x8)ai[a], (bf16x8)nbr[b], acc_im[a][b], 0, 0, 0);
                     }
             } else {
-                const uint32_t trA = *reinterpret_cast<const uint32_t*>(base + 0 * PLANE + lrow * ROWB + koff);
-                const uint32_t tiA = *reinterpret_cast<const uint32_t*>(base + 1 * PLANE + lrow * ROWB + koff);
-                const uint32_t trB = *reinterpret_cast<const uint32_t*>(base + 2 * PLANE + lrow * ROWB + koff);
-                const uint32_t tiB = *reinterpret_cast<const uint32_t*>(base + 3 * PLANE + lrow * ROWB + koff);
+                const uint32_t trA = *reinterpret_cast<const uint32_t*>(base + (0 + trow) * ROWB + koff);
+                const uint32_t tiA = *reinterpret_cast<const uint32_t*>(base + (16 + trow) * ROWB + koff);
+                const uint32_t trB = *reinterpret_cast<const uint32_t*>(base + (32 + trow) * ROWB + koff);
+                const uint32_t tiB = *reinterpret_cast<const uint32_t*>(base + (48 + trow) * ROWB + koff);
                 uint32_t mA[2], mB[2];
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
-                    mA[a] = *reinterpret_cast<const uint32_t*>(base + 4 * PLANE + (2 * wi + a) * ROWB + koff);
-                    mB[a] = *reinterpret_cast<const uint32_t*>(base + 4 * PLANE + (MK_TI + 2 * wj + a) * ROWB + koff);
+                    mA[a] = *reinterpret_cast<const uint32_t*>(base + (64 + 2 * (2 * wi + a) + qs) * ROWB + koff);
+                    mB[a] = *reinterpret_cast<const uint32_t*>(base + (72 + 2 * (2 * wj + a) + qs) * ROWB + koff);
                 }
 #pragma unroll
                 for (int a = 0; a < 2; ++a) {
@@ -284,32 +307,235 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, in
                 }
             }
         }
-        if (kt + 1 < n_kt) {
-            lstore(buf ^ 1);
-        }
+        if (kt + 1 < n_kt) lstore(buf ^ 1);
         __syncthreads();
     }
 
-    // epilogue
+    // epilogue: accumulator element v of lane l is row 8(v/4) + 4(l/32) + v%4 of the A fragment
+    // and column l % 32 of the B fragment
     const bool diag = (u == up);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-        const int i = I * MK_TI + 2 * wi + a;
+        const int fA = 2 * wi + a;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            const int ip = Ip * MK_TI + 2 * wj + b;
-            const int jp = Jp * MK_TJ + (lane & 31);
-            const long kp = ext_to_p(ip, jp, N, M);
+            const int fB = 2 * wj + b;
+            const int qB = lane & 31;
+            const long kp = wb_to_p(sbB * MK_TS + 2 * fB + (qB >> 4), hbB * MK_TH + (qB & 15), N, M);
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
-                const int j = J * MK_TJ + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const long k = ext_to_p(i, j, N, M);
+                const int qA = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const long k = wb_to_p(sbA * MK_TS + 2 * fA + (qA >> 4), hbA * MK_TH + (qA & 15), N, M);
                 if (k < 0 || kp < 0) continue;
-                const double2 ok = Om[k], okp = Om[kp];
-                const double2 mm = zconjmul(ok, okp);
+                const double2 mm = zconjmul(Om[k], Om[kp]);
                 float2 val = make_float2((float)((double)(acc_re[a][b][v] * inv_n) - mm.x),
                                          (float)((double)(acc_im[a][b][v] * inv_n) - mm.y));
                 if (k == kp) val.y = 0.f;     // S is Hermitian: its diagonal is real
+                S[k * P + kp] = val;
+                if (!diag) S[kp * P + k] = cconj(val);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ border kernel: a rows
+// Workgroup x: a-row block ab = x / nX (rows: sites 128 ab + r) against column set y = x % nX:
+// y < nW the W/b tile y, else the a-row block y - nW (blocks with y - nW < ab are skipped).
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_sbuild_border(SbGeom gm, long ns_pad, int nA,
+                                                       const typename Pol<BF16>::E* __restrict__ Tr,
+                                                       const typename Pol<BF16>::E* __restrict__ Ti,
+                                                       const typename Pol<BF16>::E* __restrict__ Sm,
+                                                       const double2* __restrict__ Om, float inv_n,
+                                                       float2* __restrict__ S) {
+    using E = typename Pol<BF16>::E;
+    constexpr int KT = BF16 ? 64 : 32;
+    constexpr int ROWB = KT * (int)sizeof(E) + (BF16 ? 16 : 4);
+    // stage rows: [0,128) masks of the a rows; [128,256) the columns: a-row masks, or
+    // Tr(16) Ti(16) masks(8) of a W/b tile; 256: the sample weights (1, 0 past n)
+    constexpr int ROWS = 257;
+    constexpr int STAGE = ROWS * ROWB;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
+    using St = Stager<ROWS, KT, E>;
+    constexpr uint32_t ONE = Pol<BF16>::kOne;
+
+    const int nW = gm.nSB * gm.nHB;
+    const int nX = nW + nA;
+    const int ab = blockIdx.x / nX, y = blockIdx.x % nX;
+    const bool colA = y >= nW;
+    if (colA && y - nW < ab) return;
+    const int abB = y - nW;
+    const int sbB = colA ? 0 : y / gm.nHB, hbB = colA ? 0 : y % gm.nHB;
+    const int N = gm.N, M = gm.M;
+    const long P = gm.P;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wi = wave >> 1, wj = wave & 1;
+    floatx16 acc_re[2][2], acc_im[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) { acc_re[a][b][v] = 0.f; acc_im[a][b][v] = 0.f; }
+
+    i32x4 stage_regs[St::PER_THREAD];
+    // source row of stage row `row`, or nullptr for a row of zeros (sites past the mask planes)
+    auto src_row = [&](int row) -> const E* {
+        if (row == 256) return Sm + (long)gm.Np * ns_pad;
+        if (row < 128) {
+            const int site = MK_AB * ab + row;
+            return site < gm.Np ? Sm + (long)site * ns_pad : nullptr;
+        }
+        const int r = row - 128;
+        if (colA) {
+            const int site = MK_AB * abB + r;
+            return site < gm.Np ? Sm + (long)site * ns_pad : nullptr;
+        }
+        if (r < 32) return ((r < 16) ? Tr : Ti) + (long)(hbB * MK_TH + (r & 15)) * ns_pad;
+        if (r < 40) return Sm + (long)(sbB * MK_TS + (r - 32)) * ns_pad;
+        return nullptr;
+    };
+    auto gload = [&](long kt) {
+#pragma unroll
+        for (int qq = 0; qq < St::PER_THREAD; ++qq) {
+            const int c = tid + qq * 256;
+            i32x4 v = {0, 0, 0, 0};
+            if (c < St::TOTAL) {
+                const int row = c / St::CH_PER_ROW, ch = c % St::CH_PER_ROW;
+                const E* s = src_row(row);
+                if (s) v = *reinterpret_cast<const i32x4*>(s + kt * KT + ch * (St::CHUNK / (int)sizeof(E)));
+            }
+            stage_regs[qq] = v;
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int qq = 0; qq < St::PER_THREAD; ++qq) {
+            const int c = tid + qq * 256;
+            if (c >= St::TOTAL) continue;
+            const int row = c / St::CH_PER_ROW, ch = c % St::CH_PER_ROW;
+            unsigned char* dst = lds + buf * STAGE + row * ROWB + ch * St::CHUNK;
+            if constexpr (BF16) {
+                *reinterpret_cast<i32x4*>(dst) = stage_regs[qq];
+            } else {
+#pragma unroll
+                for (int w4 = 0; w4 < 4; ++w4) reinterpret_cast<int*>(dst)[w4] = stage_regs[qq][w4];
+            }
+        }
+    };
+
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    const int q = lane & 31, lhalf = lane >> 5;
+    const int trow = q & 15, qs = q >> 4;
+    const long n_kt = ns_pad / KT;
+    for (long kt = 0; kt < n_kt; ++kt) {
+        const int buf = (int)(kt & 1);
+        if (kt + 1 < n_kt) gload(kt + 1);
+        const unsigned char* base = lds + buf * STAGE;
+#pragma unroll
+        for (int ks = 0; ks < KT; ks += Pol<BF16>::kStep) {
+            const int koff = (ks + Pol<BF16>::kPerLane * lhalf) * (int)sizeof(E);
+            if constexpr (BF16) {
+                const i32x4 one = {(int)(ONE | (ONE << 16)), (int)(ONE | (ONE << 16)), (int)(ONE | (ONE << 16)),
+                                   (int)(ONE | (ONE << 16))};
+                const i32x4 wrow = *reinterpret_cast<const i32x4*>(base + 256 * ROWB + koff);
+                i32x4 a_op[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+                    a_op[a] = wrow ^ *reinterpret_cast<const i32x4*>(base + (32 * (2 * wi + a) + q) * ROWB + koff);
+                if (colA) {
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        const i32x4 b_op =
+                            one ^ *reinterpret_cast<const i32x4*>(base + (128 + 32 * (2 * wj + b) + q) * ROWB + koff);
+#pragma unroll
+                        for (int a = 0; a < 2; ++a)
+                            acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16((bf16x8)a_op[a], (bf16x8)b_op,
+                                                                                  acc_re[a][b], 0, 0, 0);
+                    }
+                } else {
+                    const i32x4 trB = *reinterpret_cast<const i32x4*>(base + (128 + trow) * ROWB + koff);
+                    const i32x4 tiB = *reinterpret_cast<const i32x4*>(base + (144 + trow) * ROWB + koff);
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        const i32x4 mB =
+                            *reinterpret_cast<const i32x4*>(base + (160 + 2 * (2 * wj + b) + qs) * ROWB + koff);
+                        const i32x4 br = trB ^ mB, bi = tiB ^ mB;
+#pragma unroll
+                        for (int a = 0; a < 2; ++a) {
+                            acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16((bf16x8)a_op[a], (bf16x8)br,
+                                                                                  acc_re[a][b], 0, 0, 0);
+                            acc_im[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16((bf16x8)a_op[a], (bf16x8)bi,
+                                                                                  acc_im[a][b], 0, 0, 0);
+                        }
+                    }
+                }
+            } else {
+                const uint32_t wrow = *reinterpret_cast<const uint32_t*>(base + 256 * ROWB + koff);
+                float a_op[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+                    a_op[a] = __uint_as_float(wrow ^ *reinterpret_cast<const uint32_t*>(
+                                                         base + (32 * (2 * wi + a) + q) * ROWB + koff));
+                if (colA) {
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        const float b_op = __uint_as_float(
+                            ONE ^ *reinterpret_cast<const uint32_t*>(base + (128 + 32 * (2 * wj + b) + q) * ROWB + koff));
+#pragma unroll
+                        for (int a = 0; a < 2; ++a)
+                            acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[a], b_op, acc_re[a][b], 0, 0, 0);
+                    }
+                } else {
+                    const uint32_t trB = *reinterpret_cast<const uint32_t*>(base + (128 + trow) * ROWB + koff);
+                    const uint32_t tiB = *reinterpret_cast<const uint32_t*>(base + (144 + trow) * ROWB + koff);
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        const uint32_t mB =
+                            *reinterpret_cast<const uint32_t*>(base + (160 + 2 * (2 * wj + b) + qs) * ROWB + koff);
+                        const float br = __uint_as_float(trB ^ mB), bi = __uint_as_float(tiB ^ mB);
+#pragma unroll
+                        for (int a = 0; a < 2; ++a) {
+                            acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[a], br, acc_re[a][b], 0, 0, 0);
+                            acc_im[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[a], bi, acc_im[a][b], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+        if (kt + 1 < n_kt) lstore(buf ^ 1);
+        __syncthreads();
+    }
+
+    // epilogue: row = a parameter (site 128 ab + 32 fA + qA); column = W/b row or a parameter
+    const bool diag = colA && abB == ab;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int fA = 2 * wi + a;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int fB = 2 * wj + b;
+            const int qB = lane & 31;
+            long kp;
+            if (colA) {
+                const int site = MK_AB * abB + 32 * fB + qB;
+                kp = site < N ? site : -1;
+            } else {
+                kp = wb_to_p(sbB * MK_TS + 2 * fB + (qB >> 4), hbB * MK_TH + (qB & 15), N, M);
+            }
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int qA = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int siteA = MK_AB * ab + 32 * fA + qA;
+                const long k = siteA < N ? siteA : -1;
+                if (k < 0 || kp < 0) continue;
+                const double2 mm = zconjmul(Om[k], Om[kp]);
+                float2 val = make_float2((float)((double)(acc_re[a][b][v] * inv_n) - mm.x),
+                                         (float)((double)(acc_im[a][b][v] * inv_n) - mm.y));
+                if (k == kp) val.y = 0.f;
                 S[k * P + kp] = val;
                 if (!diag) S[kp * P + k] = cconj(val);
             }
@@ -321,58 +547,49 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(int N, int M, long P, in
 hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n, const double2* Om,
                               float2* S, int prec, void* pack, size_t pack_bytes, const int2* order, long n_order,
                               Profiler* prof, hipStream_t stream) {
-    const int Mp = ((M + 1 + MK_TJ - 1) / MK_TJ) * MK_TJ;
-    const int Np = ((N + 1 + MK_TI - 1) / MK_TI) * MK_TI;
+    const SbGeom gm = sb_geom(N, M);
+    (void)P;
     const long ns_pad = ((n + MK_KT - 1) / MK_KT) * MK_KT;
-    const int nJ = Mp / MK_TJ, nI = Np / MK_TI;
     static_assert(MK_KT % 64 == 0, "the packing grid assumes 64-sample blocks");
-    (void)nI;
-    const long pairs = n_order;
     const bool bf16 = (prec == CRBM_PREC_BF16);
     const size_t esz = bf16 ? 2 : 4;
-    const size_t need = esz * ((size_t)2 * Mp * ns_pad + (size_t)Np * ns_pad);
+    const size_t need = esz * ((size_t)2 * gm.Mp * ns_pad + (size_t)(gm.Np + 1) * ns_pad);
     if (need > pack_bytes) return hipErrorOutOfMemory;
     const float inv_n = 1.0f / (float)n;
-    dim3 gt((unsigned)(ns_pad / 64), (unsigned)((Mp + 63) / 64));
-    const long ms = (long)Np * ns_pad;
-    if (bf16) {
-        uint16_t* Tr = static_cast<uint16_t*>(pack);
-        uint16_t* Ti = Tr + (size_t)Mp * ns_pad;
-        uint16_t* Sm = Ti + (size_t)Mp * ns_pad;
+    const dim3 gt((unsigned)(ns_pad / 64), (unsigned)((gm.Mp + 63) / 64));
+    const long ms = (long)(gm.Np + 1) * ns_pad;
+    const int nA = (N + MK_AB - 1) / MK_AB;
+    const int nX = gm.nSB * gm.nHB + nA;
+    auto run = [&](auto tag) {
+        using E = typename decltype(tag)::E;
+        constexpr bool B16 = sizeof(E) == 2;
+        E* Tr = static_cast<E*>(pack);
+        E* Ti = Tr + (size_t)gm.Mp * ns_pad;
+        E* Sm = Ti + (size_t)gm.Mp * ns_pad;
         prof->begin(PROF_PACK, stream);
-        hipLaunchKernelGGL(k_pack_t<uint16_t>, gt, dim3(256), 0, stream, T, n, M, Mp, ns_pad, Tr, Ti);
-        hipLaunchKernelGGL(k_pack_sig<uint16_t>, dim3((unsigned)((ms + 255) / 256)), dim3(256), 0, stream, sig, n, N,
-                           Np, ns_pad, Sm);
+        hipLaunchKernelGGL(k_pack_t<E>, gt, dim3(256), 0, stream, T, n, M, gm.Mp, ns_pad, Tr, Ti);
+        hipLaunchKernelGGL(k_pack_sig<E>, dim3((unsigned)((ms + 255) / 256)), dim3(256), 0, stream, sig, n, N, gm.Np,
+                           ns_pad, Sm);
         prof->end(stream);
         prof->begin(PROF_SBUILD, stream);
-        hipLaunchKernelGGL(k_sbuild_mfma<true>, dim3((unsigned)pairs), dim3(256), 0, stream, N, M, P, nJ, order,
-                           ns_pad, Tr, Ti, Sm, Om, inv_n, S);
+        hipLaunchKernelGGL(k_sbuild_mfma<B16>, dim3((unsigned)n_order), dim3(256), 0, stream, gm, order, ns_pad, Tr, Ti,
+                           Sm, Om, inv_n, S);
+        hipLaunchKernelGGL(k_sbuild_border<B16>, dim3((unsigned)(nA * nX)), dim3(256), 0, stream, gm, ns_pad, nA, Tr,
+                           Ti, Sm, Om, inv_n, S);
         prof->end(stream);
-    } else {
-        uint32_t* Tr = static_cast<uint32_t*>(pack);
-        uint32_t* Ti = Tr + (size_t)Mp * ns_pad;
-        uint32_t* Sm = Ti + (size_t)Mp * ns_pad;
-        prof->begin(PROF_PACK, stream);
-        hipLaunchKernelGGL(k_pack_t<uint32_t>, gt, dim3(256), 0, stream, T, n, M, Mp, ns_pad, Tr, Ti);
-        hipLaunchKernelGGL(k_pack_sig<uint32_t>, dim3((unsigned)((ms + 255) / 256)), dim3(256), 0, stream, sig, n, N,
-                           Np, ns_pad, Sm);
-        prof->end(stream);
-        prof->begin(PROF_SBUILD, stream);
-        hipLaunchKernelGGL(k_sbuild_mfma<false>, dim3((unsigned)pairs), dim3(256), 0, stream, N, M, P, nJ, order,
-                           ns_pad, Tr, Ti, Sm, Om, inv_n, S);
-        prof->end(stream);
-    }
+    };
+    if (bf16) run(Pol<true>{});
+    else run(Pol<false>{});
     return hipGetLastError();
 }
 
-// Dispatch order of the tile pairs (u <= u').  Workgroup b runs on XCD b % n_xcd (round-robin
+// Dispatch order of the W/b tile pairs (u <= u').  Workgroup b runs on XCD b % n_xcd (round-robin
 // dispatch), so the pairs are grouped into g x g super-tiles, super-tiles are dealt to the XCDs in
 // turn, and each XCD's list is interleaved into the grid: the workgroups one XCD runs together
 // then share few operand slabs, which stay in that XCD's L2.  Padding entries are (-1, -1).
 std::vector<int2> sbuild_order(int N, int M, int n_xcd, int g) {
-    const int Mp = ((M + 1 + MK_TJ - 1) / MK_TJ) * MK_TJ;
-    const int Np = ((N + 1 + MK_TI - 1) / MK_TI) * MK_TI;
-    const int nt = (Np / MK_TI) * (Mp / MK_TJ);
+    const SbGeom gm = sb_geom(N, M);
+    const int nt = gm.nSB * gm.nHB;
     const int ns = (nt + g - 1) / g;
     std::vector<std::vector<int2>> per(n_xcd);
     int st = 0;
@@ -394,10 +611,9 @@ std::vector<int2> sbuild_order(int N, int M, int n_xcd, int g) {
 }
 
 size_t sbuild_pack_bytes(int N, int M, long max_samples) {
-    const size_t Mp = ((M + 1 + MK_TJ - 1) / MK_TJ) * MK_TJ;
-    const size_t Np = ((N + 1 + MK_TI - 1) / MK_TI) * MK_TI;
+    const SbGeom gm = sb_geom(N, M);
     const size_t ns_pad = ((max_samples + MK_KT - 1) / MK_KT) * MK_KT;
-    return 4 * (2 * Mp * ns_pad + Np * ns_pad);
+    return 4 * (2 * (size_t)gm.Mp * ns_pad + (size_t)(gm.Np + 1) * ns_pad);
 }
 
 }  // namespace crbm
