@@ -173,14 +173,19 @@ def main():
     if "sbuild" in prof and solver == crbm.CG_DENSE:
         c, t = prof["sbuild"]
         avg_s = t / c / 1e3
-        flops = 4.0 * P * (P + 1) * ns          # 8 real flops per complex MAC, P(P+1)/2 entries
+        # the kernel builds the rows and columns of b and W (R = M + N M of the P parameters):
+        # R(R+1)/2 complex entries x N_s samples x 8 real flops; the N rows of a are the border kernel's
+        R_rows = P - N
+        flops = 4.0 * R_rows * (R_rows + 1) * ns
         peak = BF16_PEAK_TFLOPS if prec == crbm.BF16 else FP32_MATRIX_PEAK_TFLOPS
         achieved = flops / avg_s / 1e12
         traffic = measured_traffic() if (prec == crbm.BF16 and C == wl.chains and sweeps == wl.sweeps) else None
+        esz = 2 if prec == crbm.BF16 else 4
         roof = {"kernel": "k_sbuild_mfma", "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": traffic, "algorithmic_flops": flops,
-                "algorithmic_bytes": 2 * ((M + 1 + 31) // 32 * 32) * ns * 2 + ((N + 1 + 3) // 4 * 4) * ns * 2
-                + 8 * P * P}
+                # each operand read once (T re and im of M units, N + 1 sign rows) and both triangles written
+                "algorithmic_bytes": (2 * M + N + 1) * ns * esz + 8 * R_rows * R_rows,
+                "note": "rows of b and W (R = P - N); the N rows of a run in k_sbuild_border (phase 'sborder')"}
     else:
         c, t = prof["ot"]
         avg_s = t / c / 1e3

@@ -34,7 +34,7 @@ EXPORTS = ("crbm_plan_create", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_la
            "crbm_batched_autotune", "crbm_moment_matrices", "crbm_corrected_moments", "crbm_lanczos",
            "crbm_spectrum_kpm", "crbm_spectrum_cf", "crbm_probe_mfma", "crbm_probe_hbm",
            "crbm_sym_matrices")
-PROF_NAMES = ("sample", "theta", "local", "ot", "sbuild", "cg", "moment", "pack", "cholesky", "batched", "gram")
+PROF_NAMES = ("sample", "theta", "local", "ot", "sbuild", "cg", "moment", "pack", "cholesky", "batched", "gram", "sborder")
 
 
 class CrbmError(RuntimeError):

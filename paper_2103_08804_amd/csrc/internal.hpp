@@ -110,7 +110,7 @@ struct SrWork {
 
 // instrumentation group ids (mirrors CRBM_PROF_* of the public header)
 enum { PROF_SAMPLE = 0, PROF_THETA, PROF_LOCAL, PROF_OT, PROF_SBUILD, PROF_CG, PROF_MOMENT, PROF_PACK, PROF_CHOLESKY,
-       PROF_BATCHED, PROF_GRAM, PROF_COUNT };
+       PROF_BATCHED, PROF_GRAM, PROF_SBORDER, PROF_COUNT };
 
 struct SrArgs {
     int N, M, P;

@@ -574,6 +574,8 @@ hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const flo
         prof->begin(PROF_SBUILD, stream);
         hipLaunchKernelGGL(k_sbuild_mfma<B16>, dim3((unsigned)n_order), dim3(256), 0, stream, gm, order, ns_pad, Tr, Ti,
                            Sm, Om, inv_n, S);
+        prof->end(stream);
+        prof->begin(PROF_SBORDER, stream);
         hipLaunchKernelGGL(k_sbuild_border<B16>, dim3((unsigned)(nA * nX)), dim3(256), 0, stream, gm, ns_pad, nA, Tr,
                            Ti, Sm, Om, inv_n, S);
         prof->end(stream);
