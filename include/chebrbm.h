@@ -68,7 +68,9 @@ enum { CRBM_PREC_FP32 = 0, CRBM_PREC_BF16 = 1 };
 
 /* plan flags */
 #define CRBM_PLAN_DENSE_S 1    /* reserve the dense P x P complex64 matrix S and the packed operands of
-                                  its matrix-core contraction (needed by CG_DENSE) */
+                                  its matrix-core contraction (needed by CG_DENSE); for small P also up to
+                                  min(8, 2^30 / (8 P^2)) more P x P slices, so that the contraction can be
+                                  split over samples when its tile pairs alone cannot fill the device */
 #define CRBM_PLAN_CHOLESKY 2   /* also reserve a P x P complex128 factor (CHOLESKY; needs P <= 4000) */
 
 /* workspace buffers readable through crbm_plan_buffer (device pointers) */

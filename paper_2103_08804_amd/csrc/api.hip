@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -62,6 +63,8 @@ constexpr int kQChunk = 8;
 constexpr int kMomBlocks = 256;
 constexpr int kMaxMomentEntries = 4096;   // n_q * (n_max + 1)
 constexpr int kMaxBasis = 256;             // K = n_max + 1 of the moment-correction matrices
+constexpr long kSplitBytes = 1L << 30;     // bound of the split-contraction buffer
+constexpr long kMaxSplits = 8;
 constexpr int kXcds = 8;                   // accelerator complex dies of the MI355X (round-robin dispatch)
 #ifndef CRBM_SUPERTILE
 #define CRBM_SUPERTILE 8
@@ -302,6 +305,13 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
         rc = rc ? rc : p->alloc(&d_order, order.size());
         p->w.sb_order = d_order;
         p->w.sb_order_len = (long)order.size();
+        // buffer of a contraction split over samples when the tile pairs alone cannot fill the device
+        const long slice = P * P * (long)sizeof(float2);
+        const long nsm = std::min<long>(kMaxSplits, kSplitBytes / slice);
+        if (!rc && nsm >= 2) {
+            rc = p->alloc(&p->w.spart, (size_t)(nsm * P * P));
+            p->w.nsplit_max = (int)nsm;
+        }
     }
     p->w.prof = &p->prof;
     if (rc) { delete p; return rc; }
@@ -310,6 +320,7 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
         p->n_cu = 256;
     p->b_waves = 4;
     p->b_blocks = 4 * p->n_cu;
+    p->w.n_cu = p->n_cu;
     e = hipMemcpy(p->bonds, bonds.data(), bonds.size() * sizeof(int2), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->w.scal, 0, 32 * sizeof(double));
     if (e == hipSuccess && !order.empty())

@@ -105,6 +105,9 @@ struct SrWork {
     size_t pack_bytes;
     const int2* sb_order;     // dispatch order of its tile pairs
     long sb_order_len;
+    float2* spart;            // [nsplit_max][P][P] partial sums of a contraction split over samples (or null)
+    int nsplit_max;
+    int n_cu;
     Profiler* prof;
 };
 

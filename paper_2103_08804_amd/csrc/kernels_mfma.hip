@@ -24,7 +24,11 @@
 // is the sign XOR-ed into the sample-weight row (1, or 0 for padded samples).
 //
 // Both epilogues scale by 1/n, subtract <O_k>^* <O_k'>, map the row to the
-// parameter index and write the block and its conjugate transpose.
+// parameter index and write the block and its conjugate transpose.  When the
+// tile pairs are too few to fill the device (small P), the sample range is
+// split over `nsplit` workgroups per pair: each writes its raw sums to its own
+// P x P slice, and a reduction adds the slices in split order (deterministic)
+// before scaling and subtracting the means.
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -148,8 +152,11 @@ struct Stager {
 };
 
 // ------------------------------------------------------------------ main kernel: W/b tile pairs
+// Split mode (nsplit > 1): workgroup x handles tile pair x % n_order over the K tiles of split
+// x / n_order and writes the raw sums into S + split * P * P (no scaling, no means).
 template <bool BF16>
-__global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* __restrict__ order, long ns_pad,
+__global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* __restrict__ order, long n_order,
+                                                        long ns_pad, int nsplit,
                                                         const typename Pol<BF16>::E* __restrict__ Tr,
                                                         const typename Pol<BF16>::E* __restrict__ Ti,
                                                         const typename Pol<BF16>::E* __restrict__ Sm,
@@ -166,7 +173,8 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
     using St = Stager<ROWS, KT, E>;
 
     // tile pair (u, u'), u <= u', from the dispatch-order table (entries < 0 are padding)
-    const int2 pr = order[blockIdx.x];
+    const int split = (int)(blockIdx.x / n_order);
+    const int2 pr = order[blockIdx.x % n_order];
     if (pr.x < 0) return;
     const int u = pr.x, up = pr.y;
     const int sbA = u / gm.nHB, hbA = u % gm.nHB;
@@ -226,17 +234,23 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
         }
     };
 
-    gload(0);
-    lstore(0);
+    // this workgroup's K tiles [kt0, kt1)
+    const long n_kt_all = ns_pad / KT;
+    const long per = (n_kt_all + nsplit - 1) / nsplit;
+    const long kt0 = split * per;
+    const long kt1 = kt0 + per < n_kt_all ? kt0 + per : n_kt_all;
+    if (kt0 < kt1) {
+        gload(kt0);
+        lstore(0);
+    }
     __syncthreads();
 
     // fragment rows: lane row q = lane % 32 is (site 2f + q / 16, hidden q % 16) of fragment f
     const int q = lane & 31, lhalf = lane >> 5;
     const int trow = q & 15, qs = q >> 4;
-    const long n_kt = ns_pad / KT;
-    for (long kt = 0; kt < n_kt; ++kt) {
-        const int buf = (int)(kt & 1);
-        if (kt + 1 < n_kt) gload(kt + 1);
+    for (long kt = kt0; kt < kt1; ++kt) {
+        const int buf = (int)((kt - kt0) & 1);
+        if (kt + 1 < kt1) gload(kt + 1);
         const unsigned char* base = lds + buf * STAGE;
 #pragma unroll
         for (int ks = 0; ks < KT; ks += Pol<BF16>::kStep) {
@@ -307,13 +321,15 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
                 }
             }
         }
-        if (kt + 1 < n_kt) lstore(buf ^ 1);
+        if (kt + 1 < kt1) lstore(buf ^ 1);
         __syncthreads();
     }
 
     // epilogue: accumulator element v of lane l is row 8(v/4) + 4(l/32) + v%4 of the A fragment
     // and column l % 32 of the B fragment
     const bool diag = (u == up);
+    const bool raw = nsplit > 1;
+    float2* out = S + (raw ? (long)split * P * P : 0L);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         const int fA = 2 * wi + a;
@@ -327,12 +343,17 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
                 const int qA = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                 const long k = wb_to_p(sbA * MK_TS + 2 * fA + (qA >> 4), hbA * MK_TH + (qA & 15), N, M);
                 if (k < 0 || kp < 0) continue;
-                const double2 mm = zconjmul(Om[k], Om[kp]);
-                float2 val = make_float2((float)((double)(acc_re[a][b][v] * inv_n) - mm.x),
-                                         (float)((double)(acc_im[a][b][v] * inv_n) - mm.y));
-                if (k == kp) val.y = 0.f;     // S is Hermitian: its diagonal is real
-                S[k * P + kp] = val;
-                if (!diag) S[kp * P + k] = cconj(val);
+                float2 val;
+                if (raw) {
+                    val = make_float2(acc_re[a][b][v], acc_im[a][b][v]);
+                } else {
+                    const double2 mm = zconjmul(Om[k], Om[kp]);
+                    val = make_float2((float)((double)(acc_re[a][b][v] * inv_n) - mm.x),
+                                      (float)((double)(acc_im[a][b][v] * inv_n) - mm.y));
+                    if (k == kp) val.y = 0.f;     // S is Hermitian: its diagonal is real
+                }
+                out[k * P + kp] = val;
+                if (!diag) out[kp * P + k] = cconj(val);
             }
         }
     }
@@ -342,7 +363,7 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
 // Workgroup x: a-row block ab = x / nX (rows: sites 128 ab + r) against column set y = x % nX:
 // y < nW the W/b tile y, else the a-row block y - nW (blocks with y - nW < ab are skipped).
 template <bool BF16>
-__global__ __launch_bounds__(256) void k_sbuild_border(SbGeom gm, long ns_pad, int nA,
+__global__ __launch_bounds__(256, 2) void k_sbuild_border(SbGeom gm, long ns_pad, int nA, int nsplit,
                                                        const typename Pol<BF16>::E* __restrict__ Tr,
                                                        const typename Pol<BF16>::E* __restrict__ Ti,
                                                        const typename Pol<BF16>::E* __restrict__ Sm,
@@ -352,16 +373,15 @@ __global__ __launch_bounds__(256) void k_sbuild_border(SbGeom gm, long ns_pad, i
     constexpr int KT = BF16 ? 64 : 32;
     constexpr int ROWB = KT * (int)sizeof(E) + (BF16 ? 16 : 4);
     // stage rows: [0,128) masks of the a rows; [128,256) the columns: a-row masks, or
-    // Tr(16) Ti(16) masks(8) of a W/b tile; 256: the sample weights (1, 0 past n)
-    constexpr int ROWS = 257;
+    // Tr(16) Ti(16) masks(8) of a W/b tile; 256: the sample weights (1, 0 past n); 257: zeros
+    constexpr int ROWS = 258;
     constexpr int STAGE = ROWS * ROWB;
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
     using St = Stager<ROWS, KT, E>;
-    constexpr uint32_t ONE = Pol<BF16>::kOne;
-
     const int nW = gm.nSB * gm.nHB;
     const int nX = nW + nA;
-    const int ab = blockIdx.x / nX, y = blockIdx.x % nX;
+    const int split = (int)(blockIdx.x / (nA * nX));
+    const int ab = (blockIdx.x % (nA * nX)) / nX, y = blockIdx.x % nX;
     const bool colA = y >= nW;
     if (colA && y - nW < ab) return;
     const int abB = y - nW;
@@ -383,6 +403,7 @@ __global__ __launch_bounds__(256) void k_sbuild_border(SbGeom gm, long ns_pad, i
     // source row of stage row `row`, or nullptr for a row of zeros (sites past the mask planes)
     auto src_row = [&](int row) -> const E* {
         if (row == 256) return Sm + (long)gm.Np * ns_pad;
+        if (row > 256) return nullptr;
         if (row < 128) {
             const int site = MK_AB * ab + row;
             return site < gm.Np ? Sm + (long)site * ns_pad : nullptr;
@@ -425,93 +446,78 @@ __global__ __launch_bounds__(256) void k_sbuild_border(SbGeom gm, long ns_pad, i
         }
     };
 
-    gload(0);
-    lstore(0);
+    const long n_kt_all = ns_pad / KT;
+    const long per = (n_kt_all + nsplit - 1) / nsplit;
+    const long kt0 = split * per;
+    const long kt1 = kt0 + per < n_kt_all ? kt0 + per : n_kt_all;
+    if (kt0 < kt1) {
+        gload(kt0);
+        lstore(0);
+    }
     __syncthreads();
     const int q = lane & 31, lhalf = lane >> 5;
-    const int trow = q & 15, qs = q >> 4;
-    const long n_kt = ns_pad / KT;
-    for (long kt = 0; kt < n_kt; ++kt) {
-        const int buf = (int)(kt & 1);
-        if (kt + 1 < n_kt) gload(kt + 1);
+    // per-lane LDS rows of the operands.  A: the a-row masks XOR the sample-weight row.  B: a W/b
+    // fragment (T row q % 16, mask row 2 f + q / 16), or a block of a rows (T = the weight row,
+    // Ti = the zero row, mask row 32 f + q); so one branch-free pair of products serves both.
+    const int rA0 = 32 * (2 * wi + 0) + q, rA1 = 32 * (2 * wi + 1) + q;
+    const int rTr = colA ? 256 : 128 + (q & 15);
+    const int rTi = colA ? 257 : 144 + (q & 15);
+    const int rB0 = colA ? 128 + 32 * (2 * wj + 0) + q : 160 + 2 * (2 * wj + 0) + (q >> 4);
+    const int rB1 = colA ? 128 + 32 * (2 * wj + 1) + q : 160 + 2 * (2 * wj + 1) + (q >> 4);
+    for (long kt = kt0; kt < kt1; ++kt) {
+        const int buf = (int)((kt - kt0) & 1);
+        if (kt + 1 < kt1) gload(kt + 1);
         const unsigned char* base = lds + buf * STAGE;
 #pragma unroll
         for (int ks = 0; ks < KT; ks += Pol<BF16>::kStep) {
             const int koff = (ks + Pol<BF16>::kPerLane * lhalf) * (int)sizeof(E);
             if constexpr (BF16) {
-                const i32x4 one = {(int)(ONE | (ONE << 16)), (int)(ONE | (ONE << 16)), (int)(ONE | (ONE << 16)),
-                                   (int)(ONE | (ONE << 16))};
                 const i32x4 wrow = *reinterpret_cast<const i32x4*>(base + 256 * ROWB + koff);
-                i32x4 a_op[2];
+                const i32x4 a_op[2] = {wrow ^ *reinterpret_cast<const i32x4*>(base + rA0 * ROWB + koff),
+                                       wrow ^ *reinterpret_cast<const i32x4*>(base + rA1 * ROWB + koff)};
+                const i32x4 trB = *reinterpret_cast<const i32x4*>(base + rTr * ROWB + koff);
+                const i32x4 tiB = *reinterpret_cast<const i32x4*>(base + rTi * ROWB + koff);
+                const i32x4 mB[2] = {*reinterpret_cast<const i32x4*>(base + rB0 * ROWB + koff),
+                                     *reinterpret_cast<const i32x4*>(base + rB1 * ROWB + koff)};
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
-                    a_op[a] = wrow ^ *reinterpret_cast<const i32x4*>(base + (32 * (2 * wi + a) + q) * ROWB + koff);
-                if (colA) {
+                for (int b = 0; b < 2; ++b) {
+                    const i32x4 br = trB ^ mB[b], bi = tiB ^ mB[b];
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-                        const i32x4 b_op =
-                            one ^ *reinterpret_cast<const i32x4*>(base + (128 + 32 * (2 * wj + b) + q) * ROWB + koff);
-#pragma unroll
-                        for (int a = 0; a < 2; ++a)
-                            acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16((bf16x8)a_op[a], (bf16x8)b_op,
-                                                                                  acc_re[a][b], 0, 0, 0);
-                    }
-                } else {
-                    const i32x4 trB = *reinterpret_cast<const i32x4*>(base + (128 + trow) * ROWB + koff);
-                    const i32x4 tiB = *reinterpret_cast<const i32x4*>(base + (144 + trow) * ROWB + koff);
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-                        const i32x4 mB =
-                            *reinterpret_cast<const i32x4*>(base + (160 + 2 * (2 * wj + b) + qs) * ROWB + koff);
-                        const i32x4 br = trB ^ mB, bi = tiB ^ mB;
-#pragma unroll
-                        for (int a = 0; a < 2; ++a) {
-                            acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16((bf16x8)a_op[a], (bf16x8)br,
-                                                                                  acc_re[a][b], 0, 0, 0);
-                            acc_im[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16((bf16x8)a_op[a], (bf16x8)bi,
-                                                                                  acc_im[a][b], 0, 0, 0);
-                        }
+                    for (int a = 0; a < 2; ++a) {
+                        acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16((bf16x8)a_op[a], (bf16x8)br,
+                                                                              acc_re[a][b], 0, 0, 0);
+                        acc_im[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16((bf16x8)a_op[a], (bf16x8)bi,
+                                                                              acc_im[a][b], 0, 0, 0);
                     }
                 }
             } else {
                 const uint32_t wrow = *reinterpret_cast<const uint32_t*>(base + 256 * ROWB + koff);
-                float a_op[2];
+                const float a_op[2] = {
+                    __uint_as_float(wrow ^ *reinterpret_cast<const uint32_t*>(base + rA0 * ROWB + koff)),
+                    __uint_as_float(wrow ^ *reinterpret_cast<const uint32_t*>(base + rA1 * ROWB + koff))};
+                const uint32_t trB = *reinterpret_cast<const uint32_t*>(base + rTr * ROWB + koff);
+                const uint32_t tiB = *reinterpret_cast<const uint32_t*>(base + rTi * ROWB + koff);
+                const uint32_t mB[2] = {*reinterpret_cast<const uint32_t*>(base + rB0 * ROWB + koff),
+                                        *reinterpret_cast<const uint32_t*>(base + rB1 * ROWB + koff)};
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
-                    a_op[a] = __uint_as_float(wrow ^ *reinterpret_cast<const uint32_t*>(
-                                                         base + (32 * (2 * wi + a) + q) * ROWB + koff));
-                if (colA) {
+                for (int b = 0; b < 2; ++b) {
+                    const float br = __uint_as_float(trB ^ mB[b]), bi = __uint_as_float(tiB ^ mB[b]);
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-                        const float b_op = __uint_as_float(
-                            ONE ^ *reinterpret_cast<const uint32_t*>(base + (128 + 32 * (2 * wj + b) + q) * ROWB + koff));
-#pragma unroll
-                        for (int a = 0; a < 2; ++a)
-                            acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[a], b_op, acc_re[a][b], 0, 0, 0);
-                    }
-                } else {
-                    const uint32_t trB = *reinterpret_cast<const uint32_t*>(base + (128 + trow) * ROWB + koff);
-                    const uint32_t tiB = *reinterpret_cast<const uint32_t*>(base + (144 + trow) * ROWB + koff);
-#pragma unroll
-                    for (int b = 0; b < 2; ++b) {
-                        const uint32_t mB =
-                            *reinterpret_cast<const uint32_t*>(base + (160 + 2 * (2 * wj + b) + qs) * ROWB + koff);
-                        const float br = __uint_as_float(trB ^ mB), bi = __uint_as_float(tiB ^ mB);
-#pragma unroll
-                        for (int a = 0; a < 2; ++a) {
-                            acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[a], br, acc_re[a][b], 0, 0, 0);
-                            acc_im[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[a], bi, acc_im[a][b], 0, 0, 0);
-                        }
+                    for (int a = 0; a < 2; ++a) {
+                        acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[a], br, acc_re[a][b], 0, 0, 0);
+                        acc_im[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(a_op[a], bi, acc_im[a][b], 0, 0, 0);
                     }
                 }
             }
         }
-        if (kt + 1 < n_kt) lstore(buf ^ 1);
+        if (kt + 1 < kt1) lstore(buf ^ 1);
         __syncthreads();
     }
 
     // epilogue: row = a parameter (site 128 ab + 32 fA + qA); column = W/b row or a parameter
     const bool diag = colA && abB == ab;
+    const bool raw = nsplit > 1;
+    float2* out = S + (raw ? (long)split * P * P : 0L);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         const int fA = 2 * wi + a;
@@ -532,23 +538,60 @@ __global__ __launch_bounds__(256) void k_sbuild_border(SbGeom gm, long ns_pad, i
                 const int siteA = MK_AB * ab + 32 * fA + qA;
                 const long k = siteA < N ? siteA : -1;
                 if (k < 0 || kp < 0) continue;
-                const double2 mm = zconjmul(Om[k], Om[kp]);
-                float2 val = make_float2((float)((double)(acc_re[a][b][v] * inv_n) - mm.x),
-                                         (float)((double)(acc_im[a][b][v] * inv_n) - mm.y));
-                if (k == kp) val.y = 0.f;
-                S[k * P + kp] = val;
-                if (!diag) S[kp * P + k] = cconj(val);
+                float2 val;
+                if (raw) {
+                    val = make_float2(acc_re[a][b][v], acc_im[a][b][v]);
+                } else {
+                    const double2 mm = zconjmul(Om[k], Om[kp]);
+                    val = make_float2((float)((double)(acc_re[a][b][v] * inv_n) - mm.x),
+                                      (float)((double)(acc_im[a][b][v] * inv_n) - mm.y));
+                    if (k == kp) val.y = 0.f;
+                }
+                out[k * P + kp] = val;
+                if (!diag) out[kp * P + k] = cconj(val);
             }
         }
     }
 }
 
+// S = (sum over the split slices, in split order, in double) / n - <O_k>^* <O_k'>, real diagonal
+__global__ __launch_bounds__(256) void k_sbuild_reduce(long P, int nsplit, const float2* __restrict__ part,
+                                                       const double2* __restrict__ Om, double inv_n,
+                                                       float2* __restrict__ S) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= P * P) return;
+    const long k = e / P, kp = e % P;
+    double x = 0.0, y = 0.0;
+    for (int s = 0; s < nsplit; ++s) {
+        const float2 v = part[(long)s * P * P + e];
+        x += (double)v.x;
+        y += (double)v.y;
+    }
+    const double2 mm = zconjmul(Om[k], Om[kp]);
+    S[e] = make_float2((float)(x * inv_n - mm.x), k == kp ? 0.f : (float)(y * inv_n - mm.y));
+}
+
+// Number of sample splits for a contraction of n samples: about eight workgroups per compute unit
+// (four rounds of two resident ones), at least 4 K tiles per split, and no more slices than the
+// plan's split buffer holds.
+int sbuild_splits(int N, int M, long n, int n_cu, int max_splits) {
+    const SbGeom gm = sb_geom(N, M);
+    const long nW = (long)gm.nSB * gm.nHB;
+    const int nA = (N + MK_AB - 1) / MK_AB;
+    const long wgs = nW * (nW + 1) / 2 + (long)nA * (nW + nA);
+    const long n_kt = ((n + MK_KT - 1) / MK_KT * MK_KT) / 64;    // the finest K tile of any variant is 64
+    long s = (8L * n_cu + wgs - 1) / wgs;
+    if (s > n_kt / 4) s = n_kt / 4;
+    if (s > max_splits) s = max_splits;
+    return s < 1 ? 1 : (int)s;
+}
+
 // ------------------------------------------------------------------ launcher
 hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n, const double2* Om,
                               float2* S, int prec, void* pack, size_t pack_bytes, const int2* order, long n_order,
-                              Profiler* prof, hipStream_t stream) {
+                              float2* split_buf, int nsplit, Profiler* prof, hipStream_t stream) {
     const SbGeom gm = sb_geom(N, M);
-    (void)P;
+    if (nsplit > 1 && !split_buf) return hipErrorInvalidValue;
     const long ns_pad = ((n + MK_KT - 1) / MK_KT) * MK_KT;
     static_assert(MK_KT % 64 == 0, "the packing grid assumes 64-sample blocks");
     const bool bf16 = (prec == CRBM_PREC_BF16);
@@ -571,13 +614,17 @@ hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const flo
         hipLaunchKernelGGL(k_pack_sig<E>, dim3((unsigned)((ms + 255) / 256)), dim3(256), 0, stream, sig, n, N, gm.Np,
                            ns_pad, Sm);
         prof->end(stream);
+        float2* out = nsplit > 1 ? split_buf : S;
         prof->begin(PROF_SBUILD, stream);
-        hipLaunchKernelGGL(k_sbuild_mfma<B16>, dim3((unsigned)n_order), dim3(256), 0, stream, gm, order, ns_pad, Tr, Ti,
-                           Sm, Om, inv_n, S);
+        hipLaunchKernelGGL(k_sbuild_mfma<B16>, dim3((unsigned)(n_order * nsplit)), dim3(256), 0, stream, gm, order,
+                           n_order, ns_pad, nsplit, Tr, Ti, Sm, Om, inv_n, out);
         prof->end(stream);
         prof->begin(PROF_SBORDER, stream);
-        hipLaunchKernelGGL(k_sbuild_border<B16>, dim3((unsigned)(nA * nX)), dim3(256), 0, stream, gm, ns_pad, nA, Tr,
-                           Ti, Sm, Om, inv_n, S);
+        hipLaunchKernelGGL(k_sbuild_border<B16>, dim3((unsigned)(nA * nX * nsplit)), dim3(256), 0, stream, gm, ns_pad,
+                           nA, nsplit, Tr, Ti, Sm, Om, inv_n, out);
+        if (nsplit > 1)
+            hipLaunchKernelGGL(k_sbuild_reduce, dim3((unsigned)((P * P + 255) / 256)), dim3(256), 0, stream, P, nsplit,
+                               split_buf, Om, 1.0 / (double)n, S);
         prof->end(stream);
     };
     if (bf16) run(Pol<true>{});

@@ -593,7 +593,8 @@ hipError_t launch_cholesky_solve(long P, const float2* S, double eps, const doub
                                  double* sc, hipStream_t stream);
 hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n, const double2* Om,
                               float2* S, int prec, void* pack, size_t pack_bytes, const int2* order, long n_order,
-                              Profiler* prof, hipStream_t stream);
+                              float2* split_buf, int nsplit, Profiler* prof, hipStream_t stream);
+int sbuild_splits(int N, int M, long n, int n_cu, int max_splits);
 
 static hipError_t apply_op(const SrArgs& A, const SrWork& W, const double2* v, double2* y, hipStream_t stream) {
     const long P = A.P;
@@ -651,8 +652,9 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
                 if (e != hipSuccess) return e;
                 om_s = W.Om16;
             }
+            const int nsplit = W.spart ? sbuild_splits(A.N, A.M, A.n, W.n_cu, W.nsplit_max) : 1;
             e = launch_sbuild_mfma(A.N, A.M, P, A.samples, A.T, A.n, om_s, W.S, A.prec, W.pack, W.pack_bytes,
-                                   W.sb_order, W.sb_order_len, W.prof, stream);
+                                   W.sb_order, W.sb_order_len, W.spart, nsplit, W.prof, stream);
         } else {
             // weighted (enumeration) sums: FP32 contraction on the vector units
             const int nt = (int)((P + SB_T - 1) / SB_T);
