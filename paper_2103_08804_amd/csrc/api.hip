@@ -58,7 +58,6 @@ using namespace crbm;
 namespace {
 constexpr int kMaxN = 256;
 constexpr int kMaxM = 512;
-constexpr long kCholMaxP = 4000;
 constexpr int kQChunk = 8;
 constexpr int kMomBlocks = 256;
 constexpr int kMaxMomentEntries = 4096;   // n_q * (n_max + 1)

@@ -130,6 +130,9 @@ struct SrArgs {
     double* stats;                     // device [8]
     int mode;                          // 0: Chebyshev fit (R = target ratio); 1: energy (R = E_loc, dgamma = -lr)
 };
+// the dense solve keeps the solution vector in LDS: P <= kCholMaxP (64 000 bytes of complex128)
+constexpr long kCholMaxP = 4000;
+
 hipError_t launch_sr_step(const SrArgs& args, const SrWork& w, hipStream_t stream);
 
 // ---------------------------------------------------------------- batched moments

@@ -1,7 +1,17 @@
 // Dense Hermitian positive-definite solve (S + eps I) x = F in double precision
-// by a left-looking Cholesky factorisation L L^H followed by two triangular
-// solves.  Used for the natural-gradient system of Sec. III when P is a few
-// thousand (the factorisation costs P^3/3 complex multiply-adds).
+// by a Cholesky factorisation L L^H followed by two triangular solves.  Used for
+// the natural-gradient system of Sec. III when P is a few thousand (the
+// factorisation costs P^3/3 complex multiply-adds).
+//
+// Right-looking and blocked in panels of CH_NB = 64 columns, per panel k:
+//   1. the diagonal block A_kk is factored in LDS by one workgroup;
+//   2. the rows below solve L_ik L_kk^H = A_ik, one wave per row (the lanes hold
+//      the 64 unknowns of the row, the substitution runs along the columns);
+//   3. the trailing lower triangle is updated, A_ij -= L_ik L_jk^H (i >= j), in
+//      32 x 32 output tiles with both 32 x 64 panels staged in LDS.
+// The triangular solves run by blocks of 64 rows in one workgroup: the
+// off-diagonal products are spread over all threads, the 64 x 64 diagonal
+// substitutions over one wave.  Everything is in double, in a fixed order.
 #include "../../include/chebrbm.h"
 #include "device.hpp"
 #include "internal.hpp"
@@ -9,7 +19,12 @@
 namespace crbm {
 
 enum { SC_FLAGS_SLOT = 15 };   // must match the scalar layout of the step driver
-constexpr long kCholMaxP = 4000;  // the triangular solves keep x in LDS (16 B per entry, < 64 KB)
+constexpr int CH_NB = 64;      // panel width
+constexpr int CH_T = 32;       // trailing-update tile
+
+__device__ __forceinline__ bool chol_failed(const double* sc) {
+    return ((int)sc[SC_FLAGS_SLOT] & CRBM_FLAG_CHOLESKY_FAIL) != 0;
+}
 
 // A64 = S + eps I (lower triangle used)
 __global__ __launch_bounds__(256) void k_chol_load(long P, const float2* __restrict__ S, double eps,
@@ -21,93 +36,218 @@ __global__ __launch_bounds__(256) void k_chol_load(long P, const float2* __restr
     A[idx] = make_double2((double)v.x + (i == j ? eps : 0.0), (double)v.y);
 }
 
-// diagonal of column j: L_jj = sqrt(A_jj - sum_{k<j} |L_jk|^2)   (one wave)
-__global__ __launch_bounds__(64) void k_chol_diag(long P, long j, double2* __restrict__ A, double* __restrict__ sc) {
-    if ((int)sc[SC_FLAGS_SLOT] & CRBM_FLAG_CHOLESKY_FAIL) return;
-    const int lane = threadIdx.x;
-    const double2* row = A + j * P;
-    double acc = 0.0;
-    for (long k = lane; k < j; k += 64) acc += row[k].x * row[k].x + row[k].y * row[k].y;
-    acc = wave_sum(acc);
-    if (lane == 0) {
-        const double d = A[j * P + j].x - acc;
-        if (!(d > 0.0) || !isfinite(d)) {
-            sc[SC_FLAGS_SLOT] = (double)((int)sc[SC_FLAGS_SLOT] | CRBM_FLAG_CHOLESKY_FAIL);
-            return;
+// 1. L_kk of the diagonal block [k0, k0 + nb)^2 in LDS (one workgroup of 256 threads)
+__global__ __launch_bounds__(256) void k_chol_diagblock(long P, long k0, int nb, double2* __restrict__ A,
+                                                        double* __restrict__ sc) {
+    __shared__ double2 L[CH_NB][CH_NB + 1];
+    __shared__ int fail;
+    if (chol_failed(sc)) return;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < nb * nb; e += 256) {
+        const int i = e / nb, j = e % nb;
+        L[i][j] = (j <= i) ? A[(k0 + i) * P + k0 + j] : make_double2(0.0, 0.0);
+    }
+    if (tid == 0) fail = 0;
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        if (tid == 0) {
+            const double d = L[j][j].x;
+            if (!(d > 0.0) || !isfinite(d)) fail = 1;
+            else L[j][j] = make_double2(sqrt(d), 0.0);
         }
-        A[j * P + j] = make_double2(sqrt(d), 0.0);
+        __syncthreads();
+        if (fail) break;
+        const double inv = 1.0 / L[j][j].x;
+        for (int i = j + 1 + tid; i < nb; i += 256) L[i][j] = make_double2(L[i][j].x * inv, L[i][j].y * inv);
+        __syncthreads();
+        const int m = nb - j - 1;
+        for (int e = tid; e < m * m; e += 256) {
+            const int i = j + 1 + e / m, l = j + 1 + e % m;
+            if (l <= i) {
+                const double2 a = L[i][j], b = L[l][j];        // L_il -= L_ij conj(L_lj)
+                L[i][l].x -= a.x * b.x + a.y * b.y;
+                L[i][l].y -= a.y * b.x - a.x * b.y;
+            }
+        }
+        __syncthreads();
+    }
+    if (fail) {
+        if (tid == 0) sc[SC_FLAGS_SLOT] = (double)((int)sc[SC_FLAGS_SLOT] | CRBM_FLAG_CHOLESKY_FAIL);
+        return;
+    }
+    for (int e = tid; e < nb * nb; e += 256) {
+        const int i = e / nb, j = e % nb;
+        if (j <= i) A[(k0 + i) * P + k0 + j] = L[i][j];
     }
 }
 
-// rows i > j: L_ij = (A_ij - sum_{k<j} L_ik conj(L_jk)) / L_jj   (one wave per row)
-__global__ __launch_bounds__(256) void k_chol_col(long P, long j, double2* __restrict__ A, const double* __restrict__ sc) {
-    if ((int)sc[SC_FLAGS_SLOT] & CRBM_FLAG_CHOLESKY_FAIL) return;
-    const int lane = threadIdx.x & 63;
-    const long i = j + 1 + (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+// 2. rows i >= k0 + nb: x L_kk^H = a with x = L_ik, a = A_ik; lane l owns column l of the row.
+//    x_m = (a_m - sum_{l<m} x_l conj(L_kk[m][l])) / L_kk[m][m]
+__global__ __launch_bounds__(256) void k_chol_panel(long P, long k0, int nb, double2* __restrict__ A,
+                                                    const double* __restrict__ sc) {
+    __shared__ double2 L[CH_NB][CH_NB + 1];
+    if (chol_failed(sc)) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int e = tid; e < nb * nb; e += 256) {
+        const int i = e / nb, j = e % nb;
+        L[i][j] = (j <= i) ? A[(k0 + i) * P + k0 + j] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const long i = k0 + nb + (long)blockIdx.x * 4 + (tid >> 6);
     if (i >= P) return;
-    const double2* ri = A + i * P;
-    const double2* rj = A + j * P;
-    double ax = 0.0, ay = 0.0;
-    for (long k = lane; k < j; k += 64) {
-        const double2 t = zmul(ri[k], make_double2(rj[k].x, -rj[k].y));
-        ax += t.x;
-        ay += t.y;
+    double2* row = A + i * P + k0;
+    double2 x = lane < nb ? row[lane] : make_double2(0.0, 0.0);
+    for (int m = 0; m < nb; ++m) {
+        // partial sum over the lanes l < m of x_l conj(L[m][l])
+        double sx = 0.0, sy = 0.0;
+        if (lane < m) {
+            const double2 b = L[m][lane];
+            sx = x.x * b.x + x.y * b.y;
+            sy = x.y * b.x - x.x * b.y;
+        }
+        sx = wave_sum(sx);
+        sy = wave_sum(sy);
+        if (lane == m) {
+            const double inv = 1.0 / L[m][m].x;
+            x = make_double2((x.x - sx) * inv, (x.y - sy) * inv);
+        }
     }
-    ax = wave_sum(ax);
-    ay = wave_sum(ay);
-    if (lane == 0) {
-        const double ljj = A[j * P + j].x;
-        A[i * P + j] = make_double2((A[i * P + j].x - ax) / ljj, (A[i * P + j].y - ay) / ljj);
-    }
+    if (lane < nb) row[lane] = x;
 }
 
-// L y = F, then L^H x = y; one block, rows in sequence, each dot product split over the block
+// 3. trailing update of the lower triangle: A_ij -= sum_l L_il conj(L_jl), i >= j >= k1 = k0 + nb.
+//    Workgroup = one 32 x 32 tile (I >= J) of the trailing matrix; thread = 2 x 2 outputs.
+__global__ __launch_bounds__(256) void k_chol_update(long P, long k0, int nb, double2* __restrict__ A,
+                                                     const double* __restrict__ sc) {
+    __shared__ double2 Li[CH_T][CH_NB + 1], Lj[CH_T][CH_NB + 1];
+    if (chol_failed(sc)) return;
+    const long k1 = k0 + nb;
+    // tile index -> (I, J), J <= I, over T = ceil((P - k1) / 32) tiles per side
+    long rem = blockIdx.x;
+    long I = 0;
+    while (rem > I) { rem -= I + 1; ++I; }
+    const long J = rem;
+    const long i0 = k1 + I * CH_T, j0 = k1 + J * CH_T;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < CH_T * nb; e += 256) {
+        const int r = e / nb, l = e % nb;
+        Li[r][l] = (i0 + r < P) ? A[(i0 + r) * P + k0 + l] : make_double2(0.0, 0.0);
+        Lj[r][l] = (j0 + r < P) ? A[(j0 + r) * P + k0 + l] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int ti = (tid >> 4) * 2, tj = (tid & 15) * 2;
+    double2 acc[2][2] = {};
+    for (int l = 0; l < nb; ++l) {
+        const double2 a0 = Li[ti][l], a1 = Li[ti + 1][l], b0 = Lj[tj][l], b1 = Lj[tj + 1][l];
+        const double2 a[2] = {a0, a1}, b[2] = {b0, b1};
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                acc[p][q].x += a[p].x * b[q].x + a[p].y * b[q].y;
+                acc[p][q].y += a[p].y * b[q].x - a[p].x * b[q].y;
+            }
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const long i = i0 + ti + p, j = j0 + tj + q;
+            if (i < P && j <= i) {
+                double2* dst = A + i * P + j;
+                *dst = make_double2(dst->x - acc[p][q].x, dst->y - acc[p][q].y);
+            }
+        }
+}
+
+// L y = F, then L^H x = y, by blocks of 64 rows in one workgroup of 1024 threads
 __global__ __launch_bounds__(1024) void k_chol_solve(long P, const double2* __restrict__ A,
                                                      const double2* __restrict__ F, double2* __restrict__ xg,
                                                      const double* __restrict__ sc) {
-    __shared__ double shx[16], shy[16];
-    extern __shared__ double2 x[];                 // the solution lives in LDS (P <= kCholMaxP)
-    const bool failed = ((int)sc[SC_FLAGS_SLOT] & CRBM_FLAG_CHOLESKY_FAIL) != 0;
+    __shared__ double2 x[kCholMaxP];               // the solution lives in LDS
+    __shared__ double2 D[CH_NB][CH_NB + 1];        // the diagonal block of the current step
+    __shared__ double2 part[16][CH_NB];            // per-wave partial sums of the off-diagonal products
+    __shared__ double2 rhs[CH_NB];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (failed) {
+    if (chol_failed(sc)) {
         for (long k = tid; k < P; k += blockDim.x) xg[k] = make_double2(0.0, 0.0);
         return;
     }
-    for (long i = 0; i < P; ++i) {                 // forward: y_i = (F_i - sum_{k<i} L_ik y_k) / L_ii
-        double ax = 0.0, ay = 0.0;
-        for (long k = tid; k < i; k += blockDim.x) {
-            const double2 t = zmul(A[i * P + k], x[k]);
-            ax += t.x;
-            ay += t.y;
-        }
-        ax = wave_sum(ax);
-        ay = wave_sum(ay);
-        if (lane == 0) { shx[wv] = ax; shy[wv] = ay; }
-        __syncthreads();
-        if (tid == 0) {
+    const long nblk = (P + CH_NB - 1) / CH_NB;
+    // forward: y_B = L_BB^{-1} (F_B - sum_{j < b0} L_Bj y_j)
+    for (long blk = 0; blk < nblk; ++blk) {
+        const long b0 = blk * CH_NB;
+        const int nb = (int)(P - b0 < CH_NB ? P - b0 : CH_NB);
+        // wave w takes rows r = w, w + 16, ... of the block; its lanes split the columns j < b0
+        for (int r = wv; r < nb; r += 16) {
             double sx = 0.0, sy = 0.0;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { sx += shx[w]; sy += shy[w]; }
-            const double lii = A[i * P + i].x;
-            x[i] = make_double2((F[i].x - sx) / lii, (F[i].y - sy) / lii);
+            const double2* Ar = A + (b0 + r) * P;
+            for (long j = lane; j < b0; j += 64) {
+                const double2 t = zmul(Ar[j], x[j]);
+                sx += t.x;
+                sy += t.y;
+            }
+            sx = wave_sum(sx);
+            sy = wave_sum(sy);
+            if (lane == 0) rhs[r] = make_double2(F[b0 + r].x - sx, F[b0 + r].y - sy);
+        }
+        for (int e = tid; e < nb * nb; e += 1024) D[e / nb][e % nb] = A[(b0 + e / nb) * P + b0 + e % nb];
+        __syncthreads();
+        if (wv == 0) {                             // 64-step substitution in one wave
+            double2 y = lane < nb ? rhs[lane] : make_double2(0.0, 0.0);
+            for (int m = 0; m < nb; ++m) {
+                double sx = 0.0, sy = 0.0;
+                if (lane < m) {
+                    const double2 t = zmul(D[m][lane], y);
+                    sx = t.x;
+                    sy = t.y;
+                }
+                sx = wave_sum(sx);
+                sy = wave_sum(sy);
+                if (lane == m) {
+                    const double inv = 1.0 / D[m][m].x;
+                    y = make_double2((y.x - sx) * inv, (y.y - sy) * inv);
+                }
+            }
+            if (lane < nb) x[b0 + lane] = y;
         }
         __syncthreads();
     }
-    for (long i = P - 1; i >= 0; --i) {            // backward: x_i = (y_i - sum_{k>i} conj(L_ki) x_k) / L_ii
-        double ax = 0.0, ay = 0.0;
-        for (long k = i + 1 + tid; k < P; k += blockDim.x) {
-            const double2 t = zconjmul(A[k * P + i], x[k]);
-            ax += t.x;
-            ay += t.y;
-        }
-        ax = wave_sum(ax);
-        ay = wave_sum(ay);
-        if (lane == 0) { shx[wv] = ax; shy[wv] = ay; }
+    // backward: x_B = L_BB^{-H} (y_B - sum_{k >= b0 + nb} conj(L_kB) x_k)
+    for (long blk = nblk - 1; blk >= 0; --blk) {
+        const long b0 = blk * CH_NB;
+        const int nb = (int)(P - b0 < CH_NB ? P - b0 : CH_NB);
+        // column sums over rows k beyond the block: wave w takes rows k = b0 + nb + w, + 16, ...; lane = column
+        double2 acc = make_double2(0.0, 0.0);
+        if (lane < nb)
+            for (long k = b0 + nb + wv; k < P; k += 16) {
+                const double2 t = zconjmul(A[k * P + b0 + lane], x[k]);
+                acc.x += t.x;
+                acc.y += t.y;
+            }
+        part[wv][lane] = acc;
+        for (int e = tid; e < nb * nb; e += 1024) D[e / nb][e % nb] = A[(b0 + e / nb) * P + b0 + e % nb];
         __syncthreads();
-        if (tid == 0) {
-            double sx = 0.0, sy = 0.0;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { sx += shx[w]; sy += shy[w]; }
-            const double lii = A[i * P + i].x;
-            x[i] = make_double2((x[i].x - sx) / lii, (x[i].y - sy) / lii);
+        if (wv == 0) {
+            double2 s = make_double2(0.0, 0.0);
+            for (int w = 0; w < 16; ++w) { s.x += part[w][lane].x; s.y += part[w][lane].y; }
+            double2 v = lane < nb ? make_double2(x[b0 + lane].x - s.x, x[b0 + lane].y - s.y) : make_double2(0.0, 0.0);
+            // x_m = (v_m - sum_{l > m} conj(L[l][m]) x_l) / L[m][m], m from the bottom of the block up
+            for (int m = nb - 1; m >= 0; --m) {
+                double sx = 0.0, sy = 0.0;
+                if (lane > m && lane < nb) {
+                    const double2 t = zconjmul(D[lane][m], v);
+                    sx = t.x;
+                    sy = t.y;
+                }
+                sx = wave_sum(sx);
+                sy = wave_sum(sy);
+                if (lane == m) {
+                    const double inv = 1.0 / D[m][m].x;
+                    v = make_double2((v.x - sx) * inv, (v.y - sy) * inv);
+                }
+            }
+            if (lane < nb) x[b0 + lane] = v;
         }
         __syncthreads();
     }
@@ -116,14 +256,18 @@ __global__ __launch_bounds__(1024) void k_chol_solve(long P, const double2* __re
 
 hipError_t launch_cholesky_solve(long P, const float2* S, double eps, const double2* F, double2* A64, double2* x,
                                  double* sc, hipStream_t stream) {
+    if (P < 1 || P > kCholMaxP) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_chol_load, dim3((unsigned)((P * P + 255) / 256)), dim3(256), 0, stream, P, S, eps, A64);
-    for (long j = 0; j < P; ++j) {
-        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, stream, P, j, A64, sc);
-        const long rows = P - j - 1;
-        if (rows > 0)
-            hipLaunchKernelGGL(k_chol_col, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, P, j, A64, sc);
+    for (long k0 = 0; k0 < P; k0 += CH_NB) {
+        const int nb = (int)(P - k0 < CH_NB ? P - k0 : CH_NB);
+        hipLaunchKernelGGL(k_chol_diagblock, dim3(1), dim3(256), 0, stream, P, k0, nb, A64, sc);
+        const long rows = P - k0 - nb;
+        if (rows <= 0) break;
+        hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, P, k0, nb, A64, sc);
+        const long T = (rows + CH_T - 1) / CH_T;
+        hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, stream, P, k0, nb, A64, sc);
     }
-    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), (size_t)P * sizeof(double2), stream, P, A64, F, x, sc);
+    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, stream, P, A64, F, x, sc);
     return hipGetLastError();
 }
 

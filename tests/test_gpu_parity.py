@@ -294,6 +294,51 @@ def test_sr_step_mc_weights_dense_vs_matfree(orc):
     assert rel_err(res[1], info["dalpha"]) < 1e-3
 
 
+@pytest.mark.parametrize("kind,Lx,Ly,M,n", [(1, 4, 4, 16, 1500), (0, 40, 1, 80, 8192)])
+def test_cholesky_solve_residual(orc, kind, Lx, Ly, M, n):
+    """Blocked FP64 Cholesky solve of (S + eps I) x = F: P = 288 (four 64-column panels and a ragged one,
+    also checked against the oracle's update) and P = 3320 (the 40-site chain with alpha = 2, 52 panels).
+    The residual against the stored FP32 S is taken in complex128 with torch; a backward-stable solve
+    leaves it below a few P * 2^-53 of |S + eps I| |x|."""
+    N = Lx * Ly
+    fit_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(31 + N, N, M, 0.1)))
+    sig = synth.random_spins(32 + N, n, N, True)
+    r = np.random.default_rng(N)
+    R = (1 + 0.3 * r.normal(size=n) + 0.2j * r.normal(size=n)).astype(np.complex64)
+    plan = _plan(kind, Lx, Ly, M, n, crbm.PLAN_DENSE_S | crbm.PLAN_CHOLESKY)
+    P = plan.P
+    sig_d = torch.from_numpy(sig).cuda()
+    T = torch.zeros(n, M, dtype=torch.complex64, device="cuda")
+    crbm.local_estimators(plan, fit_d, sig_d, tanh_out=T)
+    fit = to_oracle_rbm(orc, fit_d)
+    stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+    eps, dg = 1e-2, 0.1
+    crbm.sr_step(plan, fit_d, sig_d, T, torch.from_numpy(R).cuda(), dg, eps, crbm.CHOLESKY, crbm.FP32, 1e-10, 1,
+                 stats)
+    S = torch.zeros(P, P, dtype=torch.complex64, device="cuda")
+    F = torch.zeros(P, dtype=torch.complex128, device="cuda")
+    x = torch.zeros_like(F)
+    crbm.copy_plan_buffer(plan, crbm.BUF_S, S)
+    crbm.copy_plan_buffer(plan, crbm.BUF_F, F)
+    crbm.copy_plan_buffer(plan, crbm.BUF_DALPHA, x)
+    torch.cuda.synchronize()
+    assert int(np_of(stats)[6]) == 0
+    S64 = S.to(torch.complex128)
+    herm = (torch.linalg.matrix_norm(S64 - S64.mH) / torch.linalg.matrix_norm(S64)).item()
+    # the factorisation reads the lower triangle: the matrix it solves is that triangle's Hermitian completion
+    L = torch.tril(S64)
+    A = L + torch.tril(S64, -1).mH + eps * torch.eye(P, dtype=torch.complex128, device="cuda")
+    xs = x                                      # (S + eps I) dalpha = F, F carrying the step size
+    res = torch.linalg.vector_norm(A @ xs - F).item()
+    scale = torch.linalg.matrix_norm(A).item() * torch.linalg.vector_norm(xs).item()
+    print("P", P, "residual", res, "scale", scale, "ratio", res / scale, "hermitian defect of S", herm)
+    assert herm < 1e-6
+    assert res < 8 * P * 2.0 ** -53 * scale
+    if P < 1000:
+        _, info = orc.sr_step(fit, sig, R.astype(np.complex128), dg, eps)
+        assert rel_err(np_of(x), info["dalpha"]) < 1e-3
+
+
 # ------------------------------------------------------------------ moments and gradient
 @pytest.mark.parametrize("kind,Lx,Ly,M,n,std,sim", [CASES[1], CASES[3]])
 def test_chebyshev_moments(orc, kind, Lx, Ly, M, n, std, sim):
