@@ -293,7 +293,11 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
     rc = rc ? rc : p->alloc(&p->mom_partial, (long)kMomBlocks * kMaxMomentEntries);
     rc = rc ? rc : p->alloc(&p->bcounter, 1);
     rc = rc ? rc : p->alloc(&p->bpartial, 2 * S);
-    if (!rc && (flags & (CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY))) rc = p->alloc(&p->w.S, P * P);
+    if (!rc && (flags & (CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY))) {
+        rc = p->alloc(&p->w.S, P * P);
+        const long nT = hemv_tiles(P);
+        rc = rc ? rc : p->alloc(&p->w.hv_part, nT * nT * kHemvTile);
+    }
     if (!rc && (flags & CRBM_PLAN_CHOLESKY)) rc = p->alloc(&p->w.S64, P * P);
     std::vector<int2> order;
     if (!rc && (flags & (CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY))) {

@@ -106,6 +106,7 @@ struct SrWork {
     const int2* sb_order;     // dispatch order of its tile pairs
     long sb_order_len;
     float2* spart;            // [nsplit_max][P][P] partial sums of a contraction split over samples (or null)
+    double2* hv_part;         // [nT][nT][kHemvTile] tile shares of the dense Hermitian product (with S)
     int nsplit_max;
     int n_cu;
     Profiler* prof;
@@ -130,6 +131,10 @@ struct SrArgs {
     double* stats;                     // device [8]
     int mode;                          // 0: Chebyshev fit (R = target ratio); 1: energy (R = E_loc, dgamma = -lr)
 };
+// edge of the square tiles of the dense Hermitian product and its number of tile rows for P parameters
+constexpr int kHemvTile = 256;
+inline int hemv_tiles(long P) { return (int)((P + kHemvTile - 1) / kHemvTile); }
+
 // the dense solve keeps the solution vector in LDS: P <= kCholMaxP (64 000 bytes of complex128)
 constexpr long kCholMaxP = 4000;
 

@@ -342,59 +342,106 @@ __global__ __launch_bounds__(256) void k_sbuild(int N, int M, long P, const int8
     }
 }
 
-// ------------------------------------------------------------------ dense complex matvec
-// y = (S + eps I) x with S complex64 [P][P] (full storage), x and y complex128.
-// One wave owns SV_ROWS consecutive rows, so each x entry it loads serves SV_ROWS rows;
-// lanes read two complex S entries (16 bytes) per row and step; FP64 accumulation.
-constexpr int SV_ROWS = 8;
+// ------------------------------------------------------------------ dense Hermitian product
+// y = (S + eps I) x with S complex64 [P][P] read from its lower triangle only, x and y complex128.
+// Tile (I, J), J <= I, of HV_T x HV_T entries gives S_IJ x_J to the rows of I and, for J < I, also
+// S_IJ^H x_I to the rows of J (the upper triangle is never read, halving the bytes of a product).
+// Each partial vector has its own slot, part[A][B] = the share of tile pair {A, B} in y_A, and a
+// second pass adds the nT slots of every row in the same order (deterministic).
+constexpr int HV_T = kHemvTile;
 
-__global__ __launch_bounds__(256) void k_symv(long P, const float2* __restrict__ S, const double2* __restrict__ x,
-                                              double eps, double2* __restrict__ y, const double* __restrict__ sc) {
+__global__ __launch_bounds__(256) void k_hemv_tiles(long P, int nT, const float2* __restrict__ S,
+                                                    const double2* __restrict__ x, double2* __restrict__ part,
+                                                    const double* __restrict__ sc) {
     if (sc[SC_DONE] != 0.0) return;
-    const int lane = threadIdx.x & 63;
-    const long row0 = ((long)blockIdx.x * 4 + (threadIdx.x >> 6)) * SV_ROWS;
-    if (row0 >= P) return;
-    double ax[SV_ROWS], ay[SV_ROWS];
+    // lower-triangle tile (I, J) of this workgroup: t = I (I + 1) / 2 + J
+    const long t = blockIdx.x;
+    int I = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((long)I * (I + 1) / 2 > t) --I;
+    while ((long)(I + 1) * (I + 2) / 2 <= t) ++I;
+    const int J = (int)(t - (long)I * (I + 1) / 2);
+    __shared__ double2 xI[HV_T], xJ[HV_T];
+    __shared__ double2 cred[4][HV_T];
+    const int tid = threadIdx.x;
+    const long i0 = (long)I * HV_T, j0 = (long)J * HV_T;
+    xI[tid] = i0 + tid < P ? x[i0 + tid] : make_double2(0.0, 0.0);
+    xJ[tid] = j0 + tid < P ? x[j0 + tid] : make_double2(0.0, 0.0);
+    __syncthreads();
+    // a 16-lane group takes one row at a time; lane c0 of the group reads columns c0 + 16 j, so
+    // that every load instruction of a group covers 128 contiguous bytes of the row
+    const int lane = tid & 63, w = tid >> 6, g = lane >> 4, c0 = lane & 15;
+    const int nrows = (int)(P - i0 < HV_T ? P - i0 : HV_T);
+    const int ncols = (int)(P - j0 < HV_T ? P - j0 : HV_T);
+    double cx[16], cy[16];
 #pragma unroll
-    for (int r = 0; r < SV_ROWS; ++r) { ax[r] = 0.0; ay[r] = 0.0; }
-    const long P2 = P & ~1L;                        // columns handled in pairs
-    for (long k = 2 * lane; k < P2; k += 128) {
-        const double2 x0 = x[k], x1 = x[k + 1];
+    for (int j = 0; j < 16; ++j) { cx[j] = 0.0; cy[j] = 0.0; }
+    for (int rr = 4 * w + g; rr < nrows; rr += 16) {
+        const float2* Sr = S + (i0 + rr) * P + j0;
+        const double2 xi = xI[rr];
+        double rx = 0.0, ry = 0.0;
 #pragma unroll
-        for (int r = 0; r < SV_ROWS; ++r) {
-            const long row = row0 + r;
-            if (row >= P) break;
-            const float2* Sr = S + row * P + k;
-            float2 a0, a1;
-            if (((row * P) & 1) == 0) {             // 16-byte aligned pair
-                const float4 v = *reinterpret_cast<const float4*>(Sr);
-                a0 = make_float2(v.x, v.y);
-                a1 = make_float2(v.z, v.w);
-            } else {
-                a0 = Sr[0];
-                a1 = Sr[1];
-            }
-            ax[r] += (double)a0.x * x0.x - (double)a0.y * x0.y + (double)a1.x * x1.x - (double)a1.y * x1.y;
-            ay[r] += (double)a0.x * x0.y + (double)a0.y * x0.x + (double)a1.x * x1.y + (double)a1.y * x1.x;
+        for (int j = 0; j < 16; ++j) {
+            const int c = c0 + 16 * j;
+            // columns past P: read column 0 instead; x_J is zero there and the column share is unused
+            const float2 sv = Sr[c < ncols ? c : 0];
+            const double sx = sv.x, sy = sv.y;
+            const double2 xj = xJ[c];
+            rx += sx * xj.x - sy * xj.y;
+            ry += sx * xj.y + sy * xj.x;
+            cx[j] += sx * xi.x + sy * xi.y;            // conj(S_rc) x_r
+            cy[j] += sx * xi.y - sy * xi.x;
+        }
+#pragma unroll
+        for (int o = 8; o >= 1; o >>= 1) {
+            rx += __shfl_xor(rx, o, 16);
+            ry += __shfl_xor(ry, o, 16);
+        }
+        if (c0 == 0) part[((long)I * nT + J) * HV_T + rr] = make_double2(rx, ry);
+    }
+    if (J == I) return;                              // the diagonal tile was read in full
+    // column shares: add the 4 row groups of the wave, then the 4 waves in order
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        cx[j] += __shfl_xor(cx[j], 16);
+        cy[j] += __shfl_xor(cy[j], 16);
+        cx[j] += __shfl_xor(cx[j], 32);
+        cy[j] += __shfl_xor(cy[j], 32);
+    }
+    if (g == 0)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) cred[w][c0 + 16 * j] = make_double2(cx[j], cy[j]);
+    __syncthreads();
+    const double2 a = cred[0][tid], b = cred[1][tid], c = cred[2][tid], d = cred[3][tid];
+    part[((long)J * nT + I) * HV_T + tid] = make_double2(((a.x + b.x) + c.x) + d.x, ((a.y + b.y) + c.y) + d.y);
+}
+
+// y_k = sum_B part[k / HV_T][B][k % HV_T] + eps x_k; 64 rows per workgroup, its 4 waves add a quarter
+// of the slots each, combined in wave order
+__global__ __launch_bounds__(256) void k_hemv_reduce(long P, int nT, const double2* __restrict__ part,
+                                                     const double2* __restrict__ x, double eps,
+                                                     double2* __restrict__ y, const double* __restrict__ sc) {
+    if (sc[SC_DONE] != 0.0) return;
+    __shared__ double2 q[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const long k = (long)blockIdx.x * 64 + lane;
+    double sx = 0.0, sy = 0.0;
+    if (k < P) {
+        const long I = k / HV_T, r = k % HV_T;
+        const double2* pr = part + I * nT * HV_T + r;
+        const int per = (nT + 3) / 4;
+        const int b0 = w * per, b1 = b0 + per < nT ? b0 + per : nT;
+#pragma unroll 8
+        for (int B = b0; B < b1; ++B) {
+            const double2 v = pr[(long)B * HV_T];
+            sx += v.x;
+            sy += v.y;
         }
     }
-    if ((P & 1) && lane == 0) {                     // last column of an odd P
-        const long k = P - 1;
-        const double2 xk = x[k];
-#pragma unroll
-        for (int r = 0; r < SV_ROWS; ++r) {
-            const long row = row0 + r;
-            if (row >= P) break;
-            const float2 a = S[row * P + k];
-            ax[r] += (double)a.x * xk.x - (double)a.y * xk.y;
-            ay[r] += (double)a.x * xk.y + (double)a.y * xk.x;
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < SV_ROWS; ++r) {
-        const double sx = wave_sum(ax[r]), sy = wave_sum(ay[r]);
-        const long row = row0 + r;
-        if (lane == 0 && row < P) y[row] = make_double2(sx + eps * x[row].x, sy + eps * x[row].y);
+    q[w][lane] = make_double2(sx, sy);
+    __syncthreads();
+    if (w == 0 && k < P) {
+        const double2 a = q[0][lane], b = q[1][lane], c = q[2][lane], d = q[3][lane];
+        y[k] = make_double2((((a.x + b.x) + c.x) + d.x) + eps * x[k].x, (((a.y + b.y) + c.y) + d.y) + eps * x[k].y);
     }
 }
 
@@ -621,7 +668,11 @@ static hipError_t apply_op(const SrArgs& A, const SrWork& W, const double2* v, d
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_add_shift, dim3(nblk(P)), dim3(256), 0, stream, P, v, A.eps, y, W.scal);
     } else {
-        hipLaunchKernelGGL(k_symv, dim3(nblk(P, 4 * SV_ROWS)), dim3(256), 0, stream, P, W.S, v, A.eps, y, W.scal);
+        const int nT = hemv_tiles(P);
+        hipLaunchKernelGGL(k_hemv_tiles, dim3((unsigned)((long)nT * (nT + 1) / 2)), dim3(256), 0, stream, P, nT, W.S,
+                           v, W.hv_part, W.scal);
+        hipLaunchKernelGGL(k_hemv_reduce, dim3(nblk(P, 64)), dim3(256), 0, stream, P, nT, W.hv_part, v, A.eps, y,
+                           W.scal);
     }
     return hipGetLastError();
 }

@@ -311,6 +311,7 @@ def test_cholesky_solve_residual(orc, kind, Lx, Ly, M, n):
     T = torch.zeros(n, M, dtype=torch.complex64, device="cuda")
     crbm.local_estimators(plan, fit_d, sig_d, tanh_out=T)
     fit = to_oracle_rbm(orc, fit_d)
+    fit0 = crbm.RBM(fit_d.a.clone(), fit_d.b.clone(), fit_d.W.clone())
     stats = torch.zeros(8, dtype=torch.float64, device="cuda")
     eps, dg = 1e-2, 0.1
     crbm.sr_step(plan, fit_d, sig_d, T, torch.from_numpy(R).cuda(), dg, eps, crbm.CHOLESKY, crbm.FP32, 1e-10, 1,
@@ -337,6 +338,24 @@ def test_cholesky_solve_residual(orc, kind, Lx, Ly, M, n):
     if P < 1000:
         _, info = orc.sr_step(fit, sig, R.astype(np.complex128), dg, eps)
         assert rel_err(np_of(x), info["dalpha"]) < 1e-3
+    # dense CG on the same S and F: its product reads the 256 x 256 tiles on and below the diagonal (the
+    # diagonal tiles in full) and mirrors the ones below; the solution must solve that operator to the tolerance
+    stats2 = torch.zeros(8, dtype=torch.float64, device="cuda")
+    crbm.sr_step(plan, fit0, sig_d, T, torch.from_numpy(R).cuda(), dg, eps, crbm.CG_DENSE, crbm.FP32, 1e-11, 3000,
+                 stats2)
+    xc = torch.zeros_like(F)
+    crbm.copy_plan_buffer(plan, crbm.BUF_DALPHA, xc)
+    torch.cuda.synchronize()
+    st2 = np_of(stats2)
+    assert int(st2[6]) == 0, st2
+    tile = torch.arange(P, device="cuda") // 256
+    upper = tile[:, None] < tile[None, :]
+    Ah = torch.where(upper, S64.mH, S64) + eps * torch.eye(P, dtype=torch.complex128, device="cuda")
+    res_cg = (torch.linalg.vector_norm(Ah @ xc - F) / torch.linalg.vector_norm(F)).item()
+    print("dense CG iterations", st2[5], "residual", res_cg, "reported", st2[4])
+    assert res_cg < 1e-10
+    assert abs(st2[4] - res_cg) <= 1e-3 * res_cg + 1e-14
+    assert rel_err(np_of(xc), np_of(x)) < 1e-3
 
 
 # ------------------------------------------------------------------ moments and gradient
