@@ -72,7 +72,10 @@ def lib():
         L.orc_metropolis.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _c128p, _i8p, _c.c_int, _c.c_int,
                                      _c.c_int, _c.c_uint64, _c.c_uint64, _c.c_void_p, _c.c_void_p,
                                      _c.c_void_p, _c.c_long, _c.c_double,
-                                     _c.POINTER(_c.c_long), _c.POINTER(_c.c_long)]
+                                     _c.POINTER(_c.c_long), _c.POINTER(_c.c_long), _c.c_void_p]
+        L.orc_sr_entries.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _i8p, _c.c_void_p, _c128p, _c.c_long,
+                                     _c.c_double, _c.c_void_p, _c.c_int, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                     _c.c_void_p]
         L.orc_sr_step.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _c128p, _i8p, _c.c_void_p, _c128p,
                                   _c.c_long, _c.c_double, _c.c_double, _f64p, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p]
@@ -245,11 +248,12 @@ def target_ratio(fit, psi_n, psi_nm1, lat, sig, order, E_c, W_scale, beta_n=1.0,
     return (R, hp) if return_hpsi else R
 
 
-def metropolis(rbm, spins, n_sweeps, proposal, seed, step_offset=0, trace=None, margin=1e-4):
+def metropolis(rbm, spins, n_sweeps, proposal, seed, step_offset=0, trace=None, margin=1e-4, chain_ids=None):
     """Run the Metropolis chains in place on ``spins`` [C][N].
 
     Returns (samples [n_sweeps][C][N], n_accept [C], n_ambiguous, n_mismatch).
     ``trace`` ([C][words] uint32) replays another implementation's decisions.
+    ``chain_ids`` ([C] int) gives the chain index of each row (its random stream); default 0 .. C-1.
     """
     C, N = spins.shape
     assert spins.dtype == np.int8 and spins.flags.c_contiguous
@@ -260,9 +264,13 @@ def metropolis(rbm, spins, n_sweeps, proposal, seed, step_offset=0, trace=None, 
     if trace is not None:
         trace = np.ascontiguousarray(trace, dtype=np.uint32)
         words = trace.shape[1]
+    ids = None
+    if chain_ids is not None:
+        ids = np.ascontiguousarray(chain_ids, dtype=np.int32)
+        assert ids.shape == (C,)
     lib().orc_metropolis(N, rbm.M, rbm.a, rbm.b, rbm.W, spins, C, n_sweeps, proposal, seed, step_offset,
                          _ptr(samples), _ptr(nacc), _ptr(trace), words, margin, ctypes.byref(amb),
-                         ctypes.byref(mis))
+                         ctypes.byref(mis), _ptr(ids))
     return samples, nacc, amb.value, mis.value
 
 
@@ -281,6 +289,24 @@ def sr_step(rbm, sig, R, dgamma, eps, weights=None, want_S=False):
                            _ptr(S), _ptr(F), _ptr(dx))
     info = dict(rc=rc, gamma=stats[0], beta=complex(stats[1], stats[2]), Fnorm=stats[3], F=F, dalpha=dx, S=S)
     return new, info
+
+
+def sr_entries(rbm, sig, R, dgamma, ks, weights=None):
+    """S and F of the natural-gradient step restricted to the parameter indices ``ks``, with <O_k>,
+    gamma and beta: dict(S [len(ks)][len(ks)], F [len(ks)], Om [len(ks)], gamma, beta).  Each O_k(s)
+    is formed per sample, so the model may be too large for the full O."""
+    sig = _i8(sig)
+    R = _c128(R)
+    ks = np.ascontiguousarray(ks, dtype=np.int64)
+    nk = ks.shape[0]
+    S = np.zeros((nk, nk), np.complex128)
+    F = np.zeros(nk, np.complex128)
+    Om = np.zeros(nk, np.complex128)
+    stats = np.zeros(3, np.float64)
+    w = None if weights is None else np.ascontiguousarray(weights, np.float64)
+    lib().orc_sr_entries(rbm.N, rbm.M, rbm.b, rbm.W, sig, _ptr(w), R, sig.shape[0], dgamma, _ptr(ks), nk,
+                         _ptr(stats), _ptr(S), _ptr(F), _ptr(Om))
+    return dict(S=S, F=F, Om=Om, gamma=stats[0], beta=complex(stats[1], stats[2]))
 
 
 def sr_energy_step(rbm, sig, eloc, lr, eps, weights=None, want_S=False):

@@ -353,7 +353,8 @@ void orc_target_ratio(int N, int M,
 /* u = (x2 >> 8) 2^-24.  proposal 0: flip site i.  proposal 1: swap sites i   */
 /* and j when sigma_i != sigma_j, else a null move.  Accept iff               */
 /* u < exp(2 Re[log psi(sigma') - log psi(sigma)]).  A sample is the state    */
-/* after each sweep of N proposals.                                           */
+/* after each sweep of N proposals.  Row c of spins is chain chain_ids[c]    */
+/* (chain c when chain_ids is NULL): the chain index enters only the counter.  */
 /*                                                                            */
 /* Replay: if trace != NULL it holds one bit per proposal and chain (the      */
 /* decisions of another implementation, bit t of word t/32 of the chain's     */
@@ -366,7 +367,7 @@ void orc_metropolis(int N, int M, const cplx* a, const cplx* b, const cplx* W,
                     int8_t* spins, int C, int n_sweeps, int proposal, uint64_t seed,
                     uint64_t step_offset, int8_t* samples_out, uint32_t* n_accept,
                     const uint32_t* trace, long trace_words, double margin,
-                    long* n_ambiguous, long* n_mismatch) {
+                    long* n_ambiguous, long* n_mismatch, const int* chain_ids) {
     long amb = 0, mis = 0;
 #pragma omp parallel reduction(+:amb, mis)
     {
@@ -381,7 +382,7 @@ void orc_metropolis(int N, int M, const cplx* a, const cplx* b, const cplx* W,
                     long tloc = (long)sw * N + k;
                     uint64_t t = step_offset + (uint64_t)tloc;
                     uint32_t r4[4];
-                    philox_draw(seed, (uint32_t)c, t, 0u, r4);
+                    philox_draw(seed, (uint32_t)(chain_ids ? chain_ids[c] : c), t, 0u, r4);
                     int i = draw_index(r4[0], N), j = draw_index(r4[1], N);
                     double u = draw_unit(r4[2]);
                     memcpy(prop, s, (size_t)N);
@@ -534,6 +535,87 @@ int orc_sr_step(int N, int M, cplx* a, cplx* b, cplx* W, const int8_t* sig,
     if (stats) { stats[0] = gamma; stats[1] = creal(Rm); stats[2] = cimag(Rm); stats[3] = sqrt(fn); }
     free(O); free(Om); free(F); free(S); free(x);
     return rc;
+}
+
+/* ------------------------------------------------------------------------- */
+/* One log-derivative O_k(s) (Sec. III) from its definition: sigma_k for      */
+/* k < N, tanh theta_j for the b rows, sigma_i tanh theta_j for W_ij.         */
+/* ------------------------------------------------------------------------- */
+static cplx logderiv_entry(int N, int M, const cplx* b, const cplx* W, const int8_t* sg, long k) {
+    if (k < N) return (double)sg[k];
+    const long r = k - N;
+    const int j = (int)(r < M ? r : (r - M) % M);
+    cplx th = b[j];
+    for (int i = 0; i < N; ++i) th += (double)sg[i] * W[(long)i * M + j];
+    const cplx t = ctanh(th);
+    if (r < M) return t;
+    return (double)sg[(r - M) / M] * t;
+}
+
+/* ------------------------------------------------------------------------- */
+/* The quantities of orc_sr_step restricted to the parameter indices          */
+/* ks[0..nk): S_out[c][d] = S_{ks[c] ks[d]}, F_out[c] = F_{ks[c]},            */
+/* Om_out[c] = <O_{ks[c]}>, stats = [gamma, Re beta, Im beta], every O_k(s)  */
+/* formed per sample from its                                                  */
+/* definition, so that models whose O [n][P] does not fit in memory can be    */
+/* checked entry by entry.  The sample sums run over 64 fixed contiguous      */
+/* blocks (compensated within a block) added in block order.                  */
+/* ------------------------------------------------------------------------- */
+void orc_sr_entries(int N, int M, const cplx* b, const cplx* W, const int8_t* sig,
+                    const double* weights, const cplx* R, long n, double dgamma,
+                    const long* ks, int nk, double* stats, cplx* S_out, cplx* F_out, cplx* Om_out) {
+    ksum kR = {0, 0};
+    double r2 = 0.0, r2c = 0.0;
+    for (long s = 0; s < n; ++s) {
+        double w = weights ? weights[s] : 1.0 / (double)n;
+        kadd(&kR, w * R[s]);
+        double y = w * creal(R[s] * conj(R[s])) - r2c, t = r2 + y;
+        r2c = (t - r2) - y; r2 = t;
+    }
+    cplx Rm = kR.s;
+    double gamma = acos(fmin(1.0, sqrt(creal(Rm * conj(Rm)) / r2)));
+    double gcot = (gamma < 1e-4) ? 1.0 - gamma * gamma / 3.0 : gamma / tan(gamma);
+
+    enum { NBLK = 64 };
+    const long per = (n + NBLK - 1) / NBLK;
+    const long stride = 2L * nk + (long)nk * nk;
+    ksum* part = (ksum*)calloc((size_t)(NBLK * stride), sizeof(ksum));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int blk = 0; blk < NBLK; ++blk) {
+        cplx* o = (cplx*)malloc(sizeof(cplx) * (size_t)nk);
+        ksum* s1 = part + blk * stride;
+        ksum* s2 = s1 + nk;
+        ksum* g = s2 + nk;
+        const long s0 = blk * per, s1e = (blk + 1) * per < n ? (blk + 1) * per : n;
+        for (long s = s0; s < s1e; ++s) {
+            const int8_t* sg = sig + s * N;
+            double w = weights ? weights[s] : 1.0 / (double)n;
+            for (int c = 0; c < nk; ++c) o[c] = logderiv_entry(N, M, b, W, sg, ks[c]);
+            for (int c = 0; c < nk; ++c) {
+                kadd(&s1[c], w * o[c]);
+                kadd(&s2[c], w * conj(o[c]) * R[s]);
+                for (int d = 0; d < nk; ++d) kadd(&g[(long)c * nk + d], w * conj(o[c]) * o[d]);
+            }
+        }
+        free(o);
+    }
+    cplx* tot = (cplx*)calloc((size_t)stride, sizeof(cplx));
+    for (long e = 0; e < stride; ++e) {
+        ksum acc = {0, 0};
+        for (int blk = 0; blk < NBLK; ++blk) kadd(&acc, part[blk * stride + e].s);
+        tot[e] = acc.s;
+    }
+    const cplx* Om = tot;
+    const cplx* ORm = tot + nk;
+    const cplx* G = tot + 2 * nk;
+    for (int c = 0; c < nk; ++c) {
+        if (Om_out) Om_out[c] = Om[c];
+        if (F_out) F_out[c] = dgamma * gcot * (ORm[c] / Rm - conj(Om[c]));
+        if (S_out)
+            for (int d = 0; d < nk; ++d) S_out[(long)c * nk + d] = G[(long)c * nk + d] - conj(Om[c]) * Om[d];
+    }
+    if (stats) { stats[0] = gamma; stats[1] = creal(Rm); stats[2] = cimag(Rm); }
+    free(part); free(tot);
 }
 
 /* ------------------------------------------------------------------------- */

@@ -87,3 +87,23 @@ def test_replay_flags_planted_disagreement(orc):
     ones = np.full((4, words), 0xFFFFFFFF, np.uint32)
     _, nacc, amb, mis = orc.metropolis(z, s, sweeps, 0, seed=5, trace=ones)
     assert mis == 0 and amb == 0
+
+
+def test_chain_ids_select_the_stream(orc):
+    """Rows run under explicit chain indices reproduce those chains of a run over all of them, so a
+    few chains of a large launch can be replayed alone."""
+    N, M, C = 12, 6, 40
+    rbm = orc.RBM(*synth.random_rbm_arrays(5, N, M, 0.3, std_im=0.05))
+    spins = orc.init_chains(N, C, 91, 1)
+    start = spins.copy()
+    smp, nacc, _, _ = orc.metropolis(rbm, spins, 7, 1, seed=17, step_offset=300)
+    ids = np.array([0, 13, 39], np.int32)
+    sub = np.ascontiguousarray(start[ids])
+    smp_sub, nacc_sub, _, _ = orc.metropolis(rbm, sub, 7, 1, seed=17, step_offset=300, chain_ids=ids)
+    assert np.array_equal(smp_sub, smp[:, ids])
+    assert np.array_equal(nacc_sub, nacc[ids])
+    assert np.array_equal(sub, spins[ids])
+    # the same rows under the default indices 0, 1, 2 follow other streams
+    sub2 = np.ascontiguousarray(start[ids])
+    smp_def, _, _, _ = orc.metropolis(rbm, sub2, 7, 1, seed=17, step_offset=300)
+    assert not np.array_equal(smp_def[:, 1:], smp[:, ids[1:]])

@@ -75,3 +75,20 @@ def test_sr_uniform_weights_equal_explicit(orc):
     n1, i1 = orc.sr_step(rbm, sig, R, 0.2, 1e-2)
     n2, i2 = orc.sr_step(rbm, sig, R, 0.2, 1e-2, weights=np.full(200, 1 / 200))
     assert np.allclose(i1["dalpha"], i2["dalpha"], rtol=1e-12, atol=1e-14)
+
+
+def test_sr_entries_match_the_full_step(orc):
+    """The entry-by-entry form (for models too large for the full O) equals the full step's S, F,
+    gamma and beta on the chosen indices: weighted (enumeration) and uniform (MC) sums, indices of
+    all three parameter kinds in scrambled order and repeated."""
+    rbm, sig, p, R = _setup(orc, N=7, M=5, seed=9)
+    ks = np.array([34, 0, 6, 7, 11, 12, 13, 40, 20, 7, 3], np.int64)      # P = 7 + 5 + 35 = 47
+    for w in (p, None):
+        _, info = orc.sr_step(rbm, sig, R, 0.2, 1e-3, weights=w, want_S=True)
+        e = orc.sr_entries(rbm, sig, R, 0.2, ks, weights=w)
+        assert np.max(np.abs(e["S"] - info["S"][np.ix_(ks, ks)])) < 1e-13
+        assert np.max(np.abs(e["F"] - info["F"][ks])) < 1e-13
+        assert abs(e["gamma"] - info["gamma"]) < 1e-14 and abs(e["beta"] - info["beta"]) < 1e-14
+        O = orc.logderiv(rbm, sig)
+        wt = np.full(sig.shape[0], 1.0 / sig.shape[0]) if w is None else w
+        assert np.max(np.abs(e["Om"] - wt @ O[:, ks])) < 1e-13
