@@ -229,18 +229,6 @@ def main():
     plan.close()
 
 
-def bz_path(L, n_points):
-    """n_points momenta equally spaced in arc length along Gamma(0,0) -> X(pi,0) -> M(pi,pi) -> Gamma."""
-    corners = np.array([[0.0, 0.0], [math.pi, 0.0], [math.pi, math.pi], [0.0, 0.0]])
-    seg = np.linalg.norm(np.diff(corners, axis=0), axis=1)
-    cum = np.concatenate([[0.0], np.cumsum(seg)])
-    out = []
-    for t in np.linspace(0.0, cum[-1], n_points, endpoint=False):
-        k = min(int(np.searchsorted(cum, t, side="right")) - 1, len(seg) - 1)
-        out.append(corners[k] + (t - cum[k]) / seg[k] * (corners[k + 1] - corners[k]))
-    return np.array(out)
-
-
 def bench_batched(crbm, args):
     """Moments of 32 momenta x 64 Chebyshev orders (2048 instances) of the 8x8, alpha = 2 lattice,
     256..2048 chains per instance, 4 burn-in + 16 recorded sweeps, one persistent launch."""
@@ -248,8 +236,7 @@ def bench_batched(crbm, args):
     N, M, P = wl.N, wl.M, wl.P
     n_q, n_ord = 32, 64
     n_inst = n_q * n_ord
-    counts = np.random.default_rng(4).integers(256, 2049, n_inst)
-    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    counts, offsets, qs = synth.batched_instances(n_q, n_ord)
     total = int(offsets[-1])
     plan = crbm.Plan(crbm.SQUARE, wl.Lx, wl.Ly, M, total)
     gs = crbm.RBM.empty(N, M)
@@ -258,7 +245,6 @@ def bench_batched(crbm, args):
     for i in range(n_inst):
         crbm.init_rbm(crbm.RBM.from_packed(tp[i], N, M), wl.param_seed + 1 + i, wl.param_std)
     betas = torch.ones(n_inst, dtype=torch.complex128, device="cuda")
-    qs = np.repeat(bz_path(wl.Lx, n_q), n_ord, axis=0)
     qd = torch.from_numpy(np.ascontiguousarray(qs)).cuda()
     od = torch.from_numpy(offsets).cuda()
     mu = torch.zeros(n_inst, 2, dtype=torch.complex128, device="cuda")

@@ -331,12 +331,17 @@ int crbm_spectrum_cf(const double* a, const double* b2, int m, double E0, double
  *   chain_offsets device int64 [n_inst + 1], non-decreasing, chain_offsets[0] = 0,
  *                 chain_offsets[n_inst] = total_chains <= the plan's max_samples
  *   mu_out        complex128 [n_inst][2] = (<|f_q|^2>, <f_q^* beta t~/psi_gs>) per instance
+ *   trace         NULL, or device uint32 [total_chains][ceil((n_burn + n_sweeps) * N / 32)]: the accept
+ *                 bit of every proposal of chain g (bit t % 32 of word t / 32 of row g, t = sweep*N + k,
+ *                 burn-in included; null moves are 0), as crbm_sample records them, so that another
+ *                 implementation can replay the chains; every word is written
  * Waves of a persistent grid take chains from an atomic counter; partial sums are reduced per
  * instance in chain order, so the result does not depend on the schedule.  The launch shape is the
  * plan's default or the one chosen by crbm_batched_autotune.  Safe to capture in a graph. */
 int crbm_batched_moments(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_params, const double* betas,
                          const double* q, const int64_t* chain_offsets, int n_inst, int64_t total_chains, int n_burn,
-                         int n_sweeps, int proposal, uint64_t seed, void* mu_out, hipStream_t stream);
+                         int n_sweeps, int proposal, uint64_t seed, void* mu_out, uint32_t* trace,
+                         hipStream_t stream);
 /* Times the persistent kernel of crbm_batched_moments for several launch shapes (waves per block 1..8,
  * blocks per compute unit 1..8) on the given instances with n_sweeps_probe sweeps, stores the fastest
  * in the plan and returns it (any output may be NULL).  Synchronises the host: call it outside graph

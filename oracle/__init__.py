@@ -94,12 +94,16 @@ def lib():
         L.orc_fidelity_grad.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _i8p, _c128p, _c.c_long,
                                         _c.c_void_p]
         L.orc_fidelity_grad.restype = _c.c_double
+        L.orc_fidelity_grad_entries.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _i8p, _c128p, _c.c_long,
+                                                _c.c_void_p, _c.c_int, _c.c_void_p]
+        L.orc_fidelity_grad_entries.restype = _c.c_double
         L.orc_sr_energy_step.argtypes = L.orc_sr_step.argtypes
         L.orc_sr_energy_step.restype = _c.c_int
         _i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
         L.orc_batched_moments.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _c128p, _c128p, _c128p, _f64p, _i64p,
                                           _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_uint64, _c.c_int, _c.c_int,
-                                          _c.c_double, _c128p, _c.POINTER(_c.c_long)]
+                                          _c.c_double, _c128p, _c.POINTER(_c.c_long), _c.c_void_p, _c.c_long,
+                                          _c.POINTER(_c.c_long)]
         _lib = L
     return _lib
 
@@ -383,13 +387,36 @@ def fidelity_grad(rbm, sig, R):
     return L, g
 
 
-def batched_moments(psi_gs, t_params, betas, qs, offsets, lat, n_burn, n_sweeps, proposal, seed, margin=1e-4):
-    """Per-instance (<|f_q|^2>, <conj(f_q) beta t~/psi_gs>) and the count of near-threshold steps."""
+def fidelity_grad_entries(rbm, sig, R, ks):
+    """(L, grad[ks]): the fidelity gradient on the parameter indices ``ks`` only, each O_k(s) formed
+    per sample (for models whose O does not fit in memory)."""
+    sig = _i8(sig)
+    R = _c128(R)
+    ks = np.ascontiguousarray(ks, dtype=np.int64)
+    g = np.zeros(ks.shape[0], np.complex128)
+    L = lib().orc_fidelity_grad_entries(rbm.N, rbm.M, rbm.b, rbm.W, sig, R, sig.shape[0], _ptr(ks), ks.shape[0],
+                                        _ptr(g))
+    return L, g
+
+
+def batched_moments(psi_gs, t_params, betas, qs, offsets, lat, n_burn, n_sweeps, proposal, seed, margin=1e-4,
+                    trace=None):
+    """Per-instance (<|f_q|^2>, <conj(f_q) beta t~/psi_gs>), with (n_ambiguous, n_mismatch).
+
+    ``offsets`` holds the global chain indices of the instances (chain g's random stream is g).
+    Without ``trace``, n_ambiguous counts the steps within the margin of the threshold and n_mismatch
+    is 0.  With ``trace`` (uint32 [offsets[-1] - offsets[0]][words], row g - offsets[0]) the chains
+    replay another implementation's decisions as in metropolis()."""
     t_params = _c128(np.asarray(t_params).reshape(len(betas), -1))
     out = np.zeros((len(betas), 2), np.complex128)
-    amb = ctypes.c_long(0)
+    amb, mis = ctypes.c_long(0), ctypes.c_long(0)
+    words = 0
+    if trace is not None:
+        trace = np.ascontiguousarray(trace, dtype=np.uint32)
+        words = trace.shape[1]
     lib().orc_batched_moments(psi_gs.N, psi_gs.M, psi_gs.a, psi_gs.b, psi_gs.W, t_params, _c128(betas),
                               np.ascontiguousarray(np.asarray(qs, np.float64).reshape(-1, 2)),
                               np.ascontiguousarray(offsets, np.int64), len(betas), n_burn, n_sweeps, proposal, seed,
-                              lat.kind, lat.Lx, margin, out, ctypes.byref(amb))
-    return out, amb.value
+                              lat.kind, lat.Lx, margin, out, ctypes.byref(amb), _ptr(trace), words,
+                              ctypes.byref(mis))
+    return out, amb.value, mis.value

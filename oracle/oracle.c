@@ -687,6 +687,36 @@ double orc_fidelity_grad(int N, int M, const cplx* b, const cplx* W, const int8_
     return L;
 }
 
+/* The same gradient restricted to the parameter indices ks[0..nk), each      */
+/* O_k(s) formed per sample (for models whose O [n][P] does not fit in        */
+/* memory); sums over 64 fixed contiguous sample blocks added in block order.  */
+/* Returns L.                                                                  */
+double orc_fidelity_grad_entries(int N, int M, const cplx* b, const cplx* W, const int8_t* sig,
+                                 const cplx* R, long n, const long* ks, int nk, cplx* grad_out) {
+    double L = 0.0;
+    for (long s = 0; s < n; ++s) { cplx d = 1.0 - R[s]; L += creal(d * conj(d)); }
+    L /= (double)n;
+    enum { NBLK = 64 };
+    const long per = (n + NBLK - 1) / NBLK;
+    ksum* part = (ksum*)calloc((size_t)(NBLK * nk), sizeof(ksum));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int blk = 0; blk < NBLK; ++blk) {
+        const long s0 = blk * per, s1 = (blk + 1) * per < n ? (blk + 1) * per : n;
+        for (long s = s0; s < s1; ++s) {
+            const cplx c = (1.0 - R[s]) * conj(R[s]);
+            for (int e = 0; e < nk; ++e)
+                kadd(&part[blk * nk + e], c * conj(logderiv_entry(N, M, b, W, sig + s * N, ks[e])));
+        }
+    }
+    for (int e = 0; e < nk; ++e) {
+        ksum acc = {0, 0};
+        for (int blk = 0; blk < NBLK; ++blk) kadd(&acc, part[blk * nk + e].s);
+        grad_out[e] = 2.0 * acc.s / (double)n;
+    }
+    free(part);
+    return L;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Batched moments over (q, n) instances (Sec. II moments, App. A momentum     */
 /* form).  Instance i owns chains g in [offsets[i], offsets[i+1]) on psi_gs.  */
@@ -697,23 +727,34 @@ double orc_fidelity_grad(int N, int M, const cplx* b, const cplx* W, const int8_
 /* conj(f_q(s)) beta_i t~_i(s)/psi_gs(s), every amplitude from scratch.       */
 /* mu_out[i] = (<|f_q|^2>, <conj(f_q) beta t~/psi_gs>).  n_ambiguous counts   */
 /* steps with |u - r| <= margin * max(r, 1e-30) (where a lower-precision      */
-/* implementation could take the other branch).                               */
+/* implementation could take the other branch).  With trace != NULL (row      */
+/* g - offsets[0] of trace_words words per chain, the accept bits of another  */
+/* implementation) the chains replay those decisions as orc_metropolis does: */
+/* a differing decision counts as ambiguous within the margin, else as a     */
+/* mismatch, and the traced one is adopted.                                   */
 /* ------------------------------------------------------------------------- */
 void orc_batched_moments(int N, int M, const cplx* ag, const cplx* bg, const cplx* Wg,
                          const cplx* t_params, const cplx* betas, const double* qs,
                          const int64_t* offsets, int n_inst, int n_burn, int n_sweeps, int proposal,
-                         uint64_t seed, int kind, int Lx, double margin, cplx* mu_out, long* n_ambiguous) {
+                         uint64_t seed, int kind, int Lx, double margin, cplx* mu_out, long* n_ambiguous,
+                         const uint32_t* trace, long trace_words, long* n_mismatch) {
     long P = (long)N + M + (long)N * M;
-    long amb = 0;
+    long amb = 0, mis = 0;
     for (int inst = 0; inst < n_inst; ++inst) {
         const cplx* tp = t_params + (long)inst * P;
         const double* q = qs + 2 * inst;
-        ksum s0 = {0, 0}, s1 = {0, 0};
-        long cnt = 0;
-        for (int64_t g = offsets[inst]; g < offsets[inst + 1]; ++g) {
+        const long n_ch = (long)(offsets[inst + 1] - offsets[inst]);
+        /* per-chain sums, added in chain order below (the chains are independent) */
+        cplx* c0 = (cplx*)calloc((size_t)(n_ch > 0 ? n_ch : 1), sizeof(cplx));
+        cplx* c1 = (cplx*)calloc((size_t)(n_ch > 0 ? n_ch : 1), sizeof(cplx));
+#pragma omp parallel for schedule(dynamic, 1) reduction(+:amb, mis)
+        for (long c = 0; c < n_ch; ++c) {
+            const int64_t g = offsets[inst] + c;
+            const uint32_t* trow = trace ? trace + (long)(g - offsets[0]) * trace_words : NULL;
             int8_t* s = (int8_t*)malloc((size_t)N);
             int8_t* prop = (int8_t*)malloc((size_t)N);
             cplx* th = (cplx*)malloc(sizeof(cplx) * (size_t)M);
+            ksum s0 = {0, 0}, s1 = {0, 0};
             for (int i = 0; i < N; ++i) s[i] = (i < N / 2) ? 1 : -1;
             for (int k = N - 1; k >= 1; --k) {
                 uint32_t r[4];
@@ -736,8 +777,18 @@ void orc_batched_moments(int N, int M, const cplx* ag, const cplx* bg, const cpl
                     cplx l0 = logpsi_one(N, M, ag, bg, Wg, s, th);
                     cplx l1 = logpsi_one(N, M, ag, bg, Wg, prop, th);
                     double rr = exp(2.0 * creal(l1 - l0));
-                    if (fabs(u - rr) <= margin * fmax(rr, 1e-30)) ++amb;
-                    if (u < rr) memcpy(s, prop, (size_t)N);
+                    int dec = (u < rr);
+                    if (trow) {
+                        const long tloc = (long)sw * N + k;
+                        const int gb = (int)((trow[tloc / 32] >> (tloc % 32)) & 1u);
+                        if (gb != dec) {
+                            if (fabs(u - rr) <= margin * fmax(rr, 1e-30)) ++amb; else ++mis;
+                            dec = gb;
+                        }
+                    } else if (fabs(u - rr) <= margin * fmax(rr, 1e-30)) {
+                        ++amb;
+                    }
+                    if (dec) memcpy(s, prop, (size_t)N);
                 }
                 if (sw < n_burn) continue;
                 cplx f = fq_of(kind, Lx, N, q, s);
@@ -745,14 +796,20 @@ void orc_batched_moments(int N, int M, const cplx* ag, const cplx* bg, const cpl
                 cplx lt = logpsi_one(N, M, tp, tp + N, tp + N + M, s, th);
                 kadd(&s0, conj(f) * f);
                 kadd(&s1, conj(f) * betas[inst] * cexp(lt - lg));
-                ++cnt;
             }
+            c0[c] = s0.s;
+            c1[c] = s1.s;
             free(s); free(prop); free(th);
         }
-        mu_out[2 * inst] = cnt ? s0.s / (double)cnt : 0.0;
-        mu_out[2 * inst + 1] = cnt ? s1.s / (double)cnt : 0.0;
+        ksum t0 = {0, 0}, t1 = {0, 0};
+        for (long c = 0; c < n_ch; ++c) { kadd(&t0, c0[c]); kadd(&t1, c1[c]); }
+        const long cnt = n_ch * (long)n_sweeps;
+        mu_out[2 * inst] = cnt ? t0.s / (double)cnt : 0.0;
+        mu_out[2 * inst + 1] = cnt ? t1.s / (double)cnt : 0.0;
+        free(c0); free(c1);
     }
     if (n_ambiguous) *n_ambiguous = amb;
+    if (n_mismatch) *n_mismatch = mis;
 }
 
 /* ------------------------------------------------------------------------- */

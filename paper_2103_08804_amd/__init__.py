@@ -93,7 +93,7 @@ def lib():
         L.crbm_chebyshev_moment.argtypes = [_vp, P(_Rbm), _vp, _vp, _i, P(_d), _i, _vp, _vp, _l, _vp, _vp]
         L.crbm_fidelity_grad.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _l, _vp, _vp, _vp]
         L.crbm_batched_moments.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _i, ctypes.c_int64, _i, _i, _i, _u64,
-                                           _vp, _vp]
+                                           _vp, _vp, _vp]
         L.crbm_batched_autotune.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _i, ctypes.c_int64, _i, _i, _u64, _vp,
                                             P(_i), P(_i), P(_d), _vp]
         for name in EXPORTS:
@@ -426,19 +426,22 @@ def probe_hbm(nbytes: int = 1 << 30, stream=None) -> float:
 
 
 def batched_moments(plan: Plan, psi_gs: RBM, t_params, betas, q, chain_offsets, n_burn: int, n_sweeps: int,
-                    proposal: int, seed: int, mu_out, total_chains: int | None = None, stream=None):
+                    proposal: int, seed: int, mu_out, total_chains: int | None = None, trace=None, stream=None):
     """Per-instance (<|f_q|^2>, <f_q^* beta t~/psi_gs>) for all instances in one persistent launch.
 
     total_chains (= chain_offsets[-1]) must be given under graph capture, where reading it back from
-    the device is not allowed."""
+    the device is not allowed.  trace (int32 [total_chains][ceil((n_burn + n_sweeps) N / 32)]) receives
+    the accept bit of every proposal."""
     n_inst, P = t_params.shape
     total = int(chain_offsets[-1].item()) if total_chains is None else int(total_chains)
+    words = ((n_burn + n_sweeps) * plan.N + 31) // 32
+    tr = None if trace is None else _ptr(trace, torch.int32, (total, words), "trace")
     g = psi_gs.struct()
     _check(lib().crbm_batched_moments(
         plan.handle, ctypes.byref(g), _ptr(t_params, torch.complex64, (n_inst, plan.P), "t_params"),
         _ptr(betas, torch.complex128, (n_inst,), "betas"), _ptr(q, torch.float64, (n_inst, 2), "q"),
         _ptr(chain_offsets, torch.int64, (n_inst + 1,), "chain_offsets"), n_inst, total, n_burn, n_sweeps, proposal,
-        seed, _ptr(mu_out, torch.complex128, (n_inst, 2), "mu_out"), _stream(stream)))
+        seed, _ptr(mu_out, torch.complex128, (n_inst, 2), "mu_out"), tr, _stream(stream)))
 
 
 def batched_autotune(plan: Plan, psi_gs: RBM, t_params, betas, q, chain_offsets, n_sweeps_probe: int,

@@ -952,11 +952,13 @@ static int batched_args(crbm_plan p, const crbm_rbm* gs, const void* t_params, c
 
 int crbm_batched_moments(crbm_plan p, const crbm_rbm* gs, const void* t_params, const double* betas, const double* q,
                          const int64_t* offsets, int n_inst, int64_t total, int n_burn, int n_sweeps, int proposal,
-                         uint64_t seed, void* mu_out, hipStream_t stream) {
+                         uint64_t seed, void* mu_out, uint32_t* trace, hipStream_t stream) {
     BatchedArgs A{};
     if (int rc = batched_args(p, gs, t_params, betas, q, offsets, n_inst, total, n_burn, n_sweeps, proposal, seed, A))
         return rc;
     if (!mu_out) return fail(CRBM_EINVAL, "mu_out is NULL");
+    A.trace = trace;
+    A.trace_words = (int)(((long)(n_burn + n_sweeps) * p->N + 31) / 32);
     p->prof.begin(PROF_BATCHED, stream);
     hipError_t e = launch_batched(A, p->b_blocks, p->b_waves, static_cast<double2*>(mu_out), stream);
     p->prof.end(stream);

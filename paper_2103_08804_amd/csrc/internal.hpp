@@ -154,6 +154,8 @@ struct BatchedArgs {
     uint64_t seed;
     unsigned long long* counter;
     double2* partial;            // [total][2]
+    uint32_t* trace;             // [total][trace_words] accept bits, or null
+    int trace_words;
 };
 hipError_t launch_batched(const BatchedArgs& A, int blocks, int waves_per_block, double2* mu, hipStream_t stream);
 

@@ -108,9 +108,15 @@ __global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
         const double2 beta = A.betas[inst];
         double m0 = 0.0, mr = 0.0, mi = 0.0;
         const int total_sweeps = A.n_burn + A.n_sweeps;
+        uint32_t tw = 0;                          // accept bits of the current trace word
+        uint32_t* trow = A.trace ? A.trace + (long)g * A.trace_words : nullptr;
         for (int sw = 0; sw < total_sweeps; ++sw) {
             for (int p = 0; p < N; ++p) {
                 const uint64_t t = (uint64_t)sw * N + p;
+                if (trow && t > 0 && (t & 31) == 0) {
+                    if (lane == 0) trow[(t - 1) >> 5] = tw;
+                    tw = 0;
+                }
                 const u32x4 x = draw(A.seed, (uint32_t)g, t, 0u);
                 const int i = uniform(draw_index(x.x, N));
                 const int j = uniform(draw_index(x.y, N));
@@ -142,6 +148,7 @@ __global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
                 if (pair) da -= m2si * A.gs.a[j].x;
                 dl += da;
                 if (u < __expf(2.f * dl)) {
+                    tw |= 1u << (t & 31);
 #pragma unroll
                     for (int e = 0; e < E; ++e) {
                         const int k = e * kWave + lane;
@@ -185,6 +192,7 @@ __global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
         if (lane == 0) {
             A.partial[2 * g] = make_double2(m0, 0.0);
             A.partial[2 * g + 1] = make_double2(mr, mi);
+            if (trow) trow[((uint64_t)total_sweeps * N - 1) >> 5] = tw;
         }
     }
 }

@@ -87,3 +87,25 @@ def random_spins(seed, n, N, zero_magnetisation=False):
         return (2 * r.integers(0, 2, size=(n, N)) - 1).astype(np.int8)
     base = np.array([1] * (N // 2) + [-1] * (N - N // 2), dtype=np.int8)
     return np.stack([r.permutation(base) for _ in range(n)]).astype(np.int8)
+
+
+def bz_path(n_points):
+    """n_points momenta equally spaced in arc length along Gamma(0,0) -> X(pi,0) -> M(pi,pi) -> Gamma."""
+    corners = np.array([[0.0, 0.0], [math.pi, 0.0], [math.pi, math.pi], [0.0, 0.0]])
+    seg = np.linalg.norm(np.diff(corners, axis=0), axis=1)
+    cum = np.concatenate([[0.0], np.cumsum(seg)])
+    out = []
+    for t in np.linspace(0.0, cum[-1], n_points, endpoint=False):
+        k = min(int(np.searchsorted(cum, t, side="right")) - 1, len(seg) - 1)
+        out.append(corners[k] + (t - cum[k]) / seg[k] * (corners[k + 1] - corners[k]))
+    return np.array(out)
+
+
+def batched_instances(n_q=32, n_ord=64, seed=4, lo=256, hi=2048):
+    """The batched-moment layout: n_q momenta on the Brillouin-zone path, each repeated for n_ord
+    Chebyshev orders; chain counts per instance uniform in [lo, hi].  Returns (counts, offsets, qs)."""
+    n_inst = n_q * n_ord
+    counts = np.random.default_rng(seed).integers(lo, hi + 1, n_inst)
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    qs = np.repeat(bz_path(n_q), n_ord, axis=0)
+    return counts, offsets, qs

@@ -47,7 +47,7 @@ def test_batched_vs_oracle(orc, kind, Lx, Ly, M, counts, proposal):
     torch.cuda.synchronize()
     gs = to_oracle_rbm(orc, gs_d)
     lat = orc.Lattice(kind, Lx, Ly)
-    ref, amb = orc.batched_moments(gs, tv.astype(np.complex128), betas, qs, offsets, lat, 2, 5, proposal, 99)
+    ref, amb, _ = orc.batched_moments(gs, tv.astype(np.complex128), betas, qs, offsets, lat, 2, 5, proposal, 99)
     assert amb == 0          # no step close enough to the threshold for FP32 to take the other branch
     assert rel_err(np_of(mu), ref) < 1e-5
 

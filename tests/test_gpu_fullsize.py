@@ -1,8 +1,9 @@
-"""GPU parity at the full size of the 10x10, alpha = 4 workload (N = 100, M = 400, P = 40,500;
-4096 chains x 128 sweeps = 524,288 samples per step), in the launch configuration the benchmark
-step uses: one plan with the dense S, every call over all 524,288 samples.  Outputs the oracle
-can compute one at a time are compared on a sample of them; the rest through properties that
-hold at any size.
+"""GPU parity at the full sizes of the benchmark workloads, in the launch configurations the
+benchmark uses.  Outputs the oracle can compute one at a time are compared on a sample of them;
+the rest through properties that hold at any size.
+
+10x10, alpha = 4 (N = 100, M = 400, P = 40,500; 4096 chains x 128 sweeps = 524,288 samples per
+step; one plan with the dense S, every call over all samples):
 
 * Metropolis: 8 of the 4096 chains, spread over the launch (first, last, both halves), replayed
   by the oracle under their own chain indices: trajectories, acceptance counts and end states
@@ -21,6 +22,20 @@ hold at any size.
   FP32 accumulator that adds all n products of a sample range (4.3e-5 at n = 32,768).
 * Moments n <= 4 at q = (pi, pi) over all 524,288 samples (the benchmark runs 20 orders as 20
   launches of the same kernels): 1e-5 relative to max |mu_n| as at the small sizes.
+
+40-site chain, alpha = 2 (P = 3320; 1024 chains x 256 sweeps = 262,144 samples; FP32 S and the
+FP64 Cholesky solve): 6 chains replayed bit-exact; gamma, beta, F and S entries as above with the
+FP32 accumulation bound; the Cholesky solution's residual against the matrix it factors (the lower
+triangle's Hermitian completion plus eps I) within 8 P 2^-53 |A|_F |x|; the update exact.
+
+8x8, alpha = 2, batched moments (2048 (q, n) instances, 256-2048 chains each, 2.37 M chains, 4 + 16
+sweeps, one persistent launch after the autotuner): the launch records every accept bit, and the
+oracle replays six instances (first, second, middle, last, fewest and most chains) under their global
+chain indices: no mismatch, per-instance moments within 1e-5 relative.
+
+16x16, alpha = 2 (P = 131,840; 8192 frozen samples): the fidelity surrogate's loss within 1e-5 and
+the hand-written backward on 36 parameter indices within 1e-4 of their largest (complex64 output),
+against the oracle's target ratio over all 8192 samples and its per-index gradient.
 """
 import numpy as np
 import pytest
@@ -225,3 +240,150 @@ def test_fullsize_moments(orc, big):
     ref = orc.moments(big["gs"], ts, betas, q, big["lat"], big["sig"])
     print("moments", np_of(mu), ref)
     assert rel_err(np_of(mu), ref) < TOL
+
+
+# ------------------------------------------------------------------ 40-site chain, FP32 S + Cholesky
+def test_fullsize_chain40_cholesky_step(orc):
+    wl = synth.CHAIN40
+    n_, m_ = wl.N, wl.M
+    p_ = n_ + m_ + n_ * m_
+    C, sweeps = wl.chains, wl.sweeps
+    ns = C * sweeps
+    fit_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(wl.param_seed, n_, m_, wl.param_std)))
+    fit = to_oracle_rbm(orc, fit_d)
+    plan = crbm.Plan(wl.kind, wl.Lx, wl.Ly, m_, ns, crbm.PLAN_CHOLESKY | crbm.PLAN_DENSE_S)
+    # sampler at 1024 x 256: six chains replayed under their own indices
+    spins = torch.zeros(C, n_, dtype=torch.int8, device="cuda")
+    crbm.init_chains(plan, spins, wl.chain_seed, True)
+    start = orc.init_chains(n_, C, wl.chain_seed, 1)
+    words = (sweeps * n_ + 31) // 32
+    samples = torch.zeros(sweeps, C, n_, dtype=torch.int8, device="cuda")
+    trace = torch.zeros(C, words, dtype=torch.int32, device="cuda")
+    crbm.sample(plan, fit_d, spins, sweeps, crbm.EXCHANGE, 21, 16 * n_, samples_out=samples, trace=trace)
+    torch.cuda.synchronize()
+    ids = np.array([0, 1, 511, 512, C - 2, C - 1], np.int32)
+    sub = np.ascontiguousarray(start[ids])
+    smp_ref, _, amb, mis = orc.metropolis(fit, sub, sweeps, 1, 21, 16 * n_, trace=np_of(trace).view(np.uint32)[ids],
+                                          chain_ids=ids)
+    assert mis == 0 and amb <= max(3, 1e-3 * sweeps * n_ * len(ids))
+    assert np.array_equal(np_of(samples)[:, ids], smp_ref)
+    # the SR step over all 262,144 samples (seeded configurations)
+    sig = synth.random_spins(wl.chain_seed, ns, n_, True)
+    sd = torch.from_numpy(sig).cuda()
+    T = torch.zeros(ns, m_, dtype=torch.complex64, device="cuda")
+    crbm.local_estimators(plan, fit_d, sd, tanh_out=T)
+    r = np.random.default_rng(6)
+    R = (1 + 0.3 * r.normal(size=ns) + 0.2j * r.normal(size=ns)).astype(np.complex64)
+    before = [t.clone() for t in (fit_d.a, fit_d.b, fit_d.W)]
+    stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+    crbm.sr_step(plan, fit_d, sd, T, torch.from_numpy(R).cuda(), 0.1, wl.diag_shift, crbm.CHOLESKY, crbm.FP32, 1e-6,
+                 1, stats)
+    S = torch.zeros(p_, p_, dtype=torch.complex64, device="cuda")
+    F = torch.zeros(p_, dtype=torch.complex128, device="cuda")
+    x = torch.zeros_like(F)
+    crbm.copy_plan_buffer(plan, crbm.BUF_S, S)
+    crbm.copy_plan_buffer(plan, crbm.BUF_F, F)
+    crbm.copy_plan_buffer(plan, crbm.BUF_DALPHA, x)
+    torch.cuda.synchronize()
+    st = np_of(stats)
+    assert int(st[6]) == 0, st
+    a_ = [0, 1, 20, n_ - 1]
+    b_ = [n_ + j for j in (0, 15, 16, m_ - 1)]
+    w_ij = [(0, 0), (0, 15), (0, 16), (7, 15), (8, 16), (7, m_ - 1), (8, 0), (n_ - 1, 0), (n_ - 1, m_ - 1), (31, 47)]
+    rr = np.random.default_rng(78)
+    w_ij += [(int(i), int(j)) for i, j in zip(rr.integers(0, n_, 18), rr.integers(0, m_, 18))]
+    ks = np.array(a_ + b_ + [n_ + m_ + i * m_ + j for i, j in w_ij], np.int64)
+    e = orc.sr_entries(fit, sig, R.astype(np.complex128), 0.1, ks)
+    assert abs(st[0] - e["gamma"]) < 1e-6 * e["gamma"]
+    assert abs(complex(st[1], st[2]) - e["beta"]) < 1e-6 * abs(e["beta"])
+    Fg = np_of(F)
+    assert np.max(np.abs(Fg[ks] - e["F"])) < TOL * np.abs(Fg).max()
+    kt = torch.from_numpy(ks).cuda()
+    Sk = np_of(S.index_select(0, kt).index_select(1, kt)).astype(np.complex128)
+    err = np.abs(Sk - e["S"])
+    bound = 4.0 * np.sqrt(ns) * 2.0 ** -24 * _cs_scale(e)
+    print("chain40 FP32 S: max error / bound", (err / bound).max())
+    assert np.all(err <= bound)
+    S64 = S.to(torch.complex128)
+    A = torch.tril(S64) + torch.tril(S64, -1).mH + wl.diag_shift * torch.eye(p_, dtype=torch.complex128,
+                                                                             device="cuda")
+    res = torch.linalg.vector_norm(A @ x - F).item()
+    scale = torch.linalg.matrix_norm(A).item() * torch.linalg.vector_norm(x).item()
+    print("chain40 Cholesky residual ratio", res / scale)
+    assert res < 8 * p_ * 2.0 ** -53 * scale
+    dx = x.to(torch.complex64)
+    for got, old, part in zip((fit_d.a, fit_d.b, fit_d.W), before, (dx[:n_], dx[n_:n_ + m_], dx[n_ + m_:].view(n_, m_))):
+        assert torch.equal(got, old + part)
+
+
+# ------------------------------------------------------------------ 8x8 batched moments
+def test_fullsize_batched_instances(orc):
+    wl = synth.SQUARE8
+    n_, m_ = wl.N, wl.M
+    counts, offsets, qs = synth.batched_instances()
+    n_inst = counts.shape[0]
+    total = int(offsets[-1])
+    lat = orc.Lattice(wl.kind, wl.Lx, wl.Ly)
+    gs_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(wl.param_seed, n_, m_, wl.param_std)))
+    gs = to_oracle_rbm(orc, gs_d)
+    tv = np.stack([orc.RBM(*synth.random_rbm_arrays(wl.param_seed + 1 + i, n_, m_, wl.param_std)).vector()
+                   for i in range(n_inst)]).astype(np.complex64)
+    r = np.random.default_rng(8)
+    betas = r.normal(size=n_inst) + 1j * r.normal(size=n_inst)
+    plan = crbm.Plan(wl.kind, wl.Lx, wl.Ly, m_, total)
+    tp, bd = torch.from_numpy(tv).cuda(), torch.from_numpy(betas).cuda()
+    qd, od = torch.from_numpy(np.ascontiguousarray(qs)).cuda(), torch.from_numpy(offsets).cuda()
+    n_burn, n_sweeps = 4, wl.sweeps
+    crbm.batched_autotune(plan, gs_d, tp, bd, qd, od, 1, crbm.EXCHANGE, wl.chain_seed)
+    words = ((n_burn + n_sweeps) * n_ + 31) // 32
+    trace = torch.zeros(total, words, dtype=torch.int32, device="cuda")
+    mu = torch.zeros(n_inst, 2, dtype=torch.complex128, device="cuda")
+    crbm.batched_moments(plan, gs_d, tp, bd, qd, od, n_burn, n_sweeps, crbm.EXCHANGE, wl.chain_seed, mu, trace=trace)
+    torch.cuda.synchronize()
+    tr = np_of(trace).view(np.uint32)
+    mu_g = np_of(mu)
+    sel = sorted({0, 1, n_inst // 2, n_inst - 1, int(np.argmin(counts)), int(np.argmax(counts))})
+    for i in sel:
+        o = offsets[i:i + 2]
+        ref, amb, mis = orc.batched_moments(gs, tv[i:i + 1].astype(np.complex128), betas[i:i + 1], qs[i:i + 1], o,
+                                            lat, n_burn, n_sweeps, 1, wl.chain_seed, trace=tr[o[0]:o[1]])
+        print("instance", i, "chains", counts[i], "ambiguous", amb, "mismatch", mis)
+        assert mis == 0
+        assert amb <= max(3, 1e-4 * counts[i] * (n_burn + n_sweeps) * n_)
+        assert rel_err(mu_g[i], ref[0]) < TOL
+
+
+# ------------------------------------------------------------------ 16x16 fidelity gradient
+def test_fullsize_grad16_fidelity(orc):
+    from paper_2103_08804_amd.autograd import fidelity_loss
+    wl = synth.SQUARE16
+    n_, m_ = wl.N, wl.M
+    C = wl.chains
+    lat = orc.Lattice(wl.kind, wl.Lx, wl.Ly)
+    rb = lambda s: to_device_rbm(orc.RBM(*synth.random_rbm_arrays(s, n_, m_, wl.param_std)))
+    psm_d, psn_d, fit_d = rb(wl.param_seed + 1), rb(wl.param_seed + 2), rb(wl.param_seed + 3)
+    plan = crbm.Plan(wl.kind, wl.Lx, wl.Ly, m_, C)
+    E0 = synth.E0_PER_SITE_SQUARE * n_
+    W_scale = 1.5 * abs(E0)
+    E_c = E0 + 0.9875 * W_scale
+    q = (np.pi, np.pi)
+    cheb = crbm.make_cheb(2, E_c, W_scale, 1.0, 1.0, q)
+    sig = synth.random_spins(wl.chain_seed, C, n_, True)
+    a, b, W = (t.clone().requires_grad_(True) for t in (fit_d.a, fit_d.b, fit_d.W))
+    L = fidelity_loss(crbm.RBM(a, b, W), plan, torch.from_numpy(sig).cuda(), psn_d, psm_d, cheb)
+    L.backward()
+    torch.cuda.synchronize()
+    g = np.concatenate([np_of(a.grad), np_of(b.grad), np_of(W.grad).ravel()])
+    fit, psn, psm = (to_oracle_rbm(orc, r_) for r_ in (fit_d, psn_d, psm_d))
+    R_ref = orc.target_ratio(fit, psn, psm, lat, sig, 2, E_c, W_scale, 1.0, 1.0, q)
+    a_ = [0, 1, 128, n_ - 1]
+    b_ = [n_ + j for j in (0, 15, 16, m_ - 1)]
+    rr = np.random.default_rng(79)
+    w_ij = [(0, 0), (n_ - 1, m_ - 1), (7, 15), (8, 16)] + [(int(i), int(j)) for i, j in
+                                                          zip(rr.integers(0, n_, 24), rr.integers(0, m_, 24))]
+    ks = np.array(a_ + b_ + [n_ + m_ + i * m_ + j for i, j in w_ij], np.int64)
+    L_ref, g_ref = orc.fidelity_grad_entries(fit, sig, R_ref, ks)
+    print("16x16 loss", float(L.detach()), L_ref, "grad error", np.abs(g[ks] - g_ref).max(), np.abs(g_ref).max())
+    assert abs(float(L.detach()) - L_ref) < TOL * max(1.0, L_ref)
+    assert np.max(np.abs(g[ks] - g_ref)) < 1e-4 * np.abs(g_ref).max()
+

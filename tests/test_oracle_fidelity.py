@@ -52,3 +52,20 @@ def test_fidelity_gradient_finite_differences(orc):
         Lm, _ = loss(orc.RBM.from_vector(v0 - h * dvec, N, M))
         dd = (Lp - Lm) / (2 * h)
         assert abs(dd - np.sum((g.conj() * dvec).real)) < 1e-6 * max(1.0, np.abs(g).max())
+
+
+def test_fidelity_grad_entries_match_the_full_gradient(orc):
+    """The entry-by-entry gradient (for models whose O does not fit in memory) equals the full one on
+    scrambled and repeated indices of all three parameter kinds."""
+    N, M = 7, 5
+    lat = orc.Lattice(0, N)
+    fit = orc.RBM(*synth.random_rbm_arrays(70, N, M, 0.3))
+    psn = orc.RBM(*synth.random_rbm_arrays(71, N, M, 0.3))
+    psm = orc.RBM(*synth.random_rbm_arrays(72, N, M, 0.3))
+    sig = synth.random_spins(73, 200, N, False)
+    R = orc.target_ratio(fit, psn, psm, lat, sig, 2, -1.3, 2.5, 0.9, 1.1)
+    L, g = orc.fidelity_grad(fit, sig, R)
+    ks = np.array([46, 0, 6, 7, 11, 12, 30, 7, 3], np.int64)            # P = 7 + 5 + 35 = 47
+    Le, ge = orc.fidelity_grad_entries(fit, sig, R, ks)
+    assert abs(Le - L) < 1e-14 * max(1.0, L)
+    assert np.max(np.abs(ge - g[ks])) < 1e-13 * max(1.0, np.abs(g).max())
