@@ -267,6 +267,10 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
             }
     }
     p->n_bonds = (int)bonds.size();
+    if (p->n_bonds > kMaxBonds) {
+        delete p;
+        return fail(CRBM_EUNSUPPORTED, "%d bonds exceed the limit of %d", (int)bonds.size(), kMaxBonds);
+    }
 
     const long P = p->P, M = n_hidden, S = max_samples;
     const long plane = (N + 1) * (M + 1);

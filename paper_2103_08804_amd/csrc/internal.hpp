@@ -15,6 +15,10 @@ struct RbmView {            // device pointers, complex64 interleaved
     const float2* W;
 };
 
+// bonds of the largest lattice (square, N <= 256 sites, 2 N bonds); the local-estimator kernel keeps
+// a per-wave list of the anti-aligned ones in LDS
+constexpr int kMaxBonds = 512;
+
 struct Geometry {
     int N, M, P;
     int n_bonds;

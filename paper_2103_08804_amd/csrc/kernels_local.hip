@@ -230,46 +230,121 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __rest
                     : A.local_op ? make_float2(0.5f * (float)sp.get(0), 0.f) : fq_wave(sp, lane, g, A.q0, A.q1);
     const float inv_sqrt_n = rsqrtf((float)N);
 
-    float2 acc = make_float2(0.f, 0.f);
-    const float J = (float)g.J;
-    for (int bnd = 0; bnd < g.n_bonds; ++bnd) {
-        const int2 ij = g.bonds[bnd];
-        const int i = uniform(ij.x), j = uniform(ij.y);
-        const int si = sp.get(i), sj = sp.get(j);
-        acc = cadd(acc, cscale(d0, 0.25f * J * (float)(si * sj)));
-        if (si == sj) continue;
-        const float m2si = -2.f * (float)si;
-        // Delta_k = -2 s_i D_k with D = W_i - W_j: cosh Delta = cosh 2D, sinh Delta = -s_i sinh 2D,
-        // both read from the bond's table
-        const float4* tab = g.bond_tab + (long)bnd * M;
-        const float nsi = -(float)si;
-        float2 prod = make_float2(1.f, 0.f);
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int k = e * kWave + lane;
-            if (k < M) {
-                const float4 q = tab[k];
-                const float2 ts = cmul(TE[e], make_float2(q.z, q.w));
-                prod = cmul(prod, make_float2(fmaf(nsi, ts.x, q.x), fmaf(nsi, ts.y, q.y)));
-            }
+    // anti-aligned bonds of this sample, in bond order, compacted into the wave's LDS list
+    __shared__ short s_anti[4][kMaxBonds];
+    short* lst = s_anti[threadIdx.x >> 6];
+    const int8_t* srow = A.samples + s * N;
+    int n_anti = 0;
+    for (int c0 = 0; c0 < g.n_bonds; c0 += kWave) {
+        const int bnd = c0 + lane;
+        bool anti = false;
+        if (bnd < g.n_bonds) {
+            const int2 ij = g.bonds[bnd];
+            anti = srow[ij.x] != srow[ij.y];
         }
-        float2 lg = make_float2(0.5f * logf(prod.x * prod.x + prod.y * prod.y), atan2f(prod.y, prod.x));
-        lg = wave_sum(lg);
-        const float2 da = cscale(csub(pe.a[i], pe.a[j]), m2si);
-        const float2 rho = cexpf(cadd(lg, da));
-        float2 d1 = make_float2(1.f, 0.f);
-        if (with_fq) {
-            if (A.local_op) {
-                // s_0 / 2 after the swap of sites i and j (s_j = -s_i)
-                d1 = make_float2(i == 0 ? -0.5f * (float)si : (j == 0 ? 0.5f * (float)si : d0.x), 0.f);
-            } else {
-                // f_q(s^{ij}) = f_q(s) - N^{-1/2} s_i (e^{-iq.r_i} - e^{-iq.r_j})
-                const float2 pd = csub(site_phase(i, g.kind, g.Lx, A.q0, A.q1), site_phase(j, g.kind, g.Lx, A.q0, A.q1));
-                d1 = csub(d0, cscale(pd, inv_sqrt_n * (float)si));
-            }
-        }
-        acc = cadd(acc, cscale(cmul(d1, rho), 0.5f * J));
+        const uint64_t m = __ballot(anti);
+        if (anti) lst[n_anti + __popcll(m & ((1ull << lane) - 1ull))] = (short)bnd;
+        n_anti += __popcll(m);
     }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    const float J = (float)g.J;
+    // diagonal part: J/4 s_i s_j over all bonds, s_i s_j = -1 on the anti-aligned ones
+    const float2 diag = cscale(d0, 0.25f * J * (float)(g.n_bonds - 2 * n_anti));
+    float2 acc = make_float2(0.f, 0.f);        // off-diagonal part, on lanes 8 g (group g's bond)
+    // Bonds in batches of 8.  Each lane forms its share of a bond's factor product as
+    // (log |p|, p/|p|); a reduce-scatter over lane bits 5, 4, 3 then leaves bond b0 + g of the
+    // batch on the 8 lanes of group g = lane / 8, which add (multiply) the last 8 shares, so the
+    // exponentials and phases of the 8 bonds are evaluated lane-parallel.
+    for (int b0 = 0; b0 < n_anti; b0 += 8) {
+        float lm[8];
+        float2 ph[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            lm[b] = 0.f;
+            ph[b] = make_float2(1.f, 0.f);
+            if (b0 + b < n_anti) {
+                const int bnd = uniform((int)lst[b0 + b]);
+                const int i = uniform(g.bonds[bnd].x);
+                // Delta_k = -2 s_i D_k with D = W_i - W_j: cosh Delta = cosh 2D, sinh Delta = -s_i sinh 2D,
+                // both read from the bond's table
+                const float nsi = -(float)sp.get(i);
+                const float4* tab = g.bond_tab + (long)bnd * M;
+                float2 prod = make_float2(1.f, 0.f);
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int k = e * kWave + lane;
+                    if (k < M) {
+                        const float4 q = tab[k];
+                        const float2 ts = cmul(TE[e], make_float2(q.z, q.w));
+                        prod = cmul(prod, make_float2(fmaf(nsi, ts.x, q.x), fmaf(nsi, ts.y, q.y)));
+                    }
+                }
+                const float n2 = prod.x * prod.x + prod.y * prod.y;
+                lm[b] = 0.5f * logf(n2);
+                const float inv = n2 > 0.f ? rsqrtf(n2) : 0.f;
+                ph[b] = n2 > 0.f ? cscale(prod, inv) : make_float2(1.f, 0.f);
+            }
+        }
+        // reduce-scatter: across lane bit 5 keep 4 of 8 bonds, bit 4 keep 2, bit 3 keep 1
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const bool hi = (lane & 32) != 0;
+            const float kl = hi ? lm[t + 4] : lm[t], sl = hi ? lm[t] : lm[t + 4];
+            const float2 kp = hi ? ph[t + 4] : ph[t], sp2 = hi ? ph[t] : ph[t + 4];
+            lm[t] = kl + __shfl_xor(sl, 32);
+            ph[t] = cmul(kp, make_float2(__shfl_xor(sp2.x, 32), __shfl_xor(sp2.y, 32)));
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const bool hi = (lane & 16) != 0;
+            const float kl = hi ? lm[t + 2] : lm[t], sl = hi ? lm[t] : lm[t + 2];
+            const float2 kp = hi ? ph[t + 2] : ph[t], sp2 = hi ? ph[t] : ph[t + 2];
+            lm[t] = kl + __shfl_xor(sl, 16);
+            ph[t] = cmul(kp, make_float2(__shfl_xor(sp2.x, 16), __shfl_xor(sp2.y, 16)));
+        }
+        {
+            const bool hi = (lane & 8) != 0;
+            const float kl = hi ? lm[1] : lm[0], sl = hi ? lm[0] : lm[1];
+            const float2 kp = hi ? ph[1] : ph[0], sp2 = hi ? ph[0] : ph[1];
+            lm[0] = kl + __shfl_xor(sl, 8);
+            ph[0] = cmul(kp, make_float2(__shfl_xor(sp2.x, 8), __shfl_xor(sp2.y, 8)));
+        }
+#pragma unroll
+        for (int o = 4; o >= 1; o >>= 1) {
+            lm[0] += __shfl_xor(lm[0], o);
+            ph[0] = cmul(ph[0], make_float2(__shfl_xor(ph[0].x, o), __shfl_xor(ph[0].y, o)));
+        }
+        const int bb = b0 + (lane >> 3);
+        if (bb < n_anti) {
+            const int bnd = lst[bb];
+            const int2 ij = g.bonds[bnd];
+            const int i = ij.x, j = ij.y;
+            const float si = (float)srow[i];
+            const float m2si = -2.f * si;
+            // amplitude ratio psi(s^ij)/psi(s) = exp(sum log|p| + Re da) * (phase) * exp(i Im da)
+            const float2 da = cscale(csub(pe.a[i], pe.a[j]), m2si);
+            const float ph2 = ph[0].x * ph[0].x + ph[0].y * ph[0].y;
+            const float2 u = cscale(ph[0], rsqrtf(ph2));
+            float sn, cs;
+            sincosf(da.y, &sn, &cs);
+            const float2 rho = cscale(cmul(u, make_float2(cs, sn)), expf(lm[0] + da.x));
+            float2 d1 = make_float2(1.f, 0.f);
+            if (with_fq) {
+                if (A.local_op) {
+                    // s_0 / 2 after the swap of sites i and j (s_j = -s_i)
+                    d1 = make_float2(i == 0 ? -0.5f * si : (j == 0 ? 0.5f * si : d0.x), 0.f);
+                } else {
+                    // f_q(s^{ij}) = f_q(s) - N^{-1/2} s_i (e^{-iq.r_i} - e^{-iq.r_j})
+                    const float2 pd = csub(site_phase(i, g.kind, g.Lx, A.q0, A.q1), site_phase(j, g.kind, g.Lx, A.q0, A.q1));
+                    d1 = csub(d0, cscale(pd, inv_sqrt_n * si));
+                }
+            }
+            if ((lane & 7) == 0) acc = cadd(acc, cscale(cmul(d1, rho), 0.5f * J));
+        }
+    }
+    acc = cadd(wave_sum(acc), diag);
     if (A.eloc_out && lane == 0) A.eloc_out[s] = acc;
     if (!A.cheb_mode || !A.R_out) return;
 
