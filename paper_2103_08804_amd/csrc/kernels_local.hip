@@ -145,19 +145,153 @@ __device__ __forceinline__ float2 a_dot_sigma(const float2* a, const WaveSpins& 
 }
 
 // ------------------------------------------------------------------ local estimators
-// One wave per sample.  th1/thn/thm: theta of fit / psi_n / psi_{n-1} (precomputed).
+// A wave takes kLocalSpw consecutive samples.  Per sample it evaluates log psi, tanh theta and O
+// (lanes over the hidden units) and marks the anti-aligned bonds; then it walks the bonds once:
+// a bond's table row is read once and serves every sample of the wave in which the bond is
+// anti-aligned.  Each such (sample, bond) pair leaves its per-lane share of the factor product,
+// as (log |p|, p/|p|), in a per-wave LDS ring; every 8 pairs a reduce-scatter over lane bits
+// 5, 4, 3 gives pair g of the batch to the 8 lanes of group g = lane / 8, which finish it (the
+// exponential, the phase of a and the f_q factors) lane-parallel.
+constexpr int kLocalSpw = 4;       // samples per wave
+constexpr int kRing = 16;          // ring slots per wave: at most 7 + kLocalSpw pairs wait
+
+// Reduce-scatter of 8 bond shares (log |p|, p/|p|) over the wave: across lane bit 5 keep 4 of the 8,
+// bit 4 keep 2, bit 3 keep 1, then add (multiply) within the 8 lanes, so that lanes 8 g .. 8 g + 7
+// end with the whole of share g in lm[0], ph[0].
+__device__ __forceinline__ void reduce_scatter8(float (&lm)[8], float2 (&ph)[8], int lane) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const bool hi = (lane & 32) != 0;
+        const float kl = hi ? lm[t + 4] : lm[t], sl = hi ? lm[t] : lm[t + 4];
+        const float2 kp = hi ? ph[t + 4] : ph[t], sp = hi ? ph[t] : ph[t + 4];
+        lm[t] = kl + __shfl_xor(sl, 32);
+        ph[t] = cmul(kp, make_float2(__shfl_xor(sp.x, 32), __shfl_xor(sp.y, 32)));
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const bool hi = (lane & 16) != 0;
+        const float kl = hi ? lm[t + 2] : lm[t], sl = hi ? lm[t] : lm[t + 2];
+        const float2 kp = hi ? ph[t + 2] : ph[t], sp = hi ? ph[t] : ph[t + 2];
+        lm[t] = kl + __shfl_xor(sl, 16);
+        ph[t] = cmul(kp, make_float2(__shfl_xor(sp.x, 16), __shfl_xor(sp.y, 16)));
+    }
+    {
+        const bool hi = (lane & 8) != 0;
+        const float kl = hi ? lm[1] : lm[0], sl = hi ? lm[0] : lm[1];
+        const float2 kp = hi ? ph[1] : ph[0], sp = hi ? ph[0] : ph[1];
+        lm[0] = kl + __shfl_xor(sl, 8);
+        ph[0] = cmul(kp, make_float2(__shfl_xor(sp.x, 8), __shfl_xor(sp.y, 8)));
+    }
+#pragma unroll
+    for (int o = 4; o >= 1; o >>= 1) {
+        lm[0] += __shfl_xor(lm[0], o);
+        ph[0] = cmul(ph[0], make_float2(__shfl_xor(ph[0].x, o), __shfl_xor(ph[0].y, o)));
+    }
+}
+
+// One lane's share of the factor product of an anti-aligned bond: the bond's row (cosh 2D, sinh 2D)
+// with D = W_i - W_j gives cosh Delta = cosh 2D and sinh Delta = -s_i sinh 2D for Delta = -2 s_i D.
 template <int E>
-__global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __restrict__ th1g,
-                                               const float2* __restrict__ thng, const float2* __restrict__ thmg) {
-    const int lane = threadIdx.x & 63;
-    const long s = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (s >= A.n_samples) return;
+__device__ __forceinline__ float2 bond_share(const float4 (&tq)[E], const float2 (&te)[E], float nsi) {
+    float2 prod = make_float2(1.f, 0.f);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const float2 ts = cmul(te[e], make_float2(tq[e].z, tq[e].w));
+        prod = cmul(prod, make_float2(fmaf(nsi, ts.x, tq[e].x), fmaf(nsi, ts.y, tq[e].y)));
+    }
+    return prod;
+}
+
+// The bond's row of the table for this lane's hidden units (padding lanes give the factor 1).
+template <int E>
+__device__ __forceinline__ void bond_row(const Geometry& g, int bnd, int lane, float4 (&tq)[E]) {
+    const float4* tab = g.bond_tab + (long)bnd * g.M;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = e * kWave + lane;
+        tq[e] = (k < g.M) ? tab[k] : make_float4(1.f, 0.f, 0.f, 0.f);
+    }
+}
+
+// The exchange term of bond (i, j) for the sample with spin s_i = si, given the whole factor product
+// as (log |p|, phase): J/2 d1 psi(s^ij)/psi(s) with psi(s^ij)/psi(s) = exp(lm + Re da) phase
+// exp(i Im da), da = -2 s_i (a_i - a_j), and d1 the diagonal factor of t_0 after the swap.
+__device__ __forceinline__ float2 bond_term(const LocalArgs& A, const RbmView& pe, int i, int j, float si, float lm,
+                                            float2 ph, float2 d0, bool with_fq, float inv_sqrt_n) {
+    const Geometry& g = A.g;
+    const float2 da = cscale(csub(pe.a[i], pe.a[j]), -2.f * si);
+    const float2 u = cscale(ph, rsqrtf(ph.x * ph.x + ph.y * ph.y));
+    float sn, cs;
+    sincosf(da.y, &sn, &cs);
+    const float2 rho = cscale(cmul(u, make_float2(cs, sn)), expf(lm + da.x));
+    float2 d1 = make_float2(1.f, 0.f);
+    if (with_fq) {
+        if (A.local_op) {
+            // s_0 / 2 after the swap of sites i and j (s_j = -s_i)
+            d1 = make_float2(i == 0 ? -0.5f * si : (j == 0 ? 0.5f * si : d0.x), 0.f);
+        } else {
+            // f_q(s^{ij}) = f_q(s) - N^{-1/2} s_i (e^{-iq.r_i} - e^{-iq.r_j})
+            const float2 pd = csub(site_phase(i, g.kind, g.Lx, A.q0, A.q1), site_phase(j, g.kind, g.Lx, A.q0, A.q1));
+            d1 = csub(d0, cscale(pd, inv_sqrt_n * si));
+        }
+    }
+    return cscale(cmul(d1, rho), 0.5f * (float)g.J);
+}
+
+template <int SPW>
+__device__ __forceinline__ void local_flush(const LocalArgs& A, const RbmView& pe, int lane, long s0, int done,
+                                            int cnt, bool with_fq, float inv_sqrt_n, const float2 (&d0)[SPW],
+                                            float2 (&acc)[SPW], float (*s_lm)[kWave], float2 (*s_ph)[kWave],
+                                            const int* s_item) {
+    const Geometry& g = A.g;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float lm[8];
+    float2 ph[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const int slot = (done + b) & (kRing - 1);
+        lm[b] = b < cnt ? s_lm[slot][lane] : 0.f;
+        ph[b] = b < cnt ? s_ph[slot][lane] : make_float2(1.f, 0.f);
+    }
+    reduce_scatter8(lm, ph, lane);
+    const int gq = lane >> 3;
+    if (gq >= cnt) return;
+    const int item = s_item[(done + gq) & (kRing - 1)];
+    const int q = item >> 16, bnd = item & 0xFFFF;
+    const int2 ij = g.bonds[bnd];
+    const float si = (float)A.samples[(s0 + q) * g.N + ij.x];
+    float2 d0q = d0[0];
+#pragma unroll
+    for (int qq = 1; qq < SPW; ++qq) d0q = q == qq ? d0[qq] : d0q;
+    const float2 c = bond_term(A, pe, ij.x, ij.y, si, lm[0], ph[0], d0q, with_fq, inv_sqrt_n);
+    if ((lane & 7) == 0)
+#pragma unroll
+        for (int qq = 0; qq < SPW; ++qq)
+            if (q == qq) acc[qq] = cadd(acc[qq], c);
+}
+
+// One sample of a wave: log psi, tanh theta, O of fit; the tanh theta of the RBM whose Hamiltonian
+// action is taken (te), the diagonal factor d0 of t_0 and the anti-aligned bonds (mask words, count).
+template <int E>
+__device__ __forceinline__ void local_sample(const LocalArgs& A, const float2* __restrict__ th1g,
+                                             const float2* __restrict__ thng, int lane, long s0, int q, int nq,
+                                             bool want_local, bool with_fq, int n_words, float2 (&te)[E], float2& d0,
+                                             int& n_anti, uint64_t* mask) {
     const Geometry& g = A.g;
     const int N = g.N, M = g.M;
+    d0 = make_float2(1.f, 0.f);
+    n_anti = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) te[e] = make_float2(0.f, 0.f);
+    if (q >= nq) {
+        if (lane < n_words) mask[lane] = 0ull;
+        return;
+    }
+    const long s = s0 + q;
     WaveSpins sp;
     sp.load(A.samples + s * N, N, lane);
-
-    float2 t1[E], tE[E], TE[E];
+    float2 t1[E], T1[E];
     float2 lc1 = make_float2(0.f, 0.f);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -165,7 +299,6 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __rest
         t1[e] = (k < M) ? th1g[s * M + k] : make_float2(0.f, 0.f);
     }
     // log psi of fit and tanh theta of fit
-    float2 T1[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = e * kWave + lane;
@@ -176,9 +309,8 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __rest
             T1[e] = make_float2(0.f, 0.f);
         }
     }
-    const float2 asig1 = a_dot_sigma(A.fit.a, sp, lane, N);
     if (A.logpsi_out) {
-        const float2 lp = wave_sum(cadd(lc1, asig1));
+        const float2 lp = wave_sum(cadd(lc1, a_dot_sigma(A.fit.a, sp, lane, N)));
         if (lane == 0) A.logpsi_out[s] = lp;
     }
     if (A.tanh_out) {
@@ -191,9 +323,9 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __rest
     if (A.O_out) {
         float2* row = A.O_out + s * (long)g.P;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int site = q * kWave + lane;
-            if (site < N) row[site] = make_float2((float)sp.s[q], 0.f);
+        for (int c = 0; c < 4; ++c) {
+            const int site = c * kWave + lane;
+            if (site < N) row[site] = make_float2((float)sp.s[c], 0.f);
         }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -209,151 +341,52 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __rest
             }
         }
     }
-    if (!A.eloc_out && !A.R_out) return;
-
-    // the RBM whose Hamiltonian action is needed
-    const RbmView& pe = A.cheb_mode ? A.psn : A.fit;
+    if (!want_local) return;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = e * kWave + lane;
-        if (A.cheb_mode) {
-            tE[e] = (k < M) ? thng[s * M + k] : make_float2(0.f, 0.f);
-            TE[e] = (k < M) ? ctanhf(tE[e]) : make_float2(0.f, 0.f);
-        } else {
-            tE[e] = t1[e];
-            TE[e] = T1[e];
-        }
+        if (A.cheb_mode) te[e] = (k < M) ? ctanhf(thng[s * M + k]) : make_float2(0.f, 0.f);
+        else te[e] = T1[e];
     }
-    const bool with_fq = A.cheb_mode && A.order == 0;
     // diagonal factor of t_0: f_q (momentum q) or, with local_op, the local S^z_0 = s_0 / 2
-    const float2 d0 = !with_fq ? make_float2(1.f, 0.f)
-                    : A.local_op ? make_float2(0.5f * (float)sp.get(0), 0.f) : fq_wave(sp, lane, g, A.q0, A.q1);
-    const float inv_sqrt_n = rsqrtf((float)N);
-
-    // anti-aligned bonds of this sample, in bond order, compacted into the wave's LDS list
-    __shared__ short s_anti[4][kMaxBonds];
-    short* lst = s_anti[threadIdx.x >> 6];
+    if (with_fq) d0 = A.local_op ? make_float2(0.5f * (float)sp.get(0), 0.f) : fq_wave(sp, lane, g, A.q0, A.q1);
+    // anti-aligned bonds of the sample
     const int8_t* srow = A.samples + s * N;
-    int n_anti = 0;
-    for (int c0 = 0; c0 < g.n_bonds; c0 += kWave) {
-        const int bnd = c0 + lane;
+    for (int c = 0; c < n_words; ++c) {
+        const int bnd = c * kWave + lane;
         bool anti = false;
         if (bnd < g.n_bonds) {
             const int2 ij = g.bonds[bnd];
             anti = srow[ij.x] != srow[ij.y];
         }
         const uint64_t m = __ballot(anti);
-        if (anti) lst[n_anti + __popcll(m & ((1ull << lane) - 1ull))] = (short)bnd;
+        if (lane == 0) mask[c] = m;
         n_anti += __popcll(m);
     }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
+// One sample's local energy (J/4 s_i s_j over all bonds plus the exchange part in acc, already summed
+// over the lanes that hold it) and, in Chebyshev mode, R = phi / psi_{n+1}.
+template <int E>
+__device__ __forceinline__ void local_finish(const LocalArgs& A, const float2* __restrict__ th1g,
+                                             const float2* __restrict__ thng, const float2* __restrict__ thmg,
+                                             int lane, long s, float2 acc, float2 d0, int n_anti) {
+    const Geometry& g = A.g;
+    const int N = g.N, M = g.M;
     const float J = (float)g.J;
-    // diagonal part: J/4 s_i s_j over all bonds, s_i s_j = -1 on the anti-aligned ones
-    const float2 diag = cscale(d0, 0.25f * J * (float)(g.n_bonds - 2 * n_anti));
-    float2 acc = make_float2(0.f, 0.f);        // off-diagonal part, on lanes 8 g (group g's bond)
-    // Bonds in batches of 8.  Each lane forms its share of a bond's factor product as
-    // (log |p|, p/|p|); a reduce-scatter over lane bits 5, 4, 3 then leaves bond b0 + g of the
-    // batch on the 8 lanes of group g = lane / 8, which add (multiply) the last 8 shares, so the
-    // exponentials and phases of the 8 bonds are evaluated lane-parallel.
-    for (int b0 = 0; b0 < n_anti; b0 += 8) {
-        float lm[8];
-        float2 ph[8];
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            lm[b] = 0.f;
-            ph[b] = make_float2(1.f, 0.f);
-            if (b0 + b < n_anti) {
-                const int bnd = uniform((int)lst[b0 + b]);
-                const int i = uniform(g.bonds[bnd].x);
-                // Delta_k = -2 s_i D_k with D = W_i - W_j: cosh Delta = cosh 2D, sinh Delta = -s_i sinh 2D,
-                // both read from the bond's table
-                const float nsi = -(float)sp.get(i);
-                const float4* tab = g.bond_tab + (long)bnd * M;
-                float2 prod = make_float2(1.f, 0.f);
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const int k = e * kWave + lane;
-                    if (k < M) {
-                        const float4 q = tab[k];
-                        const float2 ts = cmul(TE[e], make_float2(q.z, q.w));
-                        prod = cmul(prod, make_float2(fmaf(nsi, ts.x, q.x), fmaf(nsi, ts.y, q.y)));
-                    }
-                }
-                const float n2 = prod.x * prod.x + prod.y * prod.y;
-                lm[b] = 0.5f * logf(n2);
-                const float inv = n2 > 0.f ? rsqrtf(n2) : 0.f;
-                ph[b] = n2 > 0.f ? cscale(prod, inv) : make_float2(1.f, 0.f);
-            }
-        }
-        // reduce-scatter: across lane bit 5 keep 4 of 8 bonds, bit 4 keep 2, bit 3 keep 1
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const bool hi = (lane & 32) != 0;
-            const float kl = hi ? lm[t + 4] : lm[t], sl = hi ? lm[t] : lm[t + 4];
-            const float2 kp = hi ? ph[t + 4] : ph[t], sp2 = hi ? ph[t] : ph[t + 4];
-            lm[t] = kl + __shfl_xor(sl, 32);
-            ph[t] = cmul(kp, make_float2(__shfl_xor(sp2.x, 32), __shfl_xor(sp2.y, 32)));
-        }
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const bool hi = (lane & 16) != 0;
-            const float kl = hi ? lm[t + 2] : lm[t], sl = hi ? lm[t] : lm[t + 2];
-            const float2 kp = hi ? ph[t + 2] : ph[t], sp2 = hi ? ph[t] : ph[t + 2];
-            lm[t] = kl + __shfl_xor(sl, 16);
-            ph[t] = cmul(kp, make_float2(__shfl_xor(sp2.x, 16), __shfl_xor(sp2.y, 16)));
-        }
-        {
-            const bool hi = (lane & 8) != 0;
-            const float kl = hi ? lm[1] : lm[0], sl = hi ? lm[0] : lm[1];
-            const float2 kp = hi ? ph[1] : ph[0], sp2 = hi ? ph[0] : ph[1];
-            lm[0] = kl + __shfl_xor(sl, 8);
-            ph[0] = cmul(kp, make_float2(__shfl_xor(sp2.x, 8), __shfl_xor(sp2.y, 8)));
-        }
-#pragma unroll
-        for (int o = 4; o >= 1; o >>= 1) {
-            lm[0] += __shfl_xor(lm[0], o);
-            ph[0] = cmul(ph[0], make_float2(__shfl_xor(ph[0].x, o), __shfl_xor(ph[0].y, o)));
-        }
-        const int bb = b0 + (lane >> 3);
-        if (bb < n_anti) {
-            const int bnd = lst[bb];
-            const int2 ij = g.bonds[bnd];
-            const int i = ij.x, j = ij.y;
-            const float si = (float)srow[i];
-            const float m2si = -2.f * si;
-            // amplitude ratio psi(s^ij)/psi(s) = exp(sum log|p| + Re da) * (phase) * exp(i Im da)
-            const float2 da = cscale(csub(pe.a[i], pe.a[j]), m2si);
-            const float ph2 = ph[0].x * ph[0].x + ph[0].y * ph[0].y;
-            const float2 u = cscale(ph[0], rsqrtf(ph2));
-            float sn, cs;
-            sincosf(da.y, &sn, &cs);
-            const float2 rho = cscale(cmul(u, make_float2(cs, sn)), expf(lm[0] + da.x));
-            float2 d1 = make_float2(1.f, 0.f);
-            if (with_fq) {
-                if (A.local_op) {
-                    // s_0 / 2 after the swap of sites i and j (s_j = -s_i)
-                    d1 = make_float2(i == 0 ? -0.5f * si : (j == 0 ? 0.5f * si : d0.x), 0.f);
-                } else {
-                    // f_q(s^{ij}) = f_q(s) - N^{-1/2} s_i (e^{-iq.r_i} - e^{-iq.r_j})
-                    const float2 pd = csub(site_phase(i, g.kind, g.Lx, A.q0, A.q1), site_phase(j, g.kind, g.Lx, A.q0, A.q1));
-                    d1 = csub(d0, cscale(pd, inv_sqrt_n * si));
-                }
-            }
-            if ((lane & 7) == 0) acc = cadd(acc, cscale(cmul(d1, rho), 0.5f * J));
-        }
-    }
-    acc = cadd(wave_sum(acc), diag);
-    if (A.eloc_out && lane == 0) A.eloc_out[s] = acc;
+    const float2 eloc = cadd(wave_sum(acc), cscale(d0, 0.25f * J * (float)(g.n_bonds - 2 * n_anti)));
+    if (A.eloc_out && lane == 0) A.eloc_out[s] = eloc;
     if (!A.cheb_mode || !A.R_out) return;
-
-    // R = phi / psi_{n+1}
-    const float2 ht = cscale(csub(acc, cmul(make_float2((float)A.E_c, 0.f), d0)), (float)(1.0 / A.W_scale));
+    WaveSpins sp;
+    sp.load(A.samples + s * N, N, lane);
+    const float2 asig1 = a_dot_sigma(A.fit.a, sp, lane, N);
+    const float2 ht = cscale(csub(eloc, cmul(make_float2((float)A.E_c, 0.f), d0)), (float)(1.0 / A.W_scale));
     float2 dn = csub(a_dot_sigma(A.psn.a, sp, lane, N), asig1);
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-        if (e * kWave + lane < M) dn = cadd(dn, csub(log2cosh(tE[e]), log2cosh(t1[e])));
+    for (int e = 0; e < E; ++e) {
+        const int k = e * kWave + lane;
+        if (k < M) dn = cadd(dn, csub(log2cosh(thng[s * M + k]), log2cosh(th1g[s * M + k])));
+    }
     dn = wave_sum(dn);
     const float2 bn = make_float2((float)A.beta_n.x, (float)A.beta_n.y);
     float2 R;
@@ -364,7 +397,7 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __rest
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = e * kWave + lane;
-            if (k < M) dm = cadd(dm, csub(log2cosh(thmg[s * M + k]), log2cosh(t1[e])));
+            if (k < M) dm = cadd(dm, csub(log2cosh(thmg[s * M + k]), log2cosh(th1g[s * M + k])));
         }
         dm = wave_sum(dm);
         const float2 fm = (A.order != 1) ? make_float2(1.f, 0.f)
@@ -375,8 +408,153 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __rest
     if (lane == 0) A.R_out[s] = R;
 }
 
-// tab[b][k] = (cosh 2D, sinh 2D) with D = W_ik - W_jk for bond b = (i, j); the difference of two
-// binary32 values is exact in binary64, and the functions are evaluated there before rounding
+template <int E>
+__global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __restrict__ th1g,
+                                               const float2* __restrict__ thng, const float2* __restrict__ thmg) {
+    constexpr int SPW = kLocalSpw;
+    __shared__ uint64_t s_mask[4][SPW][kMaxBonds / 64];
+    __shared__ float s_lm[4][kRing][kWave];
+    __shared__ float2 s_ph[4][kRing][kWave];
+    __shared__ int s_item[4][kRing];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long s0 = ((long)blockIdx.x * 4 + wv) * SPW;
+    if (s0 >= A.n_samples) return;
+    const Geometry& g = A.g;
+    const int N = g.N, M = g.M;
+    const int nq = (int)(A.n_samples - s0 < SPW ? A.n_samples - s0 : SPW);
+    const bool want_local = A.eloc_out || A.R_out;
+    const bool with_fq = A.cheb_mode && A.order == 0;
+    // the RBM whose Hamiltonian action is needed
+    const RbmView& pe = A.cheb_mode ? A.psn : A.fit;
+    const int n_words = (g.n_bonds + 63) / 64;
+
+    float2 TE[SPW][E];
+    float2 d0[SPW];
+    int n_anti[SPW];
+    static_assert(SPW == 4, "the per-sample calls below are written out for 4 samples");
+    local_sample<E>(A, th1g, thng, lane, s0, 0, nq, want_local, with_fq, n_words, TE[0], d0[0], n_anti[0], s_mask[wv][0]);
+    local_sample<E>(A, th1g, thng, lane, s0, 1, nq, want_local, with_fq, n_words, TE[1], d0[1], n_anti[1], s_mask[wv][1]);
+    local_sample<E>(A, th1g, thng, lane, s0, 2, nq, want_local, with_fq, n_words, TE[2], d0[2], n_anti[2], s_mask[wv][2]);
+    local_sample<E>(A, th1g, thng, lane, s0, 3, nq, want_local, with_fq, n_words, TE[3], d0[3], n_anti[3], s_mask[wv][3]);
+    if (!want_local) return;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+    const float inv_sqrt_n = rsqrtf((float)N);
+    float2 acc[SPW];
+#pragma unroll
+    for (int q = 0; q < SPW; ++q) acc[q] = make_float2(0.f, 0.f);
+    int pushed = 0, done = 0;
+    for (int c = 0; c < n_words; ++c) {
+        uint64_t mk[SPW];
+        uint64_t any = 0ull;
+#pragma unroll
+        for (int q = 0; q < SPW; ++q) {
+            mk[q] = s_mask[wv][q][c];
+            any |= mk[q];
+        }
+        while (any) {
+            const int bit = __builtin_ctzll(any);
+            any &= any - 1ull;
+            const int bnd = c * kWave + bit;
+            const int i = uniform(g.bonds[bnd].x);
+            float4 tq[E];
+            bond_row<E>(g, bnd, lane, tq);
+#pragma unroll
+            for (int q = 0; q < SPW; ++q) {
+                if (!((mk[q] >> bit) & 1ull)) continue;
+                const float2 prod = bond_share<E>(tq, TE[q], -(float)A.samples[(s0 + q) * N + i]);
+                const float n2 = prod.x * prod.x + prod.y * prod.y;
+                const int slot = pushed & (kRing - 1);
+                s_lm[wv][slot][lane] = 0.5f * logf(n2);
+                s_ph[wv][slot][lane] = n2 > 0.f ? cscale(prod, rsqrtf(n2)) : make_float2(1.f, 0.f);
+                if (lane == 0) s_item[wv][slot] = (q << 16) | bnd;
+                ++pushed;
+            }
+            if (pushed - done >= 8) {
+                local_flush<SPW>(A, pe, lane, s0, done, 8, with_fq, inv_sqrt_n, d0, acc, s_lm[wv], s_ph[wv],
+                                 s_item[wv]);
+                done += 8;
+            }
+        }
+    }
+    while (done < pushed) {
+        const int cnt = pushed - done < 8 ? pushed - done : 8;
+        local_flush<SPW>(A, pe, lane, s0, done, cnt, with_fq, inv_sqrt_n, d0, acc, s_lm[wv], s_ph[wv],
+                         s_item[wv]);
+        done += cnt;
+    }
+
+    local_finish<E>(A, th1g, thng, thmg, lane, s0, acc[0], d0[0], n_anti[0]);
+    if (nq > 1) local_finish<E>(A, th1g, thng, thmg, lane, s0 + 1, acc[1], d0[1], n_anti[1]);
+    if (nq > 2) local_finish<E>(A, th1g, thng, thmg, lane, s0 + 2, acc[2], d0[2], n_anti[2]);
+    if (nq > 3) local_finish<E>(A, th1g, thng, thmg, lane, s0 + 3, acc[3], d0[3], n_anti[3]);
+}
+
+// Narrow RBMs (M <= 3 x 64): one sample per wave.  With few hidden units per lane the bookkeeping of
+// the bond-major walk costs more than the table reads it saves, so each wave walks its own sample's
+// anti-aligned bonds in batches of 8 with the shares kept in registers.
+template <int E>
+__global__ __launch_bounds__(256) void k_local_one(LocalArgs A, const float2* __restrict__ th1g,
+                                                   const float2* __restrict__ thng, const float2* __restrict__ thmg) {
+    __shared__ uint64_t s_mask[4][kMaxBonds / 64];
+    __shared__ short s_anti[4][kMaxBonds];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long s = (long)blockIdx.x * 4 + wv;
+    if (s >= A.n_samples) return;
+    const Geometry& g = A.g;
+    const bool want_local = A.eloc_out || A.R_out;
+    const bool with_fq = A.cheb_mode && A.order == 0;
+    const RbmView& pe = A.cheb_mode ? A.psn : A.fit;
+    const int n_words = (g.n_bonds + 63) / 64;
+    float2 TE[E];
+    float2 d0;
+    int n_anti;
+    local_sample<E>(A, th1g, thng, lane, s, 0, 1, want_local, with_fq, n_words, TE, d0, n_anti, s_mask[wv]);
+    if (!want_local) return;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // the anti-aligned bonds in bond order
+    short* lst = s_anti[wv];
+    int base = 0;
+    for (int c = 0; c < n_words; ++c) {
+        const uint64_t m = s_mask[wv][c];
+        if ((m >> lane) & 1ull) lst[base + __popcll(m & ((1ull << lane) - 1ull))] = (short)(c * kWave + lane);
+        base += __popcll(m);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const float inv_sqrt_n = rsqrtf((float)g.N);
+    const int8_t* srow = A.samples + s * g.N;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int b0 = 0; b0 < n_anti; b0 += 8) {
+        float lm[8];
+        float2 ph[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            lm[b] = 0.f;
+            ph[b] = make_float2(1.f, 0.f);
+            if (b0 + b < n_anti) {
+                const int bnd = uniform((int)lst[b0 + b]);
+                float4 tq[E];
+                bond_row<E>(g, bnd, lane, tq);
+                const float2 prod = bond_share<E>(tq, TE, -(float)srow[uniform(g.bonds[bnd].x)]);
+                const float n2 = prod.x * prod.x + prod.y * prod.y;
+                lm[b] = 0.5f * logf(n2);
+                ph[b] = n2 > 0.f ? cscale(prod, rsqrtf(n2)) : make_float2(1.f, 0.f);
+            }
+        }
+        reduce_scatter8(lm, ph, lane);
+        const int bb = b0 + (lane >> 3);
+        if (bb < n_anti) {
+            const int2 ij = g.bonds[lst[bb]];
+            const float2 c = bond_term(A, pe, ij.x, ij.y, (float)srow[ij.x], lm[0], ph[0], d0, with_fq, inv_sqrt_n);
+            if ((lane & 7) == 0) acc = cadd(acc, c);
+        }
+    }
+    local_finish<E>(A, th1g, thng, thmg, lane, s, acc, d0, n_anti);
+}
+
 __global__ __launch_bounds__(256) void k_bond_table(const int2* __restrict__ bonds, int nb, int M,
                                                     const float2* __restrict__ W, float4* __restrict__ tab) {
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
@@ -401,11 +579,16 @@ hipError_t launch_local_core(const LocalArgs& A, const float2* th1, const float2
                            A.g.n_bonds, A.g.M, W, A.g.bond_tab);
     }
     const int E = (A.g.M + kWave - 1) / kWave;
-    const dim3 grid((unsigned)((A.n_samples + 3) / 4)), block(256);
+    const dim3 block(256);
+    const dim3 grid1((unsigned)((A.n_samples + 3) / 4));
+    const long per_block = 4L * kLocalSpw;
+    const dim3 grid4((unsigned)((A.n_samples + per_block - 1) / per_block));
     switch (E) {
-#define CRBM_CASE(e) case e: hipLaunchKernelGGL(k_local<e>, grid, block, 0, stream, A, th1, thn, thm); break;
-        CRBM_CASE(1) CRBM_CASE(2) CRBM_CASE(3) CRBM_CASE(4) CRBM_CASE(5) CRBM_CASE(6) CRBM_CASE(7) CRBM_CASE(8)
-#undef CRBM_CASE
+#define CRBM_ONE(e) case e: hipLaunchKernelGGL(k_local_one<e>, grid1, block, 0, stream, A, th1, thn, thm); break;
+#define CRBM_BM(e) case e: hipLaunchKernelGGL(k_local<e>, grid4, block, 0, stream, A, th1, thn, thm); break;
+        CRBM_ONE(1) CRBM_ONE(2) CRBM_ONE(3) CRBM_BM(4) CRBM_BM(5) CRBM_BM(6) CRBM_BM(7) CRBM_BM(8)
+#undef CRBM_ONE
+#undef CRBM_BM
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
