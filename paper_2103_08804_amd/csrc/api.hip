@@ -18,9 +18,9 @@ hipError_t launch_theta(const int8_t* sig, long n, int N, int M, const float2* b
                         hipStream_t stream, const double* skip = nullptr);
 hipError_t launch_local_core(const LocalArgs& A, const float2* th1, const float2* thn, const float2* thm,
                              hipStream_t stream);
-hipError_t launch_moment_ratio(int N, int M, const int8_t* sig, long n_s, const float2* a_t, const float2* a_g,
-                               const float2* th_t, const float2* th_g, const double2* beta, double2* B,
-                               hipStream_t stream);
+hipError_t launch_lc_sums(const int8_t* sig, long n, int N, int M, const float2* a, const float2* b,
+                          const float2* W, uint16_t* planes, float2* partial, const double2* Lg,
+                          const double2* beta, double2* B, double2* Lg_out, hipStream_t stream);
 hipError_t launch_fq_chunk(const Geometry& g, const int8_t* sig, long n_s, const double* q_host, int n_q,
                            double2* f, hipStream_t stream);
 hipError_t launch_moment_accum(const double2* f, const double2* B, int b_is_f, const double* w, long n_s, int n_q,
@@ -99,6 +99,8 @@ struct crbm_plan_s {
     double2* momB = nullptr;
     double2* momF = nullptr;
     double2* mom_partial = nullptr;
+    uint16_t* wplanes = nullptr;   // W split into 3 BF16 parts for the fused log-cosh sums
+    double2* lcLg = nullptr;       // [max_samples] sum log cosh theta + a.sigma of psi_gs
     unsigned long long* bcounter = nullptr;
     double2* bpartial = nullptr;
     int n_cu = 256;
@@ -295,6 +297,8 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
     rc = rc ? rc : p->alloc(&p->momB, S);
     rc = rc ? rc : p->alloc(&p->momF, (long)kQChunk * S);
     rc = rc ? rc : p->alloc(&p->mom_partial, (long)kMomBlocks * kMaxMomentEntries);
+    rc = rc ? rc : p->alloc(&p->wplanes, lc_plane_elems(N, M));
+    rc = rc ? rc : p->alloc(&p->lcLg, S);
     rc = rc ? rc : p->alloc(&p->bcounter, 1);
     rc = rc ? rc : p->alloc(&p->bpartial, 2 * S);
     if (!rc && (flags & (CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY))) {
@@ -584,7 +588,11 @@ int crbm_chebyshev_moment(crbm_plan p, const crbm_rbm* gs, const void* t_params,
     const int nn = n_max + 1;
     const long P = p->P;
     const float2* tp = static_cast<const float2*>(t_params);
-    hipError_t e = launch_theta(samples, n, p->N, p->M, vg.b, vg.W, p->theta[0], stream);
+    // per-sample sum log cosh theta + a.sigma of psi_gs, once; the tile partials go to theta[2]
+    p->prof.begin(PROF_MOMENT, stream);
+    hipError_t e = launch_lc_sums(samples, n, p->N, p->M, vg.a, vg.b, vg.W, p->wplanes, p->theta[2], nullptr,
+                                  nullptr, nullptr, p->lcLg, stream);
+    p->prof.end(stream);
     for (int q0 = 0; q0 < n_q && e == hipSuccess; q0 += kQChunk) {
         const int nq = (n_q - q0) < kQChunk ? (n_q - q0) : kQChunk;
         e = launch_fq_chunk(g, samples, n, q + 2 * q0, nq, p->momF, stream);
@@ -593,15 +601,11 @@ int crbm_chebyshev_moment(crbm_plan p, const crbm_rbm* gs, const void* t_params,
                                     kMomBlocks, stream);
         for (int t = 1; t <= n_max && e == hipSuccess; ++t) {
             const float2* at = tp + (long)(t - 1) * P;
-            p->prof.begin(PROF_THETA, stream);
-            e = launch_theta(samples, n, p->N, p->M, at + p->N, at + p->N + p->M, p->theta[1], stream);
+            // B_t = beta_t t~_t / psi_gs from the fused product and log-cosh sums
+            p->prof.begin(PROF_MOMENT, stream);
+            e = launch_lc_sums(samples, n, p->N, p->M, at, at + p->N, at + p->N + p->M, p->wplanes, p->theta[2],
+                               p->lcLg, reinterpret_cast<const double2*>(betas) + (t - 1), p->momB, nullptr, stream);
             p->prof.end(stream);
-            if (e == hipSuccess) {
-                p->prof.begin(PROF_MOMENT, stream);
-                e = launch_moment_ratio(p->N, p->M, samples, n, at, vg.a, p->theta[1], p->theta[0],
-                                        reinterpret_cast<const double2*>(betas) + (t - 1), p->momB, stream);
-                p->prof.end(stream);
-            }
             if (e == hipSuccess)
                 e = launch_moment_accum(p->momF, p->momB, 0, weights, n, nq, nn, q0 * nn + t, nn * n_q,
                                         p->mom_partial, kMomBlocks, stream);
@@ -687,6 +691,12 @@ int crbm_moment_matrices(crbm_plan p, const crbm_rbm* gs, const void* t_params, 
         p->prof.end(stream);
     }
     if (e == hipSuccess) e = launch_basis_pack(n, p->momF, loc, 0, Bm, HBm, stream);
+    if (e == hipSuccess && n_max > 0) {
+        p->prof.begin(PROF_MOMENT, stream);
+        e = launch_lc_sums(samples, n, p->N, p->M, vg.a, vg.b, vg.W, p->wplanes, p->theta[2], nullptr, nullptr,
+                           nullptr, p->lcLg, stream);
+        p->prof.end(stream);
+    }
     // orders 1..n_max: B_t = beta_t t~_t/psi_gs, HB_t = B_t E_loc[t~_t]
     for (int t = 1; t <= n_max && e == hipSuccess; ++t) {
         const float2* at = tp + (long)(t - 1) * P;
@@ -710,8 +720,8 @@ int crbm_moment_matrices(crbm_plan p, const crbm_rbm* gs, const void* t_params, 
         }
         if (e == hipSuccess) {
             p->prof.begin(PROF_MOMENT, stream);
-            e = launch_moment_ratio(p->N, p->M, samples, n, at, vg.a, p->theta[1], p->theta[0],
-                                    reinterpret_cast<const double2*>(betas) + (t - 1), p->momB, stream);
+            e = launch_lc_sums(samples, n, p->N, p->M, at, vt.b, vt.W, p->wplanes, p->theta[2], p->lcLg,
+                               reinterpret_cast<const double2*>(betas) + (t - 1), p->momB, nullptr, stream);
             p->prof.end(stream);
         }
         if (e == hipSuccess) e = launch_basis_pack(n, p->momB, loc, 1, Bm + (long)t * n, HBm + (long)t * n, stream);

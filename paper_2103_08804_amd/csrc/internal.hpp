@@ -15,6 +15,10 @@ struct RbmView {            // device pointers, complex64 interleaved
     const float2* W;
 };
 
+// elements of the three BF16 planes of W used by the fused log-cosh sums: 3 x (tiles of 64 units x 128
+// real columns) x (sites rounded up to 32)
+inline long lc_plane_elems(long N, long M) { return 3L * ((M + 63) / 64) * 128L * ((N + 31) / 32 * 32); }
+
 // bonds of the largest lattice (square, N <= 256 sites, 2 N bonds); the local-estimator kernel keeps
 // a per-wave list of the anti-aligned ones in LDS
 constexpr int kMaxBonds = 512;

@@ -144,6 +144,215 @@ __device__ __forceinline__ float2 a_dot_sigma(const float2* a, const WaveSpins& 
     return acc;
 }
 
+// ------------------------------------------------------------------ theta GEMM fused with sum log cosh
+// For the moment ratios only the per-sample sums  L(s) = sum_k log cosh theta_k(s)  of an RBM are
+// needed, not theta itself.  The product runs as above, with the B columns of a 64-unit tile ordered
+// [Re 0..31 | Im 0..31 | Re 32..63 | Im 32..63], so that the real and imaginary parts of a hidden unit
+// land in the same lane; each lane then forms, row by row,
+//   log cosh z = s z + log((1 + w)/2),   s = sign(Re z),  w = exp(-2 s z),  |(1 + w)/2| <= 1,
+// keeping s z as a sum and (1 + w)/2 as a product, multiplies the products over the tile's columns
+// by a reduce-scatter over the lane bits and takes one complex log per sample row.
+//
+// W is first split into its three exact BF16 parts in that column order (planes [3][Mt 128][Np],
+// Np = N rounded up to TH_K, zero padding), so the product's workgroups only copy tiles.
+__global__ __launch_bounds__(256) void k_wsplit(const float2* __restrict__ W, int N, int M, int Np, int Mt,
+                                                uint16_t* __restrict__ planes) {
+    const long rows = (long)Mt * TH_C;
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= rows * Np) return;
+    const int r = (int)(idx / Np), i = (int)(idx % Np);
+    const int rr = r % TH_C, cb = rr / 32;
+    const int k = (r / TH_C) * 64 + (cb >> 1) * 32 + rr % 32;
+    float w = 0.f;
+    if (i < N && k < M) {
+        const float2 v = W[(long)i * M + k];
+        w = (cb & 1) ? v.y : v.x;
+    }
+    const uint32_t u = __float_as_uint(w);
+    const uint32_t hi = u & 0xFFFF0000u;
+    const float r1 = w - __uint_as_float(hi);
+    const uint32_t mid = __float_as_uint(r1) & 0xFFFF0000u;
+    const float r2 = r1 - __uint_as_float(mid);
+    planes[idx] = (uint16_t)(hi >> 16);
+    planes[rows * Np + idx] = (uint16_t)(mid >> 16);
+    planes[2 * rows * Np + idx] = (uint16_t)(__float_as_uint(r2) >> 16);
+}
+
+// combine two partial sums of log cosh: the linear parts add, the bounded factors multiply
+__device__ __forceinline__ void lc_join(float2& lin, float2& pr, float2 lin2, float2 pr2) {
+    lin = cadd(lin, lin2);
+    pr = cmul(pr, pr2);
+}
+
+__global__ __launch_bounds__(256) void k_theta_lc(const int8_t* __restrict__ sig, long n, int N, int Np, int M,
+                                                  const float2* __restrict__ b, const uint16_t* __restrict__ planes,
+                                                  int Mt, float2* __restrict__ partial) {
+    __shared__ __attribute__((aligned(16))) unsigned char s_sig[TH_S * TH_ROW];
+    __shared__ __attribute__((aligned(16))) unsigned char s_w[3][TH_C * TH_ROW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long s0 = (long)blockIdx.x * TH_S;
+    const int ct = blockIdx.y;                        // 64-unit tile
+    const long rows = (long)Mt * TH_C;
+    floatx16_t acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[cb][v] = 0.f;
+
+    for (int k0 = 0; k0 < Np; k0 += TH_K) {
+        for (int e = tid; e < TH_S * TH_K; e += 256) {
+            const int ss = e / TH_K, kk = e % TH_K;
+            const long sm = s0 + ss;
+            const int i = k0 + kk;
+            uint16_t v = 0;
+            if (sm < n && i < N) v = sig[sm * N + i] > 0 ? 0x3F80 : 0xBF80;
+            *reinterpret_cast<uint16_t*>(s_sig + ss * TH_ROW + kk * 2) = v;
+        }
+        // 3 parts x 128 rows x 32 sites: 16-byte chunks of the planes
+        for (int c = tid; c < 3 * TH_C * (TH_K / 8); c += 256) {
+            const int part = c / (TH_C * (TH_K / 8)), rem = c % (TH_C * (TH_K / 8));
+            const int rr = rem / (TH_K / 8), ch = rem % (TH_K / 8);
+            const uint16_t* src = planes + part * rows * Np + ((long)ct * TH_C + rr) * Np + k0 + ch * 8;
+            *reinterpret_cast<i32x4_t*>(s_w[part] + rr * TH_ROW + ch * 16) = *reinterpret_cast<const i32x4_t*>(src);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kq = 0; kq < TH_K; kq += 16) {
+            const int koff = (kq + 8 * (lane >> 5)) * 2;
+            const i32x4_t a = *reinterpret_cast<const i32x4_t*>(s_sig + (wave * 32 + (lane & 31)) * TH_ROW + koff);
+#pragma unroll
+            for (int part = 0; part < 3; ++part)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    const i32x4_t bw =
+                        *reinterpret_cast<const i32x4_t*>(s_w[part] + (cb * 32 + (lane & 31)) * TH_ROW + koff);
+                    acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16((bf16x8_t)a, (bf16x8_t)bw, acc[cb], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    // lane column j = lane % 32: units k0u = 64 ct + j (acc 0, 1) and k1u = k0u + 32 (acc 2, 3)
+    const int j = lane & 31;
+    const int ku0 = ct * 64 + j, ku1 = ku0 + 32;
+    const float2 b0 = ku0 < M ? b[ku0] : make_float2(0.f, 0.f);
+    const float2 b1 = ku1 < M ? b[ku1] : make_float2(0.f, 0.f);
+    float2 lin[16], pr[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        lin[v] = make_float2(0.f, 0.f);
+        pr[v] = make_float2(1.f, 0.f);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if ((h == 0 ? ku0 : ku1) >= M) continue;
+            const float2 bb = h == 0 ? b0 : b1;
+            const float zx = acc[2 * h][v] + bb.x, zy = acc[2 * h + 1][v] + bb.y;
+            const float sg = zx >= 0.f ? 1.f : -1.f;
+            const float e = expf(-2.f * fabsf(zx));
+            float sn, cs;
+            sincosf(2.f * sg * zy, &sn, &cs);
+            lin[v] = cadd(lin[v], make_float2(fabsf(zx), sg * zy));
+            pr[v] = cmul(pr[v], make_float2(0.5f * (1.f + e * cs), -0.5f * e * sn));
+        }
+    }
+    // reduce-scatter of the 16 rows over the 32 columns (lane bits 4..1), then the last pair (bit 0):
+    // lane ends with row 8 b4 + 4 b3 + 2 b2 + b1 of its half
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const bool hi = (lane & 16) != 0;
+        const float2 kl = hi ? lin[t + 8] : lin[t], kp = hi ? pr[t + 8] : pr[t];
+        const float2 sl = hi ? lin[t] : lin[t + 8], sp = hi ? pr[t] : pr[t + 8];
+        lin[t] = kl;
+        pr[t] = kp;
+        lc_join(lin[t], pr[t], make_float2(__shfl_xor(sl.x, 16), __shfl_xor(sl.y, 16)),
+                make_float2(__shfl_xor(sp.x, 16), __shfl_xor(sp.y, 16)));
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const bool hi = (lane & 8) != 0;
+        const float2 kl = hi ? lin[t + 4] : lin[t], kp = hi ? pr[t + 4] : pr[t];
+        const float2 sl = hi ? lin[t] : lin[t + 4], sp = hi ? pr[t] : pr[t + 4];
+        lin[t] = kl;
+        pr[t] = kp;
+        lc_join(lin[t], pr[t], make_float2(__shfl_xor(sl.x, 8), __shfl_xor(sl.y, 8)),
+                make_float2(__shfl_xor(sp.x, 8), __shfl_xor(sp.y, 8)));
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const bool hi = (lane & 4) != 0;
+        const float2 kl = hi ? lin[t + 2] : lin[t], kp = hi ? pr[t + 2] : pr[t];
+        const float2 sl = hi ? lin[t] : lin[t + 2], sp = hi ? pr[t] : pr[t + 2];
+        lin[t] = kl;
+        pr[t] = kp;
+        lc_join(lin[t], pr[t], make_float2(__shfl_xor(sl.x, 4), __shfl_xor(sl.y, 4)),
+                make_float2(__shfl_xor(sp.x, 4), __shfl_xor(sp.y, 4)));
+    }
+    {
+        const bool hi = (lane & 2) != 0;
+        const float2 kl = hi ? lin[1] : lin[0], kp = hi ? pr[1] : pr[0];
+        const float2 sl = hi ? lin[0] : lin[1], sp = hi ? pr[0] : pr[1];
+        lin[0] = kl;
+        pr[0] = kp;
+        lc_join(lin[0], pr[0], make_float2(__shfl_xor(sl.x, 2), __shfl_xor(sl.y, 2)),
+                make_float2(__shfl_xor(sp.x, 2), __shfl_xor(sp.y, 2)));
+    }
+    lc_join(lin[0], pr[0], make_float2(__shfl_xor(lin[0].x, 1), __shfl_xor(lin[0].y, 1)),
+            make_float2(__shfl_xor(pr[0].x, 1), __shfl_xor(pr[0].y, 1)));
+    if (lane & 1) return;
+    const int v = 8 * ((lane >> 4) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 2) & 1) + ((lane >> 1) & 1);
+    const long sm = s0 + wave * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    if (sm >= n) return;
+    const float n2 = pr[0].x * pr[0].x + pr[0].y * pr[0].y;
+    partial[(long)ct * n + sm] = make_float2(lin[0].x + 0.5f * logf(n2), lin[0].y + atan2f(pr[0].y, pr[0].x));
+}
+
+// B[s] = beta exp(a.sigma + sum_tiles partial - Lg[s])  (Lg = NULL: the sums of psi_gs itself go to
+// Lg_out instead), one wave per sample; the tile partials and Lg are added in double
+__global__ __launch_bounds__(256) void k_lc_final(int N, long n, int Mt, const int8_t* __restrict__ sig,
+                                                  const float2* __restrict__ a, const float2* __restrict__ partial,
+                                                  const double2* __restrict__ Lg, const double2* __restrict__ beta,
+                                                  double2* __restrict__ B, double2* __restrict__ Lg_out) {
+    const int lane = threadIdx.x & 63;
+    const long s = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (s >= n) return;
+    WaveSpins sp;
+    sp.load(sig + s * N, N, lane);
+    const float2 as = a_dot_sigma(a, sp, lane, N);
+    double x = as.x, y = as.y;
+    if (lane < Mt) {
+        const float2 pt = partial[(long)lane * n + s];
+        x += pt.x;
+        y += pt.y;
+    }
+    x = wave_sum(x);
+    y = wave_sum(y);
+    if (lane != 0) return;
+    if (!Lg) {
+        Lg_out[s] = make_double2(x, y);
+        return;
+    }
+    const double2 g = Lg[s];
+    const double dx = x - g.x, dy = y - g.y;
+    const double m = exp(dx);
+    double sn, cs;
+    sincos(dy, &sn, &cs);
+    B[s] = zmul(*beta, make_double2(m * cs, m * sn));
+}
+
+hipError_t launch_lc_sums(const int8_t* sig, long n, int N, int M, const float2* a, const float2* b,
+                          const float2* W, uint16_t* planes, float2* partial, const double2* Lg,
+                          const double2* beta, double2* B, double2* Lg_out, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int Np = (N + TH_K - 1) / TH_K * TH_K;
+    const int Mt = (M + 63) / 64;
+    const long cnt = (long)Mt * TH_C * Np;
+    hipLaunchKernelGGL(k_wsplit, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, W, N, M, Np, Mt, planes);
+    hipLaunchKernelGGL(k_theta_lc, dim3((unsigned)((n + TH_S - 1) / TH_S), (unsigned)Mt), dim3(256), 0, stream, sig,
+                       n, N, Np, M, b, planes, Mt, partial);
+    hipLaunchKernelGGL(k_lc_final, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, N, n, Mt, sig, a, partial,
+                       Lg, beta, B, Lg_out);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ local estimators
 // A wave takes kLocalSpw consecutive samples.  Per sample it evaluates log psi, tanh theta and O
 // (lanes over the hidden units) and marks the anti-aligned bonds; then it walks the bonds once:
@@ -595,30 +804,6 @@ hipError_t launch_local_core(const LocalArgs& A, const float2* th1, const float2
 }
 
 // ------------------------------------------------------------------ moments
-// B[n][s] = beta_n exp(log t~_n(s) - log psi_gs(s)) for one order n (one wave per sample).
-template <int E>
-__global__ __launch_bounds__(256) void k_moment_ratio(int N, int M, const int8_t* __restrict__ sig, long n_s,
-                                                      const float2* __restrict__ a_t, const float2* __restrict__ a_g,
-                                                      const float2* __restrict__ th_t, const float2* __restrict__ th_g,
-                                                      const double2* __restrict__ beta, double2* __restrict__ B) {
-    const int lane = threadIdx.x & 63;
-    const long s = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (s >= n_s) return;
-    WaveSpins sp;
-    sp.load(sig + s * N, N, lane);
-    float2 d = csub(a_dot_sigma(a_t, sp, lane, N), a_dot_sigma(a_g, sp, lane, N));
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int k = e * kWave + lane;
-        if (k < M) d = cadd(d, csub(log2cosh(th_t[s * M + k]), log2cosh(th_g[s * M + k])));
-    }
-    d = wave_sum(d);
-    if (lane == 0) {
-        const float2 r = cexpf(d);
-        B[s] = zmul(*beta, make_double2((double)r.x, (double)r.y));
-    }
-}
-
 // f[q][s] = f_q(s) (double) for a chunk of up to 8 momenta, one wave per sample
 struct QChunk { double q[8][2]; };
 
@@ -684,20 +869,6 @@ __global__ void k_moment_final(const double2* __restrict__ partial, int n_blocks
     double2 acc = make_double2(0.0, 0.0);
     for (int b = 0; b < n_blocks; ++b) acc = zadd(acc, partial[(long)b * total + idx]);
     mu[idx] = acc;
-}
-
-hipError_t launch_moment_ratio(int N, int M, const int8_t* sig, long n_s, const float2* a_t, const float2* a_g,
-                               const float2* th_t, const float2* th_g, const double2* beta, double2* B,
-                               hipStream_t stream) {
-    const int E = (M + kWave - 1) / kWave;
-    const dim3 grid((unsigned)((n_s + 3) / 4)), block(256);
-    switch (E) {
-#define CRBM_CASE(e) case e: hipLaunchKernelGGL(k_moment_ratio<e>, grid, block, 0, stream, N, M, sig, n_s, a_t, a_g, th_t, th_g, beta, B); break;
-        CRBM_CASE(1) CRBM_CASE(2) CRBM_CASE(3) CRBM_CASE(4) CRBM_CASE(5) CRBM_CASE(6) CRBM_CASE(7) CRBM_CASE(8)
-#undef CRBM_CASE
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
 }
 
 hipError_t launch_fq_chunk(const Geometry& g, const int8_t* sig, long n_s, const double* q_host, int n_q,
