@@ -14,8 +14,6 @@
 #include "internal.hpp"
 
 namespace crbm {
-hipError_t launch_theta(const int8_t* sig, long n, int N, int M, const float2* b, const float2* W, float2* theta,
-                        hipStream_t stream, const double* skip = nullptr);
 hipError_t launch_local_core(const LocalArgs& A, const float2* th1, const float2* thn, const float2* thm,
                              hipStream_t stream);
 hipError_t launch_lc_sums(const int8_t* sig, long n, int N, int M, const float2* a, const float2* b,
@@ -298,6 +296,7 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
     rc = rc ? rc : p->alloc(&p->momF, (long)kQChunk * S);
     rc = rc ? rc : p->alloc(&p->mom_partial, (long)kMomBlocks * kMaxMomentEntries);
     rc = rc ? rc : p->alloc(&p->wplanes, lc_plane_elems(N, M));
+    p->w.wplanes = p->wplanes;
     rc = rc ? rc : p->alloc(&p->lcLg, S);
     rc = rc ? rc : p->alloc(&p->bcounter, 1);
     rc = rc ? rc : p->alloc(&p->bpartial, 2 * S);
@@ -493,7 +492,7 @@ int crbm_local_estimators(crbm_plan p, const crbm_rbm* fit, const crbm_rbm* psi_
     A.O_out = static_cast<float2*>(O_out);
     auto theta = [&](const RbmView& v, float2* out) {
         p->prof.begin(PROF_THETA, stream);
-        hipError_t r = launch_theta(samples, n, p->N, p->M, v.b, v.W, out, stream);
+        hipError_t r = launch_theta(samples, n, p->N, p->M, v.b, v.W, out, p->wplanes, stream);
         p->prof.end(stream);
         return r;
     };
@@ -670,7 +669,7 @@ int crbm_moment_matrices(crbm_plan p, const crbm_rbm* gs, const void* t_params, 
 
     // order 0: B_0 = f_q, HB_0 = (H S^z_q psi_gs)/psi_gs
     p->prof.begin(PROF_THETA, stream);
-    hipError_t e = launch_theta(samples, n, p->N, p->M, vg.b, vg.W, p->theta[0], stream);
+    hipError_t e = launch_theta(samples, n, p->N, p->M, vg.b, vg.W, p->theta[0], p->wplanes, stream);
     p->prof.end(stream);
     if (e == hipSuccess) e = launch_fq_chunk(g, samples, n, q, 1, p->momF, stream);
     LocalArgs A{};
@@ -705,7 +704,7 @@ int crbm_moment_matrices(crbm_plan p, const crbm_rbm* gs, const void* t_params, 
         vt.b = at + p->N;
         vt.W = at + p->N + p->M;
         p->prof.begin(PROF_THETA, stream);
-        e = launch_theta(samples, n, p->N, p->M, vt.b, vt.W, p->theta[1], stream);
+        e = launch_theta(samples, n, p->N, p->M, vt.b, vt.W, p->theta[1], p->wplanes, stream);
         p->prof.end(stream);
         LocalArgs At{};
         At.g = g;
@@ -787,7 +786,7 @@ int crbm_sym_matrices(crbm_plan p, const crbm_rbm* gs, const void* t_params, con
     hipError_t e = hipSuccess;
     auto theta = [&](const int8_t* sig, long rows, const RbmView& v, float2* out) {
         p->prof.begin(PROF_THETA, stream);
-        hipError_t r = launch_theta(sig, rows, N, M, v.b, v.W, out, stream);
+        hipError_t r = launch_theta(sig, rows, N, M, v.b, v.W, out, p->wplanes, stream);
         p->prof.end(stream);
         return r;
     };

@@ -15,7 +15,12 @@ struct RbmView {            // device pointers, complex64 interleaved
     const float2* W;
 };
 
-// elements of the three BF16 planes of W used by the fused log-cosh sums: 3 x (tiles of 64 units x 128
+// theta = sigma W + b (complex64 [n][M]) on the matrix cores; planes: lc_plane_elems(N, M) scratch for
+// the split W; skip (device, may be null) != 0 makes both launches return at once
+hipError_t launch_theta(const int8_t* sig, long n, int N, int M, const float2* b, const float2* W, float2* theta,
+                        uint16_t* planes, hipStream_t stream, const double* skip = nullptr);
+
+// elements of the three BF16 planes of W used by the theta product and the fused log-cosh sums: 3 x (tiles of 64 units x 128
 // real columns) x (sites rounded up to 32)
 inline long lc_plane_elems(long N, long M) { return 3L * ((M + 63) / 64) * 128L * ((N + 31) / 32 * 32); }
 
@@ -115,6 +120,7 @@ struct SrWork {
     long sb_order_len;
     float2* spart;            // [nsplit_max][P][P] partial sums of a contraction split over samples (or null)
     double2* hv_part;         // [nT][nT][kHemvTile] tile shares of the dense Hermitian product (with S)
+    uint16_t* wplanes;        // split-W scratch of the theta product (the matrix-free product's G)
     int nsplit_max;
     int n_cu;
     Profiler* prof;

@@ -21,95 +21,17 @@ namespace crbm {
 // binary32 W entry is split exactly into three BF16 parts by truncation,
 //   W = hi + mid + lo   (8 + 8 + 8 significand bits),
 // so three v_mfma_f32_32x32x16_bf16 products give sigma W with exact products and
-// FP32 accumulation.  The complex W is a real [N][2M] matrix (re, im interleaved), so the
-// output rows are the complex64 theta rows.  Tile: 128 samples x 128 real columns per
-// workgroup (4 waves x 32 samples x 4 column blocks), K chunks of 32 sites through LDS.
+// FP32 accumulation.  The B columns of a tile of 64 hidden units are the real and imaginary
+// parts of W ordered [Re 0..31 | Im 0..31 | Re 32..63 | Im 32..63], so that both parts of a
+// unit end in one lane; W is split into its parts in that order once per RBM (k_wsplit).
+// Tile: 128 samples x 128 real columns per workgroup (4 waves x 32 samples x 4 column blocks),
+// K chunks of 32 sites through LDS.
 typedef __attribute__((__vector_size__(8 * sizeof(short)))) short bf16x8_t;
 typedef __attribute__((__vector_size__(4 * sizeof(int)))) int i32x4_t;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16_t;
 
 constexpr int TH_S = 128, TH_C = 128, TH_K = 32;
 constexpr int TH_ROW = TH_K * 2 + 16;          // bytes per LDS row (32 bf16 + padding)
-
-__global__ __launch_bounds__(256) void k_theta(const int8_t* __restrict__ sig, long n, int N, int M,
-                                                const float2* __restrict__ b, const float2* __restrict__ W,
-                                                float2* __restrict__ theta, const double* __restrict__ skip) {
-    if (skip && *skip != 0.0) return;     // a converged iterative solve skips the product
-    __shared__ __attribute__((aligned(16))) unsigned char s_sig[TH_S * TH_ROW];
-    __shared__ __attribute__((aligned(16))) unsigned char s_w[3][TH_C * TH_ROW];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const long s0 = (long)blockIdx.x * TH_S;
-    const int c0 = blockIdx.y * TH_C;                 // first real column
-    const int C = 2 * M;                              // real columns
-    const float* Wf = reinterpret_cast<const float*>(W);
-    floatx16_t acc[4];
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) acc[cb][v] = 0.f;
-
-    for (int k0 = 0; k0 < N; k0 += TH_K) {
-        // sigma tile [128 samples][32 sites] as BF16 (+1 = 0x3F80, -1 = 0xBF80, outside = 0)
-        for (int e = tid; e < TH_S * TH_K; e += 256) {
-            const int ss = e / TH_K, kk = e % TH_K;
-            const long s = s0 + ss;
-            const int i = k0 + kk;
-            uint16_t v = 0;
-            if (s < n && i < N) v = sig[s * N + i] > 0 ? 0x3F80 : 0xBF80;
-            *reinterpret_cast<uint16_t*>(s_sig + ss * TH_ROW + kk * 2) = v;
-        }
-        // W^T tile [128 columns][32 sites], three exact BF16 parts
-        for (int e = tid; e < TH_C * TH_K; e += 256) {
-            const int kk = e / TH_C, cc = e % TH_C;
-            const int i = k0 + kk, c = c0 + cc;
-            const float w = (i < N && c < C) ? Wf[(long)i * C + c] : 0.f;
-            const uint32_t u = __float_as_uint(w);
-            const uint32_t hi = u & 0xFFFF0000u;
-            const float r1 = w - __uint_as_float(hi);
-            const uint32_t mid = __float_as_uint(r1) & 0xFFFF0000u;
-            const float r2 = r1 - __uint_as_float(mid);
-            *reinterpret_cast<uint16_t*>(s_w[0] + cc * TH_ROW + kk * 2) = (uint16_t)(hi >> 16);
-            *reinterpret_cast<uint16_t*>(s_w[1] + cc * TH_ROW + kk * 2) = (uint16_t)(mid >> 16);
-            *reinterpret_cast<uint16_t*>(s_w[2] + cc * TH_ROW + kk * 2) = (uint16_t)(__float_as_uint(r2) >> 16);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kq = 0; kq < TH_K; kq += 16) {
-            const int koff = (kq + 8 * (lane >> 5)) * 2;
-            const i32x4_t a = *reinterpret_cast<const i32x4_t*>(s_sig + (wave * 32 + (lane & 31)) * TH_ROW + koff);
-#pragma unroll
-            for (int part = 0; part < 3; ++part)
-#pragma unroll
-                for (int cb = 0; cb < 4; ++cb) {
-                    const i32x4_t bw =
-                        *reinterpret_cast<const i32x4_t*>(s_w[part] + (cb * 32 + (lane & 31)) * TH_ROW + koff);
-                    acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16((bf16x8_t)a, (bf16x8_t)bw, acc[cb], 0, 0, 0);
-                }
-        }
-        __syncthreads();
-    }
-    const float* bf = reinterpret_cast<const float*>(b);
-    float* out = reinterpret_cast<float*>(theta);
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-        const int c = c0 + cb * 32 + (lane & 31);
-        if (c >= C) continue;
-        const float bc = bf[c];
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const long s = s0 + wave * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-            if (s < n) out[s * C + c] = acc[cb][v] + bc;
-        }
-    }
-}
-
-hipError_t launch_theta(const int8_t* sig, long n, int N, int M, const float2* b, const float2* W, float2* theta,
-                        hipStream_t stream, const double* skip) {
-    if (n <= 0) return hipSuccess;
-    dim3 grid((unsigned)((n + TH_S - 1) / TH_S), (unsigned)((2 * M + TH_C - 1) / TH_C));
-    hipLaunchKernelGGL(k_theta, grid, dim3(256), 0, stream, sig, n, N, M, b, W, theta, skip);
-    return hipGetLastError();
-}
 
 // ------------------------------------------------------------------ helpers
 // f_q(sigma) = N^{-1/2} sum_r exp(-i q.r) sigma_r / 2 over the wave's spins
@@ -146,17 +68,16 @@ __device__ __forceinline__ float2 a_dot_sigma(const float2* a, const WaveSpins& 
 
 // ------------------------------------------------------------------ theta GEMM fused with sum log cosh
 // For the moment ratios only the per-sample sums  L(s) = sum_k log cosh theta_k(s)  of an RBM are
-// needed, not theta itself.  The product runs as above, with the B columns of a 64-unit tile ordered
-// [Re 0..31 | Im 0..31 | Re 32..63 | Im 32..63], so that the real and imaginary parts of a hidden unit
-// land in the same lane; each lane then forms, row by row,
+// needed, not theta itself.  With both parts of a hidden unit in one lane, each lane forms, row by row,
 //   log cosh z = s z + log((1 + w)/2),   s = sign(Re z),  w = exp(-2 s z),  |(1 + w)/2| <= 1,
 // keeping s z as a sum and (1 + w)/2 as a product, multiplies the products over the tile's columns
 // by a reduce-scatter over the lane bits and takes one complex log per sample row.
 //
-// W is first split into its three exact BF16 parts in that column order (planes [3][Mt 128][Np],
-// Np = N rounded up to TH_K, zero padding), so the product's workgroups only copy tiles.
+// The planes of W are [3][Mt 128][Np], Np = N rounded up to TH_K, zero padded; the product's
+// workgroups only copy tiles of them.
 __global__ __launch_bounds__(256) void k_wsplit(const float2* __restrict__ W, int N, int M, int Np, int Mt,
-                                                uint16_t* __restrict__ planes) {
+                                                uint16_t* __restrict__ planes, const double* __restrict__ skip) {
+    if (skip && *skip != 0.0) return;     // a converged iterative solve skips the product
     const long rows = (long)Mt * TH_C;
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
     if (idx >= rows * Np) return;
@@ -184,21 +105,18 @@ __device__ __forceinline__ void lc_join(float2& lin, float2& pr, float2 lin2, fl
     pr = cmul(pr, pr2);
 }
 
-__global__ __launch_bounds__(256) void k_theta_lc(const int8_t* __restrict__ sig, long n, int N, int Np, int M,
-                                                  const float2* __restrict__ b, const uint16_t* __restrict__ planes,
-                                                  int Mt, float2* __restrict__ partial) {
-    __shared__ __attribute__((aligned(16))) unsigned char s_sig[TH_S * TH_ROW];
-    __shared__ __attribute__((aligned(16))) unsigned char s_w[3][TH_C * TH_ROW];
+// The tile product: workgroup (x, ct) accumulates sigma[128 x s .. + 128) times the 128 plane rows of
+// unit tile ct over all sites, K chunks of TH_K sites through LDS.  Lane l of wave w ends with column
+// l % 32 of each 32-column block cb in acc[cb], rows w 32 + 8 (v / 4) + 4 (l / 32) + v % 4.
+__device__ __forceinline__ void theta_tile(const int8_t* __restrict__ sig, long n, int N, int Np,
+                                           const uint16_t* __restrict__ planes, long rows, int ct, long s0,
+                                           unsigned char* s_sig, unsigned char (*s_w)[TH_C * TH_ROW],
+                                           floatx16_t (&acc)[4]) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const long s0 = (long)blockIdx.x * TH_S;
-    const int ct = blockIdx.y;                        // 64-unit tile
-    const long rows = (long)Mt * TH_C;
-    floatx16_t acc[4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[cb][v] = 0.f;
-
     for (int k0 = 0; k0 < Np; k0 += TH_K) {
         for (int e = tid; e < TH_S * TH_K; e += 256) {
             const int ss = e / TH_K, kk = e % TH_K;
@@ -231,6 +149,56 @@ __global__ __launch_bounds__(256) void k_theta_lc(const int8_t* __restrict__ sig
         }
         __syncthreads();
     }
+}
+
+// theta = sigma W + b, complex64 [n][M]: lane column j holds units 64 ct + j (blocks 0, 1) and
+// 64 ct + 32 + j (blocks 2, 3), real and imaginary part together, so 32 lanes store 256 contiguous bytes
+__global__ __launch_bounds__(256) void k_theta(const int8_t* __restrict__ sig, long n, int N, int Np, int M,
+                                               const float2* __restrict__ b, const uint16_t* __restrict__ planes,
+                                               int Mt, float2* __restrict__ theta, const double* __restrict__ skip) {
+    if (skip && *skip != 0.0) return;     // a converged iterative solve skips the product
+    __shared__ __attribute__((aligned(16))) unsigned char s_sig[TH_S * TH_ROW];
+    __shared__ __attribute__((aligned(16))) unsigned char s_w[3][TH_C * TH_ROW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long s0 = (long)blockIdx.x * TH_S;
+    const int ct = blockIdx.y;
+    floatx16_t acc[4];
+    theta_tile(sig, n, N, Np, planes, (long)Mt * TH_C, ct, s0, s_sig, s_w, acc);
+    const int ku0 = ct * 64 + (lane & 31), ku1 = ku0 + 32;
+    const float2 b0 = ku0 < M ? b[ku0] : make_float2(0.f, 0.f);
+    const float2 b1 = ku1 < M ? b[ku1] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const long sm = s0 + wave * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (sm >= n) continue;
+        if (ku0 < M) theta[sm * M + ku0] = make_float2(acc[0][v] + b0.x, acc[1][v] + b0.y);
+        if (ku1 < M) theta[sm * M + ku1] = make_float2(acc[2][v] + b1.x, acc[3][v] + b1.y);
+    }
+}
+
+hipError_t launch_theta(const int8_t* sig, long n, int N, int M, const float2* b, const float2* W, float2* theta,
+                        uint16_t* planes, hipStream_t stream, const double* skip) {
+    if (n <= 0) return hipSuccess;
+    const int Np = (N + TH_K - 1) / TH_K * TH_K;
+    const int Mt = (M + 63) / 64;
+    const long cnt = (long)Mt * TH_C * Np;
+    hipLaunchKernelGGL(k_wsplit, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, W, N, M, Np, Mt, planes,
+                       skip);
+    hipLaunchKernelGGL(k_theta, dim3((unsigned)((n + TH_S - 1) / TH_S), (unsigned)Mt), dim3(256), 0, stream, sig, n,
+                       N, Np, M, b, planes, Mt, theta, skip);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_theta_lc(const int8_t* __restrict__ sig, long n, int N, int Np, int M,
+                                                  const float2* __restrict__ b, const uint16_t* __restrict__ planes,
+                                                  int Mt, float2* __restrict__ partial) {
+    __shared__ __attribute__((aligned(16))) unsigned char s_sig[TH_S * TH_ROW];
+    __shared__ __attribute__((aligned(16))) unsigned char s_w[3][TH_C * TH_ROW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long s0 = (long)blockIdx.x * TH_S;
+    const int ct = blockIdx.y;                        // 64-unit tile
+    floatx16_t acc[4];
+    theta_tile(sig, n, N, Np, planes, (long)Mt * TH_C, ct, s0, s_sig, s_w, acc);
     // lane column j = lane % 32: units k0u = 64 ct + j (acc 0, 1) and k1u = k0u + 32 (acc 2, 3)
     const int j = lane & 31;
     const int ku0 = ct * 64 + j, ku1 = ku0 + 32;
@@ -345,7 +313,8 @@ hipError_t launch_lc_sums(const int8_t* sig, long n, int N, int M, const float2*
     const int Np = (N + TH_K - 1) / TH_K * TH_K;
     const int Mt = (M + 63) / 64;
     const long cnt = (long)Mt * TH_C * Np;
-    hipLaunchKernelGGL(k_wsplit, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, W, N, M, Np, Mt, planes);
+    hipLaunchKernelGGL(k_wsplit, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, W, N, M, Np, Mt, planes,
+                       nullptr);
     hipLaunchKernelGGL(k_theta_lc, dim3((unsigned)((n + TH_S - 1) / TH_S), (unsigned)Mt), dim3(256), 0, stream, sig,
                        n, N, Np, M, b, planes, Mt, partial);
     hipLaunchKernelGGL(k_lc_final, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, N, n, Mt, sig, a, partial,
@@ -480,6 +449,37 @@ __device__ __forceinline__ void local_flush(const LocalArgs& A, const RbmView& p
             if (q == qq) acc[qq] = cadd(acc[qq], c);
 }
 
+// This lane's share of sum_k [log cosh theta_k - log cosh phi_k] over its hidden units, theta and phi
+// rows of two RBMs at sample s: log cosh z = s z + log((1 + w)/2), w = exp(-2 s z), with the linear
+// parts added and the factors of modulus <= 1 multiplied, so that one complex log serves E units
+// (the M log 2 of log 2 cosh cancel between the two RBMs).
+template <int E>
+__device__ __forceinline__ float2 lc_diff(const float2* __restrict__ th, const float2* __restrict__ ph, long s, int M,
+                                          int lane) {
+    float2 lin = make_float2(0.f, 0.f), pt = make_float2(1.f, 0.f), pp = make_float2(1.f, 0.f);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = e * kWave + lane;
+        if (k >= M) continue;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const float2 z = h == 0 ? th[s * M + k] : ph[s * M + k];
+            const float sg = z.x >= 0.f ? 1.f : -1.f;
+            const float ex = expf(-2.f * fabsf(z.x));
+            float sn, cs;
+            sincosf(2.f * sg * z.y, &sn, &cs);
+            const float2 f = make_float2(0.5f * (1.f + ex * cs), -0.5f * ex * sn);
+            const float2 l = make_float2(fabsf(z.x), sg * z.y);
+            if (h == 0) { lin = cadd(lin, l); pt = cmul(pt, f); }
+            else { lin = csub(lin, l); pp = cmul(pp, f); }
+        }
+    }
+    // log pt - log pp = log|pt|/|pp| + i arg(pt conj(pp))
+    const float2 q = make_float2(pt.x * pp.x + pt.y * pp.y, pt.y * pp.x - pt.x * pp.y);
+    const float nt = pt.x * pt.x + pt.y * pt.y, np = pp.x * pp.x + pp.y * pp.y;
+    return make_float2(lin.x + 0.5f * (logf(nt) - logf(np)), lin.y + atan2f(q.y, q.x));
+}
+
 // One sample of a wave: log psi, tanh theta, O of fit; the tanh theta of the RBM whose Hamiltonian
 // action is taken (te), the diagonal factor d0 of t_0 and the anti-aligned bonds (mask words, count).
 template <int E>
@@ -507,18 +507,16 @@ __device__ __forceinline__ void local_sample(const LocalArgs& A, const float2* _
         const int k = e * kWave + lane;
         t1[e] = (k < M) ? th1g[s * M + k] : make_float2(0.f, 0.f);
     }
-    // log psi of fit and tanh theta of fit
+    // tanh theta of fit, and log psi of fit when asked for
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = e * kWave + lane;
-        if (k < M) {
-            lc1 = cadd(lc1, log2cosh(t1[e]));
-            T1[e] = ctanhf(t1[e]);
-        } else {
-            T1[e] = make_float2(0.f, 0.f);
-        }
+        T1[e] = (k < M) ? ctanhf(t1[e]) : make_float2(0.f, 0.f);
     }
     if (A.logpsi_out) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (e * kWave + lane < M) lc1 = cadd(lc1, log2cosh(t1[e]));
         const float2 lp = wave_sum(cadd(lc1, a_dot_sigma(A.fit.a, sp, lane, N)));
         if (lane == 0) A.logpsi_out[s] = lp;
     }
@@ -590,24 +588,14 @@ __device__ __forceinline__ void local_finish(const LocalArgs& A, const float2* _
     sp.load(A.samples + s * N, N, lane);
     const float2 asig1 = a_dot_sigma(A.fit.a, sp, lane, N);
     const float2 ht = cscale(csub(eloc, cmul(make_float2((float)A.E_c, 0.f), d0)), (float)(1.0 / A.W_scale));
-    float2 dn = csub(a_dot_sigma(A.psn.a, sp, lane, N), asig1);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int k = e * kWave + lane;
-        if (k < M) dn = cadd(dn, csub(log2cosh(thng[s * M + k]), log2cosh(th1g[s * M + k])));
-    }
+    float2 dn = cadd(csub(a_dot_sigma(A.psn.a, sp, lane, N), asig1), lc_diff<E>(thng, th1g, s, M, lane));
     dn = wave_sum(dn);
     const float2 bn = make_float2((float)A.beta_n.x, (float)A.beta_n.y);
     float2 R;
     if (A.order == 0) {
         R = cmul(cmul(bn, ht), cexpf(dn));
     } else {
-        float2 dm = csub(a_dot_sigma(A.psm.a, sp, lane, N), asig1);
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int k = e * kWave + lane;
-            if (k < M) dm = cadd(dm, csub(log2cosh(thmg[s * M + k]), log2cosh(th1g[s * M + k])));
-        }
+        float2 dm = cadd(csub(a_dot_sigma(A.psm.a, sp, lane, N), asig1), lc_diff<E>(thmg, th1g, s, M, lane));
         dm = wave_sum(dm);
         const float2 fm = (A.order != 1) ? make_float2(1.f, 0.f)
                         : A.local_op ? make_float2(0.5f * (float)sp.get(0), 0.f) : fq_wave(sp, lane, g, A.q0, A.q1);

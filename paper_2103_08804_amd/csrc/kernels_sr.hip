@@ -17,13 +17,11 @@
 
 namespace crbm {
 
-hipError_t launch_theta(const int8_t* sig, long n, int N, int M, const float2* b, const float2* W, float2* theta,
-                        hipStream_t stream, const double* skip = nullptr);
 
-// device scalar slots
+// device scalar slots (SC_RR and SC_RR1 hold r^H r of the even and odd CG iterations; 11 is spare)
 enum {
     SC_RM_RE = 0, SC_RM_IM, SC_R2, SC_GAMMA, SC_GCOT, SC_COEF,
-    SC_RR = 8, SC_PAP, SC_ALPHA, SC_RRNEW, SC_FF, SC_DONE, SC_ITERS, SC_FLAGS, SC_RESID, SC_XX,
+    SC_RR = 8, SC_PAP, SC_RR1, SC_SPARE, SC_FF, SC_DONE, SC_ITERS, SC_FLAGS, SC_RESID, SC_XX,
     SC_COUNT = 32
 };
 
@@ -350,6 +348,9 @@ __global__ __launch_bounds__(256) void k_sbuild(int N, int M, long P, const int8
 // second pass adds the nT slots of every row in the same order (deterministic).
 constexpr int HV_T = kHemvTile;
 
+// PAIR (P even, so every row and tile starts on 16 bytes): a lane reads two adjacent columns per load,
+// columns 2 c0 + 32 j' + {0, 1}; otherwise one column, c0 + 16 j.
+template <bool PAIR>
 __global__ __launch_bounds__(256) void k_hemv_tiles(long P, int nT, const float2* __restrict__ S,
                                                     const double2* __restrict__ x, double2* __restrict__ part,
                                                     const double* __restrict__ sc) {
@@ -367,8 +368,8 @@ __global__ __launch_bounds__(256) void k_hemv_tiles(long P, int nT, const float2
     xI[tid] = i0 + tid < P ? x[i0 + tid] : make_double2(0.0, 0.0);
     xJ[tid] = j0 + tid < P ? x[j0 + tid] : make_double2(0.0, 0.0);
     __syncthreads();
-    // a 16-lane group takes one row at a time; lane c0 of the group reads columns c0 + 16 j, so
-    // that every load instruction of a group covers 128 contiguous bytes of the row
+    // a 16-lane group takes one row at a time, so that every load instruction of a group covers
+    // 128 (256 with PAIR) contiguous bytes of the row
     const int lane = tid & 63, w = tid >> 6, g = lane >> 4, c0 = lane & 15;
     const int nrows = (int)(P - i0 < HV_T ? P - i0 : HV_T);
     const int ncols = (int)(P - j0 < HV_T ? P - j0 : HV_T);
@@ -380,16 +381,29 @@ __global__ __launch_bounds__(256) void k_hemv_tiles(long P, int nT, const float2
         const double2 xi = xI[rr];
         double rx = 0.0, ry = 0.0;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int c = c0 + 16 * j;
-            // columns past P: read column 0 instead; x_J is zero there and the column share is unused
-            const float2 sv = Sr[c < ncols ? c : 0];
-            const double sx = sv.x, sy = sv.y;
-            const double2 xj = xJ[c];
-            rx += sx * xj.x - sy * xj.y;
-            ry += sx * xj.y + sy * xj.x;
-            cx[j] += sx * xi.x + sy * xi.y;            // conj(S_rc) x_r
-            cy[j] += sx * xi.y - sy * xi.x;
+        for (int jp = 0; jp < (PAIR ? 8 : 16); ++jp) {
+            float2 sv2[2];
+            if constexpr (PAIR) {
+                const int c = 2 * c0 + 32 * jp;
+                // columns past P: read columns 0, 1 instead; x_J is zero there and the column share is unused
+                const float4 v4 = *reinterpret_cast<const float4*>(Sr + (c < ncols ? c : 0));
+                sv2[0] = make_float2(v4.x, v4.y);
+                sv2[1] = make_float2(v4.z, v4.w);
+            } else {
+                const int c = c0 + 16 * jp;
+                sv2[0] = Sr[c < ncols ? c : 0];
+            }
+#pragma unroll
+            for (int h = 0; h < (PAIR ? 2 : 1); ++h) {
+                const int j = PAIR ? 2 * jp + h : jp;
+                const int c = PAIR ? 2 * c0 + 32 * jp + h : c0 + 16 * jp;
+                const double sx = sv2[h].x, sy = sv2[h].y;
+                const double2 xj = xJ[c];
+                rx += sx * xj.x - sy * xj.y;
+                ry += sx * xj.y + sy * xj.x;
+                cx[j] += sx * xi.x + sy * xi.y;            // conj(S_rc) x_r
+                cy[j] += sx * xi.y - sy * xi.x;
+            }
         }
 #pragma unroll
         for (int o = 8; o >= 1; o >>= 1) {
@@ -409,7 +423,7 @@ __global__ __launch_bounds__(256) void k_hemv_tiles(long P, int nT, const float2
     }
     if (g == 0)
 #pragma unroll
-        for (int j = 0; j < 16; ++j) cred[w][c0 + 16 * j] = make_double2(cx[j], cy[j]);
+        for (int j = 0; j < 16; ++j) cred[w][PAIR ? 2 * c0 + 32 * (j >> 1) + (j & 1) : c0 + 16 * j] = make_double2(cx[j], cy[j]);
     __syncthreads();
     const double2 a = cred[0][tid], b = cred[1][tid], c = cred[2][tid], d = cred[3][tid];
     part[((long)J * nT + I) * HV_T + tid] = make_double2(((a.x + b.x) + c.x) + d.x, ((a.y + b.y) + c.y) + d.y);
@@ -545,43 +559,87 @@ __global__ void k_sum_to(const double2* __restrict__ red, int n_red, double* __r
     sc[slot] = a;
 }
 
-// x += alpha p; r -= alpha Ap  with alpha = rr / pAp
+// real part of red[0] + ... + red[n-1] in one fixed order, the same in every block (256 threads)
+__device__ __forceinline__ double block_sum_re(const double2* __restrict__ red, int n, double* sh) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) a += red[i].x;
+    sh[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double t = sh[0];
+    __syncthreads();
+    return t;
+}
+
+// x += alpha p, r -= alpha Ap with alpha = rr / pAp (pAp from the 64 partials of k_zdot, rr in slot
+// `slot`); each block leaves its part of the new r^H r in red_rr[block]
 __global__ __launch_bounds__(256) void k_cg_xr(long P, double2* __restrict__ x, double2* __restrict__ r,
                                                const double2* __restrict__ p, const double2* __restrict__ Ap,
-                                               const double* __restrict__ sc) {
-    if (sc[SC_DONE] != 0.0) return;
-    const double alpha = sc[SC_RR] / sc[SC_PAP];
+                                               const double2* __restrict__ red_pap, double2* __restrict__ red_rr,
+                                               double* __restrict__ sc, int slot) {
+    __shared__ double sh[256];
+    if (sc[SC_DONE] != 0.0) return;              // set only by k_cg_check_p: fixed during this launch
+    const double pap = block_sum_re(red_pap, 64, sh);
+    const double alpha = sc[slot] / pap;
     const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= P) return;
-    x[k] = make_double2(x[k].x + alpha * p[k].x, x[k].y + alpha * p[k].y);
-    r[k] = make_double2(r[k].x - alpha * Ap[k].x, r[k].y - alpha * Ap[k].y);
+    double rr = 0.0;
+    if (k < P) {
+        x[k] = make_double2(x[k].x + alpha * p[k].x, x[k].y + alpha * p[k].y);
+        const double2 rk = make_double2(r[k].x - alpha * Ap[k].x, r[k].y - alpha * Ap[k].y);
+        r[k] = rk;
+        rr = rk.x * rk.x + rk.y * rk.y;
+    }
+    sh[threadIdx.x] = rr;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        red_rr[blockIdx.x] = make_double2(sh[0], 0.0);
+        if (blockIdx.x == 0) sc[SC_PAP] = pap;
+    }
 }
 
-// convergence test and beta; runs after SC_RRNEW is set
-__global__ void k_cg_check(double* __restrict__ sc, double tol, int maxit) {
-    if (threadIdx.x != 0 || sc[SC_DONE] != 0.0) return;
-    sc[SC_ITERS] += 1.0;
-    const double rn = sc[SC_RRNEW];
+// Convergence test of iteration `it` and the direction update p = r + beta p.  Every block adds the
+// r^H r partials in the same order and takes the same decision; block 0 records it: the new r^H r goes
+// to the other slot than the one read, so no block reads a slot written in this launch.
+__global__ __launch_bounds__(256) void k_cg_check_p(long P, double2* __restrict__ p, const double2* __restrict__ r,
+                                                    const double2* __restrict__ red_rr, int n_red,
+                                                    double* __restrict__ sc, double tol, int maxit, int it, int slot) {
+    __shared__ double sh[256];
+    __shared__ int s_done;
+    if (threadIdx.x == 0) s_done = sc[SC_DONE] != 0.0;   // block 0 may set it during this launch
+    __syncthreads();
+    if (s_done) return;
+    const double rn = block_sum_re(red_rr, n_red, sh);
     const bool bad = !isfinite(rn) || !(sc[SC_PAP] > 0.0);
-    if (bad) { sc[SC_FLAGS] = (double)((int)sc[SC_FLAGS] | CRBM_FLAG_NONFINITE); sc[SC_DONE] = 1.0; return; }
-    if (sqrt(rn) <= tol * sqrt(sc[SC_FF])) { sc[SC_DONE] = 1.0; sc[SC_RR] = rn; return; }
-    if (sc[SC_ITERS] >= (double)maxit) {
-        sc[SC_FLAGS] = (double)((int)sc[SC_FLAGS] | CRBM_FLAG_NOT_CONVERGED);
-        sc[SC_DONE] = 1.0;
-        sc[SC_RR] = rn;
+    const bool conv = !bad && sqrt(rn) <= tol * sqrt(sc[SC_FF]);
+    const bool last = it + 1 >= maxit;
+    const int next = slot == SC_RR ? SC_RR1 : SC_RR;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if (bad || conv || last) {
+        if (lead) {
+            int fl = (int)sc[SC_FLAGS];
+            if (bad) fl |= CRBM_FLAG_NONFINITE;
+            else if (!conv) fl |= CRBM_FLAG_NOT_CONVERGED;
+            sc[SC_FLAGS] = (double)fl;
+            sc[SC_ITERS] = (double)(it + 1);
+            sc[next] = rn;
+            sc[SC_DONE] = 1.0;
+        }
         return;
     }
-    sc[SC_ALPHA] = rn / sc[SC_RR];   // beta of the direction update
-    sc[SC_RR] = rn;
-}
-
-__global__ __launch_bounds__(256) void k_cg_p(long P, double2* __restrict__ p, const double2* __restrict__ r,
-                                              const double* __restrict__ sc) {
-    if (sc[SC_DONE] != 0.0) return;
-    const double beta = sc[SC_ALPHA];
+    const double beta = rn / sc[slot];
     const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= P) return;
-    p[k] = make_double2(r[k].x + beta * p[k].x, r[k].y + beta * p[k].y);
+    if (k < P) p[k] = make_double2(r[k].x + beta * p[k].x, r[k].y + beta * p[k].y);
+    if (lead) {
+        sc[next] = rn;
+        sc[SC_ITERS] = (double)(it + 1);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_cg_init(long P, const double2* __restrict__ F, double2* __restrict__ x,
@@ -651,7 +709,7 @@ static hipError_t apply_op(const SrArgs& A, const SrWork& W, const double2* v, d
         float2* vW = vb + A.M;
         hipLaunchKernelGGL(k_pack_v, dim3(nblk(P)), dim3(256), 0, stream, A.N, A.M, v, vb, vW, W.scal);
         float2* G = W.G;                                          // [n][M] scratch
-        hipError_t e = launch_theta(A.samples, A.n, A.N, A.M, vb, vW, G, stream, W.scal + SC_DONE);
+        hipError_t e = launch_theta(A.samples, A.n, A.N, A.M, vb, vW, G, W.wplanes, stream, W.scal + SC_DONE);
         if (e != hipSuccess) return e;
         const int E = (A.M + 63) / 64;
         const dim3 g4(nblk(A.n, 4)), b256(256);
@@ -669,8 +727,11 @@ static hipError_t apply_op(const SrArgs& A, const SrWork& W, const double2* v, d
         hipLaunchKernelGGL(k_add_shift, dim3(nblk(P)), dim3(256), 0, stream, P, v, A.eps, y, W.scal);
     } else {
         const int nT = hemv_tiles(P);
-        hipLaunchKernelGGL(k_hemv_tiles, dim3((unsigned)((long)nT * (nT + 1) / 2)), dim3(256), 0, stream, P, nT, W.S,
-                           v, W.hv_part, W.scal);
+        const dim3 grid((unsigned)((long)nT * (nT + 1) / 2));
+        if (P % 2 == 0)
+            hipLaunchKernelGGL(k_hemv_tiles<true>, grid, dim3(256), 0, stream, P, nT, W.S, v, W.hv_part, W.scal);
+        else
+            hipLaunchKernelGGL(k_hemv_tiles<false>, grid, dim3(256), 0, stream, P, nT, W.S, v, W.hv_part, W.scal);
         hipLaunchKernelGGL(k_hemv_reduce, dim3(nblk(P, 64)), dim3(256), 0, stream, P, nT, W.hv_part, v, A.eps, y,
                            W.scal);
     }
@@ -730,16 +791,17 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
         hipLaunchKernelGGL(k_cg_init, dim3(nblk(P)), dim3(256), 0, stream, P, W.F, W.x, W.r, W.p);
         hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(64), 0, stream, W.scal);
         W.prof->begin(PROF_CG, stream);
+        // partials: W.red[0, 64) for p^H Ap, W.red[64, 64 + nblk(P)) for r^H r
+        const int n_rr = (int)nblk(P);
         for (int it = 0; it < A.cg_maxit; ++it) {
+            const int slot = (it & 1) ? (int)SC_RR1 : (int)SC_RR;
             e = apply_op(A, W, W.p, W.Ap, stream);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_zdot, dim3(64), dim3(256), 0, stream, P, W.p, W.Ap, W.red, W.scal, 1);
-            hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(64), 0, stream, W.red, 64, W.scal, (int)SC_PAP, 1);
-            hipLaunchKernelGGL(k_cg_xr, dim3(nblk(P)), dim3(256), 0, stream, P, W.x, W.r, W.p, W.Ap, W.scal);
-            hipLaunchKernelGGL(k_zdot, dim3(64), dim3(256), 0, stream, P, W.r, W.r, W.red, W.scal, 1);
-            hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(64), 0, stream, W.red, 64, W.scal, (int)SC_RRNEW, 1);
-            hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64), 0, stream, W.scal, A.cg_tol, A.cg_maxit);
-            hipLaunchKernelGGL(k_cg_p, dim3(nblk(P)), dim3(256), 0, stream, P, W.p, W.r, W.scal);
+            hipLaunchKernelGGL(k_cg_xr, dim3(n_rr), dim3(256), 0, stream, P, W.x, W.r, W.p, W.Ap, W.red, W.red + 64,
+                               W.scal, slot);
+            hipLaunchKernelGGL(k_cg_check_p, dim3(n_rr), dim3(256), 0, stream, P, W.p, W.r, W.red + 64, n_rr, W.scal,
+                               A.cg_tol, A.cg_maxit, it, slot);
         }
         W.prof->end(stream);
         hipLaunchKernelGGL(k_undone, dim3(1), dim3(64), 0, stream, W.scal);
