@@ -205,6 +205,22 @@ def main():
         ceil = crbm.probe_hbm(1 << 30)
         roof["measured_ceiling"] = {"value": ceil, "unit": "GB/s", "probe": "16-byte copy of 1 GiB, read + write"}
         roof["frac_of_measured"] = roof["achieved"] / ceil
+    # the Metropolis sweep against its own ceilings (it has no datasheet roofline): half of the pair
+    # exchanges are null moves at S^z = 0 in expectation; every other proposal evaluates M Re log 2cosh
+    # and reads the rows W_i and W_j (2 M complex64) from L2
+    sampler = None
+    if "sample" in prof:
+        c, t = prof["sample"]
+        rate = C * sweeps * N / (t / c / 1e3)
+        lc = 0.5 * rate * M
+        gb = 0.5 * rate * 2 * M * 8 / 1e9
+        lc_ceil = crbm.probe_logcosh()
+        g_ceil = crbm.probe_gather(N, M)
+        sampler = {"proposals_per_s": rate, "logcosh_per_s": lc, "logcosh_ceiling": lc_ceil,
+                   "logcosh_frac": lc / lc_ceil, "row_gather_GBps": gb, "row_gather_ceiling_GBps": g_ceil,
+                   "row_gather_frac": gb / g_ceil,
+                   "probes": "Re log 2cosh in the sweep's form, 8 independent per lane, no memory traffic; whole-row "
+                             "reads of the N x M complex64 W at random rows"}
     line = {
         "metric": "MC samples/s + SR steps/s, 10x10 RBM alpha=4, BF16/batched vs plain FP32 at equal mu_n error",
         "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -220,11 +236,12 @@ def main():
         "gamma": float(st[0]),
         "phases": phases,
         "roofline": roof,
+        "sampler_roofline": sampler,
     }
     if not args.no_fp32_compare and solver == crbm.CG_DENSE and prec == crbm.BF16:
         line["fp32_compare"] = fp32_compare(crbm, plan, fit, flat, T, R, wl, args, ms_per_step, prof)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_budget_s, ns, sweeps, C)
+        line["cpu_baseline"], line["mu_error"] = cpu_baseline(args.cpu_budget_s, ns, sweeps, C)
     print(json.dumps(line))
     plan.close()
 
@@ -619,11 +636,50 @@ def cpu_baseline(budget_s, ns, sweeps, C):
     orc.moments(gs, ts, np.ones(20), [(math.pi, math.pi)], lat, sig)
     t3 = time.perf_counter()
     per_sample = 2 * (t1 - t0) / n_big + (t2 - t1) / n_big + (t3 - t2) / n_big
-    return {"value": 1.0 / per_sample, "unit": "samples/s", "cores": cores, "kind": "oracle",
+    base = {"value": 1.0 / per_sample, "unit": "samples/s", "cores": cores, "kind": "oracle",
             "sample": (f"{n_big} chains x 1 sweep (x2 for the psi_gs chains), local estimators and 20 moments on "
                        f"{n_big} samples of the 10x10 alpha=4 workload, {t3 - t0:.1f} s of CPU time; "
                        "natural-gradient step excluded (oracle dense S of 26 GB)"),
             "seconds": t3 - t0}
+    return base, mu_error_triplet(orc, gs, ts, sig, lat, ns)
+
+
+def mu_error_triplet(orc, gs, ts, sig, lat, ns_step):
+    """Error of the moments mu_n (n <= 20, q = (pi, pi)) against the FP64 oracle on the same samples, for the
+    BF16 and the plain FP32 path, beside the Monte-Carlo standard error at the step's sample count.
+
+    The moments do not go through S, so both paths run the same kernels (theta products with exact BF16
+    splits of W, FP32 log cosh, FP64 sums) and carry the same error.  The RBMs are rounded to complex64
+    once and both sides use those values; the samples are the oracle sampler's own."""
+    import torch
+    import paper_2103_08804_amd as crbm
+    r32 = lambda r: orc.RBM(*(np.asarray(x, np.complex64).astype(np.complex128) for x in (r.a, r.b, r.W)))
+    gs32, ts32 = r32(gs), [r32(t) for t in ts]
+    N, M, n_max = gs32.N, gs32.M, len(ts32)
+    n = sig.shape[0]
+    q = [(math.pi, math.pi)]
+    betas = np.ones(n_max, np.complex128)
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x, np.complex64)).cuda()
+    plan = crbm.Plan(crbm.SQUARE, lat.Lx, lat.Ly, M, n)
+    mu = torch.zeros(1, n_max + 1, dtype=torch.complex128, device="cuda")
+    crbm.chebyshev_moment(plan, crbm.RBM(dev(gs32.a), dev(gs32.b), dev(gs32.W)),
+                          torch.from_numpy(np.stack([t.vector() for t in ts32]).astype(np.complex64)).cuda(),
+                          torch.from_numpy(betas).cuda(), q, torch.from_numpy(np.ascontiguousarray(sig)).cuda(), mu)
+    got = mu.cpu().numpy()[0]
+    plan.close()
+    ref = orc.moments(gs32, ts32, betas, q, lat, sig)[0]
+    scale = np.abs(ref).max()
+    err = float(np.abs(got - ref).max() / scale)
+    # per-sample terms on a subset give the spread; the standard error is for the step's sample count
+    sub = np.ascontiguousarray(sig[:min(n, 8192)])
+    f = orc.fq(lat, q[0], sub)
+    lg = orc.logpsi(gs32, sub)
+    terms = [np.abs(f) ** 2] + [np.conj(f) * np.exp(orc.logpsi(t, sub) - lg) for t in ts32]
+    sigma = float(max(np.std(t) for t in terms) / math.sqrt(ns_step) / scale)
+    return {"n_samples": n, "bf16_path_rel_error": err, "fp32_path_rel_error": err, "sigma_mc_rel": sigma,
+            "note": ("max_n |mu_n - mu_n(FP64 oracle)| / max_n |mu_n| on the oracle's samples; sigma_mc: largest "
+                     "standard error of the mean at the step's sample count (per-sample spread on "
+                     f"{sub.shape[0]} samples), same scale; the moments do not use S")}
 
 
 if __name__ == "__main__":

@@ -155,9 +155,17 @@ int crbm_plan_profile_read(crbm_plan plan, int group, int* count, double* total_
  *   independent accumulators per wave, two workgroups of four waves per compute unit, no memory
  *   traffic in the loop), written to host *tflops_out.
  * crbm_probe_hbm: copy bandwidth in GB/s (bytes read + bytes written) of a 16-byte grid-stride copy
- *   of `bytes` (>= 1 MiB) between two device buffers, written to host *gbs_out. */
+ *   of `bytes` (>= 1 MiB) between two device buffers, written to host *gbs_out.
+ * crbm_probe_logcosh: evaluations per second of Re log(2 cosh z) in the Metropolis sweep's form
+ *   (hardware exp, cos and log; eight independent evaluations per lane, no memory traffic), the
+ *   transcendental ceiling of the sweep (Sec. III sampling), written to host *evals_out.
+ * crbm_probe_gather: GB/s of whole-row reads of an n_rows x row_elems complex64 table at pseudo-random
+ *   rows, lanes over the row (the sweep's reads of rows W_i, W_j), written to host *gbs_out; the
+ *   table holds at most 2^24 entries. */
 int crbm_probe_mfma(double* tflops_out, hipStream_t stream);
 int crbm_probe_hbm(size_t bytes, double* gbs_out, hipStream_t stream);
+int crbm_probe_logcosh(double* evals_out, hipStream_t stream);
+int crbm_probe_gather(int n_rows, int row_elems, double* gbs_out, hipStream_t stream);
 
 /* Fill a, b, W with complex numbers whose real and imaginary parts are independent
  * N(0, stddev^2): parameter k of the packed vector takes Philox4x32-10 block

@@ -32,7 +32,7 @@ EXPORTS = ("crbm_plan_create", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_la
            "crbm_plan_profile_read", "crbm_init_rbm", "crbm_init_chains", "crbm_sample", "crbm_local_estimators",
            "crbm_sr_step", "crbm_sr_energy_step", "crbm_chebyshev_moment", "crbm_fidelity_grad", "crbm_batched_moments",
            "crbm_batched_autotune", "crbm_moment_matrices", "crbm_corrected_moments", "crbm_lanczos",
-           "crbm_spectrum_kpm", "crbm_spectrum_cf", "crbm_probe_mfma", "crbm_probe_hbm",
+           "crbm_spectrum_kpm", "crbm_spectrum_cf", "crbm_probe_mfma", "crbm_probe_hbm", "crbm_probe_logcosh", "crbm_probe_gather",
            "crbm_sym_matrices")
 PROF_NAMES = ("sample", "theta", "local", "ot", "sbuild", "cg", "moment", "pack", "cholesky", "batched", "gram", "sborder")
 
@@ -90,6 +90,8 @@ def lib():
         L.crbm_spectrum_cf.argtypes = [_vp, _vp, _i, _d, _d, _vp, _i, _vp, _vp]
         L.crbm_probe_mfma.argtypes = [P(_d), _vp]
         L.crbm_probe_hbm.argtypes = [ctypes.c_size_t, P(_d), _vp]
+        L.crbm_probe_logcosh.argtypes = [P(_d), _vp]
+        L.crbm_probe_gather.argtypes = [_i, _i, P(_d), _vp]
         L.crbm_chebyshev_moment.argtypes = [_vp, P(_Rbm), _vp, _vp, _i, P(_d), _i, _vp, _vp, _l, _vp, _vp]
         L.crbm_fidelity_grad.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _l, _vp, _vp, _vp]
         L.crbm_batched_moments.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _i, ctypes.c_int64, _i, _i, _i, _u64,
@@ -422,6 +424,20 @@ def probe_hbm(nbytes: int = 1 << 30, stream=None) -> float:
     """Copy bandwidth (read + write) in GB/s of the current device (synchronises)."""
     v = ctypes.c_double()
     _check(lib().crbm_probe_hbm(nbytes, ctypes.byref(v), _stream(stream)))
+    return v.value
+
+
+def probe_logcosh(stream=None) -> float:
+    """Re log(2 cosh z) evaluations per second in the sweep's form on the current device (synchronises)."""
+    v = ctypes.c_double()
+    _check(lib().crbm_probe_logcosh(ctypes.byref(v), _stream(stream)))
+    return v.value
+
+
+def probe_gather(n_rows: int, row_elems: int, stream=None) -> float:
+    """GB/s of whole-row reads of an n_rows x row_elems complex64 table at random rows (synchronises)."""
+    v = ctypes.c_double()
+    _check(lib().crbm_probe_gather(n_rows, row_elems, ctypes.byref(v), _stream(stream)))
     return v.value
 
 

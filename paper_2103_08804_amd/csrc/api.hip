@@ -48,6 +48,9 @@ hipError_t launch_spec_cf(const double* a, const double* b2, int m, double E0, d
                           int n_w, double* A, hipStream_t stream);
 hipError_t launch_probe_mfma(int blocks, int iters, float* out, hipStream_t stream);
 hipError_t launch_probe_copy(int blocks, const void* src, void* dst, long n16, hipStream_t stream);
+hipError_t launch_probe_logcosh(int blocks, int iters, float* out, hipStream_t stream);
+hipError_t launch_probe_gather(int blocks, const void* tab, int n_rows, int M, int iters, float* out,
+                               hipStream_t stream);
 
 }  // namespace crbm
 
@@ -905,6 +908,46 @@ int crbm_probe_mfma(double* tflops_out, hipStream_t stream) {
     (void)hipFree(out);
     if (!(ms > 0)) return fail(CRBM_EHIP, "matrix-core probe failed");
     *tflops_out = (double)blocks * 4 * iters * 8 * 32768.0 / (ms * 1e-3) / 1e12;
+    return CRBM_OK;
+}
+
+int crbm_probe_logcosh(double* evals_out, hipStream_t stream) {
+    if (!evals_out) return fail(CRBM_EINVAL, "evals_out is NULL");
+    const int blocks = 8 * current_cus(), iters = 4000;
+    float* out = nullptr;
+    hipError_t e = hipMalloc(&out, (size_t)blocks * 256 * sizeof(float));
+    if (e != hipSuccess) { (void)hipGetLastError(); return fail(CRBM_ENOMEM, "probe buffer: %s", hipGetErrorString(e)); }
+    auto launch = [&]() { return launch_probe_logcosh(blocks, iters, out, stream); };
+    double ms = timed_ms(stream, launch);
+    if (ms > 0) ms = timed_ms(stream, launch);
+    (void)hipFree(out);
+    if (!(ms > 0)) return fail(CRBM_EHIP, "log-cosh probe failed");
+    *evals_out = (double)blocks * 256 * iters * 8 / (ms * 1e-3);
+    return CRBM_OK;
+}
+
+int crbm_probe_gather(int n_rows, int row_elems, double* gbs_out, hipStream_t stream) {
+    if (!gbs_out) return fail(CRBM_EINVAL, "gbs_out is NULL");
+    if (n_rows < 1 || row_elems < 1 || (long)n_rows * row_elems > (1L << 24))
+        return fail(CRBM_EINVAL, "need n_rows, row_elems >= 1 and a table of at most 2^24 entries");
+    const int blocks = 8 * current_cus(), iters = 2000;
+    float2* tab = nullptr;
+    float* out = nullptr;
+    hipError_t e = hipMalloc(&tab, (size_t)n_rows * row_elems * sizeof(float2));
+    if (e == hipSuccess) e = hipMalloc(&out, (size_t)blocks * 256 * sizeof(float));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (tab) (void)hipFree(tab);
+        return fail(CRBM_ENOMEM, "probe buffers: %s", hipGetErrorString(e));
+    }
+    auto launch = [&]() { return launch_probe_gather(blocks, tab, n_rows, row_elems, iters, out, stream); };
+    e = hipMemsetAsync(tab, 0, (size_t)n_rows * row_elems * sizeof(float2), stream);
+    double ms = e == hipSuccess ? timed_ms(stream, launch) : -1.0;
+    if (ms > 0) ms = timed_ms(stream, launch);
+    (void)hipFree(tab);
+    (void)hipFree(out);
+    if (!(ms > 0)) return fail(CRBM_EHIP, "gather probe failed");
+    *gbs_out = (double)blocks * 4 * iters * row_elems * sizeof(float2) / (ms * 1e-3) / 1e9;
     return CRBM_OK;
 }
 

@@ -72,3 +72,16 @@ def test_host_side_errors_of_the_spectral_calls():
     assert L.crbm_moment_matrices(None, None, None, None, 0, None, None, None, 1, None, None, None) == crbm.CRBM_EINVAL
     assert L.crbm_sr_energy_step(None, None, None, None, None, None, 1, 0.1, 0.0, 0, 0, 1e-6, 10, None,
                                  None) == crbm.CRBM_EINVAL
+
+
+def test_host_side_errors_of_the_probes():
+    L = crbm.lib()
+    v = ctypes.c_double()
+    assert L.crbm_probe_mfma(None, None) == crbm.CRBM_EINVAL
+    assert L.crbm_probe_hbm(1 << 30, None, None) == crbm.CRBM_EINVAL
+    assert L.crbm_probe_hbm(1000, ctypes.byref(v), None) == crbm.CRBM_EINVAL
+    assert L.crbm_probe_logcosh(None, None) == crbm.CRBM_EINVAL
+    assert L.crbm_probe_gather(100, 400, None, None) == crbm.CRBM_EINVAL
+    assert L.crbm_probe_gather(0, 400, ctypes.byref(v), None) == crbm.CRBM_EINVAL
+    assert L.crbm_probe_gather(1 << 13, 1 << 12, ctypes.byref(v), None) == crbm.CRBM_EINVAL
+    assert b"2^24" in L.crbm_last_error()

@@ -453,3 +453,16 @@ def test_dense_s_matrix_cores(orc, kind, Lx, Ly, M, n):
     assert errs[crbm.FP32][0] < 1e-5
     assert errs[crbm.FP32][1] < max(1e-4, 4 * kappa * errs[crbm.FP32][2])
     assert errs[crbm.BF16][0] < 2 ** -7
+
+
+def test_ceiling_probes():
+    """The roofline probes return finite positive rates of plausible size for an MI355X-class device."""
+    tf = crbm.probe_mfma()
+    gbs = crbm.probe_hbm(1 << 28)
+    lc = crbm.probe_logcosh()
+    gg = crbm.probe_gather(100, 400)
+    print("matrix cores TFLOP/s", tf, "HBM GB/s", gbs, "log-cosh/s", lc, "row gather GB/s", gg)
+    assert 100.0 < tf < 5000.0
+    assert 500.0 < gbs < 20000.0
+    assert 1e11 < lc < 1e14
+    assert 100.0 < gg < 100000.0
