@@ -85,12 +85,18 @@ __device__ __forceinline__ float2 log2cosh(float2 z) {
     const float wr = e * cs, wi = -e * sn;
     return make_float2(ax + 0.5f * log1pf(2.f * wr + e * e), sy + atan2f(wi, 1.f + wr));
 }
-// Re log(2 cosh z) = |x| + log(1 + 2 e cos 2y + e^2)/2, e = exp(-2|x|)  (hardware transcendentals)
+// Re log(2 cosh z) = |x| + log(q)/2, q = 1 + 2 e cos 2y + e^2 = |1 + e^{-2 s z}|^2 in [0, 4],
+// e = exp(-2|x|), on the hardware transcendentals alone: v_exp_f32 (2^x), v_cos_f32 (cos 2 pi x,
+// for |x| up to 256 revolutions, i.e. |y| < 804) and v_log_f32 (log2 x).
 __device__ __forceinline__ float re_log2cosh_fast(float2 z) {
+    constexpr float kM2Log2e = -2.8853900817779268f;  // exp(-2a) = 2^(-2a log2 e)
+    constexpr float kInvPi = 0.31830988618379067f;    // cos 2y = cos(2 pi (y / pi))
+    constexpr float kHalfLn2 = 0.34657359027997264f;  // log(q)/2 = (ln 2 / 2) log2 q
     const float ax = fabsf(z.x);
-    const float e = __expf(-2.f * ax);
-    const float c = __cosf(2.f * z.y);
-    return ax + 0.5f * __logf(fmaf(e, e, fmaf(2.f * e, c, 1.f)));
+    const float e = __builtin_amdgcn_exp2f(ax * kM2Log2e);
+    const float c = __builtin_amdgcn_cosf(z.y * kInvPi);
+    const float q = fmaf(e, e, fmaf(2.f * e, c, 1.f));
+    return fmaf(kHalfLn2, __builtin_amdgcn_logf(q), ax);
 }
 // tanh z = s (1 - w) / (1 + w), w = exp(-2 s z)
 __device__ __forceinline__ float2 ctanhf(float2 z) {
@@ -117,6 +123,25 @@ __device__ __forceinline__ double wave_sum(double v) {
 __device__ __forceinline__ float2 wave_sum(float2 v) { return make_float2(wave_sum(v.x), wave_sum(v.y)); }
 __device__ __forceinline__ double2 wave_sum(double2 v) { return make_double2(wave_sum(v.x), wave_sum(v.y)); }
 
+// Sum over the wave, returned to every lane as a wave-uniform value.  DPP only (no
+// LDS round trips): a butterfly over the 16 lanes of each row (quad swaps, then
+// the half-row and row mirrors leave the row total in every lane of the row),
+// then row broadcasts gather the four row totals into lane 63.  All 64 lanes
+// must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_move(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, false));
+}
+__device__ __forceinline__ float wave_total(float v) {
+    v += dpp_move<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
+    v += dpp_move<0x140, 0xF>(v);  // row_mirror
+    v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ float uniform(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
@@ -139,14 +164,13 @@ struct WaveSpins {
             if (site < N) row[site] = (int8_t)s[q];
         }
     }
-    // value of site i (i wave-uniform), broadcast to every lane
+    // value of site i (i wave-uniform), broadcast to every lane; each slot is read with a constant
+    // index and the choice is made among scalars, so s[] never needs an addressable copy
     __device__ __forceinline__ int get(int i) const {
-        const int q = i >> 6;
-        int v = s[0];
-        v = (q == 1) ? s[1] : v;
-        v = (q == 2) ? s[2] : v;
-        v = (q == 3) ? s[3] : v;
-        return __builtin_amdgcn_readlane(v, i & 63);
+        const int l = i & 63, q = i >> 6;
+        const int v0 = __builtin_amdgcn_readlane(s[0], l), v1 = __builtin_amdgcn_readlane(s[1], l);
+        const int v2 = __builtin_amdgcn_readlane(s[2], l), v3 = __builtin_amdgcn_readlane(s[3], l);
+        return q == 0 ? v0 : q == 1 ? v1 : q == 2 ? v2 : v3;
     }
     __device__ __forceinline__ void set(int i, int value, int lane) {
         if ((i & 63) == lane) {

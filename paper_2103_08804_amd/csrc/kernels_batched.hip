@@ -8,8 +8,9 @@
 // counter until all are done, so uneven chain counts per instance do not
 // unbalance the launch.  Per chain the wave keeps theta of psi_gs (for the
 // acceptance) and theta of t~_i (for the ratio) in registers and updates both
-// on every accepted exchange; after each recorded sweep it adds the chain's
-// terms in double precision.  Per-chain partial sums are reduced per instance
+// on every accepted move (theta of t~_i at the next accepted move or
+// measurement, so that its row reads overlap the proposals in between); after
+// each recorded sweep it adds the chain's terms in double precision.  Per-chain partial sums are reduced per instance
 // in chain order by a second kernel, so the result does not depend on the
 // schedule.  All launches are stream-ordered kernels (no host work), so the
 // sequence can be captured in a graph.
@@ -17,16 +18,115 @@
 
 #include "device.hpp"
 #include "internal.hpp"
+#include "sweep.hpp"
 
 namespace crbm {
-
-
 
 __global__ void k_batched_reset(unsigned long long* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0ull;
 }
 
-template <int E>
+// Per-chain state of one wave.  theta of t~ changes only on accepted moves;
+// its rows are fetched when a move is accepted and added at the next accepted
+// move or measurement, so their L2 round trip overlaps the following proposals.
+template <int E, bool PAIR>
+struct BatchedChain {
+    WaveSpins sp;
+    float2 thg[E], tht[E];  // theta of psi_gs and of t~
+    float Lg[E];            // Re log 2cosh theta_gs
+    float2 pti[E], ptj[E];  // rows of t~'s W for the pending update of tht
+    float pm;               // -2 s_i of the pending update, 0 when none
+    uint32_t tw;            // accept bits of the current trace word
+    double m0, mr, mi;      // sums of |f|^2 and conj(f) beta r
+};
+
+template <int E, bool PAIR>
+__device__ __forceinline__ void apply_pending(BatchedChain<E, PAIR>& c, int lane, int M) {
+    if (c.pm != 0.f) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const float2 d = row_delta<E, PAIR>(c.pti, c.ptj, e, lane, M);
+            c.tht[e].x = fmaf(c.pm, d.x, c.tht[e].x);
+            c.tht[e].y = fmaf(c.pm, d.y, c.tht[e].y);
+        }
+        c.pm = 0.f;
+    }
+}
+
+// f_q(s) and the ratio t~(s)/psi_gs(s) summed element by element, added to the chain's sums
+// ph: e^{-i q.r} and da: a_t - a_gs at this lane's sites
+template <int E, bool PAIR>
+__device__ __forceinline__ void measure(const BatchedArgs& A, BatchedChain<E, PAIR>& c, const float2 (&ph)[4],
+                                        const float2 (&da)[4], double2 beta, int lane) {
+    const int N = A.N, M = A.M;
+    apply_pending(c, lane, M);
+    float2 f = make_float2(0.f, 0.f), dlog = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+        const int site = qq * kWave + lane;
+        if (site < N) {
+            const float s = (float)c.sp.s[qq];
+            f = cadd(f, cscale(ph[qq], 0.5f * s));
+            dlog = cadd(dlog, cscale(da[qq], s));
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+        if (e * kWave + lane < M) dlog = cadd(dlog, csub(log2cosh(c.tht[e]), log2cosh(c.thg[e])));
+    f = make_float2(wave_total(f.x), wave_total(f.y));
+    dlog = make_float2(wave_total(dlog.x), wave_total(dlog.y));
+    const float2 r = cexpf(dlog);
+    const double fx = (double)f.x * (1.0 / sqrt((double)N)), fy = (double)f.y * (1.0 / sqrt((double)N));
+    const double2 br = zmul(beta, make_double2((double)r.x, (double)r.y));
+    c.m0 += fx * fx + fy * fy;
+    c.mr += fx * br.x + fy * br.y;  // conj(f) * (beta r)
+    c.mi += fx * br.y - fy * br.x;
+}
+
+struct BatchedPos {
+    long t;      // proposal index of the chain
+    int p, sw;   // position within the sweep, sweep index
+};
+
+// One proposal, with the measurement at the end of every recorded sweep.  Rows of psi_gs are read only
+// for live moves.
+template <int E, bool PAIR>
+__device__ __forceinline__ void batched_step(const BatchedArgs& A, uint64_t g, int lane, BatchedPos& pos,
+                                             BatchedChain<E, PAIR>& c, const float2* Wt, const float2 (&ph)[4],
+                                             const float2 (&da)[4], double2 beta, uint32_t* trow,
+                                             DrawBatch& batch) {
+    const int N = A.N, M = A.M;
+    Proposal cur = next_proposal(batch, A.seed, (uint32_t)g, 0ull, pos.t, lane, N);
+    const int si = c.sp.get(cur.i), sj = c.sp.get(cur.j);
+    if (!(PAIR && si == sj)) {
+        float2 wi[E], wj[E], tn[E];
+        float Ln[E];
+        fetch_rows<E, PAIR>(A.gs, M, cur, lane, wi, wj);
+        const float dl = proposal_dlog<E, PAIR>(cur, si, wi, wj, c.thg, c.Lg, tn, Ln, lane, M);
+        if (cur.u < __expf(2.f * dl)) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) { c.thg[e] = tn[e]; c.Lg[e] = Ln[e]; }
+            apply_pending(c, lane, M);
+            fetch_w<E, PAIR>(Wt, M, cur.i, cur.j, lane, c.pti, c.ptj);
+            c.pm = -2.f * (float)si;
+            c.sp.set(cur.i, -si, lane);
+            if (PAIR) c.sp.set(cur.j, -sj, lane);
+            c.tw |= 1u << (pos.t & 31);
+        }
+    }
+    if (trow && ((pos.t & 31) == 31)) {
+        if (lane == 0) trow[pos.t >> 5] = c.tw;
+        c.tw = 0;
+    }
+    ++pos.t;
+    if (++pos.p == N) {
+        if (pos.sw >= A.n_burn) measure(A, c, ph, da, beta, lane);
+        pos.p = 0;
+        ++pos.sw;
+    }
+}
+
+template <int E, bool PAIR>
 __global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
     extern __shared__ int8_t s_spins[];           // one 256-byte row per wave
     const int lane = threadIdx.x & 63;
@@ -64,135 +164,66 @@ __global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        WaveSpins sp;
-        sp.load(row, N, lane);
+        BatchedChain<E, PAIR> c;
+        c.sp.load(row, N, lane);
 
-        // theta of psi_gs and of t~_inst from the spins; the phases of this lane's sites
-        float2 thg[E], tht[E];
-        float Lg[E];
+        // theta of psi_gs and of t~_inst from the spins (lanes past M: theta = 0, see proposal_dlog)
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = e * kWave + lane;
-            thg[e] = (k < M) ? A.gs.b[k] : make_float2(0.f, 0.f);
-            tht[e] = (k < M) ? bt[k] : make_float2(0.f, 0.f);
+            c.thg[e] = (k < M) ? A.gs.b[k] : make_float2(0.f, 0.f);
+            c.tht[e] = (k < M) ? bt[k] : make_float2(0.f, 0.f);
         }
+#pragma unroll 2
         for (int i = 0; i < N; ++i) {
-            const float si = (float)sp.get(i);
+            const float si = (float)c.sp.get(i);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const int k = e * kWave + lane;
-                if (k < M) {
-                    const float2 wg = A.gs.W[(long)i * M + k], wt = Wt[(long)i * M + k];
-                    thg[e].x = fmaf(si, wg.x, thg[e].x);
-                    thg[e].y = fmaf(si, wg.y, thg[e].y);
-                    tht[e].x = fmaf(si, wt.x, tht[e].x);
-                    tht[e].y = fmaf(si, wt.y, tht[e].y);
-                }
+                const long at_ik = (long)i * M + min(k, M - 1);
+                const float2 wg = A.gs.W[at_ik], wt = Wt[at_ik];
+                const float s = (k < M) ? si : 0.f;
+                c.thg[e].x = fmaf(s, wg.x, c.thg[e].x);
+                c.thg[e].y = fmaf(s, wg.y, c.thg[e].y);
+                c.tht[e].x = fmaf(s, wt.x, c.tht[e].x);
+                c.tht[e].y = fmaf(s, wt.y, c.tht[e].y);
             }
         }
 #pragma unroll
-        for (int e = 0; e < E; ++e) Lg[e] = (e * kWave + lane < M) ? re_log2cosh_fast(thg[e]) : 0.f;
-        float2 ph[4];
+        for (int e = 0; e < E; ++e) c.Lg[e] = re_log2cosh_fast(c.thg[e]);
+        // phases e^{-i q.r} of this lane's sites (q.r reduced to [-pi, pi] in double, then a float
+        // sincos) and a_t - a_gs there
+        float2 ph[4], da[4];
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
             const int site = qq * kWave + lane;
             ph[qq] = make_float2(0.f, 0.f);
+            da[qq] = make_float2(0.f, 0.f);
             if (site < N) {
+                da[qq] = csub(at[site], A.gs.a[site]);
                 const int x = A.kind == 0 ? site : site % A.Lx;
                 const int y = A.kind == 0 ? 0 : site / A.Lx;
-                double sn, cs;
-                sincos(q0 * x + q1 * y, &sn, &cs);
-                ph[qq] = make_float2((float)cs, (float)-sn);
+                const double arg = q0 * x + q1 * y;
+                const double two_pi = 6.283185307179586476925286766559;
+                const float red = (float)(arg - two_pi * rint(arg / two_pi));
+                float sn, cs;
+                sincosf(red, &sn, &cs);
+                ph[qq] = make_float2(cs, -sn);
             }
         }
         const double2 beta = A.betas[inst];
-        double m0 = 0.0, mr = 0.0, mi = 0.0;
-        const int total_sweeps = A.n_burn + A.n_sweeps;
-        uint32_t tw = 0;                          // accept bits of the current trace word
+        c.pm = 0.f;
+        c.tw = 0;
+        c.m0 = c.mr = c.mi = 0.0;
         uint32_t* trow = A.trace ? A.trace + (long)g * A.trace_words : nullptr;
-        for (int sw = 0; sw < total_sweeps; ++sw) {
-            for (int p = 0; p < N; ++p) {
-                const uint64_t t = (uint64_t)sw * N + p;
-                if (trow && t > 0 && (t & 31) == 0) {
-                    if (lane == 0) trow[(t - 1) >> 5] = tw;
-                    tw = 0;
-                }
-                const u32x4 x = draw(A.seed, (uint32_t)g, t, 0u);
-                const int i = uniform(draw_index(x.x, N));
-                const int j = uniform(draw_index(x.y, N));
-                const float u = draw_unit(x.z);
-                const int si = sp.get(i), sj = sp.get(j);
-                const bool pair = A.proposal == 1;
-                if (pair && si == sj) continue;
-                const float m2si = -2.f * (float)si;
-                float2 tn[E];
-                float Ln[E];
-                float dsum = 0.f;
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const int k = e * kWave + lane;
-                    if (k < M) {
-                        float2 d = A.gs.W[(long)i * M + k];
-                        if (pair) d = csub(d, A.gs.W[(long)j * M + k]);
-                        tn[e].x = fmaf(m2si, d.x, thg[e].x);
-                        tn[e].y = fmaf(m2si, d.y, thg[e].y);
-                        Ln[e] = re_log2cosh_fast(tn[e]);
-                        dsum += Ln[e] - Lg[e];
-                    } else {
-                        tn[e] = thg[e];
-                        Ln[e] = Lg[e];
-                    }
-                }
-                float dl = uniform(wave_sum(dsum));
-                float da = m2si * A.gs.a[i].x;
-                if (pair) da -= m2si * A.gs.a[j].x;
-                dl += da;
-                if (u < __expf(2.f * dl)) {
-                    tw |= 1u << (t & 31);
-#pragma unroll
-                    for (int e = 0; e < E; ++e) {
-                        const int k = e * kWave + lane;
-                        thg[e] = tn[e];
-                        Lg[e] = Ln[e];
-                        if (k < M) {
-                            float2 d = Wt[(long)i * M + k];
-                            if (pair) d = csub(d, Wt[(long)j * M + k]);
-                            tht[e].x = fmaf(m2si, d.x, tht[e].x);
-                            tht[e].y = fmaf(m2si, d.y, tht[e].y);
-                        }
-                    }
-                    sp.set(i, -si, lane);
-                    if (pair) sp.set(j, -sj, lane);
-                }
-            }
-            if (sw < A.n_burn) continue;
-            // f_q(s), and the ratio t~(s)/psi_gs(s) summed element by element
-            float2 f = make_float2(0.f, 0.f), dlog = make_float2(0.f, 0.f);
-#pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {
-                const int site = qq * kWave + lane;
-                if (site < N) {
-                    const float s = (float)sp.s[qq];
-                    f = cadd(f, cscale(ph[qq], 0.5f * s));
-                    dlog = cadd(dlog, cscale(csub(at[site], A.gs.a[site]), s));
-                }
-            }
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-                if (e * kWave + lane < M) dlog = cadd(dlog, csub(log2cosh(tht[e]), log2cosh(thg[e])));
-            f = wave_sum(f);
-            dlog = wave_sum(dlog);
-            const float2 r = cexpf(dlog);
-            const double fx = (double)f.x * (1.0 / sqrt((double)N)), fy = (double)f.y * (1.0 / sqrt((double)N));
-            const double2 br = zmul(beta, make_double2((double)r.x, (double)r.y));
-            m0 += fx * fx + fy * fy;
-            mr += fx * br.x + fy * br.y;          // conj(f) * (beta r)
-            mi += fx * br.y - fy * br.x;
-        }
+        const long total = (long)(A.n_burn + A.n_sweeps) * N;
+        BatchedPos pos{0, 0, 0};
+        DrawBatch batch;
+        while (pos.t < total) batched_step<E, PAIR>(A, g, lane, pos, c, Wt, ph, da, beta, trow, batch);
         if (lane == 0) {
-            A.partial[2 * g] = make_double2(m0, 0.0);
-            A.partial[2 * g + 1] = make_double2(mr, mi);
-            if (trow) trow[((uint64_t)total_sweeps * N - 1) >> 5] = tw;
+            A.partial[2 * g] = make_double2(c.m0, 0.0);
+            A.partial[2 * g + 1] = make_double2(c.mr, c.mi);
+            if (trow && (total & 31) != 0) trow[total >> 5] = c.tw;
         }
     }
 }
@@ -227,8 +258,13 @@ hipError_t launch_batched(const BatchedArgs& A, int blocks, int waves_per_block,
     const int E = (A.M + kWave - 1) / kWave;
     const dim3 grid(blocks), block(64 * waves_per_block);
     const size_t lds = 256 * (size_t)waves_per_block;
+    const bool pair = A.proposal == 1;
     switch (E) {
-#define CRBM_CASE(e) case e: hipLaunchKernelGGL(k_batched<e>, grid, block, lds, stream, A); break;
+#define CRBM_CASE(e)                                                                                   \
+    case e:                                                                                            \
+        if (pair) hipLaunchKernelGGL((k_batched<e, true>), grid, block, lds, stream, A);               \
+        else hipLaunchKernelGGL((k_batched<e, false>), grid, block, lds, stream, A);                   \
+        break;
         CRBM_CASE(1) CRBM_CASE(2) CRBM_CASE(3) CRBM_CASE(4) CRBM_CASE(5) CRBM_CASE(6) CRBM_CASE(7) CRBM_CASE(8)
 #undef CRBM_CASE
         default: return hipErrorInvalidValue;

@@ -11,6 +11,7 @@
 // rebuilt from the spins at the start of every call.
 #include "device.hpp"
 #include "internal.hpp"
+#include "sweep.hpp"
 
 namespace crbm {
 
@@ -70,7 +71,49 @@ hipError_t launch_init_chains(int8_t* spins, int N, int n_chains, uint64_t seed,
 }
 
 // ------------------------------------------------------------------ Metropolis sweep
-template <int E>
+// Rows are read only for live moves (an exchange of equal spins changes nothing), and all loads of a
+// move are issued together before the first use.
+struct SweepPos {
+    long tloc;   // proposal index within this call
+    int p, sw;   // position within the sweep, sweep index
+};
+
+// One proposal: a single flip, or with PAIR an exchange of sites i and j.
+template <int E, bool PAIR>
+__device__ __forceinline__ void sweep_step(const SampleArgs& A, int chain, int lane, SweepPos& pos,
+                                           WaveSpins& sp, float2 (&th)[E], float (&L)[E], uint32_t& accepted,
+                                           uint32_t& bits, DrawBatch& batch) {
+    const int M = A.M;
+    Proposal cur = next_proposal(batch, A.seed, (uint32_t)chain, A.step_offset, pos.tloc, lane, A.N);
+    const int si = sp.get(cur.i);
+    const int sj = sp.get(cur.j);
+    if (!(PAIR && si == sj)) {
+        float2 wi[E], wj[E], tn[E];
+        float Ln[E];
+        fetch_rows<E, PAIR>(A.psi, M, cur, lane, wi, wj);
+        const float dl = proposal_dlog<E, PAIR>(cur, si, wi, wj, th, L, tn, Ln, lane, M);
+        if (cur.u < __expf(2.f * dl)) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) { th[e] = tn[e]; L[e] = Ln[e]; }
+            sp.set(cur.i, -si, lane);
+            if (PAIR) sp.set(cur.j, -sj, lane);
+            ++accepted;
+            bits |= 1u << (pos.tloc & 31);
+        }
+    }
+    if (A.trace && ((pos.tloc & 31) == 31)) {
+        if (lane == 0) A.trace[(long)chain * A.trace_words + (pos.tloc >> 5)] = bits;
+        bits = 0;
+    }
+    ++pos.tloc;
+    if (++pos.p == A.N) {
+        if (A.samples_out) sp.store(A.samples_out + ((long)pos.sw * A.n_chains + chain) * A.N, A.N, lane);
+        pos.p = 0;
+        ++pos.sw;
+    }
+}
+
+template <int E, bool PAIR>
 __global__ __launch_bounds__(256) void k_sample(SampleArgs A) {
     const int lane = threadIdx.x & 63;
     const int chain = uniform((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
@@ -82,6 +125,8 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs A) {
     WaveSpins sp;
     sp.load(A.spins + (long)chain * N, N, lane);
 
+    // theta = b + sigma W; lanes past M keep theta = 0, and their cached L is
+    // the same function of the same value, so they add exactly zero below
     float2 th[E];
     float L[E];
 #pragma unroll
@@ -89,82 +134,28 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs A) {
         const int k = e * kWave + lane;
         th[e] = (k < M) ? A.psi.b[k] : make_float2(0.f, 0.f);
     }
+#pragma unroll 4
     for (int i = 0; i < N; ++i) {
         const float si = (float)sp.get(i);
         const float2* Wi = W + (long)i * M;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = e * kWave + lane;
-            if (k < M) {
-                const float2 w = Wi[k];
-                th[e].x = fmaf(si, w.x, th[e].x);
-                th[e].y = fmaf(si, w.y, th[e].y);
-            }
+            const float2 w = Wi[min(k, M - 1)];
+            const float s = (k < M) ? si : 0.f;
+            th[e].x = fmaf(s, w.x, th[e].x);
+            th[e].y = fmaf(s, w.y, th[e].y);
         }
     }
 #pragma unroll
-    for (int e = 0; e < E; ++e) L[e] = (e * kWave + lane < M) ? re_log2cosh_fast(th[e]) : 0.f;
+    for (int e = 0; e < E; ++e) L[e] = re_log2cosh_fast(th[e]);
 
     uint32_t accepted = 0, bits = 0;
-    const long trace_row = (long)chain * A.trace_words;
-    for (int sw = 0; sw < A.n_sweeps; ++sw) {
-        for (int p = 0; p < N; ++p) {
-            const long tloc = (long)sw * N + p;
-            const uint64_t t = A.step_offset + (uint64_t)tloc;
-            const u32x4 x = draw(A.seed, (uint32_t)chain, t, 0u);
-            const int i = uniform(draw_index(x.x, N));
-            const int j = uniform(draw_index(x.y, N));
-            const float u = draw_unit(x.z);
-            const int si = sp.get(i);
-            const int sj = sp.get(j);
-            bool move = true;
-            if (A.proposal == 1 && si == sj) move = false;
-            if (move) {
-                const bool pair = (A.proposal == 1);
-                const float2* Wi = W + (long)i * M;
-                const float2* Wj = W + (long)j * M;
-                const float m2si = -2.f * (float)si;
-                float2 tn[E];
-                float Ln[E];
-                float dsum = 0.f;
-#pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const int k = e * kWave + lane;
-                    if (k < M) {
-                        float2 d = Wi[k];
-                        if (pair) d = csub(d, Wj[k]);     // sigma_j = -sigma_i
-                        tn[e].x = fmaf(m2si, d.x, th[e].x);
-                        tn[e].y = fmaf(m2si, d.y, th[e].y);
-                        Ln[e] = re_log2cosh_fast(tn[e]);
-                        dsum += Ln[e] - L[e];
-                    } else {
-                        tn[e] = th[e];
-                        Ln[e] = L[e];
-                    }
-                }
-                float dl = uniform(wave_sum(dsum));
-                float da = m2si * av[i].x;
-                if (pair) da -= m2si * av[j].x;
-                dl += da;
-                const float ratio = __expf(2.f * dl);
-                if (u < ratio) {
-#pragma unroll
-                    for (int e = 0; e < E; ++e) { th[e] = tn[e]; L[e] = Ln[e]; }
-                    sp.set(i, -si, lane);
-                    if (pair) sp.set(j, -sj, lane);
-                    ++accepted;
-                    bits |= 1u << (tloc & 31);
-                }
-            }
-            if (A.trace && ((tloc & 31) == 31)) {
-                if (lane == 0) A.trace[trace_row + (tloc >> 5)] = bits;
-                bits = 0;
-            }
-        }
-        if (A.samples_out) sp.store(A.samples_out + ((long)sw * A.n_chains + chain) * N, N, lane);
-    }
     const long total = (long)A.n_sweeps * N;
-    if (A.trace && (total & 31) != 0 && lane == 0) A.trace[trace_row + (total >> 5)] = bits;
+    SweepPos pos{0, 0, 0};
+    DrawBatch batch;
+    while (pos.tloc < total) sweep_step<E, PAIR>(A, chain, lane, pos, sp, th, L, accepted, bits, batch);
+    if (A.trace && (total & 31) != 0 && lane == 0) A.trace[(long)chain * A.trace_words + (total >> 5)] = bits;
 
     sp.store(A.spins + (long)chain * N, N, lane);
     if (A.n_accept && lane == 0) A.n_accept[chain] = accepted;
@@ -194,15 +185,15 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs A) {
 hipError_t launch_sample(const SampleArgs& args, hipStream_t stream) {
     const int E = (args.M + kWave - 1) / kWave;
     const dim3 grid((args.n_chains + 3) / 4), block(256);
+    const bool pair = args.proposal == 1;
     switch (E) {
-        case 1: hipLaunchKernelGGL(k_sample<1>, grid, block, 0, stream, args); break;
-        case 2: hipLaunchKernelGGL(k_sample<2>, grid, block, 0, stream, args); break;
-        case 3: hipLaunchKernelGGL(k_sample<3>, grid, block, 0, stream, args); break;
-        case 4: hipLaunchKernelGGL(k_sample<4>, grid, block, 0, stream, args); break;
-        case 5: hipLaunchKernelGGL(k_sample<5>, grid, block, 0, stream, args); break;
-        case 6: hipLaunchKernelGGL(k_sample<6>, grid, block, 0, stream, args); break;
-        case 7: hipLaunchKernelGGL(k_sample<7>, grid, block, 0, stream, args); break;
-        case 8: hipLaunchKernelGGL(k_sample<8>, grid, block, 0, stream, args); break;
+#define CRBM_CASE(e)                                                                                   \
+    case e:                                                                                            \
+        if (pair) hipLaunchKernelGGL((k_sample<e, true>), grid, block, 0, stream, args);               \
+        else hipLaunchKernelGGL((k_sample<e, false>), grid, block, 0, stream, args);                   \
+        break;
+        CRBM_CASE(1) CRBM_CASE(2) CRBM_CASE(3) CRBM_CASE(4) CRBM_CASE(5) CRBM_CASE(6) CRBM_CASE(7) CRBM_CASE(8)
+#undef CRBM_CASE
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
