@@ -53,29 +53,76 @@ __device__ __forceinline__ void apply_pending(BatchedChain<E, PAIR>& c, int lane
     }
 }
 
-// f_q(s) and the ratio t~(s)/psi_gs(s) summed element by element, added to the chain's sums
+// (cos x, sin x) of a float: x = k pi/2 + r by the Cody-Waite reduction (pi/2 = P1 + P2 + P3, each
+// k Pi removed by one fused multiply-add), r in [-pi/4, pi/4], then the Taylor series of sin r to r^9
+// and of cos r to r^10 (truncation below 2e-9) and the quadrant k mod 4.  About one ulp for
+// |x| < 3000.  The library sincos carries a large-argument reduction whose registers the whole
+// persistent kernel would pay for.
+__device__ __forceinline__ float2 cos_sin(float x) {
+    const float k = rintf(x * 0.63661977f);
+    float r = fmaf(-k, 1.5703125f, x);
+    r = fmaf(-k, 4.837512969970703e-4f, r);
+    r = fmaf(-k, 7.549790126404332e-8f, r);
+    const float r2 = r * r;
+    float ps = fmaf(r2, 2.7557319e-6f, -1.9841270e-4f);
+    ps = fmaf(r2, ps, 8.3333338e-3f);
+    ps = fmaf(r2, ps, -0.16666667f);
+    ps = fmaf(r2, ps, 1.f);
+    const float sr = r * ps;
+    float pc = fmaf(r2, -2.7557320e-7f, 2.4801588e-5f);
+    pc = fmaf(r2, pc, -1.3888889e-3f);
+    pc = fmaf(r2, pc, 4.1666668e-2f);
+    pc = fmaf(r2, pc, -0.5f);
+    const float cr = fmaf(r2, pc, 1.f);
+    const int q = (int)k & 3;
+    const float c = (q == 0) ? cr : (q == 1) ? -sr : (q == 2) ? -cr : sr;
+    const float sn = (q == 0) ? sr : (q == 1) ? cr : (q == 2) ? -sr : -cr;
+    return make_float2(c, sn);
+}
+
+// log 2cosh z = s z + log 2 + log f, f = (1 + e^{-2 s z}) / 2, s = sign Re z, |f| <= 1: adds s z to lin
+// and multiplies f into p
+__device__ __forceinline__ void cosh_factor(float2 z, float sign, float2& lin, float2& p) {
+    const float sg = z.x >= 0.f ? 1.f : -1.f;
+    const float ex = expf(-2.f * fabsf(z.x));
+    const float2 cs = cos_sin(2.f * sg * z.y);
+    lin.x += sign * fabsf(z.x);
+    lin.y += sign * sg * z.y;
+    p = cmul(p, make_float2(0.5f * (1.f + ex * cs.x), -0.5f * ex * cs.y));
+}
+
+// f_q(s) and the ratio t~(s)/psi_gs(s), added to the chain's sums.  Per lane the log cosh terms of
+// both RBMs are kept as a linear part and a product of factors of modulus <= 1 each, so that one
+// log and one atan2 per lane take the difference (the log 2 terms cancel).
 // ph: e^{-i q.r} and da: a_t - a_gs at this lane's sites
 template <int E, bool PAIR>
 __device__ __forceinline__ void measure(const BatchedArgs& A, BatchedChain<E, PAIR>& c, const float2 (&ph)[4],
                                         const float2 (&da)[4], double2 beta, int lane) {
     const int N = A.N, M = A.M;
     apply_pending(c, lane, M);
-    float2 f = make_float2(0.f, 0.f), dlog = make_float2(0.f, 0.f);
+    float2 f = make_float2(0.f, 0.f), lin = make_float2(0.f, 0.f);
+    float2 pt = make_float2(1.f, 0.f), pg = make_float2(1.f, 0.f);
 #pragma unroll
     for (int qq = 0; qq < 4; ++qq) {
         const int site = qq * kWave + lane;
         if (site < N) {
             const float s = (float)c.sp.s[qq];
             f = cadd(f, cscale(ph[qq], 0.5f * s));
-            dlog = cadd(dlog, cscale(da[qq], s));
+            lin = cadd(lin, cscale(da[qq], s));
         }
     }
 #pragma unroll
     for (int e = 0; e < E; ++e)
-        if (e * kWave + lane < M) dlog = cadd(dlog, csub(log2cosh(c.tht[e]), log2cosh(c.thg[e])));
+        if (e < E - 1 || e * kWave + lane < M) {
+            cosh_factor(c.tht[e], 1.f, lin, pt);
+            cosh_factor(c.thg[e], -1.f, lin, pg);
+        }
+    const float2 q = make_float2(pt.x * pg.x + pt.y * pg.y, pt.y * pg.x - pt.x * pg.y);  // pt conj(pg)
+    const float nt = pt.x * pt.x + pt.y * pt.y, ng = pg.x * pg.x + pg.y * pg.y;
+    const float2 dl = make_float2(lin.x + 0.5f * (logf(nt) - logf(ng)), lin.y + atan2f(q.y, q.x));
     f = make_float2(wave_total(f.x), wave_total(f.y));
-    dlog = make_float2(wave_total(dlog.x), wave_total(dlog.y));
-    const float2 r = cexpf(dlog);
+    const float2 dlog = make_float2(wave_total(dl.x), wave_total(dl.y));
+    const float2 r = cscale(cos_sin(dlog.y), expf(dlog.x));
     const double fx = (double)f.x * (1.0 / sqrt((double)N)), fy = (double)f.y * (1.0 / sqrt((double)N));
     const double2 br = zmul(beta, make_double2((double)r.x, (double)r.y));
     c.m0 += fx * fx + fy * fy;
@@ -83,20 +130,13 @@ __device__ __forceinline__ void measure(const BatchedArgs& A, BatchedChain<E, PA
     c.mi += fx * br.y - fy * br.x;
 }
 
-struct BatchedPos {
-    long t;      // proposal index of the chain
-    int p, sw;   // position within the sweep, sweep index
-};
-
-// One proposal, with the measurement at the end of every recorded sweep.  Rows of psi_gs are read only
-// for live moves.
+// Proposal t of chain g.  Rows of psi_gs are read only for live moves.
 template <int E, bool PAIR>
-__device__ __forceinline__ void batched_step(const BatchedArgs& A, uint64_t g, int lane, BatchedPos& pos,
-                                             BatchedChain<E, PAIR>& c, const float2* Wt, const float2 (&ph)[4],
-                                             const float2 (&da)[4], double2 beta, uint32_t* trow,
+__device__ __forceinline__ void batched_step(const BatchedArgs& A, uint64_t g, int lane, long t,
+                                             BatchedChain<E, PAIR>& c, const float2* Wt, uint32_t* trow,
                                              DrawBatch& batch) {
     const int N = A.N, M = A.M;
-    Proposal cur = next_proposal(batch, A.seed, (uint32_t)g, 0ull, pos.t, lane, N);
+    Proposal cur = next_proposal(batch, A.seed, (uint32_t)g, 0ull, t, lane, N);
     const int si = c.sp.get(cur.i), sj = c.sp.get(cur.j);
     if (!(PAIR && si == sj)) {
         float2 wi[E], wj[E], tn[E];
@@ -111,18 +151,12 @@ __device__ __forceinline__ void batched_step(const BatchedArgs& A, uint64_t g, i
             c.pm = -2.f * (float)si;
             c.sp.set(cur.i, -si, lane);
             if (PAIR) c.sp.set(cur.j, -sj, lane);
-            c.tw |= 1u << (pos.t & 31);
+            c.tw |= 1u << (t & 31);
         }
     }
-    if (trow && ((pos.t & 31) == 31)) {
-        if (lane == 0) trow[pos.t >> 5] = c.tw;
+    if (trow && ((t & 31) == 31)) {
+        if (lane == 0) trow[t >> 5] = c.tw;
         c.tw = 0;
-    }
-    ++pos.t;
-    if (++pos.p == N) {
-        if (pos.sw >= A.n_burn) measure(A, c, ph, da, beta, lane);
-        pos.p = 0;
-        ++pos.sw;
     }
 }
 
@@ -217,9 +251,12 @@ __global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
         c.m0 = c.mr = c.mi = 0.0;
         uint32_t* trow = A.trace ? A.trace + (long)g * A.trace_words : nullptr;
         const long total = (long)(A.n_burn + A.n_sweeps) * N;
-        BatchedPos pos{0, 0, 0};
         DrawBatch batch;
-        while (pos.t < total) batched_step<E, PAIR>(A, g, lane, pos, c, Wt, ph, da, beta, trow, batch);
+        long t = 0;
+        for (int sw = 0; sw < A.n_burn + A.n_sweeps; ++sw) {
+            for (int p = 0; p < N; ++p, ++t) batched_step<E, PAIR>(A, g, lane, t, c, Wt, trow, batch);
+            if (sw >= A.n_burn) measure(A, c, ph, da, beta, lane);
+        }
         if (lane == 0) {
             A.partial[2 * g] = make_double2(c.m0, 0.0);
             A.partial[2 * g + 1] = make_double2(c.mr, c.mi);

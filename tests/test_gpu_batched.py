@@ -37,6 +37,7 @@ def _instances(orc, kind, Lx, Ly, M, counts, seed=5):
 @pytest.mark.parametrize("kind,Lx,Ly,M,counts,proposal", [
     (1, 4, 4, 16, [3, 0, 5, 1, 7, 2], 1),
     (0, 12, 1, 24, [2, 4, 1], 0),
+    (1, 4, 4, 64, [4, 1, 2], 1),       # M fills one 64-lane group exactly
 ])
 def test_batched_vs_oracle(orc, kind, Lx, Ly, M, counts, proposal):
     N = Lx * Ly

@@ -158,6 +158,8 @@ def test_target_ratio(orc, order, kind, Lx, Ly, M, n, std, sim):
     (1, 10, 10, 400, 8, 3, 1, 0.02),
     (1, 16, 16, 512, 3, 1, 1, 0.02),
     (1, 4, 4, 24, 129, 10, 0, 0.4),
+    (1, 8, 8, 128, 16, 4, 1, 0.05),    # M fills its 64-lane groups exactly
+    (0, 6, 1, 1, 70, 30, 1, 0.5),      # one hidden unit: 63 padded lanes
 ])
 def test_sample_replay(orc, kind, Lx, Ly, M, C, sweeps, proposal, std):
     N = Lx * Ly
