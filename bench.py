@@ -38,18 +38,32 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sbuild_mfma_bf16_square10x10_alpha4_traffic.json")
 
 
+# the S contraction's source and every header it includes, in this order
+TRAFFIC_SOURCES = ("paper_2103_08804_amd/csrc/kernels_mfma.hip", "paper_2103_08804_amd/csrc/device.hpp",
+                   "paper_2103_08804_amd/csrc/internal.hpp", "include/chebrbm.h")
+
+
+def traffic_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic():
     """HBM bytes per launch of the S contraction from the committed counter runs, or None when the
-    kernel source has changed since the counters were taken."""
-    import hashlib
+    kernel or a header it includes has changed since the counters were taken."""
     try:
         d = json.load(open(TRAFFIC_FILE))
-        src = open(os.path.join(ROOT, "paper_2103_08804_amd", "csrc", "kernels_mfma.hip"), "rb").read()
+        now = traffic_source_hash()
     except OSError:
         return None
-    if hashlib.sha256(src).hexdigest() != d["kernels_mfma_hip_sha256"]:
+    if now != d.get("sources_sha256"):
         return None
     return d["traffic_bytes_per_launch"]
+
+
 BF16_PEAK_TFLOPS = 2500.0
 FP32_MATRIX_PEAK_TFLOPS = 157.3
 
