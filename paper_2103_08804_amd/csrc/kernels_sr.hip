@@ -86,10 +86,21 @@ __global__ void k_r_final(const double2* __restrict__ red, int n_blocks, double 
 }
 
 // ------------------------------------------------------------------ O^H c contraction
-// Tile: 32 extended sites x 64 extended hidden units per block; blockIdx.z = sample chunk.
+// out_c[i][j] = sum_s sigma~_i(s) y_c(s, j) with y_c(s, j) = c_c(s) conj(t~_j(s)), sigma~_N = 1 and
+// t~_M = 1: per coefficient a real (N+1) x n by n x (M+1) complex product (rows i < N are the a
+// parameters' O, row N the b parameters', the rest W's, up to conjugation and the sample weights).
+// On the matrix cores with v_mfma_f32_32x32x2f32, so products and sums stay FP32 as on the vector
+// units.  A workgroup (4 waves) owns 128 extended sites x 32 extended hidden units and one sample
+// chunk; per 32-sample tile it stages sigma~ as floats [site][sample] and y as [c][Re/Im][sample][unit]
+// in LDS, and wave w accumulates rows 32 w .. 32 w + 31 against the 32 columns for every coefficient
+// and both parts (64 accumulator registers for two coefficients), so that three workgroups share a
+// CU and one's staging overlaps another's products.  The tile after the current one is loaded into
+// registers while the products run.  Chunk sums are written in FP32 and added across chunks in FP64.
 // coef kinds: 0 -> c = w; 1 -> c = w R; 2 -> c = w u (u double2 [n]);
 //             3 -> c = 2 (1 - R) conj(R) / n
-constexpr int OT_I = 32, OT_J = 64, OT_S = 32;
+constexpr int OM_R = 128, OM_C = 32, OM_S = 32;
+
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 // the value a binary32 takes after rounding to bfloat16 (nearest, ties to even)
 __device__ __forceinline__ float round_to_bf16(float x) {
@@ -113,81 +124,126 @@ __device__ __forceinline__ float2 coef_of(int kind, long s, const double* w, dou
     }
 }
 
+// One sample tile's raw operands in registers: the tile after the current one is loaded while the
+// matrix cores work on the current one, so the loads' latency is hidden behind the products.  Thread t
+// holds sample t / 8 of the tile with sites 16 (t % 8) .. + 15 of the block and units 4 (t % 8) .. + 3.
+template <int NK>
+struct OtRaw {
+    float sg[16];   // sigma~
+    float2 t[4];    // conj(t~)
+    float2 cf;      // coefficient of sample t % 32 (t < NK * 32)
+};
+
+template <int NK>
+__device__ __forceinline__ void ot_load(OtRaw<NK>& r, int tid, int N, int M, int i0, int j0, long sb, long s_end,
+                                        const int8_t* __restrict__ sig, const float2* __restrict__ T, int kind0,
+                                        int kind1, const double* __restrict__ w, double wdef,
+                                        const float2* __restrict__ R, const double2* __restrict__ u,
+                                        double two_over_n, int round_bf16) {
+    const long s = sb + (tid >> 3);
+    const int g = tid & 7;
+    const bool in = s < s_end;
+    const int8_t* srow = sig + s * N;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int i = i0 + 16 * g + k;
+        r.sg[k] = (in && i < N) ? (float)srow[i] : ((in && i == N) ? 1.f : 0.f);
+    }
+    const float2* trow = T + s * M;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int j = j0 + 4 * g + k;
+        float2 t = make_float2(0.f, 0.f);
+        if (in && j <= M) t = (j == M) ? make_float2(1.f, 0.f) : trow[j];
+        if (round_bf16) t = make_float2(round_to_bf16(t.x), round_to_bf16(t.y));
+        r.t[k] = cconj(t);
+    }
+    r.cf = make_float2(0.f, 0.f);
+    if (tid < NK * OM_S) {
+        const long sc = sb + tid % OM_S;
+        if (sc < s_end) r.cf = coef_of(tid / OM_S == 0 ? kind0 : kind1, sc, w, wdef, R, u, two_over_n);
+    }
+}
+
+template <int NK>
 __global__ __launch_bounds__(256) void k_ot(int N, int M, const int8_t* __restrict__ sig, const float2* __restrict__ T,
-                                            long n, long chunk, int kind0, int kind1, int nk,
+                                            long n, long chunk, int kind0, int kind1,
                                             const double* __restrict__ w, const float2* __restrict__ R,
                                             const double2* __restrict__ u, double2* __restrict__ partial,
                                             const double* __restrict__ skip, int round_bf16) {
     if (skip && *skip != 0.0) return;
-    __shared__ float s_sig[OT_S][OT_I + 1];
-    __shared__ float2 s_t[OT_S][OT_J];
-    __shared__ float2 s_c[2][OT_S];
-    const int tid = threadIdx.x;
-    const int i0 = blockIdx.x * OT_I, j0 = blockIdx.y * OT_J;
+    __shared__ __align__(16) float sA[OM_S][OM_R + 4];      // sigma~ [sample][site]
+    __shared__ __align__(16) float sY[NK][2][OM_S][OM_C];   // y [c][Re/Im][sample][unit]
+    __shared__ float2 sC[NK][OM_S];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int i0 = blockIdx.x * OM_R, j0 = blockIdx.y * OM_C;
     const long s_begin = (long)blockIdx.z * chunk;
     const long s_end = min(n, s_begin + chunk);
-    const int jl = tid & 63, ib = (tid >> 6) * 8;
     const double wdef = 1.0 / (double)n;
     const double two_over_n = 2.0 / (double)n;
-    float2 acc[2][8];
+    // whether this wave's rows hold any extended site (wave-uniform); rows past N are staged as zeros
+    const bool live = i0 + 32 * wv <= N;
+    f32x16 acc[NK][2];
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
+    for (int c = 0; c < NK; ++c)
 #pragma unroll
-        for (int r = 0; r < 8; ++r) acc[c][r] = make_float2(0.f, 0.f);
+        for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[c][ri][v] = 0.f;
 
-    for (long sb = s_begin; sb < s_end; sb += OT_S) {
-        for (int e = tid; e < OT_S * OT_I; e += 256) {
-            const int ss = e / OT_I, ii = e % OT_I;
-            const long s = sb + ss;
-            const int i = i0 + ii;
-            float v = 0.f;
-            if (s < s_end && i <= N) v = (i == N) ? 1.f : (float)sig[s * N + i];
-            s_sig[ss][ii] = v;
-        }
-        for (int e = tid; e < OT_S * OT_J; e += 256) {
-            const int ss = e / OT_J, jj = e % OT_J;
-            const long s = sb + ss;
-            const int j = j0 + jj;
-            float2 v = make_float2(0.f, 0.f);
-            if (s < s_end && j <= M) v = (j == M) ? make_float2(1.f, 0.f) : cconj(T[s * M + j]);
-            if (round_bf16) v = make_float2(round_to_bf16(v.x), round_to_bf16(v.y));
-            s_t[ss][jj] = v;
-        }
-        if (tid < OT_S * 2) {
-            const int c = tid / OT_S, ss = tid % OT_S;
-            const long s = sb + ss;
-            float2 v = make_float2(0.f, 0.f);
-            if (s < s_end && c < nk) v = coef_of(c == 0 ? kind0 : kind1, s, w, wdef, R, u, two_over_n);
-            s_c[c][ss] = v;
+    OtRaw<NK> raw;
+    ot_load<NK>(raw, tid, N, M, i0, j0, s_begin, s_end, sig, T, kind0, kind1, w, wdef, R, u, two_over_n, round_bf16);
+    for (long sb = s_begin; sb < s_end; sb += OM_S) {
+        // stage this tile from registers
+        const int ss = tid >> 3, g = tid & 7;
+        if (tid < NK * OM_S) sC[tid / OM_S][tid % OM_S] = raw.cf;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) sA[ss][16 * g + k] = raw.sg[k];
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            const float2 cf = sC[c][ss];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float2 y = cmul(raw.t[k], cf);
+                sY[c][0][ss][4 * g + k] = y.x;
+                sY[c][1][ss][4 * g + k] = y.y;
+            }
         }
         __syncthreads();
-        for (int ss = 0; ss < OT_S; ++ss) {
-            const float2 t = s_t[ss][jl];
-            const float2 y0 = cmul(t, s_c[0][ss]);
-            const float2 y1 = cmul(t, s_c[1][ss]);
+        // the next tile's loads, in flight during the products
+        if (sb + OM_S < s_end)
+            ot_load<NK>(raw, tid, N, M, i0, j0, sb + OM_S, s_end, sig, T, kind0, kind1, w, wdef, R, u, two_over_n,
+                        round_bf16);
+        // lane l supplies row l % 32 (A) and column l % 32 (B) at sample 2 ks + l / 32
+        if (live) {
+#pragma unroll 4
+            for (int ks = 0; ks < OM_S / 2; ++ks) {
+                const int kk = 2 * ks + (lane >> 5);
+                const float a = sA[kk][32 * wv + (lane & 31)];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const float sv = s_sig[ss][ib + r];
-                acc[0][r].x = fmaf(sv, y0.x, acc[0][r].x);
-                acc[0][r].y = fmaf(sv, y0.y, acc[0][r].y);
-                acc[1][r].x = fmaf(sv, y1.x, acc[1][r].x);
-                acc[1][r].y = fmaf(sv, y1.y, acc[1][r].y);
+                for (int c = 0; c < NK; ++c)
+#pragma unroll
+                    for (int ri = 0; ri < 2; ++ri)
+                        acc[c][ri] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, sY[c][ri][kk][lane & 31], acc[c][ri],
+                                                                           0, 0, 0);
             }
         }
         __syncthreads();
     }
-    const int j = j0 + jl;
-    if (j > M) return;
+    // accumulator element v of lane l: row 8(v/4) + 4(l/32) + v%4 of the fragment, column l % 32
+    const int j = j0 + (lane & 31);
+    if (j > M || !live) return;
     const long plane = (long)(N + 1) * (M + 1);
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int i = i0 + ib + r;
-        if (i > N) continue;
-        const long o = (long)i * (M + 1) + j;
-        for (int c = 0; c < nk; ++c)
-            partial[((long)blockIdx.z * nk + c) * plane + o] =
-                make_double2((double)acc[c][r].x, (double)acc[c][r].y);
-    }
+    for (int c = 0; c < NK; ++c)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int i = i0 + 32 * wv + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            if (i <= N)
+                partial[((long)blockIdx.z * NK + c) * plane + (long)i * (M + 1) + j] =
+                    make_double2((double)acc[c][0][v], (double)acc[c][1][v]);
+        }
 }
 
 // out[c][P-index] = sum over chunks (FP64), with optional conjugation.
@@ -208,10 +264,16 @@ __global__ void k_ot_reduce(int N, int M, const double2* __restrict__ partial, i
     }
 }
 
+// Sample chunks: about three workgroups per CU over the (site, unit) tiles, chunks of at least 256
+// samples (a multiple of the 32-sample tile) and at most 256 of them, which the plan's reduction
+// buffer holds (it has room for min(ceil(n / 256), 257) chunks).
 struct OtPlan { long chunk; int n_chunks; };
-static OtPlan ot_plan(long n) {
-    long chunk = (n + 255) / 256;
-    chunk = ((chunk + OT_S - 1) / OT_S) * OT_S;
+static OtPlan ot_plan(int N, int M, long n) {
+    const long tiles = (long)((N + 1 + OM_R - 1) / OM_R) * ((M + 1 + OM_C - 1) / OM_C);
+    long target = (3L * 256 + tiles - 1) / tiles;
+    if (target > 256) target = 256;
+    long chunk = (n + target - 1) / target;
+    chunk = ((chunk + OM_S - 1) / OM_S) * OM_S;
     if (chunk < 256) chunk = 256;
     return {chunk, (int)((n + chunk - 1) / chunk)};
 }
@@ -220,11 +282,15 @@ static hipError_t run_ot(int N, int M, const int8_t* sig, const float2* T, long 
                          const double* w, const float2* R, const double2* u, double2* partial, int conj0,
                          double2* out0, double2* out1, hipStream_t stream, const double* skip, Profiler* prof,
                          int round_bf16 = 0) {
-    const OtPlan op = ot_plan(n);
-    dim3 grid((N + 1 + OT_I - 1) / OT_I, (M + 1 + OT_J - 1) / OT_J, op.n_chunks);
+    const OtPlan op = ot_plan(N, M, n);
+    dim3 grid((N + 1 + OM_R - 1) / OM_R, (M + 1 + OM_C - 1) / OM_C, op.n_chunks);
     if (prof) prof->begin(PROF_OT, stream);
-    hipLaunchKernelGGL(k_ot, grid, dim3(256), 0, stream, N, M, sig, T, n, op.chunk, kind0, kind1, nk, w, R, u, partial,
-                       skip, round_bf16);
+    if (nk == 2)
+        hipLaunchKernelGGL(k_ot<2>, grid, dim3(256), 0, stream, N, M, sig, T, n, op.chunk, kind0, kind1, w, R, u,
+                           partial, skip, round_bf16);
+    else
+        hipLaunchKernelGGL(k_ot<1>, grid, dim3(256), 0, stream, N, M, sig, T, n, op.chunk, kind0, kind1, w, R, u,
+                           partial, skip, round_bf16);
     if (prof) prof->end(stream);
     const long plane = (long)(N + 1) * (M + 1);
     hipLaunchKernelGGL(k_ot_reduce, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, stream, N, M, partial,
