@@ -254,6 +254,7 @@ def main():
     }
     if not args.no_fp32_compare and solver == crbm.CG_DENSE and prec == crbm.BF16:
         line["fp32_compare"] = fp32_compare(crbm, plan, fit, flat, T, R, wl, args, ms_per_step, prof)
+        line["matfree_compare"] = matfree_compare(crbm, plan, fit, flat, T, R, wl, args, ms_per_step, prof)
     if not args.no_cpu_baseline:
         line["cpu_baseline"], line["mu_error"] = cpu_baseline(args.cpu_budget_s, ns, sweeps, C)
     print(json.dumps(line))
@@ -601,6 +602,36 @@ def fp32_compare(crbm, plan, fit, flat, T, R, wl, args, ms_per_step, prof):
             "fp32_sbuild_tflops": 4.0 * P * (P + 1) * nk / (out["fp32_sbuild_ms_sub"] / 1e3) / 1e12,
             "dalpha_bf16_vs_fp32_rel_diff": rel,
             "mu_n": "identical in both paths (moments do not use S)"}
+
+
+def matfree_compare(crbm, plan, fit, flat, T, R, wl, args, ms_per_step, prof):
+    """The library's matrix-free solver on the same samples: S v = <O^*(O v)> - <O>^*(<O> v) formed from
+    the factored O at every CG iteration (theta product of V, O v, O^H u on the matrix cores) instead of
+    the dense S.  Context only: the configured workload is the dense BF16 S contraction.  Its SR step is
+    timed on the step's full sample set and swapped into the measured step time; dalpha is compared
+    with a dense BF16 solve of the same inputs."""
+    stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+    P = wl.P
+    dal, ms, its = {}, {}, {}
+    for name, sv in (("dense", crbm.CG_DENSE), ("matfree", crbm.CG_MATFREE)):
+        f = crbm.RBM(fit.a.clone(), fit.b.clone(), fit.W.clone())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        crbm.sr_step(plan, f, flat, T, R, 0.1, wl.diag_shift, sv, crbm.BF16, 1e-6, args.cg_maxit, stats)
+        torch.cuda.synchronize()
+        ms[name] = (time.perf_counter() - t0) * 1e3
+        its[name] = float(stats[5].item())
+        dx = torch.zeros(P, dtype=torch.complex128, device="cuda")
+        crbm.copy_plan_buffer(plan, crbm.BUF_DALPHA, dx)
+        torch.cuda.synchronize()
+        dal[name] = dx
+    dense_sr = sum(prof[k][1] / prof[k][0] for k in ("ot", "pack", "sbuild", "sborder", "cg") if k in prof)
+    step = ms_per_step - dense_sr + ms["matfree"]
+    rel = float((dal["matfree"] - dal["dense"]).abs().max() / dal["dense"].abs().max())
+    return {"sr_ms": ms["matfree"], "cg_iterations": its["matfree"], "dense_sr_ms": dense_sr,
+            "ms_per_step": step, "samples_per_s": flat.shape[0] / (step / 1e3),
+            "speedup_vs_dense": ms_per_step / step, "dalpha_vs_dense_bf16_rel_diff": rel,
+            "note": "context only; the configured workload is the dense BF16 S contraction"}
 
 
 def cpu_baseline(budget_s, ns, sweeps, C):
