@@ -27,6 +27,8 @@ inline long lc_plane_elems(long N, long M) { return 3L * ((M + 63) / 64) * 128L 
 // bonds of the largest lattice (square, N <= 256 sites, 2 N bonds); the local-estimator kernel keeps
 // a per-wave list of the anti-aligned ones in LDS
 constexpr int kMaxBonds = 512;
+// row length of the packed sigma~ of the O^H c contraction: sites 0..N-1, then 1 (b), then zeros
+inline int sig16_row(int N) { return ((N + 1 + 15) / 16) * 16; }
 
 struct Geometry {
     int N, M, P;
@@ -113,6 +115,7 @@ struct SrWork {
     float2* S;                // [P][P] dense (may be null)
     double2* S64;             // [P][P] dense double (Cholesky, may be null)
     float2* G;                // [n][M] scratch of the matrix-free product
+    int8_t* sig16;            // [n][sig16_row(N)] sigma~ rows for the O^H c contraction
     float2* vstage;           // [P] float copy of a CG direction
     void* pack;               // packed operand planes of the matrix-core S contraction
     size_t pack_bytes;

@@ -90,8 +90,8 @@ __global__ void k_r_final(const double2* __restrict__ red, int n_blocks, double 
 // t~_M = 1: per coefficient a real (N+1) x n by n x (M+1) complex product (rows i < N are the a
 // parameters' O, row N the b parameters', the rest W's, up to conjugation and the sample weights).
 // On the matrix cores with v_mfma_f32_32x32x2f32, so products and sums stay FP32 as on the vector
-// units.  A workgroup (4 waves) owns 128 extended sites x 32 extended hidden units and one sample
-// chunk; per 32-sample tile it stages sigma~ as floats [site][sample] and y as [c][Re/Im][sample][unit]
+// units.  A workgroup (4 waves) owns 128 extended sites x 32 extended hidden units and a run of
+// sample chunks; per 32-sample tile it stages sigma~ as floats [site][sample] and y as [c][Re/Im][sample][unit]
 // in LDS, and wave w accumulates rows 32 w .. 32 w + 31 against the 32 columns for every coefficient
 // and both parts (64 accumulator registers for two coefficients), so that three workgroups share a
 // CU and one's staging overlaps another's products.  The tile after the current one is loaded into
@@ -124,6 +124,16 @@ __device__ __forceinline__ float2 coef_of(int kind, long s, const double* w, dou
     }
 }
 
+// sigma~ rows of the contraction, packed once per call: sites 0..N-1, then 1 (the b row), then zeros up
+// to a multiple of 16 sites, so that a thread reads its 16 sites with one aligned 16-byte load.
+__global__ void k_pack_sig16(const int8_t* __restrict__ sig, long n, int N, int row, int8_t* __restrict__ out) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * row) return;
+    const long s = e / row;
+    const int i = (int)(e % row);
+    out[e] = i < N ? sig[s * N + i] : (int8_t)(i == N ? 1 : 0);
+}
+
 // One sample tile's raw operands in registers: the tile after the current one is loaded while the
 // matrix cores work on the current one, so the loads' latency is hidden behind the products.  Thread t
 // holds sample t / 8 of the tile with sites 16 (t % 8) .. + 15 of the block and units 4 (t % 8) .. + 3.
@@ -135,20 +145,20 @@ struct OtRaw {
 };
 
 template <int NK>
-__device__ __forceinline__ void ot_load(OtRaw<NK>& r, int tid, int N, int M, int i0, int j0, long sb, long s_end,
-                                        const int8_t* __restrict__ sig, const float2* __restrict__ T, int kind0,
+__device__ __forceinline__ void ot_load(OtRaw<NK>& r, int tid, int row, int M, int i0, int j0, long sb, long s_end,
+                                        const int8_t* __restrict__ sig16, const float2* __restrict__ T, int kind0,
                                         int kind1, const double* __restrict__ w, double wdef,
                                         const float2* __restrict__ R, const double2* __restrict__ u,
                                         double two_over_n, int round_bf16) {
     const long s = sb + (tid >> 3);
     const int g = tid & 7;
     const bool in = s < s_end;
-    const int8_t* srow = sig + s * N;
+    const int base = i0 + 16 * g;   // a multiple of 16, as is the packed row length
+    int4 v = make_int4(0, 0, 0, 0);
+    if (in && base < row) v = *reinterpret_cast<const int4*>(sig16 + s * row + base);
+    const int word[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int i = i0 + 16 * g + k;
-        r.sg[k] = (in && i < N) ? (float)srow[i] : ((in && i == N) ? 1.f : 0.f);
-    }
+    for (int k = 0; k < 16; ++k) r.sg[k] = (float)(int8_t)(word[k >> 2] >> (8 * (k & 3)));
     const float2* trow = T + s * M;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -165,11 +175,42 @@ __device__ __forceinline__ void ot_load(OtRaw<NK>& r, int tid, int N, int M, int
     }
 }
 
+// Stage one tile from registers into LDS (two barriers), then issue the loads of the tile after it.
 template <int NK>
-__global__ __launch_bounds__(256) void k_ot(int N, int M, const int8_t* __restrict__ sig, const float2* __restrict__ T,
-                                            long n, long chunk, int kind0, int kind1,
+__device__ __forceinline__ void ot_stage(OtRaw<NK>& raw, float (&sA)[OM_S][OM_R + 4],
+                                         float (&sY)[NK][2][OM_S][OM_C], float2 (&sC)[NK][OM_S], int tid, int row,
+                                         int M, int i0, int j0, long sb, long s_end, const int8_t* __restrict__ sig16,
+                                         const float2* __restrict__ T, int kind0, int kind1,
+                                         const double* __restrict__ w, double wdef, const float2* __restrict__ R,
+                                         const double2* __restrict__ u, double two_over_n, int round_bf16) {
+    const int ss = tid >> 3, g = tid & 7;
+    if (tid < NK * OM_S) sC[tid / OM_S][tid % OM_S] = raw.cf;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) sA[ss][16 * g + k] = raw.sg[k];
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NK; ++c) {
+        const float2 cf = sC[c][ss];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float2 y = cmul(raw.t[k], cf);
+            sY[c][0][ss][4 * g + k] = y.x;
+            sY[c][1][ss][4 * g + k] = y.y;
+        }
+    }
+    __syncthreads();
+    // the next tile's loads, in flight during the products
+    if (sb + OM_S < s_end)
+        ot_load<NK>(raw, tid, row, M, i0, j0, sb + OM_S, s_end, sig16, T, kind0, kind1, w, wdef, R, u, two_over_n,
+                    round_bf16);
+}
+
+template <int NK>
+__global__ __launch_bounds__(256) void k_ot(int N, int M, int row, const int8_t* __restrict__ sig16,
+                                            const float2* __restrict__ T,
+                                            long n, long chunk, int n_chunks, int kind0, int kind1,
                                             const double* __restrict__ w, const float2* __restrict__ R,
-                                            const double2* __restrict__ u, double2* __restrict__ partial,
+                                            const double2* __restrict__ u, float* __restrict__ partial,
                                             const double* __restrict__ skip, int round_bf16) {
     if (skip && *skip != 0.0) return;
     __shared__ __align__(16) float sA[OM_S][OM_R + 4];      // sigma~ [sample][site]
@@ -177,46 +218,37 @@ __global__ __launch_bounds__(256) void k_ot(int N, int M, const int8_t* __restri
     __shared__ float2 sC[NK][OM_S];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int i0 = blockIdx.x * OM_R, j0 = blockIdx.y * OM_C;
-    const long s_begin = (long)blockIdx.z * chunk;
-    const long s_end = min(n, s_begin + chunk);
     const double wdef = 1.0 / (double)n;
     const double two_over_n = 2.0 / (double)n;
-    // whether this wave's rows hold any extended site (wave-uniform); rows past N are staged as zeros
-    const bool live = i0 + 32 * wv <= N;
-    f32x16 acc[NK][2];
-#pragma unroll
-    for (int c = 0; c < NK; ++c)
-#pragma unroll
-        for (int ri = 0; ri < 2; ++ri)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) acc[c][ri][v] = 0.f;
-
-    OtRaw<NK> raw;
-    ot_load<NK>(raw, tid, N, M, i0, j0, s_begin, s_end, sig, T, kind0, kind1, w, wdef, R, u, two_over_n, round_bf16);
-    for (long sb = s_begin; sb < s_end; sb += OM_S) {
-        // stage this tile from registers
-        const int ss = tid >> 3, g = tid & 7;
-        if (tid < NK * OM_S) sC[tid / OM_S][tid % OM_S] = raw.cf;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) sA[ss][16 * g + k] = raw.sg[k];
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < NK; ++c) {
-            const float2 cf = sC[c][ss];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float2 y = cmul(raw.t[k], cf);
-                sY[c][0][ss][4 * g + k] = y.x;
-                sY[c][1][ss][4 * g + k] = y.y;
+    const int j = j0 + (lane & 31);
+    const long plane = (long)(N + 1) * (M + 1);
+    // chunks ck = blockIdx.z, blockIdx.z + gridDim.z, ...: each summed in FP32 on its own
+    for (int ck = blockIdx.z; ck < n_chunks; ck += gridDim.z) {
+        const long s_begin = (long)ck * chunk;
+        const long s_end = min(n, s_begin + chunk);
+        OtRaw<NK> raw;
+        ot_load<NK>(raw, tid, row, M, i0, j0, s_begin, s_end, sig16, T, kind0, kind1, w, wdef, R, u, two_over_n,
+                    round_bf16);
+        if (i0 + 32 * wv > N) {
+            // no extended site in this wave's rows: it only helps to stage the tiles
+            for (long sb = s_begin; sb < s_end; sb += OM_S) {
+                ot_stage<NK>(raw, sA, sY, sC, tid, row, M, i0, j0, sb, s_end, sig16, T, kind0, kind1, w, wdef, R, u,
+                             two_over_n, round_bf16);
+                __syncthreads();
             }
+            continue;
         }
-        __syncthreads();
-        // the next tile's loads, in flight during the products
-        if (sb + OM_S < s_end)
-            ot_load<NK>(raw, tid, N, M, i0, j0, sb + OM_S, s_end, sig, T, kind0, kind1, w, wdef, R, u, two_over_n,
-                        round_bf16);
-        // lane l supplies row l % 32 (A) and column l % 32 (B) at sample 2 ks + l / 32
-        if (live) {
+        f32x16 acc[NK][2];
+#pragma unroll
+        for (int c = 0; c < NK; ++c)
+#pragma unroll
+            for (int ri = 0; ri < 2; ++ri)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[c][ri][v] = 0.f;
+        for (long sb = s_begin; sb < s_end; sb += OM_S) {
+            ot_stage<NK>(raw, sA, sY, sC, tid, row, M, i0, j0, sb, s_end, sig16, T, kind0, kind1, w, wdef, R, u,
+                         two_over_n, round_bf16);
+            // lane l supplies row l % 32 (A) and column l % 32 (B) at sample 2 ks + l / 32; rows past N are zeros
 #pragma unroll 4
             for (int ks = 0; ks < OM_S / 2; ++ks) {
                 const int kk = 2 * ks + (lane >> 5);
@@ -225,29 +257,31 @@ __global__ __launch_bounds__(256) void k_ot(int N, int M, const int8_t* __restri
                 for (int c = 0; c < NK; ++c)
 #pragma unroll
                     for (int ri = 0; ri < 2; ++ri)
-                        acc[c][ri] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, sY[c][ri][kk][lane & 31], acc[c][ri],
-                                                                           0, 0, 0);
+                        acc[c][ri] =
+                            __builtin_amdgcn_mfma_f32_32x32x2f32(a, sY[c][ri][kk][lane & 31], acc[c][ri], 0, 0, 0);
             }
+            __syncthreads();
         }
-        __syncthreads();
+        // accumulator element v of lane l: row 8(v/4) + 4(l/32) + v%4 of the fragment, column l % 32;
+        // the chunk's FP32 sums go to planes [chunk][c][Re/Im] straight from the accumulators
+        if (j <= M) {
+#pragma unroll
+            for (int c = 0; c < NK; ++c)
+#pragma unroll
+                for (int ri = 0; ri < 2; ++ri) {
+                    float* out = partial + (((long)ck * NK + c) * 2 + ri) * plane + j;
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) {
+                        const int i = i0 + 32 * wv + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                        if (i <= N) out[(long)i * (M + 1)] = acc[c][ri][v];
+                    }
+                }
+        }
     }
-    // accumulator element v of lane l: row 8(v/4) + 4(l/32) + v%4 of the fragment, column l % 32
-    const int j = j0 + (lane & 31);
-    if (j > M || !live) return;
-    const long plane = (long)(N + 1) * (M + 1);
-#pragma unroll
-    for (int c = 0; c < NK; ++c)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int i = i0 + 32 * wv + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-            if (i <= N)
-                partial[((long)blockIdx.z * NK + c) * plane + (long)i * (M + 1) + j] =
-                    make_double2((double)acc[c][0][v], (double)acc[c][1][v]);
-        }
 }
 
-// out[c][P-index] = sum over chunks (FP64), with optional conjugation.
-__global__ void k_ot_reduce(int N, int M, const double2* __restrict__ partial, int n_chunks, int nk, int conj0,
+// out[c][P-index] = sum over chunks of the FP32 chunk sums (in FP64), with optional conjugation.
+__global__ void k_ot_reduce(int N, int M, const float* __restrict__ partial, int n_chunks, int nk, int conj0,
                             double2* __restrict__ out0, double2* __restrict__ out1, const double* __restrict__ skip) {
     if (skip && *skip != 0.0) return;
     const long plane = (long)(N + 1) * (M + 1);
@@ -258,44 +292,75 @@ __global__ void k_ot_reduce(int N, int M, const double2* __restrict__ partial, i
     const long k = ij_to_p(i, j, N, M);
     for (int c = 0; c < nk; ++c) {
         double2 acc = make_double2(0.0, 0.0);
-        for (int b = 0; b < n_chunks; ++b) acc = zadd(acc, partial[((long)b * nk + c) * plane + o]);
+        for (int b = 0; b < n_chunks; ++b) {
+            const float* pc = partial + ((long)b * nk + c) * 2 * plane;
+            acc.x += (double)pc[o];
+            acc.y += (double)pc[plane + o];
+        }
         if (c == 0 && conj0) acc.y = -acc.y;
         (c == 0 ? out0 : out1)[k] = acc;
     }
 }
 
-// Sample chunks: about three workgroups per CU over the (site, unit) tiles, chunks of at least 256
-// samples (a multiple of the 32-sample tile) and at most 256 of them, which the plan's reduction
-// buffer holds (it has room for min(ceil(n / 256), 257) chunks).
-struct OtPlan { long chunk; int n_chunks; };
-static OtPlan ot_plan(int N, int M, long n) {
-    const long tiles = (long)((N + 1 + OM_R - 1) / OM_R) * ((M + 1 + OM_C - 1) / OM_C);
-    long target = (3L * 256 + tiles - 1) / tiles;
-    if (target > 256) target = 256;
-    long chunk = (n + target - 1) / target;
+// Sample chunks of at least n/256 and at least 256 samples (a multiple of the 32-sample tile), at most
+// 256 of them, which the plan's reduction buffer holds (it has room for min(ceil(n / 256), 257)
+// chunks); each chunk is summed in FP32 on its own, as many samples as on the vector units before.
+// The grid holds as many workgroups as the device keeps resident at once (the kernel's occupancy
+// times the CUs, so that no second, nearly empty round follows); each loops over its chunks.
+struct OtPlan { long chunk; int n_chunks; int grid_z; };
+template <int NK>
+static int ot_resident_per_cu() {
+    static int cached = 0;
+    if (!cached) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_ot<NK>, 256, 0) != hipSuccess || nb < 1) nb = 1;
+        cached = nb;
+    }
+    return cached;
+}
+static OtPlan ot_plan(int N, int M, long n, int nk, int n_cu) {
+    long chunk = (n + 255) / 256;
     chunk = ((chunk + OM_S - 1) / OM_S) * OM_S;
     if (chunk < 256) chunk = 256;
-    return {chunk, (int)((n + chunk - 1) / chunk)};
+    const int n_chunks = (int)((n + chunk - 1) / chunk);
+    const long tiles = (long)((N + 1 + OM_R - 1) / OM_R) * ((M + 1 + OM_C - 1) / OM_C);
+    const long slots = (long)n_cu * (nk == 2 ? ot_resident_per_cu<2>() : ot_resident_per_cu<1>());
+    long z = slots / tiles;
+    if (z < 1) z = 1;
+    if (z > n_chunks) z = n_chunks;
+    // the same number of chunks for every workgroup where possible
+    z = (n_chunks + ((n_chunks + z - 1) / z) - 1) / ((n_chunks + z - 1) / z);
+    return {chunk, n_chunks, (int)z};
 }
 
-static hipError_t run_ot(int N, int M, const int8_t* sig, const float2* T, long n, int kind0, int kind1, int nk,
-                         const double* w, const float2* R, const double2* u, double2* partial, int conj0,
+// sig16: the packed sigma~ rows (k_pack_sig16) of the n samples; partial: scratch of at least
+// 2 nk (N + 1)(M + 1) floats per chunk
+static hipError_t run_ot(int N, int M, const int8_t* sig16, const float2* T, long n, int kind0, int kind1, int nk,
+                         const double* w, const float2* R, const double2* u, void* partial_buf, int conj0,
                          double2* out0, double2* out1, hipStream_t stream, const double* skip, Profiler* prof,
-                         int round_bf16 = 0) {
-    const OtPlan op = ot_plan(N, M, n);
-    dim3 grid((N + 1 + OM_R - 1) / OM_R, (M + 1 + OM_C - 1) / OM_C, op.n_chunks);
+                         int n_cu, int round_bf16 = 0) {
+    const OtPlan op = ot_plan(N, M, n, nk, n_cu);
+    const int row = sig16_row(N);
+    float* partial = static_cast<float*>(partial_buf);
+    dim3 grid((N + 1 + OM_R - 1) / OM_R, (M + 1 + OM_C - 1) / OM_C, op.grid_z);
     if (prof) prof->begin(PROF_OT, stream);
     if (nk == 2)
-        hipLaunchKernelGGL(k_ot<2>, grid, dim3(256), 0, stream, N, M, sig, T, n, op.chunk, kind0, kind1, w, R, u,
-                           partial, skip, round_bf16);
+        hipLaunchKernelGGL(k_ot<2>, grid, dim3(256), 0, stream, N, M, row, sig16, T, n, op.chunk, op.n_chunks, kind0,
+                           kind1, w, R, u, partial, skip, round_bf16);
     else
-        hipLaunchKernelGGL(k_ot<1>, grid, dim3(256), 0, stream, N, M, sig, T, n, op.chunk, kind0, kind1, w, R, u,
-                           partial, skip, round_bf16);
+        hipLaunchKernelGGL(k_ot<1>, grid, dim3(256), 0, stream, N, M, row, sig16, T, n, op.chunk, op.n_chunks, kind0,
+                           kind1, w, R, u, partial, skip, round_bf16);
     if (prof) prof->end(stream);
     const long plane = (long)(N + 1) * (M + 1);
     hipLaunchKernelGGL(k_ot_reduce, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, stream, N, M, partial,
                        op.n_chunks, nk, conj0, out0, out1, skip);
     return hipGetLastError();
+}
+
+static void pack_sig16(const int8_t* sig, long n, int N, int8_t* out, hipStream_t stream) {
+    const long cnt = n * (long)sig16_row(N);
+    hipLaunchKernelGGL(k_pack_sig16, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, sig, n, N,
+                       sig16_row(N), out);
 }
 
 // Fit mode (0):    F_k = coef [ORm_k / <R> - conj(Om_k)];
@@ -787,8 +852,8 @@ static hipError_t apply_op(const SrArgs& A, const SrWork& W, const double2* v, d
         }
         hipLaunchKernelGGL(k_dot_ov, dim3(64), dim3(256), 0, stream, P, W.Om, v, W.red, W.scal);
         hipLaunchKernelGGL(k_sub_mean, dim3(nblk(A.n)), dim3(256), 0, stream, A.n, W.u, W.red, 64, W.scal);
-        e = run_ot(A.N, A.M, A.samples, A.T, A.n, 2, 0, 1, A.weights, A.R, W.u, W.red + 64, 0, y, nullptr, stream,
-                   W.scal + SC_DONE, nullptr);
+        e = run_ot(A.N, A.M, W.sig16, A.T, A.n, 2, 0, 1, A.weights, A.R, W.u, W.red + 64, 0, y, nullptr, stream,
+                   W.scal + SC_DONE, nullptr, W.n_cu);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_add_shift, dim3(nblk(P)), dim3(256), 0, stream, P, v, A.eps, y, W.scal);
     } else {
@@ -812,8 +877,9 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
     hipLaunchKernelGGL(k_r_moments, dim3(nb_r), dim3(256), 0, stream, A.R, A.weights, A.n, W.red);
     hipLaunchKernelGGL(k_r_final, dim3(1), dim3(64), 0, stream, W.red, nb_r, A.dgamma, A.mode, W.scal);
     // conj(<O>) and <O^* R>
-    e = run_ot(A.N, A.M, A.samples, A.T, A.n, 0, 1, 2, A.weights, A.R, nullptr, W.red, 0, W.Om, W.ORm, stream, nullptr,
-               W.prof);
+    pack_sig16(A.samples, A.n, A.N, W.sig16, stream);
+    e = run_ot(A.N, A.M, W.sig16, A.T, A.n, 0, 1, 2, A.weights, A.R, nullptr, W.red, 0, W.Om, W.ORm, stream, nullptr,
+               W.prof, W.n_cu);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_make_f, dim3(nblk(P)), dim3(256), 0, stream, P, A.mode, W.Om, W.ORm, W.scal, W.F);
     hipLaunchKernelGGL(k_zdot, dim3(64), dim3(256), 0, stream, P, W.F, W.F, W.red, W.scal, 0);
@@ -825,8 +891,8 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
             // S stays the centred Gram matrix of one set of vectors (positive semi-definite).
             const double2* om_s = W.Om;
             if (A.prec == CRBM_PREC_BF16) {
-                e = run_ot(A.N, A.M, A.samples, A.T, A.n, 0, 0, 1, nullptr, A.R, nullptr, W.red, 1, W.Om16, nullptr,
-                           stream, nullptr, nullptr, 1);
+                e = run_ot(A.N, A.M, W.sig16, A.T, A.n, 0, 0, 1, nullptr, A.R, nullptr, W.red, 1, W.Om16, nullptr,
+                           stream, nullptr, nullptr, W.n_cu, 1);
                 if (e != hipSuccess) return e;
                 om_s = W.Om16;
             }
@@ -901,8 +967,9 @@ __global__ void k_loss(const float2* __restrict__ R, long n, double* __restrict_
 
 hipError_t launch_fidelity_grad(const GradArgs& A, const SrWork& W, hipStream_t stream) {
     if (A.grad) {
-        hipError_t e = run_ot(A.N, A.M, A.samples, A.T, A.n, 3, 0, 1, nullptr, A.R, nullptr, W.red, 0, A.grad, nullptr,
-                              stream, nullptr, W.prof);
+        pack_sig16(A.samples, A.n, A.N, W.sig16, stream);
+        hipError_t e = run_ot(A.N, A.M, W.sig16, A.T, A.n, 3, 0, 1, nullptr, A.R, nullptr, W.red, 0, A.grad, nullptr,
+                              stream, nullptr, W.prof, W.n_cu);
         if (e != hipSuccess) return e;
     }
     if (A.loss) hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, stream, A.R, A.n, A.loss);
