@@ -367,6 +367,15 @@ __device__ __forceinline__ void reduce_scatter8(float (&lm)[8], float2 (&ph)[8],
     }
 }
 
+// (log |p|, p / |p|) of a lane's share p, from n2 = |p|^2, on the hardware log2 and reciprocal square
+// root: n2 is a product of a few factors of modest size, far from the denormal range the library
+// forms guard against (p = 0 gives log |p| = -inf and the phase 1).
+__device__ __forceinline__ void share_polar(float2 prod, float n2, float& lm, float2& ph) {
+    constexpr float kHalfLn2 = 0.34657359027997264f;
+    lm = kHalfLn2 * __builtin_amdgcn_logf(n2);
+    ph = n2 > 0.f ? cscale(prod, __builtin_amdgcn_rsqf(n2)) : make_float2(1.f, 0.f);
+}
+
 // One lane's share of the factor product of an anti-aligned bond: the bond's row (cosh 2D, sinh 2D)
 // with D = W_i - W_j gives cosh Delta = cosh 2D and sinh Delta = -s_i sinh 2D for Delta = -2 s_i D.
 template <int E>
@@ -661,10 +670,12 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __rest
             for (int q = 0; q < SPW; ++q) {
                 if (!((mk[q] >> bit) & 1ull)) continue;
                 const float2 prod = bond_share<E>(tq, TE[q], -(float)A.samples[(s0 + q) * N + i]);
-                const float n2 = prod.x * prod.x + prod.y * prod.y;
                 const int slot = pushed & (kRing - 1);
-                s_lm[wv][slot][lane] = 0.5f * logf(n2);
-                s_ph[wv][slot][lane] = n2 > 0.f ? cscale(prod, rsqrtf(n2)) : make_float2(1.f, 0.f);
+                float lmv;
+                float2 phv;
+                share_polar(prod, prod.x * prod.x + prod.y * prod.y, lmv, phv);
+                s_lm[wv][slot][lane] = lmv;
+                s_ph[wv][slot][lane] = phv;
                 if (lane == 0) s_item[wv][slot] = (q << 16) | bnd;
                 ++pushed;
             }
@@ -736,9 +747,7 @@ __global__ __launch_bounds__(256) void k_local_one(LocalArgs A, const float2* __
                 float4 tq[E];
                 bond_row<E>(g, bnd, lane, tq);
                 const float2 prod = bond_share<E>(tq, TE, -(float)srow[uniform(g.bonds[bnd].x)]);
-                const float n2 = prod.x * prod.x + prod.y * prod.y;
-                lm[b] = 0.5f * logf(n2);
-                ph[b] = n2 > 0.f ? cscale(prod, rsqrtf(n2)) : make_float2(1.f, 0.f);
+                share_polar(prod, prod.x * prod.x + prod.y * prod.y, lm[b], ph[b]);
             }
         }
         reduce_scatter8(lm, ph, lane);
