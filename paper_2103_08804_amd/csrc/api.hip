@@ -293,7 +293,8 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
     rc = rc ? rc : p->alloc(&p->w.vstage, P);
     rc = rc ? rc : p->alloc(&p->w.u, S);
     rc = rc ? rc : p->alloc(&p->w.red, red_len);
-    rc = rc ? rc : p->alloc(&p->w.G, S * M);
+    // G: the matrix-free product's O v partials, ceil(M / 64) double2 (2 ceil(M / 64) float2) per sample
+    rc = rc ? rc : p->alloc(&p->w.G, S * 2 * ((M + 63) / 64));
     rc = rc ? rc : p->alloc(&p->w.sig16, S * (long)sig16_row(N));
     for (int k = 0; k < 3 && !rc; ++k) rc = p->alloc(&p->theta[k], S * M);
     rc = rc ? rc : p->alloc(&p->momB, S);

@@ -19,6 +19,11 @@ struct RbmView {            // device pointers, complex64 interleaved
 // the split W; skip (device, may be null) != 0 makes both launches return at once
 hipError_t launch_theta(const int8_t* sig, long n, int N, int M, const float2* b, const float2* W, float2* theta,
                         uint16_t* planes, hipStream_t stream, const double* skip = nullptr);
+// O v of the matrix-free S product, u[s] = sum_k T_sk (sigma_s V_W + v_b)_k + sigma_s . v_a, without
+// writing the n x M product; partial: n * ceil(M / 64) double2 scratch
+hipError_t launch_theta_ov(const int8_t* sig, long n, int N, int M, const float2* vb, const float2* vW,
+                           const double2* va, const float2* T, uint16_t* planes, double2* partial, double2* u,
+                           hipStream_t stream, const double* skip);
 
 // elements of the three BF16 planes of W used by the theta product and the fused log-cosh sums: 3 x (tiles of 64 units x 128
 // real columns) x (sites rounded up to 32)
@@ -114,7 +119,7 @@ struct SrWork {
     long red_len;
     float2* S;                // [P][P] dense (may be null)
     double2* S64;             // [P][P] dense double (Cholesky, may be null)
-    float2* G;                // [n][M] scratch of the matrix-free product
+    float2* G;                // [n][2 ceil(M / 64)] scratch of the matrix-free product (its O v partials)
     int8_t* sig16;            // [n][sig16_row(N)] sigma~ rows for the O^H c contraction
     float2* vstage;           // [P] float copy of a CG direction
     void* pack;               // packed operand planes of the matrix-core S contraction

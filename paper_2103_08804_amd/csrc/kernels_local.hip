@@ -189,6 +189,109 @@ hipError_t launch_theta(const int8_t* sig, long n, int N, int M, const float2* b
     return hipGetLastError();
 }
 
+// O v of the matrix-free S product without writing G = sigma V_W + v_b: the theta product of V tile by
+// tile, each unit's G_sk multiplied by T_sk in the epilogue and the tile's 64 units summed per sample in
+// double (products in FP32 widened to double, as a separate pass over G would); a reduce-scatter over
+// lane bits 4..0 leaves each row's sum in two lanes.  partial[ct][s] (double2, n per 64-unit tile).
+__global__ __launch_bounds__(256) void k_theta_ov(const int8_t* __restrict__ sig, long n, int N, int Np, int M,
+                                                  const float2* __restrict__ vb, const uint16_t* __restrict__ planes,
+                                                  int Mt, const float2* __restrict__ T, double2* __restrict__ partial,
+                                                  const double* __restrict__ skip) {
+    if (skip && *skip != 0.0) return;     // a converged iterative solve skips the product
+    __shared__ __attribute__((aligned(16))) unsigned char s_sig[TH_S * TH_ROW];
+    __shared__ __attribute__((aligned(16))) unsigned char s_w[3][TH_C * TH_ROW];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const long s0 = (long)blockIdx.x * TH_S;
+    const int ct = blockIdx.y;
+    floatx16_t acc[4];
+    theta_tile(sig, n, N, Np, planes, (long)Mt * TH_C, ct, s0, s_sig, s_w, acc);
+    const int ku0 = ct * 64 + (lane & 31), ku1 = ku0 + 32;
+    const float2 b0 = ku0 < M ? vb[ku0] : make_float2(0.f, 0.f);
+    const float2 b1 = ku1 < M ? vb[ku1] : make_float2(0.f, 0.f);
+    double px[16], py[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const long sm = s0 + wave * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        px[v] = 0.0;
+        py[v] = 0.0;
+        if (sm >= n) continue;
+        if (ku0 < M) {
+            const float2 t = T[sm * M + ku0];
+            const float gx = acc[0][v] + b0.x, gy = acc[1][v] + b0.y;
+            px[v] += (double)t.x * gx - (double)t.y * gy;
+            py[v] += (double)t.x * gy + (double)t.y * gx;
+        }
+        if (ku1 < M) {
+            const float2 t = T[sm * M + ku1];
+            const float gx = acc[2][v] + b1.x, gy = acc[3][v] + b1.y;
+            px[v] += (double)t.x * gx - (double)t.y * gy;
+            py[v] += (double)t.x * gy + (double)t.y * gx;
+        }
+    }
+    // reduce-scatter of the 16 rows over the 32 columns: lane bits 4, 3, 2, 1 halve the rows a lane
+    // keeps, bit 0 adds the last pair; the lane ends with row index 8 b4 + 4 b3 + 2 b2 + b1
+#pragma unroll
+    for (int w = 8, bit = 16; w >= 1; w >>= 1, bit >>= 1) {
+        const bool hi = (lane & bit) != 0;
+#pragma unroll
+        for (int t = 0; t < w; ++t) {
+            const double kx = hi ? px[t + w] : px[t], ky = hi ? py[t + w] : py[t];
+            const double sx = hi ? px[t] : px[t + w], sy = hi ? py[t] : py[t + w];
+            px[t] = kx + __shfl_xor(sx, bit);
+            py[t] = ky + __shfl_xor(sy, bit);
+        }
+    }
+    px[0] += __shfl_xor(px[0], 1);
+    py[0] += __shfl_xor(py[0], 1);
+    if (lane & 1) return;
+    const int v = 8 * ((lane >> 4) & 1) + 4 * ((lane >> 3) & 1) + 2 * ((lane >> 2) & 1) + ((lane >> 1) & 1);
+    const long sm = s0 + wave * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+    if (sm < n) partial[(long)ct * n + sm] = make_double2(px[0], py[0]);
+}
+
+// u[s] = sum over the tiles of partial[ct][s] + sigma_s . v_a: one wave per sample on a bounded grid
+// (waves step through the samples), so that the launches a converged solve skips stay cheap
+constexpr int kOvFinalBlocks = 4096;
+__global__ __launch_bounds__(256) void k_ov_final(int N, long n, int Mt, const int8_t* __restrict__ sig,
+                                                  const double2* __restrict__ va, const double2* __restrict__ partial,
+                                                  double2* __restrict__ u, const double* __restrict__ skip) {
+    if (skip && *skip != 0.0) return;
+    const int lane = threadIdx.x & 63;
+    for (long s = (long)blockIdx.x * 4 + (threadIdx.x >> 6); s < n; s += (long)gridDim.x * 4) {
+        double ax = 0.0, ay = 0.0;
+        for (int i = lane; i < N; i += kWave) {
+            const double sv = (double)sig[s * N + i];
+            ax += sv * va[i].x;
+            ay += sv * va[i].y;
+        }
+        for (int ct = lane; ct < Mt; ct += kWave) {
+            const double2 p = partial[(long)ct * n + s];
+            ax += p.x;
+            ay += p.y;
+        }
+        ax = wave_sum(ax);
+        ay = wave_sum(ay);
+        if (lane == 0) u[s] = make_double2(ax, ay);
+    }
+}
+
+hipError_t launch_theta_ov(const int8_t* sig, long n, int N, int M, const float2* vb, const float2* vW,
+                           const double2* va, const float2* T, uint16_t* planes, double2* partial, double2* u,
+                           hipStream_t stream, const double* skip) {
+    if (n <= 0) return hipSuccess;
+    const int Np = (N + TH_K - 1) / TH_K * TH_K;
+    const int Mt = (M + 63) / 64;
+    const long cnt = (long)Mt * TH_C * Np;
+    hipLaunchKernelGGL(k_wsplit, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, vW, N, M, Np, Mt, planes,
+                       skip);
+    hipLaunchKernelGGL(k_theta_ov, dim3((unsigned)((n + TH_S - 1) / TH_S), (unsigned)Mt), dim3(256), 0, stream, sig,
+                       n, N, Np, M, vb, planes, Mt, T, partial, skip);
+    const long fb = (n + 3) / 4;
+    hipLaunchKernelGGL(k_ov_final, dim3((unsigned)(fb < kOvFinalBlocks ? fb : kOvFinalBlocks)), dim3(256), 0, stream,
+                       N, n, Mt, sig, va, partial, u, skip);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void k_theta_lc(const int8_t* __restrict__ sig, long n, int N, int Np, int M,
                                                   const float2* __restrict__ b, const uint16_t* __restrict__ planes,
                                                   int Mt, float2* __restrict__ partial) {

@@ -602,33 +602,6 @@ __global__ __launch_bounds__(256) void k_pack_v(int N, int M, const double2* __r
     if (k < N + M) vb[k - N] = f; else vW[k - N - M] = f;
 }
 
-template <int E>
-__global__ __launch_bounds__(256) void k_ov(int N, int M, const int8_t* __restrict__ sig, const float2* __restrict__ T,
-                                            const float2* __restrict__ G, const double2* __restrict__ v, long n,
-                                            double2* __restrict__ u, const double* __restrict__ sc) {
-    if (sc[SC_DONE] != 0.0) return;
-    const int lane = threadIdx.x & 63;
-    const long s = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (s >= n) return;
-    double ax = 0, ay = 0;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int k = e * kWave + lane;
-        if (k < M) {
-            const float2 t = T[s * M + k], g = G[s * M + k];
-            ax += (double)t.x * g.x - (double)t.y * g.y;
-            ay += (double)t.x * g.y + (double)t.y * g.x;
-        }
-    }
-    for (int i = lane; i < N; i += 64) {
-        const double sv = (double)sig[s * N + i];
-        ax += sv * v[i].x;
-        ay += sv * v[i].y;
-    }
-    ax = wave_sum(ax);
-    ay = wave_sum(ay);
-    if (lane == 0) u[s] = make_double2(ax, ay);
-}
 
 // u <- u - <O>.v (scalar), so that the contraction gives <O^*(O v)> - <O>^* <O>.v with <O^*> folded.
 __global__ __launch_bounds__(256) void k_dot_ov(long P, const double2* __restrict__ Om, const double2* __restrict__ v,
@@ -835,21 +808,14 @@ int sbuild_splits(int N, int M, long n, int n_cu, int max_splits);
 static hipError_t apply_op(const SrArgs& A, const SrWork& W, const double2* v, double2* y, hipStream_t stream) {
     const long P = A.P;
     if (A.solver == CRBM_SOLVER_CG_MATFREE) {
-        // G = sigma V_W + V_b  (theta GEMM with b = v_b, W = v_W), into the T-sized scratch
+        // V = (v_b, v_W) in float for the theta product (b = v_b, W = v_W)
         float2* vb = W.vstage;
         float2* vW = vb + A.M;
         hipLaunchKernelGGL(k_pack_v, dim3(nblk(P)), dim3(256), 0, stream, A.N, A.M, v, vb, vW, W.scal);
-        float2* G = W.G;                                          // [n][M] scratch
-        hipError_t e = launch_theta(A.samples, A.n, A.N, A.M, vb, vW, G, W.wplanes, stream, W.scal + SC_DONE);
+        // u = O v per sample, the theta product of V fused with the sum over T (partials in the G scratch)
+        hipError_t e = launch_theta_ov(A.samples, A.n, A.N, A.M, vb, vW, v, A.T, W.wplanes,
+                                       reinterpret_cast<double2*>(W.G), W.u, stream, W.scal + SC_DONE);
         if (e != hipSuccess) return e;
-        const int E = (A.M + 63) / 64;
-        const dim3 g4(nblk(A.n, 4)), b256(256);
-        switch (E) {
-#define CRBM_CASE(e) case e: hipLaunchKernelGGL(k_ov<e>, g4, b256, 0, stream, A.N, A.M, A.samples, A.T, G, v, A.n, W.u, W.scal); break;
-            CRBM_CASE(1) CRBM_CASE(2) CRBM_CASE(3) CRBM_CASE(4) CRBM_CASE(5) CRBM_CASE(6) CRBM_CASE(7) CRBM_CASE(8)
-#undef CRBM_CASE
-            default: return hipErrorInvalidValue;
-        }
         hipLaunchKernelGGL(k_dot_ov, dim3(64), dim3(256), 0, stream, P, W.Om, v, W.red, W.scal);
         hipLaunchKernelGGL(k_sub_mean, dim3(nblk(A.n)), dim3(256), 0, stream, A.n, W.u, W.red, 64, W.scal);
         e = run_ot(A.N, A.M, W.sig16, A.T, A.n, 2, 0, 1, A.weights, A.R, W.u, W.red + 64, 0, y, nullptr, stream,
