@@ -987,6 +987,9 @@ static int batched_args(crbm_plan p, const crbm_rbm* gs, const void* t_params, c
     if (total < 0 || total > p->max_samples)
         return fail(CRBM_ENOMEM, "total_chains = %lld must be in [0, max_samples = %ld]", (long long)total, p->max_samples);
     if (n_burn < 0 || n_sweeps < 1) return fail(CRBM_EINVAL, "need n_burn >= 0 and n_sweeps >= 1");
+    if ((int64_t)(n_burn + (int64_t)n_sweeps) * p->N > INT32_MAX)
+        return fail(CRBM_EINVAL, "(n_burn + n_sweeps) * N = %lld proposals per chain exceed 2^31 - 1",
+                    (long long)((n_burn + (int64_t)n_sweeps) * p->N));
     if (proposal != CRBM_PROPOSAL_FLIP && proposal != CRBM_PROPOSAL_EXCHANGE)
         return fail(CRBM_EINVAL, "unknown proposal %d", proposal);
     if (p->N % 2) return fail(CRBM_EINVAL, "the S^z = 0 chain starts need an even number of sites");

@@ -26,12 +26,52 @@ __global__ void k_batched_reset(unsigned long long* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0ull;
 }
 
+// Value at site i (wave-uniform) of a per-lane array holding sites 64 q + lane; ONE: all sites in slot 0
+// (N <= 64), a single readlane.
+template <bool ONE, typename T>
+__device__ __forceinline__ T site_value(const T (&v)[4], int i) {
+    const int l = i & 63;
+    if (ONE) return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[0]), l));
+    const int q = i >> 6;
+    const int v0 = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[0]), l);
+    const int v1 = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[1]), l);
+    const int v2 = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[2]), l);
+    const int v3 = __builtin_amdgcn_readlane(__builtin_bit_cast(int, v[3]), l);
+    return __builtin_bit_cast(T, q == 0 ? v0 : q == 1 ? v1 : q == 2 ? v2 : v3);
+}
+
+// Rows of one whole [N][M] complex64 matrix through a single buffer descriptor: a row is a 32-bit scalar
+// offset and the lanes' columns loop-invariant vector offsets (clamped to the row), so a proposal's loads
+// need no 64-bit address arithmetic (the sweep here is bound by scalar issue, not by its row gathers).
+struct MatRows {
+    __amdgpu_buffer_rsrc_t r;
+    int row_bytes;
+};
+
+__device__ __forceinline__ MatRows mat_rows(const float2* W, int N, int M) {
+    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(W), (short)0, N * M * (int)sizeof(float2),
+                                              0x00020000),
+            M * (int)sizeof(float2)};
+}
+
+template <int E, bool PAIR>
+__device__ __forceinline__ void mat_fetch(const MatRows& m, const unsigned (&loff)[E], int i, int j, float2 (&wi)[E],
+                                          float2 (&wj)[E]) {
+    const int oi = i * m.row_bytes, oj = j * m.row_bytes;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        wi[e] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(m.r, loff[e], oi, 0));
+        if (PAIR) wj[e] = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(m.r, loff[e], oj, 0));
+    }
+}
+
 // Per-chain state of one wave.  theta of t~ changes only on accepted moves;
 // its rows are fetched when a move is accepted and added at the next accepted
 // move or measurement, so their L2 round trip overlaps the following proposals.
 template <int E, bool PAIR>
 struct BatchedChain {
     WaveSpins sp;
+    float ag[4];            // Re a of psi_gs at sites 64 q + lane
     float2 thg[E], tht[E];  // theta of psi_gs and of t~
     float Lg[E];            // Re log 2cosh theta_gs
     float2 pti[E], ptj[E];  // rows of t~'s W for the pending update of tht
@@ -131,23 +171,25 @@ __device__ __forceinline__ void measure(const BatchedArgs& A, BatchedChain<E, PA
 }
 
 // Proposal t of chain g.  Rows of psi_gs are read only for live moves.
-template <int E, bool PAIR>
-__device__ __forceinline__ void batched_step(const BatchedArgs& A, uint64_t g, int lane, long t,
-                                             BatchedChain<E, PAIR>& c, const float2* Wt, uint32_t* trow,
-                                             DrawBatch& batch) {
+template <int E, bool PAIR, bool ONE>
+__device__ __forceinline__ void batched_step(const BatchedArgs& A, uint64_t g, int lane, int t,
+                                             BatchedChain<E, PAIR>& c, const MatRows& Wg, const MatRows& Wt,
+                                             const unsigned (&loff)[E], uint32_t* trow, DrawBatch& batch) {
     const int N = A.N, M = A.M;
     Proposal cur = next_proposal(batch, A.seed, (uint32_t)g, 0ull, t, lane, N);
-    const int si = c.sp.get(cur.i), sj = c.sp.get(cur.j);
+    const int si = site_value<ONE>(c.sp.s, cur.i), sj = site_value<ONE>(c.sp.s, cur.j);
     if (!(PAIR && si == sj)) {
         float2 wi[E], wj[E], tn[E];
         float Ln[E];
-        fetch_rows<E, PAIR>(A.gs, M, cur, lane, wi, wj);
+        cur.ai = site_value<ONE>(c.ag, cur.i);
+        cur.aj = PAIR ? site_value<ONE>(c.ag, cur.j) : 0.f;
+        mat_fetch<E, PAIR>(Wg, loff, cur.i, cur.j, wi, wj);
         const float dl = proposal_dlog<E, PAIR>(cur, si, wi, wj, c.thg, c.Lg, tn, Ln, lane, M);
         if (cur.u < __expf(2.f * dl)) {
 #pragma unroll
             for (int e = 0; e < E; ++e) { c.thg[e] = tn[e]; c.Lg[e] = Ln[e]; }
             apply_pending(c, lane, M);
-            fetch_w<E, PAIR>(Wt, M, cur.i, cur.j, lane, c.pti, c.ptj);
+            mat_fetch<E, PAIR>(Wt, loff, cur.i, cur.j, c.pti, c.ptj);
             c.pm = -2.f * (float)si;
             c.sp.set(cur.i, -si, lane);
             if (PAIR) c.sp.set(cur.j, -sj, lane);
@@ -160,7 +202,7 @@ __device__ __forceinline__ void batched_step(const BatchedArgs& A, uint64_t g, i
     }
 }
 
-template <int E, bool PAIR>
+template <int E, bool PAIR, bool ONE>
 __global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
     extern __shared__ int8_t s_spins[];           // one 256-byte row per wave
     const int lane = threadIdx.x & 63;
@@ -200,6 +242,11 @@ __global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         BatchedChain<E, PAIR> c;
         c.sp.load(row, N, lane);
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            const int site = qq * kWave + lane;
+            c.ag[qq] = site < N ? A.gs.a[site].x : 0.f;
+        }
 
         // theta of psi_gs and of t~_inst from the spins (lanes past M: theta = 0, see proposal_dlog)
 #pragma unroll
@@ -250,11 +297,15 @@ __global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
         c.tw = 0;
         c.m0 = c.mr = c.mi = 0.0;
         uint32_t* trow = A.trace ? A.trace + (long)g * A.trace_words : nullptr;
-        const long total = (long)(A.n_burn + A.n_sweeps) * N;
+        const int total = (A.n_burn + A.n_sweeps) * N;   // the plan checks that it fits
+        const MatRows Wg = mat_rows(A.gs.W, N, M), Wtr = mat_rows(Wt, N, M);
+        unsigned loff[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) loff[e] = (unsigned)min(e * kWave + lane, M - 1) * (unsigned)sizeof(float2);
         DrawBatch batch;
-        long t = 0;
+        int t = 0;
         for (int sw = 0; sw < A.n_burn + A.n_sweeps; ++sw) {
-            for (int p = 0; p < N; ++p, ++t) batched_step<E, PAIR>(A, g, lane, t, c, Wt, trow, batch);
+            for (int p = 0; p < N; ++p, ++t) batched_step<E, PAIR, ONE>(A, g, lane, t, c, Wg, Wtr, loff, trow, batch);
             if (sw >= A.n_burn) measure(A, c, ph, da, beta, lane);
         }
         if (lane == 0) {
@@ -295,12 +346,14 @@ hipError_t launch_batched(const BatchedArgs& A, int blocks, int waves_per_block,
     const int E = (A.M + kWave - 1) / kWave;
     const dim3 grid(blocks), block(64 * waves_per_block);
     const size_t lds = 256 * (size_t)waves_per_block;
-    const bool pair = A.proposal == 1;
+    const bool pair = A.proposal == 1, one = A.N <= kWave;
     switch (E) {
 #define CRBM_CASE(e)                                                                                   \
     case e:                                                                                            \
-        if (pair) hipLaunchKernelGGL((k_batched<e, true>), grid, block, lds, stream, A);               \
-        else hipLaunchKernelGGL((k_batched<e, false>), grid, block, lds, stream, A);                   \
+        if (pair && one) hipLaunchKernelGGL((k_batched<e, true, true>), grid, block, lds, stream, A);  \
+        else if (pair) hipLaunchKernelGGL((k_batched<e, true, false>), grid, block, lds, stream, A);   \
+        else if (one) hipLaunchKernelGGL((k_batched<e, false, true>), grid, block, lds, stream, A);    \
+        else hipLaunchKernelGGL((k_batched<e, false, false>), grid, block, lds, stream, A);            \
         break;
         CRBM_CASE(1) CRBM_CASE(2) CRBM_CASE(3) CRBM_CASE(4) CRBM_CASE(5) CRBM_CASE(6) CRBM_CASE(7) CRBM_CASE(8)
 #undef CRBM_CASE
