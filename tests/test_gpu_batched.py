@@ -38,6 +38,7 @@ def _instances(orc, kind, Lx, Ly, M, counts, seed=5):
     (1, 4, 4, 16, [3, 0, 5, 1, 7, 2], 1),
     (0, 12, 1, 24, [2, 4, 1], 0),
     (1, 4, 4, 64, [4, 1, 2], 1),       # M fills one 64-lane group exactly
+    (1, 10, 10, 16, [2, 1, 2], 1),     # N > 64: spins and a spread over two lane slots
 ])
 def test_batched_vs_oracle(orc, kind, Lx, Ly, M, counts, proposal):
     N = Lx * Ly
@@ -87,3 +88,15 @@ def test_batched_graph_replay_and_autotune(orc):
     crbm.batched_moments(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 1, 3, 1, 7, eager)
     torch.cuda.synchronize()
     assert torch.equal(eager, ref)
+
+
+def test_batched_rejects_oversized_chains(orc):
+    """More than 2^31 - 1 proposals per chain is refused on the host, before any launch."""
+    kind, Lx, Ly, M = 1, 4, 4, 16
+    gs_d, tv, betas, qs, offsets, dev = _instances(orc, kind, Lx, Ly, M, [2, 3])
+    plan = crbm.Plan(kind, Lx, Ly, M, int(offsets[-1]))
+    mu = torch.zeros(2, 2, dtype=torch.complex128, device="cuda")
+    n_sweeps = (2 ** 31) // (Lx * Ly) + 1
+    with pytest.raises(crbm.CrbmError):
+        crbm.batched_moments(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 0, n_sweeps, 1, 3, mu,
+                             total_chains=int(offsets[-1]))
