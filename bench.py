@@ -96,7 +96,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the library runs on one GPU per process; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import paper_2103_08804_amd as crbm
