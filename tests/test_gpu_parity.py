@@ -296,10 +296,12 @@ def test_sr_step_mc_weights_dense_vs_matfree(orc):
     assert rel_err(res[1], info["dalpha"]) < 1e-3
 
 
-@pytest.mark.parametrize("kind,Lx,Ly,M,n", [(1, 4, 4, 16, 1500), (0, 40, 1, 80, 8192)])
+@pytest.mark.parametrize("kind,Lx,Ly,M,n", [(1, 4, 4, 16, 1500), (0, 40, 1, 80, 8192), (0, 15, 1, 19, 2000)])
 def test_cholesky_solve_residual(orc, kind, Lx, Ly, M, n):
     """Blocked FP64 Cholesky solve of (S + eps I) x = F: P = 288 (four 64-column panels and a ragged one,
-    also checked against the oracle's update) and P = 3320 (the 40-site chain with alpha = 2, 52 panels).
+    also checked against the oracle's update), P = 3320 (the 40-site chain with alpha = 2, 52 panels) and
+    P = 319 (odd: rows of S start on 8 bytes, so the dense CG product reads one column per load; two
+    tiles, the second ragged).
     The residual against the stored FP32 S is taken in complex128 with torch; a backward-stable solve
     leaves it below a few P * 2^-53 of |S + eps I| |x|."""
     N = Lx * Ly
