@@ -337,7 +337,10 @@ int crbm_spectrum_cf(const double* a, const double* b2, int m, double E0, double
  *   betas         complex128 [n_inst]
  *   q             device double [n_inst][2]
  *   chain_offsets device int64 [n_inst + 1], non-decreasing, chain_offsets[0] = 0,
- *                 chain_offsets[n_inst] = total_chains <= the plan's max_samples
+ *                 chain_offsets[n_inst] = total_chains <= the plan's max_samples.  The offsets live in
+ *                 device memory and are not checked on the host: a chain takes the instance found by
+ *                 binary search whatever they hold, and an instance whose range is not inside
+ *                 [0, total_chains] gets NaN in both moments (no access outside the buffers)
  *   mu_out        complex128 [n_inst][2] = (<|f_q|^2>, <f_q^* beta t~/psi_gs>) per instance
  *   trace         NULL, or device uint32 [total_chains][ceil((n_burn + n_sweeps) * N / 32)]: the accept
  *                 bit of every proposal of chain g (bit t % 32 of word t / 32 of row g, t = sweep*N + k,

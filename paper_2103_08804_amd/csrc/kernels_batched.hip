@@ -316,13 +316,22 @@ __global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
     }
 }
 
-// mu_out[i] = (sum of chain partials of instance i) / (c_i n_sweeps)
+// mu_out[i] = (sum of chain partials of instance i) / (c_i n_sweeps).  An instance whose chain range
+// [offsets[i], offsets[i+1]) is not inside [0, total) reads no partials and gets NaN moments.
 __global__ void k_batched_reduce(const double2* __restrict__ partial, const int64_t* __restrict__ offsets, int n_inst,
-                                 int n_sweeps, double2* __restrict__ mu) {
+                                 int64_t total, int n_sweeps, double2* __restrict__ mu) {
     const int i = blockIdx.x;
     if (i >= n_inst) return;
     __shared__ double sh[4][4];
     const int64_t b = offsets[i], e = offsets[i + 1];
+    if (b < 0 || e < b || e > total) {
+        if (threadIdx.x == 0) {
+            const double nan = __builtin_nan("");
+            mu[2 * i] = make_double2(nan, nan);
+            mu[2 * i + 1] = make_double2(nan, nan);
+        }
+        return;
+    }
     double a0 = 0, ar = 0, ai = 0;
     for (int64_t c = b + threadIdx.x; c < e; c += blockDim.x) {
         a0 += partial[2 * c].x;
@@ -360,7 +369,7 @@ hipError_t launch_batched(const BatchedArgs& A, int blocks, int waves_per_block,
         default: return hipErrorInvalidValue;
     }
     hipLaunchKernelGGL(k_batched_reduce, dim3(A.n_inst), dim3(256), 0, stream, A.partial, A.offsets, A.n_inst,
-                       A.n_sweeps, mu);
+                       (int64_t)A.total, A.n_sweeps, mu);
     return hipGetLastError();
 }
 

@@ -100,3 +100,25 @@ def test_batched_rejects_oversized_chains(orc):
     with pytest.raises(crbm.CrbmError):
         crbm.batched_moments(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 0, n_sweeps, 1, 3, mu,
                              total_chains=int(offsets[-1]))
+
+
+def test_batched_bad_offsets_give_nan(orc):
+    """Offsets live on the device and are not checked on the host: an instance whose chain range is
+    reversed or runs past total_chains gets NaN moments, the others are unaffected."""
+    kind, Lx, Ly, M = 1, 4, 4, 16
+    counts = [3, 2, 3]
+    gs_d, tv, betas, qs, offsets, dev = _instances(orc, kind, Lx, Ly, M, counts)
+    total = int(offsets[-1])
+    plan = crbm.Plan(kind, Lx, Ly, M, total)
+    good = torch.zeros(3, 2, dtype=torch.complex128, device="cuda")
+    crbm.batched_moments(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 1, 3, 1, 5, good, total_chains=total)
+    bad_off = torch.tensor([0, 3, 1, total + 4], dtype=torch.int64, device="cuda")   # [3, 1) reversed, [1, 12) past 8
+    bad = torch.zeros_like(good)
+    crbm.batched_moments(plan, gs_d, dev["t"], dev["b"], dev["q"], bad_off, 1, 3, 1, 5, bad, total_chains=total)
+    torch.cuda.synchronize()
+    b = np_of(bad)
+    assert np.all(np.isfinite(np_of(good)))
+    assert np.all(np.isnan(b[1].real)) and np.all(np.isnan(b[1].imag))
+    assert np.all(np.isnan(b[2].real)) and np.all(np.isnan(b[2].imag))
+    # instance 0 owns chains 0..2 under both offset vectors: same chains, same sums
+    assert np.array_equal(b[0], np_of(good)[0])
