@@ -32,6 +32,44 @@ __device__ __forceinline__ float2 cexpf(float2 z) {
     return make_float2(e * c, e * s);
 }
 
+// (cos x, sin x) of a float: x = k pi/2 + r by the Cody-Waite reduction (pi/2 = P1 + P2 + P3, each
+// k Pi removed by one fused multiply-add), r in [-pi/4, pi/4], then the Taylor series of sin r to r^9
+// and of cos r to r^10 (truncation below 2e-9) and the quadrant k mod 4.  About one ulp for
+// |x| < 3000.  The library sincos carries a large-argument reduction whose code and registers every
+// kernel that evaluates log cosh per hidden unit would pay for.
+__device__ __forceinline__ float2 cos_sin(float x) {
+    const float k = rintf(x * 0.63661977f);
+    float r = fmaf(-k, 1.5703125f, x);
+    r = fmaf(-k, 4.837512969970703e-4f, r);
+    r = fmaf(-k, 7.549790126404332e-8f, r);
+    const float r2 = r * r;
+    float ps = fmaf(r2, 2.7557319e-6f, -1.9841270e-4f);
+    ps = fmaf(r2, ps, 8.3333338e-3f);
+    ps = fmaf(r2, ps, -0.16666667f);
+    ps = fmaf(r2, ps, 1.f);
+    const float sr = r * ps;
+    float pc = fmaf(r2, -2.7557320e-7f, 2.4801588e-5f);
+    pc = fmaf(r2, pc, -1.3888889e-3f);
+    pc = fmaf(r2, pc, 4.1666668e-2f);
+    pc = fmaf(r2, pc, -0.5f);
+    const float cr = fmaf(r2, pc, 1.f);
+    const int q = (int)k & 3;
+    const float c = (q == 0) ? cr : (q == 1) ? -sr : (q == 2) ? -cr : sr;
+    const float sn = (q == 0) ? sr : (q == 1) ? cr : (q == 2) ? -sr : -cr;
+    return make_float2(c, sn);
+}
+
+// log 2cosh z = s z + log 2 + log f, f = (1 + e^{-2 s z}) / 2, s = sign Re z, |f| <= 1: adds s z to lin
+// and multiplies f into p
+__device__ __forceinline__ void cosh_factor(float2 z, float sign, float2& lin, float2& p) {
+    const float sg = z.x >= 0.f ? 1.f : -1.f;
+    const float ex = expf(-2.f * fabsf(z.x));
+    const float2 cs = cos_sin(2.f * sg * z.y);
+    lin.x += sign * fabsf(z.x);
+    lin.y += sign * sg * z.y;
+    p = cmul(p, make_float2(0.5f * (1.f + ex * cs.x), -0.5f * ex * cs.y));
+}
+
 // double complex
 __device__ __forceinline__ double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 zsub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
@@ -80,9 +118,8 @@ __device__ __forceinline__ float2 log2cosh(float2 z) {
     const float s = z.x >= 0.f ? 1.f : -1.f;
     const float ax = fabsf(z.x), sy = s * z.y;
     const float e = expf(-2.f * ax);
-    float sn, cs;
-    sincosf(2.f * sy, &sn, &cs);
-    const float wr = e * cs, wi = -e * sn;
+    const float2 cs = cos_sin(2.f * sy);
+    const float wr = e * cs.x, wi = -e * cs.y;
     return make_float2(ax + 0.5f * log1pf(2.f * wr + e * e), sy + atan2f(wi, 1.f + wr));
 }
 // Re log(2 cosh z) = |x| + log(q)/2, q = 1 + 2 e cos 2y + e^2 = |1 + e^{-2 s z}|^2 in [0, 4],
@@ -102,9 +139,8 @@ __device__ __forceinline__ float re_log2cosh_fast(float2 z) {
 __device__ __forceinline__ float2 ctanhf(float2 z) {
     const float s = z.x >= 0.f ? 1.f : -1.f;
     const float e = expf(-2.f * fabsf(z.x));
-    float sn, cs;
-    sincosf(2.f * s * z.y, &sn, &cs);
-    const float wr = e * cs, wi = -e * sn;
+    const float2 cs = cos_sin(2.f * s * z.y);
+    const float wr = e * cs.x, wi = -e * cs.y;
     float2 q = cdiv(make_float2(1.f - wr, -wi), make_float2(1.f + wr, wi));
     return make_float2(s * q.x, s * q.y);
 }

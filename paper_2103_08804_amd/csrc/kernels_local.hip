@@ -316,13 +316,7 @@ __global__ __launch_bounds__(256) void k_theta_lc(const int8_t* __restrict__ sig
         for (int h = 0; h < 2; ++h) {
             if ((h == 0 ? ku0 : ku1) >= M) continue;
             const float2 bb = h == 0 ? b0 : b1;
-            const float zx = acc[2 * h][v] + bb.x, zy = acc[2 * h + 1][v] + bb.y;
-            const float sg = zx >= 0.f ? 1.f : -1.f;
-            const float e = expf(-2.f * fabsf(zx));
-            float sn, cs;
-            sincosf(2.f * sg * zy, &sn, &cs);
-            lin[v] = cadd(lin[v], make_float2(fabsf(zx), sg * zy));
-            pr[v] = cmul(pr[v], make_float2(0.5f * (1.f + e * cs), -0.5f * e * sn));
+            cosh_factor(make_float2(acc[2 * h][v] + bb.x, acc[2 * h + 1][v] + bb.y), 1.f, lin[v], pr[v]);
         }
     }
     // reduce-scatter of the 16 rows over the 32 columns (lane bits 4..1), then the last pair (bit 0):
@@ -576,14 +570,8 @@ __device__ __forceinline__ float2 lc_diff(const float2* __restrict__ th, const f
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const float2 z = h == 0 ? th[s * M + k] : ph[s * M + k];
-            const float sg = z.x >= 0.f ? 1.f : -1.f;
-            const float ex = expf(-2.f * fabsf(z.x));
-            float sn, cs;
-            sincosf(2.f * sg * z.y, &sn, &cs);
-            const float2 f = make_float2(0.5f * (1.f + ex * cs), -0.5f * ex * sn);
-            const float2 l = make_float2(fabsf(z.x), sg * z.y);
-            if (h == 0) { lin = cadd(lin, l); pt = cmul(pt, f); }
-            else { lin = csub(lin, l); pp = cmul(pp, f); }
+            if (h == 0) cosh_factor(z, 1.f, lin, pt);
+            else cosh_factor(z, -1.f, lin, pp);
         }
     }
     // log pt - log pp = log|pt|/|pp| + i arg(pt conj(pp))
