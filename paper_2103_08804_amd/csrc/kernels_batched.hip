@@ -234,8 +234,8 @@ __global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
         }
 #pragma unroll
         for (int e = 0; e < E; ++e) c.Lg[e] = re_log2cosh_fast(c.thg[e]);
-        // phases e^{-i q.r} of this lane's sites (q.r reduced to [-pi, pi] in double, then a float
-        // sincos) and a_t - a_gs there
+        // phases e^{-i q.r} of this lane's sites (q.r reduced to [-pi, pi] in double, then cos_sin of
+        // the float, accurate there) and a_t - a_gs there
         float2 ph[4], da[4];
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
@@ -249,9 +249,8 @@ __global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
                 const double arg = q0 * x + q1 * y;
                 const double two_pi = 6.283185307179586476925286766559;
                 const float red = (float)(arg - two_pi * rint(arg / two_pi));
-                float sn, cs;
-                sincosf(red, &sn, &cs);
-                ph[qq] = make_float2(cs, -sn);
+                const float2 cs = cos_sin(red);
+                ph[qq] = make_float2(cs.x, -cs.y);
             }
         }
         const double2 beta = A.betas[inst];
