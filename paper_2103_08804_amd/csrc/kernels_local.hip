@@ -792,9 +792,10 @@ __global__ __launch_bounds__(256) void k_local(LocalArgs A, const float2* __rest
 
 // Narrow RBMs (M <= 3 x 64): one sample per wave.  With few hidden units per lane the bookkeeping of
 // the bond-major walk costs more than the table reads it saves, so each wave walks its own sample's
-// anti-aligned bonds in batches of 8 with the shares kept in registers.
+// anti-aligned bonds in batches of 8 with the shares kept in registers.  Five waves per SIMD: the
+// kernel fits in 96 registers without spilling, and the walk's table reads want the extra wave.
 template <int E>
-__global__ __launch_bounds__(256) void k_local_one(LocalArgs A, const float2* __restrict__ th1g,
+__global__ __launch_bounds__(256, 5) void k_local_one(LocalArgs A, const float2* __restrict__ th1g,
                                                    const float2* __restrict__ thng, const float2* __restrict__ thmg) {
     __shared__ uint64_t s_mask[4][kMaxBonds / 64];
     __shared__ short s_anti[4][kMaxBonds];
