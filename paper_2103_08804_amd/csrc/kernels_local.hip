@@ -107,7 +107,9 @@ __device__ __forceinline__ void lc_join(float2& lin, float2& pr, float2 lin2, fl
 
 // The tile product: workgroup (x, ct) accumulates sigma[128 x s .. + 128) times the 128 plane rows of
 // unit tile ct over all sites, K chunks of TH_K sites through LDS.  Lane l of wave w ends with column
-// l % 32 of each 32-column block cb in acc[cb], rows w 32 + 8 (v / 4) + 4 (l / 32) + v % 4.
+// l % 32 of each 32-column block cb in acc[cb], rows w 32 + 8 (v / 4) + 4 (l / 32) + v % 4.  The kernels
+// built on it ask for four waves per SIMD: they then fit in 96 registers with the accumulators among
+// them, and four workgroups of 40 KB fill the compute unit's LDS.
 __device__ __forceinline__ void theta_tile(const int8_t* __restrict__ sig, long n, int N, int Np,
                                            const uint16_t* __restrict__ planes, long rows, int ct, long s0,
                                            unsigned char* s_sig, unsigned char (*s_w)[TH_C * TH_ROW],
@@ -153,7 +155,7 @@ __device__ __forceinline__ void theta_tile(const int8_t* __restrict__ sig, long 
 
 // theta = sigma W + b, complex64 [n][M]: lane column j holds units 64 ct + j (blocks 0, 1) and
 // 64 ct + 32 + j (blocks 2, 3), real and imaginary part together, so 32 lanes store 256 contiguous bytes
-__global__ __launch_bounds__(256) void k_theta(const int8_t* __restrict__ sig, long n, int N, int Np, int M,
+__global__ __launch_bounds__(256, 4) void k_theta(const int8_t* __restrict__ sig, long n, int N, int Np, int M,
                                                const float2* __restrict__ b, const uint16_t* __restrict__ planes,
                                                int Mt, float2* __restrict__ theta, const double* __restrict__ skip) {
     if (skip && *skip != 0.0) return;     // a converged iterative solve skips the product
@@ -193,7 +195,7 @@ hipError_t launch_theta(const int8_t* sig, long n, int N, int M, const float2* b
 // tile, each unit's G_sk multiplied by T_sk in the epilogue and the tile's 64 units summed per sample in
 // double (products in FP32 widened to double, as a separate pass over G would); a reduce-scatter over
 // lane bits 4..0 leaves each row's sum in two lanes.  partial[ct][s] (double2, n per 64-unit tile).
-__global__ __launch_bounds__(256) void k_theta_ov(const int8_t* __restrict__ sig, long n, int N, int Np, int M,
+__global__ __launch_bounds__(256, 4) void k_theta_ov(const int8_t* __restrict__ sig, long n, int N, int Np, int M,
                                                   const float2* __restrict__ vb, const uint16_t* __restrict__ planes,
                                                   int Mt, const float2* __restrict__ T, double2* __restrict__ partial,
                                                   const double* __restrict__ skip) {
@@ -292,7 +294,7 @@ hipError_t launch_theta_ov(const int8_t* sig, long n, int N, int M, const float2
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_theta_lc(const int8_t* __restrict__ sig, long n, int N, int Np, int M,
+__global__ __launch_bounds__(256, 4) void k_theta_lc(const int8_t* __restrict__ sig, long n, int N, int Np, int M,
                                                   const float2* __restrict__ b, const uint16_t* __restrict__ planes,
                                                   int Mt, float2* __restrict__ partial) {
     __shared__ __attribute__((aligned(16))) unsigned char s_sig[TH_S * TH_ROW];
