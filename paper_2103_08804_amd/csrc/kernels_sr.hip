@@ -205,8 +205,10 @@ __device__ __forceinline__ void ot_stage(OtRaw<NK>& raw, float (&sA)[OM_S][OM_R 
                     round_bf16);
 }
 
+// One coefficient vector: four waves per SIMD in 128 registers; two: three waves in 168 (no spills in
+// either, the matrix-core accumulators among the vector registers).
 template <int NK>
-__global__ __launch_bounds__(256) void k_ot(int N, int M, int row, const int8_t* __restrict__ sig16,
+__global__ __launch_bounds__(256, NK == 1 ? 4 : 3) void k_ot(int N, int M, int row, const int8_t* __restrict__ sig16,
                                             const float2* __restrict__ T,
                                             long n, long chunk, int n_chunks, int kind0, int kind1,
                                             const double* __restrict__ w, const float2* __restrict__ R,
