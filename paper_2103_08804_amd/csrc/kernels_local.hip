@@ -708,7 +708,8 @@ __device__ __forceinline__ void local_finish(const LocalArgs& A, const float2* _
 }
 
 // Three waves per SIMD up to 7 x 64 hidden units: E = 6 and 7 then spill 44 and 80 bytes per lane, and
-// the third wave still makes the bond walk 15% faster at E = 7; E = 8 keeps two waves.
+// the third wave still makes the bond walk 15% faster at E = 7; E = 8 keeps two waves (with three, its
+// 128-byte spill made it 2% slower).
 template <int E>
 __global__ __launch_bounds__(256, E <= 7 ? 3 : 2) void k_local(LocalArgs A, const float2* __restrict__ th1g,
                                                const float2* __restrict__ thng, const float2* __restrict__ thmg) {
