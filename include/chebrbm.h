@@ -230,6 +230,23 @@ int crbm_sr_step(crbm_plan plan, const crbm_rbm* fit, const int8_t* samples, con
                  int solver, int s_precision, double cg_tol, int cg_maxit, double* stats_out,
                  hipStream_t stream);
 
+/* Figure of merit and normalisation of a fit as it stands (Sec. III), from the target ratios R of its
+ * current parameters (crbm_local_estimators in Chebyshev mode):
+ *   gamma = arccos sqrt(|<R>|^2/<|R|^2>),   beta = <R>   (the normalisation taken once the steps are done).
+ * weights: double [n] or NULL (1/n), as in crbm_sr_step.
+ * stats_out: device double [5] = {gamma, Re beta, Im beta, <|R|^2>, flags (CRBM_FLAG_NONFINITE when
+ * <|R|^2> is not positive or a sum is not finite)}. */
+int crbm_fit_stats(crbm_plan plan, const void* R, const double* weights, long n_samples, double* stats_out,
+                   hipStream_t stream);
+
+/* Exact-enumeration weights: with all configurations listed once as samples, the sampling distribution
+ * of Sec. III, P(s) = |psi_s|^2/<psi|psi>, is
+ *   weights_out[s] = exp(2 Re logpsi[s] - LSE),   LSE = log sum_s' exp(2 Re logpsi[s'])   (double).
+ * logpsi: complex64 [n] (as written by crbm_local_estimators); weights_out: double [n].
+ * The partial sums are merged in a fixed order (deterministic).  Every weight is NaN when no amplitude
+ * is finite and non-zero. */
+int crbm_enum_weights(crbm_plan plan, const void* logpsi, long n, double* weights_out, hipStream_t stream);
+
 /* Natural-gradient energy minimisation of psi, by which the ground state psi_gs that seeds the
  * expansion is obtained (Sec. I, with the metric S of Sec. III):
  *   E = <E_loc>,  F_k = -lr [<O_k^* E_loc> - <O_k>^* <E_loc>]   (the bracket is dE/d conj(alpha_k)),

@@ -146,10 +146,37 @@ int orc_lattice_bonds(int kind, int Lx, int Ly, int* bonds) {
 /*   theta_j = b_j + sum_i W_ij sigma_i.                                      */
 /* log(2cosh z) = s z + log(1 + exp(-2 s z)), s = sign(Re z): the principal   */
 /* branch of the second term, so Im log psi is defined modulo 2 pi.           */
+/* Near a zero of cosh, z = i pi (m + 1/2) + d with |d| small, 1 + exp(-2sz)  */
+/* cancels to |d| and loses about log10(1/|d|) digits; there the identities   */
+/* cosh z = i (-1)^m sinh d and tanh z = coth d are used instead, with        */
+/* d = z - i pi (m + 1/2) formed with pi to about 32 digits (z itself is     */
+/* exact: a sum of a few parameters).  Both forms are the definition; only    */
+/* the rounding differs.                                                      */
 /* ------------------------------------------------------------------------- */
+/* pi = PI_HI + PI_LO to about 1e-32 (PI_HI the double nearest pi); the product PI_HI (m + 1/2) and its    */
+/* exact rounding error (fma) keep d exact to about 1e-32 |m|.                                             */
+static const double PI_LO = 1.2246467991473532e-16;
+
+static int near_zero_of_cosh(cplx z, double* m, cplx* d) {
+    *m = rint(cimag(z) / M_PI - 0.5);
+    const double h = *m + 0.5, hi = M_PI * h, err = fma(M_PI, h, -hi);
+    *d = creal(z) + I * (((cimag(z) - hi) - err) - PI_LO * h);
+    return cabs(*d) < 0.5;
+}
+
 static cplx log2cosh(cplx z) {
+    double m;
+    cplx d;
+    if (near_zero_of_cosh(z, &m, &d)) return log(2.0) + clog(csinh(d)) + I * (M_PI * (m + 0.5));
     double s = (creal(z) >= 0.0) ? 1.0 : -1.0;
     return s * z + clog(1.0 + cexp(-2.0 * s * z));
+}
+
+static cplx tanh_of(cplx z) {
+    double m;
+    cplx d;
+    if (near_zero_of_cosh(z, &m, &d)) return ccosh(d) / csinh(d);
+    return ctanh(z);
 }
 
 static void theta_of(int N, int M, const cplx* b, const cplx* W, const int8_t* sig, cplx* th) {
@@ -277,9 +304,9 @@ void orc_logderiv(int N, int M, const cplx* b, const cplx* W, const int8_t* sig,
             cplx* row = O + s * P;
             theta_of(N, M, b, W, sg, th);
             for (int i = 0; i < N; ++i) row[i] = (double)sg[i];
-            for (int j = 0; j < M; ++j) row[N + j] = ctanh(th[j]);
+            for (int j = 0; j < M; ++j) row[N + j] = tanh_of(th[j]);
             for (int i = 0; i < N; ++i)
-                for (int j = 0; j < M; ++j) row[N + M + (long)i * M + j] = (double)sg[i] * ctanh(th[j]);
+                for (int j = 0; j < M; ++j) row[N + M + (long)i * M + j] = (double)sg[i] * tanh_of(th[j]);
         }
         free(th);
     }
@@ -547,7 +574,7 @@ static cplx logderiv_entry(int N, int M, const cplx* b, const cplx* W, const int
     const int j = (int)(r < M ? r : (r - M) % M);
     cplx th = b[j];
     for (int i = 0; i < N; ++i) th += (double)sg[i] * W[(long)i * M + j];
-    const cplx t = ctanh(th);
+    const cplx t = tanh_of(th);
     if (r < M) return t;
     return (double)sg[(r - M) / M] * t;
 }

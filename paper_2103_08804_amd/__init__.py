@@ -33,7 +33,7 @@ EXPORTS = ("crbm_plan_create", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_la
            "crbm_sr_step", "crbm_sr_energy_step", "crbm_chebyshev_moment", "crbm_fidelity_grad", "crbm_batched_moments",
            "crbm_batched_autotune", "crbm_moment_matrices", "crbm_corrected_moments", "crbm_lanczos",
            "crbm_spectrum_kpm", "crbm_spectrum_cf", "crbm_probe_mfma", "crbm_probe_hbm", "crbm_probe_logcosh", "crbm_probe_gather",
-           "crbm_sym_matrices")
+           "crbm_sym_matrices", "crbm_fit_stats", "crbm_enum_weights")
 PROF_NAMES = ("sample", "theta", "local", "ot", "sbuild", "cg", "moment", "pack", "cholesky", "batched", "gram", "sborder")
 
 
@@ -82,6 +82,8 @@ def lib():
                                             _vp, _vp]
         L.crbm_sr_step.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _l, _d, _d, _i, _i, _d, _i, _vp, _vp]
         L.crbm_sr_energy_step.argtypes = L.crbm_sr_step.argtypes
+        L.crbm_fit_stats.argtypes = [_vp, _vp, _vp, _l, _vp, _vp]
+        L.crbm_enum_weights.argtypes = [_vp, _vp, _l, _vp, _vp]
         L.crbm_moment_matrices.argtypes = [_vp, P(_Rbm), _vp, _vp, _i, P(_d), _vp, _vp, _l, _vp, _vp, _vp]
         L.crbm_sym_matrices.argtypes = [_vp, P(_Rbm), _vp, _vp, _i, _i, _vp, _vp, _l, _vp, _vp, _vp]
         L.crbm_corrected_moments.argtypes = [_vp, _vp, _vp, _i, _d, _d, _i, _vp, _vp, _vp]
@@ -312,6 +314,21 @@ def sr_energy_step(plan: Plan, psi: RBM, samples, tanh_theta, eloc, lr: float, d
         _ptr(weights, torch.float64, (n,), "weights"), _ptr(tanh_theta, torch.complex64, (n, M), "tanh_theta"),
         _ptr(eloc, torch.complex64, (n,), "eloc"), n, lr, diag_shift, solver, precision, cg_tol, cg_maxit,
         _ptr(stats_out, torch.float64, (8,), "stats_out"), _stream(stream)))
+
+
+def fit_stats(plan: Plan, R, stats_out, weights=None, stream=None):
+    """stats_out (float64 [5]) = {gamma, Re beta, Im beta, <|R|^2>, flags} of the ratios R (complex64 [n])."""
+    n = R.shape[0]
+    _check(lib().crbm_fit_stats(plan.handle, _ptr(R, torch.complex64, (n,), "R"),
+                                _ptr(weights, torch.float64, (n,), "weights"), n,
+                                _ptr(stats_out, torch.float64, (5,), "stats_out"), _stream(stream)))
+
+
+def enum_weights(plan: Plan, logpsi, weights_out, stream=None):
+    """weights_out (float64 [n]) = |psi_s|^2 / sum |psi|^2 from logpsi (complex64 [n]), all configurations listed once."""
+    n = logpsi.shape[0]
+    _check(lib().crbm_enum_weights(plan.handle, _ptr(logpsi, torch.complex64, (n,), "logpsi"), n,
+                                   _ptr(weights_out, torch.float64, (n,), "weights_out"), _stream(stream)))
 
 
 def chebyshev_moment(plan: Plan, psi_gs: RBM, t_params, betas, qs, samples, mu_out, weights=None, stream=None):

@@ -3,6 +3,7 @@
 // Nothing here synchronises the host; every launch goes to the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -95,6 +96,7 @@ struct crbm_plan_s {
     int flags = 0;
     int2* bonds = nullptr;
     float4* bond_tab = nullptr;
+    uint8_t* node_flag = nullptr;
     SrWork w{};
     float2* theta[3] = {nullptr, nullptr, nullptr};
     double2* momB = nullptr;
@@ -119,6 +121,7 @@ struct crbm_plan_s {
         g.N = N; g.M = M; g.P = (int)P; g.n_bonds = n_bonds; g.bonds = bonds;
         g.kind = lat.kind; g.Lx = lat.Lx; g.J = lat.J;
         g.bond_tab = bond_tab;
+        g.node_flag = node_flag;
         return g;
     }
     template <class T>
@@ -171,6 +174,11 @@ int check_rbm(const crbm_plan_s* p, const crbm_rbm* r, const char* name) {
         return fail(CRBM_EINVAL, "%s has shape (N=%d, M=%d) but the plan has (N=%d, M=%d)", name, r->n_visible,
                     r->n_hidden, p->N, p->M);
     return CRBM_OK;
+}
+
+// principal complex logarithm of a complex double, rounded to binary32 (log 0 = -inf)
+float2 log_of(double2 z) {
+    return make_float2((float)std::log(std::hypot(z.x, z.y)), (float)std::atan2(z.y, z.x));
 }
 
 RbmView view(const crbm_rbm* r) {
@@ -281,6 +289,7 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
     int rc = CRBM_OK;
     rc = rc ? rc : p->alloc(&p->bonds, bonds.size());
     rc = rc ? rc : p->alloc(&p->bond_tab, bonds.size() * (size_t)n_hidden);
+    rc = rc ? rc : p->alloc(&p->node_flag, S);
     rc = rc ? rc : p->alloc(&p->w.scal, 32);
     rc = rc ? rc : p->alloc(&p->w.Om, P);
     rc = rc ? rc : p->alloc(&p->w.Om16, P);
@@ -485,6 +494,8 @@ int crbm_local_estimators(crbm_plan p, const crbm_rbm* fit, const crbm_rbm* psi_
         A.W_scale = cheb->W_scale;
         A.beta_n = make_double2(cheb->beta_n[0], cheb->beta_n[1]);
         A.beta_nm1 = make_double2(cheb->beta_nm1[0], cheb->beta_nm1[1]);
+        A.lbeta_n = log_of(A.beta_n);
+        A.lbeta_nm1 = log_of(A.beta_nm1);
         A.q0 = cheb->q[0];
         A.q1 = p->lat.kind == CRBM_LATTICE_CHAIN ? 0.0 : cheb->q[1];
     }
@@ -569,6 +580,24 @@ int crbm_sr_energy_step(crbm_plan p, const crbm_rbm* psi, const int8_t* samples,
                         int cg_maxit, double* stats_out, hipStream_t stream) {
     return sr_step_common(p, psi, samples, weights, T, eloc, n, -lr, eps, solver, prec, cg_tol, cg_maxit, stats_out,
                           1, stream);
+}
+
+int crbm_fit_stats(crbm_plan p, const void* R, const double* weights, long n, double* stats_out, hipStream_t stream) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (!R || !stats_out) return fail(CRBM_EINVAL, "R and stats_out must be non-NULL");
+    if (n < 1) return fail(CRBM_EINVAL, "n_samples must be >= 1");
+    if (int rc = set_device(p)) return rc;
+    hipError_t e = launch_fit_stats(static_cast<const float2*>(R), weights, n, p->w.red, stats_out, stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "fit_stats launch");
+}
+
+int crbm_enum_weights(crbm_plan p, const void* logpsi, long n, double* weights_out, hipStream_t stream) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (!logpsi || !weights_out) return fail(CRBM_EINVAL, "logpsi and weights_out must be non-NULL");
+    if (n < 1) return fail(CRBM_EINVAL, "n must be >= 1");
+    if (int rc = set_device(p)) return rc;
+    hipError_t e = launch_enum_weights(static_cast<const float2*>(logpsi), n, p->w.red, weights_out, stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "enum_weights launch");
 }
 
 int crbm_chebyshev_moment(crbm_plan p, const crbm_rbm* gs, const void* t_params, const double* betas, int n_max,

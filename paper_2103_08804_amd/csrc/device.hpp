@@ -112,6 +112,94 @@ __device__ __forceinline__ u32x4 draw(uint64_t seed, uint32_t a, uint64_t b, uin
 __device__ __forceinline__ int draw_index(uint32_t x, int n) { return (int)__umulhi(x, (uint32_t)n); }
 __device__ __forceinline__ float draw_unit(uint32_t x) { return (float)(x >> 8) * (1.0f / 16777216.0f); }
 
+// ---------------------------------------------------------------- near the zeros of cosh
+// cosh z vanishes at z = i pi (m + 1/2), where complex RBMs put hidden units to represent nodes of a
+// state.  A binary32 theta locates such a zero only to its own rounding (about 1e-7 |theta| after the sum
+// over sites), so cosh, tanh and log cosh at distance d from it carry relative errors near 1e-7 / d.  A
+// unit whose binary32 theta lies within kPoleBand of a zero (in both parts) is therefore re-evaluated:
+// theta in double from the sample's spins and the parameters (each term is a binary32 value, so the sum is
+// exact while the terms span fewer than about 25 binary orders of magnitude), delta = theta - i pi (m + 1/2)
+// with pi to about 32 digits, and
+//   cosh theta = i (-1)^m sinh delta,  log cosh theta = log sinh delta + i pi (m + 1/2),  tanh theta = coth delta.
+constexpr float kPoleBand = 0.5f;
+constexpr double kPiLo = 1.2246467991473532e-16;   // pi minus the double nearest pi
+
+__device__ __forceinline__ bool near_pole(float2 z) {
+    if (!(fabsf(z.x) < kPoleBand)) return false;
+    const float m = rintf(fmaf(z.y, 0.31830988618379067f, -0.5f));
+    return fabsf(fmaf(-3.14159265358979f, m + 0.5f, z.y)) < kPoleBand;
+}
+
+// theta_k = b_k + sum_i s_i W_ik in double over one sample's spins
+__device__ __forceinline__ double2 theta_double(const int8_t* __restrict__ srow, int N, int M, int k,
+                                                const float2* __restrict__ b, const float2* __restrict__ W) {
+    double x = (double)b[k].x, y = (double)b[k].y;
+    for (int i = 0; i < N; ++i) {
+        const float2 w = W[(long)i * M + k];
+        const double s = (double)srow[i];
+        x = fma(s, (double)w.x, x);
+        y = fma(s, (double)w.y, y);
+    }
+    return make_double2(x, y);
+}
+
+// delta = t - i pi (m + 1/2) for the zero of cosh nearest to t (pi to about 32 digits); h = m + 1/2
+__device__ __forceinline__ double2 pole_offset(double2 t, double& h) {
+    const double m = rint(t.y * 0.31830988618379067 - 0.5);
+    h = m + 0.5;
+    const double hi = 3.141592653589793 * h, err = fma(3.141592653589793, h, -hi);
+    return make_double2(t.x, ((t.y - hi) - err) - kPiLo * h);
+}
+
+// sinh d and cosh d of a complex d with |Re d|, |Im d| < 0.6, by the Taylor series of sinh, cosh, sin and cos
+// (truncation below 1e-19 relative)
+__device__ __forceinline__ void sinh_cosh_small(double2 d, double2& sh, double2& ch) {
+    const double dx = d.x, dy = d.y, x2 = dx * dx, y2 = dy * dy;
+    const double shx = dx * (1.0 + x2 / 6.0 * (1.0 + x2 / 20.0 * (1.0 + x2 / 42.0 * (1.0 + x2 / 72.0 * (1.0 + x2 / 110.0 *
+                       (1.0 + x2 / 156.0 * (1.0 + x2 / 210.0)))))));
+    const double chx = 1.0 + x2 / 2.0 * (1.0 + x2 / 12.0 * (1.0 + x2 / 30.0 * (1.0 + x2 / 56.0 * (1.0 + x2 / 90.0 *
+                       (1.0 + x2 / 132.0 * (1.0 + x2 / 182.0 * (1.0 + x2 / 240.0)))))));
+    const double sy = dy * (1.0 - y2 / 6.0 * (1.0 - y2 / 20.0 * (1.0 - y2 / 42.0 * (1.0 - y2 / 72.0 * (1.0 - y2 / 110.0 *
+                      (1.0 - y2 / 156.0 * (1.0 - y2 / 210.0)))))));
+    const double cy = 1.0 - y2 / 2.0 * (1.0 - y2 / 12.0 * (1.0 - y2 / 30.0 * (1.0 - y2 / 56.0 * (1.0 - y2 / 90.0 *
+                      (1.0 - y2 / 132.0 * (1.0 - y2 / 182.0 * (1.0 - y2 / 240.0)))))));
+    sh = make_double2(shx * cy, chx * sy);
+    ch = make_double2(chx * cy, shx * sy);
+}
+
+// log cosh theta (without log 2) and tanh theta, rounded to binary32, from theta in double near a zero of
+// cosh; the logarithm of the modulus on a power-of-two scaled copy, so that a modulus below the binary32
+// range still has its logarithm.
+__device__ __forceinline__ void pole_eval(double2 t, float2& lc, float2& th) {
+    double h;
+    double2 sh, ch;
+    sinh_cosh_small(pole_offset(t, h), sh, ch);
+    const int e = ilogb(fmax(fabs(sh.x), fabs(sh.y)));
+    const float ur = (float)ldexp(sh.x, -e), ui = (float)ldexp(sh.y, -e);
+    constexpr float kLn2 = 0.69314718055994531f;
+    lc = make_float2(0.5f * logf(ur * ur + ui * ui) + (float)e * kLn2, atan2f(ui, ur) + (float)(3.141592653589793 * h));
+    const double den = sh.x * sh.x + sh.y * sh.y;
+    th = make_float2((float)((ch.x * sh.x + ch.y * sh.y) / den), (float)((ch.y * sh.x - ch.x * sh.y) / den));
+}
+
+// log cosh z in double: the identities above next to a zero of cosh, elsewhere s z + log((1 + w)/2) with
+// w = exp(-2 s z), s = sign Re z
+__device__ __forceinline__ double2 log_cosh_double(double2 z) {
+    double h;
+    const double2 d = pole_offset(z, h);
+    if (fabs(d.x) < 0.5 && fabs(d.y) < 0.5) {
+        double2 sh, ch;
+        sinh_cosh_small(d, sh, ch);
+        return make_double2(0.5 * log(sh.x * sh.x + sh.y * sh.y), atan2(sh.y, sh.x) + 3.141592653589793 * h);
+    }
+    const double sg = z.x >= 0.0 ? 1.0 : -1.0;
+    const double e = exp(-2.0 * fabs(z.x));
+    double sn, cs;
+    sincos(2.0 * sg * z.y, &sn, &cs);
+    const double ur = 0.5 * (1.0 + e * cs), ui = -0.5 * e * sn;
+    return make_double2(fabs(z.x) + 0.5 * log(ur * ur + ui * ui), sg * z.y + atan2(ui, ur));
+}
+
 // ---------------------------------------------------------------- log(2 cosh z), tanh z
 // log(2 cosh z) = s z + log(1 + w), w = exp(-2 s z), s = sign(Re z), |w| <= 1.
 __device__ __forceinline__ float2 log2cosh(float2 z) {

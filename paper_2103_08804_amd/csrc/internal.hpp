@@ -41,7 +41,8 @@ struct Geometry {
     const int2* bonds;      // device [n_bonds]
     int kind, Lx;           // for site positions (f_q phases)
     double J;
-    float4* bond_tab;       // device [n_bonds][M] workspace: (cosh 2D, sinh 2D), D = W_i - W_j of one RBM
+    float4* bond_tab;       // device [n_bonds][M] workspace: (exp 2D, exp -2D), D = W_i - W_j of one RBM
+    uint8_t* node_flag;     // device [max_samples] workspace: 1 where the local-energy RBM is next to a node
 };
 
 // ---------------------------------------------------------------- init
@@ -74,6 +75,7 @@ struct LocalArgs {
     int order;
     double E_c, W_scale;
     double2 beta_n, beta_nm1;
+    float2 lbeta_n, lbeta_nm1;   // log beta_n, log beta_nm1 (principal branch; beta = 0 gives Re = -inf)
     double q0, q1;
     const int8_t* samples;
     long n_samples;
@@ -108,7 +110,7 @@ struct SrWork {
     double* scal;             // [32] device scalars (see kernels_sr.hip)
     double2* Om;              // [P]  <O>
     double2* Om16;            // [P]  <O> of the BF16-rounded operands
-    double2* ORm;             // [P]  <O^* R>
+    double2* ORm;             // [P]  <O^* (R - <R>)> (R = E_loc in energy mode)
     double2* F;               // [P]
     double2* x;               // [P]  solution
     double2* r;               // [P]
@@ -191,5 +193,11 @@ struct GradArgs {
     double* loss;                      // [1] or null
 };
 hipError_t launch_fidelity_grad(const GradArgs& args, const SrWork& w, hipStream_t stream);
+
+// gamma, beta = <R>, <|R|^2> and a flag word of the current fit (out: device double [5]); red: 512 double2
+hipError_t launch_fit_stats(const float2* R, const double* w, long n, double2* red, double* out, hipStream_t stream);
+// p(s) = exp(2 Re log psi_s - LSE) over n listed configurations; part: kLseParts double2 scratch
+constexpr int kLseParts = 256;
+hipError_t launch_enum_weights(const float2* logpsi, long n, double2* part, double* w, hipStream_t stream);
 
 }  // namespace crbm

@@ -26,12 +26,16 @@ __device__ __forceinline__ bool chol_failed(const double* sc) {
     return ((int)sc[SC_FLAGS_SLOT] & CRBM_FLAG_CHOLESKY_FAIL) != 0;
 }
 
-// A64 = S + eps I (lower triangle used)
+// A64 = S + eps I (lower triangle used); S == null: A64 already holds S in double, only the shift is added
 __global__ __launch_bounds__(256) void k_chol_load(long P, const float2* __restrict__ S, double eps,
                                                    double2* __restrict__ A) {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= P * P) return;
     const long i = idx / P, j = idx % P;
+    if (!S) {
+        if (i == j) A[idx].x += eps;
+        return;
+    }
     const float2 v = S[idx];
     A[idx] = make_double2((double)v.x + (i == j ? eps : 0.0), (double)v.y);
 }
@@ -255,9 +259,10 @@ __global__ __launch_bounds__(1024) void k_chol_solve(long P, const double2* __re
 }
 
 hipError_t launch_cholesky_solve(long P, const float2* S, double eps, const double2* F, double2* A64, double2* x,
-                                 double* sc, hipStream_t stream) {
+                                 double* sc, bool a64_holds_s, hipStream_t stream) {
     if (P < 1 || P > kCholMaxP) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_chol_load, dim3((unsigned)((P * P + 255) / 256)), dim3(256), 0, stream, P, S, eps, A64);
+    hipLaunchKernelGGL(k_chol_load, dim3((unsigned)((P * P + 255) / 256)), dim3(256), 0, stream, P,
+                       a64_holds_s ? nullptr : S, eps, A64);
     for (long k0 = 0; k0 < P; k0 += CH_NB) {
         const int nb = (int)(P - k0 < CH_NB ? P - k0 : CH_NB);
         hipLaunchKernelGGL(k_chol_diagblock, dim3(1), dim3(256), 0, stream, P, k0, nb, A64, sc);

@@ -295,8 +295,9 @@ hipError_t launch_theta_ov(const int8_t* sig, long n, int N, int M, const float2
 }
 
 __global__ __launch_bounds__(256, 4) void k_theta_lc(const int8_t* __restrict__ sig, long n, int N, int Np, int M,
-                                                  const float2* __restrict__ b, const uint16_t* __restrict__ planes,
-                                                  int Mt, float2* __restrict__ partial) {
+                                                  const float2* __restrict__ b, const float2* __restrict__ W,
+                                                  const uint16_t* __restrict__ planes, int Mt,
+                                                  float2* __restrict__ partial) {
     __shared__ __attribute__((aligned(16))) unsigned char s_sig[TH_S * TH_ROW];
     __shared__ __attribute__((aligned(16))) unsigned char s_w[3][TH_C * TH_ROW];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -310,6 +311,7 @@ __global__ __launch_bounds__(256, 4) void k_theta_lc(const int8_t* __restrict__ 
     const float2 b0 = ku0 < M ? b[ku0] : make_float2(0.f, 0.f);
     const float2 b1 = ku1 < M ? b[ku1] : make_float2(0.f, 0.f);
     float2 lin[16], pr[16];
+    uint32_t poles = 0;   // bit 2 v + h: element (row v, unit h) within the band of a zero of cosh
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
         lin[v] = make_float2(0.f, 0.f);
@@ -318,8 +320,23 @@ __global__ __launch_bounds__(256, 4) void k_theta_lc(const int8_t* __restrict__ 
         for (int h = 0; h < 2; ++h) {
             if ((h == 0 ? ku0 : ku1) >= M) continue;
             const float2 bb = h == 0 ? b0 : b1;
-            cosh_factor(make_float2(acc[2 * h][v] + bb.x, acc[2 * h + 1][v] + bb.y), 1.f, lin[v], pr[v]);
+            const float2 z = make_float2(acc[2 * h][v] + bb.x, acc[2 * h + 1][v] + bb.y);
+            if (near_pole(z)) poles |= 1u << (2 * v + h);
+            else cosh_factor(z, 1.f, lin[v], pr[v]);
         }
+    }
+    // accumulator element v of lane l is row 8 (v / 4) + 4 (l / 32) + v % 4 of the wave's 32 samples
+    while (poles) {
+        const int bit = __ffs(poles) - 1;
+        poles &= poles - 1;
+        const int v = bit >> 1, ku = (bit & 1) ? ku1 : ku0;
+        const long row = s0 + wave * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        if (row >= n) continue;
+        float2 lcr, thr;
+        pole_eval(theta_double(sig + row * N, N, M, ku, b, W), lcr, thr);
+#pragma unroll
+        for (int vv = 0; vv < 16; ++vv)
+            if (vv == v) lin[vv] = cadd(lin[vv], lcr);
     }
     // reduce-scatter of the 16 rows over the 32 columns (lane bits 4..1), then the last pair (bit 0):
     // lane ends with row 8 b4 + 4 b3 + 2 b2 + b1 of its half
@@ -415,7 +432,7 @@ hipError_t launch_lc_sums(const int8_t* sig, long n, int N, int M, const float2*
     hipLaunchKernelGGL(k_wsplit, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, W, N, M, Np, Mt, planes,
                        nullptr);
     hipLaunchKernelGGL(k_theta_lc, dim3((unsigned)((n + TH_S - 1) / TH_S), (unsigned)Mt), dim3(256), 0, stream, sig,
-                       n, N, Np, M, b, planes, Mt, partial);
+                       n, N, Np, M, b, W, planes, Mt, partial);
     hipLaunchKernelGGL(k_lc_final, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, stream, N, n, Mt, sig, a, partial,
                        Lg, beta, B, Lg_out);
     return hipGetLastError();
@@ -475,18 +492,33 @@ __device__ __forceinline__ void share_polar(float2 prod, float n2, float& lm, fl
     ph = n2 > 0.f ? cscale(prod, __builtin_amdgcn_rsqf(n2)) : make_float2(1.f, 0.f);
 }
 
-// One lane's share of the factor product of an anti-aligned bond: the bond's row (cosh 2D, sinh 2D)
-// with D = W_i - W_j gives cosh Delta = cosh 2D and sinh Delta = -s_i sinh 2D for Delta = -2 s_i D.
+// One lane's share of the factor product of an anti-aligned bond (i, j).  With Delta_k = -2 s_i D_k,
+// D = W_i - W_j, s_k = sign Re theta_k and w_k = exp(-2 s_k theta_k) (|w_k| <= 1),
+//   cosh(theta_k + Delta_k) / cosh theta_k = [exp(s_k Delta_k) + w_k exp(-s_k Delta_k)] / (1 + w_k),
+// whose numerator has no cancellation when |Delta| is large (the form cosh Delta + tanh theta sinh Delta
+// subtracts two numbers of size exp|Delta| when Re theta and Re Delta have opposite signs).  The bond's
+// table row holds (exp 2D, exp -2D); exp(s_k Delta_k) is exp 2D when s_k = -s_i.  The denominators are
+// the same for every bond of the sample: qinv = prod 1/(1 + w_k) over this lane's units (each factor in
+// [0.58, 1.72] off the zeros of cosh), multiplied into the lane's share so that its logarithm stays the
+// logarithm of the lane's part of the ratio; units near a zero of cosh enter a per-sample constant
+// instead (bond_term).  neg: bit e set when s_k < 0 for this lane's unit e, flipped for s_i = +1.
 template <int E>
-__device__ __forceinline__ float2 bond_share(const float4 (&tq)[E], const float2 (&te)[E], float nsi) {
+__device__ __forceinline__ float2 bond_share(const float4 (&tq)[E], const float2 (&tw)[E], uint32_t neg,
+                                             float2 qinv) {
     float2 prod = make_float2(1.f, 0.f);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const float2 ts = cmul(te[e], make_float2(tq[e].z, tq[e].w));
-        prod = cmul(prod, make_float2(fmaf(nsi, ts.x, tq[e].x), fmaf(nsi, ts.y, tq[e].y)));
+        const bool sel = ((neg >> e) & 1u) == 0u;
+        const float2 X = sel ? make_float2(tq[e].x, tq[e].y) : make_float2(tq[e].z, tq[e].w);
+        const float2 Y = sel ? make_float2(tq[e].z, tq[e].w) : make_float2(tq[e].x, tq[e].y);
+        const float2 num = make_float2(fmaf(tw[e].x, Y.x, fmaf(-tw[e].y, Y.y, X.x)),
+                                       fmaf(tw[e].x, Y.y, fmaf(tw[e].y, Y.x, X.y)));
+        prod = cmul(prod, num);
     }
-    return prod;
+    return cmul(prod, qinv);
 }
+// the sign word of bond_share for a bond whose first site has spin si
+__device__ __forceinline__ uint32_t bond_neg(uint32_t neg, float si) { return si > 0.f ? ~neg : neg; }
 
 // The bond's row of the table for this lane's hidden units (padding lanes give the factor 1).
 template <int E>
@@ -495,17 +527,18 @@ __device__ __forceinline__ void bond_row(const Geometry& g, int bnd, int lane, f
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = e * kWave + lane;
-        tq[e] = (k < g.M) ? tab[k] : make_float4(1.f, 0.f, 0.f, 0.f);
+        tq[e] = (k < g.M) ? tab[k] : make_float4(1.f, 0.f, 1.f, 0.f);
     }
 }
 
 // The exchange term of bond (i, j) for the sample with spin s_i = si, given the whole factor product
 // as (log |p|, phase): J/2 d1 psi(s^ij)/psi(s) with psi(s^ij)/psi(s) = exp(lm + Re da) phase
-// exp(i Im da), da = -2 s_i (a_i - a_j), and d1 the diagonal factor of t_0 after the swap.
+// exp(i Im da), da = -2 s_i (a_i - a_j) + cq (cq = -sum log(1 + w_k) over the units next to a zero of
+// cosh, whose denominators are kept out of the shares), and d1 the diagonal factor of t_0 after the swap.
 __device__ __forceinline__ float2 bond_term(const LocalArgs& A, const RbmView& pe, int i, int j, float si, float lm,
-                                            float2 ph, float2 d0, bool with_fq, float inv_sqrt_n) {
+                                            float2 ph, float2 d0, float2 cq, bool with_fq, float inv_sqrt_n) {
     const Geometry& g = A.g;
-    const float2 da = cscale(csub(pe.a[i], pe.a[j]), -2.f * si);
+    const float2 da = cadd(cscale(csub(pe.a[i], pe.a[j]), -2.f * si), cq);
     const float2 u = cscale(ph, rsqrtf(ph.x * ph.x + ph.y * ph.y));
     float sn, cs;
     sincosf(da.y, &sn, &cs);
@@ -527,8 +560,8 @@ __device__ __forceinline__ float2 bond_term(const LocalArgs& A, const RbmView& p
 template <int SPW>
 __device__ __forceinline__ void local_flush(const LocalArgs& A, const RbmView& pe, int lane, long s0, int done,
                                             int cnt, bool with_fq, float inv_sqrt_n, const float2 (&d0)[SPW],
-                                            float2 (&acc)[SPW], float (*s_lm)[kWave], float2 (*s_ph)[kWave],
-                                            const int* s_item) {
+                                            const float2 (&cq)[SPW], float2 (&acc)[SPW], float (*s_lm)[kWave],
+                                            float2 (*s_ph)[kWave], const int* s_item) {
     const Geometry& g = A.g;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -547,10 +580,13 @@ __device__ __forceinline__ void local_flush(const LocalArgs& A, const RbmView& p
     const int q = item >> 16, bnd = item & 0xFFFF;
     const int2 ij = g.bonds[bnd];
     const float si = (float)A.samples[(s0 + q) * g.N + ij.x];
-    float2 d0q = d0[0];
+    float2 d0q = d0[0], cqq = cq[0];
 #pragma unroll
-    for (int qq = 1; qq < SPW; ++qq) d0q = q == qq ? d0[qq] : d0q;
-    const float2 c = bond_term(A, pe, ij.x, ij.y, si, lm[0], ph[0], d0q, with_fq, inv_sqrt_n);
+    for (int qq = 1; qq < SPW; ++qq) {
+        d0q = q == qq ? d0[qq] : d0q;
+        cqq = q == qq ? cq[qq] : cqq;
+    }
+    const float2 c = bond_term(A, pe, ij.x, ij.y, si, lm[0], ph[0], d0q, cqq, with_fq, inv_sqrt_n);
     if ((lane & 7) == 0)
 #pragma unroll
         for (int qq = 0; qq < SPW; ++qq)
@@ -558,13 +594,16 @@ __device__ __forceinline__ void local_flush(const LocalArgs& A, const RbmView& p
 }
 
 // This lane's share of sum_k [log cosh theta_k - log cosh phi_k] over its hidden units, theta and phi
-// rows of two RBMs at sample s: log cosh z = s z + log((1 + w)/2), w = exp(-2 s z), with the linear
-// parts added and the factors of modulus <= 1 multiplied, so that one complex log serves E units
-// (the M log 2 of log 2 cosh cancel between the two RBMs).
+// rows of two RBMs (parameters vt, vp) at sample s (spins srow): log cosh z = s z + log((1 + w)/2),
+// w = exp(-2 s z), with the linear parts added and the factors of modulus <= 1 multiplied, so that one
+// complex log serves E units (the M log 2 of log 2 cosh cancel between the two RBMs); units near a zero
+// of cosh are re-evaluated in double and enter the linear part.
 template <int E>
 __device__ __forceinline__ float2 lc_diff(const float2* __restrict__ th, const float2* __restrict__ ph, long s, int M,
-                                          int lane) {
+                                          int lane, const RbmView& vt, const RbmView& vp,
+                                          const int8_t* __restrict__ srow, int N) {
     float2 lin = make_float2(0.f, 0.f), pt = make_float2(1.f, 0.f), pp = make_float2(1.f, 0.f);
+    uint32_t poles = 0;   // bit 2 e + h
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = e * kWave + lane;
@@ -572,9 +611,19 @@ __device__ __forceinline__ float2 lc_diff(const float2* __restrict__ th, const f
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const float2 z = h == 0 ? th[s * M + k] : ph[s * M + k];
-            if (h == 0) cosh_factor(z, 1.f, lin, pt);
+            if (near_pole(z)) poles |= 1u << (2 * e + h);
+            else if (h == 0) cosh_factor(z, 1.f, lin, pt);
             else cosh_factor(z, -1.f, lin, pp);
         }
+    }
+    while (poles) {
+        const int bit = __ffs(poles) - 1;
+        poles &= poles - 1;
+        const int h = bit & 1, k = (bit >> 1) * kWave + lane;
+        const RbmView& v = h == 0 ? vt : vp;
+        float2 lcr, thr;
+        pole_eval(theta_double(srow, N, M, k, v.b, v.W), lcr, thr);
+        lin = h == 0 ? cadd(lin, lcr) : csub(lin, lcr);
     }
     // log pt - log pp = log|pt|/|pp| + i arg(pt conj(pp))
     const float2 q = make_float2(pt.x * pp.x + pt.y * pp.y, pt.y * pp.x - pt.x * pp.y);
@@ -582,19 +631,26 @@ __device__ __forceinline__ float2 lc_diff(const float2* __restrict__ th, const f
     return make_float2(lin.x + 0.5f * (logf(nt) - logf(np)), lin.y + atan2f(q.y, q.x));
 }
 
-// One sample of a wave: log psi, tanh theta, O of fit; the tanh theta of the RBM whose Hamiltonian
-// action is taken (te), the diagonal factor d0 of t_0 and the anti-aligned bonds (mask words, count).
+// One sample of a wave: log psi, tanh theta, O of fit; for the RBM whose Hamiltonian action is taken
+// the bond-factor data of bond_share (w_k of this lane's units, their signs neg, the lane's product qinv of
+// the denominators and the constant cq of those next to a zero of cosh), the diagonal factor d0 of t_0 and
+// the anti-aligned bonds (mask words, count).
 template <int E>
 __device__ __forceinline__ void local_sample(const LocalArgs& A, const float2* __restrict__ th1g,
                                              const float2* __restrict__ thng, int lane, long s0, int q, int nq,
-                                             bool want_local, bool with_fq, int n_words, float2 (&te)[E], float2& d0,
-                                             int& n_anti, uint64_t* mask) {
+                                             bool want_local, bool with_fq, int n_words, float2 (&tw)[E],
+                                             uint32_t& neg, float2& qinv, float2& cq, float2& d0, int& n_anti,
+                                             bool& node, uint64_t* mask) {
     const Geometry& g = A.g;
     const int N = g.N, M = g.M;
     d0 = make_float2(1.f, 0.f);
     n_anti = 0;
+    neg = 0u;
+    qinv = make_float2(1.f, 0.f);
+    cq = make_float2(0.f, 0.f);
+    node = false;
 #pragma unroll
-    for (int e = 0; e < E; ++e) te[e] = make_float2(0.f, 0.f);
+    for (int e = 0; e < E; ++e) tw[e] = make_float2(0.f, 0.f);
     if (q >= nq) {
         if (lane < n_words) mask[lane] = 0ull;
         return;
@@ -609,16 +665,28 @@ __device__ __forceinline__ void local_sample(const LocalArgs& A, const float2* _
         const int k = e * kWave + lane;
         t1[e] = (k < M) ? th1g[s * M + k] : make_float2(0.f, 0.f);
     }
-    // tanh theta of fit, and log psi of fit when asked for
+    // tanh theta of fit, and log psi of fit when asked for; units near a zero of cosh re-evaluated in double
+    const int8_t* srow = A.samples + s * N;
+    uint32_t poles = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = e * kWave + lane;
-        T1[e] = (k < M) ? ctanhf(t1[e]) : make_float2(0.f, 0.f);
+        const bool p = k < M && near_pole(t1[e]);
+        poles |= p ? 1u << e : 0u;
+        T1[e] = (k < M && !p) ? ctanhf(t1[e]) : make_float2(0.f, 0.f);
+        if (A.logpsi_out && k < M && !p) lc1 = cadd(lc1, log2cosh(t1[e]));
+    }
+    while (poles) {
+        const int e = __ffs(poles) - 1;
+        poles &= poles - 1;
+        float2 lcr, thr;
+        pole_eval(theta_double(srow, N, M, e * kWave + lane, A.fit.b, A.fit.W), lcr, thr);
+        lc1 = cadd(lc1, make_float2(lcr.x + 0.69314718055994531f, lcr.y));
+#pragma unroll
+        for (int ee = 0; ee < E; ++ee)
+            if (ee == e) T1[ee] = thr;
     }
     if (A.logpsi_out) {
-#pragma unroll
-        for (int e = 0; e < E; ++e)
-            if (e * kWave + lane < M) lc1 = cadd(lc1, log2cosh(t1[e]));
         const float2 lp = wave_sum(cadd(lc1, a_dot_sigma(A.fit.a, sp, lane, N)));
         if (lane == 0) A.logpsi_out[s] = lp;
     }
@@ -651,16 +719,46 @@ __device__ __forceinline__ void local_sample(const LocalArgs& A, const float2* _
         }
     }
     if (!want_local) return;
+    // bond-factor data of psi_n (Chebyshev mode) or fit (energy mode): w_k = exp(-2 s_k theta_k) with
+    // s_k = sign Re theta_k, qinv = 1 / prod (1 + w_k) over this lane's units, and for the units near a zero
+    // of cosh cq = -sum log(1 + w_k) (wave total) with log(1 + w_k) = log 2 - s_k theta_k + log cosh theta_k,
+    // theta_k in double
+    {
+        const float2* thp = A.cheb_mode ? thng : th1g;
+        const RbmView& vp = A.cheb_mode ? A.psn : A.fit;
+        uint32_t pw = 0;
+        float2 q1 = make_float2(1.f, 0.f), cl = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int k = e * kWave + lane;
-        if (A.cheb_mode) te[e] = (k < M) ? ctanhf(thng[s * M + k]) : make_float2(0.f, 0.f);
-        else te[e] = T1[e];
+        for (int e = 0; e < E; ++e) {
+            const int k = e * kWave + lane;
+            if (k >= M) continue;
+            const float2 z = thp[s * M + k];
+            const float sg = z.x >= 0.f ? 1.f : -1.f;
+            neg |= z.x >= 0.f ? 0u : 1u << e;
+            const float ex = expf(-2.f * fabsf(z.x));
+            const float2 cs = cos_sin(2.f * sg * z.y);
+            tw[e] = make_float2(ex * cs.x, -ex * cs.y);
+            if (near_pole(z)) pw |= 1u << e;
+            else q1 = cmul(q1, make_float2(1.f + tw[e].x, tw[e].y));   // |1 + w| in [0.58, 2] off the band
+        }
+        node = __ballot(pw != 0u) != 0ull;
+        if (lane == 0) g.node_flag[s] = node ? 1 : 0;
+        while (pw) {
+            const int e = __ffs(pw) - 1;
+            pw &= pw - 1;
+            const double2 td = theta_double(srow, N, M, e * kWave + lane, vp.b, vp.W);
+            float2 lcr, thr;
+            pole_eval(td, lcr, thr);
+            const float sg = ((neg >> e) & 1u) ? -1.f : 1.f;
+            cl = cadd(cl, make_float2(lcr.x + 0.69314718055994531f - sg * (float)td.x, lcr.y - sg * (float)td.y));
+        }
+        qinv = cdiv(make_float2(1.f, 0.f), q1);
+        cq = wave_sum(make_float2(-cl.x, -cl.y));
+        cq = make_float2(uniform(cq.x), uniform(cq.y));   // wave-uniform: scalar registers
     }
     // diagonal factor of t_0: f_q (momentum q) or, with local_op, the local S^z_0 = s_0 / 2
     if (with_fq) d0 = A.local_op ? make_float2(0.5f * (float)sp.get(0), 0.f) : fq_wave(sp, lane, g, A.q0, A.q1);
     // anti-aligned bonds of the sample
-    const int8_t* srow = A.samples + s * N;
     for (int c = 0; c < n_words; ++c) {
         const int bnd = c * kWave + lane;
         bool anti = false;
@@ -674,35 +772,127 @@ __device__ __forceinline__ void local_sample(const LocalArgs& A, const float2* _
     }
 }
 
-// One sample's local energy (J/4 s_i s_j over all bonds plus the exchange part in acc, already summed
-// over the lanes that hold it) and, in Chebyshev mode, R = phi / psi_{n+1}.
+// The exchange part of E_loc, sum over anti-aligned bonds of (J/2) d1 psi(s^ij)/psi(s), in double, for a
+// sample at which psi (the RBM whose Hamiltonian action is taken) is next to a node (a unit next to a zero
+// of cosh): there psi(s) ~ 0 while (H psi)(s) is of the size of E psi(s), so the bond terms are large and
+// cancel, which binary32 factors cannot resolve.  theta, every unit factor cosh(theta + Delta)/cosh theta,
+// a_i - a_j and f_q are taken in double.  Used by k_local_nodes only, so that the main kernels keep their
+// registers and need no stack.
 template <int E>
+__device__ __forceinline__ double2 exchange_double(const LocalArgs& A, const RbmView& pe, long s, int lane,
+                                                const uint64_t* mask, int n_words, bool with_fq) {
+    const Geometry& g = A.g;
+    const int N = g.N, M = g.M;
+    const int8_t* srow = A.samples + s * N;
+    double2 th[E], lc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = e * kWave + lane;
+        th[e] = k < M ? theta_double(srow, N, M, k, pe.b, pe.W) : make_double2(0.0, 0.0);
+        lc[e] = k < M ? log_cosh_double(th[e]) : make_double2(0.0, 0.0);
+    }
+    const double inv_sqrt_n = 1.0 / sqrt((double)N);
+    auto phase = [&](int r) {
+        const int x = g.kind == 0 ? r : r % g.Lx, y = g.kind == 0 ? 0 : r / g.Lx;
+        double sn, cs;
+        sincos(A.q0 * x + A.q1 * y, &sn, &cs);
+        return make_double2(cs, -sn);
+    };
+    double2 fq = make_double2(0.0, 0.0);
+    if (with_fq && !A.local_op) {
+        for (int r = lane; r < N; r += kWave) {
+            const double2 p = phase(r);
+            fq.x += 0.5 * srow[r] * p.x;
+            fq.y += 0.5 * srow[r] * p.y;
+        }
+        fq = wave_sum(fq);
+        fq = make_double2(fq.x * inv_sqrt_n, fq.y * inv_sqrt_n);
+    }
+    double2 acc = make_double2(0.0, 0.0);
+    for (int c = 0; c < n_words; ++c) {
+        uint64_t m = mask[c];
+        while (m) {
+            const int bnd = c * kWave + __builtin_ctzll(m);
+            m &= m - 1ull;
+            const int2 ij = g.bonds[bnd];
+            const double si = (double)srow[ij.x];
+            double2 d = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int k = e * kWave + lane;
+                if (k >= M) continue;
+                const float2 wi = pe.W[(long)ij.x * M + k], wj = pe.W[(long)ij.y * M + k];
+                const double2 z = make_double2(th[e].x - 2.0 * si * ((double)wi.x - (double)wj.x),
+                                               th[e].y - 2.0 * si * ((double)wi.y - (double)wj.y));
+                const double2 l2 = log_cosh_double(z);
+                d.x += l2.x - lc[e].x;
+                d.y += l2.y - lc[e].y;
+            }
+            d = wave_sum(d);
+            const float2 ai = pe.a[ij.x], aj = pe.a[ij.y];
+            d.x -= 2.0 * si * ((double)ai.x - (double)aj.x);
+            d.y -= 2.0 * si * ((double)ai.y - (double)aj.y);
+            const double mag = exp(d.x);
+            double sn, cs;
+            sincos(d.y, &sn, &cs);
+            double2 t = make_double2(0.5 * g.J * mag * cs, 0.5 * g.J * mag * sn);
+            if (with_fq) {
+                double2 d1;
+                if (A.local_op) {
+                    d1 = make_double2(ij.x == 0 ? -0.5 * si : (ij.y == 0 ? 0.5 * si : 0.5 * srow[0]), 0.0);
+                } else {
+                    const double2 pi_ = phase(ij.x), pj = phase(ij.y);
+                    d1 = make_double2(fq.x - inv_sqrt_n * si * (pi_.x - pj.x), fq.y - inv_sqrt_n * si * (pi_.y - pj.y));
+                }
+                t = zmul(d1, t);
+            }
+            acc = zadd(acc, t);
+        }
+    }
+    return acc;
+}
+
+// One sample's local energy (J/4 s_i s_j over all bonds plus the exchange part in acc, already summed
+// over the lanes that hold it, or formed in double at a node of psi) and, in Chebyshev mode, R = phi / psi_{n+1}.
+template <int E, bool NODE>
 __device__ __forceinline__ void local_finish(const LocalArgs& A, const float2* __restrict__ th1g,
                                              const float2* __restrict__ thng, const float2* __restrict__ thmg,
-                                             int lane, long s, float2 acc, float2 d0, int n_anti) {
+                                             int lane, long s, float2 acc, float2 d0, int n_anti,
+                                             const uint64_t* mask, int n_words) {
     const Geometry& g = A.g;
     const int N = g.N, M = g.M;
     const float J = (float)g.J;
-    const float2 eloc = cadd(wave_sum(acc), cscale(d0, 0.25f * J * (float)(g.n_bonds - 2 * n_anti)));
+    float2 exch;
+    if (NODE) {
+        const double2 x = exchange_double<E>(A, A.cheb_mode ? A.psn : A.fit, s, lane, mask, n_words,
+                                             A.cheb_mode && A.order == 0);
+        exch = make_float2((float)x.x, (float)x.y);
+    } else {
+        exch = wave_sum(acc);
+    }
+    const float2 eloc = cadd(exch, cscale(d0, 0.25f * J * (float)(g.n_bonds - 2 * n_anti)));
     if (A.eloc_out && lane == 0) A.eloc_out[s] = eloc;
     if (!A.cheb_mode || !A.R_out) return;
     WaveSpins sp;
     sp.load(A.samples + s * N, N, lane);
     const float2 asig1 = a_dot_sigma(A.fit.a, sp, lane, N);
     const float2 ht = cscale(csub(eloc, cmul(make_float2((float)A.E_c, 0.f), d0)), (float)(1.0 / A.W_scale));
-    float2 dn = cadd(csub(a_dot_sigma(A.psn.a, sp, lane, N), asig1), lc_diff<E>(thng, th1g, s, M, lane));
+    const int8_t* srow = A.samples + s * N;
+    float2 dn = cadd(csub(a_dot_sigma(A.psn.a, sp, lane, N), asig1),
+                     lc_diff<E>(thng, th1g, s, M, lane, A.psn, A.fit, srow, N));
     dn = wave_sum(dn);
-    const float2 bn = make_float2((float)A.beta_n.x, (float)A.beta_n.y);
+    // beta enters through its logarithm, added to the log-amplitude difference before the exponential, so
+    // that neither a small beta nor a large ratio of unnormalised states leaves the binary32 range on its own
     float2 R;
     if (A.order == 0) {
-        R = cmul(cmul(bn, ht), cexpf(dn));
+        R = cmul(ht, cexpf(cadd(dn, A.lbeta_n)));
     } else {
-        float2 dm = cadd(csub(a_dot_sigma(A.psm.a, sp, lane, N), asig1), lc_diff<E>(thmg, th1g, s, M, lane));
+        float2 dm = cadd(csub(a_dot_sigma(A.psm.a, sp, lane, N), asig1),
+                         lc_diff<E>(thmg, th1g, s, M, lane, A.psm, A.fit, srow, N));
         dm = wave_sum(dm);
         const float2 fm = (A.order != 1) ? make_float2(1.f, 0.f)
                         : A.local_op ? make_float2(0.5f * (float)sp.get(0), 0.f) : fq_wave(sp, lane, g, A.q0, A.q1);
-        const float2 bm = make_float2((float)A.beta_nm1.x, (float)A.beta_nm1.y);
-        R = csub(cscale(cmul(cmul(bn, ht), cexpf(dn)), 2.f), cmul(cmul(bm, fm), cexpf(dm)));
+        R = csub(cscale(cmul(ht, cexpf(cadd(dn, A.lbeta_n))), 2.f), cmul(fm, cexpf(cadd(dm, A.lbeta_nm1))));
     }
     if (lane == 0) A.R_out[s] = R;
 }
@@ -730,14 +920,25 @@ __global__ __launch_bounds__(256, E <= 7 ? 3 : 2) void k_local(LocalArgs A, cons
     const RbmView& pe = A.cheb_mode ? A.psn : A.fit;
     const int n_words = (g.n_bonds + 63) / 64;
 
-    float2 TE[SPW][E];
+    float2 TW[SPW][E];
+    uint32_t NEG[SPW];
+    float2 QI[SPW], CQ[SPW];
+    bool NODE[SPW];
     float2 d0[SPW];
     int n_anti[SPW];
     static_assert(SPW == 4, "the per-sample calls below are written out for 4 samples");
-    local_sample<E>(A, th1g, thng, lane, s0, 0, nq, want_local, with_fq, n_words, TE[0], d0[0], n_anti[0], s_mask[wv][0]);
-    local_sample<E>(A, th1g, thng, lane, s0, 1, nq, want_local, with_fq, n_words, TE[1], d0[1], n_anti[1], s_mask[wv][1]);
-    local_sample<E>(A, th1g, thng, lane, s0, 2, nq, want_local, with_fq, n_words, TE[2], d0[2], n_anti[2], s_mask[wv][2]);
-    local_sample<E>(A, th1g, thng, lane, s0, 3, nq, want_local, with_fq, n_words, TE[3], d0[3], n_anti[3], s_mask[wv][3]);
+    local_sample<E>(A, th1g, thng, lane, s0, 0, nq, want_local, with_fq, n_words, TW[0], NEG[0], QI[0], CQ[0], d0[0],
+                    n_anti[0], NODE[0],
+                    s_mask[wv][0]);
+    local_sample<E>(A, th1g, thng, lane, s0, 1, nq, want_local, with_fq, n_words, TW[1], NEG[1], QI[1], CQ[1], d0[1],
+                    n_anti[1], NODE[1],
+                    s_mask[wv][1]);
+    local_sample<E>(A, th1g, thng, lane, s0, 2, nq, want_local, with_fq, n_words, TW[2], NEG[2], QI[2], CQ[2], d0[2],
+                    n_anti[2], NODE[2],
+                    s_mask[wv][2]);
+    local_sample<E>(A, th1g, thng, lane, s0, 3, nq, want_local, with_fq, n_words, TW[3], NEG[3], QI[3], CQ[3], d0[3],
+                    n_anti[3], NODE[3],
+                    s_mask[wv][3]);
     if (!want_local) return;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -765,7 +966,8 @@ __global__ __launch_bounds__(256, E <= 7 ? 3 : 2) void k_local(LocalArgs A, cons
 #pragma unroll
             for (int q = 0; q < SPW; ++q) {
                 if (!((mk[q] >> bit) & 1ull)) continue;
-                const float2 prod = bond_share<E>(tq, TE[q], -(float)A.samples[(s0 + q) * N + i]);
+                const float2 prod =
+                    bond_share<E>(tq, TW[q], bond_neg(NEG[q], (float)A.samples[(s0 + q) * N + i]), QI[q]);
                 const int slot = pushed & (kRing - 1);
                 float lmv;
                 float2 phv;
@@ -776,7 +978,7 @@ __global__ __launch_bounds__(256, E <= 7 ? 3 : 2) void k_local(LocalArgs A, cons
                 ++pushed;
             }
             if (pushed - done >= 8) {
-                local_flush<SPW>(A, pe, lane, s0, done, 8, with_fq, inv_sqrt_n, d0, acc, s_lm[wv], s_ph[wv],
+                local_flush<SPW>(A, pe, lane, s0, done, 8, with_fq, inv_sqrt_n, d0, CQ, acc, s_lm[wv], s_ph[wv],
                                  s_item[wv]);
                 done += 8;
             }
@@ -784,15 +986,15 @@ __global__ __launch_bounds__(256, E <= 7 ? 3 : 2) void k_local(LocalArgs A, cons
     }
     while (done < pushed) {
         const int cnt = pushed - done < 8 ? pushed - done : 8;
-        local_flush<SPW>(A, pe, lane, s0, done, cnt, with_fq, inv_sqrt_n, d0, acc, s_lm[wv], s_ph[wv],
+        local_flush<SPW>(A, pe, lane, s0, done, cnt, with_fq, inv_sqrt_n, d0, CQ, acc, s_lm[wv], s_ph[wv],
                          s_item[wv]);
         done += cnt;
     }
 
-    local_finish<E>(A, th1g, thng, thmg, lane, s0, acc[0], d0[0], n_anti[0]);
-    if (nq > 1) local_finish<E>(A, th1g, thng, thmg, lane, s0 + 1, acc[1], d0[1], n_anti[1]);
-    if (nq > 2) local_finish<E>(A, th1g, thng, thmg, lane, s0 + 2, acc[2], d0[2], n_anti[2]);
-    if (nq > 3) local_finish<E>(A, th1g, thng, thmg, lane, s0 + 3, acc[3], d0[3], n_anti[3]);
+    local_finish<E, false>(A, th1g, thng, thmg, lane, s0, acc[0], d0[0], n_anti[0], s_mask[wv][0], n_words);
+    if (nq > 1) local_finish<E, false>(A, th1g, thng, thmg, lane, s0 + 1, acc[1], d0[1], n_anti[1], s_mask[wv][1], n_words);
+    if (nq > 2) local_finish<E, false>(A, th1g, thng, thmg, lane, s0 + 2, acc[2], d0[2], n_anti[2], s_mask[wv][2], n_words);
+    if (nq > 3) local_finish<E, false>(A, th1g, thng, thmg, lane, s0 + 3, acc[3], d0[3], n_anti[3], s_mask[wv][3], n_words);
 }
 
 // Narrow RBMs (M <= 3 x 64): one sample per wave.  With few hidden units per lane the bookkeeping of
@@ -812,10 +1014,14 @@ __global__ __launch_bounds__(256, 5) void k_local_one(LocalArgs A, const float2*
     const bool with_fq = A.cheb_mode && A.order == 0;
     const RbmView& pe = A.cheb_mode ? A.psn : A.fit;
     const int n_words = (g.n_bonds + 63) / 64;
-    float2 TE[E];
+    float2 TW[E];
+    uint32_t neg;
+    float2 qinv, cq;
     float2 d0;
     int n_anti;
-    local_sample<E>(A, th1g, thng, lane, s, 0, 1, want_local, with_fq, n_words, TE, d0, n_anti, s_mask[wv]);
+    bool node;
+    local_sample<E>(A, th1g, thng, lane, s, 0, 1, want_local, with_fq, n_words, TW, neg, qinv, cq, d0, n_anti, node,
+                    s_mask[wv]);
     if (!want_local) return;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -843,7 +1049,7 @@ __global__ __launch_bounds__(256, 5) void k_local_one(LocalArgs A, const float2*
                 const int bnd = uniform((int)lst[b0 + b]);
                 float4 tq[E];
                 bond_row<E>(g, bnd, lane, tq);
-                const float2 prod = bond_share<E>(tq, TE, -(float)srow[uniform(g.bonds[bnd].x)]);
+                const float2 prod = bond_share<E>(tq, TW, bond_neg(neg, (float)srow[uniform(g.bonds[bnd].x)]), qinv);
                 share_polar(prod, prod.x * prod.x + prod.y * prod.y, lm[b], ph[b]);
             }
         }
@@ -851,13 +1057,51 @@ __global__ __launch_bounds__(256, 5) void k_local_one(LocalArgs A, const float2*
         const int bb = b0 + (lane >> 3);
         if (bb < n_anti) {
             const int2 ij = g.bonds[lst[bb]];
-            const float2 c = bond_term(A, pe, ij.x, ij.y, (float)srow[ij.x], lm[0], ph[0], d0, with_fq, inv_sqrt_n);
+            const float2 c = bond_term(A, pe, ij.x, ij.y, (float)srow[ij.x], lm[0], ph[0], d0, cq, with_fq, inv_sqrt_n);
             if ((lane & 7) == 0) acc = cadd(acc, c);
         }
     }
-    local_finish<E>(A, th1g, thng, thmg, lane, s, acc, d0, n_anti);
+    local_finish<E, false>(A, th1g, thng, thmg, lane, s, acc, d0, n_anti, s_mask[wv], n_words);
 }
 
+// Samples at which the local-energy RBM is next to a node (flagged by k_local / k_local_one): E_loc with
+// the exchange sum in double (exchange_double) and, in Chebyshev mode, R, overwriting the binary32 values
+// of the main kernel.  One wave per sample; unflagged samples return at once.
+template <int E>
+__global__ __launch_bounds__(256) void k_local_nodes(LocalArgs A, const float2* __restrict__ th1g,
+                                                     const float2* __restrict__ thng, const float2* __restrict__ thmg) {
+    __shared__ uint64_t s_mask[4][kMaxBonds / 64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const long s = (long)blockIdx.x * 4 + wv;
+    if (s >= A.n_samples) return;
+    const Geometry& g = A.g;
+    if (!g.node_flag[s]) return;
+    const int8_t* srow = A.samples + s * g.N;
+    const int n_words = (g.n_bonds + 63) / 64;
+    int n_anti = 0;
+    for (int c = 0; c < n_words; ++c) {
+        const int bnd = c * kWave + lane;
+        bool anti = false;
+        if (bnd < g.n_bonds) {
+            const int2 ij = g.bonds[bnd];
+            anti = srow[ij.x] != srow[ij.y];
+        }
+        const uint64_t m = __ballot(anti);
+        if (lane == 0) s_mask[wv][c] = m;
+        n_anti += __popcll(m);
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float2 d0 = make_float2(1.f, 0.f);
+    if (A.cheb_mode && A.order == 0) {
+        WaveSpins sp;
+        sp.load(srow, g.N, lane);
+        d0 = A.local_op ? make_float2(0.5f * (float)sp.get(0), 0.f) : fq_wave(sp, lane, g, A.q0, A.q1);
+    }
+    local_finish<E, true>(A, th1g, thng, thmg, lane, s, make_float2(0.f, 0.f), d0, n_anti, s_mask[wv], n_words);
+}
+
+// (exp 2D, exp -2D) per bond and hidden unit, D = W_i - W_j, from the binary32 weights in double
 __global__ __launch_bounds__(256) void k_bond_table(const int2* __restrict__ bonds, int nb, int M,
                                                     const float2* __restrict__ W, float4* __restrict__ tab) {
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
@@ -866,10 +1110,10 @@ __global__ __launch_bounds__(256) void k_bond_table(const int2* __restrict__ bon
     const int2 ij = bonds[b];
     const float2 wi = W[(long)ij.x * M + k], wj = W[(long)ij.y * M + k];
     const double x = 2.0 * ((double)wi.x - (double)wj.x), y = 2.0 * ((double)wi.y - (double)wj.y);
-    const double ch = cosh(x), sh = sinh(x);
+    const double ep = exp(x), em = exp(-x);
     double sn, cs;
     sincos(y, &sn, &cs);
-    tab[idx] = make_float4((float)(ch * cs), (float)(sh * sn), (float)(sh * cs), (float)(ch * sn));
+    tab[idx] = make_float4((float)(ep * cs), (float)(ep * sn), (float)(em * cs), (float)(-em * sn));
 }
 
 hipError_t launch_local_core(const LocalArgs& A, const float2* th1, const float2* thn, const float2* thm,
@@ -893,6 +1137,15 @@ hipError_t launch_local_core(const LocalArgs& A, const float2* th1, const float2
 #undef CRBM_ONE
 #undef CRBM_BM
         default: return hipErrorInvalidValue;
+    }
+    if (A.eloc_out || A.R_out) {
+        switch (E) {
+#define CRBM_NODES(e) case e: hipLaunchKernelGGL(k_local_nodes<e>, grid1, block, 0, stream, A, th1, thn, thm); break;
+            CRBM_NODES(1) CRBM_NODES(2) CRBM_NODES(3) CRBM_NODES(4) CRBM_NODES(5) CRBM_NODES(6) CRBM_NODES(7)
+            CRBM_NODES(8)
+#undef CRBM_NODES
+            default: return hipErrorInvalidValue;
+        }
     }
     return hipGetLastError();
 }

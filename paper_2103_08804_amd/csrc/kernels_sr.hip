@@ -11,6 +11,8 @@
 // Partial sums run in FP32 over a chunk of samples and in FP64 across chunks.
 #include <float.h>
 
+#include <algorithm>
+
 #include "../../include/chebrbm.h"
 #include "device.hpp"
 #include "internal.hpp"
@@ -18,10 +20,11 @@
 namespace crbm {
 
 
-// device scalar slots (SC_RR and SC_RR1 hold r^H r of the even and odd CG iterations; 11 is spare)
+// device scalar slots (SC_RR and SC_RR1 hold r^H r of the even and odd CG iterations; SC_WSUM the sum of the
+// sample weights)
 enum {
     SC_RM_RE = 0, SC_RM_IM, SC_R2, SC_GAMMA, SC_GCOT, SC_COEF,
-    SC_RR = 8, SC_PAP, SC_RR1, SC_SPARE, SC_FF, SC_DONE, SC_ITERS, SC_FLAGS, SC_RESID, SC_XX,
+    SC_RR = 8, SC_PAP, SC_RR1, SC_WSUM, SC_FF, SC_DONE, SC_ITERS, SC_FLAGS, SC_RESID, SC_XX,
     SC_COUNT = 32
 };
 
@@ -38,26 +41,26 @@ __device__ __forceinline__ long ij_to_p(int i, int j, int N, int M) {
 }
 
 // ------------------------------------------------------------------ scalar reductions
-// red[blk] = (sum w R, sum w |R|^2)
+// red[2 blk] = (sum w Re R, sum w Im R), red[2 blk + 1] = (sum w |R|^2, sum w)
 __global__ __launch_bounds__(256) void k_r_moments(const float2* __restrict__ R, const double* __restrict__ w, long n,
                                                    double2* __restrict__ red) {
-    __shared__ double sh[3][4];
-    double rx = 0, ry = 0, r2 = 0;
+    __shared__ double sh[4][4];
+    double rx = 0, ry = 0, r2 = 0, ws_sum = 0;
     const double wdef = 1.0 / (double)n;
     for (long s = (long)blockIdx.x * 256 + threadIdx.x; s < n; s += (long)gridDim.x * 256) {
         const double ws = w ? w[s] : wdef;
         const double x = R[s].x, y = R[s].y;
-        rx += ws * x; ry += ws * y; r2 += ws * (x * x + y * y);
+        rx += ws * x; ry += ws * y; r2 += ws * (x * x + y * y); ws_sum += ws;
     }
-    rx = wave_sum(rx); ry = wave_sum(ry); r2 = wave_sum(r2);
+    rx = wave_sum(rx); ry = wave_sum(ry); r2 = wave_sum(r2); ws_sum = wave_sum(ws_sum);
     const int wv = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { sh[0][wv] = rx; sh[1][wv] = ry; sh[2][wv] = r2; }
+    if ((threadIdx.x & 63) == 0) { sh[0][wv] = rx; sh[1][wv] = ry; sh[2][wv] = r2; sh[3][wv] = ws_sum; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a = 0, b = 0, c = 0;
-        for (int k = 0; k < 4; ++k) { a += sh[0][k]; b += sh[1][k]; c += sh[2][k]; }
+        double a = 0, b = 0, c = 0, d = 0;
+        for (int k = 0; k < 4; ++k) { a += sh[0][k]; b += sh[1][k]; c += sh[2][k]; d += sh[3][k]; }
         red[2 * blockIdx.x] = make_double2(a, b);
-        red[2 * blockIdx.x + 1] = make_double2(c, 0.0);
+        red[2 * blockIdx.x + 1] = make_double2(c, d);
     }
 }
 
@@ -67,10 +70,13 @@ __global__ __launch_bounds__(256) void k_r_moments(const float2* __restrict__ R,
 __global__ void k_r_final(const double2* __restrict__ red, int n_blocks, double dgamma, int mode,
                           double* __restrict__ sc) {
     if (threadIdx.x != 0) return;
-    double a = 0, b = 0, c = 0;
-    for (int k = 0; k < n_blocks; ++k) { a += red[2 * k].x; b += red[2 * k].y; c += red[2 * k + 1].x; }
+    double a = 0, b = 0, c = 0, d = 0;
+    for (int k = 0; k < n_blocks; ++k) {
+        a += red[2 * k].x; b += red[2 * k].y; c += red[2 * k + 1].x; d += red[2 * k + 1].y;
+    }
     sc[SC_RM_RE] = a; sc[SC_RM_IM] = b; sc[SC_R2] = c;
     for (int k = SC_RR; k < SC_COUNT; ++k) sc[k] = 0.0;
+    sc[SC_WSUM] = d;
     if (mode == 1) {
         sc[SC_GAMMA] = c - (a * a + b * b);
         sc[SC_GCOT] = 1.0;
@@ -85,6 +91,76 @@ __global__ void k_r_final(const double2* __restrict__ red, int n_blocks, double 
     if (!(c > 0.0) || !isfinite(a) || !isfinite(b) || !isfinite(c)) sc[SC_FLAGS] = CRBM_FLAG_NONFINITE;
 }
 
+// gamma and beta = <R> of the fit as it stands (Sec. III: beta is taken once the steps are done):
+// out = {gamma, Re <R>, Im <R>, <|R|^2>, flags}
+__global__ void k_fit_stats(const double2* __restrict__ red, int n_blocks, double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double a = 0, b = 0, c = 0;
+    for (int k = 0; k < n_blocks; ++k) { a += red[2 * k].x; b += red[2 * k].y; c += red[2 * k + 1].x; }
+    const double gamma = acos(fmin(1.0, sqrt((a * a + b * b) / c)));
+    out[0] = gamma;
+    out[1] = a;
+    out[2] = b;
+    out[3] = c;
+    out[4] = (!(c > 0.0) || !isfinite(a) || !isfinite(b) || !isfinite(c)) ? (double)CRBM_FLAG_NONFINITE : 0.0;
+}
+
+// Exact-enumeration weights p(s) = |psi_s|^2 / sum_s' |psi_s'|^2 = exp(2 Re log psi_s - LSE) (the sampling
+// distribution of Sec. III with every configuration listed once).  Pass 1: per block the largest
+// 2 Re log psi and the sum of exp(2 Re log psi - that largest value).  Pass 2: every block merges the
+// partials in block order (the same result in every block) and writes its share of the weights.
+constexpr int kLseBlocks = kLseParts;
+__global__ __launch_bounds__(256) void k_lse_partial(const float2* __restrict__ lp, long n, double2* __restrict__ part) {
+    __shared__ double sh[4];
+    double mx = -INFINITY;
+    for (long s = (long)blockIdx.x * 256 + threadIdx.x; s < n; s += (long)gridDim.x * 256)
+        mx = fmax(mx, 2.0 * (double)lp[s].x);
+    for (int o = 32; o >= 1; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, kWave));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    mx = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    double acc = 0.0;
+    if (mx > -INFINITY)
+        for (long s = (long)blockIdx.x * 256 + threadIdx.x; s < n; s += (long)gridDim.x * 256)
+            acc += exp(2.0 * (double)lp[s].x - mx);
+    acc = wave_sum(acc);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double2(mx, sh[0] + sh[1] + sh[2] + sh[3]);
+}
+__global__ __launch_bounds__(256) void k_lse_weights(const float2* __restrict__ lp, long n,
+                                                     const double2* __restrict__ part, int n_part,
+                                                     double* __restrict__ w) {
+    __shared__ double lse;
+    if (threadIdx.x == 0) {
+        double mx = -INFINITY;
+        for (int k = 0; k < n_part; ++k) mx = fmax(mx, part[k].x);
+        double z = 0.0;
+        for (int k = 0; k < n_part; ++k)
+            if (part[k].x > -INFINITY) z += part[k].y * exp(part[k].x - mx);
+        lse = mx + log(z);   // NaN or infinite when no amplitude is finite and non-zero
+    }
+    __syncthreads();
+    const double L = lse;
+    for (long s = (long)blockIdx.x * 256 + threadIdx.x; s < n; s += (long)gridDim.x * 256)
+        w[s] = exp(2.0 * (double)lp[s].x - L);
+}
+
+hipError_t launch_fit_stats(const float2* R, const double* w, long n, double2* red, double* out, hipStream_t stream) {
+    const int nb = 256;
+    hipLaunchKernelGGL(k_r_moments, dim3(nb), dim3(256), 0, stream, R, w, n, red);
+    hipLaunchKernelGGL(k_fit_stats, dim3(1), dim3(64), 0, stream, red, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_enum_weights(const float2* lp, long n, double2* part, double* w, hipStream_t stream) {
+    hipLaunchKernelGGL(k_lse_partial, dim3(kLseBlocks), dim3(256), 0, stream, lp, n, part);
+    const unsigned nb = (unsigned)std::min<long>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_lse_weights, dim3(nb), dim3(256), 0, stream, lp, n, part, kLseBlocks, w);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ O^H c contraction
 // out_c[i][j] = sum_s sigma~_i(s) y_c(s, j) with y_c(s, j) = c_c(s) conj(t~_j(s)), sigma~_N = 1 and
 // t~_M = 1: per coefficient a real (N+1) x n by n x (M+1) complex product (rows i < N are the a
@@ -97,7 +173,9 @@ __global__ void k_r_final(const double2* __restrict__ red, int n_blocks, double 
 // CU and one's staging overlaps another's products.  The tile after the current one is loaded into
 // registers while the products run.  Chunk sums are written in FP32 and added across chunks in FP64.
 // coef kinds: 0 -> c = w; 1 -> c = w R; 2 -> c = w u (u double2 [n]);
-//             3 -> c = 2 (1 - R) conj(R) / n
+//             3 -> c = 2 (1 - R) conj(R) / n; 4 -> c = w (R - u[0]) (u pointing at <R>: the centred
+//             ratio, whose contraction <O^* (R - <R>)> = <O^* R> - <O^*><R> carries no cancellation of
+//             the mean of O)
 constexpr int OM_R = 128, OM_C = 32, OM_S = 32;
 
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
@@ -116,6 +194,7 @@ __device__ __forceinline__ float2 coef_of(int kind, long s, const double* w, dou
         case 0: return make_float2(ws, 0.f);
         case 1: return cscale(R[s], ws);
         case 2: return make_float2((float)(u[s].x) * ws, (float)(u[s].y) * ws);
+        case 4: return cscale(csub(R[s], make_float2((float)u[0].x, (float)u[0].y)), ws);
         default: {
             const float2 r = R[s];
             const float2 d = cmul(make_float2(1.f - r.x, -r.y), cconj(r));
@@ -365,8 +444,9 @@ static void pack_sig16(const int8_t* sig, long n, int N, int8_t* out, hipStream_
                        sig16_row(N), out);
 }
 
-// Fit mode (0):    F_k = coef [ORm_k / <R> - conj(Om_k)];
-// energy mode (1): F_k = coef [ORm_k - conj(Om_k) <E>]   (ORm = <O^* E_loc>, coef = -lr).
+// ORc = <O^* (R - <R>)> = <O^* R> - <O^*><R>  (R = E_loc in energy mode):
+// fit mode (0):    F_k = coef [<O_k^* R>/<R> - <O_k^*>] = coef ORc_k / <R>;
+// energy mode (1): F_k = coef [<O_k^* E> - <O_k^*><E>] = coef ORc_k   (coef = -lr).
 // Om holds conj(<O>) on entry and <O> on exit.
 __global__ void k_make_f(long P, int mode, double2* __restrict__ Om, const double2* __restrict__ ORm,
                          const double* __restrict__ sc, double2* __restrict__ F) {
@@ -375,24 +455,55 @@ __global__ void k_make_f(long P, int mode, double2* __restrict__ Om, const doubl
     const double2 rm = make_double2(sc[SC_RM_RE], sc[SC_RM_IM]);
     const double coef = sc[SC_COEF];
     const double2 omc = Om[k];
-    if (mode == 1) {
-        const double2 d = zsub(ORm[k], zmul(omc, rm));
-        F[k] = make_double2(coef * d.x, coef * d.y);
-    } else {
-        const double2 q = zdiv(ORm[k], rm);
-        F[k] = make_double2(coef * (q.x - omc.x), coef * (q.y - omc.y));
-    }
+    const double2 d = mode == 1 ? ORm[k] : zdiv(ORm[k], rm);
+    F[k] = make_double2(coef * d.x, coef * d.y);
     Om[k] = make_double2(omc.x, -omc.y);
 }
 
+// ------------------------------------------------------------------ weighted P-vector contractions in double
+// With sample weights (exact enumeration: every configuration once, weighted by |psi|^2 / Z) the weights span
+// many orders of magnitude and the configurations next to nodes of the state carry O_k of the same size
+// inverted, so the sums over samples run in double here: Om_k = sum_s w_s conj(O_sk) and
+// ORc_k = sum_s w_s conj(O_sk) (R_s - <R>).  One thread per parameter; threads of one site row read
+// consecutive hidden units of T.
+__global__ __launch_bounds__(256) void k_ot64(int N, int M, long P, const int8_t* __restrict__ sig,
+                                              const float2* __restrict__ T, const double* __restrict__ w,
+                                              const float2* __restrict__ R, long n, const double* __restrict__ sc,
+                                              double2* __restrict__ Om, double2* __restrict__ ORc) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P) return;
+    int i, j;
+    p_to_ij(k, N, M, i, j);
+    const double rx = sc[SC_RM_RE], ry = sc[SC_RM_IM];
+    double ox = 0, oy = 0, qx = 0, qy = 0;
+    for (long s = 0; s < n; ++s) {
+        const double ws = w[s];
+        const double sv = (i == N) ? 1.0 : (double)sig[s * N + i];
+        double tx = 1.0, ty = 0.0;
+        if (j < M) { const float2 t = T[s * M + j]; tx = t.x; ty = t.y; }
+        const double cx = ws * sv * tx, cy = -ws * sv * ty;          // w conj(O)
+        const double dx = (double)R[s].x - rx, dy = (double)R[s].y - ry;
+        ox += cx; oy += cy;
+        qx += cx * dx - cy * dy; qy += cx * dy + cy * dx;
+    }
+    Om[k] = make_double2(ox, oy);
+    ORc[k] = make_double2(qx, qy);
+}
+
 // ------------------------------------------------------------------ dense S (FP32, VALU)
-// Upper-triangle tiles (I <= J) of 64 x 64; S[k][k'] = sum_s w conj(O_sk) O_sk' - conj(Om_k) Om_k',
-// mirrored into the lower triangle so that S is stored in full.
+// Upper-triangle tiles (I <= J) of 64 x 64, mirrored into the lower triangle so that S is stored in full:
+//   S[k][k'] = sum_s w conj(O_sk - m_k) (O_sk' - m_k') + (1 - sum_s w) conj(m_k) m_k',  m = <O>,
+// which is <O^* O> - <O>^* <O> (Sec. III) with the operands centred before the sums: where |<O_k>|^2 is
+// large against the variance (tanh theta near +-1), raw sums less the product of the means would lose that
+// ratio's digits.  Binary32 operands, products and sums in double (the weighted sums serve exact enumeration
+// with a dense solve, where a few configurations next to nodes of the state can make |S| large against the
+// diagonal shift); S is written in binary32 and, for the Cholesky solve, also in double (S64).
 constexpr int SB_T = 64, SB_K = 16;
 
 __global__ __launch_bounds__(256) void k_sbuild(int N, int M, long P, const int8_t* __restrict__ sig,
                                                 const float2* __restrict__ T, const double* __restrict__ w, long n,
-                                                const double2* __restrict__ Om, float2* __restrict__ S, int ntile) {
+                                                const double2* __restrict__ Om, float2* __restrict__ S, int ntile,
+                                                const double* __restrict__ sc, double2* __restrict__ S64) {
     __shared__ float2 sa[SB_K][SB_T];
     __shared__ float2 sb[SB_K][SB_T];
     // map blockIdx.x -> (I, J), I <= J
@@ -408,12 +519,14 @@ __global__ __launch_bounds__(256) void k_sbuild(int N, int M, long P, const int8
     const bool va = kA0 + lc < P, vb = kB0 + lc < P;
     p_to_ij(va ? kA0 + lc : 0, N, M, ia, ja);
     p_to_ij(vb ? kB0 + lc : 0, N, M, ib, jb);
+    const double2 mA = va ? Om[kA0 + lc] : make_double2(0.0, 0.0), mB = vb ? Om[kB0 + lc] : make_double2(0.0, 0.0);
+    const float2 mAf = make_float2((float)mA.x, (float)mA.y), mBf = make_float2((float)mB.x, (float)mB.y);
     const double wdef = 1.0 / (double)n;
-    float2 acc[4][4];
+    double2 acc[4][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = make_float2(0.f, 0.f);
+        for (int c = 0; c < 4; ++c) acc[r][c] = make_double2(0.0, 0.0);
 
     for (long s0 = 0; s0 < n; s0 += SB_K) {
 #pragma unroll
@@ -426,12 +539,12 @@ __global__ __launch_bounds__(256) void k_sbuild(int N, int M, long P, const int8
                 if (va) {
                     const float sv = (ia == N) ? 1.f : (float)sig[s * N + ia];
                     const float2 tv = (ja == M) ? make_float2(1.f, 0.f) : T[s * M + ja];
-                    oa = cscale(cconj(tv), sv * ws);
+                    oa = cscale(cconj(csub(cscale(tv, sv), mAf)), ws);
                 }
                 if (vb) {
                     const float sv = (ib == N) ? 1.f : (float)sig[s * N + ib];
                     const float2 tv = (jb == M) ? make_float2(1.f, 0.f) : T[s * M + jb];
-                    ob = cscale(tv, sv);
+                    ob = csub(cscale(tv, sv), mBf);
                 }
             }
             sa[ss][lc] = oa;
@@ -449,8 +562,9 @@ __global__ __launch_bounds__(256) void k_sbuild(int N, int M, long P, const int8
             for (int r = 0; r < 4; ++r)
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    acc[r][c].x = fmaf(av[r].x, bv[c].x, fmaf(-av[r].y, bv[c].y, acc[r][c].x));
-                    acc[r][c].y = fmaf(av[r].x, bv[c].y, fmaf(av[r].y, bv[c].x, acc[r][c].y));
+                    const double ax = av[r].x, ay = av[r].y, bx = bv[c].x, by = bv[c].y;
+                    acc[r][c].x = fma(ax, bx, fma(-ay, by, acc[r][c].x));
+                    acc[r][c].y = fma(ax, by, fma(ay, bx, acc[r][c].y));
                 }
         }
         __syncthreads();
@@ -466,9 +580,15 @@ __global__ __launch_bounds__(256) void k_sbuild(int N, int M, long P, const int8
             if (kp >= P) continue;
             const double2 omkp = Om[kp];
             const double2 mm = zconjmul(omk, omkp);
-            const float2 v = make_float2((float)((double)acc[r][c].x - mm.x), (float)((double)acc[r][c].y - mm.y));
+            const double rest = 1.0 - sc[SC_WSUM];
+            const double2 d = make_double2(acc[r][c].x + rest * mm.x, acc[r][c].y + rest * mm.y);
+            const float2 v = make_float2((float)d.x, (float)d.y);
             S[k * P + kp] = v;
             if (I != J) S[kp * P + k] = cconj(v);
+            if (S64) {
+                S64[k * P + kp] = d;
+                if (I != J) S64[kp * P + k] = make_double2(d.x, -d.y);
+            }
         }
     }
 }
@@ -801,7 +921,7 @@ __global__ void k_stats(const double* __restrict__ sc, double* __restrict__ out)
 static inline unsigned nblk(long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 hipError_t launch_cholesky_solve(long P, const float2* S, double eps, const double2* F, double2* A64, double2* x,
-                                 double* sc, hipStream_t stream);
+                                 double* sc, bool a64_holds_s, hipStream_t stream);
 hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n, const double2* Om,
                               float2* S, int prec, void* pack, size_t pack_bytes, const int2* order, long n_order,
                               float2* split_buf, int nsplit, Profiler* prof, hipStream_t stream);
@@ -844,10 +964,19 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
     const int nb_r = 256;
     hipLaunchKernelGGL(k_r_moments, dim3(nb_r), dim3(256), 0, stream, A.R, A.weights, A.n, W.red);
     hipLaunchKernelGGL(k_r_final, dim3(1), dim3(64), 0, stream, W.red, nb_r, A.dgamma, A.mode, W.scal);
-    // conj(<O>) and <O^* R>
+    // conj(<O>) and <O^* (R - <R>)>: FP32 chunk sums on the matrix cores, or in double with sample weights
     pack_sig16(A.samples, A.n, A.N, W.sig16, stream);
-    e = run_ot(A.N, A.M, W.sig16, A.T, A.n, 0, 1, 2, A.weights, A.R, nullptr, W.red, 0, W.Om, W.ORm, stream, nullptr,
-               W.prof, W.n_cu);
+    if (A.weights) {
+        W.prof->begin(PROF_OT, stream);
+        hipLaunchKernelGGL(k_ot64, dim3(nblk(P)), dim3(256), 0, stream, A.N, A.M, P, A.samples, A.T, A.weights, A.R,
+                           A.n, W.scal, W.Om, W.ORm);
+        W.prof->end(stream);
+        e = hipGetLastError();
+    } else {
+        e = run_ot(A.N, A.M, W.sig16, A.T, A.n, 0, 4, 2, A.weights, A.R,
+                   reinterpret_cast<const double2*>(W.scal + SC_RM_RE), W.red, 0, W.Om, W.ORm, stream, nullptr, W.prof,
+                   W.n_cu);
+    }
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_make_f, dim3(nblk(P)), dim3(256), 0, stream, P, A.mode, W.Om, W.ORm, W.scal, W.F);
     hipLaunchKernelGGL(k_zdot, dim3(64), dim3(256), 0, stream, P, W.F, W.F, W.red, W.scal, 0);
@@ -873,7 +1002,8 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
             const long ntri = (long)nt * (nt + 1) / 2;
             W.prof->begin(PROF_SBUILD, stream);
             hipLaunchKernelGGL(k_sbuild, dim3((unsigned)ntri), dim3(256), 0, stream, A.N, A.M, P, A.samples, A.T,
-                               A.weights, A.n, W.Om, W.S, nt);
+                               A.weights, A.n, W.Om, W.S, nt, W.scal,
+                               A.solver == CRBM_SOLVER_CHOLESKY ? W.S64 : nullptr);
             W.prof->end(stream);
             e = hipGetLastError();
         }
@@ -882,7 +1012,7 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
 
     if (A.solver == CRBM_SOLVER_CHOLESKY) {
         W.prof->begin(PROF_CHOLESKY, stream);
-        e = launch_cholesky_solve(P, W.S, A.eps, W.F, W.S64, W.x, W.scal, stream);
+        e = launch_cholesky_solve(P, W.S, A.eps, W.F, W.S64, W.x, W.scal, A.weights != nullptr, stream);
         W.prof->end(stream);
         if (e != hipSuccess) return e;
         // residual of the double solve against the FP32-stored S

@@ -89,6 +89,12 @@ def random_spins(seed, n, N, zero_magnetisation=False):
     return np.stack([r.permutation(base) for _ in range(n)]).astype(np.int8)
 
 
+def all_configs(N):
+    """int8 [2^N][N]: configuration s has sigma_i = +1 iff bit i of s is set (every configuration once)."""
+    s = np.arange(1 << N, dtype=np.int64)[:, None]
+    return (2 * ((s >> np.arange(N)) & 1) - 1).astype(np.int8)
+
+
 def bz_path(n_points):
     """n_points momenta equally spaced in arc length along Gamma(0,0) -> X(pi,0) -> M(pi,pi) -> Gamma."""
     corners = np.array([[0.0, 0.0], [math.pi, 0.0], [math.pi, math.pi], [0.0, 0.0]])
