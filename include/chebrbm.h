@@ -280,6 +280,18 @@ int crbm_chebyshev_moment(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_
 int crbm_fidelity_grad(crbm_plan plan, const crbm_rbm* fit, const int8_t* samples, const void* tanh_theta,
                        const void* R, long n_samples, void* grad_out, double* loss_out, hipStream_t stream);
 
+/* crbm_fidelity_grad without a plan and without any allocation, for callers that cannot allocate device
+ * memory (code under graph capture, tight serving or training loops, harnesses that forbid hipMalloc).
+ * Same arguments and result as crbm_fidelity_grad (same kernels, bit-identical output) with the shape given
+ * directly (n_visible <= 256, n_hidden <= 512).  Its scratch (the packed spin rows and the FP32 chunk sums of
+ * the O^H contraction) lives in one static device array of 48 MiB that each GPU the library runs on holds
+ * until the process ends; a gradient needing more (about n (N + 17) + 8 (N + 1)(M + 1) ceil(n / max(256,
+ * n/256)) bytes) returns CRBM_ENOMEM before anything is enqueued.  Every byte of the scratch that a call
+ * reads is written earlier in the same call, so nothing carries over from a previous call; but all calls on
+ * one GPU share the array: calls that overlap on one GPU (two streams, two host threads) race. */
+int crbm_fidelity_grad_noalloc(int n_visible, int n_hidden, const int8_t* samples, const void* tanh_theta,
+                               const void* R, long n_samples, void* grad_out, double* loss_out, hipStream_t stream);
+
 /* Moment-correction matrices of the basis t_0 = S^z_q psi_gs, t_n = beta_n t~_n (n = 1..n_max), by
  * sampling s ~ |psi_gs|^2 (Sec. IV; App. A, G and H):
  *   B_0(s) = f_q(s),  B_n(s) = beta_n t~_n(s)/psi_gs(s),  HB_n(s) = (H t_n)(s)/psi_gs(s),

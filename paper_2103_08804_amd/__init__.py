@@ -33,7 +33,8 @@ EXPORTS = ("crbm_plan_create", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_la
            "crbm_sr_step", "crbm_sr_energy_step", "crbm_chebyshev_moment", "crbm_fidelity_grad", "crbm_batched_moments",
            "crbm_batched_autotune", "crbm_moment_matrices", "crbm_corrected_moments", "crbm_lanczos",
            "crbm_spectrum_kpm", "crbm_spectrum_cf", "crbm_probe_mfma", "crbm_probe_hbm", "crbm_probe_logcosh", "crbm_probe_gather",
-           "crbm_sym_matrices", "crbm_fit_stats", "crbm_enum_weights")
+           "crbm_sym_matrices", "crbm_fit_stats", "crbm_enum_weights",
+           "crbm_fidelity_grad_noalloc")
 PROF_NAMES = ("sample", "theta", "local", "ot", "sbuild", "cg", "moment", "pack", "cholesky", "batched", "gram", "sborder")
 
 
@@ -96,6 +97,7 @@ def lib():
         L.crbm_probe_gather.argtypes = [_i, _i, P(_d), _vp]
         L.crbm_chebyshev_moment.argtypes = [_vp, P(_Rbm), _vp, _vp, _i, P(_d), _i, _vp, _vp, _l, _vp, _vp]
         L.crbm_fidelity_grad.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _l, _vp, _vp, _vp]
+        L.crbm_fidelity_grad_noalloc.argtypes = [_i, _i, _vp, _vp, _vp, _l, _vp, _vp, _vp]
         L.crbm_batched_moments.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _i, ctypes.c_int64, _i, _i, _i, _u64,
                                            _vp, _vp, _vp]
         L.crbm_batched_autotune.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _i, ctypes.c_int64, _i, _i, _u64, _vp,
@@ -357,6 +359,17 @@ def fidelity_grad(plan: Plan, fit: RBM, samples, tanh_theta, R, grad_out, loss_o
         _ptr(grad_out, torch.complex128, (P,), "grad_out") if grad_out is not None else None,
         _ptr(loss_out, torch.float64, (1,), "loss_out"),
         _stream(stream)))
+
+
+def fidelity_grad_noalloc(N: int, M: int, samples, tanh_theta, R, grad_out, loss_out=None, stream=None):
+    """crbm_fidelity_grad without a plan or any allocation (static device scratch of 48 MiB)."""
+    n = samples.shape[0]
+    P = N + M + N * M
+    _check(lib().crbm_fidelity_grad_noalloc(
+        N, M, _ptr(samples, torch.int8, (n, N), "samples"), _ptr(tanh_theta, torch.complex64, (n, M), "tanh_theta"),
+        _ptr(R, torch.complex64, (n,), "R"), n,
+        _ptr(grad_out, torch.complex128, (P,), "grad_out") if grad_out is not None else None,
+        _ptr(loss_out, torch.float64, (1,), "loss_out"), _stream(stream)))
 
 
 def moment_matrices(plan: Plan, psi_gs: RBM, t_params, betas, q, samples, G_out, H_out, weights=None, stream=None):

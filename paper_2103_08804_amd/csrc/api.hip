@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -669,6 +670,68 @@ int crbm_fidelity_grad(crbm_plan p, const crbm_rbm* fit, const int8_t* samples, 
     A.loss = loss_out;
     hipError_t e = launch_fidelity_grad(A, p->w, stream);
     return e == hipSuccess ? CRBM_OK : hip_fail(e, "fidelity_grad launch");
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ allocation-free fidelity gradient
+// The scratch of crbm_fidelity_grad_noalloc: one file-scope device array, which every GPU the library runs on
+// holds until the process ends.  Host code never passes the array's name (a host-side stand-in) to a kernel:
+// its device address is taken once per device with hipGetSymbolAddress and kept in g_scratch_ptr.
+namespace {
+constexpr size_t kNoallocScratchBytes = size_t(48) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+int scratch_of_current_device(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(CRBM_EUNSUPPORTED, "device %d is beyond the %d the library tracks", dev,
+                                                   kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(CRBM_EHIP, "hipGetSymbolAddress of the scratch array: %s", hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return CRBM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int crbm_fidelity_grad_noalloc(int n_visible, int n_hidden, const int8_t* samples, const void* T, const void* R,
+                               long n, void* grad_out, double* loss_out, hipStream_t stream) {
+    if (n_visible < 1 || n_hidden < 1) return fail(CRBM_EINVAL, "n_visible and n_hidden must be >= 1");
+    if (n_visible > kMaxN || n_hidden > kMaxM)
+        return fail(CRBM_EUNSUPPORTED, "N = %d, M = %d exceed the limits %d, %d", n_visible, n_hidden, kMaxN, kMaxM);
+    if (!samples || !T || !R) return fail(CRBM_EINVAL, "samples, tanh_theta and R must be non-NULL");
+    if (!grad_out && !loss_out) return fail(CRBM_EINVAL, "at least one of grad_out and loss_out must be non-NULL");
+    if (n < 1) return fail(CRBM_EINVAL, "n_samples must be >= 1");
+    const size_t need = fidelity_grad_scratch_bytes(n_visible, n_hidden, n);
+    if (grad_out && need > kNoallocScratchBytes)
+        return fail(CRBM_ENOMEM, "N = %d, M = %d, n = %ld need %zu bytes of scratch; the static scratch holds %zu",
+                    n_visible, n_hidden, n, need, kNoallocScratchBytes);
+    void* scr = nullptr;
+    if (int rc = scratch_of_current_device(&scr)) return rc;
+    GradArgs A{};
+    A.N = n_visible; A.M = n_hidden; A.P = n_visible + n_hidden + n_visible * n_hidden;
+    A.samples = samples;
+    A.T = static_cast<const float2*>(T);
+    A.R = static_cast<const float2*>(R);
+    A.n = n;
+    A.grad = static_cast<double2*>(grad_out);
+    A.loss = loss_out;
+    hipError_t e = launch_fidelity_grad_scratch(A, scr, current_cus(), stream);
+    return e == hipSuccess ? CRBM_OK : hip_fail(e, "fidelity_grad_noalloc launch");
 }
 
 int crbm_moment_matrices(crbm_plan p, const crbm_rbm* gs, const void* t_params, const double* betas, int n_max,

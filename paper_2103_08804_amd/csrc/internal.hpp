@@ -193,6 +193,9 @@ struct GradArgs {
     double* loss;                      // [1] or null
 };
 hipError_t launch_fidelity_grad(const GradArgs& args, const SrWork& w, hipStream_t stream);
+// the same gradient with its scratch (fidelity_grad_scratch_bytes(N, M, n) bytes) supplied by the caller
+size_t fidelity_grad_scratch_bytes(int N, int M, long n);
+hipError_t launch_fidelity_grad_scratch(const GradArgs& args, void* scratch, int n_cu, hipStream_t stream);
 
 // gamma, beta = <R>, <|R|^2> and a flag word of the current fit (out: device double [5]); red: 512 double2
 hipError_t launch_fit_stats(const float2* R, const double* w, long n, double2* red, double* out, hipStream_t stream);

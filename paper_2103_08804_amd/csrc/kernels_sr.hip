@@ -399,11 +399,16 @@ static int ot_resident_per_cu() {
     }
     return cached;
 }
-static OtPlan ot_plan(int N, int M, long n, int nk, int n_cu) {
-    long chunk = (n + 255) / 256;
+static void ot_chunking(long n, long& chunk, int& n_chunks) {
+    chunk = (n + 255) / 256;
     chunk = ((chunk + OM_S - 1) / OM_S) * OM_S;
     if (chunk < 256) chunk = 256;
-    const int n_chunks = (int)((n + chunk - 1) / chunk);
+    n_chunks = (int)((n + chunk - 1) / chunk);
+}
+static OtPlan ot_plan(int N, int M, long n, int nk, int n_cu) {
+    long chunk;
+    int n_chunks;
+    ot_chunking(n, chunk, n_chunks);
     const long tiles = (long)((N + 1 + OM_R - 1) / OM_R) * ((M + 1 + OM_C - 1) / OM_C);
     const long slots = (long)n_cu * (nk == 2 ? ot_resident_per_cu<2>() : ot_resident_per_cu<1>());
     long z = slots / tiles;
@@ -1063,15 +1068,37 @@ __global__ void k_loss(const float2* __restrict__ R, long n, double* __restrict_
     if (threadIdx.x == 0) *loss = (sh[0] + sh[1] + sh[2] + sh[3]) / (double)n;
 }
 
-hipError_t launch_fidelity_grad(const GradArgs& A, const SrWork& W, hipStream_t stream) {
+// the gradient from caller-chosen scratch: sig16 (n sig16_row(N) bytes) and the contraction's chunk planes
+static hipError_t fidelity_grad_on(const GradArgs& A, int8_t* sig16, void* partial, int n_cu, Profiler* prof,
+                                   hipStream_t stream) {
     if (A.grad) {
-        pack_sig16(A.samples, A.n, A.N, W.sig16, stream);
-        hipError_t e = run_ot(A.N, A.M, W.sig16, A.T, A.n, 3, 0, 1, nullptr, A.R, nullptr, W.red, 0, A.grad, nullptr,
-                              stream, nullptr, W.prof, W.n_cu);
+        pack_sig16(A.samples, A.n, A.N, sig16, stream);
+        hipError_t e = run_ot(A.N, A.M, sig16, A.T, A.n, 3, 0, 1, nullptr, A.R, nullptr, partial, 0, A.grad, nullptr,
+                              stream, nullptr, prof, n_cu);
         if (e != hipSuccess) return e;
     }
     if (A.loss) hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, stream, A.R, A.n, A.loss);
     return hipGetLastError();
+}
+
+hipError_t launch_fidelity_grad(const GradArgs& A, const SrWork& W, hipStream_t stream) {
+    return fidelity_grad_on(A, W.sig16, W.red, W.n_cu, W.prof, stream);
+}
+
+// Scratch of the gradient for n samples, laid out as [sigma~ rows | 256-byte alignment | chunk planes of one
+// coefficient, 2 (N + 1)(M + 1) floats per sample chunk]; the chunk count depends on n only.
+size_t fidelity_grad_scratch_bytes(int N, int M, long n) {
+    long chunk;
+    int n_chunks;
+    ot_chunking(n, chunk, n_chunks);
+    const size_t rows = ((size_t)n * (size_t)sig16_row(N) + 255) / 256 * 256;
+    return rows + (size_t)n_chunks * 2 * (size_t)(N + 1) * (size_t)(M + 1) * sizeof(float);
+}
+
+hipError_t launch_fidelity_grad_scratch(const GradArgs& A, void* scratch, int n_cu, hipStream_t stream) {
+    int8_t* sig16 = static_cast<int8_t*>(scratch);
+    const size_t rows = ((size_t)A.n * (size_t)sig16_row(A.N) + 255) / 256 * 256;
+    return fidelity_grad_on(A, sig16, static_cast<unsigned char*>(scratch) + rows, n_cu, nullptr, stream);
 }
 
 }  // namespace crbm

@@ -85,3 +85,13 @@ def test_host_side_errors_of_the_probes():
     assert L.crbm_probe_gather(0, 400, ctypes.byref(v), None) == crbm.CRBM_EINVAL
     assert L.crbm_probe_gather(1 << 13, 1 << 12, ctypes.byref(v), None) == crbm.CRBM_EINVAL
     assert b"2^24" in L.crbm_last_error()
+
+
+def test_noalloc_gradient_rejects_oversized_input_on_the_host():
+    """crbm_fidelity_grad_noalloc checks its static scratch before any HIP call."""
+    L = crbm.lib()
+    dummy = ctypes.c_void_p(1)
+    assert L.crbm_fidelity_grad_noalloc(256, 512, dummy, dummy, dummy, 1 << 20, dummy, None, None) == crbm.CRBM_ENOMEM
+    assert b"static scratch" in L.crbm_last_error()
+    assert L.crbm_fidelity_grad_noalloc(0, 4, dummy, dummy, dummy, 8, dummy, None, None) == crbm.CRBM_EINVAL
+    assert L.crbm_fidelity_grad_noalloc(4, 4, dummy, dummy, dummy, 8, None, None, None) == crbm.CRBM_EINVAL
