@@ -374,7 +374,7 @@ def bench_spectral(crbm, args):
     ns = C * sweeps
     n_max = args.n_moments
     K = n_max + 1
-    plan = crbm.Plan(crbm.SQUARE, wl.Lx, wl.Ly, M, ns)
+    plan = crbm.Plan(crbm.SQUARE, wl.Lx, wl.Ly, M, ns, crbm.PLAN_BASIS, basis_k_max=K)
     gs = crbm.RBM.empty(N, M)
     crbm.init_rbm(gs, wl.param_seed, wl.param_std)
     tp = torch.zeros(n_max, P, dtype=torch.complex64, device="cuda")
@@ -438,7 +438,7 @@ def bench_symmetry(crbm, args):
     n_max = args.n_moments
     K = n_max + 1
     ng = 4 * N
-    plan = crbm.Plan(crbm.SQUARE, wl.Lx, wl.Ly, M, ns * ng)
+    plan = crbm.Plan(crbm.SQUARE, wl.Lx, wl.Ly, M, ns * ng, crbm.PLAN_SYM_BASIS, basis_k_max=K)
     gs = crbm.RBM.empty(N, M)
     crbm.init_rbm(gs, wl.param_seed, wl.param_std)
     tp = torch.zeros(n_max, P, dtype=torch.complex64, device="cuda")

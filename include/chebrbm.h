@@ -72,6 +72,10 @@ enum { CRBM_PREC_FP32 = 0, CRBM_PREC_BF16 = 1 };
                                   min(8, 2^30 / (8 P^2)) more P x P slices, so that the contraction can be
                                   split over samples when its tile pairs alone cannot fill the device */
 #define CRBM_PLAN_CHOLESKY 2   /* also reserve a P x P complex128 factor (CHOLESKY; needs P <= 4000) */
+#define CRBM_PLAN_BASIS 4      /* reserve the workspace of crbm_moment_matrices for K = n_max + 1 <= basis_k_max
+                                  (crbm_plan_create_ex): 16 K_max max_samples + 8 max_samples bytes */
+#define CRBM_PLAN_SYM_BASIS 8  /* reserve the workspace of crbm_sym_matrices for K <= basis_k_max:
+                                  32 K_max max_samples + (N + 24) max_samples bytes (includes CRBM_PLAN_BASIS) */
 
 /* workspace buffers readable through crbm_plan_buffer (device pointers) */
 enum {
@@ -120,6 +124,12 @@ typedef struct {
  * 8*P*P bytes with CRBM_PLAN_DENSE_S).  Limits: N even or odd up to 256, M up to 512.
  * Uses the current HIP device. */
 int crbm_plan_create(crbm_plan* plan, const crbm_lattice* lattice, int n_hidden, long max_samples, int flags);
+/* The same with the basis workspace of the moment correction (Sec. IV, App. A) reserved up front for
+ * K = n_max + 1 <= basis_k_max <= 256 (flags CRBM_PLAN_BASIS / CRBM_PLAN_SYM_BASIS; basis_k_max is ignored
+ * without them), so that crbm_moment_matrices and crbm_sym_matrices allocate nothing and can be captured in
+ * a graph from their first call.  crbm_plan_create(p, l, M, S, f) is crbm_plan_create_ex(p, l, M, S, f, 0). */
+int crbm_plan_create_ex(crbm_plan* plan, const crbm_lattice* lattice, int n_hidden, long max_samples, int flags,
+                        int basis_k_max);
 int crbm_plan_destroy(crbm_plan plan);
 /* Device pointer and size in bytes of a workspace buffer (CRBM_BUF_*), valid until destroy. */
 int crbm_plan_buffer(crbm_plan plan, int which, void** dev_ptr, size_t* bytes);
@@ -299,8 +309,8 @@ int crbm_fidelity_grad_noalloc(int n_visible, int n_hidden, const int8_t* sample
  * H is the lattice Hamiltonian of the plan (units of J, not rescaled).  K = n_max + 1 <= 256.
  * t_params, betas, weights, samples as in crbm_chebyshev_moment; q: HOST double [2];
  * G_out, H_out: complex128 [K][K] (row n, column m).  Row 0 of G is the moment estimate mu_m of
- * crbm_chebyshev_moment on the same samples.  The first call with a given K * max_samples allocates
- * 16 K max_samples bytes of plan workspace (kept until the plan is destroyed); later calls do not. */
+ * crbm_chebyshev_moment on the same samples.  Needs a plan created with CRBM_PLAN_BASIS (or
+ * CRBM_PLAN_SYM_BASIS) and basis_k_max >= K; otherwise CRBM_ENOMEM.  Allocates nothing. */
 int crbm_moment_matrices(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_params, const double* betas,
                          int n_max, const double* q, const int8_t* samples, const double* weights, long n_samples,
                          void* G_out, void* H_out, hipStream_t stream);
@@ -317,8 +327,8 @@ int crbm_moment_matrices(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_p
  * k.m = 2 pi (k1 m1/Lx + k2 m2/Ly), k = k1 + Lx k2.  G_out, H_out: complex128 [N][K][K], K = n_max + 1.
  * With a translation- and rotation-invariant psi_gs, row 0 of G^(k) holds the moments of S^z_k.
  * The images of a sample are evaluated in chunks of max_samples / (N * (rotations ? 4 : 1)) samples
- * (that quotient must be >= 1); the first call with a given chunk size allocates about
- * 32 K max_samples + 9 max_samples bytes of plan workspace. */
+ * (that quotient must be >= 1).  Needs a plan created with CRBM_PLAN_SYM_BASIS and basis_k_max >= K;
+ * otherwise CRBM_ENOMEM.  Allocates nothing. */
 int crbm_sym_matrices(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_params, const double* betas,
                       int n_max, int rotations, const int8_t* samples, const double* weights, long n_samples,
                       void* G_out, void* H_out, hipStream_t stream);

@@ -24,11 +24,11 @@ CHAIN, SQUARE = 0, 1
 FLIP, EXCHANGE = 0, 1
 CG_DENSE, CG_MATFREE, CHOLESKY = 0, 1, 2
 FP32, BF16 = 0, 1
-PLAN_DENSE_S, PLAN_CHOLESKY = 1, 2
+PLAN_DENSE_S, PLAN_CHOLESKY, PLAN_BASIS, PLAN_SYM_BASIS = 1, 2, 4, 8
 BUF_F, BUF_DALPHA, BUF_OMEAN, BUF_S = 0, 1, 2, 3
 
 # names declared in include/chebrbm.h
-EXPORTS = ("crbm_plan_create", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_last_error", "crbm_plan_profile",
+EXPORTS = ("crbm_plan_create", "crbm_plan_create_ex", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_last_error", "crbm_plan_profile",
            "crbm_plan_profile_read", "crbm_init_rbm", "crbm_init_chains", "crbm_sample", "crbm_local_estimators",
            "crbm_sr_step", "crbm_sr_energy_step", "crbm_chebyshev_moment", "crbm_fidelity_grad", "crbm_batched_moments",
            "crbm_batched_autotune", "crbm_moment_matrices", "crbm_corrected_moments", "crbm_lanczos",
@@ -72,6 +72,7 @@ def lib():
         P = ctypes.POINTER
         L.crbm_last_error.restype = ctypes.c_char_p
         L.crbm_plan_create.argtypes = [P(_vp), P(_Lattice), _i, _l, _i]
+        L.crbm_plan_create_ex.argtypes = [P(_vp), P(_Lattice), _i, _l, _i, _i]
         L.crbm_plan_destroy.argtypes = [_vp]
         L.crbm_plan_buffer.argtypes = [_vp, _i, P(_vp), P(ctypes.c_size_t)]
         L.crbm_plan_profile.argtypes = [_vp, _i]
@@ -167,16 +168,18 @@ class RBM:
 
 
 class Plan:
-    """Lattice + hidden width + workspace (see crbm_plan_create)."""
+    """Lattice + hidden width + workspace (see crbm_plan_create / crbm_plan_create_ex: basis_k_max with
+    PLAN_BASIS or PLAN_SYM_BASIS reserves the moment-correction workspace)."""
 
-    def __init__(self, kind, Lx, Ly=1, M=1, max_samples=1, flags=0, J=1.0):
+    def __init__(self, kind, Lx, Ly=1, M=1, max_samples=1, flags=0, J=1.0, basis_k_max=0):
         self.kind, self.Lx, self.Ly, self.M, self.J = kind, Lx, (Ly if kind == SQUARE else 1), M, J
         self.N = self.Lx * self.Ly
         self.P = self.N + M + self.N * M
         self.max_samples = max_samples
         self._h = ctypes.c_void_p()
         lat = _Lattice(kind, Lx, Ly, J)
-        _check(lib().crbm_plan_create(ctypes.byref(self._h), ctypes.byref(lat), M, max_samples, flags))
+        _check(lib().crbm_plan_create_ex(ctypes.byref(self._h), ctypes.byref(lat), M, max_samples, flags,
+                                         basis_k_max))
 
     @property
     def handle(self):

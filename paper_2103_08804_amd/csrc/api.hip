@@ -111,11 +111,13 @@ struct crbm_plan_s {
     int b_waves = 4, b_blocks = 1024;
     Profiler prof;
     std::vector<void*> allocs;
-    // grow-only workspace of the moment-correction path (allocated on first use)
+    // workspace of the moment-correction path, reserved at creation (CRBM_PLAN_BASIS / CRBM_PLAN_SYM_BASIS;
+    // the small dense buffer of the corrected moments and Lanczos in every plan); the calls check its size
     enum { GB_BASIS = 0, GB_HBASIS, GB_ELOC, GB_GRAM, GB_SMALL, GB_SYMIMG, GB_SYMLT, GB_SYMLG, GB_SYMBT, GB_SYMHBT,
            GB_COUNT };
     void* grow_ptr[GB_COUNT] = {};
     size_t grow_cap[GB_COUNT] = {};
+    int basis_k_max = 0;
 
     Geometry geometry() const {
         Geometry g;
@@ -138,9 +140,8 @@ struct crbm_plan_s {
         *p = static_cast<T*>(q);
         return CRBM_OK;
     }
-    // make grow_ptr[id] hold at least `bytes`; an existing smaller buffer is released first
-    // (hipFree waits for the device, so no launch still reads it)
-    int grow(int id, size_t bytes) {
+    // reserve grow_ptr[id] with `bytes` (at plan creation only)
+    int reserve(int id, size_t bytes) {
         if (grow_cap[id] >= bytes) return CRBM_OK;
         if (grow_ptr[id]) { (void)hipFree(grow_ptr[id]); grow_ptr[id] = nullptr; grow_cap[id] = 0; }
         void* q = nullptr;
@@ -152,6 +153,12 @@ struct crbm_plan_s {
         grow_ptr[id] = q;
         grow_cap[id] = bytes;
         return CRBM_OK;
+    }
+    // the calls: the reserved buffer must hold `bytes`
+    int need(int id, size_t bytes, const char* flag) const {
+        if (grow_cap[id] >= bytes) return CRBM_OK;
+        return fail(CRBM_ENOMEM, "the plan's basis workspace holds %zu bytes where %zu are needed: create the plan with "
+                    "crbm_plan_create_ex, %s and basis_k_max >= K", grow_cap[id], bytes, flag);
     }
     ~crbm_plan_s() {
         for (void* p : allocs) (void)hipFree(p);
@@ -235,6 +242,11 @@ extern "C" {
 const char* crbm_last_error(void) { return g_err; }
 
 int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long max_samples, int flags) {
+    return crbm_plan_create_ex(out, lat, n_hidden, max_samples, flags, 0);
+}
+
+int crbm_plan_create_ex(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long max_samples, int flags,
+                        int basis_k_max) {
     if (!out) return fail(CRBM_EINVAL, "plan output pointer is NULL");
     *out = nullptr;
     if (!lat) return fail(CRBM_EINVAL, "lattice is NULL");
@@ -248,7 +260,11 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
     if (n_hidden < 1) return fail(CRBM_EINVAL, "n_hidden must be >= 1 (got %d)", n_hidden);
     if (n_hidden > kMaxM) return fail(CRBM_EUNSUPPORTED, "M = %d hidden units exceeds the limit of %d", n_hidden, kMaxM);
     if (max_samples < 1) return fail(CRBM_EINVAL, "max_samples must be >= 1 (got %ld)", max_samples);
-    if (flags & ~(CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY)) return fail(CRBM_EINVAL, "unknown plan flags 0x%x", flags);
+    if (flags & ~(CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY | CRBM_PLAN_BASIS | CRBM_PLAN_SYM_BASIS))
+        return fail(CRBM_EINVAL, "unknown plan flags 0x%x", flags);
+    const bool basis = (flags & (CRBM_PLAN_BASIS | CRBM_PLAN_SYM_BASIS)) != 0;
+    if (basis && (basis_k_max < 1 || basis_k_max > kMaxBasis))
+        return fail(CRBM_EINVAL, "basis_k_max must be in [1, %d] with CRBM_PLAN_BASIS (got %d)", kMaxBasis, basis_k_max);
 
     crbm_plan_s* p = new (std::nothrow) crbm_plan_s();
     if (!p) return fail(CRBM_ENOMEM, "host allocation of the plan failed");
@@ -336,6 +352,25 @@ int crbm_plan_create(crbm_plan* out, const crbm_lattice* lat, int n_hidden, long
         if (!rc && nsm >= 2) {
             rc = p->alloc(&p->w.spart, (size_t)(nsm * P * P));
             p->w.nsplit_max = (int)nsm;
+        }
+    }
+    // small dense buffer of the corrected moments and Lanczos (K <= 256), in every plan
+    rc = rc ? rc : p->reserve(crbm_plan_s::GB_SMALL, (size_t)(4L * kMaxBasis * kMaxBasis + kMaxBasis) * sizeof(double2));
+    if (!rc && basis) {
+        const size_t col = (size_t)basis_k_max * (size_t)S * sizeof(float2);
+        p->basis_k_max = basis_k_max;
+        rc = p->reserve(crbm_plan_s::GB_BASIS, col);
+        rc = rc ? rc : p->reserve(crbm_plan_s::GB_HBASIS, col);
+        rc = rc ? rc : p->reserve(crbm_plan_s::GB_ELOC, (size_t)S * sizeof(float2));
+        long gl = 0;   // the Gram partials' length is not monotone in K: the largest up to K_max
+        for (int k = 1; k <= basis_k_max; ++k) gl = std::max(gl, gram_partial_len(k));
+        rc = rc ? rc : p->reserve(crbm_plan_s::GB_GRAM, (size_t)gl * sizeof(double2));
+        if (!rc && (flags & CRBM_PLAN_SYM_BASIS)) {
+            rc = p->reserve(crbm_plan_s::GB_SYMBT, col);
+            rc = rc ? rc : p->reserve(crbm_plan_s::GB_SYMHBT, col);
+            rc = rc ? rc : p->reserve(crbm_plan_s::GB_SYMIMG, (size_t)S * (size_t)N);
+            rc = rc ? rc : p->reserve(crbm_plan_s::GB_SYMLT, (size_t)S * sizeof(float2));
+            rc = rc ? rc : p->reserve(crbm_plan_s::GB_SYMLG, (size_t)S * sizeof(float2));
         }
     }
     p->w.prof = &p->prof;
@@ -749,11 +784,12 @@ int crbm_moment_matrices(crbm_plan p, const crbm_rbm* gs, const void* t_params, 
                                         p->max_samples);
     if (int rc = set_device(p)) return rc;
     const int K = n_max + 1;
-    const size_t col_bytes = (size_t)K * (size_t)p->max_samples * sizeof(float2);
-    int rc = p->grow(crbm_plan_s::GB_BASIS, col_bytes);
-    rc = rc ? rc : p->grow(crbm_plan_s::GB_HBASIS, col_bytes);
-    rc = rc ? rc : p->grow(crbm_plan_s::GB_ELOC, (size_t)p->max_samples * sizeof(float2));
-    rc = rc ? rc : p->grow(crbm_plan_s::GB_GRAM, (size_t)gram_partial_len(kMaxBasis) * sizeof(double2));
+    const size_t col_bytes = (size_t)K * (size_t)n * sizeof(float2);
+    const char* fl = "CRBM_PLAN_BASIS";
+    int rc = p->need(crbm_plan_s::GB_BASIS, col_bytes, fl);
+    rc = rc ? rc : p->need(crbm_plan_s::GB_HBASIS, col_bytes, fl);
+    rc = rc ? rc : p->need(crbm_plan_s::GB_ELOC, (size_t)n * sizeof(float2), fl);
+    rc = rc ? rc : p->need(crbm_plan_s::GB_GRAM, (size_t)gram_partial_len(K) * sizeof(double2), fl);
     if (rc) return rc;
     float2* Bm = static_cast<float2*>(p->grow_ptr[crbm_plan_s::GB_BASIS]);
     float2* HBm = static_cast<float2*>(p->grow_ptr[crbm_plan_s::GB_HBASIS]);
@@ -854,15 +890,16 @@ int crbm_sym_matrices(crbm_plan p, const crbm_rbm* gs, const void* t_params, con
     const long cmax = p->max_samples / ng;                  // samples per chunk
     const long rows_max = cmax * ng;
     const size_t colb = (size_t)K * (size_t)rows_max * sizeof(float2);
-    int rc = p->grow(crbm_plan_s::GB_BASIS, colb);
-    rc = rc ? rc : p->grow(crbm_plan_s::GB_HBASIS, colb);
-    rc = rc ? rc : p->grow(crbm_plan_s::GB_SYMBT, colb);
-    rc = rc ? rc : p->grow(crbm_plan_s::GB_SYMHBT, colb);
-    rc = rc ? rc : p->grow(crbm_plan_s::GB_SYMIMG, (size_t)rows_max * N);
-    rc = rc ? rc : p->grow(crbm_plan_s::GB_SYMLT, (size_t)rows_max * sizeof(float2));
-    rc = rc ? rc : p->grow(crbm_plan_s::GB_ELOC, (size_t)rows_max * sizeof(float2));
-    rc = rc ? rc : p->grow(crbm_plan_s::GB_SYMLG, (size_t)cmax * sizeof(float2));
-    rc = rc ? rc : p->grow(crbm_plan_s::GB_GRAM, (size_t)gram_partial_len(kMaxBasis) * sizeof(double2));
+    const char* fl = "CRBM_PLAN_SYM_BASIS";
+    int rc = p->need(crbm_plan_s::GB_BASIS, colb, fl);
+    rc = rc ? rc : p->need(crbm_plan_s::GB_HBASIS, colb, fl);
+    rc = rc ? rc : p->need(crbm_plan_s::GB_SYMBT, colb, fl);
+    rc = rc ? rc : p->need(crbm_plan_s::GB_SYMHBT, colb, fl);
+    rc = rc ? rc : p->need(crbm_plan_s::GB_SYMIMG, (size_t)rows_max * N, fl);
+    rc = rc ? rc : p->need(crbm_plan_s::GB_SYMLT, (size_t)rows_max * sizeof(float2), fl);
+    rc = rc ? rc : p->need(crbm_plan_s::GB_ELOC, (size_t)rows_max * sizeof(float2), fl);
+    rc = rc ? rc : p->need(crbm_plan_s::GB_SYMLG, (size_t)cmax * sizeof(float2), fl);
+    rc = rc ? rc : p->need(crbm_plan_s::GB_GRAM, (size_t)gram_partial_len(K) * sizeof(double2), fl);
     if (rc) return rc;
     float2* Bm = static_cast<float2*>(p->grow_ptr[crbm_plan_s::GB_BASIS]);
     float2* HBm = static_cast<float2*>(p->grow_ptr[crbm_plan_s::GB_HBASIS]);
@@ -944,8 +981,6 @@ int crbm_corrected_moments(crbm_plan p, const void* G, const void* H, int K, dou
     if (!(W_scale != 0.0) || !(W_scale - W_scale == 0.0) || !(E_c - E_c == 0.0))
         return fail(CRBM_EINVAL, "E_c must be finite and W_scale finite and non-zero");
     if (int rc = set_device(p)) return rc;
-    if (int rc = p->grow(crbm_plan_s::GB_SMALL, (size_t)(4L * kMaxBasis * kMaxBasis + kMaxBasis) * sizeof(double2)))
-        return rc;
     hipError_t e = launch_correct(K, static_cast<const double2*>(G), static_cast<const double2*>(H), E_c, W_scale,
                                   n_out, static_cast<double2*>(p->grow_ptr[crbm_plan_s::GB_SMALL]), mu_out, info_out,
                                   stream);
@@ -960,8 +995,6 @@ int crbm_lanczos(crbm_plan p, const void* G, const void* H, int K, int n_steps, 
     if (K < 1 || K > kMaxBasis) return fail(CRBM_EINVAL, "K must be in [1, %d] (got %d)", kMaxBasis, K);
     if (n_steps < 1) return fail(CRBM_EINVAL, "n_steps must be >= 1");
     if (int rc = set_device(p)) return rc;
-    if (int rc = p->grow(crbm_plan_s::GB_SMALL, (size_t)(4L * kMaxBasis * kMaxBasis + kMaxBasis) * sizeof(double2)))
-        return rc;
     hipError_t e = launch_lanczos(K, static_cast<const double2*>(G), static_cast<const double2*>(H), n_steps,
                                   static_cast<double2*>(p->grow_ptr[crbm_plan_s::GB_SMALL]), a_out, b2_out, info_out,
                                   stream);

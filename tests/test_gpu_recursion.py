@@ -95,7 +95,7 @@ def _oracle_run(c, name):
 
 
 def _plan():
-    return crbm.Plan(crbm.CHAIN, N, 1, M, 1 << N, crbm.PLAN_CHOLESKY)
+    return crbm.Plan(crbm.CHAIN, N, 1, M, 1 << N, crbm.PLAN_CHOLESKY | crbm.PLAN_BASIS, basis_k_max=N_MAX + 1)
 
 
 def _settings():

@@ -52,8 +52,8 @@ def test_moment_matrices(orc, kind, Lx, Ly, M, n_max, n, q):
     sig = orc.enumerate_configs(N) if n is None else synth.random_spins(92, n, N, True)
     ns = sig.shape[0]
     w = orc.enum_weights(orc.logpsi(gs, sig)) if n is None else None
-    plan = crbm.Plan(kind, Lx, Ly, M, ns)
     K = n_max + 1
+    plan = crbm.Plan(kind, Lx, Ly, M, ns, crbm.PLAN_BASIS, basis_k_max=K)
     G = torch.zeros(K, K, dtype=torch.complex128, device="cuda")
     H = torch.zeros_like(G)
     sig_d = _dev(sig, torch.int8)
@@ -225,3 +225,54 @@ def test_kpm_spectrum(jackson):
     torch.cuda.synchronize()
     ref = spectral.kpm_spectrum(mu, E0, E_c, W_scale, omega, damping=jackson)
     assert np.max(np.abs(np_of(A) - ref)) < 1e-9 * np.max(np.abs(ref))
+
+
+def test_moment_matrices_first_call_under_graph_capture(orc):
+    """With the basis workspace reserved at plan creation, the very first crbm_moment_matrices call on a plan
+    (and crbm_corrected_moments after it) can be captured in a graph: nothing allocates or synchronises.
+    Each of three replays, with eager work of the program between them, equals an eager run on a second
+    plan bit for bit."""
+    N, M, n_max, n = 8, 8, 4, 700
+    K = n_max + 1
+    lat = orc.Lattice(0, N)
+    gs_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(95, N, M, 0.1, std_im=0.05)))
+    tp = _dev(np.stack([orc.RBM(*synth.random_rbm_arrays(96 + t, N, M, 0.1, std_im=0.05)).vector()
+                        for t in range(n_max)]).astype(np.complex64), torch.complex64)
+    betas = _dev(np.linspace(0.5, 1.5, n_max) + 0.1j, torch.complex128)
+    sig = _dev(synth.random_spins(97, n, N, True), torch.int8)
+    q = (np.pi, 0.0)
+    E0 = -3.6510934089371783   # any scale: the same on both sides
+    E_c, W_scale = E0 + 0.9875 * 1.5 * abs(E0), 1.5 * abs(E0)
+
+    def run(plan, G, H, mu, info):
+        crbm.moment_matrices(plan, gs_d, tp, betas, q, sig, G, H)
+        crbm.corrected_moments(plan, G, H, E_c, W_scale, mu, info)
+
+    def bufs():
+        G = torch.zeros(K, K, dtype=torch.complex128, device="cuda")
+        return G, torch.zeros_like(G), torch.zeros(12, dtype=torch.float64, device="cuda"), \
+            torch.zeros(3, dtype=torch.float64, device="cuda")
+
+    eager_plan = crbm.Plan(0, N, 1, M, n, crbm.PLAN_BASIS, basis_k_max=K)
+    ref = bufs()
+    run(eager_plan, *ref)
+    plan = crbm.Plan(0, N, 1, M, n, crbm.PLAN_BASIS, basis_k_max=K)
+    out = bufs()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        run(plan, *out)           # the plan's first call
+    for rep in range(3):
+        for t in out:
+            t.fill_(-7.0)         # the program's own eager work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b), rep
+    # without the reservation the call refuses instead of allocating
+    bare = crbm.Plan(0, N, 1, M, n)
+    with pytest.raises(crbm.CrbmError) as ei:
+        crbm.moment_matrices(bare, gs_d, tp, betas, q, sig, *bufs()[:2])
+    assert ei.value.code == crbm.CRBM_ENOMEM
+    for p in (plan, eager_plan, bare):
+        p.close()

@@ -47,8 +47,8 @@ def test_sym_matrices(orc, kind, Lx, Ly, M, n_max, n, rot, chunk):
     ns = sig.shape[0]
     w = orc.enum_weights(orc.logpsi(gs, sig)) if n is None else None
     ng = N * (4 if rot else 1)
-    plan = crbm.Plan(kind, Lx, Ly, M, ng * (chunk or ns))
     K = n_max + 1
+    plan = crbm.Plan(kind, Lx, Ly, M, ng * (chunk or ns), crbm.PLAN_SYM_BASIS, basis_k_max=K)
     G = torch.zeros(N, K, K, dtype=torch.complex128, device="cuda")
     H = torch.zeros_like(G)
     crbm.sym_matrices(plan, gs_d, torch.from_numpy(tv).cuda(), torch.from_numpy(betas).cuda(),
@@ -63,14 +63,14 @@ def test_sym_matrices(orc, kind, Lx, Ly, M, n_max, n, rot, chunk):
 
 
 def test_sym_matrices_rejects_bad_shapes(orc):
-    plan = crbm.Plan(1, 4, 2, 4, 1000)
+    plan = crbm.Plan(1, 4, 2, 4, 1000, crbm.PLAN_SYM_BASIS, basis_k_max=1)
     gs = crbm.RBM.empty(8, 4)
     crbm.init_rbm(gs, 1, 0.01)
     sig = torch.ones(3, 8, dtype=torch.int8, device="cuda")
     G = torch.zeros(8, 1, 1, dtype=torch.complex128, device="cuda")
     with pytest.raises(crbm.CrbmError):                  # rotations need L x L
         crbm.sym_matrices(plan, gs, None, None, sig, G, G.clone(), rotations=True)
-    small = crbm.Plan(1, 4, 4, 4, 10)
+    small = crbm.Plan(1, 4, 4, 4, 10, crbm.PLAN_SYM_BASIS, basis_k_max=1)
     gs16 = crbm.RBM.empty(16, 4)
     crbm.init_rbm(gs16, 1, 0.01)
     G16 = torch.zeros(16, 1, 1, dtype=torch.complex128, device="cuda")
