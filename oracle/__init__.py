@@ -76,6 +76,9 @@ def lib():
         L.orc_sr_entries.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _i8p, _c.c_void_p, _c128p, _c.c_long,
                                      _c.c_double, _c.c_void_p, _c.c_int, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                      _c.c_void_p]
+        L.orc_sr_diagonal.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _i8p, _c.c_void_p, _c.c_long,
+                                      _f64p, _c128p]
+        L.orc_sr_diagonal.restype = None
         L.orc_sr_step.argtypes = [_c.c_int, _c.c_int, _c128p, _c128p, _c128p, _i8p, _c.c_void_p, _c128p,
                                   _c.c_long, _c.c_double, _c.c_double, _f64p, _c.c_void_p, _c.c_void_p,
                                   _c.c_void_p]
@@ -311,6 +314,16 @@ def sr_entries(rbm, sig, R, dgamma, ks, weights=None):
     lib().orc_sr_entries(rbm.N, rbm.M, rbm.b, rbm.W, sig, _ptr(w), R, sig.shape[0], dgamma, _ptr(ks), nk,
                          _ptr(stats), _ptr(S), _ptr(F), _ptr(Om))
     return dict(S=S, F=F, Om=Om, gamma=stats[0], beta=complex(stats[1], stats[2]))
+
+
+def sr_diagonal(rbm, sig, weights=None):
+    """(S_kk for every parameter k, <O_k>) over the samples, without forming O [n][P]."""
+    sig = _i8(sig)
+    S = np.zeros(rbm.P, np.float64)
+    Om = np.zeros(rbm.P, np.complex128)
+    w = None if weights is None else np.ascontiguousarray(weights, np.float64)
+    lib().orc_sr_diagonal(rbm.N, rbm.M, rbm.b, rbm.W, sig, _ptr(w), sig.shape[0], S, Om)
+    return S, Om
 
 
 def sr_energy_step(rbm, sig, eloc, lr, eps, weights=None, want_S=False):

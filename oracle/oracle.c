@@ -646,6 +646,54 @@ void orc_sr_entries(int N, int M, const cplx* b, const cplx* W, const int8_t* si
 }
 
 /* ------------------------------------------------------------------------- */
+/* The diagonal of S and the means, for every parameter (Sec. III):           */
+/*   S_kk = <|O_k|^2> - |<O_k>|^2,  Om_out[k] = <O_k>,  k in [0, P),          */
+/* the full O row of each sample formed from its definition (as in           */
+/* orc_logderiv) and summed as orc_sr_entries does: 64 fixed contiguous       */
+/* blocks, compensated within a block, added in block order.  For models and  */
+/* sample sets whose O [n][P] does not fit in memory.                         */
+/* ------------------------------------------------------------------------- */
+void orc_sr_diagonal(int N, int M, const cplx* b, const cplx* W, const int8_t* sig, const double* weights,
+                     long n, double* S_out, cplx* Om_out) {
+    const long P = (long)N + M + (long)N * M;
+    enum { NBLK = 64 };
+    const long per = (n + NBLK - 1) / NBLK;
+    ksum* part = (ksum*)calloc((size_t)(NBLK * 2 * P), sizeof(ksum));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int blk = 0; blk < NBLK; ++blk) {
+        cplx* th = (cplx*)malloc(sizeof(cplx) * (size_t)M);
+        cplx* o = (cplx*)malloc(sizeof(cplx) * (size_t)P);
+        ksum* s1 = part + (long)blk * 2 * P;
+        ksum* s2 = s1 + P;
+        const long s0 = blk * per, s1e = (blk + 1) * per < n ? (blk + 1) * per : n;
+        for (long s = s0; s < s1e; ++s) {
+            const int8_t* sg = sig + s * N;
+            const double w = weights ? weights[s] : 1.0 / (double)n;
+            theta_of(N, M, b, W, sg, th);
+            for (int i = 0; i < N; ++i) o[i] = (double)sg[i];
+            for (int j = 0; j < M; ++j) o[N + j] = tanh_of(th[j]);
+            for (int i = 0; i < N; ++i)
+                for (int j = 0; j < M; ++j) o[N + M + (long)i * M + j] = (double)sg[i] * o[N + j];
+            for (long k = 0; k < P; ++k) {
+                kadd(&s1[k], w * o[k]);
+                kadd(&s2[k], w * creal(o[k] * conj(o[k])));
+            }
+        }
+        free(th); free(o);
+    }
+    for (long k = 0; k < P; ++k) {
+        ksum m = {0, 0}, q = {0, 0};
+        for (int blk = 0; blk < NBLK; ++blk) {
+            kadd(&m, part[(long)blk * 2 * P + k].s);
+            kadd(&q, part[(long)blk * 2 * P + P + k].s);
+        }
+        if (Om_out) Om_out[k] = m.s;
+        S_out[k] = creal(q.s) - creal(m.s * conj(m.s));
+    }
+    free(part);
+}
+
+/* ------------------------------------------------------------------------- */
 /* Chebyshev moments (Sec. II; App. A for the momentum form), sampled over    */
 /* s ~ |psi_gs|^2:                                                            */
 /*   mu_0(q) = < |f_q|^2 >,                                                   */

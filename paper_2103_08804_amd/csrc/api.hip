@@ -351,8 +351,10 @@ int crbm_plan_create_ex(crbm_plan* out, const crbm_lattice* lat, int n_hidden, l
         const long nsm = std::min<long>(kMaxSplits, kSplitBytes / slice);
         if (!rc && nsm >= 2) {
             rc = p->alloc(&p->w.spart, (size_t)(nsm * P * P));
+            rc = rc ? rc : p->alloc(&p->w.bx_part, (size_t)(nsm * N * P));
             p->w.nsplit_max = (int)nsm;
         }
+        rc = rc ? rc : p->alloc(&p->w.bx, (size_t)(N * P));
     }
     // small dense buffer of the corrected moments and Lanczos (K <= 256), in every plan
     rc = rc ? rc : p->reserve(crbm_plan_s::GB_SMALL, (size_t)(4L * kMaxBasis * kMaxBasis + kMaxBasis) * sizeof(double2));

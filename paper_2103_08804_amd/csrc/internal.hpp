@@ -109,7 +109,7 @@ hipError_t launch_moments(const MomentArgs& args, hipStream_t stream);
 struct SrWork {
     double* scal;             // [32] device scalars (see kernels_sr.hip)
     double2* Om;              // [P]  <O>
-    double2* Om16;            // [P]  <O> of the BF16-rounded operands
+    double2* Om16;            // [P]  <O> of the operands of the matrix-core S contraction (shifted, rounded)
     double2* ORm;             // [P]  <O^* (R - <R>)> (R = E_loc in energy mode)
     double2* F;               // [P]
     double2* x;               // [P]  solution
@@ -129,6 +129,8 @@ struct SrWork {
     const int2* sb_order;     // dispatch order of its tile pairs
     long sb_order_len;
     float2* spart;            // [nsplit_max][P][P] partial sums of a contraction split over samples (or null)
+    float2* bx;               // [N][P] raw a-row sums of the matrix-core S contraction
+    float2* bx_part;          // [nsplit_max][N][P] their split partial sums (with spart)
     double2* hv_part;         // [nT][nT][kHemvTile] tile shares of the dense Hermitian product (with S)
     uint16_t* wplanes;        // split-W scratch of the theta product (the matrix-free product's G)
     int nsplit_max;

@@ -5,12 +5,25 @@
 // j in [0, M), with O_(i,j)(s) = sigma~_si T_sj (i = N gives O_b = T), and the
 // a parameters are the rows i < N with O_a = sigma_i.
 //
+// Centring.  Where |<T_j>| is large against the spread of T_j (a unit with
+// |Re theta| of a few), raw sums <O^* O> less the product of the means would
+// lose the ratio's digits to the operand rounding and to the FP32 sums.  The
+// T planes therefore hold T'_j = T_j - c_j with the shift c_j = <T_j> rounded
+// to binary32, and the contraction is put back together in double:
+//   <O^*_(i,j) O_(i',j')> = <s s' T'^*_j T'_j'> + c_j^* X(i,i',j') + c_j' X(i,i',j)^*
+//                           + c_j^* c_j' Y(i,i'),
+// X(i,i',j) = <s_i s_i' T'_j>, Y(i,i') = <s_i s_i'> (s = sigma~).  The border
+// kernel's sums over a rows are exactly the X and Y with i, i' < N; those with
+// an extended site N follow from the means.  The means of the operands the
+// contraction sees (T' rounded as packed, plus c) are supplied by the caller,
+// so that S stays the centred Gram matrix of one set of vectors.
+//
 // Main kernel (W and b rows).  A row tile is 8 extended sites x 16 hidden
 // units = 128 rows, made of four 32-row matrix-core fragments of 2 sites x 16
 // hidden units each; N + 1 sites and M hidden units are padded only to
-// multiples of 8 and 16.  A workgroup streams, per sample, the T values of
+// multiples of 8 and 16.  A workgroup streams, per sample, the T' values of
 // 16 + 16 hidden units and the sign masks of 8 + 8 sites and synthesises the
-// 128 + 128 operand rows by XOR-ing the sign bit into the floating-point T
+// 128 + 128 operand rows by XOR-ing the sign bit into the floating-point T'
 // (sigma = +-1 is exact in any format).  Each workgroup (4 waves) owns a
 // 128 x 128 complex tile pair (u <= u') and accumulates, per wave, a 64 x 64
 // complex block as 4 real products (RR + II -> Re, RI - IR -> Im) in FP32 with
@@ -19,16 +32,18 @@
 // K tiles of samples are double-buffered through LDS.
 //
 // Border kernel (a rows).  The a rows are real (sigma_i), so a block of 128 of
-// them against a W/b tile needs 2 real products (sigma x sigma' T_re,
-// sigma x sigma' T_im), and against a block of a rows only one.  Their operand
+// them against a W/b tile needs 2 real products (sigma x sigma' T'_re,
+// sigma x sigma' T'_im), and against a block of a rows only one.  Their operand
 // is the sign XOR-ed into the sample-weight row (1, or 0 for padded samples).
+// It runs first and writes its raw sums (the X and Y above, times n) to an
+// N x P side buffer; a last kernel turns them into the a rows and columns of S.
 //
-// Both epilogues scale by 1/n, subtract <O_k>^* <O_k'>, map the row to the
-// parameter index and write the block and its conjugate transpose.  When the
-// tile pairs are too few to fill the device (small P), the sample range is
-// split over `nsplit` workgroups per pair: each writes its raw sums to its own
-// P x P slice, and a reduction adds the slices in split order (deterministic)
-// before scaling and subtracting the means.
+// The main epilogue scales by 1/n, adds the shift terms, subtracts
+// <O_k>^* <O_k'>, maps the row to the parameter index and writes the block and
+// its conjugate transpose.  When the tile pairs are too few to fill the device
+// (small P), the sample range is split over `nsplit` workgroups per pair: each
+// writes its raw sums to its own slice, and reductions add the slices in split
+// order (deterministic, in double) before the same epilogue arithmetic.
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -50,6 +65,7 @@ constexpr int MK_AB = 128;      // a rows per border block
 #define CRBM_MK_KT 128
 #endif
 constexpr int MK_KT = CRBM_MK_KT;   // samples per LDS K tile (BF16 main kernel)
+constexpr int MK_KB = 64;           // K tiles per accumulation block (FP32 main kernel: 4096 samples)
 
 struct SbGeom {
     int N, M;
@@ -68,20 +84,32 @@ static SbGeom sb_geom(int N, int M) {
 }
 
 // ------------------------------------------------------------------ packing
-// planes: Tr[j][s], Ti[j][s] for j < Mp (j >= M -> 0), s < ns_pad (s >= n -> 0)
+// planes: Tr[j][s], Ti[j][s] = T'_sj = T_sj - c_j for j < Mp (j >= M -> 0), s < ns_pad (s >= n -> 0),
+// c_j = shift[N + j] rounded to binary32
 // masks:  Sm[i][s] = sign bit of sigma_si (i < N), 0 for i >= N (sigma~_N = 1 and padding);
 //         row Np holds the sample weights of the a rows: 1 for s < n, 0 for the padded samples
 template <typename E>
-__global__ __launch_bounds__(256) void k_pack_t(const float2* __restrict__ T, long n, int M, int Mp, long ns_pad,
+__global__ __launch_bounds__(256) void k_pack_t(const float2* __restrict__ T, long n, int N, int M, int Mp,
+                                                long ns_pad, const double2* __restrict__ shift,
                                                 E* __restrict__ Tr, E* __restrict__ Ti) {
     __shared__ float2 tile[64][65];
     const long s0 = (long)blockIdx.x * 64;
     const int j0 = blockIdx.y * 64;
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    float2 c = make_float2(0.f, 0.f);
+    if (j0 + tx < M) {
+        const double2 cd = shift[N + j0 + tx];
+        c = make_float2((float)cd.x, (float)cd.y);
+    }
     for (int r = ty; r < 64; r += 4) {
         const long s = s0 + r;
         const int j = j0 + tx;
-        tile[r][tx] = (s < n && j < M) ? T[s * M + j] : make_float2(0.f, 0.f);
+        float2 v = make_float2(0.f, 0.f);
+        if (s < n && j < M) {
+            const float2 t = T[s * M + j];
+            v = make_float2(t.x - c.x, t.y - c.y);
+        }
+        tile[r][tx] = v;
     }
     __syncthreads();
     for (int r = ty; r < 64; r += 4) {
@@ -124,6 +152,65 @@ __device__ __forceinline__ long wb_to_p(int i, int j, int N, int M) {
     return (long)N + M + (long)i * M + j;
 }
 
+// ------------------------------------------------------------------ centring (shift terms in double)
+struct Centre {
+    const float2* bx;       // [N][P] raw border sums: sum_s sigma_si O'_k(s)  (a rows against every parameter)
+    const double2* shift;   // c_j = shift[N + j] rounded to binary32
+    const double2* Om;      // <O_k> of the operands as contracted
+    double inv_n;
+    int N, M;
+    long P;
+};
+__device__ __forceinline__ double2 centre_c(const Centre& c, int j) {
+    const double2 v = c.shift[c.N + j];
+    return make_double2((double)(float)v.x, (double)(float)v.y);
+}
+// X(i, i', j) = <s_i s_i' T'_j> for extended sites i, i' in [0, N]; the pair is taken in one order so
+// that X is symmetric in (i, i') to the bit
+__device__ __forceinline__ double2 centre_x(const Centre& c, int i, int ip, int j) {
+    const int lo = i < ip ? i : ip, hi = i < ip ? ip : i;
+    if (hi < c.N) {
+        const float2 v = c.bx[(long)lo * c.P + (long)c.N + c.M + (long)hi * c.M + j];
+        return make_double2((double)v.x * c.inv_n, (double)v.y * c.inv_n);
+    }
+    const double2 cj = centre_c(c, j);
+    if (lo < c.N) {   // <s_i T'_j> = <O_(i,j)> - c_j <sigma_i>
+        const double2 w = c.Om[(long)c.N + c.M + (long)lo * c.M + j];
+        const double sm = c.Om[lo].x;
+        return make_double2(w.x - sm * cj.x, w.y - sm * cj.y);
+    }
+    const double2 b = c.Om[c.N + j];   // <T'_j> = <O_b_j> - c_j
+    return make_double2(b.x - cj.x, b.y - cj.y);
+}
+// Y(i, i') = <s_i s_i'>: exact integer counts from the border sums, <sigma_i>, or 1
+__device__ __forceinline__ double centre_y(const Centre& c, int i, int ip) {
+    const int lo = i < ip ? i : ip, hi = i < ip ? ip : i;
+    if (hi < c.N) return (double)c.bx[(long)lo * c.P + hi].x * c.inv_n;
+    if (lo < c.N) return c.Om[lo].x;
+    return 1.0;
+}
+// S entry of the W/b rows (i, j) = parameter k and (i', j') = parameter kp from
+// raw = <s_i s_i' T'^*_j T'_j'>
+__device__ __forceinline__ double2 centre_wb(const Centre& c, double2 raw, int i, int j, int ip, int jp, long k,
+                                              long kp) {
+    const double2 cj = centre_c(c, j), cjp = centre_c(c, jp);
+    const double2 x1 = centre_x(c, i, ip, jp), x2 = centre_x(c, i, ip, j);
+    const double y = centre_y(c, i, ip);
+    double2 v = raw;
+    v = zadd(v, zconjmul(cj, x1));                       // c_j^* X(i,i',j')
+    v = zadd(v, zconjmul(x2, cjp));                      // X(i,i',j)^* c_j'
+    const double2 cc = zconjmul(cj, cjp);
+    v = make_double2(v.x + cc.x * y, v.y + cc.y * y);    // c_j^* c_j' Y(i,i')
+    return zsub(v, zconjmul(c.Om[k], c.Om[kp]));
+}
+// extended site and unit of the W/b parameter kp >= N
+__device__ __forceinline__ void wb_of_p(long kp, int N, int M, int& i, int& j) {
+    if (kp < (long)N + M) { i = N; j = (int)(kp - N); return; }
+    const long r = kp - N - M;
+    i = (int)(r / M);
+    j = (int)(r % M);
+}
+
 // Precision policy: BF16 (E = uint16_t, 8 samples per lane fragment) or FP32 (E = uint32_t, 1 sample).
 template <bool BF16>
 struct Pol;
@@ -160,8 +247,7 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
                                                         const typename Pol<BF16>::E* __restrict__ Tr,
                                                         const typename Pol<BF16>::E* __restrict__ Ti,
                                                         const typename Pol<BF16>::E* __restrict__ Sm,
-                                                        const double2* __restrict__ Om, float inv_n,
-                                                        float2* __restrict__ S) {
+                                                        Centre cen, float2* __restrict__ S) {
     using E = typename Pol<BF16>::E;
     constexpr int KT = BF16 ? MK_KT : 64;          // samples per LDS K tile of this precision
     // bytes per LDS row, padded so that the 16 rows of a fragment read fall in distinct banks
@@ -245,6 +331,40 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
     }
     __syncthreads();
 
+    const bool diag = (u == up);
+    const bool raw = nsplit > 1;
+    float2* out = S + (raw ? (long)split * P * P : 0L);
+    // FP32 operands: the matrix-core accumulators' error grows with the count of accumulations, so the
+    // sums run in blocks of MK_KB K tiles (4096 samples), each added to this pair's own entries of the
+    // output (its upper tile; FP32 adds on the vector units) and the accumulators cleared
+    bool flushed = false;
+    auto flush = [&]() {
+        // an opaque copy of the lane index, so that the entry indices are formed here and not kept
+        // live through the K loop
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int qB = ln & 31;
+                const long kp = wb_to_p(sbB * MK_TS + 2 * (2 * wj + b) + (qB >> 4), hbB * MK_TH + (qB & 15), N, M);
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int qA = 8 * (v >> 2) + 4 * (ln >> 5) + (v & 3);
+                    const long k = wb_to_p(sbA * MK_TS + 2 * (2 * wi + a) + (qA >> 4), hbA * MK_TH + (qA & 15), N, M);
+                    if (k >= 0 && kp >= 0) {
+                        float2* o = out + k * P + kp;
+                        const float2 prev = flushed ? *o : make_float2(0.f, 0.f);
+                        *o = make_float2(prev.x + acc_re[a][b][v], prev.y + acc_im[a][b][v]);
+                    }
+                    acc_re[a][b][v] = 0.f;
+                    acc_im[a][b][v] = 0.f;
+                }
+            }
+        flushed = true;
+    };
+
     // fragment rows: lane row q = lane % 32 is (site 2f + q / 16, hidden q % 16) of fragment f
     const int q = lane & 31, lhalf = lane >> 5;
     const int trow = q & 15, qs = q >> 4;
@@ -322,14 +442,14 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
             }
         }
         if (kt + 1 < kt1) lstore(buf ^ 1);
+        if constexpr (!BF16) {
+            if ((kt - kt0 + 1) % MK_KB == 0 && kt + 1 < kt1) flush();
+        }
         __syncthreads();
     }
 
     // epilogue: accumulator element v of lane l is row 8(v/4) + 4(l/32) + v%4 of the A fragment
     // and column l % 32 of the B fragment
-    const bool diag = (u == up);
-    const bool raw = nsplit > 1;
-    float2* out = S + (raw ? (long)split * P * P : 0L);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         const int fA = 2 * wi + a;
@@ -337,20 +457,26 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
         for (int b = 0; b < 2; ++b) {
             const int fB = 2 * wj + b;
             const int qB = lane & 31;
-            const long kp = wb_to_p(sbB * MK_TS + 2 * fB + (qB >> 4), hbB * MK_TH + (qB & 15), N, M);
+            const int iB = sbB * MK_TS + 2 * fB + (qB >> 4), jB = hbB * MK_TH + (qB & 15);
+            const long kp = wb_to_p(iB, jB, N, M);
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int qA = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const long k = wb_to_p(sbA * MK_TS + 2 * fA + (qA >> 4), hbA * MK_TH + (qA & 15), N, M);
+                const int iA = sbA * MK_TS + 2 * fA + (qA >> 4), jA = hbA * MK_TH + (qA & 15);
+                const long k = wb_to_p(iA, jA, N, M);
                 if (k < 0 || kp < 0) continue;
+                float2 sum = make_float2(acc_re[a][b][v], acc_im[a][b][v]);
+                if (flushed) {
+                    const float2 prev = out[k * P + kp];
+                    sum = make_float2(prev.x + sum.x, prev.y + sum.y);
+                }
                 float2 val;
                 if (raw) {
-                    val = make_float2(acc_re[a][b][v], acc_im[a][b][v]);
+                    val = sum;
                 } else {
-                    const double2 mm = zconjmul(Om[k], Om[kp]);
-                    val = make_float2((float)((double)(acc_re[a][b][v] * inv_n) - mm.x),
-                                      (float)((double)(acc_im[a][b][v] * inv_n) - mm.y));
-                    if (k == kp) val.y = 0.f;     // S is Hermitian: its diagonal is real
+                    const double2 r = make_double2((double)sum.x * cen.inv_n, (double)sum.y * cen.inv_n);
+                    const double2 d = centre_wb(cen, r, iA, jA, iB, jB, k, kp);
+                    val = make_float2((float)d.x, k == kp ? 0.f : (float)d.y);   // Hermitian: real diagonal
                 }
                 out[k * P + kp] = val;
                 if (!diag) out[kp * P + k] = cconj(val);
@@ -367,8 +493,7 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_border(SbGeom gm, long ns_pad
                                                        const typename Pol<BF16>::E* __restrict__ Tr,
                                                        const typename Pol<BF16>::E* __restrict__ Ti,
                                                        const typename Pol<BF16>::E* __restrict__ Sm,
-                                                       const double2* __restrict__ Om, float inv_n,
-                                                       float2* __restrict__ S) {
+                                                       float2* __restrict__ bx) {
     using E = typename Pol<BF16>::E;
     constexpr int KT = BF16 ? 64 : 32;
     constexpr int ROWB = KT * (int)sizeof(E) + (BF16 ? 16 : 4);
@@ -514,10 +639,11 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_border(SbGeom gm, long ns_pad
         __syncthreads();
     }
 
-    // epilogue: row = a parameter (site 128 ab + 32 fA + qA); column = W/b row or a parameter
+    // epilogue: row = a parameter (site 128 ab + 32 fA + qA); column = W/b row or a parameter.  The raw
+    // sums go to row k of the N x P side buffer (of this split's slice); an a-row block writes its
+    // transpose as well, so that every entry of the buffer is written.
     const bool diag = colA && abB == ab;
-    const bool raw = nsplit > 1;
-    float2* out = S + (raw ? (long)split * P * P : 0L);
+    float2* out = bx + (long)split * N * P;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         const int fA = 2 * wi + a;
@@ -538,37 +664,74 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_border(SbGeom gm, long ns_pad
                 const int siteA = MK_AB * ab + 32 * fA + qA;
                 const long k = siteA < N ? siteA : -1;
                 if (k < 0 || kp < 0) continue;
-                float2 val;
-                if (raw) {
-                    val = make_float2(acc_re[a][b][v], acc_im[a][b][v]);
-                } else {
-                    const double2 mm = zconjmul(Om[k], Om[kp]);
-                    val = make_float2((float)((double)(acc_re[a][b][v] * inv_n) - mm.x),
-                                      (float)((double)(acc_im[a][b][v] * inv_n) - mm.y));
-                    if (k == kp) val.y = 0.f;
-                }
+                const float2 val = make_float2(acc_re[a][b][v], acc_im[a][b][v]);
                 out[k * P + kp] = val;
-                if (!diag) out[kp * P + k] = cconj(val);
+                if (colA && !diag) out[kp * P + k] = val;     // Y is real and symmetric
             }
         }
     }
 }
 
-// S = (sum over the split slices, in split order, in double) / n - <O_k>^* <O_k'>, real diagonal
-__global__ __launch_bounds__(256) void k_sbuild_reduce(long P, int nsplit, const float2* __restrict__ part,
-                                                       const double2* __restrict__ Om, double inv_n,
+// bx = the border sums of the nsplit slices, added in split order in double
+__global__ __launch_bounds__(256) void k_bx_reduce(long count, int nsplit, const float2* __restrict__ part,
+                                                   float2* __restrict__ bx) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= count) return;
+    double x = 0.0, y = 0.0;
+    for (int s = 0; s < nsplit; ++s) {
+        const float2 v = part[(long)s * count + e];
+        x += (double)v.x;
+        y += (double)v.y;
+    }
+    bx[e] = make_float2((float)x, (float)y);
+}
+
+// The a rows and columns of S from the border sums: k = a_i, kp any parameter,
+//   S[a_i][a_i'] = Y(i,i') - <sigma_i><sigma_i'>,
+//   S[a_i][(i',j')] = X(i,i',j') + c_j' Y(i,i') - <sigma_i> <O_(i',j')>   (and its conjugate at [kp][k]).
+__global__ __launch_bounds__(256) void k_sbuild_arows(Centre cen, float2* __restrict__ S) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    const int N = cen.N, M = cen.M;
+    const long P = cen.P;
+    if (e >= (long)N * P) return;
+    const int i = (int)(e / P);
+    const long kp = e % P;
+    const double2 mm = zconjmul(cen.Om[i], cen.Om[kp]);
+    if (kp < N) {
+        const double y = centre_y(cen, i, (int)kp);
+        S[(long)i * P + kp] = make_float2((float)(y - mm.x), 0.f);
+        return;
+    }
+    int ip, jp;
+    wb_of_p(kp, N, M, ip, jp);
+    const double2 x = centre_x(cen, i, ip, jp);
+    const double2 cjp = centre_c(cen, jp);
+    const double y = centre_y(cen, i, ip);
+    const float2 val = make_float2((float)(x.x + cjp.x * y - mm.x), (float)(x.y + cjp.y * y - mm.y));
+    S[(long)i * P + kp] = val;
+    S[kp * P + i] = cconj(val);
+}
+
+// W/b entries of S from the split slices: their sums (in split order, in double) / n with the shift
+// terms and the means, real diagonal.  The a rows and columns come from k_sbuild_arows.
+__global__ __launch_bounds__(256) void k_sbuild_reduce(Centre cen, int nsplit, const float2* __restrict__ part,
                                                        float2* __restrict__ S) {
+    const long P = cen.P;
     const long e = (long)blockIdx.x * 256 + threadIdx.x;
     if (e >= P * P) return;
     const long k = e / P, kp = e % P;
+    if (k < cen.N || kp < cen.N) return;
     double x = 0.0, y = 0.0;
     for (int s = 0; s < nsplit; ++s) {
         const float2 v = part[(long)s * P * P + e];
         x += (double)v.x;
         y += (double)v.y;
     }
-    const double2 mm = zconjmul(Om[k], Om[kp]);
-    S[e] = make_float2((float)(x * inv_n - mm.x), k == kp ? 0.f : (float)(y * inv_n - mm.y));
+    int i, j, ip, jp;
+    wb_of_p(k, cen.N, cen.M, i, j);
+    wb_of_p(kp, cen.N, cen.M, ip, jp);
+    const double2 d = centre_wb(cen, make_double2(x * cen.inv_n, y * cen.inv_n), i, j, ip, jp, k, kp);
+    S[e] = make_float2((float)d.x, k == kp ? 0.f : (float)d.y);
 }
 
 // Number of sample splits for a contraction of n samples: about eight workgroups per compute unit
@@ -587,22 +750,34 @@ int sbuild_splits(int N, int M, long n, int n_cu, int max_splits) {
 }
 
 // ------------------------------------------------------------------ launcher
-hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n, const double2* Om,
-                              float2* S, int prec, void* pack, size_t pack_bytes, const int2* order, long n_order,
-                              float2* split_buf, int nsplit, Profiler* prof, hipStream_t stream) {
+// shift: <O> of the unrounded operands (c_j from its b entries); Om: <O> of the operands as contracted
+// (T' rounded as packed, plus c); bx: N x P side buffer; bx_part: nsplit of them when nsplit > 1.
+hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n,
+                              const double2* shift, const double2* Om, float2* S, int prec, void* pack,
+                              size_t pack_bytes, const int2* order, long n_order, float2* split_buf, int nsplit,
+                              float2* bx, float2* bx_part, Profiler* prof, hipStream_t stream) {
     const SbGeom gm = sb_geom(N, M);
-    if (nsplit > 1 && !split_buf) return hipErrorInvalidValue;
+    if (nsplit > 1 && (!split_buf || !bx_part)) return hipErrorInvalidValue;
+    if (!bx) return hipErrorInvalidValue;
     const long ns_pad = ((n + MK_KT - 1) / MK_KT) * MK_KT;
     static_assert(MK_KT % 64 == 0, "the packing grid assumes 64-sample blocks");
     const bool bf16 = (prec == CRBM_PREC_BF16);
     const size_t esz = bf16 ? 2 : 4;
     const size_t need = esz * ((size_t)2 * gm.Mp * ns_pad + (size_t)(gm.Np + 1) * ns_pad);
     if (need > pack_bytes) return hipErrorOutOfMemory;
-    const float inv_n = 1.0f / (float)n;
+    Centre cen;
+    cen.bx = bx;
+    cen.shift = shift;
+    cen.Om = Om;
+    cen.inv_n = 1.0 / (double)n;
+    cen.N = N;
+    cen.M = M;
+    cen.P = P;
     const dim3 gt((unsigned)(ns_pad / 64), (unsigned)((gm.Mp + 63) / 64));
     const long ms = (long)(gm.Np + 1) * ns_pad;
     const int nA = (N + MK_AB - 1) / MK_AB;
     const int nX = gm.nSB * gm.nHB + nA;
+    const long nbx = (long)N * P;
     auto run = [&](auto tag) {
         using E = typename decltype(tag)::E;
         constexpr bool B16 = sizeof(E) == 2;
@@ -610,21 +785,27 @@ hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const flo
         E* Ti = Tr + (size_t)gm.Mp * ns_pad;
         E* Sm = Ti + (size_t)gm.Mp * ns_pad;
         prof->begin(PROF_PACK, stream);
-        hipLaunchKernelGGL(k_pack_t<E>, gt, dim3(256), 0, stream, T, n, M, gm.Mp, ns_pad, Tr, Ti);
+        hipLaunchKernelGGL(k_pack_t<E>, gt, dim3(256), 0, stream, T, n, N, M, gm.Mp, ns_pad, shift, Tr, Ti);
         hipLaunchKernelGGL(k_pack_sig<E>, dim3((unsigned)((ms + 255) / 256)), dim3(256), 0, stream, sig, n, N, gm.Np,
                            ns_pad, Sm);
         prof->end(stream);
-        float2* out = nsplit > 1 ? split_buf : S;
-        prof->begin(PROF_SBUILD, stream);
-        hipLaunchKernelGGL(k_sbuild_mfma<B16>, dim3((unsigned)(n_order * nsplit)), dim3(256), 0, stream, gm, order,
-                           n_order, ns_pad, nsplit, Tr, Ti, Sm, Om, inv_n, out);
-        prof->end(stream);
+        // the border sums first: the main epilogue reads them
         prof->begin(PROF_SBORDER, stream);
         hipLaunchKernelGGL(k_sbuild_border<B16>, dim3((unsigned)(nA * nX * nsplit)), dim3(256), 0, stream, gm, ns_pad,
-                           nA, nsplit, Tr, Ti, Sm, Om, inv_n, out);
+                           nA, nsplit, Tr, Ti, Sm, nsplit > 1 ? bx_part : bx);
         if (nsplit > 1)
-            hipLaunchKernelGGL(k_sbuild_reduce, dim3((unsigned)((P * P + 255) / 256)), dim3(256), 0, stream, P, nsplit,
-                               split_buf, Om, 1.0 / (double)n, S);
+            hipLaunchKernelGGL(k_bx_reduce, dim3((unsigned)((nbx + 255) / 256)), dim3(256), 0, stream, nbx, nsplit,
+                               bx_part, bx);
+        prof->end(stream);
+        prof->begin(PROF_SBUILD, stream);
+        hipLaunchKernelGGL(k_sbuild_mfma<B16>, dim3((unsigned)(n_order * nsplit)), dim3(256), 0, stream, gm, order,
+                           n_order, ns_pad, nsplit, Tr, Ti, Sm, cen, nsplit > 1 ? split_buf : S);
+        prof->end(stream);
+        prof->begin(PROF_SBORDER, stream);
+        if (nsplit > 1)
+            hipLaunchKernelGGL(k_sbuild_reduce, dim3((unsigned)((P * P + 255) / 256)), dim3(256), 0, stream, cen,
+                               nsplit, split_buf, S);
+        hipLaunchKernelGGL(k_sbuild_arows, dim3((unsigned)((nbx + 255) / 256)), dim3(256), 0, stream, cen, S);
         prof->end(stream);
     };
     if (bf16) run(Pol<true>{});

@@ -228,7 +228,7 @@ __device__ __forceinline__ void ot_load(OtRaw<NK>& r, int tid, int row, int M, i
                                         const int8_t* __restrict__ sig16, const float2* __restrict__ T, int kind0,
                                         int kind1, const double* __restrict__ w, double wdef,
                                         const float2* __restrict__ R, const double2* __restrict__ u,
-                                        double two_over_n, int round_bf16) {
+                                        double two_over_n, int round_bf16, const double2* __restrict__ shift_b) {
     const long s = sb + (tid >> 3);
     const int g = tid & 7;
     const bool in = s < s_end;
@@ -244,6 +244,10 @@ __device__ __forceinline__ void ot_load(OtRaw<NK>& r, int tid, int row, int M, i
         const int j = j0 + 4 * g + k;
         float2 t = make_float2(0.f, 0.f);
         if (in && j <= M) t = (j == M) ? make_float2(1.f, 0.f) : trow[j];
+        if (shift_b && in && j < M) {
+            const double2 c = shift_b[j];
+            t = make_float2(t.x - (float)c.x, t.y - (float)c.y);
+        }
         if (round_bf16) t = make_float2(round_to_bf16(t.x), round_to_bf16(t.y));
         r.t[k] = cconj(t);
     }
@@ -261,7 +265,8 @@ __device__ __forceinline__ void ot_stage(OtRaw<NK>& raw, float (&sA)[OM_S][OM_R 
                                          int M, int i0, int j0, long sb, long s_end, const int8_t* __restrict__ sig16,
                                          const float2* __restrict__ T, int kind0, int kind1,
                                          const double* __restrict__ w, double wdef, const float2* __restrict__ R,
-                                         const double2* __restrict__ u, double two_over_n, int round_bf16) {
+                                         const double2* __restrict__ u, double two_over_n, int round_bf16,
+                                         const double2* __restrict__ shift_b) {
     const int ss = tid >> 3, g = tid & 7;
     if (tid < NK * OM_S) sC[tid / OM_S][tid % OM_S] = raw.cf;
 #pragma unroll
@@ -281,7 +286,7 @@ __device__ __forceinline__ void ot_stage(OtRaw<NK>& raw, float (&sA)[OM_S][OM_R 
     // the next tile's loads, in flight during the products
     if (sb + OM_S < s_end)
         ot_load<NK>(raw, tid, row, M, i0, j0, sb + OM_S, s_end, sig16, T, kind0, kind1, w, wdef, R, u, two_over_n,
-                    round_bf16);
+                    round_bf16, shift_b);
 }
 
 // One coefficient vector: four waves per SIMD in 128 registers; two: three waves in 168 (no spills in
@@ -292,7 +297,8 @@ __global__ __launch_bounds__(256, NK == 1 ? 4 : 3) void k_ot(int N, int M, int r
                                             long n, long chunk, int n_chunks, int kind0, int kind1,
                                             const double* __restrict__ w, const float2* __restrict__ R,
                                             const double2* __restrict__ u, float* __restrict__ partial,
-                                            const double* __restrict__ skip, int round_bf16) {
+                                            const double* __restrict__ skip, int round_bf16,
+                                            const double2* __restrict__ shift_b) {
     if (skip && *skip != 0.0) return;
     __shared__ __align__(16) float sA[OM_S][OM_R + 4];      // sigma~ [sample][site]
     __shared__ __align__(16) float sY[NK][2][OM_S][OM_C];   // y [c][Re/Im][sample][unit]
@@ -309,12 +315,12 @@ __global__ __launch_bounds__(256, NK == 1 ? 4 : 3) void k_ot(int N, int M, int r
         const long s_end = min(n, s_begin + chunk);
         OtRaw<NK> raw;
         ot_load<NK>(raw, tid, row, M, i0, j0, s_begin, s_end, sig16, T, kind0, kind1, w, wdef, R, u, two_over_n,
-                    round_bf16);
+                    round_bf16, shift_b);
         if (i0 + 32 * wv > N) {
             // no extended site in this wave's rows: it only helps to stage the tiles
             for (long sb = s_begin; sb < s_end; sb += OM_S) {
                 ot_stage<NK>(raw, sA, sY, sC, tid, row, M, i0, j0, sb, s_end, sig16, T, kind0, kind1, w, wdef, R, u,
-                             two_over_n, round_bf16);
+                             two_over_n, round_bf16, shift_b);
                 __syncthreads();
             }
             continue;
@@ -328,7 +334,7 @@ __global__ __launch_bounds__(256, NK == 1 ? 4 : 3) void k_ot(int N, int M, int r
                 for (int v = 0; v < 16; ++v) acc[c][ri][v] = 0.f;
         for (long sb = s_begin; sb < s_end; sb += OM_S) {
             ot_stage<NK>(raw, sA, sY, sC, tid, row, M, i0, j0, sb, s_end, sig16, T, kind0, kind1, w, wdef, R, u,
-                         two_over_n, round_bf16);
+                         two_over_n, round_bf16, shift_b);
             // lane l supplies row l % 32 (A) and column l % 32 (B) at sample 2 ks + l / 32; rows past N are zeros
 #pragma unroll 4
             for (int ks = 0; ks < OM_S / 2; ++ks) {
@@ -361,9 +367,12 @@ __global__ __launch_bounds__(256, NK == 1 ? 4 : 3) void k_ot(int N, int M, int r
     }
 }
 
-// out[c][P-index] = sum over chunks of the FP32 chunk sums (in FP64), with optional conjugation.
+// out[c][P-index] = sum over chunks of the FP32 chunk sums (in FP64), with optional conjugation.  With
+// shift_b (coefficient vector 0, real): the chunks summed T - c_j for the units j < M, and c_j (or its
+// conjugate) times the sum of sigma~_i (the column j = M; 1 for the b row) is added back here.
 __global__ void k_ot_reduce(int N, int M, const float* __restrict__ partial, int n_chunks, int nk, int conj0,
-                            double2* __restrict__ out0, double2* __restrict__ out1, const double* __restrict__ skip) {
+                            double2* __restrict__ out0, double2* __restrict__ out1, const double* __restrict__ skip,
+                            const double2* __restrict__ shift_b) {
     if (skip && *skip != 0.0) return;
     const long plane = (long)(N + 1) * (M + 1);
     const long o = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -379,6 +388,17 @@ __global__ void k_ot_reduce(int N, int M, const float* __restrict__ partial, int
             acc.y += (double)pc[plane + o];
         }
         if (c == 0 && conj0) acc.y = -acc.y;
+        if (c == 0 && shift_b && j < M) {
+            double y = 1.0;
+            if (i < N) {
+                const long oy = (long)i * (M + 1) + M;
+                y = 0.0;
+                for (int b = 0; b < n_chunks; ++b) y += (double)partial[(long)b * nk * 2 * plane + oy];
+            }
+            const double cx = (double)(float)shift_b[j].x, cy = (double)(float)shift_b[j].y;
+            acc.x += cx * y;
+            acc.y += (conj0 ? cy : -cy) * y;
+        }
         (c == 0 ? out0 : out1)[k] = acc;
     }
 }
@@ -424,7 +444,7 @@ static OtPlan ot_plan(int N, int M, long n, int nk, int n_cu) {
 static hipError_t run_ot(int N, int M, const int8_t* sig16, const float2* T, long n, int kind0, int kind1, int nk,
                          const double* w, const float2* R, const double2* u, void* partial_buf, int conj0,
                          double2* out0, double2* out1, hipStream_t stream, const double* skip, Profiler* prof,
-                         int n_cu, int round_bf16 = 0) {
+                         int n_cu, int round_bf16 = 0, const double2* shift_b = nullptr) {
     const OtPlan op = ot_plan(N, M, n, nk, n_cu);
     const int row = sig16_row(N);
     float* partial = static_cast<float*>(partial_buf);
@@ -432,14 +452,14 @@ static hipError_t run_ot(int N, int M, const int8_t* sig16, const float2* T, lon
     if (prof) prof->begin(PROF_OT, stream);
     if (nk == 2)
         hipLaunchKernelGGL(k_ot<2>, grid, dim3(256), 0, stream, N, M, row, sig16, T, n, op.chunk, op.n_chunks, kind0,
-                           kind1, w, R, u, partial, skip, round_bf16);
+                           kind1, w, R, u, partial, skip, round_bf16, shift_b);
     else
         hipLaunchKernelGGL(k_ot<1>, grid, dim3(256), 0, stream, N, M, row, sig16, T, n, op.chunk, op.n_chunks, kind0,
-                           kind1, w, R, u, partial, skip, round_bf16);
+                           kind1, w, R, u, partial, skip, round_bf16, shift_b);
     if (prof) prof->end(stream);
     const long plane = (long)(N + 1) * (M + 1);
     hipLaunchKernelGGL(k_ot_reduce, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, stream, N, M, partial,
-                       op.n_chunks, nk, conj0, out0, out1, skip);
+                       op.n_chunks, nk, conj0, out0, out1, skip, shift_b);
     return hipGetLastError();
 }
 
@@ -927,9 +947,10 @@ static inline unsigned nblk(long n, int t = 256) { return (unsigned)((n + t - 1)
 
 hipError_t launch_cholesky_solve(long P, const float2* S, double eps, const double2* F, double2* A64, double2* x,
                                  double* sc, bool a64_holds_s, hipStream_t stream);
-hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n, const double2* Om,
-                              float2* S, int prec, void* pack, size_t pack_bytes, const int2* order, long n_order,
-                              float2* split_buf, int nsplit, Profiler* prof, hipStream_t stream);
+hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n,
+                              const double2* shift, const double2* Om, float2* S, int prec, void* pack,
+                              size_t pack_bytes, const int2* order, long n_order, float2* split_buf, int nsplit,
+                              float2* bx, float2* bx_part, Profiler* prof, hipStream_t stream);
 int sbuild_splits(int N, int M, long n, int n_cu, int max_splits);
 
 static hipError_t apply_op(const SrArgs& A, const SrWork& W, const double2* v, double2* y, hipStream_t stream) {
@@ -989,18 +1010,17 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
 
     if (A.solver != CRBM_SOLVER_CG_MATFREE) {
         if (A.weights == nullptr) {
-            // With BF16 operands the subtracted mean comes from the same rounded operands, so that
-            // S stays the centred Gram matrix of one set of vectors (positive semi-definite).
-            const double2* om_s = W.Om;
-            if (A.prec == CRBM_PREC_BF16) {
-                e = run_ot(A.N, A.M, W.sig16, A.T, A.n, 0, 0, 1, nullptr, A.R, nullptr, W.red, 1, W.Om16, nullptr,
-                           stream, nullptr, nullptr, W.n_cu, 1);
-                if (e != hipSuccess) return e;
-                om_s = W.Om16;
-            }
+            // The contraction sees T' = T - c (c = <T> in binary32; rounded to BF16 with BF16 operands).
+            // The subtracted means are those of the same operands, T' + c, summed as T' in the chunks
+            // with c <sigma~> added in double: S stays the centred Gram matrix of one set of vectors
+            // (positive semi-definite) and no sum carries |c|^2 against the spread of T.
+            e = run_ot(A.N, A.M, W.sig16, A.T, A.n, 0, 0, 1, nullptr, A.R, nullptr, W.red, 1, W.Om16, nullptr,
+                       stream, nullptr, nullptr, W.n_cu, A.prec == CRBM_PREC_BF16 ? 1 : 0, W.Om + A.N);
+            if (e != hipSuccess) return e;
             const int nsplit = W.spart ? sbuild_splits(A.N, A.M, A.n, W.n_cu, W.nsplit_max) : 1;
-            e = launch_sbuild_mfma(A.N, A.M, P, A.samples, A.T, A.n, om_s, W.S, A.prec, W.pack, W.pack_bytes,
-                                   W.sb_order, W.sb_order_len, W.spart, nsplit, W.prof, stream);
+            e = launch_sbuild_mfma(A.N, A.M, P, A.samples, A.T, A.n, W.Om, W.Om16, W.S, A.prec, W.pack,
+                                   W.pack_bytes, W.sb_order, W.sb_order_len, W.spart, nsplit, W.bx, W.bx_part,
+                                   W.prof, stream);
         } else {
             // weighted (enumeration) sums: FP32 contraction on the vector units
             const int nt = (int)((P + SB_T - 1) / SB_T);

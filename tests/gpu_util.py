@@ -63,3 +63,33 @@ def eloc_rounding_bound(rbm, bonds, sig, J=1.0):
         rho = np.abs(np.exp(lp2 - lp0[anti]))
         out[anti] += 0.5 * J * rho * (logpsi_rounding_bound(rbm, s2) + base[anti])
     return out
+
+
+def log_amp_scale(rbm, sig):
+    """max over the rows of sig of sum_j |theta_j| + |a . sigma|: the size of the terms whose binary32
+    sums make log psi (theta = b + sigma W)."""
+    s = np.asarray(sig, np.float64)
+    th = rbm.b[None, :] + s @ rbm.W
+    return float(np.max(np.abs(th).sum(axis=1) + np.abs(s @ rbm.a)))
+
+
+def lattice_images(sig, Lx, Ly, rotations):
+    """Every translation (and, with rotations, every rotation by a multiple of pi/2) of each row of sig
+    on the Lx x Ly torus, stacked: the configurations the symmetry projection evaluates."""
+    g = np.asarray(sig).reshape(-1, Ly, Lx)
+    out = []
+    for r in range(4 if rotations else 1):
+        gr = np.rot90(g, r, axes=(1, 2))
+        for dy in range(Ly):
+            for dx in range(Lx):
+                out.append(np.roll(np.roll(gr, dy, axis=1), dx, axis=2).reshape(g.shape[0], -1))
+    return np.concatenate(out)
+
+
+def ratio_gram_tol(L_states, L_gs, floor=1e-5):
+    """Tolerance of G and H (relative to their largest entry) for basis ratios r = t / psi_gs formed from
+    binary32 log amplitudes.  Each log psi is a binary32 tree sum of depth at most 8 (two units per lane,
+    six lane levels, the log of the product factor) of terms of total size L, so |d log psi| <= 8 u L
+    (u = 2^-24); a ratio carries two of them and a Gram entry <r_k^* r_k'> two ratios, and by
+    Cauchy-Schwarz |<r_k^* r_k'>| <= max|G|: 16 u (L_t + L_gs), L_t the largest over the states."""
+    return max(floor, 16.0 * EPS32 * (L_states + L_gs))

@@ -92,3 +92,23 @@ def test_sr_entries_match_the_full_step(orc):
         O = orc.logderiv(rbm, sig)
         wt = np.full(sig.shape[0], 1.0 / sig.shape[0]) if w is None else w
         assert np.max(np.abs(e["Om"] - wt @ O[:, ks])) < 1e-13
+
+
+def test_sr_diagonal_matches_the_full_step(orc):
+    """The diagonal-only form equals the full step's diagonal of S and the means of O, weighted and
+    uniform, including a model whose b puts |<tanh theta>| far above its spread (the diagonal of the b
+    rows is then small against |<O>|^2)."""
+    rbm, sig, p, R = _setup(orc, N=7, M=5, seed=9)
+    biased = orc.RBM(rbm.a, rbm.b + 2.5, rbm.W)
+    for model in (rbm, biased):
+        for w in (p, None):
+            _, info = orc.sr_step(model, sig, R, 0.2, 1e-3, weights=w, want_S=True)
+            d, Om = orc.sr_diagonal(model, sig, weights=w)
+            assert np.max(np.abs(d - np.real(np.diag(info["S"])))) < 1e-13
+            O = orc.logderiv(model, sig)
+            wt = np.full(sig.shape[0], 1.0 / sig.shape[0]) if w is None else w
+            assert np.max(np.abs(Om - wt @ O)) < 1e-13
+            assert np.all(d >= -1e-15)
+    # the biased b rows: spread of tanh far below its mean
+    d, Om = orc.sr_diagonal(biased, sig)
+    assert np.all(d[7:12] < 0.05 * np.abs(Om[7:12]) ** 2)
