@@ -81,8 +81,8 @@ def parse():
     ap.add_argument("--n-moments", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-compare", action="store_true")
-    ap.add_argument("--fp32-fraction", type=int, default=16,
-                    help="the plain-FP32 S contraction is timed on N_s / this many samples and scaled")
+    ap.add_argument("--fit-steps", type=int, default=60,
+                    help="natural-gradient steps per order in the BF16-vs-FP32 fit-quality comparison")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
     ap.add_argument("--workload", choices=["square10", "batched8x8", "chain40", "grad16x16", "spectral10x10",
                                            "groundstate10x10", "symmetry6x6"], default="square10",
@@ -158,10 +158,10 @@ def main():
     crbm.sample(plan, gs, chains_gs, 16, crbm.EXCHANGE, 12, 0)
     offset = [16 * N]
 
-    def step():
+    def step(s_prec=prec):
         crbm.sample(plan, fit, chains_fit, sweeps, crbm.EXCHANGE, 11, offset[0], samples_out=samples)
         crbm.local_estimators(plan, fit, flat, psi_n=psn, psi_nm1=psm, cheb=cheb, eloc_out=El, R_out=R, tanh_out=T)
-        crbm.sr_step(plan, fit, flat, T, R, 0.1, wl.diag_shift, solver, prec, 1e-6, args.cg_maxit, stats)
+        crbm.sr_step(plan, fit, flat, T, R, 0.1, wl.diag_shift, solver, s_prec, 1e-6, args.cg_maxit, stats)
         crbm.sample(plan, gs, chains_gs, sweeps, crbm.EXCHANGE, 12, offset[0], samples_out=samples_gs)
         crbm.chebyshev_moment(plan, gs, tp, betas, [(math.pi, math.pi)], flat_gs, mu)
         offset[0] += sweeps * N
@@ -253,10 +253,11 @@ def main():
         "sampler_roofline": sampler,
     }
     if not args.no_fp32_compare and solver == crbm.CG_DENSE and prec == crbm.BF16:
-        line["fp32_compare"] = fp32_compare(crbm, plan, fit, flat, T, R, wl, args, ms_per_step, prof)
         line["matfree_compare"] = matfree_compare(crbm, plan, fit, flat, T, R, wl, args, ms_per_step, prof)
+        line["fp32_compare"] = fp32_compare(crbm, plan, fit, step, flat, T, R, wl, args, ms_per_step, stats)
+        line["fit_quality_bf16_vs_fp32"] = fit_quality_compare(crbm, args.fit_steps)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"], line["mu_error"] = cpu_baseline(args.cpu_budget_s, ns, sweeps, C)
+        line["cpu_baseline"], line["moments_vs_oracle"] = cpu_baseline(args.cpu_budget_s, ns, sweeps, C)
     print(json.dumps(line))
     plan.close()
 
@@ -568,40 +569,109 @@ def bench_grad16(crbm, args):
     plan.close()
 
 
-def fp32_compare(crbm, plan, fit, flat, T, R, wl, args, ms_per_step, prof):
-    """The plain FP32 path: the same step with FP32 operands in the S contraction.
-
-    The FP32 contraction is timed on the first N_s/k samples (its cost is linear in
-    the sample count) and scaled by k; the other stages are shared with the BF16 step.
-    The BF16 and FP32 steps' dalpha are compared on that sub-sample."""
-    k = args.fp32_fraction
-    ns = flat.shape[0]
-    nk = ns // k
-    sub_s, sub_T, sub_R = flat[:nk], T[:nk], R[:nk]
-    stats = torch.zeros(8, dtype=torch.float64, device="cuda")
-    out = {}
+def fp32_compare(crbm, plan, fit, step, flat, T, R, wl, args, ms_per_step, stats):
+    """The plain FP32 path, measured: one whole step (sampling, local estimators, the natural-gradient step
+    with FP32 operands in the S contraction, the moments) timed end to end after the BF16 steps; then the
+    BF16 step is re-run from the state and samples that FP32 step started from, and the two updates dalpha
+    are compared over all N_s = 524,288 samples (N_s > P)."""
     P = wl.P
-    dal = {}
-    for name, pr in (("fp32", crbm.FP32), ("bf16", crbm.BF16)):
-        f = crbm.RBM(fit.a.clone(), fit.b.clone(), fit.W.clone())
-        plan.profile(True)
-        crbm.sr_step(plan, f, sub_s, sub_T, sub_R, 0.1, wl.diag_shift, crbm.CG_DENSE, pr, 1e-6, args.cg_maxit, stats)
-        pr_ = plan.profile_read()
-        plan.profile(False)
-        dx = torch.zeros(P, dtype=torch.complex128, device="cuda")
-        crbm.copy_plan_buffer(plan, crbm.BUF_DALPHA, dx)
+    f0 = crbm.RBM(fit.a.clone(), fit.b.clone(), fit.W.clone())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    step(crbm.FP32)
+    torch.cuda.synchronize()
+    fp32_ms = (time.perf_counter() - t0) * 1e3
+    st32 = stats.cpu().numpy().copy()
+    d32 = torch.zeros(P, dtype=torch.complex128, device="cuda")
+    crbm.copy_plan_buffer(plan, crbm.BUF_DALPHA, d32)
+    # the BF16 step on the same state (f0) and the same samples, T and R (flat, T and R still hold them)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    crbm.sr_step(plan, f0, flat, T, R, 0.1, wl.diag_shift, crbm.CG_DENSE, crbm.BF16, 1e-6, args.cg_maxit, stats)
+    torch.cuda.synchronize()
+    bf16_sr_ms = (time.perf_counter() - t0) * 1e3
+    st16 = stats.cpu().numpy().copy()
+    d16 = torch.zeros(P, dtype=torch.complex128, device="cuda")
+    crbm.copy_plan_buffer(plan, crbm.BUF_DALPHA, d16)
+    torch.cuda.synchronize()
+    diff = d16 - d32
+    rel2 = float(torch.linalg.vector_norm(diff) / torch.linalg.vector_norm(d32))
+    relmax = float(diff.abs().max() / d32.abs().max())
+    ns = flat.shape[0]
+    return {"fp32_ms_per_step": fp32_ms, "fp32_samples_per_s": ns / (fp32_ms / 1e3),
+            "bf16_speedup_vs_fp32": fp32_ms / ms_per_step,
+            "bf16_sr_step_ms_same_inputs": bf16_sr_ms,
+            "samples": ns, "P": P,
+            "dalpha_rel_diff_l2": rel2, "dalpha_rel_diff_max": relmax,
+            "gamma": float(st32[0]), "cg_iterations": {"fp32": float(st32[5]), "bf16": float(st16[5])},
+            "note": ("fp32_ms_per_step: one whole step with FP32 S timed end to end (not scaled); dalpha of a BF16 "
+                     "and an FP32 solve from the same state and samples")}
+
+
+def fit_quality_compare(crbm, n_steps, n_orders=2):
+    """Fit quality with BF16 and with FP32 operands in the S contraction: the first Chebyshev vectors
+    t~_1, t~_2 of S^z(pi, pi) psi_gs on the 4x4 lattice, alpha = 4 (P = 1,104), fitted by Monte Carlo
+    natural-gradient steps (256 chains x 32 pair-exchange sweeps per step, dense CG, n_steps per order), from
+    identical starting states, chains and sampler seeds.  Per precision, by exact enumeration of the 12,870
+    configurations with S^z = 0 (the sector the pair-exchange chains and H keep): the infidelity gamma of each
+    fitted vector to its target, and the moments mu_1, mu_2 of the fitted sequence."""
+    from paper_2103_08804_amd import recursion as rc
+    wl = synth.SQUARE4
+    N, M = wl.N, wl.M
+    q = (math.pi, math.pi)
+    cfg = synth.all_configs(N)
+    sector = torch.from_numpy(np.ascontiguousarray(cfg[cfg.astype(np.int32).sum(axis=1) == 0])).cuda()
+    n_enum = sector.shape[0]
+    plan = crbm.Plan(crbm.SQUARE, wl.Lx, wl.Ly, M, max(wl.n_samples, n_enum), crbm.PLAN_DENSE_S)
+    gs = crbm.RBM.empty(N, M)
+    crbm.init_rbm(gs, wl.param_seed, wl.param_std)
+    t1 = crbm.RBM(gs.a.clone(), gs.b.clone(), gs.W.clone())
+    r = torch.arange(N, device="cuda")
+    t1.a += (0.1 * torch.exp(-1j * (q[0] * (r % wl.Lx) + q[1] * (r // wl.Lx)))).to(torch.complex64)
+    E0 = synth.E0_PER_SITE_SQUARE * N
+    W_scale = 1.5 * abs(E0)
+    E_c = E0 + (1.0 - 0.0125) * W_scale
+    chains0 = torch.zeros(wl.chains, N, dtype=torch.int8, device="cuda")
+    crbm.init_chains(plan, chains0, wl.chain_seed, True)
+    crbm.sample(plan, gs, chains0, 16, crbm.EXCHANGE, wl.chain_seed, 0)
+    out = {}
+    lp = torch.empty(n_enum, dtype=torch.complex64, device="cuda")
+    w = torch.empty(n_enum, dtype=torch.float64, device="cuda")
+    R = torch.empty(n_enum, dtype=torch.complex64, device="cuda")
+    fs = torch.empty(5, dtype=torch.float64, device="cuda")
+    for name, pr in (("bf16", crbm.BF16), ("fp32", crbm.FP32)):
+        settings = rc.FitSettings(n_steps=n_steps, dgamma=0.2, diag_shift=wl.diag_shift, solver=crbm.CG_DENSE,
+                                  precision=pr, cg_tol=1e-8, cg_maxit=2000)
         torch.cuda.synchronize()
-        dal[name] = dx
-        out[name + "_sbuild_ms_sub"] = pr_["sbuild"][1] / pr_["sbuild"][0]
-    fp32_build_full = out["fp32_sbuild_ms_sub"] * k
-    bf16_build = prof["sbuild"][1] / prof["sbuild"][0]
-    fp32_step = ms_per_step - bf16_build + fp32_build_full
-    rel = float((dal["bf16"] - dal["fp32"]).abs().max() / dal["fp32"].abs().max())
-    return {"sub_samples": nk, "fp32_sbuild_ms_scaled": fp32_build_full, "fp32_ms_per_step": fp32_step,
-            "fp32_samples_per_s": ns / (fp32_step / 1e3), "bf16_speedup_vs_fp32": fp32_step / ms_per_step,
-            "fp32_sbuild_tflops": 4.0 * P * (P + 1) * nk / (out["fp32_sbuild_ms_sub"] / 1e3) / 1e12,
-            "dalpha_bf16_vs_fp32_rel_diff": rel,
-            "mu_n": "identical in both paths (moments do not use S)"}
+        t0 = time.perf_counter()
+        rec = rc.chebyshev_recursion(plan, gs, t1, n_orders, q, E_c, W_scale, settings, chains=chains0.clone(),
+                                     sweeps=wl.sweeps, seed=wl.chain_seed + 1)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        # exact infidelity of every fitted vector to its target (target built from the fitted predecessors)
+        gam = []
+        for n in range(n_orders):
+            cur = rec.rbm(n, N, M)
+            psi_n = gs if n == 0 else rec.rbm(n - 1, N, M)
+            psi_nm1 = None if n == 0 else (gs if n == 1 else rec.rbm(n - 2, N, M))
+            b_n = 1.0 if n == 0 else complex(rec.betas[n - 1].item())
+            b_nm1 = 1.0 if n <= 1 else complex(rec.betas[n - 2].item())
+            cheb = crbm.make_cheb(n, E_c, W_scale, b_n, b_nm1, q)
+            crbm.local_estimators(plan, cur, sector, psi_n=psi_n, psi_nm1=psi_nm1, cheb=cheb, logpsi_out=lp, R_out=R)
+            crbm.enum_weights(plan, lp, w)
+            crbm.fit_stats(plan, R, fs, weights=w)
+            gam.append(float(fs[0].item()))
+        mu = rc.sequence_moments(plan, gs, rec, [q], sector, True)[0].cpu().numpy()
+        out[name] = {"gamma_exact": gam, "gamma_mc_last_step": rec.final_stats[:, 0].cpu().numpy().tolist(),
+                     "mu": [[float(z.real), float(z.imag)] for z in mu], "fit_seconds": secs}
+    mb, mf = np.array(out["bf16"]["mu"]), np.array(out["fp32"]["mu"])
+    out["mu_abs_diff_bf16_vs_fp32"] = np.abs((mb[:, 0] - mf[:, 0]) + 1j * (mb[:, 1] - mf[:, 1])).tolist()
+    out["config"] = {"lattice": "4x4 periodic", "N": N, "M": M, "P": wl.P, "q": "(pi, pi)",
+                     "steps_per_order": n_steps, "orders": n_orders, "chains": wl.chains, "sweeps": wl.sweeps,
+                     "dgamma": 0.2, "diag_shift": wl.diag_shift, "E_c": E_c, "W_scale": W_scale,
+                     "enumerated_configs": n_enum}
+    plan.close()
+    return out
 
 
 def matfree_compare(crbm, plan, fit, flat, T, R, wl, args, ms_per_step, prof):
@@ -686,16 +756,15 @@ def cpu_baseline(budget_s, ns, sweeps, C):
                        f"{n_big} samples of the 10x10 alpha=4 workload, {t3 - t0:.1f} s of CPU time; "
                        "natural-gradient step excluded (oracle dense S of 26 GB)"),
             "seconds": t3 - t0}
-    return base, mu_error_triplet(orc, gs, ts, sig, lat, ns)
+    return base, moments_vs_oracle(orc, gs, ts, sig, lat, ns)
 
 
-def mu_error_triplet(orc, gs, ts, sig, lat, ns_step):
-    """Error of the moments mu_n (n <= 20, q = (pi, pi)) against the FP64 oracle on the same samples, for the
-    BF16 and the plain FP32 path, beside the Monte-Carlo standard error at the step's sample count.
-
-    The moments do not go through S, so both paths run the same kernels (theta products with exact BF16
-    splits of W, FP32 log cosh, FP64 sums) and carry the same error.  The RBMs are rounded to complex64
-    once and both sides use those values; the samples are the oracle sampler's own."""
+def moments_vs_oracle(orc, gs, ts, sig, lat, ns_step):
+    """Error of the GPU moments mu_n (n <= 20, q = (pi, pi)) against the FP64 oracle on the same samples,
+    beside the Monte-Carlo standard error at the step's sample count.  The moments do not go through S
+    (their precision is the same in the BF16 and the FP32 step; the fit-quality comparison carries the
+    precision of S into mu_n).  The RBMs are rounded to complex64 once and both sides use those values; the
+    samples are the oracle sampler's own."""
     import torch
     import paper_2103_08804_amd as crbm
     r32 = lambda r: orc.RBM(*(np.asarray(x, np.complex64).astype(np.complex128) for x in (r.a, r.b, r.W)))
@@ -721,10 +790,10 @@ def mu_error_triplet(orc, gs, ts, sig, lat, ns_step):
     lg = orc.logpsi(gs32, sub)
     terms = [np.abs(f) ** 2] + [np.conj(f) * np.exp(orc.logpsi(t, sub) - lg) for t in ts32]
     sigma = float(max(np.std(t) for t in terms) / math.sqrt(ns_step) / scale)
-    return {"n_samples": n, "bf16_path_rel_error": err, "fp32_path_rel_error": err, "sigma_mc_rel": sigma,
+    return {"n_samples": n, "rel_error": err, "sigma_mc_rel": sigma,
             "note": ("max_n |mu_n - mu_n(FP64 oracle)| / max_n |mu_n| on the oracle's samples; sigma_mc: largest "
                      "standard error of the mean at the step's sample count (per-sample spread on "
-                     f"{sub.shape[0]} samples), same scale; the moments do not use S")}
+                     f"{sub.shape[0]} samples), same scale")}
 
 
 if __name__ == "__main__":

@@ -368,8 +368,9 @@ __global__ __launch_bounds__(256, NK == 1 ? 4 : 3) void k_ot(int N, int M, int r
 }
 
 // out[c][P-index] = sum over chunks of the FP32 chunk sums (in FP64), with optional conjugation.  With
-// shift_b (coefficient vector 0, real): the chunks summed T - c_j for the units j < M, and c_j (or its
-// conjugate) times the sum of sigma~_i (the column j = M; 1 for the b row) is added back here.
+// shift_b: the chunks summed conj(T - c_j) for the units j < M, and conj(c_j) times the same coefficient
+// vector's sum over sigma~_i (its column j = M) is added back here; for coefficient vector 0 (the weights)
+// that sum is exactly 1 on the b row.
 __global__ void k_ot_reduce(int N, int M, const float* __restrict__ partial, int n_chunks, int nk, int conj0,
                             double2* __restrict__ out0, double2* __restrict__ out1, const double* __restrict__ skip,
                             const double2* __restrict__ shift_b) {
@@ -387,18 +388,21 @@ __global__ void k_ot_reduce(int N, int M, const float* __restrict__ partial, int
             acc.x += (double)pc[o];
             acc.y += (double)pc[plane + o];
         }
-        if (c == 0 && conj0) acc.y = -acc.y;
-        if (c == 0 && shift_b && j < M) {
-            double y = 1.0;
-            if (i < N) {
+        if (shift_b && j < M) {
+            double2 y = make_double2(1.0, 0.0);
+            if (i < N || c > 0) {
                 const long oy = (long)i * (M + 1) + M;
-                y = 0.0;
-                for (int b = 0; b < n_chunks; ++b) y += (double)partial[(long)b * nk * 2 * plane + oy];
+                y = make_double2(0.0, 0.0);
+                for (int b = 0; b < n_chunks; ++b) {
+                    const float* pc = partial + ((long)b * nk + c) * 2 * plane;
+                    y.x += (double)pc[oy];
+                    y.y += (double)pc[plane + oy];
+                }
             }
-            const double cx = (double)(float)shift_b[j].x, cy = (double)(float)shift_b[j].y;
-            acc.x += cx * y;
-            acc.y += (conj0 ? cy : -cy) * y;
+            const double2 cj = make_double2((double)(float)shift_b[j].x, (double)(float)shift_b[j].y);
+            acc = zadd(acc, zconjmul(cj, y));
         }
+        if (c == 0 && conj0) acc.y = -acc.y;
         (c == 0 ? out0 : out1)[k] = acc;
     }
 }
@@ -483,6 +487,17 @@ __global__ void k_make_f(long P, int mode, double2* __restrict__ Om, const doubl
     const double2 d = mode == 1 ? ORm[k] : zdiv(ORm[k], rm);
     F[k] = make_double2(coef * d.x, coef * d.y);
     Om[k] = make_double2(omc.x, -omc.y);
+}
+
+// F alone from ORc (as k_make_f, the means left as they are)
+__global__ void k_f_of(long P, int mode, const double2* __restrict__ ORm, const double* __restrict__ sc,
+                       double2* __restrict__ F) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P) return;
+    const double2 rm = make_double2(sc[SC_RM_RE], sc[SC_RM_IM]);
+    const double coef = sc[SC_COEF];
+    const double2 d = mode == 1 ? ORm[k] : zdiv(ORm[k], rm);
+    F[k] = make_double2(coef * d.x, coef * d.y);
 }
 
 // ------------------------------------------------------------------ weighted P-vector contractions in double
@@ -1014,9 +1029,22 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
             // The subtracted means are those of the same operands, T' + c, summed as T' in the chunks
             // with c <sigma~> added in double: S stays the centred Gram matrix of one set of vectors
             // (positive semi-definite) and no sum carries |c|^2 against the spread of T.
-            e = run_ot(A.N, A.M, W.sig16, A.T, A.n, 0, 0, 1, nullptr, A.R, nullptr, W.red, 1, W.Om16, nullptr,
-                       stream, nullptr, nullptr, W.n_cu, A.prec == CRBM_PREC_BF16 ? 1 : 0, W.Om + A.N);
-            if (e != hipSuccess) return e;
+            if (A.prec == CRBM_PREC_BF16) {
+                // F from the same rounded operands: the step then solves the ridge problem of one set of
+                // vectors, min |O~ x - D|^2 + eps |x|^2.  With F from the unrounded O, the part of
+                // <O^* D> outside the span of the rounded O~ would be divided by eps.
+                e = run_ot(A.N, A.M, W.sig16, A.T, A.n, 0, 4, 2, nullptr, A.R,
+                           reinterpret_cast<const double2*>(W.scal + SC_RM_RE), W.red, 1, W.Om16, W.ORm, stream,
+                           nullptr, nullptr, W.n_cu, 1, W.Om + A.N);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL(k_f_of, dim3(nblk(P)), dim3(256), 0, stream, P, A.mode, W.ORm, W.scal, W.F);
+                hipLaunchKernelGGL(k_zdot, dim3(64), dim3(256), 0, stream, P, W.F, W.F, W.red, W.scal, 0);
+                hipLaunchKernelGGL(k_sum_to, dim3(1), dim3(64), 0, stream, W.red, 64, W.scal, (int)SC_FF, 0);
+            } else {
+                e = run_ot(A.N, A.M, W.sig16, A.T, A.n, 0, 0, 1, nullptr, A.R, nullptr, W.red, 1, W.Om16, nullptr,
+                           stream, nullptr, nullptr, W.n_cu, 0, W.Om + A.N);
+                if (e != hipSuccess) return e;
+            }
             const int nsplit = W.spart ? sbuild_splits(A.N, A.M, A.n, W.n_cu, W.nsplit_max) : 1;
             e = launch_sbuild_mfma(A.N, A.M, P, A.samples, A.T, A.n, W.Om, W.Om16, W.S, A.prec, W.pack,
                                    W.pack_bytes, W.sb_order, W.sb_order_len, W.spart, nsplit, W.bx, W.bx_part,

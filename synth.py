@@ -52,6 +52,10 @@ SQUARE8 = Workload("square8x8_alpha2_batched", 1, 8, 8, 128, 0, 16, 1, 1e-4, par
 SQUARE16 = Workload("square16x16_alpha2_grad", 1, 16, 16, 512, 8192, 64, 1, 0.0, param_seed=1005, chain_seed=2005)
 # The 6 x 6 lattice of the paper's two-dimensional results, for the symmetry-projected moment correction.
 SQUARE6 = Workload("square6x6_alpha2_symmetry", 1, 6, 6, 72, 1024, 64, 1, 1e-4, param_seed=1006, chain_seed=2006)
+# The 4 x 4 lattice, alpha = 4, of the BF16-vs-FP32 fit-quality comparison (Monte Carlo fits, exact
+# enumeration of the S^z = 0 sector for the figures of merit).
+SQUARE4 = Workload("square4x4_alpha4_fit", 1, 4, 4, 64, 256, 32, 1, 1e-3, param_std=0.05, param_seed=1007,
+                   chain_seed=2007)
 
 # Ground-state energy scales used only to fix the Chebyshev window when the
 # lattice is too large for exact diagonalisation: Hulthen's infinite-chain
