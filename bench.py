@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--n-moments", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-compare", action="store_true")
+    ap.add_argument("--no-plain-path", action="store_true",
+                    help="batched8x8: skip the per-instance comparison run")
     ap.add_argument("--fit-steps", type=int, default=60,
                     help="natural-gradient steps per order in the BF16-vs-FP32 fit-quality comparison")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0)
@@ -304,8 +306,71 @@ def bench_batched(crbm, args):
             "autotuned": {"waves_per_block": w, "blocks": b, "probe_ms": tune_ms},
             "kernel_ms": prof["batched"][1] / prof["batched"][0],
             "chain_steps_per_s": total * (n_burn + n_sweeps) * N / el}
+    # tail of the persistent launch: per-wave (start, end) clocks of the last timed launch
+    clk = torch.zeros(crbm.MAX_CLOCK_WAVES, 2, dtype=torch.int64, device="cuda")
+    crbm.copy_plan_buffer(plan, crbm.BUF_WAVE_CLOCKS, clk)
+    c = clk.cpu().numpy().astype(np.float64)
+    c = c[c[:, 1] > 0]
+    t_end, t_beg = c[:, 1].max(), c[:, 0].min()
+    line["tail"] = {"waves": int(c.shape[0]), "launch_us": (t_end - t_beg) / 100.0,
+                    "tail_idle_frac": float(np.sum(t_end - c[:, 1]) / np.sum(t_end - c[:, 0])),
+                    "start_spread_us": float(c[:, 0].max() - t_beg) / 100.0,
+                    "first_idle_before_end_us": float(t_end - c[:, 1].min()) / 100.0,
+                    "note": ("per-wave clocks (100 MHz): tail_idle_frac = sum over waves of (launch end - wave end) / "
+                             "sum of (launch end - wave start), the share of resident wave time spent idle once the "
+                             "chain counter ran out")}
+    # against its ceilings: half of the pair exchanges are live at S^z = 0 (independent uniform sites); a
+    # live one evaluates M Re log 2cosh of psi_gs and reads rows W_i, W_j of psi_gs (2 M complex64); the
+    # recorded sweeps add 2 M log cosh per chain (t~ and psi_gs); the rows of t~ read on accepted moves
+    # are not counted (a lower bound of the gathers)
+    kern_s = line["kernel_ms"] / 1e3
+    props = total * (n_burn + n_sweeps) * N
+    lc = (0.5 * props * M + 2.0 * total * n_sweeps * M) / kern_s
+    gb = 0.5 * props * 2 * M * 8 / kern_s / 1e9
+    lc_ceil, g_ceil = crbm.probe_logcosh(), crbm.probe_gather(N, M)
+    line["roofline"] = {"kernel": "k_batched", "bound": "alu", "achieved": lc / 1e12, "peak": lc_ceil / 1e12,
+                        "unit": "Tlogcosh/s", "frac": lc / lc_ceil, "traffic": None,
+                        "row_gather_GBps": gb, "row_gather_ceiling_GBps": g_ceil, "row_gather_frac": gb / g_ceil,
+                        "peak_note": ("measured ceilings of this device: k_probe_logcosh (Re log 2cosh in the sweep's "
+                                      "form, 8 independent per lane) and k_probe_gather (whole W rows at random "
+                                      "rows from L2)")}
+    if not args.no_plain_path:
+        line["plain_path"] = plain_path_batched(crbm, plan, gs, tp, betas, qs, counts, offsets, n_burn, n_sweeps, wl,
+                                                line["kernel_ms"])
     print(json.dumps(line))
     plan.close()
+
+
+def plain_path_batched(crbm, plan, gs, tp, betas, qs, counts, offsets, n_burn, n_sweeps, wl, batched_ms):
+    """The same instances through the per-instance calls: for instance i, its c_i chains start at S^z = 0
+    (crbm_init_chains), take n_burn + n_sweeps pair-exchange sweeps of psi_gs (crbm_sample, the recorded
+    sweeps kept), and mu_i = crbm_chebyshev_moment of t~_i at q_i over those samples.  Timed end to end
+    (one pass, host loop over the 2048 instances, one stream)."""
+    N = wl.N
+    cmax = int(counts.max())
+    spins = torch.zeros(cmax, N, dtype=torch.int8, device="cuda")
+    smp = torch.zeros(n_sweeps * cmax * N, dtype=torch.int8, device="cuda")
+    mu = torch.zeros(1, 2, dtype=torch.complex128, device="cuda")
+    n_inst = len(counts)
+
+    def one_pass():
+        for i in range(n_inst):
+            c = int(counts[i])
+            sp = spins[:c]
+            crbm.init_chains(plan, sp, wl.chain_seed + i, True)
+            crbm.sample(plan, gs, sp, n_burn, crbm.EXCHANGE, wl.chain_seed, 0)
+            out = smp[:n_sweeps * c * N].view(n_sweeps, c, N)
+            crbm.sample(plan, gs, sp, n_sweeps, crbm.EXCHANGE, wl.chain_seed, n_burn * N, samples_out=out)
+            crbm.chebyshev_moment(plan, gs, tp[i:i + 1], betas[i:i + 1], [tuple(qs[i])], out.view(-1, N), mu)
+
+    one_pass()          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    one_pass()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    return {"ms": ms, "batched_speedup": ms / batched_ms, "launches": 4 * n_inst,
+            "note": "per instance: init_chains, burn-in sweeps, recorded sweeps, one moment; same chain counts"}
 
 
 def _timed(plan, fn, steps, warmup):

@@ -82,8 +82,13 @@ enum {
     CRBM_BUF_F = 0,        /* complex128 [P]   right-hand side F of the last sr_step */
     CRBM_BUF_DALPHA = 1,   /* complex128 [P]   solution dalpha of the last sr_step */
     CRBM_BUF_OMEAN = 2,    /* complex128 [P]   <O_k> of the last sr_step */
-    CRBM_BUF_S = 3         /* complex64 [P][P] S of the last dense sr_step (both triangles) */
+    CRBM_BUF_S = 3,        /* complex64 [P][P] S of the last dense sr_step (both triangles) */
+    CRBM_BUF_WAVE_CLOCKS = 4 /* uint64 [CRBM_MAX_CLOCK_WAVES][2] (start, end) of every wave of the last
+                                crbm_batched_moments launched while profiling was on (crbm_plan_profile),
+                                in ticks of the device's constant 100 MHz clock; waves of larger grids
+                                are not recorded, unused rows are 0 */
 };
+#define CRBM_MAX_CLOCK_WAVES 16384
 
 typedef struct crbm_plan_s* crbm_plan;
 

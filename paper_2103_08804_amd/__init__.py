@@ -25,7 +25,8 @@ FLIP, EXCHANGE = 0, 1
 CG_DENSE, CG_MATFREE, CHOLESKY = 0, 1, 2
 FP32, BF16 = 0, 1
 PLAN_DENSE_S, PLAN_CHOLESKY, PLAN_BASIS, PLAN_SYM_BASIS = 1, 2, 4, 8
-BUF_F, BUF_DALPHA, BUF_OMEAN, BUF_S = 0, 1, 2, 3
+BUF_F, BUF_DALPHA, BUF_OMEAN, BUF_S, BUF_WAVE_CLOCKS = 0, 1, 2, 3, 4
+MAX_CLOCK_WAVES = 16384
 
 # names declared in include/chebrbm.h
 EXPORTS = ("crbm_plan_create", "crbm_plan_create_ex", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_last_error", "crbm_plan_profile",

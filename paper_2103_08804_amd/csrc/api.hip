@@ -106,6 +106,7 @@ struct crbm_plan_s {
     uint16_t* wplanes = nullptr;   // W split into 3 BF16 parts for the fused log-cosh sums
     double2* lcLg = nullptr;       // [max_samples] sum log cosh theta + a.sigma of psi_gs
     unsigned long long* bcounter = nullptr;
+    unsigned long long* bclocks = nullptr;   // [CRBM_MAX_CLOCK_WAVES][2] per-wave clocks of the batched kernel
     double2* bpartial = nullptr;
     int n_cu = 256;
     int b_waves = 4, b_blocks = 1024;
@@ -330,6 +331,7 @@ int crbm_plan_create_ex(crbm_plan* out, const crbm_lattice* lat, int n_hidden, l
     p->w.wplanes = p->wplanes;
     rc = rc ? rc : p->alloc(&p->lcLg, S);
     rc = rc ? rc : p->alloc(&p->bcounter, 1);
+    rc = rc ? rc : p->alloc(&p->bclocks, (size_t)2 * CRBM_MAX_CLOCK_WAVES);
     rc = rc ? rc : p->alloc(&p->bpartial, 2 * S);
     if (!rc && (flags & (CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY))) {
         rc = p->alloc(&p->w.S, P * P);
@@ -410,6 +412,8 @@ int crbm_plan_buffer(crbm_plan p, int which, void** ptr, size_t* bytes) {
         case CRBM_BUF_S:
             if (!p->w.S) return fail(CRBM_EINVAL, "the plan holds no dense S (create it with CRBM_PLAN_DENSE_S)");
             *ptr = p->w.S; b = p->P * p->P * sizeof(float2); break;
+        case CRBM_BUF_WAVE_CLOCKS:
+            *ptr = p->bclocks; b = (size_t)CRBM_MAX_CLOCK_WAVES * 2 * sizeof(unsigned long long); break;
         default: return fail(CRBM_EINVAL, "unknown buffer id %d", which);
     }
     if (bytes) *bytes = b;
@@ -1147,6 +1151,12 @@ int crbm_batched_moments(crbm_plan p, const crbm_rbm* gs, const void* t_params, 
     if (!mu_out) return fail(CRBM_EINVAL, "mu_out is NULL");
     A.trace = trace;
     A.trace_words = (int)(((long)(n_burn + n_sweeps) * p->N + 31) / 32);
+    if (p->prof.on) {
+        // every row is rewritten or cleared, so rows of an earlier, larger grid do not linger
+        hipError_t ec = launch_clear_u64(p->bclocks, (long)2 * CRBM_MAX_CLOCK_WAVES, stream);
+        if (ec != hipSuccess) return hip_fail(ec, "batched_moments clock clear");
+        A.clocks = p->bclocks;
+    }
     p->prof.begin(PROF_BATCHED, stream);
     hipError_t e = launch_batched(A, p->b_blocks, p->b_waves, static_cast<double2*>(mu_out), stream);
     p->prof.end(stream);

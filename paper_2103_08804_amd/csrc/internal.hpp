@@ -182,8 +182,11 @@ struct BatchedArgs {
     double2* partial;            // [total][2]
     uint32_t* trace;             // [total][trace_words] accept bits, or null
     int trace_words;
+    unsigned long long* clocks;  // [CRBM_MAX_CLOCK_WAVES][2] (start, end) per wave, or null
 };
 hipError_t launch_batched(const BatchedArgs& A, int blocks, int waves_per_block, double2* mu, hipStream_t stream);
+// p[0, n) = 0 with a fill kernel (no memset node when captured)
+hipError_t launch_clear_u64(unsigned long long* p, long n, hipStream_t stream);
 
 struct GradArgs {
     int N, M, P;

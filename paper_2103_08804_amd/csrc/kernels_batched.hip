@@ -16,6 +16,7 @@
 // sequence can be captured in a graph.
 #include <hip/hip_runtime.h>
 
+#include "../../include/chebrbm.h"
 #include "device.hpp"
 #include "internal.hpp"
 #include "sweep.hpp"
@@ -24,6 +25,16 @@ namespace crbm {
 
 __global__ void k_batched_reset(unsigned long long* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0ull;
+}
+
+__global__ void k_clear_u64(unsigned long long* p, long n) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = 0ull;
+}
+
+hipError_t launch_clear_u64(unsigned long long* p, long n, hipStream_t stream) {
+    hipLaunchKernelGGL(k_clear_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
 }
 
 // Value at site i (wave-uniform) of a per-lane array holding sites 64 q + lane; ONE: all sites in slot 0
@@ -171,6 +182,8 @@ __global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
     const int wv = threadIdx.x >> 6;
     int8_t* row = s_spins + wv * 256;
     const int N = A.N, M = A.M;
+    const long wave_id = (long)blockIdx.x * (blockDim.x >> 6) + wv;
+    const unsigned long long t_start = A.clocks ? wall_clock64() : 0ull;
     for (;;) {
         unsigned long long g = 0;
         if (lane == 0) g = atomicAdd(A.counter, 1ull);
@@ -274,6 +287,11 @@ __global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
             A.partial[2 * g + 1] = make_double2(c.mr, c.mi);
             if (trow && (total & 31) != 0) trow[total >> 5] = c.tw;
         }
+    }
+    // profiling: when this wave started and when it found no chain left (the tail of the launch)
+    if (A.clocks && lane == 0 && wave_id < CRBM_MAX_CLOCK_WAVES) {
+        A.clocks[2 * wave_id] = t_start;
+        A.clocks[2 * wave_id + 1] = wall_clock64();
     }
 }
 
