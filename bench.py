@@ -284,7 +284,7 @@ def bench_batched(crbm, args):
     od = torch.from_numpy(offsets).cuda()
     mu = torch.zeros(n_inst, 2, dtype=torch.complex128, device="cuda")
     n_burn, n_sweeps = 4, wl.sweeps
-    w, b, tune_ms = crbm.batched_autotune(plan, gs, tp, betas, qd, od, 1, crbm.EXCHANGE, wl.chain_seed)
+    w, b, lanes, tune_ms = crbm.batched_autotune(plan, gs, tp, betas, qd, od, 4, crbm.EXCHANGE, wl.chain_seed)
     for _ in range(args.warmup):
         crbm.batched_moments(plan, gs, tp, betas, qd, od, n_burn, n_sweeps, crbm.EXCHANGE, wl.chain_seed, mu)
     torch.cuda.synchronize()
@@ -303,7 +303,7 @@ def bench_batched(crbm, args):
             "config": {"workload": "heisenberg_square8x8_rbm_alpha2_batched_moments", "instances": n_inst,
                        "momenta": n_q, "orders": n_ord, "total_chains": total, "burn_in_sweeps": n_burn,
                        "recorded_sweeps": n_sweeps, "chains_per_instance": [int(counts.min()), int(counts.max())]},
-            "autotuned": {"waves_per_block": w, "blocks": b, "probe_ms": tune_ms},
+            "autotuned": {"waves_per_block": w, "blocks": b, "lanes_per_chain": lanes, "probe_ms": tune_ms},
             "kernel_ms": prof["batched"][1] / prof["batched"][0],
             "chain_steps_per_s": total * (n_burn + n_sweeps) * N / el}
     # tail of the persistent launch: per-wave (start, end) clocks of the last timed launch

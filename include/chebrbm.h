@@ -397,14 +397,20 @@ int crbm_batched_moments(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_p
                          const double* q, const int64_t* chain_offsets, int n_inst, int64_t total_chains, int n_burn,
                          int n_sweeps, int proposal, uint64_t seed, void* mu_out, uint32_t* trace,
                          hipStream_t stream);
-/* Times the persistent kernel of crbm_batched_moments for several launch shapes (waves per block 1..8,
- * blocks per compute unit 1..8) on the given instances with n_sweeps_probe sweeps, stores the fastest
- * in the plan and returns it (any output may be NULL).  Synchronises the host: call it outside graph
- * capture. */
+/* Times the persistent kernel of crbm_batched_moments for several launch shapes (lanes per chain 64,
+ * 32 or 16 where M allows, waves per block 1..8, blocks per compute unit 1..8) on the given instances
+ * with n_sweeps_probe sweeps, stores the fastest in the plan and returns it (any output may be NULL).
+ * Every shape gives the same moments and traces bit for bit (the sums run in one fixed order).
+ * Synchronises the host: call it outside graph capture. */
 int crbm_batched_autotune(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_params, const double* betas,
                           const double* q, const int64_t* chain_offsets, int n_inst, int64_t total_chains,
                           int n_sweeps_probe, int proposal, uint64_t seed, void* mu_scratch,
-                          int* waves_per_block, int* blocks, double* best_ms, hipStream_t stream);
+                          int* waves_per_block, int* blocks, int* lanes_per_chain, double* best_ms,
+                          hipStream_t stream);
+/* Sets the launch shape of crbm_batched_moments: waves per block (1..8), blocks, lanes per chain (64;
+ * 32 for M <= 256; 16 for M <= 128: several chains share a wave).  CRBM_EUNSUPPORTED for a lane count
+ * that M does not allow.  Does not touch the device. */
+int crbm_batched_set_shape(crbm_plan plan, int waves_per_block, int blocks, int lanes_per_chain);
 
 #ifdef __cplusplus
 }

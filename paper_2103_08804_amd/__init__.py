@@ -32,7 +32,7 @@ MAX_CLOCK_WAVES = 16384
 EXPORTS = ("crbm_plan_create", "crbm_plan_create_ex", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_last_error", "crbm_plan_profile",
            "crbm_plan_profile_read", "crbm_init_rbm", "crbm_init_chains", "crbm_sample", "crbm_local_estimators",
            "crbm_sr_step", "crbm_sr_energy_step", "crbm_chebyshev_moment", "crbm_fidelity_grad", "crbm_batched_moments",
-           "crbm_batched_autotune", "crbm_moment_matrices", "crbm_corrected_moments", "crbm_lanczos",
+           "crbm_batched_autotune", "crbm_batched_set_shape", "crbm_moment_matrices", "crbm_corrected_moments", "crbm_lanczos",
            "crbm_spectrum_kpm", "crbm_spectrum_cf", "crbm_probe_mfma", "crbm_probe_hbm", "crbm_probe_logcosh", "crbm_probe_gather",
            "crbm_sym_matrices", "crbm_fit_stats", "crbm_enum_weights",
            "crbm_fidelity_grad_noalloc")
@@ -103,7 +103,8 @@ def lib():
         L.crbm_batched_moments.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _i, ctypes.c_int64, _i, _i, _i, _u64,
                                            _vp, _vp, _vp]
         L.crbm_batched_autotune.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _i, ctypes.c_int64, _i, _i, _u64, _vp,
-                                            P(_i), P(_i), P(_d), _vp]
+                                            P(_i), P(_i), P(_i), P(_d), _vp]
+        L.crbm_batched_set_shape.argtypes = [_vp, _i, _i, _i]
         for name in EXPORTS:
             if name != "crbm_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -496,15 +497,21 @@ def batched_moments(plan: Plan, psi_gs: RBM, t_params, betas, q, chain_offsets, 
 
 def batched_autotune(plan: Plan, psi_gs: RBM, t_params, betas, q, chain_offsets, n_sweeps_probe: int,
                      proposal: int, seed: int, stream=None):
-    """Pick the launch shape of the batched kernel (host-synchronising). Returns (waves_per_block, blocks, ms)."""
+    """Pick the launch shape of the batched kernel (host-synchronising).
+    Returns (waves_per_block, blocks, lanes_per_chain, ms)."""
     n_inst = t_params.shape[0]
     total = int(chain_offsets[-1].item())
     scratch = torch.empty(n_inst, 2, dtype=torch.complex128, device=t_params.device)
     g = psi_gs.struct()
-    w, b, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    w, b, ln, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
     _check(lib().crbm_batched_autotune(
         plan.handle, ctypes.byref(g), _ptr(t_params, torch.complex64, (n_inst, plan.P), "t_params"),
         _ptr(betas, torch.complex128, (n_inst,), "betas"), _ptr(q, torch.float64, (n_inst, 2), "q"),
         _ptr(chain_offsets, torch.int64, (n_inst + 1,), "chain_offsets"), n_inst, total, n_sweeps_probe, proposal,
-        seed, _ptr(scratch), ctypes.byref(w), ctypes.byref(b), ctypes.byref(ms), _stream(stream)))
-    return w.value, b.value, ms.value
+        seed, _ptr(scratch), ctypes.byref(w), ctypes.byref(b), ctypes.byref(ln), ctypes.byref(ms), _stream(stream)))
+    return w.value, b.value, ln.value, ms.value
+
+
+def batched_set_shape(plan: Plan, waves_per_block: int, blocks: int, lanes_per_chain: int):
+    """Fix the launch shape of crbm_batched_moments (lanes per chain 64, 32 or 16)."""
+    _check(lib().crbm_batched_set_shape(plan.handle, waves_per_block, blocks, lanes_per_chain))

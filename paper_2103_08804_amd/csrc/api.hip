@@ -109,7 +109,7 @@ struct crbm_plan_s {
     unsigned long long* bclocks = nullptr;   // [CRBM_MAX_CLOCK_WAVES][2] per-wave clocks of the batched kernel
     double2* bpartial = nullptr;
     int n_cu = 256;
-    int b_waves = 4, b_blocks = 1024;
+    int b_waves = 4, b_blocks = 1024, b_lanes = 64;
     Profiler prof;
     std::vector<void*> allocs;
     // workspace of the moment-correction path, reserved at creation (CRBM_PLAN_BASIS / CRBM_PLAN_SYM_BASIS;
@@ -1158,14 +1158,15 @@ int crbm_batched_moments(crbm_plan p, const crbm_rbm* gs, const void* t_params, 
         A.clocks = p->bclocks;
     }
     p->prof.begin(PROF_BATCHED, stream);
-    hipError_t e = launch_batched(A, p->b_blocks, p->b_waves, static_cast<double2*>(mu_out), stream);
+    hipError_t e = launch_batched(A, p->b_blocks, p->b_waves, p->b_lanes, static_cast<double2*>(mu_out), stream);
     p->prof.end(stream);
     return e == hipSuccess ? CRBM_OK : hip_fail(e, "batched_moments launch");
 }
 
 int crbm_batched_autotune(crbm_plan p, const crbm_rbm* gs, const void* t_params, const double* betas, const double* q,
                           const int64_t* offsets, int n_inst, int64_t total, int n_probe, int proposal, uint64_t seed,
-                          void* mu_scratch, int* waves_out, int* blocks_out, double* ms_out, hipStream_t stream) {
+                          void* mu_scratch, int* waves_out, int* blocks_out, int* lanes_out, double* ms_out,
+                          hipStream_t stream) {
     BatchedArgs A{};
     if (int rc = batched_args(p, gs, t_params, betas, q, offsets, n_inst, total, 0, n_probe, proposal, seed, A))
         return rc;
@@ -1173,31 +1174,50 @@ int crbm_batched_autotune(crbm_plan p, const crbm_rbm* gs, const void* t_params,
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(CRBM_EHIP, "hipEventCreate");
     double best = 1e300;
-    int bw = p->b_waves, bb = p->b_blocks;
-    const int waves[4] = {1, 2, 4, 8}, per_cu[4] = {1, 2, 4, 8};
-    for (int wi = 0; wi < 4; ++wi)
-        for (int ci = 0; ci < 4; ++ci) {
-            const int blocks = per_cu[ci] * p->n_cu;
-            hipError_t r = hipEventRecord(e0, stream);
-            if (r == hipSuccess) r = launch_batched(A, blocks, waves[wi], static_cast<double2*>(mu_scratch), stream);
-            if (r == hipSuccess) r = hipEventRecord(e1, stream);
-            if (r == hipSuccess) r = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
-            if (r != hipSuccess) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return hip_fail(r, "batched autotune");
+    int bw = p->b_waves, bb = p->b_blocks, bl = p->b_lanes;
+    const int waves[4] = {1, 2, 4, 8}, per_cu[4] = {1, 2, 4, 8}, lanes[3] = {64, 32, 16};
+    for (int li = 0; li < 3; ++li) {
+        if (!batched_lanes_ok(lanes[li], p->M)) continue;
+        for (int wi = 0; wi < 4; ++wi)
+            for (int ci = 0; ci < 4; ++ci) {
+                const int blocks = per_cu[ci] * p->n_cu;
+                hipError_t r = hipEventRecord(e0, stream);
+                if (r == hipSuccess)
+                    r = launch_batched(A, blocks, waves[wi], lanes[li], static_cast<double2*>(mu_scratch), stream);
+                if (r == hipSuccess) r = hipEventRecord(e1, stream);
+                if (r == hipSuccess) r = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+                if (r != hipSuccess) {
+                    (void)hipEventDestroy(e0);
+                    (void)hipEventDestroy(e1);
+                    return hip_fail(r, "batched autotune");
+                }
+                if (ms < best) { best = ms; bw = waves[wi]; bb = blocks; bl = lanes[li]; }
             }
-            if (ms < best) { best = ms; bw = waves[wi]; bb = blocks; }
-        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     p->b_waves = bw;
     p->b_blocks = bb;
+    p->b_lanes = bl;
     if (waves_out) *waves_out = bw;
     if (blocks_out) *blocks_out = bb;
+    if (lanes_out) *lanes_out = bl;
     if (ms_out) *ms_out = best;
+    return CRBM_OK;
+}
+
+int crbm_batched_set_shape(crbm_plan p, int waves_per_block, int blocks, int lanes_per_chain) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (waves_per_block < 1 || waves_per_block > 8) return fail(CRBM_EINVAL, "waves_per_block must be in [1, 8]");
+    if (blocks < 1) return fail(CRBM_EINVAL, "blocks must be >= 1");
+    if (!batched_lanes_ok(lanes_per_chain, (int)p->M))
+        return fail(CRBM_EUNSUPPORTED, "lanes_per_chain = %d is not 64, 32 (M <= 256) or 16 (M <= 128) for M = %ld",
+                    lanes_per_chain, p->M);
+    p->b_waves = waves_per_block;
+    p->b_blocks = blocks;
+    p->b_lanes = lanes_per_chain;
     return CRBM_OK;
 }
 

@@ -184,7 +184,10 @@ struct BatchedArgs {
     int trace_words;
     unsigned long long* clocks;  // [CRBM_MAX_CLOCK_WAVES][2] (start, end) per wave, or null
 };
-hipError_t launch_batched(const BatchedArgs& A, int blocks, int waves_per_block, double2* mu, hipStream_t stream);
+// lanes per chain: 64 (any M), 32 (M <= 256) or 16 (M <= 128); the results are the same bit for bit
+bool batched_lanes_ok(int lanes, int M);
+hipError_t launch_batched(const BatchedArgs& A, int blocks, int waves_per_block, int lanes, double2* mu,
+                          hipStream_t stream);
 // p[0, n) = 0 with a fill kernel (no memset node when captured)
 hipError_t launch_clear_u64(unsigned long long* p, long n, hipStream_t stream);
 

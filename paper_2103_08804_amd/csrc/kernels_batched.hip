@@ -91,6 +91,19 @@ struct BatchedChain {
     double m0, mr, mi;      // sums of |f|^2 and conj(f) beta r
 };
 
+// log 2cosh(zt) - log 2cosh(zg) of one unit (modulo 2 pi i): with s = sign Re z and w = exp(-2 s z),
+// log 2cosh z = s z + log(1 + w), so the difference is st zt - sg zg + log((1 + wt) / (1 + wg)), one
+// log and one atan2 per unit
+__device__ __forceinline__ float2 unit_log_ratio(float2 zt, float2 zg) {
+    const float st = zt.x >= 0.f ? 1.f : -1.f, sg = zg.x >= 0.f ? 1.f : -1.f;
+    const float et = expf(-2.f * fabsf(zt.x)), eg = expf(-2.f * fabsf(zg.x));
+    const float2 ct = cos_sin(2.f * st * zt.y), cg = cos_sin(2.f * sg * zg.y);
+    const float2 a = make_float2(1.f + et * ct.x, -et * ct.y), b = make_float2(1.f + eg * cg.x, -eg * cg.y);
+    const float2 q = make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);   // a conj(b)
+    const float na = a.x * a.x + a.y * a.y, nb = b.x * b.x + b.y * b.y;
+    return make_float2(fabsf(zt.x) - fabsf(zg.x) + 0.5f * logf(na / nb), st * zt.y - sg * zg.y + atan2f(q.y, q.x));
+}
+
 template <int E, bool PAIR>
 __device__ __forceinline__ void apply_pending(BatchedChain<E, PAIR>& c, int lane, int M) {
     if (c.pm != 0.f) {
@@ -104,37 +117,32 @@ __device__ __forceinline__ void apply_pending(BatchedChain<E, PAIR>& c, int lane
     }
 }
 
-// f_q(s) and the ratio t~(s)/psi_gs(s), added to the chain's sums.  Per lane the log cosh terms of
-// both RBMs are kept as a linear part and a product of factors of modulus <= 1 each, so that one
-// log and one atan2 per lane take the difference (the log 2 terms cancel).
+// f_q(s) and the ratio t~(s)/psi_gs(s), added to the chain's sums.  Every sum runs in one fixed
+// order that does not depend on how many lanes a chain has (the canonical order, shared with the
+// grouped kernel below): per lane the slots in sequence (units 64 e + lane, sites 64 q + lane),
+// then the lanes by bits 0 .. 5.  The unit terms are log 2cosh(theta_t) - log 2cosh(theta_gs) per
+// unit (unit_log_ratio), the site terms (a_t - a_gs) s and e^{-i q.r} s / 2.
 // ph: e^{-i q.r} and da: a_t - a_gs at this lane's sites
 template <int E, bool PAIR>
 __device__ __forceinline__ void measure(const BatchedArgs& A, BatchedChain<E, PAIR>& c, const float2 (&ph)[4],
                                         const float2 (&da)[4], double2 beta, int lane) {
     const int N = A.N, M = A.M;
     apply_pending(c, lane, M);
-    float2 f = make_float2(0.f, 0.f), lin = make_float2(0.f, 0.f);
-    float2 pt = make_float2(1.f, 0.f), pg = make_float2(1.f, 0.f);
+    float2 f = make_float2(0.f, 0.f), dA = make_float2(0.f, 0.f), dU = make_float2(0.f, 0.f);
 #pragma unroll
     for (int qq = 0; qq < 4; ++qq) {
         const int site = qq * kWave + lane;
         if (site < N) {
             const float s = (float)c.sp.s[qq];
             f = cadd(f, cscale(ph[qq], 0.5f * s));
-            lin = cadd(lin, cscale(da[qq], s));
+            dA = cadd(dA, cscale(da[qq], s));
         }
     }
 #pragma unroll
     for (int e = 0; e < E; ++e)
-        if (e < E - 1 || e * kWave + lane < M) {
-            cosh_factor(c.tht[e], 1.f, lin, pt);
-            cosh_factor(c.thg[e], -1.f, lin, pg);
-        }
-    const float2 q = make_float2(pt.x * pg.x + pt.y * pg.y, pt.y * pg.x - pt.x * pg.y);  // pt conj(pg)
-    const float nt = pt.x * pt.x + pt.y * pt.y, ng = pg.x * pg.x + pg.y * pg.y;
-    const float2 dl = make_float2(lin.x + 0.5f * (logf(nt) - logf(ng)), lin.y + atan2f(q.y, q.x));
+        if (e * kWave + lane < M) dU = cadd(dU, unit_log_ratio(c.tht[e], c.thg[e]));
     f = make_float2(wave_total(f.x), wave_total(f.y));
-    const float2 dlog = make_float2(wave_total(dl.x), wave_total(dl.y));
+    const float2 dlog = make_float2(wave_total(dU.x) + wave_total(dA.x), wave_total(dU.y) + wave_total(dA.y));
     const float2 r = cscale(cos_sin(dlog.y), expf(dlog.x));
     const double fx = (double)f.x * (1.0 / sqrt((double)N)), fy = (double)f.y * (1.0 / sqrt((double)N));
     const double2 br = zmul(beta, make_double2((double)r.x, (double)r.y));
@@ -175,8 +183,11 @@ __device__ __forceinline__ void batched_step(const BatchedArgs& A, uint64_t g, i
     }
 }
 
+// Four waves per SIMD (at most 128 registers) for the small chain widths: the kernel is bound by
+// instruction issue, and a fourth wave per SIMD hides more of each wave's dependency stalls.
 template <int E, bool PAIR, bool ONE>
-__global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(E <= 2 ? 4 : 1)))
+void k_batched(BatchedArgs A) {
     extern __shared__ int8_t s_spins[];           // one 256-byte row per wave
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -295,6 +306,270 @@ __global__ __launch_bounds__(512) void k_batched(BatchedArgs A) {
     }
 }
 
+// ------------------------------------------------------------------ several chains per wave
+// A chain on L = 16 or 32 lanes (G = 64 / L chains per wave, one per lane group), for M <= 128 (L = 16)
+// or 256 (L = 32): every lane holds EL = E64 64 / L units, so the per-proposal control (draw, site
+// values, reduction, accept) is shared by G proposals of G chains.  Lane gl of a group holds the
+// units and sites 64 e + L j + gl, j < 64 / L: sums run over the slots e in sequence for each j, then
+// over the lane bits 0 .. log2 L - 1 (DPP within the row, a swap across rows for L = 32), then over
+// j by its bits, which is the 64-lane kernel's order exactly, so both give the same decisions and
+// moments bit for bit.  The group's spins live in LDS (row per chain); the group's first lane writes
+// them.  Groups step in lockstep; a group without a chain (the grid's last round) runs masked.
+
+// sum over the L lanes of each group by lane bits 0 .. log2 L - 1; every lane of the group ends with
+// the same value.  All 64 lanes must be active.
+template <int L>
+__device__ __forceinline__ float group_sum(float v) {
+    v += dpp_move<0xB1, 0xF>(v);   // bit 0: quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E, 0xF>(v);   // bit 1: quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141, 0xF>(v);  // bit 2: row_half_mirror
+    v += dpp_move<0x140, 0xF>(v);  // bit 3: row_mirror
+    if (L == 32) v += __shfl_xor(v, 16, kWave);   // bit 4
+    return v;
+}
+// canonical total of per-lane partials over sub-slots j (lane bits log2 L .. 5)
+template <int L>
+__device__ __forceinline__ float group_total(const float (&p)[64 / L]) {
+    if (L == 32) return group_sum<L>(p[0]) + group_sum<L>(p[1]);
+    const float a = group_sum<L>(p[0]) + group_sum<L>(p[1]);
+    const float b = group_sum<L>(p[2]) + group_sum<L>(p[3]);
+    return a + b;
+}
+
+// e^{-i q.r} at a site (q.r reduced to [-pi, pi] in double, then cos_sin of the float)
+__device__ __forceinline__ float2 site_phase(const BatchedArgs& A, int site, double q0, double q1) {
+    const int x = A.kind == 0 ? site : site % A.Lx;
+    const int y = A.kind == 0 ? 0 : site / A.Lx;
+    const double arg = q0 * x + q1 * y;
+    const double two_pi = 6.283185307179586476925286766559;
+    const float red = (float)(arg - two_pi * rint(arg / two_pi));
+    const float2 cs = cos_sin(red);
+    return make_float2(cs.x, -cs.y);
+}
+
+template <int L, int E64, bool PAIR>
+__global__ __launch_bounds__(512) void k_batched_grp(BatchedArgs A) {
+    constexpr int G = kWave / L;        // chains per wave
+    constexpr int J = kWave / L;        // sub-slots per lane
+    constexpr int EL = E64 * J;         // units per lane, slot k = e J + j: unit 64 e + L j + gl
+    extern __shared__ int8_t s_spins[];  // one 256-byte row per chain
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int grp = lane / L, gl = lane % L;
+    int8_t* row = s_spins + (wv * G + grp) * 256;
+    const int N = A.N, M = A.M;
+    const long wave_id = (long)blockIdx.x * (blockDim.x >> 6) + wv;
+    const unsigned long long t_start = A.clocks ? wall_clock64() : 0ull;
+    const float* gsa = reinterpret_cast<const float*>(A.gs.a);
+    for (;;) {
+        unsigned long long g0 = 0;
+        if (lane == 0) g0 = atomicAdd(A.counter, (unsigned long long)G);
+        g0 = (unsigned long long)__builtin_amdgcn_readfirstlane((int)(g0 & 0xFFFFFFFFull)) |
+             ((unsigned long long)__builtin_amdgcn_readfirstlane((int)(g0 >> 32)) << 32);
+        if ((int64_t)g0 >= A.total) break;
+        const int64_t g = (int64_t)g0 + grp;
+        const bool act = g < A.total;
+        const int64_t gq = act ? g : A.total - 1;
+        int lo = 0, hi = A.n_inst;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (A.offsets[mid] <= gq) lo = mid; else hi = mid;
+        }
+        const int inst = lo;
+        const float2* tp = A.t_params + (long)inst * A.P;
+        const float2* at = tp;
+        const float2* bt = tp + N;
+        const float2* Wt = tp + N + M;
+        const double q0 = A.q[2 * inst], q1 = A.q[2 * inst + 1];
+
+        // Fisher-Yates start at total S^z = 0 (Philox tag 1, counter a = chain id), by the group's first lane
+        if (gl == 0) {
+            for (int i = 0; i < N; ++i) row[i] = (i < N / 2) ? 1 : -1;
+            if (act)
+                for (int k = N - 1; k >= 1; --k) {
+                    const int m = draw_index(draw(A.seed, (uint32_t)g, (uint64_t)k, 1u).x, k + 1);
+                    const int8_t t = row[k];
+                    row[k] = row[m];
+                    row[m] = t;
+                }
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        float2 thg[EL], tht[EL];
+        float Lg[EL];
+        // slot k holds unit u = 64 (k / J) + L (k % J) + gl; its column clamped to the row is col(k)
+        auto col = [&](int k) { return min(kWave * (k / J) + L * (k % J) + gl, M - 1); };
+#pragma unroll
+        for (int k = 0; k < EL; ++k) {
+            const int u = kWave * (k / J) + L * (k % J) + gl;
+            thg[k] = (u < M) ? A.gs.b[u] : make_float2(0.f, 0.f);
+            tht[k] = (u < M) ? bt[u] : make_float2(0.f, 0.f);
+        }
+#pragma unroll 1
+        for (int i = 0; i < N; ++i) {
+            const float si = (float)row[i];
+#pragma unroll
+            for (int k = 0; k < EL; ++k) {
+                const int u = kWave * (k / J) + L * (k % J) + gl;
+                const float2 wg = A.gs.W[(long)i * M + col(k)], wt = Wt[(long)i * M + col(k)];
+                const float sv = (u < M) ? si : 0.f;
+                thg[k].x = fmaf(sv, wg.x, thg[k].x);
+                thg[k].y = fmaf(sv, wg.y, thg[k].y);
+                tht[k].x = fmaf(sv, wt.x, tht[k].x);
+                tht[k].y = fmaf(sv, wt.y, tht[k].y);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < EL; ++k) Lg[k] = re_log2cosh_fast(thg[k]);
+        const double2 beta = A.betas[inst];
+        float2 pt[EL];      // pending change of theta_t per unit of pm: W_t rows i (- j) of the last accepted move
+        float pm = 0.f;
+        uint32_t tw = 0;
+        double m0 = 0.0, mr = 0.0, mi = 0.0;
+        uint32_t* trow = (A.trace && act) ? A.trace + (long)g * A.trace_words : nullptr;
+        const int total = (A.n_burn + A.n_sweeps) * N;
+        int bi = 0, bj = 0;
+        float bu = 0.f;
+        auto apply = [&]() {
+            if (pm != 0.f) {
+#pragma unroll
+                for (int k = 0; k < EL; ++k) {
+                    tht[k].x = fmaf(pm, pt[k].x, tht[k].x);
+                    tht[k].y = fmaf(pm, pt[k].y, tht[k].y);
+                }
+                pm = 0.f;
+            }
+        };
+        int t = 0;
+        for (int sw = 0; sw < A.n_burn + A.n_sweeps; ++sw) {
+            for (int p = 0; p < N; ++p, ++t) {
+                // proposal t: the group's lane t % L drew it (counter t of the chain's stream, tag 0)
+                if ((t % L) == 0) {
+                    uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
+                    asm volatile("" : "+s"(k0), "+s"(k1));
+                    const uint64_t tt = (uint64_t)(t + gl);
+                    const u32x4 x = philox4x32_10((uint32_t)gq, (uint32_t)tt, (uint32_t)(tt >> 32), 0u, k0, k1);
+                    bi = draw_index(x.x, N);
+                    bj = draw_index(x.y, N);
+                    bu = draw_unit(x.z);
+                }
+                const int src = grp * L + (t % L);
+                const int ci = __shfl(bi, src, kWave), cj = __shfl(bj, src, kWave);
+                const float cu = __shfl(bu, src, kWave);
+                const int si = row[ci], sj = row[cj];
+                const bool live = act && !(PAIR && si == sj);
+                bool acc = false;
+                if (__builtin_amdgcn_ballot_w64(live)) {
+                    float2 wi[EL], wj[EL], tn[EL];
+                    float Ln[EL];
+                    const float ai = gsa[2 * ci];
+                    const float aj = PAIR ? gsa[2 * cj] : 0.f;
+#pragma unroll
+                    for (int k = 0; k < EL; ++k) {
+                        wi[k] = A.gs.W[(long)ci * M + col(k)];
+                        if (PAIR) wj[k] = A.gs.W[(long)cj * M + col(k)];
+                    }
+                    const float m2si = -2.f * (float)si;
+                    float ds[J];
+#pragma unroll
+                    for (int j = 0; j < J; ++j) ds[j] = 0.f;
+#pragma unroll
+                    for (int k = 0; k < EL; ++k) {
+                        const int u = kWave * (k / J) + L * (k % J) + gl;
+                        float2 d = PAIR ? csub(wi[k], wj[k]) : wi[k];
+                        if (u >= M) d = make_float2(0.f, 0.f);
+                        tn[k].x = fmaf(m2si, d.x, thg[k].x);
+                        tn[k].y = fmaf(m2si, d.y, thg[k].y);
+                        Ln[k] = re_log2cosh_fast(tn[k]);
+                        ds[k % J] += Ln[k] - Lg[k];
+                    }
+                    float da = m2si * ai;
+                    if (PAIR) da -= m2si * aj;
+                    const float dl = group_total<L>(ds) + da;
+                    acc = live && (cu < __expf(2.f * dl));
+                    if (acc) {
+#pragma unroll
+                        for (int k = 0; k < EL; ++k) { thg[k] = tn[k]; Lg[k] = Ln[k]; }
+                        apply();
+#pragma unroll
+                        for (int k = 0; k < EL; ++k) {
+                            const int u = kWave * (k / J) + L * (k % J) + gl;
+                            const float2 ri = Wt[(long)ci * M + col(k)];
+                            float2 d = ri;
+                            if (PAIR) d = csub(ri, Wt[(long)cj * M + col(k)]);
+                            pt[k] = (u < M) ? d : make_float2(0.f, 0.f);
+                        }
+                        pm = m2si;
+                        if (gl == 0) {
+                            row[ci] = (int8_t)(-si);
+                            if (PAIR) row[cj] = (int8_t)(-sj);
+                        }
+                    }
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                }
+                if (acc) tw |= 1u << (t & 31);
+                if ((t & 31) == 31) {
+                    if (trow && gl == 0) trow[t >> 5] = tw;
+                    tw = 0;
+                }
+            }
+            if (sw >= A.n_burn) {
+                // the measurement in the canonical order (see measure above): per sub-slot j the slots in
+                // sequence, the group's lanes, then the sub-slots by their bits
+                apply();
+                float fx_[J], fy_[J], ax_[J], ay_[J], ux_[J], uy_[J];
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    float fx = 0.f, fy = 0.f, ax = 0.f, ay = 0.f, ux = 0.f, uy = 0.f;
+#pragma unroll 1
+                    for (int qq = 0; qq < 4; ++qq) {
+                        const int site = kWave * qq + L * j + gl;
+                        if (site < N) {
+                            const float sv = (float)row[site];
+                            const float2 ph = site_phase(A, site, q0, q1);
+                            const float2 da = csub(at[site], A.gs.a[site]);
+                            const float2 fc = cscale(ph, 0.5f * sv), dc = cscale(da, sv);
+                            fx += fc.x; fy += fc.y;
+                            ax += dc.x; ay += dc.y;
+                        }
+                    }
+#pragma unroll
+                    for (int e = 0; e < E64; ++e) {
+                        const int k = e * J + j;
+                        if (kWave * e + L * j + gl < M) {
+                            const float2 d = unit_log_ratio(tht[k], thg[k]);
+                            ux += d.x;
+                            uy += d.y;
+                        }
+                    }
+                    fx_[j] = fx; fy_[j] = fy; ax_[j] = ax; ay_[j] = ay; ux_[j] = ux; uy_[j] = uy;
+                }
+                const float2 f = make_float2(group_total<L>(fx_), group_total<L>(fy_));
+                const float2 dlog = make_float2(group_total<L>(ux_) + group_total<L>(ax_),
+                                                group_total<L>(uy_) + group_total<L>(ay_));
+                const float2 r = cscale(cos_sin(dlog.y), expf(dlog.x));
+                const double fx = (double)f.x * (1.0 / sqrt((double)N)), fy = (double)f.y * (1.0 / sqrt((double)N));
+                const double2 br = zmul(beta, make_double2((double)r.x, (double)r.y));
+                m0 += fx * fx + fy * fy;
+                mr += fx * br.x + fy * br.y;
+                mi += fx * br.y - fy * br.x;
+            }
+        }
+        if (act && gl == 0) {
+            A.partial[2 * g] = make_double2(m0, 0.0);
+            A.partial[2 * g + 1] = make_double2(mr, mi);
+            if (trow && (total & 31) != 0) trow[total >> 5] = tw;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (A.clocks && lane == 0 && wave_id < CRBM_MAX_CLOCK_WAVES) {
+        A.clocks[2 * wave_id] = t_start;
+        A.clocks[2 * wave_id + 1] = wall_clock64();
+    }
+}
+
 // mu_out[i] = (sum of chain partials of instance i) / (c_i n_sweeps).  An instance whose chain range
 // [offsets[i], offsets[i+1]) is not inside [0, total) reads no partials and gets NaN moments.
 __global__ void k_batched_reduce(const double2* __restrict__ partial, const int64_t* __restrict__ offsets, int n_inst,
@@ -329,12 +604,33 @@ __global__ void k_batched_reduce(const double2* __restrict__ partial, const int6
     }
 }
 
-hipError_t launch_batched(const BatchedArgs& A, int blocks, int waves_per_block, double2* mu, hipStream_t stream) {
+bool batched_lanes_ok(int lanes, int M) {
+    if (lanes == kWave) return true;
+    const int E64 = (M + kWave - 1) / kWave;
+    return (lanes == 32 && E64 <= 4) || (lanes == 16 && E64 <= 2);
+}
+
+hipError_t launch_batched(const BatchedArgs& A, int blocks, int waves_per_block, int lanes, double2* mu,
+                          hipStream_t stream) {
+    if (!batched_lanes_ok(lanes, A.M)) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_batched_reset, dim3(1), dim3(64), 0, stream, A.counter);
     const int E = (A.M + kWave - 1) / kWave;
     const dim3 grid(blocks), block(64 * waves_per_block);
-    const size_t lds = 256 * (size_t)waves_per_block;
     const bool pair = A.proposal == 1, one = A.N <= kWave;
+    if (lanes != kWave) {
+        const size_t lds_g = 256 * (size_t)waves_per_block * (kWave / lanes);
+#define CRBM_GRP(l, e)                                                                                    \
+    if (lanes == l && E == e) {                                                                           \
+        if (pair) hipLaunchKernelGGL((k_batched_grp<l, e, true>), grid, block, lds_g, stream, A);         \
+        else hipLaunchKernelGGL((k_batched_grp<l, e, false>), grid, block, lds_g, stream, A);             \
+    }
+        CRBM_GRP(16, 1) CRBM_GRP(16, 2) CRBM_GRP(32, 1) CRBM_GRP(32, 2) CRBM_GRP(32, 3) CRBM_GRP(32, 4)
+#undef CRBM_GRP
+        hipLaunchKernelGGL(k_batched_reduce, dim3(A.n_inst), dim3(256), 0, stream, A.partial, A.offsets, A.n_inst,
+                           (int64_t)A.total, A.n_sweeps, mu);
+        return hipGetLastError();
+    }
+    const size_t lds = 256 * (size_t)waves_per_block;
     switch (E) {
 #define CRBM_CASE(e)                                                                                   \
     case e:                                                                                            \

@@ -83,8 +83,8 @@ def test_batched_graph_replay_and_autotune(orc):
         torch.cuda.synchronize()
         assert torch.equal(eager, ref)
     # a different launch shape gives the same bits
-    w, b, ms = crbm.batched_autotune(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 1, 1, 7)
-    assert w in (1, 2, 4, 8) and b >= 1 and ms > 0
+    w, b, ln, ms = crbm.batched_autotune(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 1, 1, 7)
+    assert w in (1, 2, 4, 8) and b >= 1 and ln in (16, 32, 64) and ms > 0
     crbm.batched_moments(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 1, 3, 1, 7, eager)
     torch.cuda.synchronize()
     assert torch.equal(eager, ref)
@@ -122,3 +122,38 @@ def test_batched_bad_offsets_give_nan(orc):
     assert np.all(np.isnan(b[2].real)) and np.all(np.isnan(b[2].imag))
     # instance 0 owns chains 0..2 under both offset vectors: same chains, same sums
     assert np.array_equal(b[0], np_of(good)[0])
+
+
+@pytest.mark.parametrize("kind,Lx,Ly,M,proposal", [(1, 4, 4, 16, 1), (0, 12, 1, 24, 0), (1, 4, 4, 100, 1),
+                                                    (1, 8, 8, 128, 1), (0, 66, 1, 70, 1), (1, 4, 4, 300, 1)])
+def test_batched_lanes_per_chain_bit_identical(orc, kind, Lx, Ly, M, proposal):
+    """Chains on 64, 32 or 16 lanes (one, two or four chains per wave) and several grid shapes give the
+    same moments and the same accept traces bit for bit: every sum runs in one fixed order.  Ragged M
+    (units past M in the last slots), N > 64 (sites in a second slot), uneven chain counts, both
+    proposals; 16 lanes only where M <= 128 and 32 where M <= 256, other lane counts are refused."""
+    N = Lx * Ly
+    r = np.random.default_rng(31)
+    counts = r.integers(1, 13, 37)
+    gs_d, tv, betas, qs, offsets, dev = _instances(orc, kind, Lx, Ly, M, counts, seed=9)
+    total = int(offsets[-1])
+    plan = crbm.Plan(kind, Lx, Ly, M, total)
+    words = ((1 + 3) * N + 31) // 32
+    res = {}
+    for lanes in (64, 32, 16):
+        if (lanes == 32 and M > 256) or (lanes == 16 and M > 128):
+            with pytest.raises(crbm.CrbmError):
+                crbm.batched_set_shape(plan, 4, 64, lanes)
+            continue
+        for waves, blocks in ((1, 3), (8, 512)):
+            crbm.batched_set_shape(plan, waves, blocks, lanes)
+            mu = torch.zeros(len(counts), 2, dtype=torch.complex128, device="cuda")
+            tr = torch.zeros(total, words, dtype=torch.int32, device="cuda")
+            crbm.batched_moments(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 1, 3, proposal, 7, mu, trace=tr)
+            torch.cuda.synchronize()
+            res[(lanes, waves)] = (np_of(mu), np_of(tr))
+    ref_mu, ref_tr = res[(64, 1)]
+    assert np.all(np.isfinite(ref_mu))
+    for key, (m, t) in res.items():
+        assert np.array_equal(m, ref_mu), key
+        assert np.array_equal(t, ref_tr), key
+    print("shapes compared", sorted(res))
