@@ -171,6 +171,11 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    sb_tile = None
+    if solver == crbm.CG_DENSE and prec == crbm.BF16 and args.warmup > 0:
+        # K tile of the S contraction, timed on the warm-up step's samples (both tiles give the same S)
+        kt, kt_ms = crbm.sbuild_autotune(plan, flat, T)
+        sb_tile = {"k_tile": kt, "probe_ms": kt_ms, "candidates": [64, 128]}
     plan.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -250,6 +255,7 @@ def main():
         "sampler_samples_per_s": (C * sweeps) / (prof["sample"][1] / prof["sample"][0] / 1e3) if "sample" in prof else None,
         "cg_iterations": float(st[5]), "cg_rel_residual": float(st[4]), "sr_flags": int(st[6]),
         "gamma": float(st[0]),
+        "sbuild_autotune": sb_tile,
         "phases": phases,
         "roofline": roof,
         "sampler_roofline": sampler,

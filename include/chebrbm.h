@@ -407,6 +407,16 @@ int crbm_batched_autotune(crbm_plan plan, const crbm_rbm* psi_gs, const void* t_
                           int n_sweeps_probe, int proposal, uint64_t seed, void* mu_scratch,
                           int* waves_per_block, int* blocks, int* lanes_per_chain, double* best_ms,
                           hipStream_t stream);
+/* K tile (samples staged per LDS tile: 64 or 128) of the BF16 matrix-core S contraction of this plan's
+ * dense sr_step.  Every tile gives the same S bit for bit (the samples are summed in the same order).
+ * Default 128.  Does not touch the device. */
+int crbm_plan_set_sbuild_tile(crbm_plan plan, int k_tile);
+/* Times the BF16 S contraction (Sec. III) of this plan with each K tile on the given samples (int8
+ * [n][N]) and tanh theta (complex64 [n][M]), stores the faster tile in the plan and returns it (outputs
+ * may be NULL).  Overwrites the plan's dense S.  Needs a plan with CRBM_PLAN_DENSE_S.  Synchronises the
+ * host: call it outside graph capture. */
+int crbm_sbuild_autotune(crbm_plan plan, const int8_t* samples, const void* tanh_theta, long n, int* k_tile,
+                         double* best_ms, hipStream_t stream);
 /* Sets the launch shape of crbm_batched_moments: waves per block (1..8), blocks, lanes per chain (64;
  * 32 for M <= 256; 16 for M <= 128: several chains share a wave).  CRBM_EUNSUPPORTED for a lane count
  * that M does not allow.  Does not touch the device. */

@@ -385,6 +385,7 @@ int crbm_plan_create_ex(crbm_plan* out, const crbm_lattice* lat, int n_hidden, l
     p->b_waves = 4;
     p->b_blocks = 4 * p->n_cu;
     p->w.n_cu = p->n_cu;
+    p->w.sb_kt = 128;
     e = hipMemcpy(p->bonds, bonds.data(), bonds.size() * sizeof(int2), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(p->w.scal, 0, 32 * sizeof(double));
     if (e == hipSuccess && !order.empty())
@@ -1205,6 +1206,53 @@ int crbm_batched_autotune(crbm_plan p, const crbm_rbm* gs, const void* t_params,
     if (blocks_out) *blocks_out = bb;
     if (lanes_out) *lanes_out = bl;
     if (ms_out) *ms_out = best;
+    return CRBM_OK;
+}
+
+int crbm_plan_set_sbuild_tile(crbm_plan p, int k_tile) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (k_tile != 64 && k_tile != 128) return fail(CRBM_EINVAL, "k_tile must be 64 or 128, got %d", k_tile);
+    p->w.sb_kt = k_tile;
+    return CRBM_OK;
+}
+
+int crbm_sbuild_autotune(crbm_plan p, const int8_t* samples, const void* tanh_theta, long n, int* k_tile_out,
+                         double* best_ms, hipStream_t stream) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (!p->w.S || !p->w.pack) return fail(CRBM_EINVAL, "the plan holds no dense S (create it with CRBM_PLAN_DENSE_S)");
+    if (!samples || !tanh_theta) return fail(CRBM_EINVAL, "samples and tanh_theta must be non-NULL");
+    if (n < 1 || n > p->max_samples) return fail(CRBM_ENOMEM, "n = %ld must be in [1, max_samples = %ld]", n, p->max_samples);
+    if (int rc = set_device(p)) return rc;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(CRBM_EHIP, "hipEventCreate");
+    const int nsplit = p->w.spart ? sbuild_splits((int)p->N, (int)p->M, n, p->w.n_cu, p->w.nsplit_max) : 1;
+    Profiler off;
+    double best = 1e300;
+    int bk = p->w.sb_kt;
+    const int tiles[2] = {128, 64};
+    for (int ti = 0; ti < 2; ++ti) {
+        float ms = 0.f;
+        hipError_t r = hipEventRecord(e0, stream);
+        if (r == hipSuccess)
+            r = launch_sbuild_mfma((int)p->N, (int)p->M, p->P, samples, static_cast<const float2*>(tanh_theta), n,
+                                   p->w.Om, p->w.Om, p->w.S, CRBM_PREC_BF16, tiles[ti], p->w.pack, p->w.pack_bytes,
+                                   p->w.sb_order, p->w.sb_order_len, p->w.spart, nsplit, p->w.bx, p->w.bx_part, &off,
+                                   stream);
+        if (r == hipSuccess) r = hipEventRecord(e1, stream);
+        if (r == hipSuccess) r = hipEventSynchronize(e1);
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+        if (r != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return hip_fail(r, "sbuild autotune");
+        }
+        if (ms < best) { best = ms; bk = tiles[ti]; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    p->w.sb_kt = bk;
+    if (k_tile_out) *k_tile_out = bk;
+    if (best_ms) *best_ms = best;
     return CRBM_OK;
 }
 

@@ -61,10 +61,7 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
 constexpr int MK_TS = 8;        // extended sites per W/b row tile
 constexpr int MK_TH = 16;       // hidden units per W/b row tile
 constexpr int MK_AB = 128;      // a rows per border block
-#ifndef CRBM_MK_KT
-#define CRBM_MK_KT 128
-#endif
-constexpr int MK_KT = CRBM_MK_KT;   // samples per LDS K tile (BF16 main kernel)
+constexpr int MK_KT = 128;          // sample padding of the packed planes: the largest K tile of any variant
 constexpr int MK_KB = 64;           // K tiles per accumulation block (FP32 main kernel: 4096 samples)
 
 struct SbGeom {
@@ -241,7 +238,7 @@ struct Stager {
 // ------------------------------------------------------------------ main kernel: W/b tile pairs
 // Split mode (nsplit > 1): workgroup x handles tile pair x % n_order over the K tiles of split
 // x / n_order and writes the raw sums into S + split * P * P (no scaling, no means).
-template <bool BF16>
+template <bool BF16, int KTB>
 __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* __restrict__ order, long n_order,
                                                         long ns_pad, int nsplit,
                                                         const typename Pol<BF16>::E* __restrict__ Tr,
@@ -249,7 +246,7 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
                                                         const typename Pol<BF16>::E* __restrict__ Sm,
                                                         Centre cen, float2* __restrict__ S) {
     using E = typename Pol<BF16>::E;
-    constexpr int KT = BF16 ? MK_KT : 64;          // samples per LDS K tile of this precision
+    constexpr int KT = BF16 ? KTB : 64;            // samples per LDS K tile (BF16: 64 or 128, tuned per plan)
     // bytes per LDS row, padded so that the 16 rows of a fragment read fall in distinct banks
     constexpr int ROWB = KT * (int)sizeof(E) + (BF16 ? 16 : 4);
     // stage rows: [0,16) Tr(A) [16,32) Ti(A) [32,48) Tr(B) [48,64) Ti(B) [64,72) masks(A) [72,80) masks(B)
@@ -320,10 +317,11 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
         }
     };
 
-    // this workgroup's K tiles [kt0, kt1)
+    // this workgroup's K tiles [kt0, kt1): the split ranges are set in 128-sample units, so that every
+    // K tile size sums the same samples in the same order
     const long n_kt_all = ns_pad / KT;
-    const long per = (n_kt_all + nsplit - 1) / nsplit;
-    const long kt0 = split * per;
+    const long per = (ns_pad / MK_KT + nsplit - 1) / nsplit * (MK_KT / KT);
+    const long kt0 = split * per < n_kt_all ? split * per : n_kt_all;
     const long kt1 = kt0 + per < n_kt_all ? kt0 + per : n_kt_all;
     if (kt0 < kt1) {
         gload(kt0);
@@ -753,11 +751,12 @@ int sbuild_splits(int N, int M, long n, int n_cu, int max_splits) {
 // shift: <O> of the unrounded operands (c_j from its b entries); Om: <O> of the operands as contracted
 // (T' rounded as packed, plus c); bx: N x P side buffer; bx_part: nsplit of them when nsplit > 1.
 hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n,
-                              const double2* shift, const double2* Om, float2* S, int prec, void* pack,
+                              const double2* shift, const double2* Om, float2* S, int prec, int kt_bf16, void* pack,
                               size_t pack_bytes, const int2* order, long n_order, float2* split_buf, int nsplit,
                               float2* bx, float2* bx_part, Profiler* prof, hipStream_t stream) {
     const SbGeom gm = sb_geom(N, M);
     if (nsplit > 1 && (!split_buf || !bx_part)) return hipErrorInvalidValue;
+    if (kt_bf16 != 64 && kt_bf16 != 128) return hipErrorInvalidValue;
     if (!bx) return hipErrorInvalidValue;
     const long ns_pad = ((n + MK_KT - 1) / MK_KT) * MK_KT;
     static_assert(MK_KT % 64 == 0, "the packing grid assumes 64-sample blocks");
@@ -798,8 +797,14 @@ hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const flo
                                bx_part, bx);
         prof->end(stream);
         prof->begin(PROF_SBUILD, stream);
-        hipLaunchKernelGGL(k_sbuild_mfma<B16>, dim3((unsigned)(n_order * nsplit)), dim3(256), 0, stream, gm, order,
-                           n_order, ns_pad, nsplit, Tr, Ti, Sm, cen, nsplit > 1 ? split_buf : S);
+        float2* out = nsplit > 1 ? split_buf : S;
+        const dim3 grid((unsigned)(n_order * nsplit));
+        if (B16 && kt_bf16 == 64)
+            hipLaunchKernelGGL((k_sbuild_mfma<B16, 64>), grid, dim3(256), 0, stream, gm, order, n_order, ns_pad, nsplit,
+                               Tr, Ti, Sm, cen, out);
+        else
+            hipLaunchKernelGGL((k_sbuild_mfma<B16, 128>), grid, dim3(256), 0, stream, gm, order, n_order, ns_pad,
+                               nsplit, Tr, Ti, Sm, cen, out);
         prof->end(stream);
         prof->begin(PROF_SBORDER, stream);
         if (nsplit > 1)

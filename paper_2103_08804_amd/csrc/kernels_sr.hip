@@ -962,11 +962,6 @@ static inline unsigned nblk(long n, int t = 256) { return (unsigned)((n + t - 1)
 
 hipError_t launch_cholesky_solve(long P, const float2* S, double eps, const double2* F, double2* A64, double2* x,
                                  double* sc, bool a64_holds_s, hipStream_t stream);
-hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n,
-                              const double2* shift, const double2* Om, float2* S, int prec, void* pack,
-                              size_t pack_bytes, const int2* order, long n_order, float2* split_buf, int nsplit,
-                              float2* bx, float2* bx_part, Profiler* prof, hipStream_t stream);
-int sbuild_splits(int N, int M, long n, int n_cu, int max_splits);
 
 static hipError_t apply_op(const SrArgs& A, const SrWork& W, const double2* v, double2* y, hipStream_t stream) {
     const long P = A.P;
@@ -1046,7 +1041,7 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
                 if (e != hipSuccess) return e;
             }
             const int nsplit = W.spart ? sbuild_splits(A.N, A.M, A.n, W.n_cu, W.nsplit_max) : 1;
-            e = launch_sbuild_mfma(A.N, A.M, P, A.samples, A.T, A.n, W.Om, W.Om16, W.S, A.prec, W.pack,
+            e = launch_sbuild_mfma(A.N, A.M, P, A.samples, A.T, A.n, W.Om, W.Om16, W.S, A.prec, W.sb_kt, W.pack,
                                    W.pack_bytes, W.sb_order, W.sb_order_len, W.spart, nsplit, W.bx, W.bx_part,
                                    W.prof, stream);
         } else {

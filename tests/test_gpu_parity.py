@@ -500,3 +500,36 @@ def test_ceiling_probes():
     assert 500.0 < gbs < 20000.0
     assert 1e11 < lc < 1e14
     assert 100.0 < gg < 100000.0
+
+
+@pytest.mark.parametrize("kind,Lx,Ly,M,n", [(1, 4, 4, 40, 777), (1, 10, 10, 80, 1100)])
+def test_sbuild_k_tiles_bit_identical(orc, kind, Lx, Ly, M, n):
+    """The BF16 S contraction with K tiles of 64 and 128 samples gives the same S and the same update
+    bit for bit (split over samples for the small model, one pass per tile pair for the larger), and the
+    autotuner picks one of them."""
+    N = Lx * Ly
+    fit_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(80 + N, N, M, 0.2, std_im=0.05)))
+    sig = synth.random_spins(81, n, N, True)
+    r = np.random.default_rng(4)
+    R = torch.from_numpy((1 + 0.3 * r.normal(size=n) + 0.2j * r.normal(size=n)).astype(np.complex64)).cuda()
+    plan = _plan(kind, Lx, Ly, M, n, crbm.PLAN_DENSE_S)
+    sd = torch.from_numpy(sig).cuda()
+    T = torch.zeros(n, M, dtype=torch.complex64, device="cuda")
+    crbm.local_estimators(plan, fit_d, sd, tanh_out=T)
+    out = {}
+    for kt in (128, 64):
+        crbm.set_sbuild_tile(plan, kt)
+        fd = crbm.RBM(fit_d.a.clone(), fit_d.b.clone(), fit_d.W.clone())
+        stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+        crbm.sr_step(plan, fd, sd, T, R, 0.1, 1e-2, crbm.CG_DENSE, crbm.BF16, 1e-8, 2000, stats)
+        S = torch.zeros(plan.P, plan.P, dtype=torch.complex64, device="cuda")
+        crbm.copy_plan_buffer(plan, crbm.BUF_S, S)
+        dx = torch.zeros(plan.P, dtype=torch.complex128, device="cuda")
+        crbm.copy_plan_buffer(plan, crbm.BUF_DALPHA, dx)
+        torch.cuda.synchronize()
+        out[kt] = (S, dx)
+    assert torch.equal(out[128][0], out[64][0])
+    assert torch.equal(out[128][1], out[64][1])
+    kt, ms = crbm.sbuild_autotune(plan, sd, T)
+    print("autotuned K tile", kt, "ms", ms)
+    assert kt in (64, 128) and ms > 0
