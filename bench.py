@@ -425,6 +425,15 @@ def bench_chain40(crbm, args):
 
     el, phases = _timed(plan, step, args.steps, args.warmup)
     st = stats.cpu().numpy()
+    # the FP32 S contraction of the b and W rows (R = P - N): 4 R (R + 1) N_s FLOP on the FP32 matrix cores;
+    # its row tiles are 8 extended sites x 16 units, so N + 1 = 41 sites run as 48
+    t_sb = phases["sbuild"]["avg_ms"] / 1e3
+    R_rows = P - N
+    flops = 4.0 * R_rows * (R_rows + 1) * ns
+    rows_run = 8 * ((N + 1 + 7) // 8) * 16 * ((M + 15) // 16)
+    roof = {"kernel": "k_sbuild_mfma<false> (FP32 operands)", "bound": "mfma", "achieved": flops / t_sb / 1e12,
+            "peak": FP32_MATRIX_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": flops / t_sb / 1e12 / FP32_MATRIX_PEAK_TFLOPS,
+            "traffic": None, "algorithmic_flops": flops, "rows_run_per_useful_row": rows_run / R_rows}
     print(json.dumps({"metric": "MC samples/s + SR steps/s", "value": ns / el, "unit": "samples/s", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3, "higher_is_better": True,
                       "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -432,7 +441,7 @@ def bench_chain40(crbm, args):
                                  "sweeps": sweeps, "samples_per_step": ns, "solver": "cholesky_fp64",
                                  "s_precision": "fp32", "diag_shift": wl.diag_shift},
                       "sr_steps_per_s": 1.0 / el, "sr_flags": int(st[6]), "rel_residual": float(st[4]),
-                      "phases": phases}))
+                      "phases": phases, "roofline": roof}))
     plan.close()
 
 
@@ -630,13 +639,33 @@ def bench_grad16(crbm, args):
         L.backward()
 
     el, phases = _timed(plan, step, args.steps, args.warmup)
+    # forward local estimators (k_local): per sample and anti-aligned bond, every hidden unit multiplies its
+    # bond factor (X + w Y: 4 FMA) into the running complex product (6 FLOP): 14 FLOP per (sample, bond, unit),
+    # on the vector units; a bond's table row (M x 16 B) is read once per wave of 4 samples if any of them has
+    # the bond anti-aligned.  The O^H c contraction of the backward (k_ot, one coefficient vector):
+    # 8 (N + 1)(M + 1) n FLOP on the FP32 matrix cores.
+    sg = samples.cpu().numpy().astype(np.int8).reshape(C, wl.Ly, wl.Lx)
+    anti = np.stack([sg != np.roll(sg, -1, axis=2), sg != np.roll(sg, -1, axis=1)], axis=1).reshape(C, -1)
+    n_anti = int(anti.sum())
+    rows_read = int(anti[: C // 4 * 4].reshape(C // 4, 4, -1).any(axis=1).sum())
+    t_loc = phases["local"]["avg_ms"] / 1e3
+    f_loc = 14.0 * n_anti * M
+    t_ot = phases["ot"]["avg_ms"] / 1e3
+    f_ot = 8.0 * (N + 1) * (M + 1) * C
+    roof = {"kernel": "k_local (forward local estimators)", "bound": "alu", "achieved": f_loc / t_loc / 1e12,
+            "peak": 157.3, "unit": "TFLOP/s", "frac": f_loc / t_loc / 1e12 / 157.3, "traffic": None,
+            "anti_aligned_bonds_per_sample": n_anti / C,
+            "bond_table_read_TBps": rows_read * M * 16 / t_loc / 1e12,
+            "peak_note": "FP32 vector peak (256 CUs x 4 SIMD x 64 lanes x 2 FLOP x 2.4 GHz)"}
+    roof_ot = {"kernel": "k_ot (O^H c of the backward)", "bound": "mfma", "achieved": f_ot / t_ot / 1e12,
+               "peak": FP32_MATRIX_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": f_ot / t_ot / 1e12 / FP32_MATRIX_PEAK_TFLOPS}
     print(json.dumps({"metric": "fidelity-surrogate gradients/s", "value": 1.0 / el, "unit": "gradients/s",
                       "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": el * 1e3,
                       "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
                       "data": "synthetic",
                       "config": {"workload": "heisenberg_square16x16_rbm_alpha2_gradient", "N": N, "M": M, "P": P,
                                  "samples": C, "burn_in_sweeps": 64},
-                      "samples_per_s": C / el, "phases": phases}))
+                      "samples_per_s": C / el, "phases": phases, "roofline": roof, "ot_roofline": roof_ot}))
     plan.close()
 
 
