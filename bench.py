@@ -177,10 +177,12 @@ def main():
         kt, kt_ms = crbm.sbuild_autotune(plan, flat, T)
         sb_tile = {"k_tile": kt, "probe_ms": kt_ms, "candidates": [64, 128]}
     plan.profile(True)
+    per_step = torch.zeros(args.steps, 8, dtype=torch.float64, device="cuda")   # each step's SR stats
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         step()
+        per_step[k].copy_(stats, non_blocking=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = plan.profile_read()
@@ -256,6 +258,8 @@ def main():
         "cg_iterations": float(st[5]), "cg_rel_residual": float(st[4]), "sr_flags": int(st[6]),
         "gamma": float(st[0]),
         "sbuild_autotune": sb_tile,
+        "per_step": {"gamma": [float(x) for x in per_step[:, 0].cpu()],
+                     "cg_iterations": [float(x) for x in per_step[:, 5].cpu()]},
         "phases": phases,
         "roofline": roof,
         "sampler_roofline": sampler,
