@@ -36,7 +36,11 @@ EPS32 = 2.0 ** -24
 def logpsi_rounding_bound(rbm, sig, c=16.0):
     """First-order bound on the FP32 error of log psi caused by rounding theta:
     |d log psi| <= sum_k |tanh theta_k| |d theta_k|, |d theta_k| <= c eps (|b_k| + sum_i |W_ik|).
-    Large where theta_k approaches a zero of cosh (the amplitude itself nearly vanishes)."""
+    Large where theta_k approaches a zero of cosh (the amplitude itself nearly vanishes).
+    c = 16 for N <= 16 sites: theta = b + sigma W comes from three v_mfma_f32_32x32x16_bf16 products
+    (the exact BF16 parts of W), each adding a 16-term dot product to the FP32 accumulator, so at most
+    1 + log2(16) = 5 roundings per part (the dot product's pairwise levels and the accumulation),
+    15 for the three parts, and one more for b."""
     sig = np.asarray(sig, np.float64)
     th = rbm.b[None, :] + sig @ rbm.W
     scale = np.abs(rbm.b) + np.abs(rbm.W).sum(axis=0)
