@@ -430,11 +430,13 @@ def bench_chain40(crbm, args):
     el, phases = _timed(plan, step, args.steps, args.warmup)
     st = stats.cpu().numpy()
     # the FP32 S contraction of the b and W rows (R = P - N): 4 R (R + 1) N_s FLOP on the FP32 matrix cores;
-    # its row tiles are 8 extended sites x 16 units, so N + 1 = 41 sites run as 48
+    # its row tiles are 8 sites x 16 units; with N a multiple of 8 the b rows (site N) run as thin
+    # 2-site fragments, so 41 extended sites run as 42 rather than 48
     t_sb = phases["sbuild"]["avg_ms"] / 1e3
     R_rows = P - N
     flops = 4.0 * R_rows * (R_rows + 1) * ns
-    rows_run = 8 * ((N + 1 + 7) // 8) * 16 * ((M + 15) // 16)
+    sites_run = N + 2 if N % 8 == 0 else 8 * ((N + 1 + 7) // 8)
+    rows_run = sites_run * 16 * ((M + 15) // 16)
     roof = {"kernel": "k_sbuild_mfma<false> (FP32 operands)", "bound": "mfma", "achieved": flops / t_sb / 1e12,
             "peak": FP32_MATRIX_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": flops / t_sb / 1e12 / FP32_MATRIX_PEAK_TFLOPS,
             "traffic": None, "algorithmic_flops": flops, "rows_run_per_useful_row": rows_run / R_rows}

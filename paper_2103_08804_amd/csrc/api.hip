@@ -28,6 +28,7 @@ hipError_t launch_moment_accum(const double2* f, const double2* B, int b_is_f, c
 hipError_t launch_moment_final(const double2* partial, int n_blocks, int total, double2* mu, hipStream_t stream);
 size_t sbuild_pack_bytes(int N, int M, long max_samples);
 std::vector<int2> sbuild_order(int N, int M, int n_xcd, int g);
+std::vector<int2> sbuild_order_thin(int N, int M);
 hipError_t launch_basis_pack(long n, const double2* B, const float2* loc, int mul, float2* Bcol, float2* HBcol,
                              hipStream_t stream);
 long gram_partial_len(int K);
@@ -66,7 +67,7 @@ constexpr int kMomBlocks = 256;
 constexpr int kMaxMomentEntries = 4096;   // n_q * (n_max + 1)
 constexpr int kMaxBasis = 256;             // K = n_max + 1 of the moment-correction matrices
 constexpr long kSplitBytes = 1L << 30;     // bound of the split-contraction buffer
-constexpr long kMaxSplits = 8;
+constexpr long kMaxSplits = 12;
 constexpr int kXcds = 8;                   // accelerator complex dies of the MI355X (round-robin dispatch)
 #ifndef CRBM_SUPERTILE
 #define CRBM_SUPERTILE 8
@@ -339,7 +340,7 @@ int crbm_plan_create_ex(crbm_plan* out, const crbm_lattice* lat, int n_hidden, l
         rc = rc ? rc : p->alloc(&p->w.hv_part, nT * nT * kHemvTile);
     }
     if (!rc && (flags & CRBM_PLAN_CHOLESKY)) rc = p->alloc(&p->w.S64, P * P);
-    std::vector<int2> order;
+    std::vector<int2> order, thin;
     if (!rc && (flags & (CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY))) {
         p->w.pack_bytes = sbuild_pack_bytes((int)N, (int)M, S);
         rc = p->alloc(reinterpret_cast<unsigned char**>(&p->w.pack), p->w.pack_bytes);
@@ -348,6 +349,13 @@ int crbm_plan_create_ex(crbm_plan* out, const crbm_lattice* lat, int n_hidden, l
         rc = rc ? rc : p->alloc(&d_order, order.size());
         p->w.sb_order = d_order;
         p->w.sb_order_len = (long)order.size();
+        thin = sbuild_order_thin((int)N, (int)M);
+        if (!thin.empty()) {
+            int2* d_thin = nullptr;
+            rc = rc ? rc : p->alloc(&d_thin, thin.size());
+            p->w.sb_order_thin = d_thin;
+            p->w.sb_order_thin_len = (long)thin.size();
+        }
         // buffer of a contraction split over samples when the tile pairs alone cannot fill the device
         const long slice = P * P * (long)sizeof(float2);
         const long nsm = std::min<long>(kMaxSplits, kSplitBytes / slice);
@@ -390,6 +398,9 @@ int crbm_plan_create_ex(crbm_plan* out, const crbm_lattice* lat, int n_hidden, l
     if (e == hipSuccess) e = hipMemset(p->w.scal, 0, 32 * sizeof(double));
     if (e == hipSuccess && !order.empty())
         e = hipMemcpy(const_cast<int2*>(p->w.sb_order), order.data(), order.size() * sizeof(int2),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !thin.empty() && p->w.sb_order_thin)
+        e = hipMemcpy(const_cast<int2*>(p->w.sb_order_thin), thin.data(), thin.size() * sizeof(int2),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) { delete p; return hip_fail(e, "plan initialisation"); }
     *out = p;
@@ -1236,8 +1247,8 @@ int crbm_sbuild_autotune(crbm_plan p, const int8_t* samples, const void* tanh_th
         if (r == hipSuccess)
             r = launch_sbuild_mfma((int)p->N, (int)p->M, p->P, samples, static_cast<const float2*>(tanh_theta), n,
                                    p->w.Om, p->w.Om, p->w.S, CRBM_PREC_BF16, tiles[ti], p->w.pack, p->w.pack_bytes,
-                                   p->w.sb_order, p->w.sb_order_len, p->w.spart, nsplit, p->w.bx, p->w.bx_part, &off,
-                                   stream);
+                                   p->w.sb_order, p->w.sb_order_len, p->w.sb_order_thin, p->w.sb_order_thin_len,
+                                   p->w.spart, nsplit, p->w.bx, p->w.bx_part, &off, stream);
         if (r == hipSuccess) r = hipEventRecord(e1, stream);
         if (r == hipSuccess) r = hipEventSynchronize(e1);
         if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);

@@ -128,6 +128,8 @@ struct SrWork {
     size_t pack_bytes;
     const int2* sb_order;     // dispatch order of its tile pairs
     long sb_order_len;
+    const int2* sb_order_thin; // its thin pairs (the b rows when N is a multiple of 8), or null
+    long sb_order_thin_len;
     float2* spart;            // [nsplit_max][P][P] partial sums of a contraction split over samples (or null)
     float2* bx;               // [N][P] raw a-row sums of the matrix-core S contraction
     float2* bx_part;          // [nsplit_max][N][P] their split partial sums (with spart)
@@ -188,8 +190,9 @@ struct BatchedArgs {
 // the matrix-core S contraction (kernels_mfma.hip); kt_bf16: K tile of the BF16 variant, 64 or 128
 hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n,
                               const double2* shift, const double2* Om, float2* S, int prec, int kt_bf16, void* pack,
-                              size_t pack_bytes, const int2* order, long n_order, float2* split_buf, int nsplit,
-                              float2* bx, float2* bx_part, Profiler* prof, hipStream_t stream);
+                              size_t pack_bytes, const int2* order, long n_order, const int2* order_thin,
+                              long n_thin, float2* split_buf, int nsplit, float2* bx, float2* bx_part, Profiler* prof,
+                              hipStream_t stream);
 int sbuild_splits(int N, int M, long n, int n_cu, int max_splits);
 
 // lanes per chain: 64 (any M), 32 (M <= 256) or 16 (M <= 128); the results are the same bit for bit

@@ -238,7 +238,7 @@ struct Stager {
 // ------------------------------------------------------------------ main kernel: W/b tile pairs
 // Split mode (nsplit > 1): workgroup x handles tile pair x % n_order over the K tiles of split
 // x / n_order and writes the raw sums into S + split * P * P (no scaling, no means).
-template <bool BF16, int KTB>
+template <bool BF16, int KTB, bool THIN>
 __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* __restrict__ order, long n_order,
                                                         long ns_pad, int nsplit,
                                                         const typename Pol<BF16>::E* __restrict__ Tr,
@@ -255,11 +255,14 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
     using St = Stager<ROWS, KT, E>;
 
-    // tile pair (u, u'), u <= u', from the dispatch-order table (entries < 0 are padding)
+    // tile pair (u, u'), u <= u', from the dispatch-order table (entries < 0 are padding).  THIN: the pair
+    // (h, u') of the b rows of hidden block h (the last site block, whose only real site is N: one
+    // 32-row fragment, sites N and N + 1) against tile u'; every wave takes that fragment against one
+    // fragment of u'.  Otherwise each wave takes 2 x 2 fragments of the two 128-row tiles.
     const int split = (int)(blockIdx.x / n_order);
     const int2 pr = order[blockIdx.x % n_order];
     if (pr.x < 0) return;
-    const int u = pr.x, up = pr.y;
+    const int u = THIN ? (gm.nSB - 1) * gm.nHB + pr.x : pr.x, up = pr.y;
     const int sbA = u / gm.nHB, hbA = u % gm.nHB;
     const int sbB = up / gm.nHB, hbB = up % gm.nHB;
     const int N = gm.N, M = gm.M;
@@ -267,12 +270,15 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wi = wave >> 1, wj = wave & 1;
+    constexpr int AF = THIN ? 1 : 2, BF = THIN ? 1 : 2;     // fragments per wave
+    auto fragA = [&](int a) { return THIN ? 0 : 2 * wi + a; };
+    auto fragB = [&](int b) { return THIN ? wave : 2 * wj + b; };
 
-    floatx16 acc_re[2][2], acc_im[2][2];
+    floatx16 acc_re[AF][BF], acc_im[AF][BF];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < AF; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < BF; ++b)
 #pragma unroll
             for (int v = 0; v < 16; ++v) { acc_re[a][b][v] = 0.f; acc_im[a][b][v] = 0.f; }
 
@@ -342,15 +348,15 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
         int ln = lane;
         asm volatile("" : "+v"(ln));
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < AF; ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
+            for (int b = 0; b < BF; ++b) {
                 const int qB = ln & 31;
-                const long kp = wb_to_p(sbB * MK_TS + 2 * (2 * wj + b) + (qB >> 4), hbB * MK_TH + (qB & 15), N, M);
+                const long kp = wb_to_p(sbB * MK_TS + 2 * fragB(b) + (qB >> 4), hbB * MK_TH + (qB & 15), N, M);
 #pragma unroll
                 for (int v = 0; v < 16; ++v) {
                     const int qA = 8 * (v >> 2) + 4 * (ln >> 5) + (v & 3);
-                    const long k = wb_to_p(sbA * MK_TS + 2 * (2 * wi + a) + (qA >> 4), hbA * MK_TH + (qA & 15), N, M);
+                    const long k = wb_to_p(sbA * MK_TS + 2 * fragA(a) + (qA >> 4), hbA * MK_TH + (qA & 15), N, M);
                     if (k >= 0 && kp >= 0) {
                         float2* o = out + k * P + kp;
                         const float2 prev = flushed ? *o : make_float2(0.f, 0.f);
@@ -378,37 +384,41 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
                 const i32x4 tiA = *reinterpret_cast<const i32x4*>(base + (16 + trow) * ROWB + koff);
                 const i32x4 trB = *reinterpret_cast<const i32x4*>(base + (32 + trow) * ROWB + koff);
                 const i32x4 tiB = *reinterpret_cast<const i32x4*>(base + (48 + trow) * ROWB + koff);
-                i32x4 mA[2], mB[2];
+                i32x4 mA[AF], mB[BF];
 #pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    mA[a] = *reinterpret_cast<const i32x4*>(base + (64 + 2 * (2 * wi + a) + qs) * ROWB + koff);
-                    mB[a] = *reinterpret_cast<const i32x4*>(base + (72 + 2 * (2 * wj + a) + qs) * ROWB + koff);
-                }
+                for (int a = 0; a < AF; ++a)
+                    mA[a] = *reinterpret_cast<const i32x4*>(base + (64 + 2 * fragA(a) + qs) * ROWB + koff);
+#pragma unroll
+                for (int b = 0; b < BF; ++b)
+                    mB[b] = *reinterpret_cast<const i32x4*>(base + (72 + 2 * fragB(b) + qs) * ROWB + koff);
                 const i32x4 neg = {(int)0x80008000, (int)0x80008000, (int)0x80008000, (int)0x80008000};
-                i32x4 ar[2], ai[2], br[2], bi[2], nbr[2];
+                i32x4 ar[AF], ai[AF], br[BF], bi[BF], nbr[BF];
 #pragma unroll
-                for (int a = 0; a < 2; ++a) {
+                for (int a = 0; a < AF; ++a) {
                     ar[a] = trA ^ mA[a];
                     ai[a] = tiA ^ mA[a];
-                    br[a] = trB ^ mB[a];
-                    bi[a] = tiB ^ mB[a];
-                    nbr[a] = br[a] ^ neg;
+                }
+#pragma unroll
+                for (int b = 0; b < BF; ++b) {
+                    br[b] = trB ^ mB[b];
+                    bi[b] = tiB ^ mB[b];
+                    nbr[b] = br[b] ^ neg;
                 }
                 // first product of every accumulator, then the second: eight independent
                 // matrix-core operations separate the two updates of one accumulator
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
+                for (int a = 0; a < AF; ++a)
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) {
+                    for (int b = 0; b < BF; ++b) {
                         acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                             (bf16x8)ar[a], (bf16x8)br[b], acc_re[a][b], 0, 0, 0);
                         acc_im[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                             (bf16x8)ar[a], (bf16x8)bi[b], acc_im[a][b], 0, 0, 0);
                     }
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
+                for (int a = 0; a < AF; ++a)
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) {
+                    for (int b = 0; b < BF; ++b) {
                         acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                             (bf16x8)ai[a], (bf16x8)bi[b], acc_re[a][b], 0, 0, 0);
                         acc_im[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
@@ -419,17 +429,18 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
                 const uint32_t tiA = *reinterpret_cast<const uint32_t*>(base + (16 + trow) * ROWB + koff);
                 const uint32_t trB = *reinterpret_cast<const uint32_t*>(base + (32 + trow) * ROWB + koff);
                 const uint32_t tiB = *reinterpret_cast<const uint32_t*>(base + (48 + trow) * ROWB + koff);
-                uint32_t mA[2], mB[2];
+                uint32_t mA[AF], mB[BF];
 #pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    mA[a] = *reinterpret_cast<const uint32_t*>(base + (64 + 2 * (2 * wi + a) + qs) * ROWB + koff);
-                    mB[a] = *reinterpret_cast<const uint32_t*>(base + (72 + 2 * (2 * wj + a) + qs) * ROWB + koff);
-                }
+                for (int a = 0; a < AF; ++a)
+                    mA[a] = *reinterpret_cast<const uint32_t*>(base + (64 + 2 * fragA(a) + qs) * ROWB + koff);
 #pragma unroll
-                for (int a = 0; a < 2; ++a) {
+                for (int b = 0; b < BF; ++b)
+                    mB[b] = *reinterpret_cast<const uint32_t*>(base + (72 + 2 * fragB(b) + qs) * ROWB + koff);
+#pragma unroll
+                for (int a = 0; a < AF; ++a) {
                     const float ar = __uint_as_float(trA ^ mA[a]), ai = __uint_as_float(tiA ^ mA[a]);
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) {
+                    for (int b = 0; b < BF; ++b) {
                         const float br = __uint_as_float(trB ^ mB[b]), bi = __uint_as_float(tiB ^ mB[b]);
                         acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, acc_re[a][b], 0, 0, 0);
                         acc_re[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bi, acc_re[a][b], 0, 0, 0);
@@ -449,11 +460,11 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
     // epilogue: accumulator element v of lane l is row 8(v/4) + 4(l/32) + v%4 of the A fragment
     // and column l % 32 of the B fragment
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const int fA = 2 * wi + a;
+    for (int a = 0; a < AF; ++a) {
+        const int fA = fragA(a);
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int fB = 2 * wj + b;
+        for (int b = 0; b < BF; ++b) {
+            const int fB = fragB(b);
             const int qB = lane & 31;
             const int iB = sbB * MK_TS + 2 * fB + (qB >> 4), jB = hbB * MK_TH + (qB & 15);
             const long kp = wb_to_p(iB, jB, N, M);
@@ -732,19 +743,33 @@ __global__ __launch_bounds__(256) void k_sbuild_reduce(Centre cen, int nsplit, c
     S[e] = make_float2((float)d.x, k == kp ? 0.f : (float)d.y);
 }
 
-// Number of sample splits for a contraction of n samples: about eight workgroups per compute unit
-// (four rounds of two resident ones), at least 4 K tiles per split, and no more slices than the
-// plan's split buffer holds.
+// The b rows go to thin pairs when the last site block holds site N alone (N a multiple of 8): its
+// tiles would be 7/8 padding.
+bool sbuild_thin(int N) { return N % MK_TS == 0; }
+
+// Number of sample splits for a contraction of n samples when the tile pairs alone cannot fill the
+// device: the split count s (at most max_splits, which the plan's slice buffer holds, and at least 4
+// K tiles per split) that minimises the modelled time of the launches, sum over launches of
+// ceil(pairs s / resident workgroups) / s (rounds per unit of one pair's full-sample work; a thin pair
+// counts a quarter), so that the last round of each launch is not left nearly empty.
 int sbuild_splits(int N, int M, long n, int n_cu, int max_splits) {
     const SbGeom gm = sb_geom(N, M);
-    const long nW = (long)gm.nSB * gm.nHB;
-    const int nA = (N + MK_AB - 1) / MK_AB;
-    const long wgs = nW * (nW + 1) / 2 + (long)nA * (nW + nA);
+    const bool thin = sbuild_thin(N);
+    const long nt = (long)(thin ? gm.nSB - 1 : gm.nSB) * gm.nHB;
+    const long n_main = nt * (nt + 1) / 2;
+    const long n_thin = thin ? (long)gm.nHB * nt + (long)gm.nHB * (gm.nHB + 1) / 2 : 0;
     const long n_kt = ((n + MK_KT - 1) / MK_KT * MK_KT) / 64;    // the finest K tile of any variant is 64
-    long s = (8L * n_cu + wgs - 1) / wgs;
-    if (s > n_kt / 4) s = n_kt / 4;
-    if (s > max_splits) s = max_splits;
-    return s < 1 ? 1 : (int)s;
+    long smax = max_splits < n_kt / 4 ? max_splits : n_kt / 4;
+    if (smax < 1) smax = 1;
+    const long slots = 2L * n_cu;                                  // two resident workgroups per CU
+    double best = 1e300;
+    long bs = 1;
+    for (long sp = 1; sp <= smax; ++sp) {
+        const double t = (double)((n_main * sp + slots - 1) / slots) / (double)sp +
+                         0.25 * (double)((n_thin * sp + slots - 1) / slots) / (double)sp;
+        if (t < best * (1.0 - 1e-9)) { best = t; bs = sp; }
+    }
+    return (int)bs;
 }
 
 // ------------------------------------------------------------------ launcher
@@ -752,8 +777,9 @@ int sbuild_splits(int N, int M, long n, int n_cu, int max_splits) {
 // (T' rounded as packed, plus c); bx: N x P side buffer; bx_part: nsplit of them when nsplit > 1.
 hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n,
                               const double2* shift, const double2* Om, float2* S, int prec, int kt_bf16, void* pack,
-                              size_t pack_bytes, const int2* order, long n_order, float2* split_buf, int nsplit,
-                              float2* bx, float2* bx_part, Profiler* prof, hipStream_t stream) {
+                              size_t pack_bytes, const int2* order, long n_order, const int2* order_thin,
+                              long n_thin, float2* split_buf, int nsplit, float2* bx, float2* bx_part, Profiler* prof,
+                              hipStream_t stream) {
     const SbGeom gm = sb_geom(N, M);
     if (nsplit > 1 && (!split_buf || !bx_part)) return hipErrorInvalidValue;
     if (kt_bf16 != 64 && kt_bf16 != 128) return hipErrorInvalidValue;
@@ -800,11 +826,20 @@ hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const flo
         float2* out = nsplit > 1 ? split_buf : S;
         const dim3 grid((unsigned)(n_order * nsplit));
         if (B16 && kt_bf16 == 64)
-            hipLaunchKernelGGL((k_sbuild_mfma<B16, 64>), grid, dim3(256), 0, stream, gm, order, n_order, ns_pad, nsplit,
-                               Tr, Ti, Sm, cen, out);
-        else
-            hipLaunchKernelGGL((k_sbuild_mfma<B16, 128>), grid, dim3(256), 0, stream, gm, order, n_order, ns_pad,
+            hipLaunchKernelGGL((k_sbuild_mfma<B16, 64, false>), grid, dim3(256), 0, stream, gm, order, n_order, ns_pad,
                                nsplit, Tr, Ti, Sm, cen, out);
+        else
+            hipLaunchKernelGGL((k_sbuild_mfma<B16, 128, false>), grid, dim3(256), 0, stream, gm, order, n_order,
+                               ns_pad, nsplit, Tr, Ti, Sm, cen, out);
+        if (n_thin > 0) {
+            const dim3 gth((unsigned)(n_thin * nsplit));
+            if (B16 && kt_bf16 == 64)
+                hipLaunchKernelGGL((k_sbuild_mfma<B16, 64, true>), gth, dim3(256), 0, stream, gm, order_thin, n_thin,
+                                   ns_pad, nsplit, Tr, Ti, Sm, cen, out);
+            else
+                hipLaunchKernelGGL((k_sbuild_mfma<B16, 128, true>), gth, dim3(256), 0, stream, gm, order_thin, n_thin,
+                                   ns_pad, nsplit, Tr, Ti, Sm, cen, out);
+        }
         prof->end(stream);
         prof->begin(PROF_SBORDER, stream);
         if (nsplit > 1)
@@ -824,7 +859,8 @@ hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const flo
 // then share few operand slabs, which stay in that XCD's L2.  Padding entries are (-1, -1).
 std::vector<int2> sbuild_order(int N, int M, int n_xcd, int g) {
     const SbGeom gm = sb_geom(N, M);
-    const int nt = gm.nSB * gm.nHB;
+    // with thin pairs the main kernel takes the tiles of the sites [0, N) only
+    const int nt = (sbuild_thin(N) ? gm.nSB - 1 : gm.nSB) * gm.nHB;
     const int ns = (nt + g - 1) / g;
     std::vector<std::vector<int2>> per(n_xcd);
     int st = 0;
@@ -842,6 +878,20 @@ std::vector<int2> sbuild_order(int N, int M, int n_xcd, int g) {
     std::vector<int2> out(longest * n_xcd, make_int2(-1, -1));
     for (int x = 0; x < n_xcd; ++x)
         for (size_t k = 0; k < per[x].size(); ++k) out[k * n_xcd + x] = per[x][k];
+    return out;
+}
+
+// Thin pairs (h, u'): the b rows of hidden block h against every tile u' of the sites [0, N), and
+// against the b tiles of hidden blocks h' >= h; the pairs that share a B tile sit next to each other.
+std::vector<int2> sbuild_order_thin(int N, int M) {
+    std::vector<int2> out;
+    if (!sbuild_thin(N)) return out;
+    const SbGeom gm = sb_geom(N, M);
+    const int nt_main = (gm.nSB - 1) * gm.nHB;
+    for (int up = 0; up < nt_main; ++up)
+        for (int h = 0; h < gm.nHB; ++h) out.push_back(make_int2(h, up));
+    for (int h = 0; h < gm.nHB; ++h)
+        for (int h2 = h; h2 < gm.nHB; ++h2) out.push_back(make_int2(h, nt_main + h2));
     return out;
 }
 
