@@ -313,7 +313,8 @@ def bench_batched(crbm, args):
             "config": {"workload": "heisenberg_square8x8_rbm_alpha2_batched_moments", "instances": n_inst,
                        "momenta": n_q, "orders": n_ord, "total_chains": total, "burn_in_sweeps": n_burn,
                        "recorded_sweeps": n_sweeps, "chains_per_instance": [int(counts.min()), int(counts.max())]},
-            "autotuned": {"waves_per_block": w, "blocks": b, "lanes_per_chain": lanes, "probe_ms": tune_ms},
+            "autotuned": {"waves_per_block": w, "blocks": b, "lanes_per_chain": lanes, "probe_ms": tune_ms,
+                          "psi_gs_rows_in_lds": lanes == 64 and crbm.batched_lds_rows(plan, crbm.EXCHANGE, w)},
             "kernel_ms": prof["batched"][1] / prof["batched"][0],
             "chain_steps_per_s": total * (n_burn + n_sweeps) * N / el}
     # tail of the persistent launch: per-wave (start, end) clocks of the last timed launch
@@ -330,20 +331,32 @@ def bench_batched(crbm, args):
                              "sum of (launch end - wave start), the share of resident wave time spent idle once the "
                              "chain counter ran out")}
     # against its ceilings: half of the pair exchanges are live at S^z = 0 (independent uniform sites); a
-    # live one evaluates M Re log 2cosh of psi_gs and reads rows W_i, W_j of psi_gs (2 M complex64); the
-    # recorded sweeps add 2 M log cosh per chain (t~ and psi_gs); the rows of t~ read on accepted moves
-    # are not counted (a lower bound of the gathers)
+    # live one evaluates M Re log 2cosh of psi_gs and reads rows W_i, W_j of psi_gs (2 M complex64, from
+    # LDS when the kernel keeps a copy there); an accepted one also reads rows W_i, W_j of t~ (from L2);
+    # the recorded sweeps add 2 M log cosh per chain (t~ and psi_gs).  The accepted moves are counted
+    # from the accept trace of one more launch after the timed region.
     kern_s = line["kernel_ms"] / 1e3
     props = total * (n_burn + n_sweeps) * N
+    words = ((n_burn + n_sweeps) * N + 31) // 32
+    tr = torch.zeros(total, words, dtype=torch.int32, device="cuda")
+    crbm.batched_moments(plan, gs, tp, betas, qd, od, n_burn, n_sweeps, crbm.EXCHANGE, wl.chain_seed, mu, trace=tr)
+    accepted = sum(int(((tr >> b) & 1).sum().item()) for b in range(32))
+    del tr
+    in_lds = line["autotuned"]["psi_gs_rows_in_lds"]
     lc = (0.5 * props * M + 2.0 * total * n_sweeps * M) / kern_s
-    gb = 0.5 * props * 2 * M * 8 / kern_s / 1e9
+    gs_rows = 0.5 * props * 2 * M * 8 / kern_s / 1e9
+    t_rows = accepted * 2 * M * 8 / kern_s / 1e9
+    l2 = t_rows + (0.0 if in_lds else gs_rows)
     lc_ceil, g_ceil = crbm.probe_logcosh(), crbm.probe_gather(N, M)
     line["roofline"] = {"kernel": "k_batched", "bound": "alu", "achieved": lc / 1e12, "peak": lc_ceil / 1e12,
                         "unit": "Tlogcosh/s", "frac": lc / lc_ceil, "traffic": None,
-                        "row_gather_GBps": gb, "row_gather_ceiling_GBps": g_ceil, "row_gather_frac": gb / g_ceil,
+                        "accepted_frac": accepted / props,
+                        "l2_row_gather_GBps": l2, "row_gather_ceiling_GBps": g_ceil, "l2_row_gather_frac": l2 / g_ceil,
+                        "lds_row_GBps": gs_rows if in_lds else 0.0,
                         "peak_note": ("measured ceilings of this device: k_probe_logcosh (Re log 2cosh in the sweep's "
                                       "form, 8 independent per lane) and k_probe_gather (whole W rows at random "
-                                      "rows from L2)")}
+                                      "rows from L2); the L2 row gathers are the rows of t~ on accepted moves and, "
+                                      "unless psi_gs's W sits in LDS, the rows of psi_gs on live moves")}
     if not args.no_plain_path:
         line["plain_path"] = plain_path_batched(crbm, plan, gs, tp, betas, qs, counts, offsets, n_burn, n_sweeps, wl,
                                                 line["kernel_ms"])

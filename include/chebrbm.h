@@ -421,6 +421,12 @@ int crbm_sbuild_autotune(crbm_plan plan, const int8_t* samples, const void* tanh
  * 32 for M <= 256; 16 for M <= 128: several chains share a wave).  CRBM_EUNSUPPORTED for a lane count
  * that M does not allow.  Does not touch the device. */
 int crbm_batched_set_shape(crbm_plan plan, int waves_per_block, int blocks, int lanes_per_chain);
+/* Whether crbm_batched_moments on 64 lanes per chain, with this proposal kind (CRBM_PROPOSAL_FLIP or
+ * CRBM_PROPOSAL_EXCHANGE) and waves per block, reads the rows of psi_gs from a copy of its W in LDS
+ * (*uses = 1) rather than from global memory (*uses = 0).  The copy is taken when W (N M complex64) and the spin
+ * rows fit in the compute unit's LDS and the unit still holds as many blocks as without it; both paths
+ * give the same results bit for bit.  Queries the device's occupancy; enqueues nothing. */
+int crbm_batched_lds_rows(crbm_plan plan, int proposal, int waves_per_block, int* uses);
 
 #ifdef __cplusplus
 }

@@ -32,7 +32,7 @@ MAX_CLOCK_WAVES = 16384
 EXPORTS = ("crbm_plan_create", "crbm_plan_create_ex", "crbm_plan_destroy", "crbm_plan_buffer", "crbm_last_error", "crbm_plan_profile",
            "crbm_plan_profile_read", "crbm_init_rbm", "crbm_init_chains", "crbm_sample", "crbm_local_estimators",
            "crbm_sr_step", "crbm_sr_energy_step", "crbm_chebyshev_moment", "crbm_fidelity_grad", "crbm_batched_moments",
-           "crbm_batched_autotune", "crbm_batched_set_shape", "crbm_plan_set_sbuild_tile", "crbm_sbuild_autotune", "crbm_moment_matrices", "crbm_corrected_moments", "crbm_lanczos",
+           "crbm_batched_autotune", "crbm_batched_set_shape", "crbm_batched_lds_rows", "crbm_plan_set_sbuild_tile", "crbm_sbuild_autotune", "crbm_moment_matrices", "crbm_corrected_moments", "crbm_lanczos",
            "crbm_spectrum_kpm", "crbm_spectrum_cf", "crbm_probe_mfma", "crbm_probe_hbm", "crbm_probe_logcosh", "crbm_probe_gather",
            "crbm_sym_matrices", "crbm_fit_stats", "crbm_enum_weights",
            "crbm_fidelity_grad_noalloc")
@@ -105,6 +105,7 @@ def lib():
         L.crbm_batched_autotune.argtypes = [_vp, P(_Rbm), _vp, _vp, _vp, _vp, _i, ctypes.c_int64, _i, _i, _u64, _vp,
                                             P(_i), P(_i), P(_i), P(_d), _vp]
         L.crbm_batched_set_shape.argtypes = [_vp, _i, _i, _i]
+        L.crbm_batched_lds_rows.argtypes = [_vp, _i, _i, P(_i)]
         L.crbm_plan_set_sbuild_tile.argtypes = [_vp, _i]
         L.crbm_sbuild_autotune.argtypes = [_vp, _vp, _vp, _l, P(_i), P(_d), _vp]
         for name in EXPORTS:
@@ -517,6 +518,13 @@ def batched_autotune(plan: Plan, psi_gs: RBM, t_params, betas, q, chain_offsets,
 def batched_set_shape(plan: Plan, waves_per_block: int, blocks: int, lanes_per_chain: int):
     """Fix the launch shape of crbm_batched_moments (lanes per chain 64, 32 or 16)."""
     _check(lib().crbm_batched_set_shape(plan.handle, waves_per_block, blocks, lanes_per_chain))
+
+
+def batched_lds_rows(plan: Plan, proposal: int, waves_per_block: int) -> bool:
+    """Whether the 64-lane batched kernel reads psi_gs's rows from its copy in LDS at this shape."""
+    u = ctypes.c_int()
+    _check(lib().crbm_batched_lds_rows(plan.handle, proposal, waves_per_block, ctypes.byref(u)))
+    return bool(u.value)
 
 
 def set_sbuild_tile(plan: Plan, k_tile: int):

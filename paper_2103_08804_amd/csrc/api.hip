@@ -1280,4 +1280,14 @@ int crbm_batched_set_shape(crbm_plan p, int waves_per_block, int blocks, int lan
     return CRBM_OK;
 }
 
+int crbm_batched_lds_rows(crbm_plan p, int proposal, int waves_per_block, int* uses) {
+    if (check_plan(p)) return CRBM_EINVAL;
+    if (!uses) return fail(CRBM_EINVAL, "uses is NULL");
+    if (proposal != CRBM_PROPOSAL_FLIP && proposal != CRBM_PROPOSAL_EXCHANGE) return fail(CRBM_EINVAL, "unknown proposal %d", proposal);
+    if (waves_per_block < 1 || waves_per_block > 8) return fail(CRBM_EINVAL, "waves_per_block must be in [1, 8]");
+    if (int rc = set_device(p)) return rc;
+    *uses = batched_lds_rows((int)p->N, (int)p->M, proposal, waves_per_block) ? 1 : 0;
+    return CRBM_OK;
+}
+
 }  // extern "C"

@@ -197,6 +197,7 @@ int sbuild_splits(int N, int M, long n, int n_cu, int max_splits);
 
 // lanes per chain: 64 (any M), 32 (M <= 256) or 16 (M <= 128); the results are the same bit for bit
 bool batched_lanes_ok(int lanes, int M);
+bool batched_lds_rows(int N, int M, int proposal, int waves_per_block);
 hipError_t launch_batched(const BatchedArgs& A, int blocks, int waves_per_block, int lanes, double2* mu,
                           hipStream_t stream);
 // p[0, n) = 0 with a fill kernel (no memset node when captured)

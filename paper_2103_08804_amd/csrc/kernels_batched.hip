@@ -10,11 +10,16 @@
 // acceptance) and theta of t~_i (for the ratio) in registers and updates both
 // on every accepted move (theta of t~_i at the next accepted move or
 // measurement, so that its row reads overlap the proposals in between); after
-// each recorded sweep it adds the chain's terms in double precision.  Per-chain partial sums are reduced per instance
+// each recorded sweep it adds the chain's terms in double precision.  The rows
+// of psi_gs, the same for every chain, are read from a copy in LDS when it fits
+// without lowering the occupancy: every live proposal reads two of them, and
+// from L2 those reads, with the rows of t~_i, ran at the L2 gather ceiling.  Per-chain partial sums are reduced per instance
 // in chain order by a second kernel, so the result does not depend on the
 // schedule.  All launches are stream-ordered kernels (no host work), so the
 // sequence can be captured in a graph.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "../../include/chebrbm.h"
 #include "device.hpp"
@@ -22,6 +27,9 @@
 #include "sweep.hpp"
 
 namespace crbm {
+
+// LDS of one compute unit (gfx950), the most one block of k_batched may ask for
+constexpr int kMaxBatchedLds = 160 * 1024;
 
 __global__ void k_batched_reset(unsigned long long* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0ull;
@@ -51,6 +59,29 @@ __device__ __forceinline__ T site_value(const T (&v)[4], int i) {
     return __builtin_bit_cast(T, q == 0 ? v0 : q == 1 ? v1 : q == 2 ? v2 : v3);
 }
 
+// Spins of a chain of N <= 64 sites as one wave-uniform 64-bit word, bit i set for s_i = +1: reads,
+// flips and the null test of an exchange are scalar operations.
+struct SpinBits {
+    uint64_t m;
+    __device__ __forceinline__ void load(const int8_t* row, int N, int lane) {
+        m = __ballot(lane < N && row[lane] > 0);
+    }
+    __device__ __forceinline__ int get(int i) const { return ((m >> i) & 1ull) ? 1 : -1; }
+    __device__ __forceinline__ void flip(int i, int) { m ^= 1ull << i; }
+    // spin at site 64 q + lane (0 past N)
+    __device__ __forceinline__ int at(int q, int lane, int N) const {
+        return (q == 0 && lane < N) ? (((m >> lane) & 1ull) ? 1 : -1) : 0;
+    }
+};
+// The same interface over one site per lane and slot (N <= 256).
+struct SpinLanes {
+    WaveSpins w;
+    __device__ __forceinline__ void load(const int8_t* row, int N, int lane) { w.load(row, N, lane); }
+    __device__ __forceinline__ int get(int i) const { return w.get(i); }
+    __device__ __forceinline__ void flip(int i, int lane) { w.set(i, -w.get(i), lane); }
+    __device__ __forceinline__ int at(int q, int, int) const { return w.s[q]; }
+};
+
 // Rows of one whole [N][M] complex64 matrix through a single buffer descriptor: a row is a 32-bit scalar
 // offset and the lanes' columns loop-invariant vector offsets (clamped to the row), so a proposal's loads
 // need no 64-bit address arithmetic (the sweep here is bound by scalar issue, not by its row gathers).
@@ -79,9 +110,9 @@ __device__ __forceinline__ void mat_fetch(const MatRows& m, const unsigned (&lof
 // Per-chain state of one wave.  theta of t~ changes only on accepted moves;
 // its rows are fetched when a move is accepted and added at the next accepted
 // move or measurement, so their L2 round trip overlaps the following proposals.
-template <int E, bool PAIR>
+template <int E, bool PAIR, bool ONE>
 struct BatchedChain {
-    WaveSpins sp;
+    std::conditional_t<ONE, SpinBits, SpinLanes> sp;
     float ag[4];            // Re a of psi_gs at sites 64 q + lane
     float2 thg[E], tht[E];  // theta of psi_gs and of t~
     float Lg[E];            // Re log 2cosh theta_gs
@@ -104,8 +135,8 @@ __device__ __forceinline__ float2 unit_log_ratio(float2 zt, float2 zg) {
     return make_float2(fabsf(zt.x) - fabsf(zg.x) + 0.5f * logf(na / nb), st * zt.y - sg * zg.y + atan2f(q.y, q.x));
 }
 
-template <int E, bool PAIR>
-__device__ __forceinline__ void apply_pending(BatchedChain<E, PAIR>& c, int lane, int M) {
+template <int E, bool PAIR, bool ONE>
+__device__ __forceinline__ void apply_pending(BatchedChain<E, PAIR, ONE>& c, int lane, int M) {
     if (c.pm != 0.f) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -123,8 +154,8 @@ __device__ __forceinline__ void apply_pending(BatchedChain<E, PAIR>& c, int lane
 // then the lanes by bits 0 .. 5.  The unit terms are log 2cosh(theta_t) - log 2cosh(theta_gs) per
 // unit (unit_log_ratio), the site terms (a_t - a_gs) s and e^{-i q.r} s / 2.
 // ph: e^{-i q.r} and da: a_t - a_gs at this lane's sites
-template <int E, bool PAIR>
-__device__ __forceinline__ void measure(const BatchedArgs& A, BatchedChain<E, PAIR>& c, const float2 (&ph)[4],
+template <int E, bool PAIR, bool ONE>
+__device__ __forceinline__ void measure(const BatchedArgs& A, BatchedChain<E, PAIR, ONE>& c, const float2 (&ph)[4],
                                         const float2 (&da)[4], double2 beta, int lane) {
     const int N = A.N, M = A.M;
     apply_pending(c, lane, M);
@@ -133,7 +164,7 @@ __device__ __forceinline__ void measure(const BatchedArgs& A, BatchedChain<E, PA
     for (int qq = 0; qq < 4; ++qq) {
         const int site = qq * kWave + lane;
         if (site < N) {
-            const float s = (float)c.sp.s[qq];
+            const float s = (float)c.sp.at(qq, lane, N);
             f = cadd(f, cscale(ph[qq], 0.5f * s));
             dA = cadd(dA, cscale(da[qq], s));
         }
@@ -151,20 +182,30 @@ __device__ __forceinline__ void measure(const BatchedArgs& A, BatchedChain<E, PA
     c.mi += fx * br.y - fy * br.x;
 }
 
-// Proposal t of chain g.  Rows of psi_gs are read only for live moves.
-template <int E, bool PAIR, bool ONE>
-__device__ __forceinline__ void batched_step(const BatchedArgs& A, uint64_t g, int lane, int t,
-                                             BatchedChain<E, PAIR>& c, const MatRows& Wg, const MatRows& Wt,
+// Proposal t of chain g.  Rows of psi_gs are read only for live moves, from LDS (s_w) when LDSG.
+template <int E, bool PAIR, bool ONE, bool LDSG>
+__device__ __forceinline__ void batched_step(const BatchedArgs& A, const float2* s_w, uint64_t g, int lane, int t,
+                                             BatchedChain<E, PAIR, ONE>& c, const MatRows& Wg, const MatRows& Wt,
                                              const unsigned (&loff)[E], uint32_t* trow, DrawBatch& batch) {
     const int N = A.N, M = A.M;
     Proposal cur = next_proposal(batch, A.seed, (uint32_t)g, 0ull, t, lane, N);
-    const int si = site_value<ONE>(c.sp.s, cur.i), sj = site_value<ONE>(c.sp.s, cur.j);
+    const int si = c.sp.get(cur.i), sj = c.sp.get(cur.j);
     if (!(PAIR && si == sj)) {
         float2 wi[E], wj[E], tn[E];
         float Ln[E];
         cur.ai = site_value<ONE>(c.ag, cur.i);
         cur.aj = PAIR ? site_value<ONE>(c.ag, cur.j) : 0.f;
-        mat_fetch<E, PAIR>(Wg, loff, cur.i, cur.j, wi, wj);
+        if (LDSG) {
+            const int oi = cur.i * M, oj = cur.j * M;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int col = (int)(loff[e] / sizeof(float2));
+                wi[e] = s_w[oi + col];
+                if (PAIR) wj[e] = s_w[oj + col];
+            }
+        } else {
+            mat_fetch<E, PAIR>(Wg, loff, cur.i, cur.j, wi, wj);
+        }
         const float dl = proposal_dlog<E, PAIR>(cur, si, wi, wj, c.thg, c.Lg, tn, Ln, lane, M);
         if (cur.u < __expf(2.f * dl)) {
 #pragma unroll
@@ -172,9 +213,9 @@ __device__ __forceinline__ void batched_step(const BatchedArgs& A, uint64_t g, i
             apply_pending(c, lane, M);
             mat_fetch<E, PAIR>(Wt, loff, cur.i, cur.j, c.pti, c.ptj);
             c.pm = -2.f * (float)si;
-            c.sp.set(cur.i, -si, lane);
-            if (PAIR) c.sp.set(cur.j, -sj, lane);
-            c.tw |= 1u << (t & 31);
+            c.sp.flip(cur.i, lane);
+            if (PAIR) c.sp.flip(cur.j, lane);
+            if (trow) c.tw |= 1u << (t & 31);
         }
     }
     if (trow && ((t & 31) == 31)) {
@@ -183,16 +224,22 @@ __device__ __forceinline__ void batched_step(const BatchedArgs& A, uint64_t g, i
     }
 }
 
-// Four waves per SIMD (at most 128 registers) for the small chain widths: the kernel is bound by
-// instruction issue, and a fourth wave per SIMD hides more of each wave's dependency stalls.
-template <int E, bool PAIR, bool ONE>
+// Four waves per SIMD (at most 128 registers) for the small chain widths, which hides more of each
+// wave's dependency stalls.  LDSG: the block first copies W of psi_gs ([N][M] complex64) into LDS
+// after its spin rows, and live proposals read their two rows there.
+template <int E, bool PAIR, bool ONE, bool LDSG>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(E <= 2 ? 4 : 1)))
 void k_batched(BatchedArgs A) {
-    extern __shared__ int8_t s_spins[];           // one 256-byte row per wave
+    extern __shared__ int8_t s_spins[];           // one 256-byte row per wave, then W of psi_gs (LDSG)
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     int8_t* row = s_spins + wv * 256;
     const int N = A.N, M = A.M;
+    float2* s_w = reinterpret_cast<float2*>(s_spins + 256 * (blockDim.x >> 6));
+    if (LDSG) {
+        for (int k = threadIdx.x; k < N * M; k += blockDim.x) s_w[k] = A.gs.W[k];
+        __syncthreads();
+    }
     const long wave_id = (long)blockIdx.x * (blockDim.x >> 6) + wv;
     const unsigned long long t_start = A.clocks ? wall_clock64() : 0ull;
     for (;;) {
@@ -226,7 +273,7 @@ void k_batched(BatchedArgs A) {
         }
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        BatchedChain<E, PAIR> c;
+        BatchedChain<E, PAIR, ONE> c;
         c.sp.load(row, N, lane);
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
@@ -290,7 +337,7 @@ void k_batched(BatchedArgs A) {
         DrawBatch batch;
         int t = 0;
         for (int sw = 0; sw < A.n_burn + A.n_sweeps; ++sw) {
-            for (int p = 0; p < N; ++p, ++t) batched_step<E, PAIR, ONE>(A, g, lane, t, c, Wg, Wtr, loff, trow, batch);
+            for (int p = 0; p < N; ++p, ++t) batched_step<E, PAIR, ONE, LDSG>(A, s_w, g, lane, t, c, Wg, Wtr, loff, trow, batch);
             if (sw >= A.n_burn) measure(A, c, ph, da, beta, lane);
         }
         if (lane == 0) {
@@ -610,6 +657,61 @@ bool batched_lanes_ok(int lanes, int M) {
     return (lanes == 32 && E64 <= 4) || (lanes == 16 && E64 <= 2);
 }
 
+// Blocks of k that one compute unit holds with `lds` bytes of dynamic LDS (0 when the query fails).
+template <typename K>
+static int resident_blocks(K k, int threads, size_t lds) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, threads, lds) != hipSuccess) return 0;
+    return n;
+}
+
+// Whether k_batched<E, PAIR, ONE> keeps its copy of psi_gs's W in LDS: W fits (E <= 4, at most the
+// compute unit's LDS with the spin rows) and the compute unit then holds as many blocks as without it.
+template <int E, bool PAIR, bool ONE>
+static bool lds_rows_for(int N, int M, int waves_per_block) {
+    if constexpr (E > 4) {
+        return false;
+    } else {
+        const size_t lds = 256 * (size_t)waves_per_block, lds_w = lds + (size_t)N * M * sizeof(float2);
+        if (lds_w > (size_t)kMaxBatchedLds) return false;
+        static bool attr = false;   // raise the kernel's dynamic LDS limit once per process
+        if (!attr)
+            attr = hipFuncSetAttribute((const void*)k_batched<E, PAIR, ONE, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMaxBatchedLds) == hipSuccess;
+        if (!attr) return false;
+        const int threads = kWave * waves_per_block;
+        const int with = resident_blocks(k_batched<E, PAIR, ONE, true>, threads, lds_w);
+        return with > 0 && with >= resident_blocks(k_batched<E, PAIR, ONE, false>, threads, lds);
+    }
+}
+
+template <int E, bool PAIR, bool ONE>
+static void launch_one_batched(const BatchedArgs& A, int blocks, int waves_per_block, hipStream_t stream) {
+    const dim3 grid(blocks), block(kWave * waves_per_block);
+    const size_t lds = 256 * (size_t)waves_per_block;
+    if (lds_rows_for<E, PAIR, ONE>(A.N, A.M, waves_per_block))
+        hipLaunchKernelGGL((k_batched<E, PAIR, ONE, true>), grid, block, lds + (size_t)A.N * A.M * sizeof(float2),
+                           stream, A);
+    else
+        hipLaunchKernelGGL((k_batched<E, PAIR, ONE, false>), grid, block, lds, stream, A);
+}
+
+bool batched_lds_rows(int N, int M, int proposal, int waves_per_block) {
+    const int E = (M + kWave - 1) / kWave;
+    const bool pair = proposal == 1, one = N <= kWave;
+    switch (E) {
+#define CRBM_CASE(e)                                                           \
+    case e:                                                                    \
+        if (pair && one) return lds_rows_for<e, true, true>(N, M, waves_per_block);   \
+        if (pair) return lds_rows_for<e, true, false>(N, M, waves_per_block);         \
+        if (one) return lds_rows_for<e, false, true>(N, M, waves_per_block);          \
+        return lds_rows_for<e, false, false>(N, M, waves_per_block);
+        CRBM_CASE(1) CRBM_CASE(2) CRBM_CASE(3) CRBM_CASE(4)
+#undef CRBM_CASE
+        default: return false;
+    }
+}
+
 hipError_t launch_batched(const BatchedArgs& A, int blocks, int waves_per_block, int lanes, double2* mu,
                           hipStream_t stream) {
     if (!batched_lanes_ok(lanes, A.M)) return hipErrorInvalidValue;
@@ -630,14 +732,13 @@ hipError_t launch_batched(const BatchedArgs& A, int blocks, int waves_per_block,
                            (int64_t)A.total, A.n_sweeps, mu);
         return hipGetLastError();
     }
-    const size_t lds = 256 * (size_t)waves_per_block;
     switch (E) {
-#define CRBM_CASE(e)                                                                                   \
-    case e:                                                                                            \
-        if (pair && one) hipLaunchKernelGGL((k_batched<e, true, true>), grid, block, lds, stream, A);  \
-        else if (pair) hipLaunchKernelGGL((k_batched<e, true, false>), grid, block, lds, stream, A);   \
-        else if (one) hipLaunchKernelGGL((k_batched<e, false, true>), grid, block, lds, stream, A);    \
-        else hipLaunchKernelGGL((k_batched<e, false, false>), grid, block, lds, stream, A);            \
+#define CRBM_CASE(e)                                                                              \
+    case e:                                                                                       \
+        if (pair && one) launch_one_batched<e, true, true>(A, blocks, waves_per_block, stream);   \
+        else if (pair) launch_one_batched<e, true, false>(A, blocks, waves_per_block, stream);    \
+        else if (one) launch_one_batched<e, false, true>(A, blocks, waves_per_block, stream);     \
+        else launch_one_batched<e, false, false>(A, blocks, waves_per_block, stream);             \
         break;
         CRBM_CASE(1) CRBM_CASE(2) CRBM_CASE(3) CRBM_CASE(4) CRBM_CASE(5) CRBM_CASE(6) CRBM_CASE(7) CRBM_CASE(8)
 #undef CRBM_CASE

@@ -130,7 +130,10 @@ def test_batched_lanes_per_chain_bit_identical(orc, kind, Lx, Ly, M, proposal):
     """Chains on 64, 32 or 16 lanes (one, two or four chains per wave) and several grid shapes give the
     same moments and the same accept traces bit for bit: every sum runs in one fixed order.  Ragged M
     (units past M in the last slots), N > 64 (sites in a second slot), uneven chain counts, both
-    proposals; 16 lanes only where M <= 128 and 32 where M <= 256, other lane counts are refused."""
+    proposals; 16 lanes only where M <= 128 and 32 where M <= 256, other lane counts are refused.  On
+    64 lanes the rows of psi_gs come from its copy in LDS or from global memory depending on the
+    occupancy at that block size: one wave per block keeps more blocks per compute unit without the
+    copy whenever it is large, eight with it."""
     N = Lx * Ly
     r = np.random.default_rng(31)
     counts = r.integers(1, 13, 37)
@@ -151,6 +154,12 @@ def test_batched_lanes_per_chain_bit_identical(orc, kind, Lx, Ly, M, proposal):
             crbm.batched_moments(plan, gs_d, dev["t"], dev["b"], dev["q"], dev["o"], 1, 3, proposal, 7, mu, trace=tr)
             torch.cuda.synchronize()
             res[(lanes, waves)] = (np_of(mu), np_of(tr))
+    lds = {w: crbm.batched_lds_rows(plan, proposal, w) for w in (1, 8)}
+    print("psi_gs rows from LDS at 1 and 8 waves per block:", lds)
+    if (N, M) in ((64, 128), (66, 70)):
+        assert lds == {1: False, 8: True}   # both paths are compared below
+    if M > 256:
+        assert lds == {1: False, 8: False}  # W is copied only for M <= 256
     ref_mu, ref_tr = res[(64, 1)]
     assert np.all(np.isfinite(ref_mu))
     for key, (m, t) in res.items():
