@@ -118,7 +118,8 @@ struct BatchedChain {
     float Lg[E];            // Re log 2cosh theta_gs
     float2 pti[E], ptj[E];  // rows of t~'s W for the pending update of tht
     float pm;               // -2 s_i of the pending update, 0 when none
-    uint32_t tw;            // accept bits of the current trace word
+    float da2;              // ONE: 2 (a_i - a_j) of psi_gs (2 a_i for a flip) of this lane's draw
+    int acc;                // lane l: accept bit of proposal 64 k + l of the current 64
     double m0, mr, mi;      // sums of |f|^2 and conj(f) beta r
 };
 
@@ -182,31 +183,68 @@ __device__ __forceinline__ void measure(const BatchedArgs& A, BatchedChain<E, PA
     c.mi += fx * br.y - fy * br.x;
 }
 
-// Proposal t of chain g.  Rows of psi_gs are read only for live moves, from LDS (s_w) when LDSG.
+// Trace words of the `count` proposals t0 .. t0 + count - 1 (t0 a multiple of 64) from their accept
+// bits, one per lane.
+template <int E, bool PAIR, bool ONE>
+__device__ __forceinline__ void flush_accepts(BatchedChain<E, PAIR, ONE>& c, uint32_t* trow, int t0, int count,
+                                              int lane) {
+    if (trow) {
+        const uint64_t bits = __ballot(c.acc != 0);
+        if (lane == 0) {
+            trow[t0 >> 5] = (uint32_t)bits;
+            if (count > 32) trow[(t0 >> 5) + 1] = (uint32_t)(bits >> 32);
+        }
+    }
+    c.acc = 0;
+}
+
+// Proposal t of chain g.  Rows of psi_gs are read only for live moves; with LDSG from LDS (s_w: rows
+// of E 64 columns that hold zeros past M).  Every 64th proposal draws the next 64 (one per lane), with
+// ONE also each draw's change of Re(a . s) up to the sign of s_i, and writes the accept bits of the
+// previous 64 to the trace.
 template <int E, bool PAIR, bool ONE, bool LDSG>
 __device__ __forceinline__ void batched_step(const BatchedArgs& A, const float2* s_w, uint64_t g, int lane, int t,
                                              BatchedChain<E, PAIR, ONE>& c, const MatRows& Wg, const MatRows& Wt,
                                              const unsigned (&loff)[E], uint32_t* trow, DrawBatch& batch) {
     const int N = A.N, M = A.M;
-    Proposal cur = next_proposal(batch, A.seed, (uint32_t)g, 0ull, t, lane, N);
+    const int l = t & 63;
+    if (l == 0) {
+        if (t > 0) flush_accepts(c, trow, t - 64, 64, lane);
+        batch = draw_batch(A.seed, (uint32_t)g, (uint64_t)t, lane, N);
+        if (ONE) {
+            // Re a of psi_gs at this lane's sites i, j (site k sits in lane k): the move changes
+            // Re(a . s) by -2 s_i (a_i - a_j), or by -2 s_i a_i for a flip
+            const float ai = __int_as_float(__builtin_amdgcn_ds_bpermute(batch.i << 2, __float_as_int(c.ag[0])));
+            const float aj = __int_as_float(__builtin_amdgcn_ds_bpermute(batch.j << 2, __float_as_int(c.ag[0])));
+            c.da2 = PAIR ? 2.f * (ai - aj) : 2.f * ai;
+        }
+    }
+    Proposal cur = proposal_at(batch, l);
     const int si = c.sp.get(cur.i), sj = c.sp.get(cur.j);
     if (!(PAIR && si == sj)) {
         float2 wi[E], wj[E], tn[E];
         float Ln[E];
-        cur.ai = site_value<ONE>(c.ag, cur.i);
-        cur.aj = PAIR ? site_value<ONE>(c.ag, cur.j) : 0.f;
+        float dl;
         if (LDSG) {
-            const int oi = cur.i * M, oj = cur.j * M;
+            constexpr int Mp = E * kWave;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const int col = (int)(loff[e] / sizeof(float2));
-                wi[e] = s_w[oi + col];
-                if (PAIR) wj[e] = s_w[oj + col];
+                wi[e] = s_w[cur.i * Mp + e * kWave + lane];
+                if (PAIR) wj[e] = s_w[cur.j * Mp + e * kWave + lane];
             }
         } else {
             mat_fetch<E, PAIR>(Wg, loff, cur.i, cur.j, wi, wj);
         }
-        const float dl = proposal_dlog<E, PAIR>(cur, si, wi, wj, c.thg, c.Lg, tn, Ln, lane, M);
+        if (ONE) {
+            // -2 s_i (a_i - a_j) = -s_i da2 exactly, as proposal_dlog forms it
+            const float d2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c.da2), l));
+            const float da = si > 0 ? -d2 : d2;
+            dl = units_dlog<E, PAIR, !LDSG>(si, wi, wj, c.thg, c.Lg, tn, Ln, lane, M) + da;
+        } else {
+            cur.ai = site_value<ONE>(c.ag, cur.i);
+            cur.aj = PAIR ? site_value<ONE>(c.ag, cur.j) : 0.f;
+            dl = proposal_dlog<E, PAIR>(cur, si, wi, wj, c.thg, c.Lg, tn, Ln, lane, M);
+        }
         if (cur.u < __expf(2.f * dl)) {
 #pragma unroll
             for (int e = 0; e < E; ++e) { c.thg[e] = tn[e]; c.Lg[e] = Ln[e]; }
@@ -215,18 +253,13 @@ __device__ __forceinline__ void batched_step(const BatchedArgs& A, const float2*
             c.pm = -2.f * (float)si;
             c.sp.flip(cur.i, lane);
             if (PAIR) c.sp.flip(cur.j, lane);
-            if (trow) c.tw |= 1u << (t & 31);
+            if (trow) c.acc = lane == l ? 1 : c.acc;
         }
     }
-    if (trow && ((t & 31) == 31)) {
-        if (lane == 0) trow[t >> 5] = c.tw;
-        c.tw = 0;
-    }
 }
-
 // Four waves per SIMD (at most 128 registers) for the small chain widths, which hides more of each
-// wave's dependency stalls.  LDSG: the block first copies W of psi_gs ([N][M] complex64) into LDS
-// after its spin rows, and live proposals read their two rows there.
+// wave's dependency stalls.  LDSG: the block first copies W of psi_gs ([N][M] complex64, rows padded
+// with zeros to E 64 columns) into LDS after its spin rows, and live proposals read their rows there.
 template <int E, bool PAIR, bool ONE, bool LDSG>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(E <= 2 ? 4 : 1)))
 void k_batched(BatchedArgs A) {
@@ -237,7 +270,11 @@ void k_batched(BatchedArgs A) {
     const int N = A.N, M = A.M;
     float2* s_w = reinterpret_cast<float2*>(s_spins + 256 * (blockDim.x >> 6));
     if (LDSG) {
-        for (int k = threadIdx.x; k < N * M; k += blockDim.x) s_w[k] = A.gs.W[k];
+        constexpr int Mp = E * kWave;   // rows padded to the lanes' units, zeros past M
+        for (int k = threadIdx.x; k < N * Mp; k += blockDim.x) {
+            const int i = k / Mp, col = k % Mp;
+            s_w[k] = col < M ? A.gs.W[(long)i * M + col] : make_float2(0.f, 0.f);
+        }
         __syncthreads();
     }
     const long wave_id = (long)blockIdx.x * (blockDim.x >> 6) + wv;
@@ -326,7 +363,8 @@ void k_batched(BatchedArgs A) {
         }
         const double2 beta = A.betas[inst];
         c.pm = 0.f;
-        c.tw = 0;
+        c.da2 = 0.f;
+        c.acc = 0;
         c.m0 = c.mr = c.mi = 0.0;
         uint32_t* trow = A.trace ? A.trace + (long)g * A.trace_words : nullptr;
         const int total = (A.n_burn + A.n_sweeps) * N;   // the plan checks that it fits
@@ -340,10 +378,10 @@ void k_batched(BatchedArgs A) {
             for (int p = 0; p < N; ++p, ++t) batched_step<E, PAIR, ONE, LDSG>(A, s_w, g, lane, t, c, Wg, Wtr, loff, trow, batch);
             if (sw >= A.n_burn) measure(A, c, ph, da, beta, lane);
         }
+        if (total > 0) flush_accepts(c, trow, (total - 1) & ~63, total - ((total - 1) & ~63), lane);
         if (lane == 0) {
             A.partial[2 * g] = make_double2(c.m0, 0.0);
             A.partial[2 * g + 1] = make_double2(c.mr, c.mi);
-            if (trow && (total & 31) != 0) trow[total >> 5] = c.tw;
         }
     }
     // profiling: when this wave started and when it found no chain left (the tail of the launch)
@@ -665,14 +703,14 @@ static int resident_blocks(K k, int threads, size_t lds) {
     return n;
 }
 
-// Whether k_batched<E, PAIR, ONE> keeps its copy of psi_gs's W in LDS: W fits (E <= 4, at most the
-// compute unit's LDS with the spin rows) and the compute unit then holds as many blocks as without it.
+// Whether k_batched<E, PAIR, ONE> keeps its copy of psi_gs's W in LDS: W fits (E <= 4, N E 64
+// complex64 with the spin rows at most the compute unit's LDS) and the compute unit then holds as many blocks as without it.
 template <int E, bool PAIR, bool ONE>
 static bool lds_rows_for(int N, int M, int waves_per_block) {
     if constexpr (E > 4) {
         return false;
     } else {
-        const size_t lds = 256 * (size_t)waves_per_block, lds_w = lds + (size_t)N * M * sizeof(float2);
+        const size_t lds = 256 * (size_t)waves_per_block, lds_w = lds + (size_t)N * E * kWave * sizeof(float2);
         if (lds_w > (size_t)kMaxBatchedLds) return false;
         static bool attr = false;   // raise the kernel's dynamic LDS limit once per process
         if (!attr)
@@ -690,8 +728,8 @@ static void launch_one_batched(const BatchedArgs& A, int blocks, int waves_per_b
     const dim3 grid(blocks), block(kWave * waves_per_block);
     const size_t lds = 256 * (size_t)waves_per_block;
     if (lds_rows_for<E, PAIR, ONE>(A.N, A.M, waves_per_block))
-        hipLaunchKernelGGL((k_batched<E, PAIR, ONE, true>), grid, block, lds + (size_t)A.N * A.M * sizeof(float2),
-                           stream, A);
+        hipLaunchKernelGGL((k_batched<E, PAIR, ONE, true>), grid, block,
+                           lds + (size_t)A.N * E * kWave * sizeof(float2), stream, A);
     else
         hipLaunchKernelGGL((k_batched<E, PAIR, ONE, false>), grid, block, lds, stream, A);
 }

@@ -93,33 +93,44 @@ __device__ __forceinline__ void fetch_rows(const RbmView& psi, int M, Proposal& 
 }
 
 // change of theta_k per unit of -2 s_i: W_ik (flip) or W_ik - W_jk (exchange); zero past M.
-// E = ceil(M / 64), so only the last group can hold lanes past M.
-template <int E, bool PAIR>
+// E = ceil(M / 64), so only the last group can hold lanes past M.  MASK = false for rows that hold
+// zeros past M themselves.
+template <int E, bool PAIR, bool MASK = true>
 __device__ __forceinline__ float2 row_delta(const float2 (&wi)[E], const float2 (&wj)[E], int e, int lane, int M) {
     float2 d = PAIR ? csub(wi[e], wj[e]) : wi[e];
-    if (e == E - 1 && e * kWave + lane >= M) d = make_float2(0.f, 0.f);
+    if (MASK && e == E - 1 && e * kWave + lane >= M) d = make_float2(0.f, 0.f);
     return d;
 }
 
-// theta' = theta - 2 s_i d and the change of Re log psi (returned wave-uniform).  Lanes past M
+// theta' = theta - 2 s_i d and the wave total of the change of Re log 2cosh theta.  Lanes past M
 // hold theta = 0 and L = Re log 2cosh(0) from the same function, so they add exactly zero.
+template <int E, bool PAIR, bool MASK = true>
+__device__ __forceinline__ float units_dlog(int si, const float2 (&wi)[E], const float2 (&wj)[E],
+                                            const float2 (&th)[E], const float (&L)[E], float2 (&tn)[E],
+                                            float (&Ln)[E], int lane, int M) {
+    const float m2si = -2.f * (float)si;
+    float dsum = 0.f;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const float2 d = row_delta<E, PAIR, MASK>(wi, wj, e, lane, M);
+        tn[e].x = fmaf(m2si, d.x, th[e].x);
+        tn[e].y = fmaf(m2si, d.y, th[e].y);
+        Ln[e] = re_log2cosh_fast(tn[e]);
+        const float x = Ln[e] - L[e];
+        dsum = e == 0 ? x : dsum + x;   // 0 + x would only change the sign of a zero
+    }
+    return wave_total(dsum);
+}
+
+// ... plus the change of Re(a . s): the change of Re log psi of the move (wave-uniform)
 template <int E, bool PAIR>
 __device__ __forceinline__ float proposal_dlog(const Proposal& q, int si, const float2 (&wi)[E],
                                                const float2 (&wj)[E], const float2 (&th)[E], const float (&L)[E],
                                                float2 (&tn)[E], float (&Ln)[E], int lane, int M) {
     const float m2si = -2.f * (float)si;
-    float dsum = 0.f;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const float2 d = row_delta<E, PAIR>(wi, wj, e, lane, M);
-        tn[e].x = fmaf(m2si, d.x, th[e].x);
-        tn[e].y = fmaf(m2si, d.y, th[e].y);
-        Ln[e] = re_log2cosh_fast(tn[e]);
-        dsum += Ln[e] - L[e];
-    }
     float da = m2si * q.ai;
     if (PAIR) da -= m2si * q.aj;
-    return wave_total(dsum) + uniform(da);
+    return units_dlog<E, PAIR>(si, wi, wj, th, L, tn, Ln, lane, M) + uniform(da);
 }
 
 }  // namespace crbm
