@@ -250,7 +250,9 @@ __device__ __forceinline__ double2 wave_sum(double2 v) { return make_double2(wav
 // Sum over the wave, returned to every lane as a wave-uniform value.  DPP only (no
 // LDS round trips): a butterfly over the 16 lanes of each row (quad swaps, then
 // the half-row and row mirrors leave the row total in every lane of the row),
-// then row broadcasts gather the four row totals into lane 63.  All 64 lanes
+// then row broadcasts gather the four row totals into lane 63: (R3 + R2) +
+// (R1 + R0).  The broadcasts write every row (rows 0 and 2 end with partial sums
+// that lane 63 never reads), so each step is a single DPP add.  All 64 lanes
 // must be active.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ float dpp_move(float x) {
@@ -261,8 +263,8 @@ __device__ __forceinline__ float wave_total(float v) {
     v += dpp_move<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
     v += dpp_move<0x141, 0xF>(v);  // row_half_mirror
     v += dpp_move<0x140, 0xF>(v);  // row_mirror
-    v += dpp_move<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
-    v += dpp_move<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+    v += dpp_move<0x142, 0xF>(v);  // row_bcast:15: row 3 = R3 + R2, row 1 = R1 + R0
+    v += dpp_move<0x143, 0xF>(v);  // row_bcast:31: row 3 += row 1
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
