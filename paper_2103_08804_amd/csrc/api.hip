@@ -28,7 +28,7 @@ hipError_t launch_moment_accum(const double2* f, const double2* B, int b_is_f, c
 hipError_t launch_moment_final(const double2* partial, int n_blocks, int total, double2* mu, hipStream_t stream);
 size_t sbuild_pack_bytes(int N, int M, long max_samples);
 std::vector<int2> sbuild_order(int N, int M, int n_xcd, int g);
-std::vector<int2> sbuild_order_thin(int N, int M);
+std::vector<int2> sbuild_order_ragged(int N, int M);
 hipError_t launch_basis_pack(long n, const double2* B, const float2* loc, int mul, float2* Bcol, float2* HBcol,
                              hipStream_t stream);
 long gram_partial_len(int K);
@@ -349,12 +349,12 @@ int crbm_plan_create_ex(crbm_plan* out, const crbm_lattice* lat, int n_hidden, l
         rc = rc ? rc : p->alloc(&d_order, order.size());
         p->w.sb_order = d_order;
         p->w.sb_order_len = (long)order.size();
-        thin = sbuild_order_thin((int)N, (int)M);
+        thin = sbuild_order_ragged((int)N, (int)M);
         if (!thin.empty()) {
             int2* d_thin = nullptr;
             rc = rc ? rc : p->alloc(&d_thin, thin.size());
-            p->w.sb_order_thin = d_thin;
-            p->w.sb_order_thin_len = (long)thin.size();
+            p->w.sb_order_rag = d_thin;
+            p->w.sb_order_rag_len = (long)thin.size();
         }
         // buffer of a contraction split over samples when the tile pairs alone cannot fill the device
         const long slice = P * P * (long)sizeof(float2);
@@ -399,8 +399,8 @@ int crbm_plan_create_ex(crbm_plan* out, const crbm_lattice* lat, int n_hidden, l
     if (e == hipSuccess && !order.empty())
         e = hipMemcpy(const_cast<int2*>(p->w.sb_order), order.data(), order.size() * sizeof(int2),
                       hipMemcpyHostToDevice);
-    if (e == hipSuccess && !thin.empty() && p->w.sb_order_thin)
-        e = hipMemcpy(const_cast<int2*>(p->w.sb_order_thin), thin.data(), thin.size() * sizeof(int2),
+    if (e == hipSuccess && !thin.empty() && p->w.sb_order_rag)
+        e = hipMemcpy(const_cast<int2*>(p->w.sb_order_rag), thin.data(), thin.size() * sizeof(int2),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) { delete p; return hip_fail(e, "plan initialisation"); }
     *out = p;
@@ -1247,7 +1247,7 @@ int crbm_sbuild_autotune(crbm_plan p, const int8_t* samples, const void* tanh_th
         if (r == hipSuccess)
             r = launch_sbuild_mfma((int)p->N, (int)p->M, p->P, samples, static_cast<const float2*>(tanh_theta), n,
                                    p->w.Om, p->w.Om, p->w.S, CRBM_PREC_BF16, tiles[ti], p->w.pack, p->w.pack_bytes,
-                                   p->w.sb_order, p->w.sb_order_len, p->w.sb_order_thin, p->w.sb_order_thin_len,
+                                   p->w.sb_order, p->w.sb_order_len, p->w.sb_order_rag, p->w.sb_order_rag_len,
                                    p->w.spart, nsplit, p->w.bx, p->w.bx_part, &off, stream);
         if (r == hipSuccess) r = hipEventRecord(e1, stream);
         if (r == hipSuccess) r = hipEventSynchronize(e1);

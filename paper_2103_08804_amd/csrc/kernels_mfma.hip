@@ -21,7 +21,8 @@
 // Main kernel (W and b rows).  A row tile is 8 extended sites x 16 hidden
 // units = 128 rows, made of four 32-row matrix-core fragments of 2 sites x 16
 // hidden units each; N + 1 sites and M hidden units are padded only to
-// multiples of 8 and 16.  A workgroup streams, per sample, the T' values of
+// multiples of 8 and 16, and the fragments of the last site block that hold
+// no real site are skipped (ragged pairs).  A workgroup streams, per sample, the T' values of
 // 16 + 16 hidden units and the sign masks of 8 + 8 sites and synthesises the
 // 128 + 128 operand rows by XOR-ing the sign bit into the floating-point T'
 // (sigma = +-1 is exact in any format).  Each workgroup (4 waves) owns a
@@ -46,6 +47,7 @@
 // order (deterministic, in double) before the same epilogue arithmetic.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "../../include/chebrbm.h"
@@ -238,7 +240,7 @@ struct Stager {
 // ------------------------------------------------------------------ main kernel: W/b tile pairs
 // Split mode (nsplit > 1): workgroup x handles tile pair x % n_order over the K tiles of split
 // x / n_order and writes the raw sums into S + split * P * P (no scaling, no means).
-template <bool BF16, int KTB, bool THIN>
+template <bool BF16, int KTB, int RF>
 __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* __restrict__ order, long n_order,
                                                         long ns_pad, int nsplit,
                                                         const typename Pol<BF16>::E* __restrict__ Tr,
@@ -255,14 +257,14 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
     __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
     using St = Stager<ROWS, KT, E>;
 
-    // tile pair (u, u'), u <= u', from the dispatch-order table (entries < 0 are padding).  THIN: the pair
-    // (h, u') of the b rows of hidden block h (the last site block, whose only real site is N: one
-    // 32-row fragment, sites N and N + 1) against tile u'; every wave takes that fragment against one
-    // fragment of u'.  Otherwise each wave takes 2 x 2 fragments of the two 128-row tiles.
+    // tile pair (u, u'), u <= u', from the dispatch-order table (entries < 0 are padding).  RF > 0, a
+    // ragged pair (h, u'): the tile of hidden block h in the last site block, of whose four 2-site
+    // fragments only the first RF hold real sites, against tile u'; every wave takes those RF
+    // fragments against one fragment of u'.  RF = 0: each wave takes 2 x 2 fragments of two full tiles.
     const int split = (int)(blockIdx.x / n_order);
     const int2 pr = order[blockIdx.x % n_order];
     if (pr.x < 0) return;
-    const int u = THIN ? (gm.nSB - 1) * gm.nHB + pr.x : pr.x, up = pr.y;
+    const int u = RF ? (gm.nSB - 1) * gm.nHB + pr.x : pr.x, up = pr.y;
     const int sbA = u / gm.nHB, hbA = u % gm.nHB;
     const int sbB = up / gm.nHB, hbB = up % gm.nHB;
     const int N = gm.N, M = gm.M;
@@ -270,9 +272,9 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wi = wave >> 1, wj = wave & 1;
-    constexpr int AF = THIN ? 1 : 2, BF = THIN ? 1 : 2;     // fragments per wave
-    auto fragA = [&](int a) { return THIN ? 0 : 2 * wi + a; };
-    auto fragB = [&](int b) { return THIN ? wave : 2 * wj + b; };
+    constexpr int AF = RF ? RF : 2, BF = RF ? 1 : 2;     // fragments per wave
+    auto fragA = [&](int a) { return RF ? a : 2 * wi + a; };
+    auto fragB = [&](int b) { return RF ? wave : 2 * wj + b; };
 
     floatx16 acc_re[AF][BF], acc_im[AF][BF];
 #pragma unroll
@@ -743,21 +745,26 @@ __global__ __launch_bounds__(256) void k_sbuild_reduce(Centre cen, int nsplit, c
     S[e] = make_float2((float)d.x, k == kp ? 0.f : (float)d.y);
 }
 
-// The b rows go to thin pairs when the last site block holds site N alone (N a multiple of 8): its
-// tiles would be 7/8 padding.
-bool sbuild_thin(int N) { return N % MK_TS == 0; }
+// Live 2-site fragments of the last site block when it holds fewer than seven of the N + 1 extended
+// sites (then its tiles go to ragged pairs, which skip the empty fragments), else 0.  For N a multiple
+// of 8 the block holds site N alone (one fragment, the b rows); for 10 x 10 it holds sites 96 .. 100.
+int sbuild_ragged_frags(int N) {
+    const int r = N + 1 - MK_TS * ((N + 1 + MK_TS - 1) / MK_TS - 1);   // real sites of the last block
+    const int f = (r + 1) / 2;
+    return f < MK_TS / 2 ? f : 0;
+}
 
 // Number of sample splits for a contraction of n samples when the tile pairs alone cannot fill the
 // device: the split count s (at most max_splits, which the plan's slice buffer holds, and at least 4
 // K tiles per split) that minimises the modelled time of the launches, sum over launches of
-// ceil(pairs s / resident workgroups) / s (rounds per unit of one pair's full-sample work; a thin pair
-// counts a quarter), so that the last round of each launch is not left nearly empty.
+// ceil(pairs s / resident workgroups) / s (rounds per unit of one pair's full-sample work; a ragged pair
+// of f live fragments counts f / 4), so that the last round of each launch is not left nearly empty.
 int sbuild_splits(int N, int M, long n, int n_cu, int max_splits) {
     const SbGeom gm = sb_geom(N, M);
-    const bool thin = sbuild_thin(N);
-    const long nt = (long)(thin ? gm.nSB - 1 : gm.nSB) * gm.nHB;
+    const int rf = sbuild_ragged_frags(N);
+    const long nt = (long)(rf ? gm.nSB - 1 : gm.nSB) * gm.nHB;
     const long n_main = nt * (nt + 1) / 2;
-    const long n_thin = thin ? (long)gm.nHB * nt + (long)gm.nHB * (gm.nHB + 1) / 2 : 0;
+    const long n_rag = rf ? (long)gm.nHB * nt + (long)gm.nHB * (gm.nHB + 1) / 2 : 0;
     const long n_kt = ((n + MK_KT - 1) / MK_KT * MK_KT) / 64;    // the finest K tile of any variant is 64
     long smax = max_splits < n_kt / 4 ? max_splits : n_kt / 4;
     if (smax < 1) smax = 1;
@@ -766,7 +773,7 @@ int sbuild_splits(int N, int M, long n, int n_cu, int max_splits) {
     long bs = 1;
     for (long sp = 1; sp <= smax; ++sp) {
         const double t = (double)((n_main * sp + slots - 1) / slots) / (double)sp +
-                         0.25 * (double)((n_thin * sp + slots - 1) / slots) / (double)sp;
+                         0.25 * rf * (double)((n_rag * sp + slots - 1) / slots) / (double)sp;
         if (t < best * (1.0 - 1e-9)) { best = t; bs = sp; }
     }
     return (int)bs;
@@ -777,8 +784,8 @@ int sbuild_splits(int N, int M, long n, int n_cu, int max_splits) {
 // (T' rounded as packed, plus c); bx: N x P side buffer; bx_part: nsplit of them when nsplit > 1.
 hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n,
                               const double2* shift, const double2* Om, float2* S, int prec, int kt_bf16, void* pack,
-                              size_t pack_bytes, const int2* order, long n_order, const int2* order_thin,
-                              long n_thin, float2* split_buf, int nsplit, float2* bx, float2* bx_part, Profiler* prof,
+                              size_t pack_bytes, const int2* order, long n_order, const int2* order_rag,
+                              long n_rag, float2* split_buf, int nsplit, float2* bx, float2* bx_part, Profiler* prof,
                               hipStream_t stream) {
     const SbGeom gm = sb_geom(N, M);
     if (nsplit > 1 && (!split_buf || !bx_part)) return hipErrorInvalidValue;
@@ -825,22 +832,29 @@ hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const flo
         prof->begin(PROF_SBUILD, stream);
         float2* out = nsplit > 1 ? split_buf : S;
         const dim3 grid((unsigned)(n_order * nsplit));
-        if (B16 && kt_bf16 == 64)
-            hipLaunchKernelGGL((k_sbuild_mfma<B16, 64, false>), grid, dim3(256), 0, stream, gm, order, n_order, ns_pad,
-                               nsplit, Tr, Ti, Sm, cen, out);
-        else
-            hipLaunchKernelGGL((k_sbuild_mfma<B16, 128, false>), grid, dim3(256), 0, stream, gm, order, n_order,
-                               ns_pad, nsplit, Tr, Ti, Sm, cen, out);
-        if (n_thin > 0) {
-            const dim3 gth((unsigned)(n_thin * nsplit));
+        // the FP32 variant has one K tile (64) whatever kt_bf16 says
+        auto launch = [&](auto rf_tag, const int2* ord, long n_ord) {
+            constexpr int R = decltype(rf_tag)::value;
+            const dim3 g((unsigned)(n_ord * nsplit));
             if (B16 && kt_bf16 == 64)
-                hipLaunchKernelGGL((k_sbuild_mfma<B16, 64, true>), gth, dim3(256), 0, stream, gm, order_thin, n_thin,
-                                   ns_pad, nsplit, Tr, Ti, Sm, cen, out);
+                hipLaunchKernelGGL((k_sbuild_mfma<B16, 64, R>), g, dim3(256), 0, stream, gm, ord, n_ord, ns_pad,
+                                   nsplit, Tr, Ti, Sm, cen, out);
             else
-                hipLaunchKernelGGL((k_sbuild_mfma<B16, 128, true>), gth, dim3(256), 0, stream, gm, order_thin, n_thin,
-                                   ns_pad, nsplit, Tr, Ti, Sm, cen, out);
-        }
+                hipLaunchKernelGGL((k_sbuild_mfma<B16, 128, R>), g, dim3(256), 0, stream, gm, ord, n_ord, ns_pad,
+                                   nsplit, Tr, Ti, Sm, cen, out);
+        };
+        launch(std::integral_constant<int, 0>{}, order, n_order);
         prof->end(stream);
+        if (n_rag > 0) {
+            prof->begin(PROF_SRAGGED, stream);
+            switch (sbuild_ragged_frags(N)) {
+                case 1: launch(std::integral_constant<int, 1>{}, order_rag, n_rag); break;
+                case 2: launch(std::integral_constant<int, 2>{}, order_rag, n_rag); break;
+                case 3: launch(std::integral_constant<int, 3>{}, order_rag, n_rag); break;
+                default: break;
+            }
+            prof->end(stream);
+        }
         prof->begin(PROF_SBORDER, stream);
         if (nsplit > 1)
             hipLaunchKernelGGL(k_sbuild_reduce, dim3((unsigned)((P * P + 255) / 256)), dim3(256), 0, stream, cen,
@@ -859,8 +873,8 @@ hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const flo
 // then share few operand slabs, which stay in that XCD's L2.  Padding entries are (-1, -1).
 std::vector<int2> sbuild_order(int N, int M, int n_xcd, int g) {
     const SbGeom gm = sb_geom(N, M);
-    // with thin pairs the main kernel takes the tiles of the sites [0, N) only
-    const int nt = (sbuild_thin(N) ? gm.nSB - 1 : gm.nSB) * gm.nHB;
+    // with ragged pairs the main kernel takes the tiles of the full site blocks only
+    const int nt = (sbuild_ragged_frags(N) ? gm.nSB - 1 : gm.nSB) * gm.nHB;
     const int ns = (nt + g - 1) / g;
     std::vector<std::vector<int2>> per(n_xcd);
     int st = 0;
@@ -881,11 +895,12 @@ std::vector<int2> sbuild_order(int N, int M, int n_xcd, int g) {
     return out;
 }
 
-// Thin pairs (h, u'): the b rows of hidden block h against every tile u' of the sites [0, N), and
-// against the b tiles of hidden blocks h' >= h; the pairs that share a B tile sit next to each other.
-std::vector<int2> sbuild_order_thin(int N, int M) {
+// Ragged pairs (h, u'): the last site block's tile of hidden block h against every tile u' of the full
+// site blocks, and against the last block's tiles of hidden blocks h' >= h; the pairs that share a B
+// tile sit next to each other.
+std::vector<int2> sbuild_order_ragged(int N, int M) {
     std::vector<int2> out;
-    if (!sbuild_thin(N)) return out;
+    if (!sbuild_ragged_frags(N)) return out;
     const SbGeom gm = sb_geom(N, M);
     const int nt_main = (gm.nSB - 1) * gm.nHB;
     for (int up = 0; up < nt_main; ++up)
