@@ -417,10 +417,13 @@ def test_fidelity_grad(orc):
 # ------------------------------------------------------------------ matrix-core S contraction
 @pytest.mark.parametrize("kind,Lx,Ly,M,n,bias", [(0, 10, 1, 10, 1000, 0.0), (1, 4, 4, 40, 777, 0.0),
                                                   (0, 40, 1, 80, 130, 0.0), (0, 7, 1, 3, 200, 0.0),
+                                                  (0, 12, 1, 24, 600, 0.0),
                                                   (1, 4, 4, 40, 777, 1.5), (0, 10, 1, 10, 1000, 3.0)])
 def test_dense_s_matrix_cores(orc, kind, Lx, Ly, M, n, bias):
     """S from the FP32 and BF16 matrix-core contractions (uniform weights) against the oracle's S, with
-    every entry bounded relative to the centred diagonal: |dS_kk'| <= tol sqrt(S_kk S_k'k').  The bias
+    the last site block of the N + 1 extended sites full (N = 7) or ragged with 1 (N = 16, 40), 2
+    (N = 10) or 3 (N = 12) live 2-site fragments; every entry is bounded relative to the centred
+    diagonal: |dS_kk'| <= tol sqrt(S_kk S_k'k').  The bias
     added to Re b puts |<tanh theta>| at about 5 (bias 1.5) and 200 (bias 3) times the spread of tanh
     theta, where sums of raw products less the product of the means would lose those digits.
     FP32 operands: tol 1e-5.  BF16 operands (8-bit significands, each of the two shifted operands
