@@ -30,6 +30,7 @@ namespace crbm {
 
 // LDS of one compute unit (gfx950), the most one block of k_batched may ask for
 constexpr int kMaxBatchedLds = 160 * 1024;
+constexpr int kMaxDevices = 64;
 
 __global__ void k_batched_reset(unsigned long long* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0ull;
@@ -712,11 +713,15 @@ static bool lds_rows_for(int N, int M, int waves_per_block) {
     } else {
         const size_t lds = 256 * (size_t)waves_per_block, lds_w = lds + (size_t)N * E * kWave * sizeof(float2);
         if (lds_w > (size_t)kMaxBatchedLds) return false;
-        static bool attr = false;   // raise the kernel's dynamic LDS limit once per process
-        if (!attr)
-            attr = hipFuncSetAttribute((const void*)k_batched<E, PAIR, ONE, true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMaxBatchedLds) == hipSuccess;
-        if (!attr) return false;
+        // raise the kernel's dynamic LDS limit once per device (the first call on each)
+        static signed char attr[kMaxDevices] = {};
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return false;
+        if (attr[dev] == 0)
+            attr[dev] = hipFuncSetAttribute((const void*)k_batched<E, PAIR, ONE, true>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxBatchedLds) == hipSuccess
+                            ? 1 : -1;
+        if (attr[dev] < 0) return false;
         const int threads = kWave * waves_per_block;
         const int with = resident_blocks(k_batched<E, PAIR, ONE, true>, threads, lds_w);
         return with > 0 && with >= resident_blocks(k_batched<E, PAIR, ONE, false>, threads, lds);
