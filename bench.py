@@ -293,6 +293,8 @@ def main():
         "roofline": roof,
         "sampler_roofline": sampler,
     }
+    if solver == crbm.CG_DENSE:
+        line["cg_launch_overhead"] = cg_overhead(crbm, plan, fit, flat, T, R, wl, args, s_prec=prec)
     if not args.no_fp32_compare and solver == crbm.CG_DENSE and prec == crbm.BF16:
         line["matfree_compare"] = matfree_compare(crbm, plan, fit, flat, T, R, wl, args, ms_per_step, prof)
         line["fp32_compare"] = fp32_compare(crbm, plan, fit, step, flat, T, R, wl, args, ms_per_step, stats)
@@ -720,6 +722,34 @@ def bench_grad16(crbm, args):
                                  "samples": C, "burn_in_sweeps": 64},
                       "samples_per_s": C / el, "phases": phases, "roofline": roof, "ot_roofline": roof_ot}))
     plan.close()
+
+
+def cg_overhead(crbm, plan, fit, flat, T, R, wl, args, s_prec):
+    """What the iterations enqueued past convergence cost: the dense SR step of the last timed step's
+    inputs, from the same state, with the configured iteration cap and with the cap set to the
+    iterations it needed (both converge identically); the difference of the two 'cg' phases."""
+    stats = torch.zeros(8, dtype=torch.float64, device="cuda")
+    out = {}
+    its = None
+    for cap in (args.cg_maxit, None):
+        f = crbm.RBM(fit.a.clone(), fit.b.clone(), fit.W.clone())
+        torch.cuda.synchronize()
+        plan.profile(True)
+        crbm.sr_step(plan, f, flat, T, R, 0.1, wl.diag_shift, crbm.CG_DENSE, s_prec, 1e-6,
+                     args.cg_maxit if cap else max(1, int(its)), stats)
+        torch.cuda.synchronize()
+        c, t = plan.profile_read()["cg"]
+        plan.profile(False)
+        if cap:
+            its = float(stats[5].item())
+            out["cg_ms"] = t / c
+        else:
+            out["cg_ms_cap_at_iterations"] = t / c
+    out.update({"iterations": its, "cap": args.cg_maxit, "early_exit_launches": 5 * (args.cg_maxit - int(its)),
+                "overhead_ms": out["cg_ms"] - out["cg_ms_cap_at_iterations"],
+                "note": ("every iteration up to the cap is enqueued (5 launches) so that the host never waits on "
+                         "a device flag; the ones after convergence return at once")})
+    return out
 
 
 def fp32_compare(crbm, plan, fit, step, flat, T, R, wl, args, ms_per_step, stats):
