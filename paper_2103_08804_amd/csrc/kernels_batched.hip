@@ -705,7 +705,8 @@ static int resident_blocks(K k, int threads, size_t lds) {
 }
 
 // Whether k_batched<E, PAIR, ONE> keeps its copy of psi_gs's W in LDS: W fits (E <= 4, N E 64
-// complex64 with the spin rows at most the compute unit's LDS) and the compute unit then holds as many blocks as without it.
+// complex64 with the spin rows at most the compute unit's LDS) and the compute unit then holds as
+// many blocks as without it.
 template <int E, bool PAIR, bool ONE>
 static bool lds_rows_for(int N, int M, int waves_per_block) {
     if constexpr (E > 4) {
