@@ -22,9 +22,9 @@
 // units = 128 rows, made of four 32-row matrix-core fragments of 2 sites x 16
 // hidden units each; N + 1 sites and M hidden units are padded only to
 // multiples of 8 and 16, and the fragments of the last site block that hold
-// no real site are skipped (ragged pairs).  A workgroup streams, per sample, the T' values of
-// 16 + 16 hidden units and the sign masks of 8 + 8 sites and synthesises the
-// 128 + 128 operand rows by XOR-ing the sign bit into the floating-point T'
+// no real site are skipped (ragged pairs).  A workgroup streams, per sample,
+// the T' values of 16 + 16 hidden units and the sign masks of 8 + 8 sites and
+// synthesises the 128 + 128 operand rows by XOR-ing the sign bit into the floating-point T'
 // (sigma = +-1 is exact in any format).  Each workgroup (4 waves) owns a
 // 128 x 128 complex tile pair (u <= u') and accumulates, per wave, a 64 x 64
 // complex block as 4 real products (RR + II -> Re, RI - IR -> Im) in FP32 with
