@@ -350,7 +350,9 @@ def test_fullsize_batched_instances(orc):
     tp, bd = torch.from_numpy(tv).cuda(), torch.from_numpy(betas).cuda()
     qd, od = torch.from_numpy(np.ascontiguousarray(qs)).cuda(), torch.from_numpy(offsets).cuda()
     n_burn, n_sweeps = 4, wl.sweeps
-    crbm.batched_autotune(plan, gs_d, tp, bd, qd, od, 1, crbm.EXCHANGE, wl.chain_seed)
+    w, b, lanes, _ = crbm.batched_autotune(plan, gs_d, tp, bd, qd, od, 1, crbm.EXCHANGE, wl.chain_seed)
+    print("launch shape", w, "waves x", b, "blocks,", lanes, "lanes per chain; psi_gs rows from LDS:",
+          lanes == 64 and crbm.batched_lds_rows(plan, crbm.EXCHANGE, w))
     words = ((n_burn + n_sweeps) * n_ + 31) // 32
     trace = torch.zeros(total, words, dtype=torch.int32, device="cuda")
     mu = torch.zeros(n_inst, 2, dtype=torch.complex128, device="cuda")
