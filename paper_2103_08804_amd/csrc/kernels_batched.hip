@@ -126,15 +126,20 @@ struct BatchedChain {
 
 // log 2cosh(zt) - log 2cosh(zg) of one unit (modulo 2 pi i): with s = sign Re z and w = exp(-2 s z),
 // log 2cosh z = s z + log(1 + w), so the difference is st zt - sg zg + log((1 + wt) / (1 + wg)), one
-// log and one atan2 per unit
+// atan2 per unit.  |w| <= 1 comes from the hardware base-2 exponential (an error relative to |w|, so
+// absolute and below 2^-21 in 1 + w), and the modulus part from two hardware base-2 logarithms of
+// |1 + w|^2, which lies in [0, 4] (a zero of cosh gives -inf, as the library log of the quotient did).
 __device__ __forceinline__ float2 unit_log_ratio(float2 zt, float2 zg) {
+    constexpr float kM2Log2e = -2.8853900817779268f;  // exp(-2a) = 2^(-2a log2 e)
+    constexpr float kHalfLn2 = 0.34657359027997264f;  // log(q)/2 = (ln 2 / 2) log2 q
     const float st = zt.x >= 0.f ? 1.f : -1.f, sg = zg.x >= 0.f ? 1.f : -1.f;
-    const float et = expf(-2.f * fabsf(zt.x)), eg = expf(-2.f * fabsf(zg.x));
+    const float et = __builtin_amdgcn_exp2f(fabsf(zt.x) * kM2Log2e), eg = __builtin_amdgcn_exp2f(fabsf(zg.x) * kM2Log2e);
     const float2 ct = cos_sin(2.f * st * zt.y), cg = cos_sin(2.f * sg * zg.y);
     const float2 a = make_float2(1.f + et * ct.x, -et * ct.y), b = make_float2(1.f + eg * cg.x, -eg * cg.y);
     const float2 q = make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);   // a conj(b)
     const float na = a.x * a.x + a.y * a.y, nb = b.x * b.x + b.y * b.y;
-    return make_float2(fabsf(zt.x) - fabsf(zg.x) + 0.5f * logf(na / nb), st * zt.y - sg * zg.y + atan2f(q.y, q.x));
+    const float lr = kHalfLn2 * (__builtin_amdgcn_logf(na) - __builtin_amdgcn_logf(nb));
+    return make_float2(fabsf(zt.x) - fabsf(zg.x) + lr, st * zt.y - sg * zg.y + atan2f(q.y, q.x));
 }
 
 template <int E, bool PAIR, bool ONE>
