@@ -208,7 +208,9 @@ int crbm_init_chains(crbm_plan plan, int8_t* spins, int n_chains, uint64_t seed,
  *   logpsi_out   complex64 [n_chains]    or NULL: log psi of the final states (Im mod 2 pi)
  *   samples_out  int8 [n_sweeps][n_chains][N] or NULL
  *   n_accept     uint32 [n_chains] or NULL: accepted steps in this call
- *   accept_trace uint32 [n_chains][ceil(n_sweeps*N/32)] or NULL: bit (sweep*N+k) = accepted */
+ *   accept_trace uint32 [n_chains][ceil(n_sweeps*N/32)] or NULL: bit (sweep*N+k) = accepted
+ * n_sweeps = 0 leaves the spins as they are and writes theta, log psi of the start states and
+ * n_accept = 0. */
 int crbm_sample(crbm_plan plan, const crbm_rbm* psi, int8_t* spins, void* theta_out, void* logpsi_out,
                 int n_chains, int n_sweeps, int proposal, uint64_t seed, uint64_t step_offset,
                 int8_t* samples_out, uint32_t* n_accept, uint32_t* accept_trace, hipStream_t stream);
@@ -221,7 +223,9 @@ int crbm_sample(crbm_plan plan, const crbm_rbm* psi, int8_t* spins, void* theta_
  *   R_out = phi(s)/fit(s).
  * Outputs (any may be NULL): logpsi_out complex64 [n] (log fit, Im mod 2 pi), eloc_out
  * complex64 [n], R_out complex64 [n], tanh_out complex64 [n][M] (tanh theta of fit),
- * O_out complex64 [n][P] (O_a = sigma, O_b = tanh theta, O_W = sigma_i tanh theta_j). */
+ * O_out complex64 [n][P] (O_a = sigma, O_b = tanh theta, O_W = sigma_i tanh theta_j).
+ * n_samples = 0 writes nothing and launches nothing (samples and outputs may then be NULL); the
+ * arguments are still checked. */
 int crbm_local_estimators(crbm_plan plan, const crbm_rbm* fit, const crbm_rbm* psi_n, const crbm_rbm* psi_nm1,
                           const crbm_cheb* cheb, const int8_t* samples, long n_samples,
                           void* logpsi_out, void* eloc_out, void* R_out, void* tanh_out, void* O_out,

@@ -518,8 +518,8 @@ int crbm_local_estimators(crbm_plan p, const crbm_rbm* fit, const crbm_rbm* psi_
                           void* R_out, void* tanh_out, void* O_out, hipStream_t stream) {
     if (check_plan(p)) return CRBM_EINVAL;
     if (int rc = check_rbm(p, fit, "fit")) return rc;
-    if (!samples) return fail(CRBM_EINVAL, "samples is NULL");
     if (n < 0) return fail(CRBM_EINVAL, "n_samples must be >= 0");
+    if (n > 0 && !samples) return fail(CRBM_EINVAL, "samples is NULL");
     if (n > p->max_samples) return fail(CRBM_ENOMEM, "n_samples = %ld exceeds the plan's max_samples = %ld", n,
                                         p->max_samples);
     const bool cheb_mode = psi_n != nullptr;

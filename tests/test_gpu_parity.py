@@ -216,6 +216,55 @@ def test_sample_continuation_matches_single_call(orc):
     assert torch.equal(a, b)
 
 
+def test_degenerate_calls(orc):
+    """Zero-length calls: no sweeps (spins untouched, no accepted moves, theta and log psi of the start
+    states against the oracle, one chain and five), no samples (the call succeeds and writes nothing),
+    one sample, and moments up to order 0 only (mu_0 against the oracle)."""
+    kind, Lx, Ly, M = 1, 4, 4, 24
+    N = Lx * Ly
+    lat = orc.Lattice(kind, Lx, Ly)
+    psi_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(41, N, M, 0.2, std_im=0.02)))
+    psi = to_oracle_rbm(orc, psi_d)
+    plan = _plan(kind, Lx, Ly, M, 64)
+    for C in (1, 5):
+        spins = torch.zeros(C, N, dtype=torch.int8, device="cuda")
+        crbm.init_chains(plan, spins, 17, True)
+        s0 = spins.clone()
+        theta = torch.zeros(C, M, dtype=torch.complex64, device="cuda")
+        lp = torch.zeros(C, dtype=torch.complex64, device="cuda")
+        nacc = torch.full((C,), 7, dtype=torch.int32, device="cuda")
+        crbm.sample(plan, psi_d, spins, 0, crbm.EXCHANGE, 5, 0, theta_out=theta, logpsi_out=lp, n_accept=nacc)
+        torch.cuda.synchronize()
+        assert torch.equal(spins, s0)
+        assert int(nacc.abs().sum()) == 0
+        sig = np_of(s0)
+        assert rel_err(np_of(theta), psi.b[None, :] + sig.astype(np.float64) @ psi.W) < TOL
+        lp_ref = orc.logpsi(psi, sig)
+        assert np.all(np.abs(np_of(lp).real - lp_ref.real) <= TOL * np.maximum(np.abs(lp_ref.real), 1.0))
+        assert np.all(np.abs(wrapped(np_of(lp).imag - lp_ref.imag)) <= 1e-4)
+
+    # no samples: energy mode and Chebyshev mode return without writing
+    cheb = crbm.make_cheb(1, -5.0, 8.0, 0.9, 1.1, (np.pi, np.pi))
+    empty = torch.zeros(0, N, dtype=torch.int8, device="cuda")
+    out0 = torch.zeros(0, dtype=torch.complex64, device="cuda")
+    crbm.local_estimators(plan, psi_d, empty, logpsi_out=out0, eloc_out=out0)
+    crbm.local_estimators(plan, psi_d, empty, psi_n=psi_d, psi_nm1=psi_d, cheb=cheb, R_out=out0)
+    # one sample
+    one = synth.random_spins(3, 1, N, zero_magnetisation=True)
+    el = torch.zeros(1, dtype=torch.complex64, device="cuda")
+    crbm.local_estimators(plan, psi_d, torch.from_numpy(one).cuda(), eloc_out=el)
+    torch.cuda.synchronize()
+    assert rel_err(np_of(el), orc.local_energy(psi, lat, one)) < TOL
+
+    # moments with no Chebyshev vectors: mu_0 alone
+    sig = synth.random_spins(8, 64, N, zero_magnetisation=True)
+    qs = [(np.pi, np.pi), (np.pi / 2, 0.0)]
+    mu = torch.zeros(len(qs), 1, dtype=torch.complex128, device="cuda")
+    crbm.chebyshev_moment(plan, psi_d, None, None, qs, torch.from_numpy(sig).cuda(), mu)
+    torch.cuda.synchronize()
+    assert rel_err(np_of(mu), orc.moments(psi, [], [], qs, lat, sig)) < TOL
+
+
 # ------------------------------------------------------------------ natural-gradient step
 def _sr_inputs(orc, N, M, std, seed):
     fit_d = to_device_rbm(orc.RBM(*synth.random_rbm_arrays(seed, N, M, std)))
