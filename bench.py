@@ -51,15 +51,23 @@ def traffic_source_hash():
     return h.hexdigest()
 
 
-def s_rows_split(N, M):
-    """(R_m, R_r): the b and W rows (R = M + N M) that the S contraction's main kernel takes (the full
-    8-site blocks of the N + 1 extended sites) and those of the last, partly filled block, which run as
-    ragged pairs when it holds fewer than 7 sites (else the main kernel takes all R rows)."""
+def s_rows_run(N, M):
+    """Rows of the b and W blocks (R = M + N M useful ones) that the S contraction runs on the matrix cores,
+    padding included: tiles of 8 extended sites x 16 units over the full site blocks; in the last block, when
+    it holds r < 7 of the N + 1 extended sites, 2-site fragments of 16 units, with the lone site N of two
+    hidden blocks sharing one fragment when r is odd."""
     full, last = divmod(N + 1, 8)
-    R = M + N * M
-    if 0 < last < 7:
-        return 8 * full * M, R - 8 * full * M
-    return R, 0
+    n_hb = (M + 15) // 16
+    rows = 8 * full * 16 * n_hb
+    if last == 0:
+        return rows
+    if last >= 7:
+        return rows + 8 * 16 * n_hb
+    rf = (last + 1) // 2
+    if last % 2:
+        pairs, odd = divmod(n_hb, 2)
+        return rows + 32 * (pairs * (2 * rf - 1) + odd * rf)
+    return rows + 32 * n_hb * rf
 
 
 def measured_traffic():
@@ -209,35 +217,23 @@ def main():
         avg_s = t / c / 1e3
         # the contraction builds the rows and columns of b and W (R = M + N M of the P parameters):
         # R(R+1)/2 complex entries x N_s samples x 8 real flops; the N rows of a are the border kernel's.
-        # The main kernel takes the R_m rows of the full 8-site blocks, the ragged launch the other R_r
-        # rows (against all rows).
+        # One launch takes the tile pairs of the full 8-site blocks and the ragged pairs of the last.
         R_rows = P - N
-        R_m, R_r = s_rows_split(N, M)
-        flops_main = 4.0 * R_m * (R_m + 1) * ns
+        flops = 4.0 * R_rows * (R_rows + 1) * ns
         peak = BF16_PEAK_TFLOPS if prec == crbm.BF16 else FP32_MATRIX_PEAK_TFLOPS
-        achieved = flops_main / avg_s / 1e12
+        achieved = flops / avg_s / 1e12
         traffic = measured_traffic() if (prec == crbm.BF16 and C == wl.chains and sweeps == wl.sweeps) else None
         esz = 2 if prec == crbm.BF16 else 4
-        sites_main = R_m // M
-        roof = {"kernel": "k_sbuild_mfma (tile pairs of the full site blocks)", "bound": "mfma",
+        roof = {"kernel": "k_sbuild_mfma (all tile pairs of the b and W rows, one launch)", "bound": "mfma",
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
-                "algorithmic_flops": flops_main,
-                # each operand read once (T re and im of M units, the sign rows of its sites) and both
-                # triangles of its block written
-                "algorithmic_bytes": (2 * M + sites_main) * ns * esz + 8 * R_m * R_m,
-                "note": ("rows of W of the full 8-site blocks (R_m = %d of R = P - N = %d); the other rows of W "
-                         "and b run in the ragged launch (phase 'sragged'), the N rows of a in k_sbuild_border "
-                         "(phase 'sborder')" % (R_m, R_rows))}
-        if "sragged" in prof:
-            c2, t2 = prof["sragged"]
-            rag_s = t2 / c2 / 1e3
-            flops_rag = 8.0 * ns * (R_r * R_m + R_r * (R_r + 1) / 2)
-            flops_all = 4.0 * R_rows * (R_rows + 1) * ns
-            roof["ragged_launch"] = {"ms": rag_s * 1e3, "algorithmic_flops": flops_rag,
-                                     "achieved": flops_rag / rag_s / 1e12}
-            roof["whole_contraction"] = {"ms": (avg_s + rag_s) * 1e3, "algorithmic_flops": flops_all,
-                                         "achieved": flops_all / (avg_s + rag_s) / 1e12,
-                                         "frac": flops_all / (avg_s + rag_s) / 1e12 / peak}
+                "algorithmic_flops": flops,
+                # each operand read once (T re and im of M units, the sign rows of the N + 1 extended sites)
+                # and both triangles of the block written
+                "algorithmic_bytes": (2 * M + N + 1) * ns * esz + 8 * R_rows * R_rows,
+                "rows_run_per_useful_row": s_rows_run(N, M) / R_rows,
+                "note": ("the b and W rows (R = P - N = %d) in one launch: the tile pairs of the full 8-site blocks "
+                         "and the ragged pairs of the last block; the N rows of a in k_sbuild_border (phase "
+                         "'sborder')" % R_rows)}
     else:
         c, t = prof["ot"]
         avg_s = t / c / 1e3
@@ -477,15 +473,13 @@ def bench_chain40(crbm, args):
     el, phases = _timed(plan, step, args.steps, args.warmup)
     st = stats.cpu().numpy()
     # the FP32 S contraction of the b and W rows (R = P - N): 4 R (R + 1) N_s FLOP on the FP32 matrix cores;
-    # its row tiles are 8 sites x 16 units; the last site block runs only its 2-site fragments that hold
-    # real sites (ragged pairs), so 41 extended sites run as 42 rather than 48
-    t_sb = (phases["sbuild"]["avg_ms"] + phases.get("sragged", {"avg_ms": 0.0})["avg_ms"]) / 1e3
+    # its row tiles are 8 sites x 16 units; the last site block (site 40 alone) runs as one fragment per
+    # two hidden blocks (ragged pairs)
+    t_sb = phases["sbuild"]["avg_ms"] / 1e3
     R_rows = P - N
     flops = 4.0 * R_rows * (R_rows + 1) * ns
-    full_blocks, last = divmod(N + 1, 8)
-    sites_run = 8 * full_blocks + (2 * ((last + 1) // 2) if 0 < last < 7 else (8 if last else 0))
-    rows_run = sites_run * 16 * ((M + 15) // 16)
-    roof = {"kernel": "k_sbuild_mfma<false> (FP32 operands, main and ragged launches)", "bound": "mfma",
+    rows_run = s_rows_run(N, M)
+    roof = {"kernel": "k_sbuild_mfma<false> (FP32 operands, one launch)", "bound": "mfma",
             "achieved": flops / t_sb / 1e12,
             "peak": FP32_MATRIX_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": flops / t_sb / 1e12 / FP32_MATRIX_PEAK_TFLOPS,
             "traffic": None, "algorithmic_flops": flops, "rows_run_per_useful_row": rows_run / R_rows}
@@ -878,7 +872,7 @@ def matfree_compare(crbm, plan, fit, flat, T, R, wl, args, ms_per_step, prof):
         crbm.copy_plan_buffer(plan, crbm.BUF_DALPHA, dx)
         torch.cuda.synchronize()
         dal[name] = dx
-    dense_sr = sum(prof[k][1] / prof[k][0] for k in ("ot", "pack", "sbuild", "sragged", "sborder", "cg") if k in prof)
+    dense_sr = sum(prof[k][1] / prof[k][0] for k in ("ot", "pack", "sbuild", "sborder", "cg") if k in prof)
     step = ms_per_step - dense_sr + ms["matfree"]
     rel = float((dal["matfree"] - dal["dense"]).abs().max() / dal["dense"].abs().max())
     return {"sr_ms": ms["matfree"], "cg_iterations": its["matfree"], "dense_sr_ms": dense_sr,

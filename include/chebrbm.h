@@ -152,7 +152,7 @@ enum {
     CRBM_PROF_LOCAL,        /* local-estimator kernel */
     CRBM_PROF_OT,           /* O^H c contraction kernel */
     CRBM_PROF_SBUILD,       /* dense S contraction kernel, rows of the hidden biases b and weights W (matrix cores;
-                               the tile pairs of the full site blocks) */
+                               the tile pairs of the full site blocks and those of the last, partly filled one) */
     CRBM_PROF_CG,           /* whole conjugate-gradient loop (many kernels) */
     CRBM_PROF_MOMENT,       /* per-order moment ratio kernel */
     CRBM_PROF_PACK,         /* operand packing for the S contraction (two kernels) */
@@ -160,7 +160,6 @@ enum {
     CRBM_PROF_BATCHED,      /* batched moments: counter reset, persistent kernel, per-instance reduction */
     CRBM_PROF_GRAM,         /* moment-correction matrices: G and H products and their reduction (two kernels) */
     CRBM_PROF_SBORDER,      /* dense S contraction: the rows of the visible biases a (matrix cores) */
-    CRBM_PROF_SRAGGED,      /* dense S contraction: the pairs of the last, partly filled site block (matrix cores) */
     CRBM_PROF_COUNT
 };
 int crbm_plan_profile(crbm_plan plan, int enable);

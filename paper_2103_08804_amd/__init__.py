@@ -36,8 +36,7 @@ EXPORTS = ("crbm_plan_create", "crbm_plan_create_ex", "crbm_plan_destroy", "crbm
            "crbm_spectrum_kpm", "crbm_spectrum_cf", "crbm_probe_mfma", "crbm_probe_hbm", "crbm_probe_logcosh", "crbm_probe_gather",
            "crbm_sym_matrices", "crbm_fit_stats", "crbm_enum_weights",
            "crbm_fidelity_grad_noalloc")
-PROF_NAMES = ("sample", "theta", "local", "ot", "sbuild", "cg", "moment", "pack", "cholesky", "batched", "gram", "sborder",
-              "sragged")
+PROF_NAMES = ("sample", "theta", "local", "ot", "sbuild", "cg", "moment", "pack", "cholesky", "batched", "gram", "sborder")
 
 
 class CrbmError(RuntimeError):

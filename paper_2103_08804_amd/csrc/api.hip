@@ -340,22 +340,18 @@ int crbm_plan_create_ex(crbm_plan* out, const crbm_lattice* lat, int n_hidden, l
         rc = rc ? rc : p->alloc(&p->w.hv_part, nT * nT * kHemvTile);
     }
     if (!rc && (flags & CRBM_PLAN_CHOLESKY)) rc = p->alloc(&p->w.S64, P * P);
-    std::vector<int2> order, thin;
+    std::vector<int2> order;
     if (!rc && (flags & (CRBM_PLAN_DENSE_S | CRBM_PLAN_CHOLESKY))) {
         p->w.pack_bytes = sbuild_pack_bytes((int)N, (int)M, S);
         rc = p->alloc(reinterpret_cast<unsigned char**>(&p->w.pack), p->w.pack_bytes);
+        // the pairs of full tiles, then the ragged pairs of the last site block (one launch takes both)
         order = sbuild_order((int)N, (int)M, kXcds, kSuperTile);
+        const std::vector<int2> rag = sbuild_order_ragged((int)N, (int)M);
+        order.insert(order.end(), rag.begin(), rag.end());
         int2* d_order = nullptr;
         rc = rc ? rc : p->alloc(&d_order, order.size());
         p->w.sb_order = d_order;
         p->w.sb_order_len = (long)order.size();
-        thin = sbuild_order_ragged((int)N, (int)M);
-        if (!thin.empty()) {
-            int2* d_thin = nullptr;
-            rc = rc ? rc : p->alloc(&d_thin, thin.size());
-            p->w.sb_order_rag = d_thin;
-            p->w.sb_order_rag_len = (long)thin.size();
-        }
         // buffer of a contraction split over samples when the tile pairs alone cannot fill the device
         const long slice = P * P * (long)sizeof(float2);
         const long nsm = std::min<long>(kMaxSplits, kSplitBytes / slice);
@@ -398,9 +394,6 @@ int crbm_plan_create_ex(crbm_plan* out, const crbm_lattice* lat, int n_hidden, l
     if (e == hipSuccess) e = hipMemset(p->w.scal, 0, 32 * sizeof(double));
     if (e == hipSuccess && !order.empty())
         e = hipMemcpy(const_cast<int2*>(p->w.sb_order), order.data(), order.size() * sizeof(int2),
-                      hipMemcpyHostToDevice);
-    if (e == hipSuccess && !thin.empty() && p->w.sb_order_rag)
-        e = hipMemcpy(const_cast<int2*>(p->w.sb_order_rag), thin.data(), thin.size() * sizeof(int2),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) { delete p; return hip_fail(e, "plan initialisation"); }
     *out = p;
@@ -1247,7 +1240,7 @@ int crbm_sbuild_autotune(crbm_plan p, const int8_t* samples, const void* tanh_th
         if (r == hipSuccess)
             r = launch_sbuild_mfma((int)p->N, (int)p->M, p->P, samples, static_cast<const float2*>(tanh_theta), n,
                                    p->w.Om, p->w.Om, p->w.S, CRBM_PREC_BF16, tiles[ti], p->w.pack, p->w.pack_bytes,
-                                   p->w.sb_order, p->w.sb_order_len, p->w.sb_order_rag, p->w.sb_order_rag_len,
+                                   p->w.sb_order, p->w.sb_order_len,
                                    p->w.spart, nsplit, p->w.bx, p->w.bx_part, &off, stream);
         if (r == hipSuccess) r = hipEventRecord(e1, stream);
         if (r == hipSuccess) r = hipEventSynchronize(e1);

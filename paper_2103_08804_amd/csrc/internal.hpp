@@ -126,10 +126,8 @@ struct SrWork {
     float2* vstage;           // [P] float copy of a CG direction
     void* pack;               // packed operand planes of the matrix-core S contraction
     size_t pack_bytes;
-    const int2* sb_order;     // dispatch order of its tile pairs
+    const int2* sb_order;     // dispatch order of its tile pairs (full tiles, then the ragged pairs)
     long sb_order_len;
-    const int2* sb_order_rag; // its ragged pairs (the last, partly filled site block), or null
-    long sb_order_rag_len;
     float2* spart;            // [nsplit_max][P][P] partial sums of a contraction split over samples (or null)
     float2* bx;               // [N][P] raw a-row sums of the matrix-core S contraction
     float2* bx_part;          // [nsplit_max][N][P] their split partial sums (with spart)
@@ -143,7 +141,7 @@ struct SrWork {
 
 // instrumentation group ids (mirrors CRBM_PROF_* of the public header)
 enum { PROF_SAMPLE = 0, PROF_THETA, PROF_LOCAL, PROF_OT, PROF_SBUILD, PROF_CG, PROF_MOMENT, PROF_PACK, PROF_CHOLESKY,
-       PROF_BATCHED, PROF_GRAM, PROF_SBORDER, PROF_SRAGGED, PROF_COUNT };
+       PROF_BATCHED, PROF_GRAM, PROF_SBORDER, PROF_COUNT };
 
 struct SrArgs {
     int N, M, P;
@@ -190,8 +188,8 @@ struct BatchedArgs {
 // the matrix-core S contraction (kernels_mfma.hip); kt_bf16: K tile of the BF16 variant, 64 or 128
 hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n,
                               const double2* shift, const double2* Om, float2* S, int prec, int kt_bf16, void* pack,
-                              size_t pack_bytes, const int2* order, long n_order, const int2* order_rag,
-                              long n_rag, float2* split_buf, int nsplit, float2* bx, float2* bx_part, Profiler* prof,
+                              size_t pack_bytes, const int2* order, long n_order, float2* split_buf, int nsplit,
+                              float2* bx, float2* bx_part, Profiler* prof,
                               hipStream_t stream);
 int sbuild_splits(int N, int M, long n, int n_cu, int max_splits);
 

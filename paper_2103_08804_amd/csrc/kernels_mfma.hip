@@ -22,10 +22,13 @@
 // units = 128 rows, made of four 32-row matrix-core fragments of 2 sites x 16
 // hidden units each; N + 1 sites and M hidden units are padded only to
 // multiples of 8 and 16, and the fragments of the last site block that hold
-// no real site are skipped (ragged pairs).  A workgroup streams, per sample,
-// the T' values of 16 + 16 hidden units and the sign masks of 8 + 8 sites and
-// synthesises the 128 + 128 operand rows by XOR-ing the sign bit into the floating-point T'
-// (sigma = +-1 is exact in any format).  Each workgroup (4 waves) owns a
+// no real site are skipped (ragged pairs); when that block holds an odd count of
+// sites, the half fragment of site N left over in one hidden block is filled
+// with site N of the next (a mixed fragment), so that no matrix-core work goes
+// to padding.  A workgroup streams, per sample, the T' values of 16 + 16
+// hidden units and the sign masks of 8 + 8 sites and synthesises the 128 + 128
+// operand rows by XOR-ing the sign bit into the floating-point T' (sigma = +-1
+// is exact in any format).  Each workgroup (4 waves) owns a
 // 128 x 128 complex tile pair (u <= u') and accumulates, per wave, a 64 x 64
 // complex block as 4 real products (RR + II -> Re, RI - IR -> Im) in FP32 with
 //   v_mfma_f32_32x32x16_bf16   (BF16 operands), or
@@ -47,6 +50,8 @@
 // order (deterministic, in double) before the same epilogue arithmetic.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
 #include <type_traits>
 #include <vector>
 
@@ -238,44 +243,106 @@ struct Stager {
 };
 
 // ------------------------------------------------------------------ main kernel: W/b tile pairs
-// Split mode (nsplit > 1): workgroup x handles tile pair x % n_order over the K tiles of split
-// x / n_order and writes the raw sums into S + split * P * P (no scaling, no means).
-template <bool BF16, int KTB, int RF>
-__global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* __restrict__ order, long n_order,
-                                                        long ns_pad, int nsplit,
-                                                        const typename Pol<BF16>::E* __restrict__ Tr,
-                                                        const typename Pol<BF16>::E* __restrict__ Ti,
-                                                        const typename Pol<BF16>::E* __restrict__ Sm,
-                                                        Centre cen, float2* __restrict__ S) {
+// One tile pair: the A tile (site block sbA, hidden block hbA) against the B tile (sbB, hbB), AF x BF
+// fragments per wave.  RAG: A is the last, partly filled site block; every wave takes its first AF
+// fragments against fragment `wave` of B.  Else each wave takes 2 x 2 fragments of two full tiles.
+// MODE (with RAG), see A_PLAIN: A_MIX when the block holds an odd count of real sites, so that its last
+// live fragment holds the extended site N alone and its second half (site N + 1) would be padding; here
+// that half is site N of hidden block hbM instead (the b rows of a second hidden block, whose T' rows
+// are staged after the masks), so that no matrix-core work goes to padding.  A_DUAL: the fragments of
+// two hidden blocks of that block in one workgroup (hbM's T' rows staged after the masks), so that a
+// wave issues as many matrix-core operations per operand read as a pair of full tiles.  ROWS_ALLOC: stage rows of the kernel's LDS
+// double buffer.  Split mode (nsplit > 1): this workgroup sums the K tiles of split `split` and writes
+// raw sums into S + split * P * P (no scaling, no means).
+// Helpers of sb_tile_pair, written as functions of their arguments (no closures, so that nothing of a
+// tile pair's state has to live in memory when several tile-pair bodies share one kernel).
+// The packed-plane row behind stage row `row` (the stage layout of sb_tile_pair).
+template <typename E>
+__device__ __forceinline__ const E* sb_src_row(int row, const E* Tr, const E* Ti, const E* Sm, long ns_pad, int sbA,
+                                               int hbA, int hbM, int sbB, int hbB) {
+    if (row < 64 || row >= 80) {
+        const int pl = (row < 64 ? row : row - 80) >> 4, r = row & 15;
+        const E* plane = (pl & 1) ? Ti : Tr;
+        const int hb = row >= 80 ? hbM : (pl < 2) ? hbA : hbB;
+        return plane + (long)(hb * MK_TH + r) * ns_pad;
+    }
+    const int m = row - 64;                      // mask row 0..15
+    const int site = (m < MK_TS) ? sbA * MK_TS + m : sbB * MK_TS + (m - MK_TS);
+    return Sm + (long)site * ns_pad;
+}
+// 16-byte chunks tid + 256 q of the stage of K tile kt, global -> registers
+template <typename St, int KT, typename E>
+__device__ __forceinline__ void sb_gload(i32x4 (&regs)[St::PER_THREAD], long kt, int tid, const E* Tr, const E* Ti,
+                                         const E* Sm, long ns_pad, int sbA, int hbA, int hbM, int sbB, int hbB) {
+#pragma unroll
+    for (int q = 0; q < St::PER_THREAD; ++q) {
+        const int c = tid + q * 256;
+        i32x4 v = {0, 0, 0, 0};
+        if (c < St::TOTAL) {
+            const int row = c / St::CH_PER_ROW, ch = c % St::CH_PER_ROW;
+            const E* src = sb_src_row<E>(row, Tr, Ti, Sm, ns_pad, sbA, hbA, hbM, sbB, hbB) + kt * KT +
+                           ch * (St::CHUNK / (int)sizeof(E));
+            v = *reinterpret_cast<const i32x4*>(src);
+        }
+        regs[q] = v;
+    }
+}
+// the same chunks, registers -> the LDS stage at dst
+template <typename St, int ROWB, bool BF16>
+__device__ __forceinline__ void sb_lstore(const i32x4 (&regs)[St::PER_THREAD], unsigned char* dst, int tid) {
+#pragma unroll
+    for (int q = 0; q < St::PER_THREAD; ++q) {
+        const int c = tid + q * 256;
+        if (c >= St::TOTAL) continue;
+        const int row = c / St::CH_PER_ROW, ch = c % St::CH_PER_ROW;
+        unsigned char* d = dst + row * ROWB + ch * St::CHUNK;
+        if constexpr (BF16) {
+            *reinterpret_cast<i32x4*>(d) = regs[q];
+        } else {
+#pragma unroll
+            for (int w4 = 0; w4 < 4; ++w4) reinterpret_cast<int*>(d)[w4] = regs[q][w4];
+        }
+    }
+}
+// A-fragment layouts of a tile pair: PLAIN, fragments 0 .. AF-1 of the A tile; MIX, the last of them the
+// mixed fragment (site N of hidden blocks hbA and hbM); DUAL, fragments 0 .. AF/2-1 of the last site
+// block's tiles of hidden blocks hbA and hbM (the same sites, so the same masks)
+constexpr int A_PLAIN = 0, A_MIX = 1, A_DUAL = 2;
+// (extended site, hidden unit) of row qq (0..31) of A fragment f
+template <int MODE, int AF>
+__device__ __forceinline__ int2 sb_row_a(int f, int qq, int N, int sbA, int hbA, int hbM) {
+    const int half = qq >> 4;
+    if (MODE == A_MIX && f == AF - 1) return make_int2(N, (half ? hbM : hbA) * MK_TH + (qq & 15));
+    if (MODE == A_DUAL && f >= AF / 2)
+        return make_int2(sbA * MK_TS + 2 * (f - AF / 2) + half, hbM * MK_TH + (qq & 15));
+    return make_int2(sbA * MK_TS + 2 * f + half, hbA * MK_TH + (qq & 15));
+}
+
+template <bool BF16, int KTB, int AF, int BF, bool RAG, int MODE, int ROWS_ALLOC>
+__device__ __forceinline__ void sb_tile_pair(const SbGeom& gm, int sbA, int hbA, int hbM, int sbB, int hbB, bool diag,
+                                             int split, long ns_pad, int nsplit,
+                                             const typename Pol<BF16>::E* __restrict__ Tr,
+                                             const typename Pol<BF16>::E* __restrict__ Ti,
+                                             const typename Pol<BF16>::E* __restrict__ Sm, const Centre& cen,
+                                             float2* __restrict__ S, unsigned char* lds) {
     using E = typename Pol<BF16>::E;
     constexpr int KT = BF16 ? KTB : 64;            // samples per LDS K tile (BF16: 64 or 128, tuned per plan)
     // bytes per LDS row, padded so that the 16 rows of a fragment read fall in distinct banks
     constexpr int ROWB = KT * (int)sizeof(E) + (BF16 ? 16 : 4);
-    // stage rows: [0,16) Tr(A) [16,32) Ti(A) [32,48) Tr(B) [48,64) Ti(B) [64,72) masks(A) [72,80) masks(B)
-    constexpr int ROWS = 80;
-    constexpr int STAGE = ROWS * ROWB;
-    __shared__ __attribute__((aligned(16))) unsigned char lds[2 * STAGE];
+    // stage rows: [0,16) Tr(A) [16,32) Ti(A) [32,48) Tr(B) [48,64) Ti(B) [64,72) masks(A) [72,80) masks(B);
+    // MIX and DUAL: [80,96) Tr(hbM) [96,112) Ti(hbM)
+    constexpr int ROWS = MODE != A_PLAIN ? 112 : 80;
+    static_assert(ROWS <= ROWS_ALLOC, "the stage rows exceed the LDS buffer");
+    static_assert(MODE == A_PLAIN || RAG, "mixed and dual fragments belong to the last site block");
+    static_assert(MODE != A_DUAL || AF % 2 == 0, "a dual pair holds as many fragments of each hidden block");
+    constexpr int AFH = MODE == A_DUAL ? AF / 2 : AF;   // fragments of hidden block hbA
+    constexpr int STAGE = ROWS_ALLOC * ROWB;
     using St = Stager<ROWS, KT, E>;
-
-    // tile pair (u, u'), u <= u', from the dispatch-order table (entries < 0 are padding).  RF > 0, a
-    // ragged pair (h, u'): the tile of hidden block h in the last site block, of whose four 2-site
-    // fragments only the first RF hold real sites, against tile u'; every wave takes those RF
-    // fragments against one fragment of u'.  RF = 0: each wave takes 2 x 2 fragments of two full tiles.
-    const int split = (int)(blockIdx.x / n_order);
-    const int2 pr = order[blockIdx.x % n_order];
-    if (pr.x < 0) return;
-    const int u = RF ? (gm.nSB - 1) * gm.nHB + pr.x : pr.x, up = pr.y;
-    const int sbA = u / gm.nHB, hbA = u % gm.nHB;
-    const int sbB = up / gm.nHB, hbB = up % gm.nHB;
     const int N = gm.N, M = gm.M;
     const long P = gm.P;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wi = wave >> 1, wj = wave & 1;
-    constexpr int AF = RF ? RF : 2, BF = RF ? 1 : 2;     // fragments per wave
-    auto fragA = [&](int a) { return RF ? a : 2 * wi + a; };
-    auto fragB = [&](int b) { return RF ? wave : 2 * wj + b; };
-
     floatx16 acc_re[AF][BF], acc_im[AF][BF];
 #pragma unroll
     for (int a = 0; a < AF; ++a)
@@ -285,46 +352,6 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
             for (int v = 0; v < 16; ++v) { acc_re[a][b][v] = 0.f; acc_im[a][b][v] = 0.f; }
 
     i32x4 stage_regs[St::PER_THREAD];
-    auto src_row = [&](int row) -> const E* {
-        if (row < 64) {
-            const int pl = row >> 4, r = row & 15;
-            const E* plane = (pl & 1) ? Ti : Tr;
-            const int hb = (pl < 2) ? hbA : hbB;
-            return plane + (long)(hb * MK_TH + r) * ns_pad;
-        }
-        const int m = row - 64;                      // mask row 0..15
-        const int site = (m < MK_TS) ? sbA * MK_TS + m : sbB * MK_TS + (m - MK_TS);
-        return Sm + (long)site * ns_pad;
-    };
-    auto gload = [&](long kt) {
-#pragma unroll
-        for (int q = 0; q < St::PER_THREAD; ++q) {
-            const int c = tid + q * 256;
-            i32x4 v = {0, 0, 0, 0};
-            if (c < St::TOTAL) {
-                const int row = c / St::CH_PER_ROW, ch = c % St::CH_PER_ROW;
-                const E* src = src_row(row) + kt * KT + ch * (St::CHUNK / (int)sizeof(E));
-                v = *reinterpret_cast<const i32x4*>(src);
-            }
-            stage_regs[q] = v;
-        }
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < St::PER_THREAD; ++q) {
-            const int c = tid + q * 256;
-            if (c >= St::TOTAL) continue;
-            const int row = c / St::CH_PER_ROW, ch = c % St::CH_PER_ROW;
-            unsigned char* dst = lds + buf * STAGE + row * ROWB + ch * St::CHUNK;
-            if constexpr (BF16) {
-                *reinterpret_cast<i32x4*>(dst) = stage_regs[q];
-            } else {
-#pragma unroll
-                for (int w4 = 0; w4 < 4; ++w4) reinterpret_cast<int*>(dst)[w4] = stage_regs[q][w4];
-            }
-        }
-    };
-
     // this workgroup's K tiles [kt0, kt1): the split ranges are set in 128-sample units, so that every
     // K tile size sums the same samples in the same order
     const long n_kt_all = ns_pad / KT;
@@ -332,51 +359,28 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
     const long kt0 = split * per < n_kt_all ? split * per : n_kt_all;
     const long kt1 = kt0 + per < n_kt_all ? kt0 + per : n_kt_all;
     if (kt0 < kt1) {
-        gload(kt0);
-        lstore(0);
+        sb_gload<St, KT, E>(stage_regs, kt0, tid, Tr, Ti, Sm, ns_pad, sbA, hbA, hbM, sbB, hbB);
+        sb_lstore<St, ROWB, BF16>(stage_regs, lds, tid);
     }
     __syncthreads();
 
-    const bool diag = (u == up);
     const bool raw = nsplit > 1;
     float2* out = S + (raw ? (long)split * P * P : 0L);
     // FP32 operands: the matrix-core accumulators' error grows with the count of accumulations, so the
     // sums run in blocks of MK_KB K tiles (4096 samples), each added to this pair's own entries of the
     // output (its upper tile; FP32 adds on the vector units) and the accumulators cleared
     bool flushed = false;
-    auto flush = [&]() {
-        // an opaque copy of the lane index, so that the entry indices are formed here and not kept
-        // live through the K loop
-        int ln = lane;
-        asm volatile("" : "+v"(ln));
-#pragma unroll
-        for (int a = 0; a < AF; ++a)
-#pragma unroll
-            for (int b = 0; b < BF; ++b) {
-                const int qB = ln & 31;
-                const long kp = wb_to_p(sbB * MK_TS + 2 * fragB(b) + (qB >> 4), hbB * MK_TH + (qB & 15), N, M);
-#pragma unroll
-                for (int v = 0; v < 16; ++v) {
-                    const int qA = 8 * (v >> 2) + 4 * (ln >> 5) + (v & 3);
-                    const long k = wb_to_p(sbA * MK_TS + 2 * fragA(a) + (qA >> 4), hbA * MK_TH + (qA & 15), N, M);
-                    if (k >= 0 && kp >= 0) {
-                        float2* o = out + k * P + kp;
-                        const float2 prev = flushed ? *o : make_float2(0.f, 0.f);
-                        *o = make_float2(prev.x + acc_re[a][b][v], prev.y + acc_im[a][b][v]);
-                    }
-                    acc_re[a][b][v] = 0.f;
-                    acc_im[a][b][v] = 0.f;
-                }
-            }
-        flushed = true;
-    };
 
-    // fragment rows: lane row q = lane % 32 is (site 2f + q / 16, hidden q % 16) of fragment f
+    // fragment rows: lane row q = lane % 32 is (site 2f + q / 16, hidden q % 16) of fragment f.  The
+    // mixed fragment's second half reads the T' rows of hbM (stage row 80 + ...) and has zero masks (site
+    // N), so its operands are its rows as they stand; the dual pair's second half reads hbM's rows with
+    // the masks of the first half's fragments.
     const int q = lane & 31, lhalf = lane >> 5;
     const int trow = q & 15, qs = q >> 4;
+    const int mrow = (MODE == A_MIX && !qs) ? trow : 80 + trow;
     for (long kt = kt0; kt < kt1; ++kt) {
         const int buf = (int)((kt - kt0) & 1);
-        if (kt + 1 < kt1) gload(kt + 1);
+        if (kt + 1 < kt1) sb_gload<St, KT, E>(stage_regs, kt + 1, tid, Tr, Ti, Sm, ns_pad, sbA, hbA, hbM, sbB, hbB);
         const unsigned char* base = lds + buf * STAGE;
 #pragma unroll
         for (int ks = 0; ks < KT; ks += Pol<BF16>::kStep) {
@@ -386,19 +390,35 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
                 const i32x4 tiA = *reinterpret_cast<const i32x4*>(base + (16 + trow) * ROWB + koff);
                 const i32x4 trB = *reinterpret_cast<const i32x4*>(base + (32 + trow) * ROWB + koff);
                 const i32x4 tiB = *reinterpret_cast<const i32x4*>(base + (48 + trow) * ROWB + koff);
+                i32x4 trM = trA, tiM = tiA;
+                if constexpr (MODE != A_PLAIN) {
+                    trM = *reinterpret_cast<const i32x4*>(base + mrow * ROWB + koff);
+                    tiM = *reinterpret_cast<const i32x4*>(base + (mrow + 16) * ROWB + koff);
+                }
                 i32x4 mA[AF], mB[BF];
 #pragma unroll
-                for (int a = 0; a < AF; ++a)
-                    mA[a] = *reinterpret_cast<const i32x4*>(base + (64 + 2 * fragA(a) + qs) * ROWB + koff);
+                for (int a = 0; a < AF; ++a) {
+                    if (MODE == A_MIX && a == AF - 1) continue;
+                    if (a >= AFH) mA[a] = mA[a - AFH];
+                    else mA[a] = *reinterpret_cast<const i32x4*>(base + (64 + 2 * (RAG ? a : 2 * wi + a) + qs) * ROWB + koff);
+                }
 #pragma unroll
                 for (int b = 0; b < BF; ++b)
-                    mB[b] = *reinterpret_cast<const i32x4*>(base + (72 + 2 * fragB(b) + qs) * ROWB + koff);
+                    mB[b] = *reinterpret_cast<const i32x4*>(base + (72 + 2 * (RAG ? wave : 2 * wj + b) + qs) * ROWB + koff);
                 const i32x4 neg = {(int)0x80008000, (int)0x80008000, (int)0x80008000, (int)0x80008000};
                 i32x4 ar[AF], ai[AF], br[BF], bi[BF], nbr[BF];
 #pragma unroll
                 for (int a = 0; a < AF; ++a) {
-                    ar[a] = trA ^ mA[a];
-                    ai[a] = tiA ^ mA[a];
+                    if (MODE == A_MIX && a == AF - 1) {
+                        ar[a] = trM;
+                        ai[a] = tiM;
+                    } else if (a >= AFH) {
+                        ar[a] = trM ^ mA[a];
+                        ai[a] = tiM ^ mA[a];
+                    } else {
+                        ar[a] = trA ^ mA[a];
+                        ai[a] = tiA ^ mA[a];
+                    }
                 }
 #pragma unroll
                 for (int b = 0; b < BF; ++b) {
@@ -406,8 +426,8 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
                     bi[b] = tiB ^ mB[b];
                     nbr[b] = br[b] ^ neg;
                 }
-                // first product of every accumulator, then the second: eight independent
-                // matrix-core operations separate the two updates of one accumulator
+                // first product of every accumulator, then the second: independent matrix-core
+                // operations separate the two updates of one accumulator
 #pragma unroll
                 for (int a = 0; a < AF; ++a)
 #pragma unroll
@@ -431,16 +451,26 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
                 const uint32_t tiA = *reinterpret_cast<const uint32_t*>(base + (16 + trow) * ROWB + koff);
                 const uint32_t trB = *reinterpret_cast<const uint32_t*>(base + (32 + trow) * ROWB + koff);
                 const uint32_t tiB = *reinterpret_cast<const uint32_t*>(base + (48 + trow) * ROWB + koff);
+                uint32_t trM = trA, tiM = tiA;
+                if constexpr (MODE != A_PLAIN) {
+                    trM = *reinterpret_cast<const uint32_t*>(base + mrow * ROWB + koff);
+                    tiM = *reinterpret_cast<const uint32_t*>(base + (mrow + 16) * ROWB + koff);
+                }
                 uint32_t mA[AF], mB[BF];
 #pragma unroll
                 for (int a = 0; a < AF; ++a)
-                    mA[a] = *reinterpret_cast<const uint32_t*>(base + (64 + 2 * fragA(a) + qs) * ROWB + koff);
+                    mA[a] = (MODE == A_MIX && a == AF - 1) ? 0u
+                            : (a >= AFH) ? mA[a - AFH]
+                                         : *reinterpret_cast<const uint32_t*>(
+                                               base + (64 + 2 * (RAG ? a : 2 * wi + a) + qs) * ROWB + koff);
 #pragma unroll
                 for (int b = 0; b < BF; ++b)
-                    mB[b] = *reinterpret_cast<const uint32_t*>(base + (72 + 2 * fragB(b) + qs) * ROWB + koff);
+                    mB[b] = *reinterpret_cast<const uint32_t*>(base + (72 + 2 * (RAG ? wave : 2 * wj + b) + qs) * ROWB + koff);
 #pragma unroll
                 for (int a = 0; a < AF; ++a) {
-                    const float ar = __uint_as_float(trA ^ mA[a]), ai = __uint_as_float(tiA ^ mA[a]);
+                    const bool second = (MODE == A_MIX && a == AF - 1) || a >= AFH;
+                    const uint32_t ra = second ? trM : trA, ia = second ? tiM : tiA;
+                    const float ar = __uint_as_float(ra ^ mA[a]), ai = __uint_as_float(ia ^ mA[a]);
 #pragma unroll
                     for (int b = 0; b < BF; ++b) {
                         const float br = __uint_as_float(trB ^ mB[b]), bi = __uint_as_float(tiB ^ mB[b]);
@@ -452,9 +482,35 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
                 }
             }
         }
-        if (kt + 1 < kt1) lstore(buf ^ 1);
+        if (kt + 1 < kt1) sb_lstore<St, ROWB, BF16>(stage_regs, lds + (buf ^ 1) * STAGE, tid);
         if constexpr (!BF16) {
-            if ((kt - kt0 + 1) % MK_KB == 0 && kt + 1 < kt1) flush();
+            if ((kt - kt0 + 1) % MK_KB == 0 && kt + 1 < kt1) {
+                // an opaque copy of the lane index, so that the entry indices are formed here and not kept
+                // live through the K loop
+                int ln = lane;
+                asm volatile("" : "+v"(ln));
+#pragma unroll
+                for (int a = 0; a < AF; ++a)
+#pragma unroll
+                    for (int b = 0; b < BF; ++b) {
+                        const int qB = ln & 31, fB = RAG ? wave : 2 * wj + b;
+                        const long kp = wb_to_p(sbB * MK_TS + 2 * fB + (qB >> 4), hbB * MK_TH + (qB & 15), N, M);
+#pragma unroll
+                        for (int v = 0; v < 16; ++v) {
+                            const int qA = 8 * (v >> 2) + 4 * (ln >> 5) + (v & 3);
+                            const int2 ij = sb_row_a<MODE, AF>(RAG ? a : 2 * wi + a, qA, N, sbA, hbA, hbM);
+                            const long k = wb_to_p(ij.x, ij.y, N, M);
+                            if (k >= 0 && kp >= 0) {
+                                float2* o = out + k * P + kp;
+                                const float2 prev = flushed ? *o : make_float2(0.f, 0.f);
+                                *o = make_float2(prev.x + acc_re[a][b][v], prev.y + acc_im[a][b][v]);
+                            }
+                            acc_re[a][b][v] = 0.f;
+                            acc_im[a][b][v] = 0.f;
+                        }
+                    }
+                flushed = true;
+            }
         }
         __syncthreads();
     }
@@ -463,17 +519,18 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
     // and column l % 32 of the B fragment
 #pragma unroll
     for (int a = 0; a < AF; ++a) {
-        const int fA = fragA(a);
+        const int fA = RAG ? a : 2 * wi + a;
 #pragma unroll
         for (int b = 0; b < BF; ++b) {
-            const int fB = fragB(b);
+            const int fB = RAG ? wave : 2 * wj + b;
             const int qB = lane & 31;
             const int iB = sbB * MK_TS + 2 * fB + (qB >> 4), jB = hbB * MK_TH + (qB & 15);
             const long kp = wb_to_p(iB, jB, N, M);
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int qA = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-                const int iA = sbA * MK_TS + 2 * fA + (qA >> 4), jA = hbA * MK_TH + (qA & 15);
+                const int2 ij = sb_row_a<MODE, AF>(fA, qA, N, sbA, hbA, hbM);
+                const int iA = ij.x, jA = ij.y;
                 const long k = wb_to_p(iA, jA, N, M);
                 if (k < 0 || kp < 0) continue;
                 float2 sum = make_float2(acc_re[a][b][v], acc_im[a][b][v]);
@@ -492,6 +549,67 @@ __global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* _
                 out[k * P + kp] = val;
                 if (!diag) out[kp * P + k] = cconj(val);
             }
+        }
+    }
+}
+
+// Ragged-pair kinds.  The A entry of a ragged pair in the order table holds RAG_FLAG | kind << 26 |
+// hM << 13 | h: h (and hM) are hidden blocks of the last site block's tiles, both below 2^13.
+constexpr int RAG_PLAIN = 0;   // the first RF fragments of tile h (the last one with its padding half)
+constexpr int RAG_MIX = 1;     // the first RF - 1 fragments of tile h, and site N of hidden blocks h and hM
+constexpr int RAG_REST = 2;    // the first RF - 1 fragments of tile h (its site N in a RAG_MIX pair)
+constexpr int RAG_DUAL = 3;    // the first RF - 1 fragments of tiles h and hM (their sites N in RAG_MIX pairs)
+constexpr int RAG_HB_BITS = 13;
+constexpr int RAG_FLAG = 1 << 30;
+__host__ __device__ constexpr int rag_entry(int kind, int h, int hM) {
+    return RAG_FLAG | kind << 26 | hM << RAG_HB_BITS | h;
+}
+__host__ __device__ constexpr int rag_kind(int x) { return (x >> 26) & 7; }
+
+// The contraction: workgroup x takes tile pair x % n_order of the dispatch-order table (entries < 0 are
+// padding): pairs (u, u') of full tiles, u <= u', and, with RF > 0, ragged pairs (rag_entry, u'): the
+// last site block's tile of hidden block h (and hM), of whose four 2-site fragments only the first RF
+// hold real sites, against tile u'.  One launch takes both, so that the short ragged pairs fill the
+// last round of the long ones.
+template <bool BF16, int KTB, int RF>
+__global__ __launch_bounds__(256, 2) void k_sbuild_mfma(SbGeom gm, const int2* __restrict__ order, long n_order,
+                                                        long ns_pad, int nsplit,
+                                                        const typename Pol<BF16>::E* __restrict__ Tr,
+                                                        const typename Pol<BF16>::E* __restrict__ Ti,
+                                                        const typename Pol<BF16>::E* __restrict__ Sm,
+                                                        Centre cen, float2* __restrict__ S) {
+    using E = typename Pol<BF16>::E;
+    constexpr int KT = BF16 ? KTB : 64;
+    constexpr int ROWB = KT * (int)sizeof(E) + (BF16 ? 16 : 4);
+    constexpr int ROWS_ALLOC = RF ? 112 : 80;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[2 * ROWS_ALLOC * ROWB];
+    const int split = (int)(blockIdx.x / n_order);
+    const int2 pr = order[blockIdx.x % n_order];
+    if (pr.x < 0) return;
+    const int sbB = pr.y / gm.nHB, hbB = pr.y % gm.nHB;
+    if (RF == 0 || !(pr.x & RAG_FLAG)) {
+        sb_tile_pair<BF16, KTB, 2, 2, false, A_PLAIN, ROWS_ALLOC>(gm, pr.x / gm.nHB, pr.x % gm.nHB, 0, sbB, hbB,
+                                                                pr.x == pr.y, split, ns_pad, nsplit, Tr, Ti, Sm,
+                                                                cen, S, lds);
+    } else if constexpr (RF > 0) {
+        const int kind = rag_kind(pr.x), sbA = gm.nSB - 1;
+        const int h = pr.x & ((1 << RAG_HB_BITS) - 1), hM = (pr.x >> RAG_HB_BITS) & ((1 << RAG_HB_BITS) - 1);
+        if (kind == RAG_MIX) {
+            sb_tile_pair<BF16, KTB, RF, 1, true, A_MIX, ROWS_ALLOC>(gm, sbA, h, hM, sbB, hbB, false, split, ns_pad,
+                                                                    nsplit, Tr, Ti, Sm, cen, S, lds);
+        } else if (kind == RAG_REST) {
+            if constexpr (RF > 1)
+                sb_tile_pair<BF16, KTB, RF - 1, 1, true, A_PLAIN, ROWS_ALLOC>(gm, sbA, h, 0, sbB, hbB, false, split,
+                                                                              ns_pad, nsplit, Tr, Ti, Sm, cen, S, lds);
+        } else if (kind == RAG_DUAL) {
+            if constexpr (RF > 1)
+                sb_tile_pair<BF16, KTB, 2 * (RF - 1), 1, true, A_DUAL, ROWS_ALLOC>(gm, sbA, h, hM, sbB, hbB, false,
+                                                                                   split, ns_pad, nsplit, Tr, Ti, Sm,
+                                                                                   cen, S, lds);
+        } else {
+            sb_tile_pair<BF16, KTB, RF, 1, true, A_PLAIN, ROWS_ALLOC>(gm, sbA, h, 0, sbB, hbB,
+                                                                      sbA * gm.nHB + h == pr.y, split, ns_pad,
+                                                                      nsplit, Tr, Ti, Sm, cen, S, lds);
         }
     }
 }
@@ -748,23 +866,80 @@ __global__ __launch_bounds__(256) void k_sbuild_reduce(Centre cen, int nsplit, c
 // Live 2-site fragments of the last site block when it holds fewer than seven of the N + 1 extended
 // sites (then its tiles go to ragged pairs, which skip the empty fragments), else 0.  For N a multiple
 // of 8 the block holds site N alone (one fragment, the b rows); for 10 x 10 it holds sites 96 .. 100.
+static int ragged_sites(int N) { return N + 1 - MK_TS * ((N + 1 + MK_TS - 1) / MK_TS - 1); }
 int sbuild_ragged_frags(int N) {
-    const int r = N + 1 - MK_TS * ((N + 1 + MK_TS - 1) / MK_TS - 1);   // real sites of the last block
-    const int f = (r + 1) / 2;
+    const int f = (ragged_sites(N) + 1) / 2;
     return f < MK_TS / 2 ? f : 0;
+}
+
+// The ragged pairs by B tile, with the work of each group in units of one RAG_PLAIN pair
+// (live fragments / RF).  When the last block holds an odd count of real sites its last live fragment
+// holds site N alone: the tiles of hidden blocks h and h + 1 (h even) then go as one RAG_MIX pair (the
+// first RF - 1 fragments of h and the mixed one) and the first RF - 1 fragments of h + 1, which join
+// those of the next such h + 3 in one RAG_DUAL pair (an odd one left over as RAG_REST; none when RF = 1):
+// 2 RF - 1 fragments where two RAG_PLAIN pairs hold 2 RF.  A last, unpaired hidden block, the pairs
+// against the last block's own tiles, and every pair when the count is even, go as RAG_PLAIN.
+struct RagGroup {
+    std::vector<int2> pairs;
+    double work;
+};
+static std::vector<RagGroup> ragged_groups(int N, int M) {
+    std::vector<RagGroup> groups;
+    const int rf = sbuild_ragged_frags(N);
+    if (!rf) return groups;
+    const SbGeom gm = sb_geom(N, M);
+    const int nt_main = (gm.nSB - 1) * gm.nHB;
+    const bool mix = (ragged_sites(N) & 1) != 0 && gm.nHB < (1 << RAG_HB_BITS);
+    const double rest = (double)(rf - 1) / (double)rf;
+    for (int up = 0; up < nt_main; ++up) {
+        RagGroup g{{}, 0.0};
+        std::vector<int> rest_hb;
+        int h = 0;
+        if (mix) {
+            for (; h + 1 < gm.nHB; h += 2) rest_hb.push_back(h + 1);
+            if (rf > 1) {
+                size_t k = 0;
+                for (; k + 1 < rest_hb.size(); k += 2) {
+                    g.pairs.push_back(make_int2(rag_entry(RAG_DUAL, rest_hb[k], rest_hb[k + 1]), up));
+                    g.work += 2.0 * rest;
+                }
+                if (k < rest_hb.size()) {
+                    g.pairs.push_back(make_int2(rag_entry(RAG_REST, rest_hb[k], 0), up));
+                    g.work += rest;
+                }
+            }
+            for (int hm : rest_hb) {
+                g.pairs.push_back(make_int2(rag_entry(RAG_MIX, hm - 1, hm), up));
+                g.work += 1.0;
+            }
+        }
+        for (; h < gm.nHB; ++h) {
+            g.pairs.push_back(make_int2(rag_entry(RAG_PLAIN, h, 0), up));
+            g.work += 1.0;
+        }
+        groups.push_back(g);
+    }
+    for (int h2 = gm.nHB - 1; h2 >= 0; --h2) {
+        RagGroup g{{}, 0.0};
+        for (int h = 0; h <= h2; ++h) g.pairs.push_back(make_int2(rag_entry(RAG_PLAIN, h, 0), nt_main + h2));
+        g.work = (double)(h2 + 1);
+        groups.push_back(g);
+    }
+    return groups;
 }
 
 // Number of sample splits for a contraction of n samples when the tile pairs alone cannot fill the
 // device: the split count s (at most max_splits, which the plan's slice buffer holds, and at least 4
-// K tiles per split) that minimises the modelled time of the launches, sum over launches of
-// ceil(pairs s / resident workgroups) / s (rounds per unit of one pair's full-sample work; a ragged pair
-// of f live fragments counts f / 4), so that the last round of each launch is not left nearly empty.
+// K tiles per split) that minimises the modelled time of the launch,
+// ceil(work s / resident workgroups) / s (rounds per unit of one pair's full-sample work; a ragged pair
+// of f live fragments counts f / 4), so that the last round of the launch is not left nearly empty.
 int sbuild_splits(int N, int M, long n, int n_cu, int max_splits) {
     const SbGeom gm = sb_geom(N, M);
     const int rf = sbuild_ragged_frags(N);
     const long nt = (long)(rf ? gm.nSB - 1 : gm.nSB) * gm.nHB;
     const long n_main = nt * (nt + 1) / 2;
-    const long n_rag = rf ? (long)gm.nHB * nt + (long)gm.nHB * (gm.nHB + 1) / 2 : 0;
+    double w_rag = 0.0;
+    for (const RagGroup& g : ragged_groups(N, M)) w_rag += g.work;
     const long n_kt = ((n + MK_KT - 1) / MK_KT * MK_KT) / 64;    // the finest K tile of any variant is 64
     long smax = max_splits < n_kt / 4 ? max_splits : n_kt / 4;
     if (smax < 1) smax = 1;
@@ -772,8 +947,8 @@ int sbuild_splits(int N, int M, long n, int n_cu, int max_splits) {
     double best = 1e300;
     long bs = 1;
     for (long sp = 1; sp <= smax; ++sp) {
-        const double t = (double)((n_main * sp + slots - 1) / slots) / (double)sp +
-                         0.25 * rf * (double)((n_rag * sp + slots - 1) / slots) / (double)sp;
+        const double w = (double)n_main + 0.25 * rf * w_rag;
+        const double t = std::ceil(w * (double)sp / (double)slots - 1e-9) / (double)sp;
         if (t < best * (1.0 - 1e-9)) { best = t; bs = sp; }
     }
     return (int)bs;
@@ -784,8 +959,8 @@ int sbuild_splits(int N, int M, long n, int n_cu, int max_splits) {
 // (T' rounded as packed, plus c); bx: N x P side buffer; bx_part: nsplit of them when nsplit > 1.
 hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n,
                               const double2* shift, const double2* Om, float2* S, int prec, int kt_bf16, void* pack,
-                              size_t pack_bytes, const int2* order, long n_order, const int2* order_rag,
-                              long n_rag, float2* split_buf, int nsplit, float2* bx, float2* bx_part, Profiler* prof,
+                              size_t pack_bytes, const int2* order, long n_order, float2* split_buf, int nsplit,
+                              float2* bx, float2* bx_part, Profiler* prof,
                               hipStream_t stream) {
     const SbGeom gm = sb_geom(N, M);
     if (nsplit > 1 && (!split_buf || !bx_part)) return hipErrorInvalidValue;
@@ -843,18 +1018,13 @@ hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const flo
                 hipLaunchKernelGGL((k_sbuild_mfma<B16, 128, R>), g, dim3(256), 0, stream, gm, ord, n_ord, ns_pad,
                                    nsplit, Tr, Ti, Sm, cen, out);
         };
-        launch(std::integral_constant<int, 0>{}, order, n_order);
-        prof->end(stream);
-        if (n_rag > 0) {
-            prof->begin(PROF_SRAGGED, stream);
-            switch (sbuild_ragged_frags(N)) {
-                case 1: launch(std::integral_constant<int, 1>{}, order_rag, n_rag); break;
-                case 2: launch(std::integral_constant<int, 2>{}, order_rag, n_rag); break;
-                case 3: launch(std::integral_constant<int, 3>{}, order_rag, n_rag); break;
-                default: break;
-            }
-            prof->end(stream);
+        switch (sbuild_ragged_frags(N)) {
+            case 1: launch(std::integral_constant<int, 1>{}, order, n_order); break;
+            case 2: launch(std::integral_constant<int, 2>{}, order, n_order); break;
+            case 3: launch(std::integral_constant<int, 3>{}, order, n_order); break;
+            default: launch(std::integral_constant<int, 0>{}, order, n_order); break;
         }
+        prof->end(stream);
         prof->begin(PROF_SBORDER, stream);
         if (nsplit > 1)
             hipLaunchKernelGGL(k_sbuild_reduce, dim3((unsigned)((P * P + 255) / 256)), dim3(256), 0, stream, cen,
@@ -895,18 +1065,17 @@ std::vector<int2> sbuild_order(int N, int M, int n_xcd, int g) {
     return out;
 }
 
-// Ragged pairs (h, u'): the last site block's tile of hidden block h against every tile u' of the full
-// site blocks, and against the last block's tiles of hidden blocks h' >= h; the pairs that share a B
-// tile sit next to each other.
+// Ragged pairs in dispatch order, after the pairs of full tiles: kind by kind, the longest first
+// (RAG_DUAL, then RAG_MIX and RAG_PLAIN, then RAG_REST), each kind by B tile.  Workgroups of one kind then
+// run side by side and the shortest fill the last round.
 std::vector<int2> sbuild_order_ragged(int N, int M) {
     std::vector<int2> out;
-    if (!sbuild_ragged_frags(N)) return out;
-    const SbGeom gm = sb_geom(N, M);
-    const int nt_main = (gm.nSB - 1) * gm.nHB;
-    for (int up = 0; up < nt_main; ++up)
-        for (int h = 0; h < gm.nHB; ++h) out.push_back(make_int2(h, up));
-    for (int h = 0; h < gm.nHB; ++h)
-        for (int h2 = h; h2 < gm.nHB; ++h2) out.push_back(make_int2(h, nt_main + h2));
+    const std::vector<RagGroup> groups = ragged_groups(N, M);
+    const int kinds[] = {RAG_DUAL, RAG_MIX, RAG_PLAIN, RAG_REST};
+    for (int kind : kinds)
+        for (const RagGroup& g : groups)
+            for (const int2& e : g.pairs)
+                if (rag_kind(e.x) == kind) out.push_back(e);
     return out;
 }
 

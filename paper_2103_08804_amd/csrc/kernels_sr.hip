@@ -1042,7 +1042,7 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
             }
             const int nsplit = W.spart ? sbuild_splits(A.N, A.M, A.n, W.n_cu, W.nsplit_max) : 1;
             e = launch_sbuild_mfma(A.N, A.M, P, A.samples, A.T, A.n, W.Om, W.Om16, W.S, A.prec, W.sb_kt, W.pack,
-                                   W.pack_bytes, W.sb_order, W.sb_order_len, W.sb_order_rag, W.sb_order_rag_len,
+                                   W.pack_bytes, W.sb_order, W.sb_order_len,
                                    W.spart, nsplit, W.bx, W.bx_part, W.prof, stream);
         } else {
             // weighted (enumeration) sums: FP32 contraction on the vector units

@@ -466,13 +466,17 @@ def test_fidelity_grad(orc):
 # ------------------------------------------------------------------ matrix-core S contraction
 @pytest.mark.parametrize("kind,Lx,Ly,M,n,bias", [(0, 10, 1, 10, 1000, 0.0), (1, 4, 4, 40, 777, 0.0),
                                                   (0, 40, 1, 80, 130, 0.0), (0, 7, 1, 3, 200, 0.0),
-                                                  (0, 12, 1, 24, 600, 0.0),
+                                                  (0, 12, 1, 24, 600, 0.0), (0, 10, 1, 40, 500, 0.0),
+                                                  (0, 18, 1, 56, 300, 0.0), (0, 12, 1, 72, 300, 0.0),
                                                   (1, 4, 4, 40, 777, 1.5), (0, 10, 1, 10, 1000, 3.0)])
 def test_dense_s_matrix_cores(orc, kind, Lx, Ly, M, n, bias):
     """S from the FP32 and BF16 matrix-core contractions (uniform weights) against the oracle's S, with
     the last site block of the N + 1 extended sites full (N = 7) or ragged with 1 (N = 16, 40), 2
-    (N = 10) or 3 (N = 12) live 2-site fragments; every entry is bounded relative to the centred
-    diagonal: |dS_kk'| <= tol sqrt(S_kk S_k'k').  The bias
+    (N = 10, 18) or 3 (N = 12) live 2-site fragments.  Those counts of real sites are odd, so site N of
+    two hidden blocks shares one mixed fragment wherever a next hidden block exists (M = 24, 40, 56, 72,
+    80), the other fragments of every second hidden block pair up across two blocks (M = 56, 72), and a
+    last unpaired block keeps its padding half (M = 10, 40, 72, 80).  Every entry is bounded relative
+    to the centred diagonal: |dS_kk'| <= tol sqrt(S_kk S_k'k').  The bias
     added to Re b puts |<tanh theta>| at about 5 (bias 1.5) and 200 (bias 3) times the spread of tanh
     theta, where sums of raw products less the product of the means would lose those digits.
     FP32 operands: tol 1e-5.  BF16 operands (8-bit significands, each of the two shifted operands
