@@ -68,6 +68,8 @@ constexpr int kMaxMomentEntries = 4096;   // n_q * (n_max + 1)
 constexpr int kMaxBasis = 256;             // K = n_max + 1 of the moment-correction matrices
 constexpr long kSplitBytes = 1L << 30;     // bound of the split-contraction buffer
 constexpr long kMaxSplits = 12;
+constexpr long kBorderSplitBytes = 256L << 20;   // bound of the border kernel's split slices
+constexpr long kMaxBorderSplits = 16;
 constexpr int kXcds = 8;                   // accelerator complex dies of the MI355X (round-robin dispatch)
 #ifndef CRBM_SUPERTILE
 #define CRBM_SUPERTILE 8
@@ -357,8 +359,14 @@ int crbm_plan_create_ex(crbm_plan* out, const crbm_lattice* lat, int n_hidden, l
         const long nsm = std::min<long>(kMaxSplits, kSplitBytes / slice);
         if (!rc && nsm >= 2) {
             rc = p->alloc(&p->w.spart, (size_t)(nsm * P * P));
-            rc = rc ? rc : p->alloc(&p->w.bx_part, (size_t)(nsm * N * P));
             p->w.nsplit_max = (int)nsm;
+        }
+        // slices of the border kernel split over samples (at least as many as the tile pairs use)
+        const long nsb = std::min<long>(kMaxBorderSplits, kBorderSplitBytes / (N * P * (long)sizeof(float2)));
+        p->w.nsb_max = 1;
+        if (!rc && nsb >= 2) {
+            rc = p->alloc(&p->w.bx_part, (size_t)(nsb * N * P));
+            p->w.nsb_max = (int)nsb;
         }
         rc = rc ? rc : p->alloc(&p->w.bx, (size_t)(N * P));
     }
@@ -1230,6 +1238,7 @@ int crbm_sbuild_autotune(crbm_plan p, const int8_t* samples, const void* tanh_th
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return fail(CRBM_EHIP, "hipEventCreate");
     const int nsplit = p->w.spart ? sbuild_splits((int)p->N, (int)p->M, n, p->w.n_cu, p->w.nsplit_max) : 1;
+    const int nsb = sbuild_border_splits((int)p->N, (int)p->M, n, p->w.n_cu, p->w.nsb_max);
     Profiler off;
     double best = 1e300;
     int bk = p->w.sb_kt;
@@ -1241,7 +1250,7 @@ int crbm_sbuild_autotune(crbm_plan p, const int8_t* samples, const void* tanh_th
             r = launch_sbuild_mfma((int)p->N, (int)p->M, p->P, samples, static_cast<const float2*>(tanh_theta), n,
                                    p->w.Om, p->w.Om, p->w.S, CRBM_PREC_BF16, tiles[ti], p->w.pack, p->w.pack_bytes,
                                    p->w.sb_order, p->w.sb_order_len,
-                                   p->w.spart, nsplit, p->w.bx, p->w.bx_part, &off, stream);
+                                   p->w.spart, nsplit, p->w.bx, p->w.bx_part, nsb, &off, stream);
         if (r == hipSuccess) r = hipEventRecord(e1, stream);
         if (r == hipSuccess) r = hipEventSynchronize(e1);
         if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);

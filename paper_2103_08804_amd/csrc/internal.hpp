@@ -134,6 +134,7 @@ struct SrWork {
     double2* hv_part;         // [nT][nT][kHemvTile] tile shares of the dense Hermitian product (with S)
     uint16_t* wplanes;        // split-W scratch of the theta product (the matrix-free product's G)
     int nsplit_max;
+    int nsb_max;              // slices of bx_part: sample splits of the border kernel (1: none)
     int sb_kt;                // K tile (samples) of the BF16 S contraction: 64 or 128
     int n_cu;
     Profiler* prof;
@@ -189,9 +190,10 @@ struct BatchedArgs {
 hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n,
                               const double2* shift, const double2* Om, float2* S, int prec, int kt_bf16, void* pack,
                               size_t pack_bytes, const int2* order, long n_order, float2* split_buf, int nsplit,
-                              float2* bx, float2* bx_part, Profiler* prof,
+                              float2* bx, float2* bx_part, int nsb, Profiler* prof,
                               hipStream_t stream);
 int sbuild_splits(int N, int M, long n, int n_cu, int max_splits);
+int sbuild_border_splits(int N, int M, long n, int n_cu, int max_splits);
 
 // lanes per chain: 64 (any M), 32 (M <= 256) or 16 (M <= 128); the results are the same bit for bit
 bool batched_lanes_ok(int lanes, int M);

@@ -954,16 +954,40 @@ int sbuild_splits(int N, int M, long n, int n_cu, int max_splits) {
     return (int)bs;
 }
 
+// Sample splits of the border kernel.  Its nA x (W/b tiles + nA) workgroups each run the whole sample
+// range and, for small N, fill few of the resident slots (one K tile in flight per workgroup, so it waits
+// on its loads): the split count s (at most max_splits, at least 4 K tiles of 64 per split) that
+// minimises ceil(workgroups s / resident workgroups) / s.
+int sbuild_border_splits(int N, int M, long n, int n_cu, int max_splits) {
+    if (max_splits < 2) return 1;
+    const SbGeom gm = sb_geom(N, M);
+    const long nA = (N + MK_AB - 1) / MK_AB;
+    const long nwg = nA * ((long)gm.nSB * gm.nHB + nA);
+    const long n_kt = ((n + MK_KT - 1) / MK_KT * MK_KT) / 64;
+    long smax = max_splits < n_kt / 4 ? max_splits : n_kt / 4;
+    if (smax < 1) smax = 1;
+    const long slots = 2L * n_cu;
+    double best = 1e300;
+    long bs = 1;
+    for (long sp = 1; sp <= smax; ++sp) {
+        const double t = (double)((nwg * sp + slots - 1) / slots) / (double)sp;
+        if (t < best * (1.0 - 1e-9)) { best = t; bs = sp; }
+    }
+    return (int)bs;
+}
+
 // ------------------------------------------------------------------ launcher
 // shift: <O> of the unrounded operands (c_j from its b entries); Om: <O> of the operands as contracted
-// (T' rounded as packed, plus c); bx: N x P side buffer; bx_part: nsplit of them when nsplit > 1.
+// (T' rounded as packed, plus c); bx: N x P side buffer; bx_part: nsb of them when the border kernel is
+// split nsb > 1 ways over the samples (independently of the nsplit of the tile pairs).
 hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const float2* T, long n,
                               const double2* shift, const double2* Om, float2* S, int prec, int kt_bf16, void* pack,
                               size_t pack_bytes, const int2* order, long n_order, float2* split_buf, int nsplit,
-                              float2* bx, float2* bx_part, Profiler* prof,
+                              float2* bx, float2* bx_part, int nsb, Profiler* prof,
                               hipStream_t stream) {
     const SbGeom gm = sb_geom(N, M);
-    if (nsplit > 1 && (!split_buf || !bx_part)) return hipErrorInvalidValue;
+    if (nsplit > 1 && !split_buf) return hipErrorInvalidValue;
+    if (nsb < 1 || (nsb > 1 && !bx_part)) return hipErrorInvalidValue;
     if (kt_bf16 != 64 && kt_bf16 != 128) return hipErrorInvalidValue;
     if (!bx) return hipErrorInvalidValue;
     const long ns_pad = ((n + MK_KT - 1) / MK_KT) * MK_KT;
@@ -998,10 +1022,10 @@ hipError_t launch_sbuild_mfma(int N, int M, long P, const int8_t* sig, const flo
         prof->end(stream);
         // the border sums first: the main epilogue reads them
         prof->begin(PROF_SBORDER, stream);
-        hipLaunchKernelGGL(k_sbuild_border<B16>, dim3((unsigned)(nA * nX * nsplit)), dim3(256), 0, stream, gm, ns_pad,
-                           nA, nsplit, Tr, Ti, Sm, nsplit > 1 ? bx_part : bx);
-        if (nsplit > 1)
-            hipLaunchKernelGGL(k_bx_reduce, dim3((unsigned)((nbx + 255) / 256)), dim3(256), 0, stream, nbx, nsplit,
+        hipLaunchKernelGGL(k_sbuild_border<B16>, dim3((unsigned)(nA * nX * nsb)), dim3(256), 0, stream, gm, ns_pad,
+                           nA, nsb, Tr, Ti, Sm, nsb > 1 ? bx_part : bx);
+        if (nsb > 1)
+            hipLaunchKernelGGL(k_bx_reduce, dim3((unsigned)((nbx + 255) / 256)), dim3(256), 0, stream, nbx, nsb,
                                bx_part, bx);
         prof->end(stream);
         prof->begin(PROF_SBUILD, stream);

@@ -1041,9 +1041,10 @@ hipError_t launch_sr_step(const SrArgs& A, const SrWork& W, hipStream_t stream) 
                 if (e != hipSuccess) return e;
             }
             const int nsplit = W.spart ? sbuild_splits(A.N, A.M, A.n, W.n_cu, W.nsplit_max) : 1;
+            const int nsb = sbuild_border_splits(A.N, A.M, A.n, W.n_cu, W.nsb_max);
             e = launch_sbuild_mfma(A.N, A.M, P, A.samples, A.T, A.n, W.Om, W.Om16, W.S, A.prec, W.sb_kt, W.pack,
                                    W.pack_bytes, W.sb_order, W.sb_order_len,
-                                   W.spart, nsplit, W.bx, W.bx_part, W.prof, stream);
+                                   W.spart, nsplit, W.bx, W.bx_part, nsb, W.prof, stream);
         } else {
             // weighted (enumeration) sums: FP32 contraction on the vector units
             const int nt = (int)((P + SB_T - 1) / SB_T);
