@@ -380,7 +380,7 @@ def bench_batched(crbm, args):
                         "accepted_frac": accepted / props,
                         "l2_row_gather_GBps": l2, "row_gather_ceiling_GBps": g_ceil, "l2_row_gather_frac": l2 / g_ceil,
                         "lds_row_GBps": gs_rows if in_lds else 0.0,
-                        "bound_note": ("VALU issue: per proposal about 43 VALU instructions (SQ counters), of which the "
+                        "bound_note": ("VALU issue: per proposal about 39 VALU instructions (SQ counters), of which the "
                                        "log-cosh of a live move is about 9; the rest is the per-move control of one "
                                        "chain per wave"),
                         "peak_note": ("measured ceilings of this device: k_probe_logcosh (Re log 2cosh in the sweep's "

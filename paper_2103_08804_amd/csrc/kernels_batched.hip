@@ -119,10 +119,19 @@ struct BatchedChain {
     float Lg[E];            // Re log 2cosh theta_gs
     float2 pti[E], ptj[E];  // rows of t~'s W for the pending update of tht
     float pm;               // -2 s_i of the pending update, 0 when none
-    float da2;              // ONE: 2 (a_i - a_j) of psi_gs (2 a_i for a flip) of this lane's draw
+    float lu;               // ln(u) / 2 of this lane's draw: the acceptance test in the log domain
+    float thp, thm;         // ONE: lu less the move's change of Re(a . s) of psi_gs, for s_i = +1 and -1
     int acc;                // lane l: accept bit of proposal 64 k + l of the current 64
     double m0, mr, mi;      // sums of |f|^2 and conj(f) beta r
 };
+
+// ln(u) / 2 from the hardware base-2 logarithm.  A move is accepted when u < |psi(s')/psi(s)|^2, that
+// is when the change of Re log psi exceeds ln(u) / 2: the test compares that change with this
+// threshold less the change of Re(a . s), so no exponential is taken per move (u = 0 gives -inf: accept).
+__device__ __forceinline__ float half_ln(float u) {
+    constexpr float kHalfLn2 = 0.34657359027997264f;  // ln(u)/2 = (ln 2 / 2) log2 u
+    return kHalfLn2 * __builtin_amdgcn_logf(u);
+}
 
 // log 2cosh(zt) - log 2cosh(zg) of one unit (modulo 2 pi i): with s = sign Re z and w = exp(-2 s z),
 // log 2cosh z = s z + log(1 + w), so the difference is st zt - sg zg + log((1 + wt) / (1 + wg)), one
@@ -205,9 +214,10 @@ __device__ __forceinline__ void flush_accepts(BatchedChain<E, PAIR, ONE>& c, uin
 }
 
 // Proposal t of chain g.  Rows of psi_gs are read only for live moves; with LDSG from LDS (s_w: rows
-// of E 64 columns that hold zeros past M).  Every 64th proposal draws the next 64 (one per lane), with
-// ONE also each draw's change of Re(a . s) up to the sign of s_i, and writes the accept bits of the
-// previous 64 to the trace.
+// of E 64 columns that hold zeros past M).  Every 64th proposal draws the next 64 (one per lane) with
+// their thresholds ln(u)/2 (with ONE less each draw's change of Re(a . s), for both signs of s_i), and
+// writes the accept bits of the previous 64 to the trace.  The move is accepted when the wave total of
+// the log-cosh change exceeds ln(u)/2 less the change of Re(a . s), the same test in every kernel here.
 template <int E, bool PAIR, bool ONE, bool LDSG>
 __device__ __forceinline__ void batched_step(const BatchedArgs& A, const float2* s_w, uint64_t g, int lane, int t,
                                              BatchedChain<E, PAIR, ONE>& c, const MatRows& Wg, const MatRows& Wt,
@@ -217,12 +227,16 @@ __device__ __forceinline__ void batched_step(const BatchedArgs& A, const float2*
     if (l == 0) {
         if (t > 0) flush_accepts(c, trow, t - 64, 64, lane);
         batch = draw_batch(A.seed, (uint32_t)g, (uint64_t)t, lane, N);
+        c.lu = half_ln(batch.u);
         if (ONE) {
             // Re a of psi_gs at this lane's sites i, j (site k sits in lane k): the move changes
-            // Re(a . s) by -2 s_i (a_i - a_j), or by -2 s_i a_i for a flip
+            // Re(a . s) by -2 s_i (a_i - a_j), or by -2 s_i a_i for a flip, that is by -s_i d2 (exactly
+            // as -2 s_i a_i + 2 s_i a_j rounds)
             const float ai = __int_as_float(__builtin_amdgcn_ds_bpermute(batch.i << 2, __float_as_int(c.ag[0])));
             const float aj = __int_as_float(__builtin_amdgcn_ds_bpermute(batch.j << 2, __float_as_int(c.ag[0])));
-            c.da2 = PAIR ? 2.f * (ai - aj) : 2.f * ai;
+            const float d2 = PAIR ? 2.f * (ai - aj) : 2.f * ai;
+            c.thp = c.lu + d2;   // s_i = +1: the change is -d2
+            c.thm = c.lu - d2;
         }
     }
     Proposal cur = proposal_at(batch, l);
@@ -230,7 +244,7 @@ __device__ __forceinline__ void batched_step(const BatchedArgs& A, const float2*
     if (!(PAIR && si == sj)) {
         float2 wi[E], wj[E], tn[E];
         float Ln[E];
-        float dl;
+        float total, thr;
         if (LDSG) {
             constexpr int Mp = E * kWave;
 #pragma unroll
@@ -242,16 +256,16 @@ __device__ __forceinline__ void batched_step(const BatchedArgs& A, const float2*
             mat_fetch<E, PAIR>(Wg, loff, cur.i, cur.j, wi, wj);
         }
         if (ONE) {
-            // -2 s_i (a_i - a_j) = -s_i da2 exactly, as proposal_dlog forms it
-            const float d2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c.da2), l));
-            const float da = si > 0 ? -d2 : d2;
-            dl = units_dlog<E, PAIR, !LDSG>(si, wi, wj, c.thg, c.Lg, tn, Ln, lane, M) + da;
+            total = units_dlog<E, PAIR, !LDSG>(si, wi, wj, c.thg, c.Lg, tn, Ln, lane, M);
+            thr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(si > 0 ? c.thp : c.thm), l));
         } else {
-            cur.ai = site_value<ONE>(c.ag, cur.i);
-            cur.aj = PAIR ? site_value<ONE>(c.ag, cur.j) : 0.f;
-            dl = proposal_dlog<E, PAIR>(cur, si, wi, wj, c.thg, c.Lg, tn, Ln, lane, M);
+            const float m2si = -2.f * (float)si;
+            float da = m2si * site_value<ONE>(c.ag, cur.i);
+            if (PAIR) da -= m2si * site_value<ONE>(c.ag, cur.j);
+            total = units_dlog<E, PAIR>(si, wi, wj, c.thg, c.Lg, tn, Ln, lane, M);
+            thr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c.lu), l)) - uniform(da);
         }
-        if (cur.u < __expf(2.f * dl)) {
+        if (total > thr) {
 #pragma unroll
             for (int e = 0; e < E; ++e) { c.thg[e] = tn[e]; c.Lg[e] = Ln[e]; }
             apply_pending(c, lane, M);
@@ -369,7 +383,7 @@ void k_batched(BatchedArgs A) {
         }
         const double2 beta = A.betas[inst];
         c.pm = 0.f;
-        c.da2 = 0.f;
+        c.lu = c.thp = c.thm = 0.f;
         c.acc = 0;
         c.m0 = c.mr = c.mi = 0.0;
         uint32_t* trow = A.trace ? A.trace + (long)g * A.trace_words : nullptr;
@@ -577,8 +591,7 @@ __global__ __launch_bounds__(512) void k_batched_grp(BatchedArgs A) {
                     }
                     float da = m2si * ai;
                     if (PAIR) da -= m2si * aj;
-                    const float dl = group_total<L>(ds) + da;
-                    acc = live && (cu < __expf(2.f * dl));
+                    acc = live && (group_total<L>(ds) > half_ln(cu) - da);
                     if (acc) {
 #pragma unroll
                         for (int k = 0; k < EL; ++k) { thg[k] = tn[k]; Lg[k] = Ln[k]; }
