@@ -40,53 +40,63 @@ __global__ __launch_bounds__(256) void k_chol_load(long P, const float2* __restr
     A[idx] = make_double2((double)v.x + (i == j ? eps : 0.0), (double)v.y);
 }
 
-// 1. L_kk of the diagonal block [k0, k0 + nb)^2 in LDS (one workgroup of 256 threads)
+// 1. L_kk of the diagonal block [k0, k0 + nb)^2 in LDS (one workgroup of 256 threads, a 16 x 16 grid over
+//    rows and columns).  Column j: every thread reads the pivot d = L_jj (final since the last barrier, so
+//    all take the same decision) and updates its share of the trailing lower triangle with the column
+//    scaled by 1 / sqrt(d) on the fly; after one barrier the column itself is scaled.  The next column
+//    reads column j + 1 and its own trailing block only, so one barrier per column suffices.
 __global__ __launch_bounds__(256) void k_chol_diagblock(long P, long k0, int nb, double2* __restrict__ A,
                                                         double* __restrict__ sc) {
     __shared__ double2 L[CH_NB][CH_NB + 1];
-    __shared__ int fail;
     if (chol_failed(sc)) return;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < nb * nb; e += 256) {
-        const int i = e / nb, j = e % nb;
-        L[i][j] = (j <= i) ? A[(k0 + i) * P + k0 + j] : make_double2(0.0, 0.0);
-    }
-    if (tid == 0) fail = 0;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    for (int i = ty; i < nb; i += 16)
+        for (int j = tx; j < nb; j += 16) L[i][j] = (j <= i) ? A[(k0 + i) * P + k0 + j] : make_double2(0.0, 0.0);
     __syncthreads();
+    bool fail = false;
     for (int j = 0; j < nb; ++j) {
-        if (tid == 0) {
-            const double d = L[j][j].x;
-            if (!(d > 0.0) || !isfinite(d)) fail = 1;
-            else L[j][j] = make_double2(sqrt(d), 0.0);
+        const double d = L[j][j].x;
+        if (!(d > 0.0) || !isfinite(d)) {
+            fail = true;
+            break;
         }
-        __syncthreads();
-        if (fail) break;
-        const double inv = 1.0 / L[j][j].x;
-        for (int i = j + 1 + tid; i < nb; i += 256) L[i][j] = make_double2(L[i][j].x * inv, L[i][j].y * inv);
-        __syncthreads();
-        const int m = nb - j - 1;
-        for (int e = tid; e < m * m; e += 256) {
-            const int i = j + 1 + e / m, l = j + 1 + e % m;
-            if (l <= i) {
-                const double2 a = L[i][j], b = L[l][j];        // L_il -= L_ij conj(L_lj)
-                L[i][l].x -= a.x * b.x + a.y * b.y;
-                L[i][l].y -= a.y * b.x - a.x * b.y;
+        const double s = sqrt(d), inv = 1.0 / s;
+        double2 b[4];                                  // L_lj / s for this thread's columns l
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int l = j + 1 + tx + 16 * m;
+            b[m] = l < nb ? make_double2(L[l][j].x * inv, L[l][j].y * inv) : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int i = j + 1 + ty + 16 * p;
+            if (i >= nb) break;
+            const double2 a = make_double2(L[i][j].x * inv, L[i][j].y * inv);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int l = j + 1 + tx + 16 * m;
+                if (l <= i) {                          // L_il -= L_ij conj(L_lj)
+                    L[i][l].x -= a.x * b[m].x + a.y * b[m].y;
+                    L[i][l].y -= a.y * b[m].x - a.x * b[m].y;
+                }
             }
         }
         __syncthreads();
+        if (tid == 0) L[j][j] = make_double2(s, 0.0);
+        for (int i = j + 1 + tid; i < nb; i += 256) L[i][j] = make_double2(L[i][j].x * inv, L[i][j].y * inv);
     }
     if (fail) {
         if (tid == 0) sc[SC_FLAGS_SLOT] = (double)((int)sc[SC_FLAGS_SLOT] | CRBM_FLAG_CHOLESKY_FAIL);
         return;
     }
-    for (int e = tid; e < nb * nb; e += 256) {
-        const int i = e / nb, j = e % nb;
-        if (j <= i) A[(k0 + i) * P + k0 + j] = L[i][j];
-    }
+    __syncthreads();
+    for (int i = ty; i < nb; i += 16)
+        for (int j = tx; j <= i; j += 16) A[(k0 + i) * P + k0 + j] = L[i][j];
 }
 
 // 2. rows i >= k0 + nb: x L_kk^H = a with x = L_ik, a = A_ik; lane l owns column l of the row.
-//    x_m = (a_m - sum_{l<m} x_l conj(L_kk[m][l])) / L_kk[m][m]
+//    x_m = (a_m - sum_{l<m} x_l conj(L_kk[m][l])) / L_kk[m][m]: once x_l is known (step l, lane l) it is
+//    read by every lane, and lanes m > l subtract its term from their own a_m, in the order l = 0, 1, ...
 __global__ __launch_bounds__(256) void k_chol_panel(long P, long k0, int nb, double2* __restrict__ A,
                                                     const double* __restrict__ sc) {
     __shared__ double2 L[CH_NB][CH_NB + 1];
@@ -102,18 +112,15 @@ __global__ __launch_bounds__(256) void k_chol_panel(long P, long k0, int nb, dou
     double2* row = A + i * P + k0;
     double2 x = lane < nb ? row[lane] : make_double2(0.0, 0.0);
     for (int m = 0; m < nb; ++m) {
-        // partial sum over the lanes l < m of x_l conj(L[m][l])
-        double sx = 0.0, sy = 0.0;
-        if (lane < m) {
-            const double2 b = L[m][lane];
-            sx = x.x * b.x + x.y * b.y;
-            sy = x.y * b.x - x.x * b.y;
-        }
-        sx = wave_sum(sx);
-        sy = wave_sum(sy);
         if (lane == m) {
             const double inv = 1.0 / L[m][m].x;
-            x = make_double2((x.x - sx) * inv, (x.y - sy) * inv);
+            x = make_double2(x.x * inv, x.y * inv);
+        }
+        const double xr = __shfl(x.x, m), xi = __shfl(x.y, m);
+        if (lane > m && lane < nb) {
+            const double2 c = L[lane][m];           // x_m conj(L[lane][m])
+            x.x -= xr * c.x + xi * c.y;
+            x.y -= xi * c.x - xr * c.y;
         }
     }
     if (lane < nb) row[lane] = x;
