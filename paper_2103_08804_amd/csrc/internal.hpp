@@ -163,7 +163,7 @@ struct SrArgs {
 constexpr int kHemvTile = 256;
 inline int hemv_tiles(long P) { return (int)((P + kHemvTile - 1) / kHemvTile); }
 
-// the dense solve keeps the solution vector in LDS: P <= kCholMaxP (64 000 bytes of complex128)
+// the dense FP64 solve is meant for P of a few thousand (its factor is P^2 complex128 values)
 constexpr long kCholMaxP = 4000;
 
 hipError_t launch_sr_step(const SrArgs& args, const SrWork& w, hipStream_t stream);

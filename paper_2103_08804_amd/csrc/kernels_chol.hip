@@ -9,9 +9,9 @@
 //      the 64 unknowns of the row, the substitution runs along the columns);
 //   3. the trailing lower triangle is updated, A_ij -= L_ik L_jk^H (i >= j), in
 //      32 x 32 output tiles with both 32 x 64 panels staged in LDS.
-// The triangular solves run by blocks of 64 rows in one workgroup: the
-// off-diagonal products are spread over all threads, the 64 x 64 diagonal
-// substitutions over one wave.  Everything is in double, in a fixed order.
+// The triangular solves run by blocks of 64 rows: one wave substitutes in the
+// diagonal block, a wide kernel applies the block to the rest of the vector.
+// Everything is in double, in a fixed order.
 #include "../../include/chebrbm.h"
 #include "device.hpp"
 #include "internal.hpp"
@@ -171,98 +171,86 @@ __global__ __launch_bounds__(256) void k_chol_update(long P, long k0, int nb, do
         }
 }
 
-// L y = F, then L^H x = y, by blocks of 64 rows in one workgroup of 1024 threads
-__global__ __launch_bounds__(1024) void k_chol_solve(long P, const double2* __restrict__ A,
-                                                     const double2* __restrict__ F, double2* __restrict__ xg,
-                                                     const double* __restrict__ sc) {
-    __shared__ double2 x[kCholMaxP];               // the solution lives in LDS
-    __shared__ double2 D[CH_NB][CH_NB + 1];        // the diagonal block of the current step
-    __shared__ double2 part[16][CH_NB];            // per-wave partial sums of the off-diagonal products
-    __shared__ double2 rhs[CH_NB];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (chol_failed(sc)) {
-        for (long k = tid; k < P; k += blockDim.x) xg[k] = make_double2(0.0, 0.0);
-        return;
-    }
-    const long nblk = (P + CH_NB - 1) / CH_NB;
-    // forward: y_B = L_BB^{-1} (F_B - sum_{j < b0} L_Bj y_j)
-    for (long blk = 0; blk < nblk; ++blk) {
-        const long b0 = blk * CH_NB;
-        const int nb = (int)(P - b0 < CH_NB ? P - b0 : CH_NB);
-        // wave w takes rows r = w, w + 16, ... of the block; its lanes split the columns j < b0
-        for (int r = wv; r < nb; r += 16) {
-            double sx = 0.0, sy = 0.0;
-            const double2* Ar = A + (b0 + r) * P;
-            for (long j = lane; j < b0; j += 64) {
-                const double2 t = zmul(Ar[j], x[j]);
-                sx += t.x;
-                sy += t.y;
+// L y = F, then L^H x = y, in place in x, by blocks of 64 rows.  Per block: one wave substitutes within
+// the diagonal block (each unknown, once known, is read by every lane and the later lanes subtract its
+// term), then a kernel over the whole width applies the block's unknowns to the rest: forward, the rows
+// below (one wave per row, the lanes over the block's 64 columns); backward, the columns to the left
+// (one thread per column, the block's 64 rows in order).
+
+// x = F, or 0 after a failed factorisation
+__global__ __launch_bounds__(256) void k_trsv_init(long P, const double2* __restrict__ F, double2* __restrict__ x,
+                                                   const double* __restrict__ sc) {
+    const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < P) x[k] = chol_failed(sc) ? make_double2(0.0, 0.0) : F[k];
+}
+
+// the diagonal block [b0, b0 + nb): forward (L_BB y_B = x_B) or backward (L_BB^H x_B = x_B), one wave
+__global__ __launch_bounds__(64) void k_trsv_diag(long P, const double2* __restrict__ A, long b0, int nb, int backward,
+                                                  double2* __restrict__ x, const double* __restrict__ sc) {
+    __shared__ double2 D[CH_NB][CH_NB + 1];
+    if (chol_failed(sc)) return;
+    const int lane = threadIdx.x;
+    for (int r = 0; r < nb; ++r) D[r][lane] = lane <= r ? A[(b0 + r) * P + b0 + lane] : make_double2(0.0, 0.0);
+    __syncthreads();
+    double2 v = lane < nb ? x[b0 + lane] : make_double2(0.0, 0.0);
+    if (!backward) {
+        // y_m = (x_m - sum_{l<m} L_ml y_l) / L_mm, l = 0, 1, ...
+        for (int m = 0; m < nb; ++m) {
+            if (lane == m) {
+                const double inv = 1.0 / D[m][m].x;
+                v = make_double2(v.x * inv, v.y * inv);
             }
-            sx = wave_sum(sx);
-            sy = wave_sum(sy);
-            if (lane == 0) rhs[r] = make_double2(F[b0 + r].x - sx, F[b0 + r].y - sy);
+            const double2 ym = make_double2(__shfl(v.x, m), __shfl(v.y, m));
+            if (lane > m && lane < nb) {
+                const double2 t = zmul(D[lane][m], ym);
+                v.x -= t.x;
+                v.y -= t.y;
+            }
         }
-        for (int e = tid; e < nb * nb; e += 1024) D[e / nb][e % nb] = A[(b0 + e / nb) * P + b0 + e % nb];
-        __syncthreads();
-        if (wv == 0) {                             // 64-step substitution in one wave
-            double2 y = lane < nb ? rhs[lane] : make_double2(0.0, 0.0);
-            for (int m = 0; m < nb; ++m) {
-                double sx = 0.0, sy = 0.0;
-                if (lane < m) {
-                    const double2 t = zmul(D[m][lane], y);
-                    sx = t.x;
-                    sy = t.y;
-                }
-                sx = wave_sum(sx);
-                sy = wave_sum(sy);
-                if (lane == m) {
-                    const double inv = 1.0 / D[m][m].x;
-                    y = make_double2((y.x - sx) * inv, (y.y - sy) * inv);
-                }
+    } else {
+        // x_m = (v_m - sum_{l>m} conj(L_lm) x_l) / L_mm, m from the bottom of the block up
+        for (int m = nb - 1; m >= 0; --m) {
+            if (lane == m) {
+                const double inv = 1.0 / D[m][m].x;
+                v = make_double2(v.x * inv, v.y * inv);
             }
-            if (lane < nb) x[b0 + lane] = y;
+            const double2 xm = make_double2(__shfl(v.x, m), __shfl(v.y, m));
+            if (lane < m) {
+                const double2 t = zconjmul(D[m][lane], xm);   // conj(L_m,lane) x_m
+                v.x -= t.x;
+                v.y -= t.y;
+            }
         }
-        __syncthreads();
     }
-    // backward: x_B = L_BB^{-H} (y_B - sum_{k >= b0 + nb} conj(L_kB) x_k)
-    for (long blk = nblk - 1; blk >= 0; --blk) {
-        const long b0 = blk * CH_NB;
-        const int nb = (int)(P - b0 < CH_NB ? P - b0 : CH_NB);
-        // column sums over rows k beyond the block: wave w takes rows k = b0 + nb + w, + 16, ...; lane = column
-        double2 acc = make_double2(0.0, 0.0);
-        if (lane < nb)
-            for (long k = b0 + nb + wv; k < P; k += 16) {
-                const double2 t = zconjmul(A[k * P + b0 + lane], x[k]);
-                acc.x += t.x;
-                acc.y += t.y;
-            }
-        part[wv][lane] = acc;
-        for (int e = tid; e < nb * nb; e += 1024) D[e / nb][e % nb] = A[(b0 + e / nb) * P + b0 + e % nb];
-        __syncthreads();
-        if (wv == 0) {
-            double2 s = make_double2(0.0, 0.0);
-            for (int w = 0; w < 16; ++w) { s.x += part[w][lane].x; s.y += part[w][lane].y; }
-            double2 v = lane < nb ? make_double2(x[b0 + lane].x - s.x, x[b0 + lane].y - s.y) : make_double2(0.0, 0.0);
-            // x_m = (v_m - sum_{l > m} conj(L[l][m]) x_l) / L[m][m], m from the bottom of the block up
-            for (int m = nb - 1; m >= 0; --m) {
-                double sx = 0.0, sy = 0.0;
-                if (lane > m && lane < nb) {
-                    const double2 t = zconjmul(D[lane][m], v);
-                    sx = t.x;
-                    sy = t.y;
-                }
-                sx = wave_sum(sx);
-                sy = wave_sum(sy);
-                if (lane == m) {
-                    const double inv = 1.0 / D[m][m].x;
-                    v = make_double2((v.x - sx) * inv, (v.y - sy) * inv);
-                }
-            }
-            if (lane < nb) x[b0 + lane] = v;
-        }
-        __syncthreads();
+    if (lane < nb) x[b0 + lane] = v;
+}
+
+// forward: x_k -= sum_{l < nb} L_k,b0+l y_b0+l for the rows k >= b0 + nb, one wave per row
+__global__ __launch_bounds__(256) void k_trsv_rows(long P, const double2* __restrict__ A, long b0, int nb,
+                                                   double2* __restrict__ x, const double* __restrict__ sc) {
+    if (chol_failed(sc)) return;
+    const int lane = threadIdx.x & 63;
+    const long k = b0 + nb + (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= P) return;
+    double2 t = make_double2(0.0, 0.0);
+    if (lane < nb) t = zmul(A[k * P + b0 + lane], x[b0 + lane]);
+    const double tx = wave_sum(t.x), ty = wave_sum(t.y);
+    if (lane == 0) x[k] = make_double2(x[k].x - tx, x[k].y - ty);
+}
+
+// backward: x_j -= sum_{r < nb} conj(L_b0+r,j) x_b0+r for the columns j < b0, one thread per column
+__global__ __launch_bounds__(256) void k_trsv_cols(long P, const double2* __restrict__ A, long b0, int nb,
+                                                   double2* __restrict__ x, const double* __restrict__ sc) {
+    if (chol_failed(sc)) return;
+    const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= b0) return;
+    double ax = 0.0, ay = 0.0;
+    for (int r = 0; r < nb; ++r) {
+        const double2 t = zconjmul(A[(b0 + r) * P + j], x[b0 + r]);
+        ax += t.x;
+        ay += t.y;
     }
-    for (long k = tid; k < P; k += blockDim.x) xg[k] = x[k];
+    x[j] = make_double2(x[j].x - ax, x[j].y - ay);
 }
 
 hipError_t launch_cholesky_solve(long P, const float2* S, double eps, const double2* F, double2* A64, double2* x,
@@ -279,7 +267,25 @@ hipError_t launch_cholesky_solve(long P, const float2* S, double eps, const doub
         const long T = (rows + CH_T - 1) / CH_T;
         hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, stream, P, k0, nb, A64, sc);
     }
-    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, stream, P, A64, F, x, sc);
+    hipLaunchKernelGGL(k_trsv_init, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, stream, P, F, x, sc);
+    const long nblk = (P + CH_NB - 1) / CH_NB;
+    for (long blk = 0; blk < nblk; ++blk) {
+        const long b0 = blk * CH_NB;
+        const int nb = (int)(P - b0 < CH_NB ? P - b0 : CH_NB);
+        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(64), 0, stream, P, A64, b0, nb, 0, x, sc);
+        const long rows = P - b0 - nb;
+        if (rows > 0)
+            hipLaunchKernelGGL(k_trsv_rows, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, P, A64, b0, nb, x,
+                               sc);
+    }
+    for (long blk = nblk - 1; blk >= 0; --blk) {
+        const long b0 = blk * CH_NB;
+        const int nb = (int)(P - b0 < CH_NB ? P - b0 : CH_NB);
+        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(64), 0, stream, P, A64, b0, nb, 1, x, sc);
+        if (b0 > 0)
+            hipLaunchKernelGGL(k_trsv_cols, dim3((unsigned)((b0 + 255) / 256)), dim3(256), 0, stream, P, A64, b0, nb, x,
+                               sc);
+    }
     return hipGetLastError();
 }
 
