@@ -22,6 +22,13 @@ enum { SC_FLAGS_SLOT = 15 };   // must match the scalar layout of the step drive
 constexpr int CH_NB = 64;      // panel width
 constexpr int CH_T = 32;       // trailing-update tile
 
+// the value of v in lane m (m wave-uniform), through scalar registers
+__device__ __forceinline__ double lane_value(double v, int m) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, m), hi = __builtin_amdgcn_readlane((int)(b >> 32), m);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 __device__ __forceinline__ bool chol_failed(const double* sc) {
     return ((int)sc[SC_FLAGS_SLOT] & CRBM_FLAG_CHOLESKY_FAIL) != 0;
 }
@@ -111,12 +118,10 @@ __global__ __launch_bounds__(256) void k_chol_panel(long P, long k0, int nb, dou
     if (i >= P) return;
     double2* row = A + i * P + k0;
     double2 x = lane < nb ? row[lane] : make_double2(0.0, 0.0);
+    const double dinv = lane < nb ? 1.0 / L[lane][lane].x : 0.0;   // lane m divides by L_mm at step m
     for (int m = 0; m < nb; ++m) {
-        if (lane == m) {
-            const double inv = 1.0 / L[m][m].x;
-            x = make_double2(x.x * inv, x.y * inv);
-        }
-        const double xr = __shfl(x.x, m), xi = __shfl(x.y, m);
+        if (lane == m) x = make_double2(x.x * dinv, x.y * dinv);
+        const double xr = lane_value(x.x, m), xi = lane_value(x.y, m);
         if (lane > m && lane < nb) {
             const double2 c = L[lane][m];           // x_m conj(L[lane][m])
             x.x -= xr * c.x + xi * c.y;
@@ -184,23 +189,26 @@ __global__ __launch_bounds__(256) void k_trsv_init(long P, const double2* __rest
     if (k < P) x[k] = chol_failed(sc) ? make_double2(0.0, 0.0) : F[k];
 }
 
-// the diagonal block [b0, b0 + nb): forward (L_BB y_B = x_B) or backward (L_BB^H x_B = x_B), one wave
-__global__ __launch_bounds__(64) void k_trsv_diag(long P, const double2* __restrict__ A, long b0, int nb, int backward,
-                                                  double2* __restrict__ x, const double* __restrict__ sc) {
+// the diagonal block [b0, b0 + nb): forward (L_BB y_B = x_B) or backward (L_BB^H x_B = x_B); four waves
+// stage the block, the first substitutes
+__global__ __launch_bounds__(256) void k_trsv_diag(long P, const double2* __restrict__ A, long b0, int nb, int backward,
+                                                   double2* __restrict__ x, const double* __restrict__ sc) {
     __shared__ double2 D[CH_NB][CH_NB + 1];
     if (chol_failed(sc)) return;
-    const int lane = threadIdx.x;
-    for (int r = 0; r < nb; ++r) D[r][lane] = lane <= r ? A[(b0 + r) * P + b0 + lane] : make_double2(0.0, 0.0);
+    for (int e = threadIdx.x; e < nb * CH_NB; e += 256) {
+        const int r = e / CH_NB, c = e % CH_NB;
+        D[r][c] = c <= r ? A[(b0 + r) * P + b0 + c] : make_double2(0.0, 0.0);
+    }
     __syncthreads();
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
     double2 v = lane < nb ? x[b0 + lane] : make_double2(0.0, 0.0);
+    const double dinv = lane < nb ? 1.0 / D[lane][lane].x : 0.0;   // lane m divides by L_mm at step m
     if (!backward) {
         // y_m = (x_m - sum_{l<m} L_ml y_l) / L_mm, l = 0, 1, ...
         for (int m = 0; m < nb; ++m) {
-            if (lane == m) {
-                const double inv = 1.0 / D[m][m].x;
-                v = make_double2(v.x * inv, v.y * inv);
-            }
-            const double2 ym = make_double2(__shfl(v.x, m), __shfl(v.y, m));
+            if (lane == m) v = make_double2(v.x * dinv, v.y * dinv);
+            const double2 ym = make_double2(lane_value(v.x, m), lane_value(v.y, m));
             if (lane > m && lane < nb) {
                 const double2 t = zmul(D[lane][m], ym);
                 v.x -= t.x;
@@ -210,11 +218,8 @@ __global__ __launch_bounds__(64) void k_trsv_diag(long P, const double2* __restr
     } else {
         // x_m = (v_m - sum_{l>m} conj(L_lm) x_l) / L_mm, m from the bottom of the block up
         for (int m = nb - 1; m >= 0; --m) {
-            if (lane == m) {
-                const double inv = 1.0 / D[m][m].x;
-                v = make_double2(v.x * inv, v.y * inv);
-            }
-            const double2 xm = make_double2(__shfl(v.x, m), __shfl(v.y, m));
+            if (lane == m) v = make_double2(v.x * dinv, v.y * dinv);
+            const double2 xm = make_double2(lane_value(v.x, m), lane_value(v.y, m));
             if (lane < m) {
                 const double2 t = zconjmul(D[m][lane], xm);   // conj(L_m,lane) x_m
                 v.x -= t.x;
@@ -272,7 +277,7 @@ hipError_t launch_cholesky_solve(long P, const float2* S, double eps, const doub
     for (long blk = 0; blk < nblk; ++blk) {
         const long b0 = blk * CH_NB;
         const int nb = (int)(P - b0 < CH_NB ? P - b0 : CH_NB);
-        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(64), 0, stream, P, A64, b0, nb, 0, x, sc);
+        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(256), 0, stream, P, A64, b0, nb, 0, x, sc);
         const long rows = P - b0 - nb;
         if (rows > 0)
             hipLaunchKernelGGL(k_trsv_rows, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, P, A64, b0, nb, x,
@@ -281,7 +286,7 @@ hipError_t launch_cholesky_solve(long P, const float2* S, double eps, const doub
     for (long blk = nblk - 1; blk >= 0; --blk) {
         const long b0 = blk * CH_NB;
         const int nb = (int)(P - b0 < CH_NB ? P - b0 : CH_NB);
-        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(64), 0, stream, P, A64, b0, nb, 1, x, sc);
+        hipLaunchKernelGGL(k_trsv_diag, dim3(1), dim3(256), 0, stream, P, A64, b0, nb, 1, x, sc);
         if (b0 > 0)
             hipLaunchKernelGGL(k_trsv_cols, dim3((unsigned)((b0 + 255) / 256)), dim3(256), 0, stream, P, A64, b0, nb, x,
                                sc);
