@@ -47,18 +47,19 @@ __global__ __launch_bounds__(256) void k_chol_load(long P, const float2* __restr
     A[idx] = make_double2((double)v.x + (i == j ? eps : 0.0), (double)v.y);
 }
 
-// 1. L_kk of the diagonal block [k0, k0 + nb)^2 in LDS (one workgroup of 256 threads, a 16 x 16 grid over
-//    rows and columns).  Column j: every thread reads the pivot d = L_jj (final since the last barrier, so
-//    all take the same decision) and updates its share of the trailing lower triangle with the column
-//    scaled by 1 / sqrt(d) on the fly; after one barrier the column itself is scaled.  The next column
-//    reads column j + 1 and its own trailing block only, so one barrier per column suffices.
-__global__ __launch_bounds__(256) void k_chol_diagblock(long P, long k0, int nb, double2* __restrict__ A,
-                                                        double* __restrict__ sc) {
+// 1. L_kk of the diagonal block [k0, k0 + nb)^2 in LDS (one workgroup of 1024 threads, a 32 x 32 grid over
+//    rows and columns, four waves per SIMD to overlap their LDS latencies).  Column j: every thread reads the
+//    pivot d = L_jj (final since the last barrier, so all take the same decision) and updates its share of
+//    the trailing lower triangle with the column scaled by 1 / sqrt(d) on the fly; after one barrier the
+//    column itself is scaled.  The next column reads column j + 1 and its own trailing block only, so one
+//    barrier per column suffices.
+__global__ __launch_bounds__(1024) void k_chol_diagblock(long P, long k0, int nb, double2* __restrict__ A,
+                                                         double* __restrict__ sc) {
     __shared__ double2 L[CH_NB][CH_NB + 1];
     if (chol_failed(sc)) return;
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    for (int i = ty; i < nb; i += 16)
-        for (int j = tx; j < nb; j += 16) L[i][j] = (j <= i) ? A[(k0 + i) * P + k0 + j] : make_double2(0.0, 0.0);
+    const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+    for (int i = ty; i < nb; i += 32)
+        for (int j = tx; j < nb; j += 32) L[i][j] = (j <= i) ? A[(k0 + i) * P + k0 + j] : make_double2(0.0, 0.0);
     __syncthreads();
     bool fail = false;
     for (int j = 0; j < nb; ++j) {
@@ -68,20 +69,20 @@ __global__ __launch_bounds__(256) void k_chol_diagblock(long P, long k0, int nb,
             break;
         }
         const double s = sqrt(d), inv = 1.0 / s;
-        double2 b[4];                                  // L_lj / s for this thread's columns l
+        double2 b[2];                                  // L_lj / s for this thread's columns l
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int l = j + 1 + tx + 16 * m;
+        for (int m = 0; m < 2; ++m) {
+            const int l = j + 1 + tx + 32 * m;
             b[m] = l < nb ? make_double2(L[l][j].x * inv, L[l][j].y * inv) : make_double2(0.0, 0.0);
         }
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int i = j + 1 + ty + 16 * p;
+        for (int p = 0; p < 2; ++p) {
+            const int i = j + 1 + ty + 32 * p;
             if (i >= nb) break;
             const double2 a = make_double2(L[i][j].x * inv, L[i][j].y * inv);
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int l = j + 1 + tx + 16 * m;
+            for (int m = 0; m < 2; ++m) {
+                const int l = j + 1 + tx + 32 * m;
                 if (l <= i) {                          // L_il -= L_ij conj(L_lj)
                     L[i][l].x -= a.x * b[m].x + a.y * b[m].y;
                     L[i][l].y -= a.y * b[m].x - a.x * b[m].y;
@@ -90,15 +91,15 @@ __global__ __launch_bounds__(256) void k_chol_diagblock(long P, long k0, int nb,
         }
         __syncthreads();
         if (tid == 0) L[j][j] = make_double2(s, 0.0);
-        for (int i = j + 1 + tid; i < nb; i += 256) L[i][j] = make_double2(L[i][j].x * inv, L[i][j].y * inv);
+        for (int i = j + 1 + tid; i < nb; i += 1024) L[i][j] = make_double2(L[i][j].x * inv, L[i][j].y * inv);
     }
     if (fail) {
         if (tid == 0) sc[SC_FLAGS_SLOT] = (double)((int)sc[SC_FLAGS_SLOT] | CRBM_FLAG_CHOLESKY_FAIL);
         return;
     }
     __syncthreads();
-    for (int i = ty; i < nb; i += 16)
-        for (int j = tx; j <= i; j += 16) A[(k0 + i) * P + k0 + j] = L[i][j];
+    for (int i = ty; i < nb; i += 32)
+        for (int j = tx; j <= i; j += 32) A[(k0 + i) * P + k0 + j] = L[i][j];
 }
 
 // 2. rows i >= k0 + nb: x L_kk^H = a with x = L_ik, a = A_ik; lane l owns column l of the row.
@@ -265,7 +266,7 @@ hipError_t launch_cholesky_solve(long P, const float2* S, double eps, const doub
                        a64_holds_s ? nullptr : S, eps, A64);
     for (long k0 = 0; k0 < P; k0 += CH_NB) {
         const int nb = (int)(P - k0 < CH_NB ? P - k0 : CH_NB);
-        hipLaunchKernelGGL(k_chol_diagblock, dim3(1), dim3(256), 0, stream, P, k0, nb, A64, sc);
+        hipLaunchKernelGGL(k_chol_diagblock, dim3(1), dim3(1024), 0, stream, P, k0, nb, A64, sc);
         const long rows = P - k0 - nb;
         if (rows <= 0) break;
         hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, stream, P, k0, nb, A64, sc);
